@@ -1,0 +1,329 @@
+"""Preconditioner pieces, written out with explicit sparse matrices.
+
+Oracle (test infrastructure only).
+
+Paper passages followed
+  * Section 2.2, eq. (stoch-prec): block-diagonal preconditioner
+    blkdiag(M_gamma, beta M, S); Section 2.2, eq. (mathcalZ):
+    S = Z M_gamma^{-1} Z^T with Z = sum_l H_l (x) A-tilde_l,
+    A-tilde_1 = A_1 + sqrt((1+gamma)/beta) M, so S^{-1} = Z^{-1} M_gamma Z^{-1}.
+  * Section 2.2 and Section 5: the mass blocks are inverted approximately by
+    Chebyshev semi-iteration (Golub & Varga), D = ((lmin+lmax)/2) diag(M) with
+    eigenvalue bounds [1/4, 9/4] of diag(M)^{-1} M.
+  * Algorithm 1 (hGS): symmetric block Gauss-Seidel over the degree levels,
+    diagonal blocks A-tilde_1, off-diagonal products truncated to the modes in
+    I_tau (eq. matvec-block).
+  * Algorithm 5 with N = 1 (Section 5): each Z^{-1} is one hGS application
+    from a zero initial guess.
+  * Section 3.1, eq. (precon for time), eq. (Z hat approx), eq. (A_hat) and
+    Algorithm 4: the time-dependent preconditioner
+    blkdiag(tau D (x) M_gamma, tau beta D (x) M, S-tilde) with Z-tilde
+    block-diagonal in time and A-hat_1 = (1 + tau sqrt((1+gamma)/beta)) M
+    + tau A_1, A-hat_l = tau A_l.
+
+Readings (the paper is silent or ambiguous):
+  * Chebyshev recurrence: the textbook Golub-Varga weights omega_1 = 1,
+    omega_2 = 1/(1 - rho^2/2), omega_{k+1} = 1/(1 - rho^2 omega_k / 4);
+  * the Schur block applies hGS twice (one Richardson N = 1 step per Z^{-1})
+    with the M_gamma multiply between them;
+  * S-tilde carries the 1/tau of S-bar, so S-tilde^{-1} = tau Z-tilde^{-1}
+    (D (x) M_gamma) Z-tilde^{-1};
+  * truncation r keeps the modes k = 1..r-1 (r = 1 is the mean-based
+    preconditioner, r = M+1 keeps every mode of the affine field);
+  * the A-tilde_1 / A-hat_1 solves inside hGS are either exact (sparse LU,
+    the "ideal" preconditioner of the analysis) or one geometric-multigrid
+    V-cycle (the solver's choice in place of the paper's direct solves); the
+    multigrid is defined in class GMG below.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from numpy.polynomial import Chebyshev, Polynomial
+
+from . import fem, kkt
+
+
+# ----------------------------------------------------------------------------
+# Chebyshev semi-iteration for the mass matrix
+# ----------------------------------------------------------------------------
+
+def cheb_mass(Mi: sp.spmatrix, R: np.ndarray, steps: int,
+              lmin: float = 0.25, lmax: float = 2.25) -> np.ndarray:
+    """Approximate M^{-1} applied to each row of R by `steps` Chebyshev
+    semi-iterations from x = 0 (Golub-Varga recurrence, textbook weights)."""
+    gam = 0.5 * (lmin + lmax)
+    rho = (lmax - lmin) / (lmax + lmin)
+    dinv = 1.0 / (gam * Mi.diagonal())
+    R = np.atleast_2d(R)
+    x_prev = np.zeros_like(R)
+    x = R * dinv                                   # k = 1, omega_1 = 1
+    omega = 1.0
+    for k in range(1, steps):
+        omega = 1.0 / (1.0 - 0.5 * rho * rho) if k == 1 else 1.0 / (1.0 - 0.25 * rho * rho * omega)
+        r = R - (Mi @ x.T).T
+        x_new = omega * (r * dinv + x - x_prev) + x_prev
+        x_prev, x = x, x_new
+    return x
+
+
+# ----------------------------------------------------------------------------
+# Geometric multigrid for a K + b M (constant coefficients)
+# ----------------------------------------------------------------------------
+
+def prolongation_1d(nc: int) -> sp.csr_matrix:
+    """Linear interpolation from the nc-1 interior nodes of a 1-D grid with nc
+    cells to the 2nc-1 interior nodes of its bisection (zero end values)."""
+    nf = 2 * nc
+    rows, cols, vals = [], [], []
+    for I in range(1, nc):              # coarse interior node I at fine node 2I
+        j = I - 1
+        for fi, w in ((2 * I - 1, 0.5), (2 * I, 1.0), (2 * I + 1, 0.5)):
+            rows.append(fi - 1)
+            cols.append(j)
+            vals.append(w)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf - 1, nc - 1))
+
+
+def prolongation_2d(nc: int) -> sp.csr_matrix:
+    """Bilinear interpolation = tensor product of 1-D linear interpolation
+    (interior nodes, iy-major)."""
+    p = prolongation_1d(nc)
+    return sp.kron(p, p, format="csr")
+
+
+def sine_lambda_max(n: int, a: float, b: float) -> float:
+    """Largest eigenvalue of diag(A)^{-1} A for A = a K + b M on the interior
+    of the uniform n x n Q1 grid.
+
+    The unit-coefficient Q1 matrices are K = K1 (x) M1 + M1 (x) K1 and
+    M = M1 (x) M1 with the 1-D P1 matrices K1 = tridiag(-1,2,-1)/h and
+    M1 = h tridiag(1,4,1)/6, whose common eigenvectors are the discrete sines
+    with eigenvalues (2/h)(1 - cos i pi h) and (h/3)(2 + cos i pi h); the
+    diagonal of A is the constant a 8/3 + b 4h^2/9."""
+    h = 1.0 / n
+    th = np.arange(1, n) * np.pi * h
+    k1 = (2.0 / h) * (1.0 - np.cos(th))
+    m1 = (h / 3.0) * (2.0 + np.cos(th))
+    lam = a * (np.outer(k1, m1) + np.outer(m1, k1)) + b * np.outer(m1, m1)
+    diag = a * 8.0 / 3.0 + b * 4.0 * h * h / 9.0
+    return float(lam.max() / diag)
+
+
+class GMG:
+    """One V-cycle of geometric multigrid for A = a K + b M on the n x n grid.
+
+    Definition (the solver's choice; the paper factorises A-tilde_1 directly):
+      * levels n, n/2, ..., n_c with n_c = min(n, 8) (n a power of two);
+      * level operator a K_l + b M_l, assembled on each grid (for nested Q1
+        with constant coefficients this equals the Galerkin product
+        P^T A_{l+1} P);
+      * prolongation P = bilinear interpolation, restriction R = P^T;
+      * smoother: polynomial (Chebyshev) smoothing x <- x + q(B) D^{-1}(b - A x)
+        with B = D^{-1} A, D = diag(A), whose error propagator is
+        T_nu((theta - B)/delta) / T_nu(theta/delta) on [lo, hi] =
+        [0.3, 1.1] * lambda_max(B); nu_pre steps before and nu_post after the
+        coarse correction;
+      * coarsest level solved exactly (dense inverse);
+      * zero initial guess.
+    """
+
+    def __init__(self, n: int, a: float, b: float, nu_pre: int = 2, nu_post: int = 2,
+                 n_coarse: int = 8):
+        self.n, self.a, self.b = n, a, b
+        self.nu_pre, self.nu_post = nu_pre, nu_post
+        sizes = [n]
+        while sizes[-1] > n_coarse:
+            sizes.append(sizes[-1] // 2)
+        self.sizes = sizes
+        self.A, self.Dinv, self.q = [], [], []
+        for m in sizes:
+            K = fem.restrict(fem.assemble_full(m, 1.0, "stiffness"), m)
+            Mm = fem.restrict(fem.assemble_full(m, 1.0, "mass"), m)
+            A = (a * K + b * Mm).tocsr()
+            self.A.append(A)
+            self.Dinv.append(1.0 / A.diagonal())
+            lmax = sine_lambda_max(m, a, b)
+            self.q.append((self._smoother_poly(nu_pre, 0.3 * lmax, 1.1 * lmax),
+                           self._smoother_poly(nu_post, 0.3 * lmax, 1.1 * lmax)))
+        self.P = [prolongation_2d(m // 2) for m in sizes[:-1]]
+        self.coarse_inv = np.linalg.inv(self.A[-1].toarray())
+
+    @staticmethod
+    def _smoother_poly(nu: int, lo: float, hi: float) -> np.ndarray:
+        """Power-series coefficients of q with 1 - t q(t) = T_nu((theta-t)/delta)/T_nu(theta/delta)."""
+        if nu == 0:
+            return np.zeros(1)
+        theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+        Tn = Chebyshev.basis(nu).convert(kind=Polynomial)
+        z = Polynomial([theta / delta, -1.0 / delta])
+        p = Polynomial([0.0])
+        zp = Polynomial([1.0])
+        for c in Tn.coef:
+            p = p + c * zp
+            zp = zp * z
+        p = p / Tn(theta / delta)
+        one_minus = Polynomial([1.0]) - p
+        q, rem = divmod(one_minus, Polynomial([0.0, 1.0]))
+        assert np.all(np.abs(rem.coef) < 1e-10 * np.max(np.abs(one_minus.coef)))
+        return q.coef
+
+    def _smooth(self, lvl: int, x: np.ndarray, b: np.ndarray, which: int) -> np.ndarray:
+        coef = self.q[lvl][which]
+        if len(coef) == 1 and coef[0] == 0.0:
+            return x
+        A, Dinv = self.A[lvl], self.Dinv[lvl]
+        w = Dinv[:, None] * (b - A @ x)
+        # Horner: q(B) w = c0 w + B (c1 w + B (c2 w + ...)), B = D^{-1} A
+        y = coef[-1] * w
+        for c in coef[-2::-1]:
+            y = c * w + Dinv[:, None] * (A @ y)
+        return x + y
+
+    def _vcycle(self, lvl: int, b: np.ndarray) -> np.ndarray:
+        if lvl == len(self.sizes) - 1:
+            return self.coarse_inv @ b
+        x = np.zeros_like(b)
+        x = self._smooth(lvl, x, b, 0)
+        r = b - self.A[lvl] @ x
+        P = self.P[lvl]
+        x = x + P @ self._vcycle(lvl + 1, P.T @ r)
+        x = self._smooth(lvl, x, b, 1)
+        return x
+
+    def apply(self, B: np.ndarray) -> np.ndarray:
+        """V-cycle applied to each row of B (shape (cols, n_int))."""
+        B = np.atleast_2d(B)
+        return self._vcycle(0, B.T).T
+
+
+class ExactSolve:
+    """Exact inverse of A = a K + b M (sparse LU), for the ideal preconditioner."""
+
+    def __init__(self, n: int, a: float, b: float):
+        K = fem.restrict(fem.assemble_full(n, 1.0, "stiffness"), n)
+        Mm = fem.restrict(fem.assemble_full(n, 1.0, "mass"), n)
+        self.A = (a * K + b * Mm).tocsc()
+        self.lu = spla.splu(self.A)
+
+    def apply(self, B: np.ndarray) -> np.ndarray:
+        B = np.atleast_2d(B)
+        return self.lu.solve(np.ascontiguousarray(B.T)).T
+
+
+# ----------------------------------------------------------------------------
+# hGS (Algorithm 1) and the Schur block
+# ----------------------------------------------------------------------------
+
+def mean_operator_coeffs(sg: kkt.SG):
+    """(a, b, scale): A-tilde_1 = a K_unit + b M and the factor on the
+    off-level products, steady (eq. mathcalZ) or time-dependent (eq. A_hat).
+
+    The mean coefficient kappa_0 must be a constant c0, so K_0 = c0 K_unit."""
+    p = sg.prob
+    c0 = float(sg.kappa[0].reshape(-1)[0])
+    s = np.sqrt((1.0 + p.gamma) / p.beta)
+    if p.steady:
+        return c0, s, 1.0
+    tau = p.tau
+    return tau * c0, 1.0 + tau * s, tau
+
+
+def make_inner(sg: kkt.SG, mode: str = "gmg", nu_pre: int = 2, nu_post: int = 2):
+    a, b, _ = mean_operator_coeffs(sg)
+    if mode == "exact":
+        return ExactSolve(sg.prob.n, a, b)
+    return GMG(sg.prob.n, a, b, nu_pre, nu_post)
+
+
+def hgs(sg: kkt.SG, R: np.ndarray, inner, r_trunc: int) -> np.ndarray:
+    """Algorithm 1 applied to R (shape (n_xi, n_int)), zero initial guess.
+
+    Levels d = 0..P are the degree blocks; sweep d = 0..P then P-1..0.  For
+    level d: V_(d) = A1^{-1} [R_(d) - sum_{tau in I_tau} scale A_tau V_(other) H_tau]
+    with the product taken over all columns outside level d (the E and F
+    terms of eq. alg-hGS2), using the current V.  I_tau = modes 1..r-1."""
+    off = sg.offsets
+    P = len(off) - 2
+    _, _, scale = mean_operator_coeffs(sg)
+    modes = list(range(1, min(r_trunc, sg.prob.M + 1)))
+    V = np.zeros_like(R)
+    order = list(range(P + 1)) + list(range(P - 1, -1, -1))
+    for d in order:
+        lo, hi = int(off[d]), int(off[d + 1])
+        B = R[lo:hi].copy()
+        if modes:
+            Vm = V.copy()
+            Vm[lo:hi] = 0.0
+            for k in modes:
+                Gk = sg.G[k]
+                # rows lo:hi of (G_k^T V) then K_k on the spatial index
+                W = Gk[:, lo:hi].T @ Vm
+                B -= scale * (sg.K[k] @ W.T).T
+        V[lo:hi] = inner.apply(B)
+    return V
+
+
+def schur_inverse(sg: kkt.SG, R: np.ndarray, inner, r_trunc: int) -> np.ndarray:
+    """Steady: S^{-1} r ~ Z^{-1} M_gamma Z^{-1} r with each Z^{-1} one hGS.
+    Time-dependent (R has a leading n_t axis): per step t,
+    tau Z_t^{-1} (D_tt M_gamma) Z_t^{-1} r_t."""
+    p = sg.prob
+    hg = kkt.h_gamma(sg)[:, None]
+    if p.steady:
+        V = hgs(sg, R, inner, r_trunc)
+        W = hg * kkt.mass_apply(sg, V)
+        return hgs(sg, W, inner, r_trunc)
+    nt, tau = p.n_t, p.tau
+    D = np.ones(nt)
+    D[0] = D[-1] = 0.5
+    out = np.empty_like(R)
+    for t in range(nt):
+        V = hgs(sg, R[t], inner, r_trunc)
+        W = D[t] * hg * kkt.mass_apply(sg, V)
+        out[t] = tau * hgs(sg, W, inner, r_trunc)
+    return out
+
+
+def precond_apply(sg: kkt.SG, r: np.ndarray, inner=None, r_trunc: int | None = None,
+                  cheb_steps: int = 5) -> np.ndarray:
+    """Block-diagonal preconditioner of eq. (stoch-prec) / eq. (precon for time)
+    applied to a flat KKT vector."""
+    p = sg.prob
+    if inner is None:
+        inner = make_inner(sg)
+    if r_trunc is None:
+        r_trunc = p.M + 1
+    Ry, Ru, Rl = kkt.split(sg, r)
+    hg = kkt.h_gamma(sg)[:, None]
+    if p.steady:
+        Zy = kkt_cheb(sg, Ry, cheb_steps) / hg
+        Zu = kkt_cheb(sg, Ru, cheb_steps) / p.beta
+    else:
+        nt, tau = p.n_t, p.tau
+        D = np.ones(nt)
+        D[0] = D[-1] = 0.5
+        Zy = np.empty_like(Ry)
+        Zu = np.empty_like(Ru)
+        for t in range(nt):
+            Zy[t] = kkt_cheb(sg, Ry[t], cheb_steps) / (tau * D[t] * hg)
+            Zu[t] = kkt_cheb(sg, Ru[t], cheb_steps) / (p.beta * tau * D[t])
+    Zl = schur_inverse(sg, Rl, inner, r_trunc)
+    return np.concatenate([Zy.ravel(), Zu.ravel(), Zl.ravel()])
+
+
+def kkt_cheb(sg: kkt.SG, R: np.ndarray, steps: int) -> np.ndarray:
+    return cheb_mass(sg.Mi, R, steps)
+
+
+def z_truncated(sg: kkt.SG, r_trunc: int) -> sp.csr_matrix:
+    """Explicit Z_r = I (x) A1 + scale sum_{k=1}^{r-1} G_k (x) K_k (eq. S_r)."""
+    a, b, scale = mean_operator_coeffs(sg)
+    n = sg.prob.n
+    K = fem.restrict(fem.assemble_full(n, 1.0, "stiffness"), n)
+    A1 = (a * K + b * sg.Mi).tocsr()
+    Z = sp.kron(sp.identity(sg.n_xi), A1, format="csr")
+    for k in range(1, min(r_trunc, sg.prob.M + 1)):
+        Z = Z + scale * sp.kron(sp.csr_matrix(sg.G[k]), sg.K[k], format="csr")
+    return Z.tocsr()
