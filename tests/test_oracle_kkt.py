@@ -23,7 +23,8 @@ def test_kkt_symmetric_and_direct_residual():
     assert abs(K - K.T).max() == 0.0
     x = kkt.solve_direct(sg)
     b = kkt.rhs(sg)
-    assert np.linalg.norm(b - K @ x) / np.linalg.norm(b) < 1e-13
+    assert np.linalg.norm(b - K @ x) / np.linalg.norm(b) < 1e-12
+    assert kkt._backward_error(K, x, b) < 1e-15
 
 
 def test_matricized_apply_equals_kronecker():
