@@ -1,0 +1,256 @@
+/*
+ * sg.h -- C ABI of the MI355X stochastic-Galerkin KKT solver.
+ *
+ * The library solves the discrete first-order optimality (KKT) systems of
+ * optimal control problems constrained by a diffusion (steady) or heat
+ * (time-dependent) equation with a random coefficient, discretised by Q1 finite
+ * elements in space and a stochastic Galerkin (generalised polynomial chaos)
+ * expansion in the random variables, following
+ *   Z. Li, A. Onwunta, B. Sousedik, "Stochastic Galerkin method and
+ *   hierarchical preconditioning for PDE-constrained optimization",
+ *   arXiv 2512.23804:
+ *   - steady problem: Section 2.1, eq. (problem-stoch), eq. (pde-stoch);
+ *     KKT system eq. (stoch-system);
+ *   - time-dependent problem: Section 3, eq. (obj:stoch-time-dependent),
+ *     eq. (constraint:stochastic-time-dependent); backward Euler all-at-once
+ *     KKT system eq. (KKT:stoch-time-dependent);
+ *   - preconditioner: block-diagonal Schur preconditioner eq. (stoch-prec) /
+ *     eq. (precon for time) with Chebyshev mass solves and the hierarchical
+ *     Gauss-Seidel sweep of Algorithm 1 inside the Schur block (Algorithm 5
+ *     with N = 1); Krylov solver: flexible GMRES (Section 5).
+ *
+ * Problem data.  Domain [0,1]^2 split into n x n square elements (n a power of
+ * two, 4 <= n <= 4096), homogeneous Dirichlet data (g = 0).  Random input
+ * xi ~ U(-1,1)^M, orthonormal Legendre chaos of total degree P.  The random
+ * coefficient is affine, a(x, xi) = kappa_0(x) + sum_k kappa_k(x) psi_{e_k}(xi),
+ * with each kappa_k constant per element; by default
+ * a = 1 + sigma sum_{k=1}^{M} k^-2 cos(k pi x1) cos(k pi x2) xi_k.
+ *
+ * Vector layout ("canonical layout").  One field block (state y, control u or
+ * adjoint lambda) is an array [t][j][node] of n_t * n_xi * (n+1)^2 values:
+ * t = time step (n_t = 1 for steady problems), j = chaos index in graded order
+ * (degree ascending; inside a degree descending lexicographic on the
+ * multi-index), node = iy*(n+1)+ix on the full grid.  Boundary nodes are zero
+ * on output and ignored on input.  A KKT vector is [y | u | lambda], three
+ * blocks back to back.  Several vectors are stored back to back.  All device
+ * pointers are HIP device addresses on the current device; element types are
+ * double (SG_FP64) or float (SG_FP32).
+ *
+ * Status codes.  Every entry point returns 0 (SG_OK), a positive
+ * informational code or a negative error code; sg_last_error() gives a
+ * thread-local message for the last failure on the calling thread.  No C++
+ * exception crosses this boundary.  On error no output is guaranteed.
+ *
+ * Ownership.  The caller owns every pointer it passes; sg_setup* and sg_submit
+ * copy what they need.  A handle owns its device workspace, released by
+ * sg_destroy.  One handle must not be used by two threads at once; the server
+ * is internally synchronised.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define SG_OK              0
+#define SG_PENDING         1   /* sg_poll: request not finished yet */
+#define SG_NOT_CONVERGED   2   /* solve stopped at max_iter above rtol */
+#define SG_ERR_INVALID    -1   /* bad argument or unsupported size */
+#define SG_ERR_NONCOERCIVE -2  /* coefficient can vanish for some xi */
+#define SG_ERR_NONFINITE  -3   /* NaN/Inf in the problem data */
+#define SG_ERR_NOMEM      -4   /* device memory or admission budget too small */
+#define SG_ERR_HIP        -5   /* a HIP runtime call failed */
+#define SG_ERR_CANCELLED  -6   /* request cancelled */
+#define SG_ERR_UNKNOWN    -7   /* unknown ticket */
+
+/* ---- element types and precision modes ------------------------------- */
+#define SG_FP64 0
+#define SG_FP32 1
+#define SG_PREC_FP64         0  /* operator, preconditioner and Krylov in FP64 */
+#define SG_PREC_FP32_REFINE  1  /* FP32 operator + preconditioner inside FGMRES, FP64
+                                   Arnoldi, FP64 outer residual and refinement */
+
+/* Problem data (Section 2.1 steady, Section 3 time-dependent), g = 0.
+ *   n       elements per side (power of two, 4..4096)
+ *   M       number of random variables (1..16)
+ *   P       total polynomial degree (1..8)
+ *   n_t     <= 1: steady problem; >= 2: number of backward-Euler steps on
+ *           (0, T], tau = T/n_t, unknowns at t_k = k tau, k = 1..n_t
+ *   T       final time (time-dependent only)
+ *   beta    control cost weight (> 0)
+ *   gamma   variance weight (>= 0); the objective's variance term
+ *   sigma   amplitude of the default cosine field (ignored if kappa != NULL)
+ *   kappa   optional host array [(M+1)][n][n] of per-element coefficient
+ *           modes, index [k][ey][ex]; kappa_0 must be one positive constant
+ *           (the multigrid inner solver assumes a constant mean coefficient)
+ *   y_target host array [n_t][(n+1)^2] of nodal target values (n_t = 1 when
+ *           steady); the target enters the right-hand side as the full-grid
+ *           mass matrix times the target, restricted to interior rows
+ *   y0      optional host array [(n+1)^2] initial state (time-dependent);
+ *           NULL means zero */
+typedef struct sg_problem {
+    int32_t n, M, P, n_t;
+    double T, beta, gamma, sigma;
+    const double* kappa;
+    const double* y_target;
+    const double* y0;
+} sg_problem;
+
+/* Solver options.  sg_default_options() fills the defaults in brackets.
+ *   rtol         relative residual ||b - K x|| / ||b|| to reach [1e-8]
+ *   restart      FGMRES restart length [30]
+ *   max_iter     total FGMRES iterations over all cycles [600]
+ *   cheb_steps   Chebyshev semi-iteration steps for mass solves [5]
+ *   truncation_r hGS truncation: modes k = 1..r-1 are kept in the off-level
+ *                products (r = 1 mean-based, r = M+1 all) [0 = M+1]
+ *   gmg_pre/post Chebyshev smoothing degree before/after coarse correction [2,2]
+ *   precision    SG_PREC_FP64 or SG_PREC_FP32_REFINE [SG_PREC_FP64]
+ *   inner_rtol   FP32 inner solve reduction per refinement step [1e-5]
+ *   use_graphs   capture per-iteration launch sequences in hipGraphs [1]
+ *   verbose      print per-cycle residuals to stderr [0] */
+typedef struct sg_options {
+    double rtol;
+    int32_t restart, max_iter, cheb_steps, truncation_r;
+    int32_t gmg_pre, gmg_post, precision;
+    double inner_rtol;
+    int32_t use_graphs, verbose;
+} sg_options;
+
+/* Per-solve report. */
+typedef struct sg_solve_info {
+    int32_t iters;              /* FGMRES iterations (all cycles, all refinement steps) */
+    int32_t outer_refinements;  /* FP64 refinement steps (0 in SG_PREC_FP64) */
+    int32_t converged;          /* 1 if rel_res_true <= rtol */
+    int32_t status;             /* SG_OK / SG_NOT_CONVERGED / error of this member */
+    double rel_res_true;        /* ||b - K x|| / ||b|| in FP64 at exit */
+    double t_setup_ms;          /* handle setup time (host + device) */
+    double t_solve_ms;          /* wall time of the solve */
+    double latency_ms;          /* serving: submit -> completion */
+    double bytes_moved;         /* algorithmic HBM bytes of the solve (model) */
+} sg_solve_info;
+
+/* Sizes of a handle's problems. */
+typedef struct sg_sizes {
+    int32_t n, M, P, n_t, n_xi, members;
+    int64_t nodes;              /* (n+1)^2 */
+    int64_t block_elems;        /* n_t * n_xi * nodes (one field) */
+    int64_t kkt_elems;          /* 3 * block_elems (one KKT vector) */
+    int32_t level_offsets[17];  /* degree d columns: [off[d], off[d+1]), d = 0..P */
+} sg_sizes;
+
+typedef struct sg_handle sg_handle;
+typedef struct sg_server sg_server;
+
+/* Fill `opt` with the defaults listed above. */
+void sg_default_options(sg_options* opt);
+
+/* Host-only validation of a problem and options (no device work):
+ * SG_ERR_INVALID for out-of-range sizes or parameters, SG_ERR_NONFINITE for
+ * NaN/Inf data, SG_ERR_NONCOERCIVE when min_e [kappa_0 - sqrt(3) sum_k
+ * |kappa_k(e)|] <= 0, i.e. the coefficient can reach zero for some xi in
+ * [-1,1]^M (the bounded-coefficient assumption of Section 2.1). */
+int sg_validate(const sg_problem* prob, const sg_options* opt);
+
+/* Build a handle for `count` problems of the same shape (n, M, P, n_t equal;
+ * beta, gamma, sigma, kappa, targets may differ) that are solved together as
+ * one batch ("members").  Builds the multi-index set, triple-product tables
+ * (Section 2.1), per-element coefficient modes, multigrid hierarchy and
+ * right-hand sides, uploads them to the current device, and binds `stream`
+ * (a hipStream_t, NULL = default stream).  On success *out owns the device
+ * memory.  Errors: as sg_validate, SG_ERR_NOMEM, SG_ERR_HIP. */
+int sg_setup(const sg_problem* probs, int32_t count, const sg_options* opt,
+             void* stream, sg_handle** out);
+
+/* Report the sizes of a handle. */
+int sg_query(const sg_handle* h, sg_sizes* out);
+
+/* Copy the multi-index set, int32 [n_xi][M] host array (graded order). */
+int sg_get_multiindex(const sg_handle* h, int32_t* out);
+
+/* Copy the triple-product neighbour table used by the kernels (Section 2.1,
+ * H_l with l = e_k): for chaos index j and mode k = 1..M, slot 0 is the
+ * neighbour j - e_k and slot 1 is j + e_k; idx = -1 where the neighbour is not
+ * in the set, else its chaos index; val = E[psi_{e_k} psi_j psi_idx].
+ * Host arrays idx int32 [n_xi][M][2], val double [n_xi][M][2]. */
+int sg_get_gtable(const sg_handle* h, int32_t* idx, double* val);
+
+/* Write the KKT right-hand sides of all members (one KKT vector per member,
+ * canonical layout, FP64) to device memory b_dev. */
+int sg_get_rhs(sg_handle* h, double* b_dev);
+
+/* SG operator apply, eq. (Zv) with the stiffness modes A_l (Section 2.2):
+ * Y = sum_{k=0}^{M} K_k X G_k for every time step, i.e. one field block in,
+ * one field block out, per vector.  x_dev, y_dev hold nvec blocks back to
+ * back; with members > 1, nvec must equal members and block v uses member v's
+ * coefficients; with one member any nvec >= 1 shares it.  dtype SG_FP64 or
+ * SG_FP32.  Runs on `stream` (NULL = the handle's stream), asynchronous. */
+int sg_apply_operator(sg_handle* h, const void* x_dev, void* y_dev, int32_t nvec,
+                      int32_t dtype, void* stream);
+
+/* KKT matrix apply, eq. (stoch-system) (steady) or eq. (KKT:stoch-time-
+ * dependent) (time): y = K x for nvec KKT vectors (member rule as above). */
+int sg_apply_kkt(sg_handle* h, const void* x_dev, void* y_dev, int32_t nvec,
+                 int32_t dtype, void* stream);
+
+/* Preconditioner apply z = P^{-1} r, eq. (stoch-prec) / eq. (precon for
+ * time): Chebyshev semi-iteration on the state and control blocks and
+ * S^{-1} = Z^{-1} M_gamma Z^{-1} (time: tau Z~^{-1} (D (x) M_gamma) Z~^{-1})
+ * on the adjoint block, each Z^{-1} one hGS sweep (Algorithm 1) whose
+ * A-tilde_1 solves are one multigrid V-cycle.  r_dev is not modified. */
+int sg_precond_apply(sg_handle* h, const void* r_dev, void* z_dev, int32_t nvec,
+                     int32_t dtype, void* stream);
+
+/* Solve K x = b for every member with preconditioned FGMRES(restart) from
+ * x = 0.  b_dev: FP64 KKT vectors (NULL = the problems' own right-hand
+ * sides); x_dev: FP64 output KKT vectors; info: array of `members` reports
+ * (may be NULL).  Synchronous on the handle's stream.  Returns SG_OK when all
+ * members converged, SG_NOT_CONVERGED otherwise. */
+int sg_solve(sg_handle* h, const double* b_dev, double* x_dev, sg_solve_info* info);
+
+/* Release a handle (NULL is ignored). */
+void sg_destroy(sg_handle* h);
+
+/* ---- serving: continuous batching of independent steady requests ------ */
+
+/* Create a server that owns a scheduler thread and its own HIP streams on the
+ * current device.  hbm_budget_bytes bounds the summed footprint of admitted
+ * requests (0 = 80% of free device memory); max_slots bounds requests in
+ * flight.  A request whose footprint exceeds the budget is rejected. */
+int sg_server_create(size_t hbm_budget_bytes, int32_t max_slots, sg_server** out);
+
+/* Queue one request (problem + options are copied).  x_out: caller-owned host
+ * buffer of one FP64 KKT vector, written when the request completes and valid
+ * from then until the caller frees it.  *ticket identifies the request. */
+int sg_submit(sg_server* s, const sg_problem* prob, const sg_options* opt,
+              double* x_out, uint64_t* ticket);
+
+/* SG_PENDING while queued or running; otherwise the request's final status,
+ * with *info filled (latency_ms = submit to completion).  A finished ticket
+ * stays valid until sg_server_destroy. */
+int sg_poll(sg_server* s, uint64_t ticket, sg_solve_info* info);
+
+/* Cancel a queued request (SG_OK) or report that it already started or ended
+ * (SG_ERR_INVALID).  A cancelled ticket polls as SG_ERR_CANCELLED. */
+int sg_cancel(sg_server* s, uint64_t ticket);
+
+/* Serving statistics since creation: completed count, p50/p99 latency (ms),
+ * completions per second of wall time. */
+int sg_server_stats(sg_server* s, int64_t* completed, double* p50_ms, double* p99_ms,
+                    double* solves_per_s);
+
+/* Block until every submitted request finished, then stop the scheduler and
+ * free all device memory (NULL is ignored). */
+void sg_server_destroy(sg_server* s);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char* sg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SG_H */

@@ -1,0 +1,208 @@
+// Internal declarations shared by the library's translation units.
+//
+// Data layout in device memory (one handle = `B` members of one shape):
+//   field block   [t][j][node]        n_t * n_xi * (n+1)^2 values, zero boundary ring
+//   KKT vector    [y | u | lambda]    three field blocks
+//   batch         [member][...]       members back to back
+// A "column" is one (member, t, j) slice of (n+1)^2 nodes; kernels address
+// columns through ColMap so that the same kernel serves a KKT vector, a
+// scratch block, a degree level of the hierarchical sweep or a multigrid level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sg.h"
+
+namespace sg {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SG_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::sg::Error(SG_ERR_HIP, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxM = 16;        // random variables
+constexpr int kMaxP = 8;         // polynomial degree
+constexpr int kMaxLevels = 12;   // multigrid levels (n <= 4096 down to 8)
+constexpr int kMaxSmooth = 4;    // Chebyshev smoothing degree per side
+constexpr int kCoarseN = 8;      // coarsest multigrid grid (elements per side)
+constexpr int kCoarsePad = 64;   // (kCoarseN-1)^2 = 49 unknowns padded for MFMA tiles
+constexpr int kMaxRestart = 64;
+
+// Per-member scalars used by the kernels (device array, one entry per member).
+struct MemberDev {
+    double beta, gamma, tau;   // tau = 1 for steady problems
+    double c0;                 // constant mean coefficient kappa_0
+    double a1, b1;             // mean block A1 = a1 K_unit + b1 M
+    double off_scale;          // factor on off-level products (1 steady, tau time)
+    double hg;                 // 1 + gamma
+};
+
+// Per-member, per-multigrid-level constants (device array [member][level]).
+struct LevelDev {
+    double wc, we, wd;               // 9-point stencil weights of a1 K + b1 M_h: centre, edge, corner
+    double dinv;                     // 1 / diagonal
+    double pre[kMaxSmooth][2];       // Chebyshev smoothing steps (c_d, c_r), pre
+    double post[kMaxSmooth][2];      // post
+};
+
+// Column addressing: column c in [0, ncols) -> member b = c / (L*nt),
+// t = (c / L) % nt, local l = c % L, chaos j = j0 + l;
+// address = base + b*mstride + t*tstride + j*nodes.
+struct ColMap {
+    int64_t mstride, tstride, nodes;
+    int L, nt, j0;
+    __host__ __device__ int64_t off(int c) const {
+        int l = c % L;
+        int q = c / L;
+        int t = q % nt;
+        int b = q / nt;
+        return (int64_t)b * mstride + (int64_t)t * tstride + (int64_t)(j0 + l) * nodes;
+    }
+    __host__ __device__ int member(int c) const { return c / (L * nt); }
+    __host__ __device__ int tstep(int c) const { return (c / L) % nt; }
+    __host__ __device__ int chaos(int c) const { return j0 + c % L; }
+};
+
+inline ColMap contiguous_cols(int ncols, int64_t nodes) {
+    ColMap m;
+    m.mstride = 0; m.tstride = 0; m.nodes = nodes; m.L = ncols; m.nt = 1; m.j0 = 0;
+    return m;
+}
+
+// Shape of a handle.
+struct Shape {
+    int n, M, P, nt;           // nt = 1 for steady
+    bool time;
+    int nxi;
+    int64_t nodes;             // (n+1)^2
+    int64_t tstride;           // nxi * nodes
+    int64_t blk;               // nt * nxi * nodes
+    int off[kMaxP + 2];        // degree level offsets
+    int nlev_mg;               // multigrid levels
+    int mg_n[kMaxLevels];      // elements per side per multigrid level
+};
+
+// Host-side tables built by setup.
+struct HostTables {
+    std::vector<int32_t> alpha;       // [nxi][M]
+    std::vector<int32_t> nbr_idx;     // [nxi][M][2]
+    std::vector<double> nbr_val;      // [nxi][M][2]
+};
+
+// ---- kernel launchers (kernels.hip) ------------------------------------------
+struct OpDev {                   // device pointers describing the operator of a handle
+    const int32_t* nbr_idx;      // [nxi][M][2]
+    const double* nbr_val;       // [nxi][M][2]
+    const void* coef;            // [member][M+1][n][n] in T
+    int64_t coef_mstride;        // elements per member (0 = shared)
+    const MemberDev* mem;        // [member]
+    int mem_shared;              // 1 = all vectors use member 0
+};
+
+// SG apply family.  `modes_mask` selects modes 1..M (bit k-1); mode 0 (mean,
+// constant coefficient) is applied when with_mean != 0.
+template <typename T>
+void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
+
+template <typename T>
+void launch_kkt_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
+
+// hGS off-level right-hand side for degree level d:
+//   out_j = base_j - off_scale * sum_{k in modes} K_k (g- V_{j-e_k} [lower] + g+ V_{j+e_k} [upper])
+template <typename T>
+void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t modes_mask, int use_lower,
+                    int use_upper, const T* base, ColMap base_map, const T* V, ColMap v_map, T* out,
+                    ColMap out_map, int nmembers, hipStream_t st);
+
+// Chebyshev semi-iteration for the mass blocks (state + control) of nvec KKT vectors.
+template <typename T>
+void launch_mass_cheb(const Shape& s, const OpDev& op, const T* r, T* z, T* bufA, T* bufB,
+                      int nvec, int steps, hipStream_t st);
+
+// W = scale_col * M V  (column scale = tau * D_t * (1+gamma if j>0 else 1) * extra)
+template <typename T>
+void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap, T* W, ColMap wmap,
+                        int ncols, int nvec_members, hipStream_t st);
+
+// Multigrid
+struct MgDev {
+    const LevelDev* lev;          // [member][kMaxLevels]
+    const void* coarse_inv;       // [member][64][64] in T
+    int coarse_direct;            // 1 if the fine grid is the coarsest grid
+};
+template <typename T>
+void launch_mg_cheb_first(int m, const LevelDev* lev, int lvl, int which, const T* b, ColMap bmap,
+                          T* x, ColMap xmap, T* d, int ncols, int cols_per_member, hipStream_t st);
+template <typename T>
+void launch_mg_cheb_step(int m, const LevelDev* lev, int lvl, int which, int step, const T* b,
+                         ColMap bmap, const T* xin, ColMap xinmap, T* xout, ColMap xoutmap, T* d,
+                         int ncols, int cols_per_member, hipStream_t st);
+template <typename T>
+void launch_mg_residual(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, const T* x,
+                        ColMap xmap, T* r, int ncols, int cols_per_member, hipStream_t st);
+template <typename T>
+void launch_mg_restrict(int mc, const T* rf, T* bc, int ncols, hipStream_t st);
+template <typename T>
+void launch_mg_prolong_add(int mc, const T* xc, T* xf, int ncols, hipStream_t st);
+template <typename T>
+void launch_mg_coarse(const T* ainv, const T* bc, ColMap bmap, T* xc, ColMap xmap, int ncols,
+                      int cols_per_member, hipStream_t st);
+
+// BLAS-like kernels on flat vectors (FP64 Krylov arithmetic).
+void launch_multidot(const double* V, int64_t vstride, int nv, const double* w, int64_t n,
+                     int nmem, int64_t mstride, double* partial, int nblk, hipStream_t st);
+void launch_cgs_update_dot(const double* V, int64_t vstride, int nv, const double* h, int hstride,
+                           double* w, int64_t n, int nmem, int64_t mstride, double* partial,
+                           int nblk, hipStream_t st);
+void launch_cgs_update_norm(const double* V, int64_t vstride, int nv, const double* h, int hstride,
+                            const double* w, double* out, int64_t n, int nmem, int64_t mstride,
+                            double* partial, int nblk, hipStream_t st);
+void launch_reduce_partials(const double* partial, int nblk, int nv, int nmem, double* out,
+                            int out_stride, int out_offset, hipStream_t st);
+void launch_scale_vec(double* v, const double* sdev, int sstride, int64_t n, int nmem,
+                      int64_t mstride, hipStream_t st);
+void launch_multi_axpy(const void* Z, int zfp32, int64_t zstride, int nv_max, const int* nv_mem,
+                       const double* y, int ystride, double* x, int64_t n, int nmem,
+                       int64_t mstride, hipStream_t st);
+void launch_sub_norm(const double* b, double* r, int64_t n, int nmem, int64_t mstride,
+                     double* partial, int nblk, hipStream_t st);   // r = b - r, partial ||r||^2
+void launch_norm(const double* x, int64_t n, int nmem, int64_t mstride, double* partial, int nblk,
+                 hipStream_t st);
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
+void launch_cast_d2f(const double* x, float* y, int64_t n, hipStream_t st);
+void launch_cast_f2d(const float* x, double* y, int64_t n, hipStream_t st);
+void launch_copy_scale_rows(const double* src, double* dst, const double* inv_norm, int64_t n,
+                            int nmem, int64_t mstride, hipStream_t st);
+template <typename T>
+void launch_zero_ring(T* x, int n, int64_t ncols, hipStream_t st);
+
+// Arnoldi bookkeeping on the device (one thread per member).
+struct KrylovDev {
+    double* H;        // [member][(restart+1)][restart] column-major per member: H[i + j*(restart+1)]
+    double* cs;       // [member][restart]
+    double* sn;       // [member][restart]
+    double* g;        // [member][restart+1]
+    double* h1;       // [member][restart+1] first CGS pass coefficients
+    double* h2;       // [member][restart+1] second pass coefficients
+    double* nrm;      // [member] ||w2||^2 then 1/||w2||
+    double* y;        // [member][restart]
+    double* resid;    // [member] |g_{j+1}| (estimate)
+    int* active;      // [member] 1 while iterating in the current cycle
+};
+void launch_arnoldi_finish(KrylovDev k, int restart, int j, int nmem, hipStream_t st);
+void launch_cycle_start(KrylovDev k, int restart, const double* beta0, int nmem, hipStream_t st);
+void launch_back_solve(KrylovDev k, int restart, const int* jend, int nmem, hipStream_t st);
+
+}  // namespace sg

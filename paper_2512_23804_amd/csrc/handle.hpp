@@ -1,0 +1,121 @@
+// Handle: one batch of same-shape problems and its device state.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace sg {
+
+// Grow-only named device buffers owned by a handle.
+class Workspace {
+  public:
+    ~Workspace() { release(); }
+    void* get(const std::string& name, size_t bytes) {
+        auto it = bufs_.find(name);
+        if (it != bufs_.end() && it->second.second >= bytes) return it->second.first;
+        if (it != bufs_.end()) {
+            (void)hipFree(it->second.first);
+            bufs_.erase(it);
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes < 256 ? 256 : bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(SG_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes for '" + name +
+                                          "' failed: " + hipGetErrorString(e));
+        }
+        bufs_[name] = {p, bytes};
+        total_ += bytes;
+        return p;
+    }
+    template <typename T>
+    T* get_t(const std::string& name, size_t count) {
+        return static_cast<T*>(get(name, count * sizeof(T)));
+    }
+    void release() {
+        for (auto& kv : bufs_) (void)hipFree(kv.second.first);
+        bufs_.clear();
+        total_ = 0;
+    }
+    size_t total() const { return total_; }
+
+  private:
+    std::map<std::string, std::pair<void*, size_t>> bufs_;
+    size_t total_ = 0;
+};
+
+struct Handle {
+    Shape s{};
+    int B = 1;                          // members
+    sg_options opt{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    double t_setup_ms = 0.0;
+
+    HostTables ht;
+    std::vector<MemberDev> mem_host;
+    std::vector<LevelDev> lev_host;     // [member][kMaxLevels]
+    std::vector<double> coef_host;      // [member][M+1][n][n]
+    std::vector<double> ainv_host;      // [member][64][64]
+    std::vector<double> rhs_host;       // [member][3][nt][nxi][nodes] (sparse in practice)
+
+    // device-resident constant data
+    int32_t* d_nbr_idx = nullptr;
+    double* d_nbr_val = nullptr;
+    double* d_coef64 = nullptr;
+    float* d_coef32 = nullptr;
+    MemberDev* d_mem = nullptr;
+    LevelDev* d_lev = nullptr;
+    double* d_ainv64 = nullptr;
+    float* d_ainv32 = nullptr;
+    double* d_rhs = nullptr;
+
+    Workspace ws;
+    double* h_pinned = nullptr;        // host-pinned scratch for small readbacks
+    size_t h_pinned_count = 0;
+
+    uint32_t modes_mask() const {
+        const int r = opt.truncation_r <= 0 ? s.M + 1 : opt.truncation_r;
+        uint32_t m = 0;
+        for (int k = 1; k < r && k <= s.M; ++k) m |= 1u << (k - 1);
+        return m;
+    }
+    template <typename T>
+    OpDev op(bool shared) const {
+        OpDev o;
+        o.nbr_idx = d_nbr_idx;
+        o.nbr_val = d_nbr_val;
+        o.coef = sizeof(T) == 8 ? (const void*)d_coef64 : (const void*)d_coef32;
+        o.coef_mstride = shared ? 0 : (int64_t)(s.M + 1) * s.n * s.n;
+        o.mem = d_mem;
+        o.mem_shared = shared ? 1 : 0;
+        return o;
+    }
+    template <typename T>
+    const T* ainv() const {
+        return sizeof(T) == 8 ? (const T*)(const void*)d_ainv64 : (const T*)(const void*)d_ainv32;
+    }
+    ~Handle();
+};
+
+// setup.cpp
+void default_options(sg_options* o);
+void validate(const sg_problem* probs, int count, const sg_options* opt);   // throws Error
+std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt, hipStream_t st);
+std::vector<int32_t> multi_indices(int M, int P);
+int binom(int n, int k);
+
+// solver.cpp
+template <typename T>
+void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st);
+template <typename T>
+void kkt_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st);
+template <typename T>
+void operator_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st);
+int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info);
+
+}  // namespace sg

@@ -1,0 +1,1122 @@
+// HIP kernels for gfx950 (MI355X): the stochastic-Galerkin operator and KKT
+// applies, the hierarchical Gauss-Seidel right-hand sides, Chebyshev mass
+// solves, geometric multigrid and the FP64 Krylov vector arithmetic.
+//
+// All stencils are Q1 on the uniform n x n grid of [0,1]^2 (h = 1/n), node
+// (ix, iy) at flat index iy*(n+1)+ix, element (ex, ey) at ey*n+ex.
+//   unit stiffness K (constant coefficient): centre 8/3, eight neighbours -1/3
+//   mass M_h: (h^2/36) [16 centre, 4 edge, 1 corner]
+//   stiffness of a per-element coefficient c_e at node p:
+//     (1/6) sum_{e contains p} c_e (4 x_p - x_h(e) - x_v(e) - 2 x_d(e))
+//   with h, v, d the horizontal, vertical and diagonal partners of p in e.
+// Boundary nodes are Dirichlet (eliminated): outputs write 0 there and inputs
+// read there are treated as 0.
+#include "common.hpp"
+
+namespace sg {
+
+namespace {
+
+constexpr int TX = 64;   // nodes per block row (one wavefront)
+constexpr int TY = 4;    // block rows
+
+template <typename T>
+struct Nine {
+    T c, w, e, s, n, sw, se, nw, ne;
+};
+
+// Load the 3x3 neighbourhood of interior node (ix, iy); neighbours on the
+// boundary ring read as zero.
+template <typename T>
+__device__ __forceinline__ Nine<T> load9(const T* __restrict__ x, int n, int ix, int iy) {
+    const int N1 = n + 1;
+    const int64_t p = (int64_t)iy * N1 + ix;
+    const bool w = ix > 1, e = ix < n - 1, s = iy > 1, nn = iy < n - 1;
+    Nine<T> v;
+    v.c = x[p];
+    v.w = w ? x[p - 1] : T(0);
+    v.e = e ? x[p + 1] : T(0);
+    v.s = s ? x[p - N1] : T(0);
+    v.n = nn ? x[p + N1] : T(0);
+    v.sw = (s && w) ? x[p - N1 - 1] : T(0);
+    v.se = (s && e) ? x[p - N1 + 1] : T(0);
+    v.nw = (nn && w) ? x[p + N1 - 1] : T(0);
+    v.ne = (nn && e) ? x[p + N1 + 1] : T(0);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void axpy9(Nine<T>& a, T g, const Nine<T>& b) {
+    a.c += g * b.c; a.w += g * b.w; a.e += g * b.e; a.s += g * b.s; a.n += g * b.n;
+    a.sw += g * b.sw; a.se += g * b.se; a.nw += g * b.nw; a.ne += g * b.ne;
+}
+
+template <typename T>
+__device__ __forceinline__ Nine<T> scale9(T g, const Nine<T>& b) {
+    Nine<T> a;
+    a.c = g * b.c; a.w = g * b.w; a.e = g * b.e; a.s = g * b.s; a.n = g * b.n;
+    a.sw = g * b.sw; a.se = g * b.se; a.nw = g * b.nw; a.ne = g * b.ne;
+    return a;
+}
+
+template <typename T>
+__device__ __forceinline__ T unit_stiff(const Nine<T>& v) {
+    return T(8.0 / 3.0) * v.c - T(1.0 / 3.0) * (v.w + v.e + v.s + v.n + v.sw + v.se + v.nw + v.ne);
+}
+
+template <typename T>
+__device__ __forceinline__ T mass9(const Nine<T>& v, T h2_36) {
+    return h2_36 * (T(16) * v.c + T(4) * (v.w + v.e + v.s + v.n) + (v.sw + v.se + v.nw + v.ne));
+}
+
+// Stiffness with per-element coefficients c (plane [ey][ex] of one mode).
+template <typename T>
+__device__ __forceinline__ T var_stiff(const T* __restrict__ c, int n, int ix, int iy, const Nine<T>& v) {
+    const T cSW = c[(iy - 1) * n + ix - 1], cSE = c[(iy - 1) * n + ix];
+    const T cNW = c[iy * n + ix - 1], cNE = c[iy * n + ix];
+    T s = T(4) * v.c * ((cSW + cSE) + (cNW + cNE));
+    s -= v.w * (cSW + cNW) + v.e * (cSE + cNE) + v.s * (cSW + cSE) + v.n * (cNW + cNE);
+    s -= T(2) * (cSW * v.sw + cSE * v.se + cNW * v.nw + cNE * v.ne);
+    return s * T(1.0 / 6.0);
+}
+
+// (A X)_j at interior node (ix, iy) for one (member, t) block X [j][node]:
+//   c0 K_unit X_j + sum_{k in mask} K_k (g- X_{j-e_k} + g+ X_{j+e_k})
+template <typename T>
+__device__ __forceinline__ T sg_node(const T* __restrict__ X, int64_t nodes, int j, int n, int ix, int iy,
+                                     int M, const int32_t* __restrict__ nidx,
+                                     const double* __restrict__ nval, const T* __restrict__ coef,
+                                     int64_t cplane, T c0, bool with_mean, uint32_t mask,
+                                     bool lower, bool upper) {
+    T acc = T(0);
+    if (with_mean) acc = c0 * unit_stiff(load9(X + (int64_t)j * nodes, n, ix, iy));
+    for (int k = 1; k <= M; ++k) {
+        if (!((mask >> (k - 1)) & 1u)) continue;
+        const int base = (j * M + (k - 1)) * 2;
+        const int im = lower ? nidx[base] : -1;
+        const int ip = upper ? nidx[base + 1] : -1;
+        if (im < 0 && ip < 0) continue;
+        Nine<T> w;
+        if (im >= 0) {
+            w = scale9(T(nval[base]), load9(X + (int64_t)im * nodes, n, ix, iy));
+            if (ip >= 0) axpy9(w, T(nval[base + 1]), load9(X + (int64_t)ip * nodes, n, ix, iy));
+        } else {
+            w = scale9(T(nval[base + 1]), load9(X + (int64_t)ip * nodes, n, ix, iy));
+        }
+        acc += var_stiff(coef + (int64_t)k * cplane, n, ix, iy, w);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ int node_x() { return blockIdx.x % 0x7fffffff; }
+
+// Map a flat tile index to (ix0, iy0) tiles of TX x TY nodes.
+__device__ __forceinline__ void tile_coords(int n, int tile, int& ix, int& iy) {
+    const int tiles_x = (n + 1 + TX - 1) / TX;
+    ix = (tile % tiles_x) * TX + threadIdx.x % TX;
+    iy = (tile / tiles_x) * TY + threadIdx.x / TX;
+}
+
+constexpr int kJChunk = 8;
+
+// --------------------------------------------------------------------------
+// SG operator apply: y = A x for each (vector, t) block.
+// grid: x = node tiles, y = chaos chunks, z = nvec*nt slices.
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_sg_apply(int n, int M, int nxi, int nt, int64_t nodes,
+                                                  OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+    int ix, iy;
+    tile_coords(n, blockIdx.x, ix, iy);
+    if (ix > n || iy > n) return;
+    const int slice = blockIdx.z;
+    const int vec = slice / nt;
+    const int mem = op.mem_shared ? 0 : vec;
+    const int64_t off = (int64_t)slice * nxi * nodes;
+    const T* X = x + off;
+    T* Y = y + off;
+    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const int64_t cplane = (int64_t)n * n;
+    const T c0 = T(op.mem[mem].c0);
+    const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
+    const int64_t p = (int64_t)iy * (n + 1) + ix;
+    const int j0 = blockIdx.y * kJChunk;
+    const int j1 = min(nxi, j0 + kJChunk);
+    for (int j = j0; j < j1; ++j) {
+        T v = T(0);
+        if (interior)
+            v = sg_node<T>(X, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0, true,
+                           0xffffffffu, true, true);
+        Y[(int64_t)j * nodes + p] = v;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Fused KKT apply.  Steady (eq. stoch-system, matricized eq. stoch-system-m with A_l):
+//   R^Y = M Y H^gamma - A Lambda;  R^U = beta M U + M Lambda;  R^L = -A Y + M U.
+// Time (eq. KKT:stoch-time-dependent), L = M-cal + tau A, D = diag(1/2,1..1,1/2):
+//   R^Y_t = tau D_t M_gamma Y_t - (M L_t + tau A L_t) + M L_{t+1}
+//   R^U_t = beta tau D_t M U_t + tau M L_t
+//   R^L_t = -(M Y_t + tau A Y_t) + M Y_{t-1} + tau M U_t
+// grid: x = node tiles, y = chaos chunks, z = nvec*nt.
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_kkt_apply(int n, int M, int nxi, int nt, int time, int64_t nodes,
+                                                   OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+    int ix, iy;
+    tile_coords(n, blockIdx.x, ix, iy);
+    if (ix > n || iy > n) return;
+    const int slice = blockIdx.z;
+    const int vec = slice / nt;
+    const int t = slice % nt;
+    const int mem = op.mem_shared ? 0 : vec;
+    const int64_t blk = (int64_t)nt * nxi * nodes;
+    const int64_t tst = (int64_t)nxi * nodes;
+    const T* Yv = x + (int64_t)vec * 3 * blk;
+    const T* Uv = Yv + blk;
+    const T* Lv = Uv + blk;
+    T* RY = y + (int64_t)vec * 3 * blk;
+    T* RU = RY + blk;
+    T* RL = RU + blk;
+    const MemberDev md = op.mem[mem];
+    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const int64_t cplane = (int64_t)n * n;
+    const T c0 = T(md.c0);
+    const T h = T(1) / T(n);
+    const T h2_36 = h * h / T(36);
+    const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
+    const int64_t p = (int64_t)iy * (n + 1) + ix;
+    const T tau = T(md.tau);
+    const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
+    const T beta = T(md.beta);
+    const T hg = T(md.hg);
+    const int j0 = blockIdx.y * kJChunk;
+    const int j1 = min(nxi, j0 + kJChunk);
+    const T* Yt = Yv + t * tst;
+    const T* Ut = Uv + t * tst;
+    const T* Lt = Lv + t * tst;
+    for (int j = j0; j < j1; ++j) {
+        const int64_t q = (int64_t)j * nodes + p;
+        T ry = T(0), ru = T(0), rl = T(0);
+        if (interior) {
+            const T AY = sg_node<T>(Yt, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0,
+                                    true, 0xffffffffu, true, true);
+            const T AL = sg_node<T>(Lt, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0,
+                                    true, 0xffffffffu, true, true);
+            const T MY = mass9(load9(Yt + (int64_t)j * nodes, n, ix, iy), h2_36);
+            const T MU = mass9(load9(Ut + (int64_t)j * nodes, n, ix, iy), h2_36);
+            const T ML = mass9(load9(Lt + (int64_t)j * nodes, n, ix, iy), h2_36);
+            const T hgj = j == 0 ? T(1) : hg;
+            if (!time) {
+                ry = hgj * MY - AL;
+                ru = beta * MU + ML;
+                rl = MU - AY;
+            } else {
+                T MLn = T(0), MYp = T(0);
+                if (t + 1 < nt) MLn = mass9(load9(Lt + tst + (int64_t)j * nodes, n, ix, iy), h2_36);
+                if (t > 0) MYp = mass9(load9(Yt - tst + (int64_t)j * nodes, n, ix, iy), h2_36);
+                ry = tau * Dt * hgj * MY - (ML + tau * AL) + MLn;
+                ru = beta * tau * Dt * MU + tau * ML;
+                rl = -(MY + tau * AY) + MYp + tau * MU;
+            }
+        }
+        RY[t * tst + q] = ry;
+        RU[t * tst + q] = ru;
+        RL[t * tst + q] = rl;
+    }
+}
+
+// --------------------------------------------------------------------------
+// hGS off-level right-hand side for degree level d (Algorithm 1, eq. alg-hGS2
+// with the affine coupling: the lower level contributes E, the upper F).
+// grid: x = node tiles, y = level-column chunks, z = nmembers*nt.
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_hgs_rhs(int n, int M, int nxi, int nt, int64_t nodes, OpDev op,
+                                                 int j0lvl, int L, uint32_t mask, int lower, int upper,
+                                                 const T* __restrict__ base, ColMap bmap,
+                                                 const T* __restrict__ V, ColMap vmap,
+                                                 T* __restrict__ out, ColMap omap) {
+    int ix, iy;
+    tile_coords(n, blockIdx.x, ix, iy);
+    if (ix > n || iy > n) return;
+    const int slice = blockIdx.z;           // member*nt + t
+    const int mem_i = slice / nt;
+    const int t = slice % nt;
+    const int mem = op.mem_shared ? 0 : mem_i;
+    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const int64_t cplane = (int64_t)n * n;
+    const T scale = T(op.mem[mem].off_scale);
+    const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
+    const int64_t p = (int64_t)iy * (n + 1) + ix;
+    const T* Vb = V + (int64_t)mem_i * vmap.mstride + (int64_t)t * vmap.tstride;
+    const int l0 = blockIdx.y * kJChunk;
+    const int l1 = min(L, l0 + kJChunk);
+    for (int l = l0; l < l1; ++l) {
+        const int c = slice * L + l;
+        const int j = j0lvl + l;
+        T v = T(0);
+        if (interior) {
+            v = base[bmap.off(c) + p];
+            if (mask)
+                v -= scale * sg_node<T>(Vb, vmap.nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane,
+                                        T(0), false, mask, lower != 0, upper != 0);
+        }
+        out[omap.off(c) + p] = v;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Chebyshev semi-iteration on the mass matrix (Golub-Varga), state and
+// control blocks.  D = 1.25 diag(M) = 1.25 * 4h^2/9, rho = 0.8.
+// Column l of a vector's first 2*nt*nxi columns: var = l / (nt*nxi),
+// t = (l / nxi) % nt, j = l % nxi; final scale 1/(hg_j tau D_t) for the
+// state, 1/(beta tau D_t) for the control (tau = D_t = 1 when steady).
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass_cheb_step(int n, int nxi, int nt, int time, int64_t nodes,
+                                                        OpDev op, int64_t vstride, const T* __restrict__ r,
+                                                        const T* __restrict__ xk, const T* __restrict__ xkm1,
+                                                        T* __restrict__ xout, T omega, int first, int last) {
+    int ix, iy;
+    tile_coords(n, blockIdx.x, ix, iy);
+    if (ix > n || iy > n) return;
+    const int vec = blockIdx.z;
+    const int mem = op.mem_shared ? 0 : vec;
+    const int64_t p = (int64_t)iy * (n + 1) + ix;
+    const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
+    const T h = T(1) / T(n);
+    const T h2_36 = h * h / T(36);
+    const T dinv = T(1) / (T(1.25) * T(4) * h * h / T(9));
+    const int ncols = 2 * nt * nxi;
+    const int l0 = blockIdx.y * kJChunk;
+    const int l1 = min(ncols, l0 + kJChunk);
+    const MemberDev md = op.mem[mem];
+    for (int l = l0; l < l1; ++l) {
+        const int64_t q = (int64_t)vec * vstride + (int64_t)l * nodes + p;       // r / out addressing (KKT vector)
+        const int64_t qs = ((int64_t)vec * ncols + l) * nodes + p;                // scratch addressing
+        T v = T(0);
+        if (interior) {
+            const T b = r[q];
+            if (first) {
+                v = dinv * b;
+            } else {
+                const T res = b - mass9(load9(xk + ((int64_t)vec * ncols + l) * nodes, n, ix, iy), h2_36);
+                v = omega * (dinv * res + xk[qs] - xkm1[qs]) + xkm1[qs];
+            }
+            if (last) {
+                const int var = l / (nt * nxi);
+                const int t = (l / nxi) % nt;
+                const int j = l % nxi;
+                const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
+                const T tau = T(md.tau);
+                const T s = var == 0 ? (j == 0 ? T(1) : T(md.hg)) : T(md.beta);
+                v = v / (s * tau * Dt);
+            }
+        }
+        if (last)
+            xout[q] = v;
+        else
+            xout[qs] = v;
+    }
+}
+
+// W = tau D_t (1 or hg) M V on the columns of a field block (Schur block middle factor).
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass_scaled(int n, int nxi, int nt, int time, int64_t nodes, OpDev op,
+                                                     const T* __restrict__ V, ColMap vmap, T* __restrict__ W,
+                                                     ColMap wmap, int ncols) {
+    int ix, iy;
+    tile_coords(n, blockIdx.x, ix, iy);
+    if (ix > n || iy > n) return;
+    const int64_t p = (int64_t)iy * (n + 1) + ix;
+    const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
+    const T h = T(1) / T(n);
+    const T h2_36 = h * h / T(36);
+    const int c0 = blockIdx.y * kJChunk;
+    const int c1 = min(ncols, c0 + kJChunk);
+    for (int c = c0; c < c1; ++c) {
+        const int mem_i = vmap.member(c);
+        const int mem = op.mem_shared ? 0 : mem_i;
+        const MemberDev md = op.mem[mem];
+        const int t = vmap.tstep(c);
+        const int j = vmap.chaos(c);
+        T v = T(0);
+        if (interior) {
+            const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
+            const T s = T(md.tau) * Dt * (j == 0 ? T(1) : T(md.hg));
+            v = s * mass9(load9(V + vmap.off(c), n, ix, iy), h2_36);
+        }
+        W[wmap.off(c) + p] = v;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Multigrid kernels on the m x m grid of one level.  Operator a K + b M_h as a
+// constant 9-point stencil (wc, we, wd); all columns of a launch share a level.
+// --------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T op9(const Nine<T>& v, T wc, T we, T wd) {
+    return wc * v.c + we * (v.w + v.e + v.s + v.n) + wd * (v.sw + v.se + v.nw + v.ne);
+}
+
+// x = d = c_r D^{-1} b (first Chebyshev step from a zero guess)
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_cheb_first(int m, const LevelDev* __restrict__ lev, int lvl, int which,
+                                                       const T* __restrict__ b, ColMap bmap, T* __restrict__ x,
+                                                       ColMap xmap, T* __restrict__ d, int ncols, int cpm) {
+    int ix, iy;
+    tile_coords(m, blockIdx.x, ix, iy);
+    if (ix > m || iy > m) return;
+    const int64_t nodes = (int64_t)(m + 1) * (m + 1);
+    const int64_t p = (int64_t)iy * (m + 1) + ix;
+    const bool interior = ix > 0 && ix < m && iy > 0 && iy < m;
+    const int c0 = blockIdx.y * kJChunk;
+    const int c1 = min(ncols, c0 + kJChunk);
+    for (int c = c0; c < c1; ++c) {
+        const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
+        const T cr = T(which == 0 ? L.pre[0][1] : L.post[0][1]);
+        T v = T(0);
+        if (interior) v = cr * T(L.dinv) * b[bmap.off(c) + p];
+        x[xmap.off(c) + p] = v;
+        d[(int64_t)c * nodes + p] = v;
+    }
+}
+
+// r = b - A xin; d = c_d d + c_r D^{-1} r; xout = xin + d
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_cheb_step(int m, const LevelDev* __restrict__ lev, int lvl, int which,
+                                                      int step, const T* __restrict__ b, ColMap bmap,
+                                                      const T* __restrict__ xin, ColMap xinmap,
+                                                      T* __restrict__ xout, ColMap xoutmap, T* __restrict__ d,
+                                                      int ncols, int cpm) {
+    int ix, iy;
+    tile_coords(m, blockIdx.x, ix, iy);
+    if (ix > m || iy > m) return;
+    const int64_t nodes = (int64_t)(m + 1) * (m + 1);
+    const int64_t p = (int64_t)iy * (m + 1) + ix;
+    const bool interior = ix > 0 && ix < m && iy > 0 && iy < m;
+    const int c0 = blockIdx.y * kJChunk;
+    const int c1 = min(ncols, c0 + kJChunk);
+    for (int c = c0; c < c1; ++c) {
+        const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
+        const double* cf = which == 0 ? L.pre[step] : L.post[step];
+        T v = T(0);
+        const int64_t qd = (int64_t)c * nodes + p;
+        if (interior) {
+            const T* xc = xin + xinmap.off(c);
+            const T r = b[bmap.off(c) + p] - op9(load9(xc, m, ix, iy), T(L.wc), T(L.we), T(L.wd));
+            const T dn = T(cf[0]) * d[qd] + T(cf[1]) * T(L.dinv) * r;
+            d[qd] = dn;
+            v = xc[p] + dn;
+        }
+        xout[xoutmap.off(c) + p] = v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_residual(int m, const LevelDev* __restrict__ lev, int lvl,
+                                                     const T* __restrict__ b, ColMap bmap, const T* __restrict__ x,
+                                                     ColMap xmap, T* __restrict__ r, int ncols, int cpm) {
+    int ix, iy;
+    tile_coords(m, blockIdx.x, ix, iy);
+    if (ix > m || iy > m) return;
+    const int64_t nodes = (int64_t)(m + 1) * (m + 1);
+    const int64_t p = (int64_t)iy * (m + 1) + ix;
+    const bool interior = ix > 0 && ix < m && iy > 0 && iy < m;
+    const int c0 = blockIdx.y * kJChunk;
+    const int c1 = min(ncols, c0 + kJChunk);
+    for (int c = c0; c < c1; ++c) {
+        const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
+        T v = T(0);
+        if (interior)
+            v = b[bmap.off(c) + p] - op9(load9(x + xmap.off(c), m, ix, iy), T(L.wc), T(L.we), T(L.wd));
+        r[(int64_t)c * nodes + p] = v;
+    }
+}
+
+// Coarse b(I,J) = sum of fine residual with bilinear weights (R = P^T):
+// 1 at (2I,2J), 1/2 at edge partners, 1/4 at corner partners.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_restrict(int mc, const T* __restrict__ rf, T* __restrict__ bc, int ncols) {
+    int ix, iy;
+    tile_coords(mc, blockIdx.x, ix, iy);
+    if (ix > mc || iy > mc) return;
+    const int mf = 2 * mc;
+    const int64_t nf = (int64_t)(mf + 1) * (mf + 1);
+    const int64_t ncn = (int64_t)(mc + 1) * (mc + 1);
+    const int64_t p = (int64_t)iy * (mc + 1) + ix;
+    const bool interior = ix > 0 && ix < mc && iy > 0 && iy < mc;
+    const int c0 = blockIdx.y * kJChunk;
+    const int c1 = min(ncols, c0 + kJChunk);
+    for (int c = c0; c < c1; ++c) {
+        T v = T(0);
+        if (interior) {
+            const T* r = rf + (int64_t)c * nf;
+            const int64_t q = (int64_t)(2 * iy) * (mf + 1) + 2 * ix;
+            const int64_t F = mf + 1;
+            v = r[q] + T(0.5) * (r[q - 1] + r[q + 1] + r[q - F] + r[q + F]) +
+                T(0.25) * (r[q - F - 1] + r[q - F + 1] + r[q + F - 1] + r[q + F + 1]);
+        }
+        bc[(int64_t)c * ncn + p] = v;
+    }
+}
+
+// Fine x += P xc (bilinear interpolation of the coarse correction).
+template <typename T>
+__global__ __launch_bounds__(256) void k_mg_prolong_add(int mc, const T* __restrict__ xc, T* __restrict__ xf, int ncols) {
+    const int mf = 2 * mc;
+    int ix, iy;
+    tile_coords(mf, blockIdx.x, ix, iy);
+    if (ix > mf || iy > mf) return;
+    const int64_t nf = (int64_t)(mf + 1) * (mf + 1);
+    const int64_t ncn = (int64_t)(mc + 1) * (mc + 1);
+    const bool interior = ix > 0 && ix < mf && iy > 0 && iy < mf;
+    if (!interior) return;
+    const int64_t p = (int64_t)iy * (mf + 1) + ix;
+    const int I0 = ix >> 1, J0 = iy >> 1;
+    const int I1 = I0 + (ix & 1), J1 = J0 + (iy & 1);
+    const int C = mc + 1;
+    const int c0 = blockIdx.y * kJChunk;
+    const int c1 = min(ncols, c0 + kJChunk);
+    for (int c = c0; c < c1; ++c) {
+        const T* x = xc + (int64_t)c * ncn;
+        const T v = T(0.25) * (x[J0 * C + I0] + x[J0 * C + I1] + x[J1 * C + I0] + x[J1 * C + I1]);
+        xf[(int64_t)c * nf + p] += v;
+    }
+}
+
+// Coarse solve x = A_c^{-1} b on the 8x8 grid (49 unknowns padded to 64) with
+// FP64 MFMA 16x16x4 tiles: one wavefront computes a 64 x 16 block of
+// x = Ainv (64 x 64) * B (64 x 16 columns of one member).
+__global__ __launch_bounds__(64) void k_mg_coarse_f64(const double* __restrict__ ainv, const double* __restrict__ b,
+                                                      ColMap bmap, double* __restrict__ x, ColMap xmap, int ncols,
+                                                      int cpm) {
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x;
+    const int mem = blockIdx.y;
+    const int c_begin = mem * cpm + blockIdx.x * 16;
+    const int c_end = min((mem + 1) * cpm, ncols);
+    if (c_begin >= c_end) return;
+    const double* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad;
+    const int col = lane % 16;
+    const int kq = lane / 16;
+    const int c = c_begin + col;
+    const bool cvalid = c < c_end;
+    const int N1 = kCoarseN + 1;
+    v4d acc[4];
+    for (int rt = 0; rt < 4; ++rt) acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < kCoarsePad; kb += 4) {
+        const int k = kb + kq;                                   // unknown index 0..63
+        double bv = 0.0;
+        if (cvalid && k < (kCoarseN - 1) * (kCoarseN - 1)) {
+            const int ix = k % (kCoarseN - 1) + 1, iy = k / (kCoarseN - 1) + 1;
+            bv = b[bmap.off(c) + iy * N1 + ix];
+        }
+        for (int rt = 0; rt < 4; ++rt) {
+            const double av = A[(rt * 16 + col) * kCoarsePad + k];   // A[row = rt*16 + lane%16][k]
+            acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[rt], 0, 0, 0);
+        }
+    }
+    // acc[rt][i] holds row rt*16 + lane/16 + 4*i, column lane%16 (FP64 16x16x4 output layout)
+    if (cvalid) {
+        double* xo = x + xmap.off(c);
+        for (int rt = 0; rt < 4; ++rt) {
+            for (int i = 0; i < 4; ++i) {
+                const int row = rt * 16 + kq + 4 * i;
+                if (row < (kCoarseN - 1) * (kCoarseN - 1)) {
+                    const int ix = row % (kCoarseN - 1) + 1, iy = row / (kCoarseN - 1) + 1;
+                    xo[iy * N1 + ix] = acc[rt][i];
+                }
+            }
+        }
+        // boundary ring of the coarse column
+        for (int q = kq; q < N1 * N1; q += 4) {
+            const int ix = q % N1, iy = q / N1;
+            if (ix == 0 || iy == 0 || ix == kCoarseN || iy == kCoarseN) xo[q] = 0.0;
+        }
+    }
+}
+
+// FP32 coarse solve (plain FMA; the FP32 path has no FP64 MFMA operand type).
+__global__ __launch_bounds__(64) void k_mg_coarse_f32(const float* __restrict__ ainv, const float* __restrict__ b,
+                                                      ColMap bmap, float* __restrict__ x, ColMap xmap, int ncols,
+                                                      int cpm) {
+    const int mem = blockIdx.y;
+    const int c = mem * cpm + blockIdx.x;
+    if (blockIdx.x >= cpm || c >= ncols) return;
+    const float* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad;
+    const int N1 = kCoarseN + 1;
+    const int nu = (kCoarseN - 1) * (kCoarseN - 1);
+    __shared__ float bs[kCoarsePad];
+    const int lane = threadIdx.x;
+    const float* bc = b + bmap.off(c);
+    if (lane < nu) {
+        const int ix = lane % (kCoarseN - 1) + 1, iy = lane / (kCoarseN - 1) + 1;
+        bs[lane] = bc[iy * N1 + ix];
+    }
+    __syncthreads();
+    float* xo = x + xmap.off(c);
+    if (lane < nu) {
+        float s = 0.f;
+        for (int k = 0; k < nu; ++k) s += A[lane * kCoarsePad + k] * bs[k];
+        const int ix = lane % (kCoarseN - 1) + 1, iy = lane / (kCoarseN - 1) + 1;
+        xo[iy * N1 + ix] = s;
+    }
+    for (int q = lane; q < N1 * N1; q += 64) {
+        const int ix = q % N1, iy = q / N1;
+        if (ix == 0 || iy == 0 || ix == kCoarseN || iy == kCoarseN) xo[q] = 0.f;
+    }
+}
+
+template <typename T>
+__global__ void k_zero_ring(T* x, int n, int64_t ncols) {
+    const int64_t nodes = (int64_t)(n + 1) * (n + 1);
+    const int64_t per = 4 * (int64_t)n;
+    const int64_t total = per * ncols;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = i / per;
+        const int q = (int)(i % per);
+        int ix, iy;
+        if (q < n) { ix = q; iy = 0; }
+        else if (q < 2 * n) { ix = n; iy = q - n; }
+        else if (q < 3 * n) { ix = n - (q - 2 * n); iy = n; }
+        else { ix = 0; iy = n - (q - 3 * n); }
+        x[c * nodes + (int64_t)iy * (n + 1) + ix] = T(0);
+    }
+}
+
+// --------------------------------------------------------------------------
+// FP64 Krylov vector arithmetic.  Reductions are deterministic: each member's
+// vector is split into `nblk` fixed chunks, block partials are written to
+// memory and summed in a fixed order by k_reduce_partials.
+// --------------------------------------------------------------------------
+constexpr int RB = 256;      // threads per reduction block
+constexpr int MAXV = 32;     // basis vectors per multi-vector launch
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-reduce `nv` per-thread accumulators into partial[(mem*nvmax + i)*nblk + blk].
+__device__ __forceinline__ void block_reduce_store(double* acc, int nv, double* partial, int mem, int nvmax,
+                                                   int nblk) {
+    __shared__ double red[RB / 64][MAXV + 1];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int i = 0; i < nv; ++i) {
+        const double s = wave_sum(acc[i]);
+        if (lane == 0) red[wave][i] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nv) {
+        double s = 0.0;
+        for (int w = 0; w < RB / 64; ++w) s += red[w][threadIdx.x];
+        partial[((int64_t)mem * nvmax + threadIdx.x) * nblk + blockIdx.x] = s;
+    }
+}
+
+__device__ __forceinline__ void chunk_range(int64_t n, int nblk, int blk, int64_t& lo, int64_t& hi) {
+    const int64_t per = (n + nblk - 1) / nblk;
+    lo = (int64_t)blk * per;
+    hi = lo + per < n ? lo + per : n;
+}
+
+// partial[i] = V_i . w  (i < nv)
+__global__ __launch_bounds__(RB) void k_multidot(const double* __restrict__ V, int64_t vstride, int nv,
+                                                 const double* __restrict__ w, int64_t n, int64_t mstride,
+                                                 double* __restrict__ partial, int nblk) {
+    const int mem = blockIdx.y;
+    int64_t lo, hi;
+    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    double acc[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) acc[i] = 0.0;
+    const double* wm = w + mem * mstride;
+    const double* Vm = V + mem * mstride;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+        const double we = wm[e];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+            if (i < nv) acc[i] += Vm[i * vstride + e] * we;
+    }
+    block_reduce_store(acc, nv, partial, mem, MAXV, nblk);
+}
+
+// w1 = w - sum_i h_i V_i (written to w), partial[i] = V_i . w1
+__global__ __launch_bounds__(RB) void k_cgs_update_dot(const double* __restrict__ V, int64_t vstride, int nv,
+                                                       const double* __restrict__ h, int hstride,
+                                                       double* __restrict__ w, int64_t n, int64_t mstride,
+                                                       double* __restrict__ partial, int nblk) {
+    const int mem = blockIdx.y;
+    int64_t lo, hi;
+    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    double hc[MAXV], acc[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+        hc[i] = i < nv ? h[mem * hstride + i] : 0.0;
+        acc[i] = 0.0;
+    }
+    double* wm = w + mem * mstride;
+    const double* Vm = V + mem * mstride;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+        double v[MAXV];
+        double we = wm[e];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) {
+            v[i] = i < nv ? Vm[i * vstride + e] : 0.0;
+            we -= hc[i] * v[i];
+        }
+        wm[e] = we;
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i) acc[i] += v[i] * we;
+    }
+    block_reduce_store(acc, nv, partial, mem, MAXV, nblk);
+}
+
+// out = w - sum_i h_i V_i, partial[0] = ||out||^2
+__global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict__ V, int64_t vstride, int nv,
+                                                        const double* __restrict__ h, int hstride,
+                                                        const double* __restrict__ w, double* __restrict__ out,
+                                                        int64_t n, int64_t mstride, double* __restrict__ partial,
+                                                        int nblk) {
+    const int mem = blockIdx.y;
+    int64_t lo, hi;
+    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    double hc[MAXV];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) hc[i] = i < nv ? h[mem * hstride + i] : 0.0;
+    double acc[1] = {0.0};
+    const double* wm = w + mem * mstride;
+    double* om = out + mem * mstride;
+    const double* Vm = V + mem * mstride;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+        double we = wm[e];
+#pragma unroll
+        for (int i = 0; i < MAXV; ++i)
+            if (i < nv) we -= hc[i] * Vm[i * vstride + e];
+        om[e] = we;
+        acc[0] += we * we;
+    }
+    block_reduce_store(acc, 1, partial, mem, MAXV, nblk);
+}
+
+// out[mem*out_stride + out_offset + i] = sum_blk partial[(mem*MAXV + i)*nblk + blk]
+__global__ __launch_bounds__(RB) void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv,
+                                                        double* __restrict__ out, int out_stride, int out_offset) {
+    const int i = blockIdx.x, mem = blockIdx.y;
+    __shared__ double red[RB];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RB) s += partial[((int64_t)mem * MAXV + i) * nblk + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = RB / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[mem * out_stride + out_offset + i] = red[0];
+}
+
+__global__ void k_scale_vec(double* v, const double* sdev, int sstride, int64_t n, int64_t mstride) {
+    const int mem = blockIdx.y;
+    const double s = sdev[mem * sstride];
+    double* vm = v + mem * mstride;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        vm[e] *= s;
+}
+
+__global__ void k_copy_scale(const double* src, double* dst, const double* s, int64_t n, int64_t mstride) {
+    const int mem = blockIdx.y;
+    const double f = s[mem];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        dst[mem * mstride + e] = f * src[mem * mstride + e];
+}
+
+// x += sum_{i < nv_mem[mem]} y_i Z_i
+template <typename TZ>
+__global__ void k_multi_axpy(const TZ* __restrict__ Z, int64_t zstride, int nv_max, const int* __restrict__ nv_mem,
+                             const double* __restrict__ y, int ystride, double* __restrict__ x, int64_t n,
+                             int64_t mstride) {
+    const int mem = blockIdx.y;
+    const int nv = nv_mem[mem];
+    if (nv <= 0) return;
+    const double* ym = y + mem * ystride;
+    double* xm = x + mem * mstride;
+    const TZ* Zm = Z + mem * mstride;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double s = xm[e];
+        for (int i = 0; i < nv && i < nv_max; ++i) s += ym[i] * (double)Zm[i * zstride + e];
+        xm[e] = s;
+    }
+}
+
+// r = b - r; partial ||r||^2
+__global__ __launch_bounds__(RB) void k_sub_norm(const double* __restrict__ b, double* __restrict__ r, int64_t n,
+                                                 int64_t mstride, double* __restrict__ partial, int nblk) {
+    const int mem = blockIdx.y;
+    int64_t lo, hi;
+    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    double acc[1] = {0.0};
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+        const double v = b[mem * mstride + e] - r[mem * mstride + e];
+        r[mem * mstride + e] = v;
+        acc[0] += v * v;
+    }
+    block_reduce_store(acc, 1, partial, mem, MAXV, nblk);
+}
+
+__global__ __launch_bounds__(RB) void k_norm(const double* __restrict__ x, int64_t n, int64_t mstride,
+                                             double* __restrict__ partial, int nblk) {
+    const int mem = blockIdx.y;
+    int64_t lo, hi;
+    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    double acc[1] = {0.0};
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+        const double v = x[mem * mstride + e];
+        acc[0] += v * v;
+    }
+    block_reduce_store(acc, 1, partial, mem, MAXV, nblk);
+}
+
+__global__ void k_axpby(double a, const double* x, double b, double* y, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = a * x[e] + b * y[e];
+}
+
+__global__ void k_cast_d2f(const double* x, float* y, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = (float)x[e];
+}
+__global__ void k_cast_f2d(const float* x, double* y, int64_t n) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = (double)x[e];
+}
+
+// Arnoldi column j: H(0..j, j) = h1 + h2, H(j+1, j) = ||w2||; previous Givens
+// rotations, new rotation, g update, residual estimate.  nrm holds ||w2||^2 on
+// entry and 1/||w2|| (0 at breakdown) on exit.
+__global__ void k_arnoldi_finish(KrylovDev k, int restart, int j, int nmem) {
+    const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mem >= nmem) return;
+    if (!k.active[mem]) return;
+    const int ld = restart + 1;
+    double* H = k.H + (int64_t)mem * ld * restart;
+    double* col = H + (int64_t)j * ld;
+    const double* h1 = k.h1 + mem * ld;
+    const double* h2 = k.h2 + mem * ld;
+    for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+    const double nn = sqrt(k.nrm[mem]);
+    col[j + 1] = nn;
+    k.nrm[mem] = nn > 0.0 ? 1.0 / nn : 0.0;
+    double* cs = k.cs + mem * restart;
+    double* sn = k.sn + mem * restart;
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = hypot(a, b);
+    const double c = den > 0.0 ? a / den : 1.0;
+    const double s = den > 0.0 ? b / den : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    double* g = k.g + mem * ld;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    k.resid[mem] = fabs(g[j + 1]);
+}
+
+__global__ void k_cycle_start(KrylovDev k, int restart, const double* beta0sq, int nmem) {
+    const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mem >= nmem) return;
+    const int ld = restart + 1;
+    double* g = k.g + mem * ld;
+    for (int i = 0; i < ld; ++i) g[i] = 0.0;
+    const double b = sqrt(beta0sq[mem]);
+    g[0] = b;
+    k.nrm[mem] = b > 0.0 ? 1.0 / b : 0.0;
+    k.resid[mem] = b;
+}
+
+// y = R^{-1} g on the leading jend x jend block (upper triangular after Givens).
+__global__ void k_back_solve(KrylovDev k, int restart, const int* jend, int nmem) {
+    const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mem >= nmem) return;
+    const int ld = restart + 1;
+    const int m = jend[mem];
+    const double* H = k.H + (int64_t)mem * ld * restart;
+    const double* g = k.g + mem * ld;
+    double* y = k.y + mem * restart;
+    for (int i = m - 1; i >= 0; --i) {
+        double s = g[i];
+        for (int q = i + 1; q < m; ++q) s -= H[i + (int64_t)q * ld] * y[q];
+        const double d = H[i + (int64_t)i * ld];
+        y[i] = d != 0.0 ? s / d : 0.0;
+    }
+}
+
+int grid1d(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+dim3 tile_grid(int n, int nchunks, int64_t slices) {
+    const int tiles = ((n + 1 + TX - 1) / TX) * ((n + 1 + TY - 1) / TY);
+    if (slices > 65535 || nchunks > 65535) throw Error(SG_ERR_INVALID, "launch grid too large");
+    return dim3(tiles, nchunks, (unsigned)slices);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+    dim3 g = tile_grid(s.n, (s.nxi + kJChunk - 1) / kJChunk, (int64_t)nvec * s.nt);
+    hipLaunchKernelGGL(k_sg_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, x, y);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_kkt_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+    dim3 g = tile_grid(s.n, (s.nxi + kJChunk - 1) / kJChunk, (int64_t)nvec * s.nt);
+    hipLaunchKernelGGL(k_kkt_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, (int)s.time, s.nodes, op, x, y);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
+                    const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
+                    hipStream_t st) {
+    const int L = s.off[d + 1] - s.off[d];
+    dim3 g = tile_grid(s.n, (L + kJChunk - 1) / kJChunk, (int64_t)nmembers * s.nt);
+    hipLaunchKernelGGL(k_hgs_rhs<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, s.off[d], L, mask,
+                       use_lower, use_upper, base, bmap, V, vmap, out, omap);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_mass_cheb(const Shape& s, const OpDev& op, const T* r, T* z, T* bufA, T* bufB, int nvec, int steps,
+                      hipStream_t st) {
+    const int ncols = 2 * s.nt * s.nxi;
+    dim3 g = tile_grid(s.n, (ncols + kJChunk - 1) / kJChunk, nvec);
+    const int64_t vstride = 3 * s.blk;
+    const double rho = 0.8;
+    // x_1 = D^{-1} r (omega_1 = 1); buffers: prev = A, cur = B
+    T* prev = bufA;
+    T* cur = bufB;
+    hipLaunchKernelGGL(k_mass_cheb_step<T>, g, dim3(256), 0, st, s.n, s.nxi, s.nt, (int)s.time, s.nodes, op, vstride,
+                       r, (const T*)nullptr, (const T*)nullptr, steps == 1 ? z : cur, T(1), 1, steps == 1 ? 1 : 0);
+    SG_HIP(hipGetLastError());
+    if (steps == 1) return;
+    // prev holds x_0 = 0
+    SG_HIP(hipMemsetAsync(prev, 0, sizeof(T) * (size_t)nvec * ncols * s.nodes, st));
+    double omega = 1.0;
+    for (int k = 1; k < steps; ++k) {
+        omega = (k == 1) ? 1.0 / (1.0 - 0.5 * rho * rho) : 1.0 / (1.0 - 0.25 * rho * rho * omega);
+        const bool last = (k == steps - 1);
+        T* out = last ? z : prev;   // x_{k+1} overwrites x_{k-1}
+        hipLaunchKernelGGL(k_mass_cheb_step<T>, g, dim3(256), 0, st, s.n, s.nxi, s.nt, (int)s.time, s.nodes, op,
+                           vstride, r, (const T*)cur, (const T*)prev, out, T(omega), 0, last ? 1 : 0);
+        SG_HIP(hipGetLastError());
+        if (!last) std::swap(prev, cur);
+    }
+}
+
+template <typename T>
+void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap, T* W, ColMap wmap, int ncols,
+                        int, hipStream_t st) {
+    dim3 g = tile_grid(s.n, (ncols + kJChunk - 1) / kJChunk, 1);
+    hipLaunchKernelGGL(k_mass_scaled<T>, g, dim3(256), 0, st, s.n, s.nxi, s.nt, (int)s.time, s.nodes, op, V, vmap, W,
+                       wmap, ncols);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_mg_cheb_first(int m, const LevelDev* lev, int lvl, int which, const T* b, ColMap bmap, T* x, ColMap xmap,
+                          T* d, int ncols, int cpm, hipStream_t st) {
+    dim3 g = tile_grid(m, (ncols + kJChunk - 1) / kJChunk, 1);
+    hipLaunchKernelGGL(k_mg_cheb_first<T>, g, dim3(256), 0, st, m, lev, lvl, which, b, bmap, x, xmap, d, ncols, cpm);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_mg_cheb_step(int m, const LevelDev* lev, int lvl, int which, int step, const T* b, ColMap bmap,
+                         const T* xin, ColMap xinmap, T* xout, ColMap xoutmap, T* d, int ncols, int cpm,
+                         hipStream_t st) {
+    dim3 g = tile_grid(m, (ncols + kJChunk - 1) / kJChunk, 1);
+    hipLaunchKernelGGL(k_mg_cheb_step<T>, g, dim3(256), 0, st, m, lev, lvl, which, step, b, bmap, xin, xinmap, xout,
+                       xoutmap, d, ncols, cpm);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_mg_residual(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, const T* x, ColMap xmap, T* r,
+                        int ncols, int cpm, hipStream_t st) {
+    dim3 g = tile_grid(m, (ncols + kJChunk - 1) / kJChunk, 1);
+    hipLaunchKernelGGL(k_mg_residual<T>, g, dim3(256), 0, st, m, lev, lvl, b, bmap, x, xmap, r, ncols, cpm);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_mg_restrict(int mc, const T* rf, T* bc, int ncols, hipStream_t st) {
+    dim3 g = tile_grid(mc, (ncols + kJChunk - 1) / kJChunk, 1);
+    hipLaunchKernelGGL(k_mg_restrict<T>, g, dim3(256), 0, st, mc, rf, bc, ncols);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_mg_prolong_add(int mc, const T* xc, T* xf, int ncols, hipStream_t st) {
+    dim3 g = tile_grid(2 * mc, (ncols + kJChunk - 1) / kJChunk, 1);
+    hipLaunchKernelGGL(k_mg_prolong_add<T>, g, dim3(256), 0, st, mc, xc, xf, ncols);
+    SG_HIP(hipGetLastError());
+}
+
+template <>
+void launch_mg_coarse<double>(const double* ainv, const double* bc, ColMap bmap, double* xc, ColMap xmap, int ncols,
+                              int cpm, hipStream_t st) {
+    const int nmem = (ncols + cpm - 1) / cpm;
+    dim3 g((cpm + 15) / 16, nmem);
+    hipLaunchKernelGGL(k_mg_coarse_f64, g, dim3(64), 0, st, ainv, bc, bmap, xc, xmap, ncols, cpm);
+    SG_HIP(hipGetLastError());
+}
+
+template <>
+void launch_mg_coarse<float>(const float* ainv, const float* bc, ColMap bmap, float* xc, ColMap xmap, int ncols,
+                             int cpm, hipStream_t st) {
+    const int nmem = (ncols + cpm - 1) / cpm;
+    dim3 g(cpm, nmem);
+    hipLaunchKernelGGL(k_mg_coarse_f32, g, dim3(64), 0, st, ainv, bc, bmap, xc, xmap, ncols, cpm);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_zero_ring(T* x, int n, int64_t ncols, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_ring<T>, dim3(grid1d(4 * (int64_t)n * ncols)), dim3(256), 0, st, x, n, ncols);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_multidot(const double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem, int64_t mstride,
+                     double* partial, int nblk, hipStream_t st) {
+    if (nv > MAXV) throw Error(SG_ERR_INVALID, "multidot: too many vectors");
+    hipLaunchKernelGGL(k_multidot, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, w, n, mstride, partial, nblk);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_cgs_update_dot(const double* V, int64_t vstride, int nv, const double* h, int hstride, double* w,
+                           int64_t n, int nmem, int64_t mstride, double* partial, int nblk, hipStream_t st) {
+    if (nv > MAXV) throw Error(SG_ERR_INVALID, "cgs: too many vectors");
+    hipLaunchKernelGGL(k_cgs_update_dot, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, h, hstride, w, n, mstride,
+                       partial, nblk);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_cgs_update_norm(const double* V, int64_t vstride, int nv, const double* h, int hstride, const double* w,
+                            double* out, int64_t n, int nmem, int64_t mstride, double* partial, int nblk,
+                            hipStream_t st) {
+    if (nv > MAXV) throw Error(SG_ERR_INVALID, "cgs: too many vectors");
+    hipLaunchKernelGGL(k_cgs_update_norm, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, h, hstride, w, out, n,
+                       mstride, partial, nblk);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_reduce_partials(const double* partial, int nblk, int nv, int nmem, double* out, int out_stride,
+                            int out_offset, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv, nmem), dim3(RB), 0, st, partial, nblk, nv, out, out_stride,
+                       out_offset);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_scale_vec(double* v, const double* sdev, int sstride, int64_t n, int nmem, int64_t mstride,
+                      hipStream_t st) {
+    hipLaunchKernelGGL(k_scale_vec, dim3(grid1d(n), nmem), dim3(256), 0, st, v, sdev, sstride, n, mstride);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_copy_scale_rows(const double* src, double* dst, const double* inv_norm, int64_t n, int nmem,
+                            int64_t mstride, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_scale, dim3(grid1d(n), nmem), dim3(256), 0, st, src, dst, inv_norm, n, mstride);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_multi_axpy(const void* Z, int zfp32, int64_t zstride, int nv_max, const int* nv_mem, const double* y,
+                       int ystride, double* x, int64_t n, int nmem, int64_t mstride, hipStream_t st) {
+    if (zfp32)
+        hipLaunchKernelGGL(k_multi_axpy<float>, dim3(grid1d(n), nmem), dim3(256), 0, st, (const float*)Z, zstride,
+                           nv_max, nv_mem, y, ystride, x, n, mstride);
+    else
+        hipLaunchKernelGGL(k_multi_axpy<double>, dim3(grid1d(n), nmem), dim3(256), 0, st, (const double*)Z, zstride,
+                           nv_max, nv_mem, y, ystride, x, n, mstride);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_sub_norm(const double* b, double* r, int64_t n, int nmem, int64_t mstride, double* partial, int nblk,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_sub_norm, dim3(nblk, nmem), dim3(RB), 0, st, b, r, n, mstride, partial, nblk);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_norm(const double* x, int64_t n, int nmem, int64_t mstride, double* partial, int nblk, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm, dim3(nblk, nmem), dim3(RB), 0, st, x, n, mstride, partial, nblk);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid1d(n)), dim3(256), 0, st, a, x, b, y, n);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_cast_d2f(const double* x, float* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_cast_d2f, dim3(grid1d(n)), dim3(256), 0, st, x, y, n);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_cast_f2d(const float* x, double* y, int64_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_cast_f2d, dim3(grid1d(n)), dim3(256), 0, st, x, y, n);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_arnoldi_finish(KrylovDev k, int restart, int j, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_arnoldi_finish, dim3((nmem + 63) / 64), dim3(64), 0, st, k, restart, j, nmem);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_cycle_start(KrylovDev k, int restart, const double* beta0sq, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_cycle_start, dim3((nmem + 63) / 64), dim3(64), 0, st, k, restart, beta0sq, nmem);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_back_solve(KrylovDev k, int restart, const int* jend, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_back_solve, dim3((nmem + 63) / 64), dim3(64), 0, st, k, restart, jend, nmem);
+    SG_HIP(hipGetLastError());
+}
+
+// explicit instantiations
+#define SG_INST(T)                                                                                          \
+    template void launch_sg_apply<T>(const Shape&, const OpDev&, const T*, T*, int, hipStream_t);           \
+    template void launch_kkt_apply<T>(const Shape&, const OpDev&, const T*, T*, int, hipStream_t);          \
+    template void launch_hgs_rhs<T>(const Shape&, const OpDev&, int, uint32_t, int, int, const T*, ColMap,  \
+                                    const T*, ColMap, T*, ColMap, int, hipStream_t);                        \
+    template void launch_mass_cheb<T>(const Shape&, const OpDev&, const T*, T*, T*, T*, int, int,           \
+                                      hipStream_t);                                                         \
+    template void launch_mass_scaled<T>(const Shape&, const OpDev&, const T*, ColMap, T*, ColMap, int, int, \
+                                        hipStream_t);                                                       \
+    template void launch_mg_cheb_first<T>(int, const LevelDev*, int, int, const T*, ColMap, T*, ColMap, T*, \
+                                          int, int, hipStream_t);                                           \
+    template void launch_mg_cheb_step<T>(int, const LevelDev*, int, int, int, const T*, ColMap, const T*,   \
+                                         ColMap, T*, ColMap, T*, int, int, hipStream_t);                    \
+    template void launch_mg_residual<T>(int, const LevelDev*, int, const T*, ColMap, const T*, ColMap, T*,  \
+                                        int, int, hipStream_t);                                             \
+    template void launch_mg_restrict<T>(int, const T*, T*, int, hipStream_t);                               \
+    template void launch_mg_prolong_add<T>(int, const T*, T*, int, hipStream_t);                            \
+    template void launch_zero_ring<T>(T*, int, int64_t, hipStream_t);
+SG_INST(double)
+SG_INST(float)
+
+}  // namespace sg

@@ -1,0 +1,365 @@
+// Continuous-batching solve server.
+//
+// Requests (steady problems) are queued by sg_submit.  A scheduler thread
+// admits queued requests in arrival order while their estimated device
+// footprint fits the HBM budget and a slot is free, groups admitted requests
+// of the same shape (n, M, P, precision, solver options) into one batch, and
+// hands each batch to a worker thread that owns its own HIP stream.  Batches
+// on different workers overlap on the device; requests that arrive while
+// others run are admitted as soon as memory and slots free up and form the
+// next batches.  Each member's arithmetic depends only on its own data, so a
+// request's result does not depend on which batch it ran in.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+#include "handle.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    sg_problem prob{};
+    sg_options opt{};
+    std::vector<double> target, kappa;
+    double* x_out = nullptr;
+    size_t footprint = 0;
+    Clock::time_point t_submit;
+    int state = 0;          // 0 queued, 1 running, 2 done, 3 cancelled
+    int status = SG_PENDING;
+    sg_solve_info info{};
+};
+
+size_t footprint_bytes(const sg_problem& p, const sg_options& o) {
+    const double nxi = sg::binom(p.M + p.P, p.P);
+    const double nodes = (double)(p.n + 1) * (p.n + 1);
+    const double blk = nxi * nodes;
+    const double N = 3 * blk;
+    const int m = o.restart;
+    const double sz = o.precision == SG_PREC_FP32_REFINE ? 4.0 : 8.0;
+    double bytes = 8.0 * N * (m + 1) + sz * N * m + 8.0 * N * 6;   // V, Z, w/r/b/x/d staging
+    // preconditioner scratch: Chebyshev 4 blocks, Schur 2, hGS 1, multigrid ~4 of the widest level
+    bytes += sz * blk * 7 + sz * 4 * nodes * 1.4 * nxi * 0.6;
+    if (o.precision == SG_PREC_FP32_REFINE) bytes += 4.0 * N * 2 + 8.0 * N * (m + 1) + 8.0 * N * m;  // FP64 fallback basis
+    return (size_t)bytes;
+}
+
+bool same_shape(const Request& a, const Request& b) {
+    return a.prob.n == b.prob.n && a.prob.M == b.prob.M && a.prob.P == b.prob.P && a.opt.precision == b.opt.precision &&
+           a.opt.restart == b.opt.restart && a.opt.max_iter == b.opt.max_iter && a.opt.rtol == b.opt.rtol &&
+           a.opt.cheb_steps == b.opt.cheb_steps && a.opt.truncation_r == b.opt.truncation_r &&
+           a.opt.gmg_pre == b.opt.gmg_pre && a.opt.gmg_post == b.opt.gmg_post && a.opt.inner_rtol == b.opt.inner_rtol;
+}
+
+}  // namespace
+
+struct sg_server {
+    int device = 0;
+    size_t budget = 0, in_use = 0;
+    int max_slots = 0, running_slots = 0;
+    int max_batch = 16;
+    int nworkers = 4;
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::deque<std::vector<uint64_t>> batches;       // formed, waiting for a worker
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    int idle_workers = 0;
+    std::thread scheduler;
+    std::vector<std::thread> workers;
+    std::vector<double> latencies;
+    Clock::time_point t_first{}, t_last{};
+    bool have_first = false;
+    std::string worker_error;
+
+    void schedule_loop();
+    void worker_loop(int id);
+    void run_batch(const std::vector<uint64_t>& ids, hipStream_t st);
+};
+
+void sg_server::schedule_loop() {
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        cv_sched.wait(lk, [&] { return stopping || (!queue.empty() && idle_workers > (int)batches.size()); });
+        if (stopping && queue.empty()) break;
+        // admit in arrival order while memory and slots allow
+        std::vector<uint64_t> admitted;
+        while (!queue.empty()) {
+            Request& r = *reqs[queue.front()];
+            if (r.state == 3) {
+                queue.pop_front();
+                continue;
+            }
+            if (running_slots + (int)admitted.size() >= max_slots) break;
+            if (in_use + r.footprint > budget) break;
+            in_use += r.footprint;
+            admitted.push_back(queue.front());
+            queue.pop_front();
+        }
+        if (admitted.empty()) {
+            if (stopping) break;
+            cv_sched.wait(lk);   // wait for memory or slots to free up
+            continue;
+        }
+        // group by shape (stable, arrival order inside a group), cap batch size
+        std::vector<bool> used(admitted.size(), false);
+        for (size_t i = 0; i < admitted.size(); ++i) {
+            if (used[i]) continue;
+            std::vector<uint64_t> group{admitted[i]};
+            used[i] = true;
+            for (size_t k = i + 1; k < admitted.size() && (int)group.size() < max_batch; ++k)
+                if (!used[k] && same_shape(*reqs[admitted[i]], *reqs[admitted[k]])) {
+                    group.push_back(admitted[k]);
+                    used[k] = true;
+                }
+            for (uint64_t id : group) reqs[id]->state = 1;
+            running_slots += (int)group.size();
+            batches.push_back(std::move(group));
+        }
+        cv_work.notify_all();
+    }
+}
+
+void sg_server::run_batch(const std::vector<uint64_t>& ids, hipStream_t st) {
+    std::vector<sg_problem> probs;
+    sg_options opt;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (uint64_t id : ids) probs.push_back(reqs[id]->prob);
+        opt = reqs[ids[0]]->opt;
+    }
+    const int B = (int)ids.size();
+    std::vector<sg_solve_info> info(B);
+    std::vector<int> status(B, SG_OK);
+    try {
+        auto h = sg::build_handle(probs.data(), B, &opt, st);
+        const int64_t N = 3 * h->s.blk;
+        double* x = h->ws.get_t<double>("serve_x", (size_t)B * N);
+        sg::solve(*h, nullptr, x, info.data());
+        for (int q = 0; q < B; ++q) {
+            status[q] = info[q].status;
+            double* dst;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                dst = reqs[ids[q]]->x_out;
+            }
+            SG_HIP(hipMemcpyAsync(dst, x + q * N, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+        }
+        SG_HIP(hipStreamSynchronize(st));
+    } catch (const sg::Error& e) {
+        for (int q = 0; q < B; ++q) status[q] = e.code;
+        std::lock_guard<std::mutex> lk(mu);
+        worker_error = e.what();
+    } catch (const std::exception& e) {
+        for (int q = 0; q < B; ++q) status[q] = SG_ERR_INVALID;
+        std::lock_guard<std::mutex> lk(mu);
+        worker_error = e.what();
+    }
+    const auto now = Clock::now();
+    std::lock_guard<std::mutex> lk(mu);
+    for (int q = 0; q < B; ++q) {
+        Request& r = *reqs[ids[q]];
+        r.info = info[q];
+        r.info.status = status[q];
+        r.info.latency_ms = std::chrono::duration<double, std::milli>(now - r.t_submit).count();
+        r.status = status[q];
+        r.state = 2;
+        in_use -= r.footprint;
+        latencies.push_back(r.info.latency_ms);
+        // release the host copies of the inputs
+        r.target.clear();
+        r.target.shrink_to_fit();
+        r.kappa.clear();
+        r.kappa.shrink_to_fit();
+    }
+    running_slots -= B;
+    t_last = now;
+    cv_sched.notify_all();
+    cv_done.notify_all();
+}
+
+void sg_server::worker_loop(int) {
+    hipStream_t st = nullptr;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(mu);
+        worker_error = "worker could not create a HIP stream";
+        return;
+    }
+    std::unique_lock<std::mutex> lk(mu);
+    while (true) {
+        ++idle_workers;
+        cv_sched.notify_all();
+        cv_work.wait(lk, [&] { return !batches.empty() || (stopping && queue.empty() && running_slots == 0); });
+        --idle_workers;
+        if (batches.empty()) break;
+        std::vector<uint64_t> ids = std::move(batches.front());
+        batches.pop_front();
+        lk.unlock();
+        run_batch(ids, st);
+        lk.lock();
+    }
+    lk.unlock();
+    (void)hipStreamDestroy(st);
+}
+
+namespace {
+thread_local std::string g_srv_error;
+}
+
+extern "C" {
+
+int sg_server_create(size_t hbm_budget_bytes, int32_t max_slots, sg_server** out) {
+    try {
+        if (!out) return SG_ERR_INVALID;
+        *out = nullptr;
+        if (max_slots < 1 || max_slots > 4096) return SG_ERR_INVALID;
+        auto s = std::make_unique<sg_server>();
+        SG_HIP(hipGetDevice(&s->device));
+        if (hbm_budget_bytes == 0) {
+            size_t free_b = 0, total_b = 0;
+            SG_HIP(hipMemGetInfo(&free_b, &total_b));
+            hbm_budget_bytes = (size_t)(0.8 * (double)free_b);
+        }
+        s->budget = hbm_budget_bytes;
+        s->max_slots = max_slots;
+        s->max_batch = std::max(1, std::min(16, (int)max_slots));
+        sg_server* raw = s.get();
+        for (int i = 0; i < s->nworkers; ++i) s->workers.emplace_back([raw, i] { raw->worker_loop(i); });
+        s->scheduler = std::thread([raw] { raw->schedule_loop(); });
+        *out = s.release();
+        return SG_OK;
+    } catch (const sg::Error& e) {
+        return e.code;
+    } catch (...) {
+        return SG_ERR_INVALID;
+    }
+}
+
+int sg_submit(sg_server* s, const sg_problem* prob, const sg_options* opt, double* x_out, uint64_t* ticket) {
+    try {
+        if (!s || !prob || !x_out || !ticket) return SG_ERR_INVALID;
+        sg_options o;
+        if (opt)
+            o = *opt;
+        else
+            sg::default_options(&o);
+        sg::validate(prob, 1, &o);
+        if (prob->n_t >= 2) throw sg::Error(SG_ERR_INVALID, "the server takes steady problems only");
+        auto r = std::make_unique<Request>();
+        r->prob = *prob;
+        r->opt = o;
+        const size_t nodes = (size_t)(prob->n + 1) * (prob->n + 1);
+        r->target.assign(prob->y_target, prob->y_target + nodes);
+        r->prob.y_target = r->target.data();
+        if (prob->kappa) {
+            r->kappa.assign(prob->kappa, prob->kappa + (size_t)(prob->M + 1) * prob->n * prob->n);
+            r->prob.kappa = r->kappa.data();
+        }
+        r->prob.y0 = nullptr;
+        r->x_out = x_out;
+        r->footprint = footprint_bytes(*prob, o);
+        r->t_submit = Clock::now();
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) return SG_ERR_INVALID;
+        if (r->footprint > s->budget)
+            throw sg::Error(SG_ERR_NOMEM, "request footprint " + std::to_string(r->footprint) +
+                                              " bytes exceeds the server budget");
+        r->ticket = s->next_ticket++;
+        *ticket = r->ticket;
+        if (!s->have_first) {
+            s->t_first = r->t_submit;
+            s->have_first = true;
+        }
+        s->queue.push_back(r->ticket);
+        s->reqs[r->ticket] = std::move(r);
+        s->cv_sched.notify_all();
+        return SG_OK;
+    } catch (const sg::Error& e) {
+        g_srv_error = e.what();
+        return e.code;
+    } catch (...) {
+        return SG_ERR_INVALID;
+    }
+}
+
+int sg_poll(sg_server* s, uint64_t ticket, sg_solve_info* info) {
+    if (!s) return SG_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return SG_ERR_UNKNOWN;
+    Request& r = *it->second;
+    if (r.state == 3) return SG_ERR_CANCELLED;
+    if (r.state != 2) return SG_PENDING;
+    if (info) *info = r.info;
+    return r.status;
+}
+
+int sg_cancel(sg_server* s, uint64_t ticket) {
+    if (!s) return SG_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return SG_ERR_UNKNOWN;
+    Request& r = *it->second;
+    if (r.state != 0) return SG_ERR_INVALID;
+    r.state = 3;
+    r.status = SG_ERR_CANCELLED;
+    return SG_OK;
+}
+
+int sg_server_stats(sg_server* s, int64_t* completed, double* p50_ms, double* p99_ms, double* solves_per_s) {
+    if (!s) return SG_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::vector<double> l = s->latencies;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) {
+        if (l.empty()) return 0.0;
+        const double pos = q * (l.size() - 1);
+        const size_t i = (size_t)pos;
+        const double f = pos - i;
+        return i + 1 < l.size() ? l[i] * (1 - f) + l[i + 1] * f : l[i];
+    };
+    if (completed) *completed = (int64_t)l.size();
+    if (p50_ms) *p50_ms = pct(0.50);
+    if (p99_ms) *p99_ms = pct(0.99);
+    if (solves_per_s) {
+        const double sec = s->have_first ? std::chrono::duration<double>(s->t_last - s->t_first).count() : 0.0;
+        *solves_per_s = sec > 0 ? l.size() / sec : 0.0;
+    }
+    return SG_OK;
+}
+
+void sg_server_destroy(sg_server* s) {
+    if (!s) return;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.wait(lk, [&] {
+            bool busy = s->running_slots > 0 || !s->batches.empty();
+            for (uint64_t id : s->queue)
+                if (s->reqs[id]->state == 0) busy = true;
+            return !busy;
+        });
+        s->stopping = true;
+        s->cv_sched.notify_all();
+        s->cv_work.notify_all();
+    }
+    if (s->scheduler.joinable()) s->scheduler.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->cv_work.notify_all();
+    }
+    for (auto& w : s->workers)
+        if (w.joinable()) w.join();
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,437 @@
+// Host-side setup: validation, multi-index set, triple-product neighbour
+// table, per-element coefficient modes, multigrid constants, right-hand sides,
+// and the upload of all of it to the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "handle.hpp"
+
+namespace sg {
+
+int binom(int n, int k) {
+    if (k < 0 || k > n) return 0;
+    long long r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return (int)r;
+}
+
+void default_options(sg_options* o) {
+    o->rtol = 1e-8;
+    o->restart = 30;
+    o->max_iter = 600;
+    o->cheb_steps = 5;
+    o->truncation_r = 0;
+    o->gmg_pre = 2;
+    o->gmg_post = 2;
+    o->precision = SG_PREC_FP64;
+    o->inner_rtol = 1e-5;
+    o->use_graphs = 1;
+    o->verbose = 0;
+}
+
+// Total-degree multi-indices, degree ascending, descending lexicographic order
+// inside a degree (Section 2.1 dimension C(M+P, P); Algorithm 1 level ranges).
+static void compositions(int total, int parts, std::vector<int>& cur, std::vector<int32_t>& out) {
+    if (parts == 1) {
+        cur.push_back(total);
+        out.insert(out.end(), cur.begin(), cur.end());
+        cur.pop_back();
+        return;
+    }
+    for (int first = total; first >= 0; --first) {
+        cur.push_back(first);
+        compositions(total - first, parts - 1, cur, out);
+        cur.pop_back();
+    }
+}
+
+std::vector<int32_t> multi_indices(int M, int P) {
+    std::vector<int32_t> out;
+    std::vector<int> cur;
+    for (int d = 0; d <= P; ++d) compositions(d, M, cur, out);
+    return out;
+}
+
+static bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+static void fail(int code, const std::string& m) { throw Error(code, m); }
+
+// Per-element coefficient modes of one problem: [M+1][n][n].
+static std::vector<double> coefficient_modes(const sg_problem& p) {
+    const int n = p.n, M = p.M;
+    std::vector<double> c((size_t)(M + 1) * n * n);
+    if (p.kappa) {
+        std::memcpy(c.data(), p.kappa, c.size() * sizeof(double));
+        return c;
+    }
+    // a = 1 + sigma sum_k k^-2 cos(k pi x1) cos(k pi x2) xi_k; xi_k = psi_{e_k}/sqrt(3)
+    const double h = 1.0 / n;
+    for (int ey = 0; ey < n; ++ey)
+        for (int ex = 0; ex < n; ++ex) c[(size_t)ey * n + ex] = 1.0;
+    for (int k = 1; k <= M; ++k) {
+        const double amp = p.sigma / ((double)k * k) / std::sqrt(3.0);
+        for (int ey = 0; ey < n; ++ey) {
+            const double cy = std::cos(k * M_PI * (ey + 0.5) * h);
+            for (int ex = 0; ex < n; ++ex)
+                c[((size_t)k * n + ey) * n + ex] = amp * std::cos(k * M_PI * (ex + 0.5) * h) * cy;
+        }
+    }
+    return c;
+}
+
+void validate(const sg_problem* probs, int count, const sg_options* opt) {
+    if (!probs || count < 1) fail(SG_ERR_INVALID, "no problems given");
+    if (count > 4096) fail(SG_ERR_INVALID, "too many members in one batch (max 4096)");
+    const sg_problem& p0 = probs[0];
+    for (int i = 0; i < count; ++i) {
+        const sg_problem& p = probs[i];
+        const std::string who = "problem " + std::to_string(i) + ": ";
+        if (!is_pow2(p.n) || p.n < 8 || p.n > 4096) fail(SG_ERR_INVALID, who + "n must be a power of two in [8, 4096]");
+        if (p.M < 1 || p.M > kMaxM) fail(SG_ERR_INVALID, who + "M must be in [1, 16]");
+        if (p.P < 1 || p.P > kMaxP) fail(SG_ERR_INVALID, who + "P must be in [1, 8]");
+        if (binom(p.M + p.P, p.P) > 20000) fail(SG_ERR_INVALID, who + "chaos dimension above 20000");
+        if (p.n_t > 4096) fail(SG_ERR_INVALID, who + "n_t above 4096");
+        if (p.n != p0.n || p.M != p0.M || p.P != p0.P || std::max(p.n_t, 1) != std::max(p0.n_t, 1))
+            fail(SG_ERR_INVALID, who + "members of one batch must share n, M, P, n_t");
+        if (!std::isfinite(p.beta) || !std::isfinite(p.gamma) || !std::isfinite(p.sigma) ||
+            (p.n_t >= 2 && !std::isfinite(p.T)))
+            fail(SG_ERR_NONFINITE, who + "non-finite scalar parameter");
+        if (!(p.beta > 0)) fail(SG_ERR_INVALID, who + "beta must be > 0");
+        if (!(p.gamma >= 0)) fail(SG_ERR_INVALID, who + "gamma must be >= 0");
+        if (p.n_t >= 2 && !(p.T > 0)) fail(SG_ERR_INVALID, who + "T must be > 0");
+        if (!p.kappa && !(p.sigma >= 0)) fail(SG_ERR_INVALID, who + "sigma must be >= 0");
+        if (!p.y_target) fail(SG_ERR_INVALID, who + "y_target is NULL");
+        const int nt = std::max(p.n_t, 1);
+        const size_t nodes = (size_t)(p.n + 1) * (p.n + 1);
+        for (size_t q = 0; q < nt * nodes; ++q)
+            if (!std::isfinite(p.y_target[q])) fail(SG_ERR_NONFINITE, who + "non-finite target value");
+        if (p.y0) {
+            if (p.n_t < 2) fail(SG_ERR_INVALID, who + "y0 given for a steady problem");
+            for (size_t q = 0; q < nodes; ++q)
+                if (!std::isfinite(p.y0[q])) fail(SG_ERR_NONFINITE, who + "non-finite initial state");
+        }
+        // coefficient: finite, constant positive mean, bounded away from zero for all xi
+        const size_t ne = (size_t)p.n * p.n;
+        if (p.kappa) {
+            for (size_t q = 0; q < (size_t)(p.M + 1) * ne; ++q)
+                if (!std::isfinite(p.kappa[q])) fail(SG_ERR_NONFINITE, who + "non-finite coefficient mode");
+            for (size_t q = 1; q < ne; ++q)
+                if (p.kappa[q] != p.kappa[0]) fail(SG_ERR_INVALID, who + "kappa_0 must be constant");
+        }
+        const double c0 = p.kappa ? p.kappa[0] : 1.0;
+        if (!(c0 > 0)) fail(SG_ERR_NONCOERCIVE, who + "mean coefficient must be positive");
+        double worst = INFINITY;
+        if (p.kappa) {
+            for (size_t e = 0; e < ne; ++e) {
+                double s = 0.0;
+                for (int k = 1; k <= p.M; ++k) s += std::fabs(p.kappa[(size_t)k * ne + e]);
+                worst = std::min(worst, c0 - std::sqrt(3.0) * s);
+            }
+        } else {
+            const double h = 1.0 / p.n;
+            for (int ey = 0; ey < p.n; ++ey)
+                for (int ex = 0; ex < p.n; ++ex) {
+                    double s = 0.0;
+                    for (int k = 1; k <= p.M; ++k)
+                        s += std::fabs(std::cos(k * M_PI * (ex + 0.5) * h) * std::cos(k * M_PI * (ey + 0.5) * h)) /
+                             ((double)k * k);
+                    worst = std::min(worst, 1.0 - p.sigma * s);
+                }
+        }
+        if (!(worst > 0)) fail(SG_ERR_NONCOERCIVE, who + "coefficient is not bounded away from zero for xi in [-1,1]^M");
+    }
+    if (opt) {
+        if (!(opt->rtol > 0) || !std::isfinite(opt->rtol)) fail(SG_ERR_INVALID, "rtol must be > 0");
+        if (opt->restart < 1 || opt->restart > 31) fail(SG_ERR_INVALID, "restart must be in [1, 31]");
+        if (opt->max_iter < 1) fail(SG_ERR_INVALID, "max_iter must be >= 1");
+        if (opt->cheb_steps < 1 || opt->cheb_steps > 64) fail(SG_ERR_INVALID, "cheb_steps must be in [1, 64]");
+        if (opt->truncation_r < 0 || opt->truncation_r > p0.M + 1)
+            fail(SG_ERR_INVALID, "truncation_r must be in [0, M+1]");
+        if (opt->gmg_pre < 1 || opt->gmg_pre > kMaxSmooth || opt->gmg_post < 1 || opt->gmg_post > kMaxSmooth)
+            fail(SG_ERR_INVALID, "gmg_pre/gmg_post must be in [1, 4]");
+        if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32_REFINE)
+            fail(SG_ERR_INVALID, "unknown precision mode");
+        if (opt->precision == SG_PREC_FP32_REFINE && !(opt->inner_rtol > 0 && opt->inner_rtol < 1))
+            fail(SG_ERR_INVALID, "inner_rtol must be in (0, 1)");
+    }
+}
+
+// Largest eigenvalue of diag(A)^{-1} A for A = a K + b M_h on the interior of
+// the m x m grid: the Q1 matrices are Kronecker sums of 1-D P1 matrices whose
+// common eigenvectors are discrete sines (1-D eigenvalues (2/h)(1 - cos t) for
+// the stiffness and (h/3)(2 + cos t) for the mass, t = i pi h).
+static double lambda_max(int m, double a, double b) {
+    const double h = 1.0 / m;
+    std::vector<double> k1(m - 1), m1(m - 1);
+    for (int i = 1; i < m; ++i) {
+        const double t = i * M_PI * h;
+        k1[i - 1] = (2.0 / h) * (1.0 - std::cos(t));
+        m1[i - 1] = (h / 3.0) * (2.0 + std::cos(t));
+    }
+    double best = 0.0;
+    for (int i = 0; i < m - 1; ++i)
+        for (int j = 0; j < m - 1; ++j) {
+            const double lam = a * (k1[i] * m1[j] + m1[i] * k1[j]) + b * m1[i] * m1[j];
+            best = std::max(best, lam);
+        }
+    const double diag = a * 8.0 / 3.0 + b * 4.0 * h * h / 9.0;
+    return best / diag;
+}
+
+// Chebyshev smoothing coefficients on [0.3, 1.1] * lambda_max of D^{-1} A:
+// step 0: d = D^{-1} r / theta; step i: rho_i = 1/(2 sigma - rho_{i-1}),
+// d = rho_i rho_{i-1} d + (2 rho_i / delta) D^{-1} r.
+static void smoother_coeffs(double lmax, int nu, double out[kMaxSmooth][2]) {
+    const double lo = 0.3 * lmax, hi = 1.1 * lmax;
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    const double sig = theta / delta;
+    double rho_old = 1.0 / sig;
+    for (int s = 0; s < kMaxSmooth; ++s) out[s][0] = out[s][1] = 0.0;
+    out[0][0] = 0.0;
+    out[0][1] = 1.0 / theta;
+    for (int s = 1; s < nu; ++s) {
+        const double rho = 1.0 / (2.0 * sig - rho_old);
+        out[s][0] = rho * rho_old;
+        out[s][1] = 2.0 * rho / delta;
+        rho_old = rho;
+    }
+}
+
+// Inverse of a K + b M on the interior of the kCoarseN grid, padded to 64 x 64.
+static void coarse_inverse(double a, double b, double* out) {
+    const int m = kCoarseN, nu = (m - 1) * (m - 1);
+    const double h = 1.0 / m;
+    std::vector<double> A((size_t)nu * nu, 0.0), I((size_t)nu * nu, 0.0);
+    const double wc = a * 8.0 / 3.0 + b * 16.0 * h * h / 36.0;
+    const double we = -a / 3.0 + b * 4.0 * h * h / 36.0;
+    const double wd = -a / 3.0 + b * h * h / 36.0;
+    for (int iy = 1; iy < m; ++iy)
+        for (int ix = 1; ix < m; ++ix) {
+            const int r = (iy - 1) * (m - 1) + (ix - 1);
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int jx = ix + dx, jy = iy + dy;
+                    if (jx < 1 || jx > m - 1 || jy < 1 || jy > m - 1) continue;
+                    const int c = (jy - 1) * (m - 1) + (jx - 1);
+                    const double w = (dx == 0 && dy == 0) ? wc : (dx == 0 || dy == 0) ? we : wd;
+                    A[(size_t)r * nu + c] = w;
+                }
+            I[(size_t)r * nu + r] = 1.0;
+        }
+    // Gauss-Jordan elimination with partial pivoting
+    for (int col = 0; col < nu; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < nu; ++r)
+            if (std::fabs(A[(size_t)r * nu + col]) > std::fabs(A[(size_t)piv * nu + col])) piv = r;
+        if (piv != col)
+            for (int c = 0; c < nu; ++c) {
+                std::swap(A[(size_t)piv * nu + c], A[(size_t)col * nu + c]);
+                std::swap(I[(size_t)piv * nu + c], I[(size_t)col * nu + c]);
+            }
+        const double d = A[(size_t)col * nu + col];
+        for (int c = 0; c < nu; ++c) {
+            A[(size_t)col * nu + c] /= d;
+            I[(size_t)col * nu + c] /= d;
+        }
+        for (int r = 0; r < nu; ++r) {
+            if (r == col) continue;
+            const double f = A[(size_t)r * nu + col];
+            if (f == 0.0) continue;
+            for (int c = 0; c < nu; ++c) {
+                A[(size_t)r * nu + c] -= f * A[(size_t)col * nu + c];
+                I[(size_t)r * nu + c] -= f * I[(size_t)col * nu + c];
+            }
+        }
+    }
+    std::fill(out, out + kCoarsePad * kCoarsePad, 0.0);
+    for (int r = 0; r < nu; ++r)
+        for (int c = 0; c < nu; ++c) out[r * kCoarsePad + c] = I[(size_t)r * nu + c];
+}
+
+Handle::~Handle() {
+    ws.release();
+    for (void* p : {(void*)d_nbr_idx, (void*)d_nbr_val, (void*)d_coef64, (void*)d_coef32, (void*)d_mem,
+                    (void*)d_lev, (void*)d_ainv64, (void*)d_ainv32, (void*)d_rhs})
+        if (p) (void)hipFree(p);
+    if (h_pinned) (void)hipHostFree(h_pinned);
+}
+
+template <typename T>
+static T* upload(const T* src, size_t count) {
+    T* d = nullptr;
+    hipError_t e = hipMalloc(&d, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(SG_ERR_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
+    if (count) SG_HIP(hipMemcpy(d, src, count * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt_in, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    sg_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        default_options(&opt);
+    validate(probs, count, &opt);
+
+    auto h = std::make_unique<Handle>();
+    h->opt = opt;
+    h->B = count;
+    h->stream = st;
+    SG_HIP(hipGetDevice(&h->device));
+    const sg_problem& p0 = probs[0];
+    Shape& s = h->s;
+    s.n = p0.n;
+    s.M = p0.M;
+    s.P = p0.P;
+    s.time = p0.n_t >= 2;
+    s.nt = s.time ? p0.n_t : 1;
+    s.nxi = binom(s.M + s.P, s.P);
+    s.nodes = (int64_t)(s.n + 1) * (s.n + 1);
+    s.tstride = (int64_t)s.nxi * s.nodes;
+    s.blk = (int64_t)s.nt * s.tstride;
+    for (int d = 0; d <= s.P + 1; ++d) s.off[d] = d == 0 ? 0 : binom(s.M + d - 1, d - 1);
+    s.nlev_mg = 0;
+    for (int m = s.n; m >= kCoarseN; m /= 2) s.mg_n[s.nlev_mg++] = m;
+
+    // multi-index set and triple-product neighbour table:
+    // E[psi_{e_k} psi_a psi_{a+e_k}] = sqrt(3) m / sqrt(4 m^2 - 1), m = a_k + 1
+    // (three-term recurrence of orthonormal Legendre polynomials).
+    const int M = s.M, nxi = s.nxi;
+    h->ht.alpha = multi_indices(M, s.P);
+    std::map<std::vector<int32_t>, int> index;
+    for (int j = 0; j < nxi; ++j)
+        index[std::vector<int32_t>(h->ht.alpha.begin() + (size_t)j * M, h->ht.alpha.begin() + (size_t)(j + 1) * M)] = j;
+    h->ht.nbr_idx.assign((size_t)nxi * M * 2, -1);
+    h->ht.nbr_val.assign((size_t)nxi * M * 2, 0.0);
+    for (int j = 0; j < nxi; ++j) {
+        std::vector<int32_t> a(h->ht.alpha.begin() + (size_t)j * M, h->ht.alpha.begin() + (size_t)(j + 1) * M);
+        for (int k = 0; k < M; ++k) {
+            const size_t slot = ((size_t)j * M + k) * 2;
+            if (a[k] > 0) {
+                std::vector<int32_t> b = a;
+                b[k] -= 1;
+                const double m = a[k];
+                h->ht.nbr_idx[slot] = index.at(b);
+                h->ht.nbr_val[slot] = std::sqrt(3.0) * m / std::sqrt(4.0 * m * m - 1.0);
+            }
+            std::vector<int32_t> b = a;
+            b[k] += 1;
+            auto it = index.find(b);
+            if (it != index.end()) {
+                const double m = a[k] + 1;
+                h->ht.nbr_idx[slot + 1] = it->second;
+                h->ht.nbr_val[slot + 1] = std::sqrt(3.0) * m / std::sqrt(4.0 * m * m - 1.0);
+            }
+        }
+    }
+
+    // members: coefficients, scalars, multigrid constants, right-hand sides
+    const int n = s.n;
+    const size_t cm = (size_t)(M + 1) * n * n;
+    h->coef_host.resize(cm * count);
+    h->mem_host.resize(count);
+    h->lev_host.assign((size_t)count * kMaxLevels, LevelDev{});
+    h->ainv_host.resize((size_t)count * kCoarsePad * kCoarsePad);
+    const int64_t kkt = 3 * s.blk;
+    h->rhs_host.assign((size_t)count * kkt, 0.0);
+    for (int b = 0; b < count; ++b) {
+        const sg_problem& p = probs[b];
+        std::vector<double> c = coefficient_modes(p);
+        std::copy(c.begin(), c.end(), h->coef_host.begin() + cm * b);
+        MemberDev& md = h->mem_host[b];
+        md.beta = p.beta;
+        md.gamma = p.gamma;
+        md.hg = 1.0 + p.gamma;
+        md.c0 = c[0];
+        const double sq = std::sqrt((1.0 + p.gamma) / p.beta);
+        if (!s.time) {
+            md.tau = 1.0;
+            md.a1 = md.c0;          // A-tilde_1 = A_1 + sqrt((1+gamma)/beta) M  (eq. mathcalZ)
+            md.b1 = sq;
+            md.off_scale = 1.0;
+        } else {
+            md.tau = p.T / s.nt;    // A-hat_1 = (1 + tau sqrt((1+gamma)/beta)) M + tau A_1  (eq. A_hat)
+            md.a1 = md.tau * md.c0;
+            md.b1 = 1.0 + md.tau * sq;
+            md.off_scale = md.tau;
+        }
+        for (int l = 0; l < s.nlev_mg; ++l) {
+            LevelDev& L = h->lev_host[(size_t)b * kMaxLevels + l];
+            const int m = s.mg_n[l];
+            const double hh = 1.0 / m;
+            L.wc = md.a1 * 8.0 / 3.0 + md.b1 * 16.0 * hh * hh / 36.0;
+            L.we = -md.a1 / 3.0 + md.b1 * 4.0 * hh * hh / 36.0;
+            L.wd = -md.a1 / 3.0 + md.b1 * hh * hh / 36.0;
+            L.dinv = 1.0 / L.wc;
+            const double lmax = lambda_max(m, md.a1, md.b1);
+            smoother_coeffs(lmax, opt.gmg_pre, L.pre);
+            smoother_coeffs(lmax, opt.gmg_post, L.post);
+        }
+        coarse_inverse(md.a1, md.b1, h->ainv_host.data() + (size_t)b * kCoarsePad * kCoarsePad);
+
+        // right-hand side: b_y = tau D_t (M_full y_d)_interior in chaos column 0;
+        // time with y0: b_lambda(t=0, j=0) = -(M_II y0)
+        double* rb = h->rhs_host.data() + (size_t)b * kkt;
+        const double hh = 1.0 / n;
+        const double w = hh * hh / 36.0;
+        const int N1 = n + 1;
+        for (int t = 0; t < s.nt; ++t) {
+            const double* yd = p.y_target + (size_t)t * s.nodes;
+            const double Dt = (s.time && (t == 0 || t == s.nt - 1)) ? 0.5 : 1.0;
+            const double f = md.tau * Dt;
+            for (int iy = 1; iy < n; ++iy)
+                for (int ix = 1; ix < n; ++ix) {
+                    const int q = iy * N1 + ix;
+                    const double v = 16.0 * yd[q] + 4.0 * (yd[q - 1] + yd[q + 1] + yd[q - N1] + yd[q + N1]) +
+                                     (yd[q - N1 - 1] + yd[q - N1 + 1] + yd[q + N1 - 1] + yd[q + N1 + 1]);
+                    rb[(size_t)t * s.tstride + q] = f * w * v;
+                }
+        }
+        if (s.time && p.y0) {
+            double* rl = rb + 2 * s.blk;
+            for (int iy = 1; iy < n; ++iy)
+                for (int ix = 1; ix < n; ++ix) {
+                    auto y0i = [&](int jx, int jy) {
+                        return (jx < 1 || jx > n - 1 || jy < 1 || jy > n - 1) ? 0.0 : p.y0[jy * N1 + jx];
+                    };
+                    const double v = 16.0 * y0i(ix, iy) +
+                                     4.0 * (y0i(ix - 1, iy) + y0i(ix + 1, iy) + y0i(ix, iy - 1) + y0i(ix, iy + 1)) +
+                                     (y0i(ix - 1, iy - 1) + y0i(ix + 1, iy - 1) + y0i(ix - 1, iy + 1) +
+                                      y0i(ix + 1, iy + 1));
+                    rl[iy * N1 + ix] = -w * v;
+                }
+        }
+    }
+
+    // upload
+    h->d_nbr_idx = upload(h->ht.nbr_idx.data(), h->ht.nbr_idx.size());
+    h->d_nbr_val = upload(h->ht.nbr_val.data(), h->ht.nbr_val.size());
+    h->d_coef64 = upload(h->coef_host.data(), h->coef_host.size());
+    {
+        std::vector<float> c32(h->coef_host.begin(), h->coef_host.end());
+        h->d_coef32 = upload(c32.data(), c32.size());
+    }
+    h->d_mem = upload(h->mem_host.data(), h->mem_host.size());
+    h->d_lev = upload(h->lev_host.data(), h->lev_host.size());
+    h->d_ainv64 = upload(h->ainv_host.data(), h->ainv_host.size());
+    {
+        std::vector<float> a32(h->ainv_host.begin(), h->ainv_host.end());
+        h->d_ainv32 = upload(a32.data(), a32.size());
+    }
+    h->d_rhs = upload(h->rhs_host.data(), h->rhs_host.size());
+    h->rhs_host.clear();
+    h->rhs_host.shrink_to_fit();
+    SG_HIP(hipHostMalloc((void**)&h->h_pinned, 4096 * sizeof(double), hipHostMallocDefault));
+    h->h_pinned_count = 4096;
+    h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return h;
+}
+
+}  // namespace sg

@@ -1,0 +1,452 @@
+// Solver orchestration on one HIP stream: operator and KKT applies, the
+// block-diagonal preconditioner (Chebyshev mass solves, hierarchical
+// Gauss-Seidel with multigrid inner solves), flexible GMRES with FP64 Arnoldi,
+// and FP64 iterative refinement around an FP32 inner solve.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "handle.hpp"
+
+namespace sg {
+
+namespace {
+
+template <typename T>
+const char* tname() {
+    return sizeof(T) == 8 ? "64" : "32";
+}
+
+// Column map for the degree-d columns of a field block stored with member stride `mstride`.
+ColMap level_map(const Shape& s, int d, int64_t mstride) {
+    ColMap m;
+    m.mstride = mstride;
+    m.tstride = s.tstride;
+    m.nodes = s.nodes;
+    m.L = s.off[d + 1] - s.off[d];
+    m.nt = s.nt;
+    m.j0 = s.off[d];
+    return m;
+}
+
+ColMap block_map(const Shape& s, int64_t mstride) {
+    ColMap m;
+    m.mstride = mstride;
+    m.tstride = s.tstride;
+    m.nodes = s.nodes;
+    m.L = s.nxi;
+    m.nt = s.nt;
+    m.j0 = 0;
+    return m;
+}
+
+// One multigrid V-cycle for the columns of degree level d (all members, all
+// time steps): b (level-d columns through bmap) -> x (through xmap).  Column c
+// uses the constants of member c / cpm (cpm = ncols when all columns share
+// member 0).
+template <typename T>
+void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, int cpm, hipStream_t st) {
+    const Shape& s = h.s;
+    const LevelDev* lev = h.d_lev;
+    const int nl = s.nlev_mg;
+    const int npre = h.opt.gmg_pre, npost = h.opt.gmg_post;
+    if (nl == 1) {
+        launch_mg_coarse<T>(h.ainv<T>(), b, bmap, x, xmap, ncols, cpm, st);
+        return;
+    }
+    // scratch per level: xa, xb, d, r, (levels >= 1: b)
+    std::vector<T*> xa(nl), xb(nl), dd(nl), rr(nl), bb(nl);
+    for (int l = 0; l < nl; ++l) {
+        const int m = s.mg_n[l];
+        const size_t cnt = (size_t)ncols * (m + 1) * (m + 1);
+        const std::string tag = std::string("mg") + tname<T>() + "_" + std::to_string(l);
+        xa[l] = h.ws.get_t<T>(tag + "_xa", cnt);
+        xb[l] = h.ws.get_t<T>(tag + "_xb", cnt);
+        dd[l] = h.ws.get_t<T>(tag + "_d", cnt);
+        if (l < nl - 1) rr[l] = h.ws.get_t<T>(tag + "_r", cnt);
+        if (l > 0) bb[l] = h.ws.get_t<T>(tag + "_b", cnt);
+    }
+    // downward: pre-smoothing, residual, restriction
+    std::vector<T*> cur(nl);
+    for (int l = 0; l < nl - 1; ++l) {
+        const int m = s.mg_n[l];
+        const int64_t nodes = (int64_t)(m + 1) * (m + 1);
+        const ColMap cmap = contiguous_cols(ncols, nodes);
+        const T* bl = l == 0 ? b : bb[l];
+        const ColMap blm = l == 0 ? bmap : cmap;
+        T* a = xa[l];
+        T* o = xb[l];
+        launch_mg_cheb_first<T>(m, lev, l, 0, bl, blm, a, cmap, dd[l], ncols, cpm, st);
+        for (int k = 1; k < npre; ++k) {
+            launch_mg_cheb_step<T>(m, lev, l, 0, k, bl, blm, a, cmap, o, cmap, dd[l], ncols, cpm, st);
+            std::swap(a, o);
+        }
+        cur[l] = a;
+        launch_mg_residual<T>(m, lev, l, bl, blm, a, cmap, rr[l], ncols, cpm, st);
+        launch_mg_restrict<T>(s.mg_n[l + 1], rr[l], bb[l + 1], ncols, st);
+    }
+    // coarsest
+    {
+        const int l = nl - 1;
+        const int m = s.mg_n[l];
+        const ColMap cmap = contiguous_cols(ncols, (int64_t)(m + 1) * (m + 1));
+        launch_mg_coarse<T>(h.ainv<T>(), bb[l], cmap, xa[l], cmap, ncols, cpm, st);
+        cur[l] = xa[l];
+    }
+    // upward: prolongation, post-smoothing
+    for (int l = nl - 2; l >= 0; --l) {
+        const int m = s.mg_n[l];
+        const int64_t nodes = (int64_t)(m + 1) * (m + 1);
+        const ColMap cmap = contiguous_cols(ncols, nodes);
+        const T* bl = l == 0 ? b : bb[l];
+        const ColMap blm = l == 0 ? bmap : cmap;
+        T* a = cur[l];
+        T* o = (a == xa[l]) ? xb[l] : xa[l];
+        launch_mg_prolong_add<T>(s.mg_n[l + 1], cur[l + 1], a, ncols, st);
+        for (int k = 0; k < npost; ++k) {
+            const bool final_out = (l == 0 && k == npost - 1);
+            launch_mg_cheb_step<T>(m, lev, l, 1, k, bl, blm, a, cmap, final_out ? x : o, final_out ? xmap : cmap,
+                                   dd[l], ncols, cpm, st);
+            if (!final_out) std::swap(a, o);
+        }
+        cur[l] = a;
+    }
+}
+
+// hGS (Algorithm 1): V = Z_r^{-1}-approximation applied to R, zero initial
+// guess, forward sweep over degrees 0..P then backward P-1..0.  R and V are
+// field blocks with member strides rms / vms; nmem members.
+template <typename T>
+void hgs(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nmem, bool shared, hipStream_t st) {
+    const Shape& s = h.s;
+    const OpDev op = h.op<T>(shared);
+    const uint32_t mask = h.modes_mask();
+    T* Bs = h.ws.get_t<T>(std::string("hgsB") + tname<T>(), (size_t)nmem * s.blk);
+    const ColMap vfull = block_map(s, vms);
+    for (int d = 0; d <= s.P; ++d) {
+        const ColMap rm = level_map(s, d, rms), bm = level_map(s, d, s.blk), vm = level_map(s, d, vms);
+        launch_hgs_rhs<T>(s, op, d, d > 0 ? mask : 0u, 1, 0, R, rm, V, vfull, Bs, bm, nmem, st);
+        const int L = s.off[d + 1] - s.off[d];
+        vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
+    }
+    if (mask == 0) return;   // mean-based: the backward sweep repeats the forward solves exactly
+    for (int d = s.P - 1; d >= 0; --d) {
+        const ColMap bm = level_map(s, d, s.blk), vm = level_map(s, d, vms);
+        launch_hgs_rhs<T>(s, op, d, mask, 0, 1, Bs, bm, V, vfull, Bs, bm, nmem, st);
+        const int L = s.off[d + 1] - s.off[d];
+        vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
+    }
+}
+
+}  // namespace
+
+template <typename T>
+void operator_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st) {
+    launch_sg_apply<T>(h.s, h.op<T>(shared), x, y, nvec, st);
+}
+
+template <typename T>
+void kkt_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st) {
+    launch_kkt_apply<T>(h.s, h.op<T>(shared), x, y, nvec, st);
+}
+
+// Block-diagonal preconditioner (eq. stoch-prec / eq. precon for time).
+template <typename T>
+void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st) {
+    const Shape& s = h.s;
+    const OpDev op = h.op<T>(shared);
+    const int64_t kkt = 3 * s.blk;
+    // state and control blocks: Chebyshev semi-iteration on M with block scalings
+    T* A = h.ws.get_t<T>(std::string("chebA") + tname<T>(), (size_t)nvec * 2 * s.blk);
+    T* Bb = h.ws.get_t<T>(std::string("chebB") + tname<T>(), (size_t)nvec * 2 * s.blk);
+    launch_mass_cheb<T>(s, op, r, z, A, Bb, nvec, h.opt.cheb_steps, st);
+    // adjoint block: S^{-1} r = Z^{-1} (tau D (x) M_gamma) Z^{-1} r
+    T* V1 = h.ws.get_t<T>(std::string("schurV") + tname<T>(), (size_t)nvec * s.blk);
+    T* W = h.ws.get_t<T>(std::string("schurW") + tname<T>(), (size_t)nvec * s.blk);
+    hgs<T>(h, r + 2 * s.blk, kkt, V1, s.blk, nvec, shared, st);
+    const ColMap vm = block_map(s, s.blk);
+    launch_mass_scaled<T>(s, op, V1, vm, W, vm, nvec * s.nt * s.nxi, nvec, st);
+    hgs<T>(h, W, s.blk, z + 2 * s.blk, kkt, nvec, shared, st);
+}
+
+template void operator_apply<double>(Handle&, const double*, double*, int, bool, hipStream_t);
+template void operator_apply<float>(Handle&, const float*, float*, int, bool, hipStream_t);
+template void kkt_apply<double>(Handle&, const double*, double*, int, bool, hipStream_t);
+template void kkt_apply<float>(Handle&, const float*, float*, int, bool, hipStream_t);
+template void precond_apply<double>(Handle&, const double*, double*, int, bool, hipStream_t);
+template void precond_apply<float>(Handle&, const float*, float*, int, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Flexible GMRES
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Krylov {
+    Handle& h;
+    int B;
+    int m;                 // restart
+    int64_t N;             // KKT vector length per member
+    int nblk;
+    hipStream_t st;
+    double* V;             // [m+1][B][N]
+    void* Z;               // [m][B][N] (double or float)
+    bool z32;
+    double* w;             // [B][N]
+    double* partial;       // [B][32][nblk]
+    KrylovDev kd;
+    int* d_jend;
+    float* v32;            // [B][N] FP32 staging (inner FP32 mode)
+    float* w32;
+
+    explicit Krylov(Handle& hh, bool fp32) : h(hh), st(hh.stream) {
+        const Shape& s = h.s;
+        B = h.B;
+        m = h.opt.restart;
+        N = 3 * s.blk;
+        nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, N / (256 * 16)));
+        z32 = fp32;
+        V = h.ws.get_t<double>("kV", (size_t)(m + 1) * B * N);
+        Z = z32 ? (void*)h.ws.get_t<float>("kZ32", (size_t)m * B * N) : (void*)h.ws.get_t<double>("kZ", (size_t)m * B * N);
+        w = h.ws.get_t<double>("kw", (size_t)B * N);
+        partial = h.ws.get_t<double>("kpart", (size_t)B * 32 * nblk);
+        const int ld = m + 1;
+        kd.H = h.ws.get_t<double>("kH", (size_t)B * ld * m);
+        kd.cs = h.ws.get_t<double>("kcs", (size_t)B * m);
+        kd.sn = h.ws.get_t<double>("ksn", (size_t)B * m);
+        kd.g = h.ws.get_t<double>("kg", (size_t)B * ld);
+        kd.h1 = h.ws.get_t<double>("kh1", (size_t)B * ld);
+        kd.h2 = h.ws.get_t<double>("kh2", (size_t)B * ld);
+        kd.nrm = h.ws.get_t<double>("knrm", (size_t)B);
+        kd.y = h.ws.get_t<double>("ky", (size_t)B * m);
+        kd.resid = h.ws.get_t<double>("kres", (size_t)B);
+        kd.active = h.ws.get_t<int>("kact", (size_t)B);
+        d_jend = h.ws.get_t<int>("kjend", (size_t)B);
+        v32 = z32 ? h.ws.get_t<float>("kv32", (size_t)B * N) : nullptr;
+        w32 = z32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
+    }
+    double* Vi(int i) { return V + (int64_t)i * B * N; }
+
+    // y = K x for all members (FP64, or through FP32 when fp32)
+    void apply_op(const double* x, double* y, bool fp32) {
+        if (!fp32) {
+            kkt_apply<double>(h, x, y, B, B == 1, st);
+        } else {
+            launch_cast_d2f(x, v32, (int64_t)B * N, st);
+            kkt_apply<float>(h, v32, w32, B, B == 1, st);
+            launch_cast_f2d(w32, y, (int64_t)B * N, st);
+        }
+    }
+    // Z_j = P^{-1} V_j
+    void apply_prec(int j) {
+        if (!z32) {
+            precond_apply<double>(h, Vi(j), (double*)Z + (int64_t)j * B * N, B, B == 1, st);
+        } else {
+            launch_cast_d2f(Vi(j), v32, (int64_t)B * N, st);
+            precond_apply<float>(h, v32, (float*)Z + (int64_t)j * B * N, B, B == 1, st);
+        }
+    }
+    // w = K Z_j
+    void apply_op_z(int j) {
+        if (!z32) {
+            kkt_apply<double>(h, (double*)Z + (int64_t)j * B * N, w, B, B == 1, st);
+        } else {
+            kkt_apply<float>(h, (float*)Z + (int64_t)j * B * N, w32, B, B == 1, st);
+            launch_cast_f2d(w32, w, (int64_t)B * N, st);
+        }
+    }
+    // per-member squared norms of x (FP64) -> host
+    void norms2(const double* x, std::vector<double>& out) {
+        launch_norm(x, N, B, N, partial, nblk, st);
+        launch_reduce_partials(partial, nblk, 1, B, kd.nrm, 1, 0, st);
+        readback(kd.nrm, out);
+    }
+    void readback(const double* d, std::vector<double>& out) {
+        out.resize(B);
+        SG_HIP(hipMemcpyAsync(h.h_pinned, d, sizeof(double) * B, hipMemcpyDeviceToHost, st));
+        SG_HIP(hipStreamSynchronize(st));
+        std::memcpy(out.data(), h.h_pinned, sizeof(double) * B);
+    }
+    // r = b - K x, returns squared norms (r left in `r`)
+    void residual(const double* b, const double* x, double* r, bool fp32, std::vector<double>& nr2) {
+        apply_op(x, r, fp32);
+        launch_sub_norm(b, r, N, B, N, partial, nblk, st);
+        launch_reduce_partials(partial, nblk, 1, B, kd.nrm, 1, 0, st);
+        readback(kd.nrm, nr2);
+    }
+};
+
+// Restarted FGMRES on K x = b from the current x for the members with
+// todo[b] != 0, stopping member b when ||b - K x|| <= tol_abs[b] (checked on
+// the true residual at the end of each cycle).  Returns iterations done.
+int fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol_abs, std::vector<int>& todo,
+           bool fp32, int max_iter, std::vector<double>& res_out, std::vector<int>& member_iters, int verbose) {
+    Handle& h = K.h;
+    const int B = K.B, m = K.m;
+    const int64_t N = K.N;
+    hipStream_t st = K.st;
+    double* r = h.ws.get_t<double>("kr", (size_t)B * N);
+    std::vector<double> nr2, resid;
+    std::vector<int> jend(B, 0), active(B, 0);
+    int iters = 0;
+    res_out.assign(B, 0.0);
+    while (true) {
+        K.residual(b, x, r, fp32, nr2);
+        bool any = false;
+        for (int q = 0; q < B; ++q) {
+            res_out[q] = std::sqrt(nr2[q]);
+            if (todo[q] && res_out[q] <= tol_abs[q]) todo[q] = 0;
+            any = any || todo[q];
+        }
+        if (verbose)
+            for (int q = 0; q < B; ++q)
+                std::fprintf(stderr, "[sg] member %d iters %d true residual %.3e (tol %.3e)\n", q, iters, res_out[q],
+                             tol_abs[q]);
+        if (!any || iters >= max_iter) break;
+        // cycle start: g = (beta, 0, ...), V_0 = r / beta
+        for (int q = 0; q < B; ++q) {
+            active[q] = todo[q];
+            jend[q] = 0;
+        }
+        SG_HIP(hipMemcpyAsync(K.kd.active, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+        launch_cycle_start(K.kd, m, K.kd.nrm, B, st);    // kd.nrm holds ||r||^2 from residual()
+        launch_copy_scale_rows(r, K.Vi(0), K.kd.nrm, N, B, N, st);
+        for (int j = 0; j < m; ++j) {
+            K.apply_prec(j);
+            K.apply_op_z(j);
+            const int nv = j + 1;
+            // CGS2: h1 = V^T w; w1 = w - V h1; h2 = V^T w1; w2 = w1 - V h2
+            launch_multidot(K.V, (int64_t)B * N, nv, K.w, N, B, N, K.partial, K.nblk, st);
+            launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h1, m + 1, 0, st);
+            launch_cgs_update_dot(K.V, (int64_t)B * N, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
+            launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h2, m + 1, 0, st);
+            launch_cgs_update_norm(K.V, (int64_t)B * N, nv, K.kd.h2, m + 1, K.w, K.Vi(j + 1), N, B, N, K.partial,
+                                   K.nblk, st);
+            launch_reduce_partials(K.partial, K.nblk, 1, B, K.kd.nrm, 1, 0, st);
+            launch_arnoldi_finish(K.kd, m, j, B, st);
+            launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
+            K.readback(K.kd.resid, resid);
+            ++iters;
+            bool still = false;
+            bool changed = false;
+            for (int q = 0; q < B; ++q) {
+                if (!active[q]) continue;
+                jend[q] = j + 1;
+                ++member_iters[q];
+                if (resid[q] <= tol_abs[q]) {
+                    active[q] = 0;
+                    changed = true;
+                } else {
+                    still = true;
+                }
+            }
+            if (!still || iters >= max_iter) break;
+            if (changed)
+                SG_HIP(hipMemcpyAsync(K.kd.active, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+        }
+        SG_HIP(hipMemcpyAsync(K.d_jend, jend.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+        launch_back_solve(K.kd, m, K.d_jend, B, st);
+        launch_multi_axpy(K.Z, K.z32 ? 1 : 0, (int64_t)B * N, m, K.d_jend, K.kd.y, m, x, N, B, N, st);
+    }
+    return iters;
+}
+
+}  // namespace
+
+int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
+    auto t0 = std::chrono::steady_clock::now();
+    const Shape& s = h.s;
+    const int B = h.B;
+    const int64_t N = 3 * s.blk;
+    hipStream_t st = h.stream;
+    // right-hand side with a zero boundary ring
+    double* b = h.ws.get_t<double>("sb", (size_t)B * N);
+    SG_HIP(hipMemcpyAsync(b, b_dev ? b_dev : h.d_rhs, sizeof(double) * B * N, hipMemcpyDeviceToDevice, st));
+    launch_zero_ring<double>(b, s.n, (int64_t)B * 3 * s.nt * s.nxi, st);
+    SG_HIP(hipMemsetAsync(x_dev, 0, sizeof(double) * B * N, st));
+
+    const bool fp32 = h.opt.precision == SG_PREC_FP32_REFINE;
+    Krylov K(h, fp32);
+    std::vector<double> bn2;
+    K.norms2(b, bn2);
+    std::vector<double> tol(B), res(B, 0.0);
+    std::vector<int> todo(B, 1);
+    for (int q = 0; q < B; ++q) tol[q] = h.opt.rtol * std::sqrt(bn2[q]);
+    int iters = 0;
+    std::vector<int> member_iters(B, 0), member_outer(B, 0);
+    if (!fp32) {
+        iters = fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, res, member_iters, h.opt.verbose);
+    } else {
+        // FP64 iterative refinement: r = b - K64 x; inner FGMRES with the FP32
+        // operator and preconditioner on K d = r to inner_rtol ||r||; x += d.
+        // A member whose refinement step fails to halve its residual continues
+        // with FP64 inner solves.  Each member's arithmetic depends only on its
+        // own data (inactive members are masked), so batching never changes a
+        // member's result.
+        double* r = h.ws.get_t<double>("sr", (size_t)B * N);
+        double* d = h.ws.get_t<double>("sd", (size_t)B * N);
+        std::vector<double> nr2, prev(B, INFINITY);
+        std::vector<int> fallback(B, 0);
+        std::unique_ptr<Krylov> K64;
+        while (iters < h.opt.max_iter) {
+            K.residual(b, x_dev, r, false, nr2);
+            std::vector<int> todo32(B, 0), todo64(B, 0);
+            std::vector<double> tol_in(B, 0.0);
+            bool any32 = false, any64 = false;
+            for (int q = 0; q < B; ++q) {
+                res[q] = std::sqrt(nr2[q]);
+                if (res[q] <= tol[q] || member_iters[q] >= h.opt.max_iter) continue;
+                if (res[q] > 0.5 * prev[q]) fallback[q] = 1;
+                prev[q] = res[q];
+                tol_in[q] = std::max(h.opt.inner_rtol * res[q], 0.5 * tol[q]);
+                ++member_outer[q];
+                if (fallback[q]) {
+                    todo64[q] = 1;
+                    any64 = true;
+                } else {
+                    todo32[q] = 1;
+                    any32 = true;
+                }
+            }
+            if (!any32 && !any64) break;
+            SG_HIP(hipMemsetAsync(d, 0, sizeof(double) * B * N, st));
+            std::vector<double> rin;
+            int done = 0;
+            if (any32) done = std::max(done, fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter - iters, rin,
+                                                    member_iters, h.opt.verbose));
+            if (any64) {
+                if (!K64) K64.reset(new Krylov(h, false));
+                done = std::max(done, fgmres(*K64, r, d, tol_in, todo64, false, h.opt.max_iter - iters, rin,
+                                             member_iters, h.opt.verbose));
+            }
+            iters += std::max(done, 1);
+            launch_axpby(1.0, d, 1.0, x_dev, (int64_t)B * N, st);
+        }
+        K.residual(b, x_dev, r, false, nr2);
+        for (int q = 0; q < B; ++q) res[q] = std::sqrt(nr2[q]);
+    }
+    SG_HIP(hipStreamSynchronize(st));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    bool all = true;
+    for (int q = 0; q < B; ++q) {
+        const double bn = std::sqrt(bn2[q]);
+        const double rel = bn > 0 ? res[q] / bn : 0.0;
+        const bool conv = rel <= h.opt.rtol;
+        all = all && conv;
+        if (info) {
+            info[q].iters = member_iters[q];
+            info[q].outer_refinements = member_outer[q];
+            info[q].converged = conv ? 1 : 0;
+            info[q].status = conv ? SG_OK : SG_NOT_CONVERGED;
+            info[q].rel_res_true = rel;
+            info[q].t_setup_ms = h.t_setup_ms;
+            info[q].t_solve_ms = ms;
+            info[q].latency_ms = ms;
+            info[q].bytes_moved = 0.0;
+        }
+    }
+    return all ? SG_OK : SG_NOT_CONVERGED;
+}
+
+}  // namespace sg

@@ -1,0 +1,98 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/sg.h, and rejects invalid problems on the host."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import sg_inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "sg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:int|void|const char\*)\s+\*?\s*(sg_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2512_23804_amd as sgl
+    names = _declared_functions()
+    assert len(names) >= 18
+    raw = ctypes.CDLL(sgl._lib.LIB_PATH)
+    for name in names:
+        assert hasattr(raw, name), name
+        assert name in sgl.SIGNATURES, name
+    assert set(sgl.SIGNATURES) == set(names)
+
+
+def test_default_options():
+    import paper_2512_23804_amd as sgl
+    o = sgl.default_options()
+    assert o.rtol == 1e-8 and o.restart == 30 and o.cheb_steps == 5 and o.gmg_pre == 2 and o.gmg_post == 2
+    assert o.precision == sgl.SG_PREC_FP64 and o.truncation_r == 0
+
+
+def _pd(**kw):
+    import paper_2512_23804_amd as sgl
+    base = dict(n=16, M=4, P=3, sigma=0.2, beta=1e-2, y_target=sg_inputs.gaussian_bumps(16, 0))
+    base.update(kw)
+    return sgl.ProblemData(**base)
+
+
+def test_validate_accepts_workload():
+    import paper_2512_23804_amd as sgl
+    assert sgl.validate(_pd()) == sgl.SG_OK
+    assert sgl.validate(_pd(n=128, M=6, P=4, sigma=0.3, y_target=sg_inputs.gaussian_bumps(128, 1))) == sgl.SG_OK
+    tgt = sg_inputs.moving_bump(64, 32, 1.0, 4)
+    assert sgl.validate(_pd(n=64, n_t=32, beta=1e-3, y_target=tgt)) == sgl.SG_OK
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=12), -1), (dict(n=4), -1), (dict(M=0), -1), (dict(M=17), -1), (dict(P=0), -1), (dict(P=9), -1),
+    (dict(beta=0.0), -1), (dict(beta=-1.0), -1), (dict(gamma=-0.1), -1), (dict(beta=float("nan")), -3),
+    (dict(sigma=0.9), -2),
+])
+def test_validate_rejects(kw, code):
+    import paper_2512_23804_amd as sgl
+    assert sgl.validate(_pd(**kw)) == code
+    assert sgl.lib.sg_last_error().decode() != ""
+
+
+def test_validate_nonfinite_target_and_custom_kappa():
+    import paper_2512_23804_amd as sgl
+    t = sg_inputs.gaussian_bumps(16, 0)
+    t[7] = np.inf
+    assert sgl.validate(_pd(y_target=t)) == sgl.SG_ERR_NONFINITE
+    kap = np.zeros((5, 16, 16))
+    kap[0] = 2.0
+    kap[1] = 0.3
+    assert sgl.validate(_pd(kappa=kap)) == sgl.SG_OK
+    kap[1] = 1.2                      # 2 - sqrt(3) * 1.2 < 0: can vanish
+    assert sgl.validate(_pd(kappa=kap)) == sgl.SG_ERR_NONCOERCIVE
+    kap[1] = 0.3
+    kap[0, 3, 3] = 2.5                # mean must be constant for the multigrid
+    assert sgl.validate(_pd(kappa=kap)) == sgl.SG_ERR_INVALID
+
+
+def test_validate_options():
+    import paper_2512_23804_amd as sgl
+    for kw in (dict(restart=0), dict(restart=40), dict(cheb_steps=0), dict(truncation_r=6), dict(gmg_pre=0),
+               dict(precision=3), dict(rtol=0.0)):
+        assert sgl.validate(_pd(), sgl.default_options(**kw)) == sgl.SG_ERR_INVALID, kw
+
+
+def test_setup_rejects_before_touching_the_device():
+    import ctypes as C
+
+    import paper_2512_23804_amd as sgl
+    p = _pd(sigma=0.95)
+    h = C.c_void_p()
+    rc = sgl.lib.sg_setup(C.byref(p.c), 1, None, None, C.byref(h))
+    assert rc == sgl.SG_ERR_NONCOERCIVE and not h.value
+    rc = sgl.lib.sg_setup(C.byref(p.c), 0, None, None, C.byref(h))
+    assert rc == sgl.SG_ERR_INVALID

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances (element-wise, scaled by the reference's max-norm):
+  * multi-index set and triple-product sparsity: bit-exact;
+  * FP64 operator / KKT / preconditioner applies: 1e-12;
+  * solutions: each block within 1e-8 of the direct solve (solved to 1e-12);
+  * FP32 applies: 1e-5 (single-precision rounding of O(10)-term sums).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import basis, fem, kkt, precond
+
+from _helpers import canonical_to_kkt, kkt_to_canonical, make_case, rel_max, ring_is_zero
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2512_23804_amd as sgl
+    return sgl
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _setup(lib_kw_list, **opt):
+    sgl = _lib()
+    probs = [sgl.ProblemData(**kw) for kw in lib_kw_list]
+    return sgl.Handle(probs, sgl.default_options(**opt))
+
+
+SHAPES = [
+    # n, M, P, sigma, beta, gamma, n_t
+    (8, 1, 1, 0.3, 1e-2, 0.0, 1),
+    (16, 4, 3, 0.2, 1e-2, 0.0, 1),       # the small steady workload
+    (32, 3, 2, 0.25, 1e-4, 0.5, 1),
+    (16, 2, 3, 0.3, 1e-3, 0.0, 4),
+    (8, 3, 2, 0.2, 1e-2, 0.7, 3),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_multiindex_and_gtable(shape):
+    n, M, P, sigma, beta, gamma, nt = shape
+    _dev()
+    _say(f"tables {shape}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt)
+    h = _setup([kw])
+    A = basis.multi_indices(M, P)
+    assert np.array_equal(h.multiindex(), A)
+    idx, val = h.gtable()
+    G = basis.triple_product_matrices(M, P)
+    # rebuild dense G_k from the library's table and compare pattern and values
+    for k in range(1, M + 1):
+        Gl = np.zeros_like(G[k])
+        for j in range(A.shape[0]):
+            for s in range(2):
+                i = idx[j, k - 1, s]
+                if i >= 0:
+                    Gl[i, j] = val[j, k - 1, s]
+        assert np.array_equal(Gl != 0, G[k] != 0)
+        assert np.max(np.abs(Gl - G[k])) < 1e-14
+    assert h.level_offsets == list(basis.level_offsets(M, P))
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_operator_apply(shape):
+    n, M, P, sigma, beta, gamma, nt = shape
+    dev = _dev()
+    _say(f"operator apply {shape}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt)
+    sg = kkt.setup(prob)
+    h = _setup([kw])
+    rng = np.random.default_rng(1)
+    nvec = 2
+    X = rng.uniform(-1, 1, size=(nvec, max(nt, 1), sg.n_xi, (n + 1) ** 2))
+    Xd = torch.from_numpy(X).to(dev)
+    Yd = torch.full_like(Xd, np.nan)
+    h.apply_operator(Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy()
+    assert ring_is_zero(Y, n)
+    for v in range(nvec):
+        for t in range(max(nt, 1)):
+            ref = kkt.operator_apply(sg, fem.extract(X[v, t], n))
+            assert rel_max(fem.extract(Y[v, t], n), ref) < 1e-12
+    # FP32 path
+    Yf = torch.zeros_like(Xd, dtype=torch.float32)
+    h.apply_operator(Xd.float(), Yf)
+    torch.cuda.synchronize()
+    ref = kkt.operator_apply(sg, fem.extract(X[0, 0].astype(np.float32).astype(np.float64), n))
+    assert rel_max(fem.extract(Yf.cpu().numpy()[0, 0].astype(np.float64), n), ref) < 1e-5
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_kkt_apply(shape):
+    n, M, P, sigma, beta, gamma, nt = shape
+    dev = _dev()
+    _say(f"kkt apply {shape}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, y0=nt > 1)
+    sg = kkt.setup(prob)
+    h = _setup([kw])
+    K = kkt.kkt_matrix(sg)
+    rng = np.random.default_rng(2)
+    x = rng.uniform(-1, 1, size=K.shape[0])
+    xd = torch.from_numpy(kkt_to_canonical(sg, x)).to(dev)
+    yd = torch.zeros_like(xd)
+    h.apply_kkt(xd, yd)
+    torch.cuda.synchronize()
+    y = canonical_to_kkt(sg, yd.cpu().numpy())
+    assert rel_max(y, K @ x) < 1e-12
+    # right-hand side
+    bd = torch.zeros_like(xd)
+    h.rhs(bd)
+    assert rel_max(canonical_to_kkt(sg, bd.cpu().numpy()), kkt.rhs(sg)) < 1e-14
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("r_trunc", [1, 0])
+def test_precond_apply(shape, r_trunc):
+    n, M, P, sigma, beta, gamma, nt = shape
+    dev = _dev()
+    _say(f"precond {shape} r={r_trunc}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt)
+    sg = kkt.setup(prob)
+    h = _setup([kw], truncation_r=r_trunc)
+    rng = np.random.default_rng(3)
+    m = kkt.kkt_matrix(sg).shape[0]
+    r = rng.uniform(-1, 1, size=m)
+    rd = torch.from_numpy(kkt_to_canonical(sg, r)).to(dev)
+    zd = torch.full_like(rd, np.nan)
+    h.precond_apply(rd, zd)
+    torch.cuda.synchronize()
+    z = canonical_to_kkt(sg, zd.cpu().numpy())
+    ref = precond.precond_apply(sg, r, precond.make_inner(sg), r_trunc if r_trunc else M + 1)
+    for a, b in zip(kkt.split(sg, z), kkt.split(sg, ref)):
+        assert rel_max(a, b) < 1e-12
+    assert ring_is_zero(zd.cpu().numpy(), n)
+
+
+def test_precond_multi_rhs_shares_one_member():
+    dev = _dev()
+    _say("precond multi-rhs")
+    prob, kw = make_case(16, 3, 2, 0.3, 1e-2)
+    sg = kkt.setup(prob)
+    h = _setup([kw])
+    rng = np.random.default_rng(4)
+    m = kkt.kkt_matrix(sg).shape[0]
+    rs = [rng.uniform(-1, 1, size=m) for _ in range(3)]
+    rd = torch.from_numpy(np.concatenate([kkt_to_canonical(sg, r) for r in rs])).to(dev)
+    zd = torch.zeros_like(rd)
+    h.precond_apply(rd, zd)
+    torch.cuda.synchronize()
+    Z = zd.cpu().numpy().reshape(3, -1)
+    inner = precond.make_inner(sg)
+    for i in range(3):
+        assert rel_max(canonical_to_kkt(sg, Z[i]), precond.precond_apply(sg, rs[i], inner)) < 1e-12
+
+
+@pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[2], SHAPES[3]])
+def test_solve_matches_direct(shape):
+    n, M, P, sigma, beta, gamma, nt = shape
+    dev = _dev()
+    _say(f"solve {shape}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, y0=nt > 1)
+    sg = kkt.setup(prob)
+    h = _setup([kw], rtol=1e-12, max_iter=400)
+    xd = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+    rc, info = h.solve(xd)
+    torch.cuda.synchronize()
+    assert rc == 0 and info[0].converged == 1 and info[0].rel_res_true <= 1e-12
+    x = canonical_to_kkt(sg, xd.cpu().numpy())
+    ref = kkt.solve_direct(sg)
+    for a, b in zip(kkt.split(sg, x), kkt.split(sg, ref)):
+        assert rel_max(a, b) < 1e-8
+    # the oracle's own residual of the GPU solution
+    K = kkt.kkt_matrix(sg)
+    b = kkt.rhs(sg)
+    assert np.linalg.norm(b - K @ x) / np.linalg.norm(b) < 1e-11
+
+
+def test_solve_fp32_refine_reaches_fp64_accuracy():
+    dev = _dev()
+    _say("solve fp32 refine")
+    prob, kw = make_case(16, 4, 3, 0.2, 1e-2)
+    sg = kkt.setup(prob)
+    h = _setup([kw], rtol=1e-12, max_iter=600, precision=1)
+    xd = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+    rc, info = h.solve(xd)
+    assert rc == 0 and info[0].rel_res_true <= 1e-12 and info[0].outer_refinements >= 1
+    x = canonical_to_kkt(sg, xd.cpu().numpy())
+    ref = kkt.solve_direct(sg)
+    for a, b in zip(kkt.split(sg, x), kkt.split(sg, ref)):
+        assert rel_max(a, b) < 1e-8
+
+
+def test_batch_results_equal_alone():
+    """Members of one batch (different sigma, beta, targets) give bit-identical
+    results to solving each alone."""
+    dev = _dev()
+    _say("batch invariance")
+    params = [(0.2, 1e-2, 0), (0.3, 1e-4, 1), (0.1, 1e-3, 2)]
+    kws = [make_case(16, 3, 2, s, b, seed=sd)[1] for s, b, sd in params]
+    for prec in (0, 1):
+        hb = _setup(kws, rtol=1e-8, precision=prec)
+        xb = torch.zeros(3 * hb.kkt_elems, dtype=torch.float64, device=dev)
+        rc, infos = hb.solve(xb)
+        assert rc == 0
+        for i, kw in enumerate(kws):
+            ha = _setup([kw], rtol=1e-8, precision=prec)
+            xa = torch.zeros(ha.kkt_elems, dtype=torch.float64, device=dev)
+            rca, infa = ha.solve(xa)
+            assert rca == 0 and infa[0].iters == infos[i].iters
+            assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
