@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark: stochastic-Galerkin KKT solves per second on one MI355X.
+
+A step is one pass of the whole hot path over one batch: a preconditioned
+FGMRES(30) solve to relative residual 1e-8 of every member of the batch
+(block-diagonal Schur preconditioner with Chebyshev mass solves and the
+hierarchical Gauss-Seidel sweep with multigrid inner solves).  The default
+workload is the steady 128 x 128 problem (16,641 nodes, M = 6 random
+variables, total degree P = 4, n_xi = 210, sigma = 0.3) with its beta sweep
+{1e-2, 1e-4, 1e-6} solved as one batch of three members (seeded Gaussian-bump
+targets).  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E
+
+WORKLOADS = {
+    # name: (n, M, P, sigma, betas, n_t, seeds)
+    "steady-128-M6-P4": dict(n=128, M=6, P=4, sigma=0.3, betas=(1e-2, 1e-4, 1e-6), n_t=1, seeds=(1, 2, 3)),
+    "steady-16-M4-P3": dict(n=16, M=4, P=3, sigma=0.2, betas=(1e-2,), n_t=1, seeds=(0,)),
+    "heat-64-M4-P3-nt32": dict(n=64, M=4, P=3, sigma=0.2, betas=(1e-3,), n_t=32, seeds=(4,)),
+    "steady-512-M8-P3": dict(n=512, M=8, P=3, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(5,)),
+}
+DEFAULT = "steady-128-M6-P4"
+PROF_KIND = {"kkt_apply": 1, "mg_smooth": 2, "multidot": 3, "hgs_rhs": 4}
+
+
+def make_problems(sgl, sg_inputs, wl):
+    probs = []
+    for beta, seed in zip(wl["betas"], wl["seeds"]):
+        if wl["n_t"] > 1:
+            tgt = sg_inputs.moving_bump(wl["n"], wl["n_t"], 1.0, seed)
+        else:
+            tgt = sg_inputs.gaussian_bumps(wl["n"], seed)
+        probs.append(sgl.ProblemData(wl["n"], wl["M"], wl["P"], wl["sigma"], beta, tgt, n_t=wl["n_t"], T=1.0))
+    return probs
+
+
+def timed_solves(torch, sgl, probs, opts, steps, warmup, stream):
+    h = sgl.Handle(probs, opts, stream=stream)
+    x = torch.zeros(h.members * h.kkt_elems, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        h.solve(x)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, info = h.solve(x)
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h.close()
+    return dt, infos
+
+
+def sg_apply_bandwidth(torch, sgl, probs, stream, min_bytes=1 << 30, reps=20):
+    """Average duration of the SG operator apply (sg_apply_operator) with HIP
+    events on the library's stream, rotating over enough input/output blocks
+    that the working set exceeds the 256 MB last-level cache."""
+    h = sgl.Handle(probs[:1], sgl.default_options(), stream=stream)
+    blk = h.block_elems
+    nbuf = max(2, int(np.ceil(min_bytes / (16 * blk))))
+    xs = [torch.rand(blk, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+    ys = [torch.empty(blk, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+    with torch.cuda.stream(stream):
+        for i in range(nbuf):
+            h.apply_operator(xs[i], ys[i], stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for r in range(reps):
+            for i in range(nbuf):
+                h.apply_operator(xs[i], ys[i], stream=stream)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (reps * nbuf)
+    s = h.sizes
+    bytes_per = 8.0 * (2 * blk + (s.M + 1) * s.n * s.n)
+    h.close()
+    return dict(ms=ms, bytes=bytes_per, GBps=bytes_per / ms / 1e6, buffers=nbuf)
+
+
+def cpu_baseline(wl, gpu_iters):
+    """The oracle (plain FP64 numpy/scipy, single thread) timed on one
+    preconditioned FGMRES iteration of the first member: one preconditioner
+    application (Chebyshev + two hGS sweeps with multigrid) and one matricized
+    KKT apply; scaled by the GPU run's iterations per solve."""
+    from threadpoolctl import threadpool_limits
+
+    import sg_inputs
+    from oracle import kkt, precond
+
+    with threadpool_limits(limits=1):
+        if wl["n_t"] > 1:
+            tgt = sg_inputs.moving_bump(wl["n"], wl["n_t"], 1.0, wl["seeds"][0])
+        else:
+            tgt = sg_inputs.gaussian_bumps(wl["n"], wl["seeds"][0])
+        prob = kkt.Problem(n=wl["n"], M=wl["M"], P=wl["P"], sigma=wl["sigma"], beta=wl["betas"][0],
+                           n_t=wl["n_t"], y_target=tgt)
+        sg = kkt.setup(prob)
+        inner = precond.make_inner(sg)
+        r = kkt.rhs(sg)
+        t0 = time.perf_counter()
+        z = precond.precond_apply(sg, r, inner)
+        w = kkt.kkt_apply_matricized(sg, z)
+        # Arnoldi work of an average iteration (15 basis vectors, two Gram-Schmidt passes)
+        V = np.random.default_rng(0).standard_normal((15, r.size))
+        for _ in range(2):
+            hcoef = V @ w
+            w = w - V.T @ hcoef
+        t_iter = time.perf_counter() - t0
+    per_solve = t_iter * gpu_iters
+    return dict(value=1.0 / per_solve, unit="solves/s", cores=1, kind="oracle",
+                sample=f"one FGMRES iteration of the oracle at the workload size ({t_iter:.1f} s), "
+                       f"scaled by {gpu_iters:.1f} iterations per solve")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--profile-kernel", default="kkt_apply", choices=sorted(PROF_KIND))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2512_23804_amd as sgl
+    import sg_inputs
+
+    wl = WORKLOADS[args.workload]
+    probs = make_problems(sgl, sg_inputs, wl)
+    stream = torch.cuda.Stream()
+    prof = PROF_KIND[args.profile_kernel]
+
+    # headline: FP64 batch (the whole beta sweep) per step
+    opts = sgl.default_options(rtol=1e-8, profile=prof)
+    dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream)
+    nsolve = len(probs) * args.steps
+    value = nsolve / dt
+    iters = [i.iters for step in infos for i in step]
+    rel = max(i.rel_res_true for step in infos for i in step)
+    pms = sum(step[0].prof_ms for step in infos)
+    pbytes = sum(step[0].prof_bytes for step in infos)
+    plaunch = sum(step[0].prof_launches for step in infos)
+    achieved = pbytes / pms / 1e6 if pms > 0 else 0.0
+    out = {
+        "metric": "KKT solves/s to rel-res 1e-8 (FP64 vs FP32+refine); SG apply HBM GB/s",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Gaussian-bump targets, cosine random field)",
+        "config": {"workload": args.workload, "n": wl["n"], "M": wl["M"], "P": wl["P"], "sigma": wl["sigma"],
+                   "betas": list(wl["betas"]), "n_t": wl["n_t"], "batch": len(probs), "restart": 30,
+                   "rtol": 1e-8, "precision": "fp64"},
+        "iterations": iters[: len(probs)],
+        "max_rel_res": rel,
+        "roofline": {"bound": "hbm", "kernel": args.profile_kernel, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "launches": plaunch, "avg_launch_ms": pms / max(plaunch, 1),
+                     "bytes_per_launch": pbytes / max(plaunch, 1)},
+    }
+    if not args.no_extras:
+        o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE)
+        dt32, inf32 = timed_solves(torch, sgl, probs, o32, args.steps, 1, stream)
+        out["fp32_refine"] = {"value": nsolve / dt32, "unit": "solves/s", "dtype": "f32 operator/preconditioner, "
+                              "f64 Arnoldi and refinement", "iterations": [i.iters for i in inf32[0]],
+                              "max_rel_res": max(i.rel_res_true for st in inf32 for i in st)}
+        single = []
+        t_single = 0.0
+        for p in probs:
+            dts, infs = timed_solves(torch, sgl, [p], sgl.default_options(rtol=1e-8), 1, 1, stream)
+            t_single += dts
+            single.append(infs[0][0].iters)
+        out["fp64_single"] = {"value": len(probs) / t_single, "unit": "solves/s", "iterations": single}
+        out["sg_apply"] = sg_apply_bandwidth(torch, sgl, probs, stream)
+        out["sg_apply"]["frac_of_hbm_peak"] = out["sg_apply"]["GBps"] / HBM_PEAK_GBPS
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, float(np.mean(iters)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -112,14 +112,23 @@ typedef struct sg_problem {
  *   precision    SG_PREC_FP64 or SG_PREC_FP32_REFINE [SG_PREC_FP64]
  *   inner_rtol   FP32 inner solve reduction per refinement step [1e-5]
  *   use_graphs   capture per-iteration launch sequences in hipGraphs [1]
- *   verbose      print per-cycle residuals to stderr [0] */
+ *   verbose      print per-cycle residuals to stderr [0]
+ *   profile      time one kernel's launches with HIP events during sg_solve
+ *                (SG_PROF_* below) and report them in sg_solve_info [0] */
 typedef struct sg_options {
     double rtol;
     int32_t restart, max_iter, cheb_steps, truncation_r;
     int32_t gmg_pre, gmg_post, precision;
     double inner_rtol;
-    int32_t use_graphs, verbose;
+    int32_t use_graphs, verbose, profile;
 } sg_options;
+
+/* Kernels that sg_options.profile can time (HIP events around every launch). */
+#define SG_PROF_NONE        0
+#define SG_PROF_KKT_APPLY   1   /* fused KKT apply (two SG operator applies + mass terms) */
+#define SG_PROF_MG_SMOOTH   2   /* multigrid Chebyshev smoothing step, finest level */
+#define SG_PROF_MULTIDOT    3   /* Arnoldi multi-dot (first Gram-Schmidt pass) */
+#define SG_PROF_HGS_RHS     4   /* hierarchical Gauss-Seidel off-level right-hand side */
 
 /* Per-solve report. */
 typedef struct sg_solve_info {
@@ -132,6 +141,9 @@ typedef struct sg_solve_info {
     double t_solve_ms;          /* wall time of the solve */
     double latency_ms;          /* serving: submit -> completion */
     double bytes_moved;         /* algorithmic HBM bytes of the solve (model) */
+    double prof_ms;             /* profiled kernel: summed launch durations (HIP events) */
+    double prof_bytes;          /* profiled kernel: summed algorithmic bytes of those launches */
+    int32_t prof_launches;      /* profiled kernel: number of launches */
 } sg_solve_info;
 
 /* Sizes of a handle's problems. */

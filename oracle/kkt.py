@@ -354,6 +354,36 @@ def kkt_apply(sg: SG, x: np.ndarray) -> np.ndarray:
     return kkt_matrix(sg) @ x
 
 
+def kkt_apply_matricized(sg: SG, x: np.ndarray) -> np.ndarray:
+    """KKT matrix times a flat vector in the matricized form of
+    eq. (stoch-system-m) (steady) and of the time-dependent blocks, without
+    forming any Kronecker product (for sizes where the explicit matrix is too
+    large).  Uses A_l in all three block rows."""
+    p = sg.prob
+    Y, U, L = split(sg, x)
+    hg = h_gamma(sg)[:, None]
+    if p.steady:
+        RY = hg * mass_apply(sg, Y) - operator_apply(sg, L)
+        RU = p.beta * mass_apply(sg, U) + mass_apply(sg, L)
+        RL = -operator_apply(sg, Y) + mass_apply(sg, U)
+        return np.concatenate([RY.ravel(), RU.ravel(), RL.ravel()])
+    nt, tau = p.n_t, p.tau
+    D = np.ones(nt)
+    D[0] = D[-1] = 0.5
+    RY, RU, RL = np.empty_like(Y), np.empty_like(U), np.empty_like(L)
+    for t in range(nt):
+        ML = mass_apply(sg, L[t])
+        MY = mass_apply(sg, Y[t])
+        MU = mass_apply(sg, U[t])
+        # (A_t^T lambda)_t = L lambda_t - M lambda_{t+1};  (A_t y)_t = L y_t - M y_{t-1}
+        AtL = ML + tau * operator_apply(sg, L[t]) - (mass_apply(sg, L[t + 1]) if t + 1 < nt else 0.0)
+        AtY = MY + tau * operator_apply(sg, Y[t]) - (mass_apply(sg, Y[t - 1]) if t > 0 else 0.0)
+        RY[t] = tau * D[t] * hg * MY - AtL
+        RU[t] = p.beta * tau * D[t] * MU + tau * ML
+        RL[t] = -AtY + tau * MU
+    return np.concatenate([RY.ravel(), RU.ravel(), RL.ravel()])
+
+
 def moments(Y: np.ndarray):
     """Mean and variance fields of an SG expansion (orthonormal basis):
     E[y] = Y_0 and Var[y] = sum_{j>=1} Y_j^2 (Section 2.1, H^sigma)."""

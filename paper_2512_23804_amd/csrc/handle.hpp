@@ -48,6 +48,24 @@ class Workspace {
     size_t total_ = 0;
 };
 
+// HIP-event timing of one kernel's launches (sg_options.profile).
+struct Prof {
+    int kind = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double bytes = 0.0;
+    void reset() {
+        used = 0;
+        bytes = 0.0;
+    }
+    ~Prof() {
+        for (auto& e : ev) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+};
+
 struct Handle {
     Shape s{};
     int B = 1;                          // members
@@ -75,6 +93,7 @@ struct Handle {
     double* d_rhs = nullptr;
 
     Workspace ws;
+    Prof prof;
     double* h_pinned = nullptr;        // host-pinned scratch for small readbacks
     size_t h_pinned_count = 0;
 
@@ -110,6 +129,9 @@ std::vector<int32_t> multi_indices(int M, int P);
 int binom(int n, int k);
 
 // solver.cpp
+bool prof_begin(Handle& h, int kind, hipStream_t st);        // true if this launch is timed
+void prof_end(Handle& h, hipStream_t st, double bytes);
+double prof_collect_ms(Handle& h);                           // waits for the events, sums durations
 template <typename T>
 void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st);
 template <typename T>

@@ -30,6 +30,7 @@ void default_options(sg_options* o) {
     o->inner_rtol = 1e-5;
     o->use_graphs = 1;
     o->verbose = 0;
+    o->profile = SG_PROF_NONE;
 }
 
 // Total-degree multi-indices, degree ascending, descending lexicographic order
@@ -84,7 +85,7 @@ static std::vector<double> coefficient_modes(const sg_problem& p) {
 
 void validate(const sg_problem* probs, int count, const sg_options* opt) {
     if (!probs || count < 1) fail(SG_ERR_INVALID, "no problems given");
-    if (count > 4096) fail(SG_ERR_INVALID, "too many members in one batch (max 4096)");
+    if (count > 2048) fail(SG_ERR_INVALID, "too many members in one batch (max 2048)");
     const sg_problem& p0 = probs[0];
     for (int i = 0; i < count; ++i) {
         const sg_problem& p = probs[i];
@@ -154,6 +155,7 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
             fail(SG_ERR_INVALID, "gmg_pre/gmg_post must be in [1, 4]");
         if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32_REFINE)
             fail(SG_ERR_INVALID, "unknown precision mode");
+        if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_HGS_RHS) fail(SG_ERR_INVALID, "unknown profile kind");
         if (opt->precision == SG_PREC_FP32_REFINE && !(opt->inner_rtol > 0 && opt->inner_rtol < 1))
             fail(SG_ERR_INVALID, "inner_rtol must be in (0, 1)");
     }

@@ -12,6 +12,35 @@
 
 namespace sg {
 
+bool prof_begin(Handle& h, int kind, hipStream_t st) {
+    if (h.prof.kind != kind || kind == SG_PROF_NONE) return false;
+    if (h.prof.used == h.prof.ev.size()) {
+        hipEvent_t a, b;
+        SG_HIP(hipEventCreate(&a));
+        SG_HIP(hipEventCreate(&b));
+        h.prof.ev.push_back({a, b});
+    }
+    SG_HIP(hipEventRecord(h.prof.ev[h.prof.used].first, st));
+    return true;
+}
+
+void prof_end(Handle& h, hipStream_t st, double bytes) {
+    SG_HIP(hipEventRecord(h.prof.ev[h.prof.used].second, st));
+    ++h.prof.used;
+    h.prof.bytes += bytes;
+}
+
+double prof_collect_ms(Handle& h) {
+    double total = 0.0;
+    for (size_t i = 0; i < h.prof.used; ++i) {
+        SG_HIP(hipEventSynchronize(h.prof.ev[i].second));
+        float ms = 0.f;
+        SG_HIP(hipEventElapsedTime(&ms, h.prof.ev[i].first, h.prof.ev[i].second));
+        total += ms;
+    }
+    return total;
+}
+
 namespace {
 
 template <typename T>
@@ -80,7 +109,9 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         T* o = xb[l];
         launch_mg_cheb_first<T>(m, lev, l, 0, bl, blm, a, cmap, dd[l], ncols, cpm, st);
         for (int k = 1; k < npre; ++k) {
+            const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
             launch_mg_cheb_step<T>(m, lev, l, 0, k, bl, blm, a, cmap, o, cmap, dd[l], ncols, cpm, st);
+            if (tp) prof_end(h, st, 5.0 * sizeof(T) * ncols * (double)nodes);
             std::swap(a, o);
         }
         cur[l] = a;
@@ -107,8 +138,10 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         launch_mg_prolong_add<T>(s.mg_n[l + 1], cur[l + 1], a, ncols, st);
         for (int k = 0; k < npost; ++k) {
             const bool final_out = (l == 0 && k == npost - 1);
+            const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
             launch_mg_cheb_step<T>(m, lev, l, 1, k, bl, blm, a, cmap, final_out ? x : o, final_out ? xmap : cmap,
                                    dd[l], ncols, cpm, st);
+            if (tp) prof_end(h, st, 5.0 * sizeof(T) * ncols * (double)nodes);
             if (!final_out) std::swap(a, o);
         }
         cur[l] = a;
@@ -127,15 +160,21 @@ void hgs(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nmem, bool s
     const ColMap vfull = block_map(s, vms);
     for (int d = 0; d <= s.P; ++d) {
         const ColMap rm = level_map(s, d, rms), bm = level_map(s, d, s.blk), vm = level_map(s, d, vms);
-        launch_hgs_rhs<T>(s, op, d, d > 0 ? mask : 0u, 1, 0, R, rm, V, vfull, Bs, bm, nmem, st);
         const int L = s.off[d + 1] - s.off[d];
+        const int Ln = d > 0 ? s.off[d] - s.off[d - 1] : 0;
+        const bool tp = prof_begin(h, SG_PROF_HGS_RHS, st);
+        launch_hgs_rhs<T>(s, op, d, d > 0 ? mask : 0u, 1, 0, R, rm, V, vfull, Bs, bm, nmem, st);
+        if (tp) prof_end(h, st, (double)sizeof(T) * (2 * L + (mask ? Ln : 0)) * s.nodes * s.nt * nmem);
         vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
     }
     if (mask == 0) return;   // mean-based: the backward sweep repeats the forward solves exactly
     for (int d = s.P - 1; d >= 0; --d) {
         const ColMap bm = level_map(s, d, s.blk), vm = level_map(s, d, vms);
-        launch_hgs_rhs<T>(s, op, d, mask, 0, 1, Bs, bm, V, vfull, Bs, bm, nmem, st);
         const int L = s.off[d + 1] - s.off[d];
+        const int Lu = s.off[d + 2] - s.off[d + 1];
+        const bool tp = prof_begin(h, SG_PROF_HGS_RHS, st);
+        launch_hgs_rhs<T>(s, op, d, mask, 0, 1, Bs, bm, V, vfull, Bs, bm, nmem, st);
+        if (tp) prof_end(h, st, (double)sizeof(T) * (2 * L + Lu) * s.nodes * s.nt * nmem);
         vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
     }
 }
@@ -149,7 +188,12 @@ void operator_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStrea
 
 template <typename T>
 void kkt_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st) {
+    const bool tp = prof_begin(h, SG_PROF_KKT_APPLY, st);
     launch_kkt_apply<T>(h.s, h.op<T>(shared), x, y, nvec, st);
+    // algorithmic bytes: read the three fields, write the three results, read the coefficient modes
+    if (tp)
+        prof_end(h, st,
+                 (double)sizeof(T) * nvec * (6.0 * h.s.blk + (shared ? 1.0 / nvec : 1.0) * (h.s.M + 1) * h.s.n * h.s.n));
 }
 
 // Block-diagonal preconditioner (eq. stoch-prec / eq. precon for time).
@@ -278,10 +322,15 @@ struct Krylov {
 };
 
 // Restarted FGMRES on K x = b from the current x for the members with
-// todo[b] != 0, stopping member b when ||b - K x|| <= tol_abs[b] (checked on
-// the true residual at the end of each cycle).  Returns iterations done.
-int fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol_abs, std::vector<int>& todo,
-           bool fp32, int max_iter, std::vector<double>& res_out, std::vector<int>& member_iters, int verbose) {
+// todo[b] != 0.  Member b stops when ||b - K x|| <= tol_abs[b] (true residual,
+// checked at the start of each cycle) or when its own iteration count reaches
+// max_iter; with max_cycles > 0 at most that many cycles run (the inner
+// solves of iterative refinement run one cycle and stop on the Arnoldi
+// estimate).  All stopping decisions are per member, so a member's arithmetic
+// never depends on the other members of the batch.
+void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol_abs, std::vector<int>& todo,
+            bool fp32, int max_iter, int max_cycles, std::vector<double>& res_out, std::vector<int>& member_iters,
+            int verbose) {
     Handle& h = K.h;
     const int B = K.B, m = K.m;
     const int64_t N = K.N;
@@ -289,27 +338,28 @@ int fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol
     double* r = h.ws.get_t<double>("kr", (size_t)B * N);
     std::vector<double> nr2, resid;
     std::vector<int> jend(B, 0), active(B, 0);
-    int iters = 0;
     res_out.assign(B, 0.0);
-    while (true) {
-        K.residual(b, x, r, fp32, nr2);
+    int* pinned_i = reinterpret_cast<int*>(h.h_pinned + 2048);   // upload staging (after a stream sync)
+    for (int cycle = 0; max_cycles <= 0 || cycle < max_cycles; ++cycle) {
+        K.residual(b, x, r, fp32, nr2);       // synchronises the stream
         bool any = false;
         for (int q = 0; q < B; ++q) {
             res_out[q] = std::sqrt(nr2[q]);
-            if (todo[q] && res_out[q] <= tol_abs[q]) todo[q] = 0;
+            if (todo[q] && (res_out[q] <= tol_abs[q] || member_iters[q] >= max_iter)) todo[q] = 0;
             any = any || todo[q];
         }
         if (verbose)
             for (int q = 0; q < B; ++q)
-                std::fprintf(stderr, "[sg] member %d iters %d true residual %.3e (tol %.3e)\n", q, iters, res_out[q],
-                             tol_abs[q]);
-        if (!any || iters >= max_iter) break;
+                std::fprintf(stderr, "[sg] member %d iters %d true residual %.3e (tol %.3e)%s\n", q, member_iters[q],
+                             res_out[q], tol_abs[q], fp32 ? " [fp32 inner]" : "");
+        if (!any) break;
         // cycle start: g = (beta, 0, ...), V_0 = r / beta
         for (int q = 0; q < B; ++q) {
             active[q] = todo[q];
             jend[q] = 0;
+            pinned_i[q] = active[q];
         }
-        SG_HIP(hipMemcpyAsync(K.kd.active, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+        SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
         launch_cycle_start(K.kd, m, K.kd.nrm, B, st);    // kd.nrm holds ||r||^2 from residual()
         launch_copy_scale_rows(r, K.Vi(0), K.kd.nrm, N, B, N, st);
         for (int j = 0; j < m; ++j) {
@@ -317,7 +367,9 @@ int fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol
             K.apply_op_z(j);
             const int nv = j + 1;
             // CGS2: h1 = V^T w; w1 = w - V h1; h2 = V^T w1; w2 = w1 - V h2
+            const bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
             launch_multidot(K.V, (int64_t)B * N, nv, K.w, N, B, N, K.partial, K.nblk, st);
+            if (tp) prof_end(h, st, 8.0 * (nv + 1) * (double)B * N);
             launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h1, m + 1, 0, st);
             launch_cgs_update_dot(K.V, (int64_t)B * N, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
             launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h2, m + 1, 0, st);
@@ -326,30 +378,31 @@ int fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol
             launch_reduce_partials(K.partial, K.nblk, 1, B, K.kd.nrm, 1, 0, st);
             launch_arnoldi_finish(K.kd, m, j, B, st);
             launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
-            K.readback(K.kd.resid, resid);
-            ++iters;
-            bool still = false;
-            bool changed = false;
+            K.readback(K.kd.resid, resid);    // synchronises the stream
+            bool still = false, changed = false;
             for (int q = 0; q < B; ++q) {
                 if (!active[q]) continue;
                 jend[q] = j + 1;
                 ++member_iters[q];
-                if (resid[q] <= tol_abs[q]) {
+                if (resid[q] <= tol_abs[q] || member_iters[q] >= max_iter) {
                     active[q] = 0;
                     changed = true;
                 } else {
                     still = true;
                 }
             }
-            if (!still || iters >= max_iter) break;
-            if (changed)
-                SG_HIP(hipMemcpyAsync(K.kd.active, active.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+            if (!still) break;
+            if (changed) {
+                for (int q = 0; q < B; ++q) pinned_i[q] = active[q];
+                SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
+            }
         }
-        SG_HIP(hipMemcpyAsync(K.d_jend, jend.data(), sizeof(int) * B, hipMemcpyHostToDevice, st));
+        for (int q = 0; q < B; ++q) pinned_i[B + q] = jend[q];
+        SG_HIP(hipMemcpyAsync(K.d_jend, pinned_i + B, sizeof(int) * B, hipMemcpyHostToDevice, st));
         launch_back_solve(K.kd, m, K.d_jend, B, st);
         launch_multi_axpy(K.Z, K.z32 ? 1 : 0, (int64_t)B * N, m, K.d_jend, K.kd.y, m, x, N, B, N, st);
+        SG_HIP(hipStreamSynchronize(st));     // the staging area is reused next cycle
     }
-    return iters;
 }
 
 }  // namespace
@@ -367,29 +420,29 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
     SG_HIP(hipMemsetAsync(x_dev, 0, sizeof(double) * B * N, st));
 
     const bool fp32 = h.opt.precision == SG_PREC_FP32_REFINE;
+    h.prof.kind = h.opt.profile;
+    h.prof.reset();
     Krylov K(h, fp32);
     std::vector<double> bn2;
     K.norms2(b, bn2);
     std::vector<double> tol(B), res(B, 0.0);
     std::vector<int> todo(B, 1);
     for (int q = 0; q < B; ++q) tol[q] = h.opt.rtol * std::sqrt(bn2[q]);
-    int iters = 0;
     std::vector<int> member_iters(B, 0), member_outer(B, 0);
     if (!fp32) {
-        iters = fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, res, member_iters, h.opt.verbose);
+        fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, 0, res, member_iters, h.opt.verbose);
     } else {
-        // FP64 iterative refinement: r = b - K64 x; inner FGMRES with the FP32
-        // operator and preconditioner on K d = r to inner_rtol ||r||; x += d.
-        // A member whose refinement step fails to halve its residual continues
-        // with FP64 inner solves.  Each member's arithmetic depends only on its
-        // own data (inactive members are masked), so batching never changes a
-        // member's result.
+        // FP64 iterative refinement: r = b - K64 x (FP64); one inner FGMRES
+        // cycle with the FP32 operator and preconditioner (FP64 Arnoldi) on
+        // K d = r, stopping on its estimate at inner_rtol ||r||; x += d.  A
+        // member whose step fails to halve its residual continues with FP64
+        // inner cycles.  Every decision is per member (batch invariant).
         double* r = h.ws.get_t<double>("sr", (size_t)B * N);
         double* d = h.ws.get_t<double>("sd", (size_t)B * N);
         std::vector<double> nr2, prev(B, INFINITY);
         std::vector<int> fallback(B, 0);
         std::unique_ptr<Krylov> K64;
-        while (iters < h.opt.max_iter) {
+        while (true) {
             K.residual(b, x_dev, r, false, nr2);
             std::vector<int> todo32(B, 0), todo64(B, 0);
             std::vector<double> tol_in(B, 0.0);
@@ -412,22 +465,18 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
             if (!any32 && !any64) break;
             SG_HIP(hipMemsetAsync(d, 0, sizeof(double) * B * N, st));
             std::vector<double> rin;
-            int done = 0;
-            if (any32) done = std::max(done, fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter - iters, rin,
-                                                    member_iters, h.opt.verbose));
+            if (any32) fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
             if (any64) {
                 if (!K64) K64.reset(new Krylov(h, false));
-                done = std::max(done, fgmres(*K64, r, d, tol_in, todo64, false, h.opt.max_iter - iters, rin,
-                                             member_iters, h.opt.verbose));
+                fgmres(*K64, r, d, tol_in, todo64, false, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
             }
-            iters += std::max(done, 1);
             launch_axpby(1.0, d, 1.0, x_dev, (int64_t)B * N, st);
         }
-        K.residual(b, x_dev, r, false, nr2);
-        for (int q = 0; q < B; ++q) res[q] = std::sqrt(nr2[q]);
     }
     SG_HIP(hipStreamSynchronize(st));
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const double pms = prof_collect_ms(h);
+    h.prof.kind = SG_PROF_NONE;     // only sg_solve is profiled
     bool all = true;
     for (int q = 0; q < B; ++q) {
         const double bn = std::sqrt(bn2[q]);
@@ -444,6 +493,9 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
             info[q].t_solve_ms = ms;
             info[q].latency_ms = ms;
             info[q].bytes_moved = 0.0;
+            info[q].prof_ms = pms;
+            info[q].prof_bytes = h.prof.bytes;
+            info[q].prof_launches = (int32_t)h.prof.used;
         }
     }
     return all ? SG_OK : SG_NOT_CONVERGED;

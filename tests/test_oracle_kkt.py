@@ -172,3 +172,15 @@ def test_moments():
     mean, var = kkt.moments(Y)
     assert np.array_equal(mean, Y[0])
     assert np.all(var >= 0) and np.max(var) > 0
+
+
+@pytest.mark.parametrize("nt", [1, 4])
+def test_matricized_kkt_apply_equals_explicit(nt):
+    if nt == 1:
+        sg = _steady(n=8, M=3, P=2, gamma=0.4)
+    else:
+        sg = _time_problem(n=8, M=2, P=2, nt=nt, gamma=0.4)
+    K = kkt.kkt_matrix(sg)
+    x = sg_inputs.random_block(K.shape[0], 3)
+    ref = K @ x
+    assert np.max(np.abs(kkt.kkt_apply_matricized(sg, x) - ref)) < 1e-13 * np.max(np.abs(ref))
