@@ -12,6 +12,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsgkkt.so")
+# experiments only: extra compiler flags and an alternative output path
+EXTRA = os.environ.get("SG_EXTRA_FLAGS", "").split()
+OUT = os.environ.get("SG_LIB_OUT", LIB)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -34,8 +37,8 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     """Compile every source into LIB (always recompiles).  Returns the path."""
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *sources(), "-o", tmp]
+    tmp = OUT + ".tmp"
+    cmd = [HIPCC, *FLAGS, *EXTRA, *sources(), "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     proc = subprocess.run(cmd, capture_output=True, text=True)
@@ -46,8 +49,8 @@ def build(verbose: bool = False) -> str:
     msgs = [ln for ln in (proc.stdout + proc.stderr).splitlines() if ln.strip() and noise not in ln]
     if msgs and verbose:
         sys.stderr.write("\n".join(msgs) + "\n")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, OUT)
+    return OUT
 
 
 if __name__ == "__main__":

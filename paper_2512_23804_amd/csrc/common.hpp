@@ -111,6 +111,15 @@ struct OpDev {                   // device pointers describing the operator of a
     int mem_shared;              // 1 = all vectors use member 0
 };
 
+// Element-sweep kernels (sweep.hip); return false when the shape needs the
+// generic kernels (more than 8 random variables).
+template <typename T>
+bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
+template <typename T>
+bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
+                        const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
+                        hipStream_t st);
+
 // SG apply family.  `modes_mask` selects modes 1..M (bit k-1); mode 0 (mean,
 // constant coefficient) is applied when with_mean != 0.
 template <typename T>

@@ -878,6 +878,7 @@ dim3 tile_grid(int n, int nchunks, int64_t slices) {
 // ---------------------------------------------------------------------------
 template <typename T>
 void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+    if (launch_sgx_apply<T>(s, op, x, y, nvec, st)) return;
     dim3 g = tile_grid(s.n, (s.nxi + kJChunk - 1) / kJChunk, (int64_t)nvec * s.nt);
     hipLaunchKernelGGL(k_sg_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, x, y);
     SG_HIP(hipGetLastError());
@@ -894,6 +895,8 @@ template <typename T>
 void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
                     const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
                     hipStream_t st) {
+    if (launch_sgx_hgs_rhs<T>(s, op, d, mask, use_lower, use_upper, base, bmap, V, vmap, out, omap, nmembers, st))
+        return;
     const int L = s.off[d + 1] - s.off[d];
     dim3 g = tile_grid(s.n, (L + kJChunk - 1) / kJChunk, (int64_t)nmembers * s.nt);
     hipLaunchKernelGGL(k_hgs_rhs<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, s.off[d], L, mask,

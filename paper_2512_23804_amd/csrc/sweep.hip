@@ -1,0 +1,347 @@
+// Element-sweep kernels for the stochastic-Galerkin operator on gfx950.
+//
+// The SG operator Y_j = sum_k K_k W_{k,j} (W_{0,j} = X_j, W_{k,j} =
+// g- X_{j-e_k} + g+ X_{j+e_k}) is evaluated element by element:
+//   K_k = sum_e c_{k,e} K_ref,  so  (sum_k K_k W_k)|_e = K_ref (sum_k c_{k,e} W_k|_e),
+// i.e. the chaos neighbours are combined at the four corners of each element
+// with that element's coefficients, and one reference-element stiffness
+// (1/6)[4 -1 -2 -1; ...] is applied per element and output column.  For local
+// corner a with opposite corner o and corner sum s this is (5 v_a - v_o - s)/6.
+//
+// Work mapping (64-wide wavefronts): a wavefront owns one output chaos column
+// j; its two 32-lane halves each walk a strip of R node rows of a 30-column
+// x-tile.  Lane l holds node column X = 30*tx + l - 1 (lanes 0 and 31 are
+// halos), loads each input value once per row, gets the x+1 neighbour by a
+// lane shuffle and keeps the previous row in registers, so every input value
+// is read about once per output column.  The node value is the sum of the
+// corner contributions of its four elements: two from its own lane (this and
+// the previous element row) and two from the lane to the left.
+// Blocks (4 wavefronts = 4 consecutive output columns of one spatial tile) are
+// numbered so that each XCD receives a contiguous range of tiles with all
+// their chaos columns: the neighbour columns a tile reads stay in that XCD's L2.
+#include "common.hpp"
+
+namespace sg {
+
+namespace {
+
+constexpr int GW = 32;          // lanes per strip group
+constexpr int GOUT = GW - 2;    // output node columns per group
+constexpr int KMAX = 8;         // modes handled by the sweep kernels
+
+__device__ __forceinline__ int xcd_swizzle(int bid, int nb_padded) {
+    const int per = nb_padded >> 3;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+template <typename T>
+__device__ __forceinline__ T ldn(const T* __restrict__ col, int n, int X, int Y) {
+    return (X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1) ? col[(int64_t)Y * (n + 1) + X] : T(0);
+}
+
+template <typename T>
+__device__ __forceinline__ T shdn(T v) {
+    return __shfl_down(v, 1, GW);
+}
+template <typename T>
+__device__ __forceinline__ T shup(T v) {
+    return __shfl_up(v, 1, GW);
+}
+
+// Reference-element stiffness on a corner vector: k_a = (5 v_a - v_opp - s)/6.
+template <typename T>
+__device__ __forceinline__ void kref(T v0, T v1, T v2, T v3, T& k0, T& k1, T& k2, T& k3) {
+    const T s = (v0 + v1) + (v2 + v3);
+    const T sixth = T(1.0 / 6.0);
+    k0 = (T(5) * v0 - v2 - s) * sixth;
+    k1 = (T(5) * v1 - v3 - s) * sixth;
+    k2 = (T(5) * v2 - v0 - s) * sixth;
+    k3 = (T(5) * v3 - v1 - s) * sixth;
+}
+
+struct SweepGeom {
+    int tiles_x, tiles_y, nchunks, nb;
+};
+
+#ifndef SG_SWEEP_ROWS
+#define SG_SWEEP_ROWS 4
+#endif
+#ifndef SG_SWEEP_WAVES
+#define SG_SWEEP_WAVES 4
+#endif
+constexpr int RS = SG_SWEEP_ROWS;   // node rows per strip (output rows per 32-lane group)
+
+// Per-lane strip geometry: node rows y0-1 .. y0+RS (RS+2 rows) and element
+// rows y0-1 .. y0+RS-1 (RS+1 rows) of node column X.  Offsets are clamped into
+// the grid so that every load is in bounds; the masks zero what lies on the
+// Dirichlet ring or outside the grid.
+struct Strip {
+    int n, xc, xe, y0;
+    uint32_t nmask, emask;
+    __device__ __forceinline__ void init(int n_, int X, int y0_) {
+        n = n_;
+        y0 = y0_;
+        xc = min(max(X, 0), n);
+        xe = min(max(X, 0), n - 1);
+        const bool xin = X >= 1 && X <= n - 1;
+        const bool xev = X >= 0 && X <= n - 1;
+        nmask = 0;
+        emask = 0;
+#pragma unroll
+        for (int r = 0; r < RS + 2; ++r) {
+            const int Y = y0 - 1 + r;
+            if (xin && Y >= 1 && Y <= n - 1) nmask |= 1u << r;
+        }
+#pragma unroll
+        for (int r = 0; r < RS + 1; ++r) {
+            const int ey = y0 - 1 + r;
+            if (xev && ey >= 0 && ey <= n - 1) emask |= 1u << r;
+        }
+    }
+    __device__ __forceinline__ int noff(int r) const { return min(max(y0 - 1 + r, 0), n) * (n + 1) + xc; }
+    __device__ __forceinline__ int eoff(int r) const { return min(max(y0 - 1 + r, 0), n - 1) * n + xe; }
+};
+
+// v[r] += c_r * (corner values of element row r) for one input column stream
+// (vals = node values of the column at the RS+2 strip rows, already scaled).
+template <typename T>
+__device__ __forceinline__ void corner_accumulate(T (&v)[RS + 1][4], const T (&vals)[RS + 2], const T (&c)[RS + 1]) {
+    T prev = vals[0];
+    T prevR = shdn(prev);
+#pragma unroll
+    for (int r = 0; r < RS + 1; ++r) {
+        const T top = vals[r + 1];
+        const T topR = shdn(top);
+        v[r][0] += c[r] * prev;
+        v[r][1] += c[r] * prevR;
+        v[r][2] += c[r] * topR;
+        v[r][3] += c[r] * top;
+        prev = top;
+        prevR = topR;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_col(T (&vals)[RS + 2], const T* __restrict__ col, const Strip& st, T g,
+                                         bool accumulate) {
+#pragma unroll
+    for (int r = 0; r < RS + 2; ++r) {
+        T x = col[st.noff(r)];
+        x = ((st.nmask >> r) & 1u) ? x : T(0);
+        vals[r] = accumulate ? vals[r] + g * x : g * x;
+    }
+}
+
+// Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
+// field F at output column j: c0 X_j (mean, if with_mean) plus, for every mode
+// k in mask, c_{k,e} (g- F_{j-e_k} [lower] + g+ F_{j+e_k} [upper]).
+// One term of the SG sum at output column j: mean (k = -1: c0 X_j) or mode
+// k+1 (c_{k+1,e} (g- F_{j-e_k} + g+ F_{j+e_k}), restricted to lower/upper).
+template <typename T>
+struct Term {
+    int ia, ib;
+    T ga, gb;
+    int k;
+};
+
+template <typename T>
+__device__ __forceinline__ bool term_at(int k, int j, int M, const int32_t* __restrict__ nidx,
+                                        const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
+                                        Term<T>& t) {
+    t.k = k;
+    if (k < 0) {
+        t.ia = j;
+        t.ib = -1;
+        t.ga = T(1);
+        t.gb = T(0);
+        return true;
+    }
+    if (!((mask >> k) & 1u)) return false;
+    const int base = (j * M + k) * 2;
+    t.ia = lower ? nidx[base] : -1;
+    t.ib = upper ? nidx[base + 1] : -1;
+    t.ga = T(nval[base]);
+    t.gb = T(nval[base + 1]);
+    return t.ia >= 0 || t.ib >= 0;
+}
+
+template <typename T>
+__device__ __forceinline__ int next_term(int k, int j, int M, const int32_t* __restrict__ nidx,
+                                         const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
+                                         Term<T>& t) {
+    for (; k < M; ++k)
+        if (term_at(k, j, M, nidx, nval, mask, lower, upper, t)) return k;
+    return M;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_term(T (&vals)[RS + 2], const Term<T>& t, const T* __restrict__ F, int64_t nodes,
+                                          const Strip& st) {
+    if (t.ia >= 0) load_col(vals, F + (int64_t)t.ia * nodes, st, t.ga, false);
+    if (t.ib >= 0) load_col(vals, F + (int64_t)t.ib * nodes, st, t.gb, t.ia >= 0);
+}
+
+// Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
+// field F at output column j.  The loads of the next term are issued before
+// the current term is accumulated (two terms in flight per wavefront).
+template <typename T>
+__device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
+                                         int j, int M, const int32_t* __restrict__ nidx,
+                                         const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
+                                         bool with_mean, T c0, const T* __restrict__ coef, int64_t cplane) {
+    T vals[RS + 2], nvals[RS + 2];
+    T c[RS + 1];
+    Term<T> cur, nxt;
+    int k = next_term(with_mean ? -1 : 0, j, M, nidx, nval, mask, lower, upper, cur);
+    if (k >= M) return;
+    load_term(vals, cur, F, nodes, st);
+#pragma unroll 1
+    while (true) {
+        const int kn = next_term(k + 1, j, M, nidx, nval, mask, lower, upper, nxt);
+        const bool more = kn < M;
+        if (more) load_term(nvals, nxt, F, nodes, st);
+        const T* ck = coef + (int64_t)(k + 1) * cplane;
+#pragma unroll
+        for (int r = 0; r < RS + 1; ++r) {
+            const T cv = k < 0 ? c0 : ck[st.eoff(r)];
+            c[r] = ((st.emask >> r) & 1u) ? cv : T(0);
+        }
+        corner_accumulate(v, vals, c);
+        if (!more) break;
+#pragma unroll
+        for (int r = 0; r < RS + 2; ++r) vals[r] = nvals[r];
+        cur = nxt;
+        k = kn;
+    }
+}
+
+// KIND 0: Y = A X (all modes, mean included) for nt*nvec slices.
+// KIND 1: hGS right-hand side of degree level d:
+//         out_j = base_j - off_scale * sum_{k in mask} K_k (g- V_{j-e_k} [lower] + g+ V_{j+e_k} [upper]).
+template <typename T, int KIND>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_SWEEP_WAVES))) void k_sgx(int n, int M, int nxi, int nt, int64_t nodes, OpDev op, SweepGeom g,
+                                             const T* __restrict__ x, T* __restrict__ y, int j0lvl, int L,
+                                             uint32_t mask, int lower, int upper, const T* __restrict__ base,
+                                             ColMap bmap, ColMap vmap, ColMap omap) {
+    const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (lb >= g.nb) return;
+    const int chunk = lb % g.nchunks;
+    const int rest = lb / g.nchunks;
+    const int tiles = g.tiles_x * g.tiles_y;
+    const int tile = rest % tiles;
+    const int slice = rest / tiles;
+    const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
+    // wavefront index is uniform: keep it (and everything derived from it) in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = chunk * 4 + wave;                  // output column index (in the level for KIND 1)
+    const int ncols = KIND == 0 ? nxi : L;
+    if (l >= ncols) return;                          // uniform per wavefront; no block barriers below
+    const int j = KIND == 0 ? l : j0lvl + l;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (GW - 1);
+    const int grp = lane / GW;
+    const int X = tx * GOUT + gl - 1;
+    const int y0 = (ty * 2 + grp) * RS;
+    const int mem_i = slice / nt;
+    const int t = slice % nt;
+    const int mem = op.mem_shared ? 0 : mem_i;
+    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const int64_t cplane = (int64_t)n * n;
+    const T* F = KIND == 0 ? x + (int64_t)slice * nxi * nodes
+                           : x + (int64_t)mem_i * vmap.mstride + (int64_t)t * vmap.tstride;
+    Strip st;
+    st.init(n, X, y0);
+    T v[RS + 1][4];
+#pragma unroll
+    for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
+    sg_strip(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, KIND == 0 ? 0xffffffffu : mask,
+             KIND == 0 ? true : lower != 0, KIND == 0 ? true : upper != 0, KIND == 0, T(op.mem[mem].c0), coef,
+             cplane);
+    T* out;
+    const T* bas = nullptr;
+    T scale = T(1);
+    if (KIND == 0) {
+        out = y + (int64_t)slice * nxi * nodes + (int64_t)j * nodes;
+    } else {
+        const int c = slice * L + l;
+        out = y + omap.off(c);
+        bas = base + bmap.off(c);
+        scale = T(op.mem[mem].off_scale);
+    }
+    const bool xout = gl >= 1 && gl <= GOUT && X <= n;
+    T k2p, k3p;
+    {
+        T k0, k1;
+        kref(v[0][0], v[0][1], v[0][2], v[0][3], k0, k1, k2p, k3p);
+    }
+#pragma unroll
+    for (int r = 1; r < RS + 1; ++r) {
+        T k0, k1, k2, k3;
+        kref(v[r][0], v[r][1], v[r][2], v[r][3], k0, k1, k2, k3);
+        const T A = k0 + k3p;
+        const T Bl = shup(k1 + k2p);
+        const int Y = y0 - 1 + r;                 // node row of this output
+        if (xout && Y <= n) {
+            const bool inter = (st.nmask >> r) & 1u;    // node (X, Y) is interior (strip row r)
+            const int64_t q = (int64_t)Y * (n + 1) + X;
+            T val = T(0);
+            if (KIND == 0) {
+                if (inter) val = A + Bl;
+            } else {
+                if (inter) val = bas[q] - scale * (A + Bl);
+            }
+            out[q] = val;
+        }
+        k2p = k2;
+        k3p = k3;
+    }
+}
+
+SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
+    SweepGeom g;
+    g.tiles_x = (n + 1 + GOUT - 1) / GOUT;
+    g.tiles_y = (n + 1 + 2 * rows - 1) / (2 * rows);
+    g.nchunks = (ncols + 3) / 4;
+    const int64_t nb = slices * g.tiles_x * g.tiles_y * g.nchunks;
+    if (nb > (int64_t)1 << 30) throw Error(SG_ERR_INVALID, "sweep launch grid too large");
+    g.nb = (int)nb;
+    return g;
+}
+
+}  // namespace
+
+// Returns false when the sweep kernels do not cover the shape (M > 8).
+template <typename T>
+bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+    if (s.M > KMAX) return false;
+    ColMap z{};
+    const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, RS);
+    const int grid = (g.nb + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_sgx<T, 0>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, g, x, y, 0,
+                       0, 0u, 1, 1, (const T*)nullptr, z, z, z);
+    SG_HIP(hipGetLastError());
+    return true;
+}
+
+template <typename T>
+bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
+                        const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
+                        hipStream_t st) {
+    if (s.M > KMAX) return false;
+    const int L = s.off[d + 1] - s.off[d];
+    const SweepGeom g = make_geom(s.n, L, (int64_t)nmembers * s.nt, RS);
+    const int grid = (g.nb + 7) / 8 * 8;
+    hipLaunchKernelGGL((k_sgx<T, 1>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, g, V, out,
+                       s.off[d], L, mask, use_lower, use_upper, base, bmap, vmap, omap);
+    SG_HIP(hipGetLastError());
+    return true;
+}
+
+template bool launch_sgx_apply<double>(const Shape&, const OpDev&, const double*, double*, int, hipStream_t);
+template bool launch_sgx_apply<float>(const Shape&, const OpDev&, const float*, float*, int, hipStream_t);
+template bool launch_sgx_hgs_rhs<double>(const Shape&, const OpDev&, int, uint32_t, int, int, const double*, ColMap,
+                                         const double*, ColMap, double*, ColMap, int, hipStream_t);
+template bool launch_sgx_hgs_rhs<float>(const Shape&, const OpDev&, int, uint32_t, int, int, const float*, ColMap,
+                                        const float*, ColMap, float*, ColMap, int, hipStream_t);
+
+}  // namespace sg
