@@ -145,26 +145,21 @@ template <typename T>
 void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap, T* W, ColMap wmap,
                         int ncols, int nvec_members, hipStream_t st);
 
-// Multigrid
-struct MgDev {
-    const LevelDev* lev;          // [member][kMaxLevels]
-    const void* coarse_inv;       // [member][64][64] in T
-    int coarse_direct;            // 1 if the fine grid is the coarsest grid
-};
+// Fused multigrid levels (mg.hip): down = nu pre-smoothing steps from zero +
+// residual + restriction; up = prolongation of the coarse correction + nu
+// post-smoothing steps.  Coarse arrays are contiguous [column][(m/2+1)^2].
 template <typename T>
-void launch_mg_cheb_first(int m, const LevelDev* lev, int lvl, int which, const T* b, ColMap bmap,
-                          T* x, ColMap xmap, T* d, int ncols, int cols_per_member, hipStream_t st);
+void launch_mg_down(int m, const LevelDev* lev, int lvl, int nu, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc,
+                    int ncols, int cpm, hipStream_t st);
 template <typename T>
-void launch_mg_cheb_step(int m, const LevelDev* lev, int lvl, int which, int step, const T* b,
-                         ColMap bmap, const T* xin, ColMap xinmap, T* xout, ColMap xoutmap, T* d,
-                         int ncols, int cols_per_member, hipStream_t st);
+void launch_mg_up(int m, const LevelDev* lev, int lvl, int nu, const T* xin, ColMap xinmap, const T* ec, const T* b,
+                  ColMap bmap, T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st);
+
+// All Chebyshev mass steps in one LDS-tiled kernel; false when steps > 9.
 template <typename T>
-void launch_mg_residual(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, const T* x,
-                        ColMap xmap, T* r, int ncols, int cols_per_member, hipStream_t st);
-template <typename T>
-void launch_mg_restrict(int mc, const T* rf, T* bc, int ncols, hipStream_t st);
-template <typename T>
-void launch_mg_prolong_add(int mc, const T* xc, T* xf, int ncols, hipStream_t st);
+bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, int steps, hipStream_t st);
+
+// Multigrid coarsest level: x = A_c^{-1} b (FP64 MFMA, FP32 plain).
 template <typename T>
 void launch_mg_coarse(const T* ainv, const T* bc, ColMap bmap, T* xc, ColMap xmap, int ncols,
                       int cols_per_member, hipStream_t st);

@@ -352,140 +352,8 @@ __global__ __launch_bounds__(256) void k_mass_scaled(int n, int nxi, int nt, int
 }
 
 // --------------------------------------------------------------------------
-// Multigrid kernels on the m x m grid of one level.  Operator a K + b M_h as a
-// constant 9-point stencil (wc, we, wd); all columns of a launch share a level.
+// Multigrid coarsest level (the smoothing levels are in mg.hip).
 // --------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T op9(const Nine<T>& v, T wc, T we, T wd) {
-    return wc * v.c + we * (v.w + v.e + v.s + v.n) + wd * (v.sw + v.se + v.nw + v.ne);
-}
-
-// x = d = c_r D^{-1} b (first Chebyshev step from a zero guess)
-template <typename T>
-__global__ __launch_bounds__(256) void k_mg_cheb_first(int m, const LevelDev* __restrict__ lev, int lvl, int which,
-                                                       const T* __restrict__ b, ColMap bmap, T* __restrict__ x,
-                                                       ColMap xmap, T* __restrict__ d, int ncols, int cpm) {
-    int ix, iy;
-    tile_coords(m, blockIdx.x, ix, iy);
-    if (ix > m || iy > m) return;
-    const int64_t nodes = (int64_t)(m + 1) * (m + 1);
-    const int64_t p = (int64_t)iy * (m + 1) + ix;
-    const bool interior = ix > 0 && ix < m && iy > 0 && iy < m;
-    const int c0 = blockIdx.y * kJChunk;
-    const int c1 = min(ncols, c0 + kJChunk);
-    for (int c = c0; c < c1; ++c) {
-        const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
-        const T cr = T(which == 0 ? L.pre[0][1] : L.post[0][1]);
-        T v = T(0);
-        if (interior) v = cr * T(L.dinv) * b[bmap.off(c) + p];
-        x[xmap.off(c) + p] = v;
-        d[(int64_t)c * nodes + p] = v;
-    }
-}
-
-// r = b - A xin; d = c_d d + c_r D^{-1} r; xout = xin + d
-template <typename T>
-__global__ __launch_bounds__(256) void k_mg_cheb_step(int m, const LevelDev* __restrict__ lev, int lvl, int which,
-                                                      int step, const T* __restrict__ b, ColMap bmap,
-                                                      const T* __restrict__ xin, ColMap xinmap,
-                                                      T* __restrict__ xout, ColMap xoutmap, T* __restrict__ d,
-                                                      int ncols, int cpm) {
-    int ix, iy;
-    tile_coords(m, blockIdx.x, ix, iy);
-    if (ix > m || iy > m) return;
-    const int64_t nodes = (int64_t)(m + 1) * (m + 1);
-    const int64_t p = (int64_t)iy * (m + 1) + ix;
-    const bool interior = ix > 0 && ix < m && iy > 0 && iy < m;
-    const int c0 = blockIdx.y * kJChunk;
-    const int c1 = min(ncols, c0 + kJChunk);
-    for (int c = c0; c < c1; ++c) {
-        const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
-        const double* cf = which == 0 ? L.pre[step] : L.post[step];
-        T v = T(0);
-        const int64_t qd = (int64_t)c * nodes + p;
-        if (interior) {
-            const T* xc = xin + xinmap.off(c);
-            const T r = b[bmap.off(c) + p] - op9(load9(xc, m, ix, iy), T(L.wc), T(L.we), T(L.wd));
-            const T dn = T(cf[0]) * d[qd] + T(cf[1]) * T(L.dinv) * r;
-            d[qd] = dn;
-            v = xc[p] + dn;
-        }
-        xout[xoutmap.off(c) + p] = v;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_mg_residual(int m, const LevelDev* __restrict__ lev, int lvl,
-                                                     const T* __restrict__ b, ColMap bmap, const T* __restrict__ x,
-                                                     ColMap xmap, T* __restrict__ r, int ncols, int cpm) {
-    int ix, iy;
-    tile_coords(m, blockIdx.x, ix, iy);
-    if (ix > m || iy > m) return;
-    const int64_t nodes = (int64_t)(m + 1) * (m + 1);
-    const int64_t p = (int64_t)iy * (m + 1) + ix;
-    const bool interior = ix > 0 && ix < m && iy > 0 && iy < m;
-    const int c0 = blockIdx.y * kJChunk;
-    const int c1 = min(ncols, c0 + kJChunk);
-    for (int c = c0; c < c1; ++c) {
-        const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
-        T v = T(0);
-        if (interior)
-            v = b[bmap.off(c) + p] - op9(load9(x + xmap.off(c), m, ix, iy), T(L.wc), T(L.we), T(L.wd));
-        r[(int64_t)c * nodes + p] = v;
-    }
-}
-
-// Coarse b(I,J) = sum of fine residual with bilinear weights (R = P^T):
-// 1 at (2I,2J), 1/2 at edge partners, 1/4 at corner partners.
-template <typename T>
-__global__ __launch_bounds__(256) void k_mg_restrict(int mc, const T* __restrict__ rf, T* __restrict__ bc, int ncols) {
-    int ix, iy;
-    tile_coords(mc, blockIdx.x, ix, iy);
-    if (ix > mc || iy > mc) return;
-    const int mf = 2 * mc;
-    const int64_t nf = (int64_t)(mf + 1) * (mf + 1);
-    const int64_t ncn = (int64_t)(mc + 1) * (mc + 1);
-    const int64_t p = (int64_t)iy * (mc + 1) + ix;
-    const bool interior = ix > 0 && ix < mc && iy > 0 && iy < mc;
-    const int c0 = blockIdx.y * kJChunk;
-    const int c1 = min(ncols, c0 + kJChunk);
-    for (int c = c0; c < c1; ++c) {
-        T v = T(0);
-        if (interior) {
-            const T* r = rf + (int64_t)c * nf;
-            const int64_t q = (int64_t)(2 * iy) * (mf + 1) + 2 * ix;
-            const int64_t F = mf + 1;
-            v = r[q] + T(0.5) * (r[q - 1] + r[q + 1] + r[q - F] + r[q + F]) +
-                T(0.25) * (r[q - F - 1] + r[q - F + 1] + r[q + F - 1] + r[q + F + 1]);
-        }
-        bc[(int64_t)c * ncn + p] = v;
-    }
-}
-
-// Fine x += P xc (bilinear interpolation of the coarse correction).
-template <typename T>
-__global__ __launch_bounds__(256) void k_mg_prolong_add(int mc, const T* __restrict__ xc, T* __restrict__ xf, int ncols) {
-    const int mf = 2 * mc;
-    int ix, iy;
-    tile_coords(mf, blockIdx.x, ix, iy);
-    if (ix > mf || iy > mf) return;
-    const int64_t nf = (int64_t)(mf + 1) * (mf + 1);
-    const int64_t ncn = (int64_t)(mc + 1) * (mc + 1);
-    const bool interior = ix > 0 && ix < mf && iy > 0 && iy < mf;
-    if (!interior) return;
-    const int64_t p = (int64_t)iy * (mf + 1) + ix;
-    const int I0 = ix >> 1, J0 = iy >> 1;
-    const int I1 = I0 + (ix & 1), J1 = J0 + (iy & 1);
-    const int C = mc + 1;
-    const int c0 = blockIdx.y * kJChunk;
-    const int c1 = min(ncols, c0 + kJChunk);
-    for (int c = c0; c < c1; ++c) {
-        const T* x = xc + (int64_t)c * ncn;
-        const T v = T(0.25) * (x[J0 * C + I0] + x[J0 * C + I1] + x[J1 * C + I0] + x[J1 * C + I1]);
-        xf[(int64_t)c * nf + p] += v;
-    }
-}
-
 // Coarse solve x = A_c^{-1} b on the 8x8 grid (49 unknowns padded to 64) with
 // FP64 MFMA 16x16x4 tiles: one wavefront computes a 64 x 16 block of
 // x = Ainv (64 x 64) * B (64 x 16 columns of one member).
@@ -907,6 +775,7 @@ void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int u
 template <typename T>
 void launch_mass_cheb(const Shape& s, const OpDev& op, const T* r, T* z, T* bufA, T* bufB, int nvec, int steps,
                       hipStream_t st) {
+    if (launch_mass_cheb_fused<T>(s, op, r, z, nvec, steps, st)) return;
     const int ncols = 2 * s.nt * s.nxi;
     dim3 g = tile_grid(s.n, (ncols + kJChunk - 1) / kJChunk, nvec);
     const int64_t vstride = 3 * s.blk;
@@ -941,45 +810,10 @@ void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap
     SG_HIP(hipGetLastError());
 }
 
-template <typename T>
-void launch_mg_cheb_first(int m, const LevelDev* lev, int lvl, int which, const T* b, ColMap bmap, T* x, ColMap xmap,
-                          T* d, int ncols, int cpm, hipStream_t st) {
-    dim3 g = tile_grid(m, (ncols + kJChunk - 1) / kJChunk, 1);
-    hipLaunchKernelGGL(k_mg_cheb_first<T>, g, dim3(256), 0, st, m, lev, lvl, which, b, bmap, x, xmap, d, ncols, cpm);
-    SG_HIP(hipGetLastError());
-}
 
-template <typename T>
-void launch_mg_cheb_step(int m, const LevelDev* lev, int lvl, int which, int step, const T* b, ColMap bmap,
-                         const T* xin, ColMap xinmap, T* xout, ColMap xoutmap, T* d, int ncols, int cpm,
-                         hipStream_t st) {
-    dim3 g = tile_grid(m, (ncols + kJChunk - 1) / kJChunk, 1);
-    hipLaunchKernelGGL(k_mg_cheb_step<T>, g, dim3(256), 0, st, m, lev, lvl, which, step, b, bmap, xin, xinmap, xout,
-                       xoutmap, d, ncols, cpm);
-    SG_HIP(hipGetLastError());
-}
 
-template <typename T>
-void launch_mg_residual(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, const T* x, ColMap xmap, T* r,
-                        int ncols, int cpm, hipStream_t st) {
-    dim3 g = tile_grid(m, (ncols + kJChunk - 1) / kJChunk, 1);
-    hipLaunchKernelGGL(k_mg_residual<T>, g, dim3(256), 0, st, m, lev, lvl, b, bmap, x, xmap, r, ncols, cpm);
-    SG_HIP(hipGetLastError());
-}
 
-template <typename T>
-void launch_mg_restrict(int mc, const T* rf, T* bc, int ncols, hipStream_t st) {
-    dim3 g = tile_grid(mc, (ncols + kJChunk - 1) / kJChunk, 1);
-    hipLaunchKernelGGL(k_mg_restrict<T>, g, dim3(256), 0, st, mc, rf, bc, ncols);
-    SG_HIP(hipGetLastError());
-}
 
-template <typename T>
-void launch_mg_prolong_add(int mc, const T* xc, T* xf, int ncols, hipStream_t st) {
-    dim3 g = tile_grid(2 * mc, (ncols + kJChunk - 1) / kJChunk, 1);
-    hipLaunchKernelGGL(k_mg_prolong_add<T>, g, dim3(256), 0, st, mc, xc, xf, ncols);
-    SG_HIP(hipGetLastError());
-}
 
 template <>
 void launch_mg_coarse<double>(const double* ainv, const double* bc, ColMap bmap, double* xc, ColMap xmap, int ncols,
@@ -1110,14 +944,6 @@ void launch_back_solve(KrylovDev k, int restart, const int* jend, int nmem, hipS
                                       hipStream_t);                                                         \
     template void launch_mass_scaled<T>(const Shape&, const OpDev&, const T*, ColMap, T*, ColMap, int, int, \
                                         hipStream_t);                                                       \
-    template void launch_mg_cheb_first<T>(int, const LevelDev*, int, int, const T*, ColMap, T*, ColMap, T*, \
-                                          int, int, hipStream_t);                                           \
-    template void launch_mg_cheb_step<T>(int, const LevelDev*, int, int, int, const T*, ColMap, const T*,   \
-                                         ColMap, T*, ColMap, T*, int, int, hipStream_t);                    \
-    template void launch_mg_residual<T>(int, const LevelDev*, int, const T*, ColMap, const T*, ColMap, T*,  \
-                                        int, int, hipStream_t);                                             \
-    template void launch_mg_restrict<T>(int, const T*, T*, int, hipStream_t);                               \
-    template void launch_mg_prolong_add<T>(int, const T*, T*, int, hipStream_t);                            \
     template void launch_zero_ring<T>(T*, int, int64_t, hipStream_t);
 SG_INST(double)
 SG_INST(float)

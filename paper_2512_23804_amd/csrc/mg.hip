@@ -1,0 +1,352 @@
+// Fused geometric-multigrid kernels for A = a1 K + b1 M_h on one grid level.
+//
+// One V-cycle level is two launches instead of one per smoothing step:
+//   down: x = pre-smoothing of b from a zero guess (NU Chebyshev steps),
+//         r = b - A x, b_coarse = P^T r           (b read once, x and b_coarse written)
+//   up:   x' = x + P e_coarse, then NU post-smoothing steps from x'
+// Each workgroup stages a tile of the level plus a halo of NU+1 nodes in LDS
+// and runs all steps there (the halo shrinks by one node per stencil step),
+// so the finest level is read about twice and written about twice per
+// V-cycle.  The smoother is the Chebyshev iteration
+//   r = b - A x;  d = c_d d + c_r D^{-1} r;  x = x + d
+// with per-member, per-level coefficients (c_d = 0 in the first step).
+#include "common.hpp"
+
+namespace sg {
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ T st9(const T* s, int W, int i, T wc, T we, T wd) {
+    return wc * s[i] + we * (s[i - 1] + s[i + 1] + s[i - W] + s[i + W]) +
+           wd * (s[i - W - 1] + s[i - W + 1] + s[i + W - 1] + s[i + W + 1]);
+}
+
+// down: coarse tile of TC x TC coarse nodes starting at (I0, J0).
+// Fine region: origin (2 I0 - 1 - NU, 2 J0 - 1 - NU), width W = 2 TC + 1 + 2 NU.
+template <typename T, int TC, int NU>
+__global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restrict__ lev, int lvl,
+                                                 const T* __restrict__ b, ColMap bmap, T* __restrict__ xo,
+                                                 ColMap xmap, T* __restrict__ bc, int cpm, int tiles_x) {
+    constexpr int W = 2 * TC + 1 + 2 * NU;
+    __shared__ T sb[W * W], sxa[W * W], sxb[W * W], sd[W * W];
+    const int c = blockIdx.y;
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int I0 = tx * TC, J0 = ty * TC;
+    const int FX0 = 2 * I0 - 1 - NU, FY0 = 2 * J0 - 1 - NU;
+    const int mc = m / 2;
+    const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
+    const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
+    const T* bcol = b + bmap.off(c);
+    const int N1 = m + 1;
+    // load b; x_1 = d_1 = c_r D^{-1} b
+    const T cr0 = T(L.pre[0][1]);
+    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+        const int X = FX0 + q % W, Y = FY0 + q / W;
+        const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+        const T bv = inter ? bcol[Y * N1 + X] : T(0);
+        sb[q] = bv;
+        const T x1 = cr0 * dinv * bv;
+        sxa[q] = x1;
+        sd[q] = x1;
+    }
+    __syncthreads();
+    T* cur = sxa;
+    T* nxt = sxb;
+#pragma unroll
+    for (int s = 1; s < NU; ++s) {
+        const T cd = T(L.pre[s][0]), cr = T(L.pre[s][1]);
+        const int lo = s, hi = W - s;
+        for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+            const int i = q % W, j = q / W;
+            if (i < lo || i >= hi || j < lo || j >= hi) continue;
+            const int X = FX0 + i, Y = FY0 + j;
+            const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+            T v = T(0);
+            if (inter) {
+                const T r = sb[q] - st9(cur, W, q, wc, we, wd);
+                const T dn = cd * sd[q] + cr * dinv * r;
+                sd[q] = dn;
+                v = cur[q] + dn;
+            }
+            nxt[q] = v;
+        }
+        __syncthreads();
+        T* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    // residual on [NU, W-NU) into sd (the step direction is no longer needed)
+    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+        const int i = q % W, j = q / W;
+        if (i < NU || i >= W - NU || j < NU || j >= W - NU) continue;
+        const int X = FX0 + i, Y = FY0 + j;
+        const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+        sd[q] = inter ? sb[q] - st9(cur, W, q, wc, we, wd) : T(0);
+    }
+    __syncthreads();
+    // restriction (R = P^T: 1 centre, 1/2 edge partners, 1/4 corner partners)
+    T* bco = bc + (int64_t)c * (mc + 1) * (mc + 1);
+    for (int q = threadIdx.x; q < TC * TC; q += blockDim.x) {
+        const int I = I0 + q % TC, J = J0 + q / TC;
+        if (I > mc || J > mc) continue;
+        T v = T(0);
+        if (I >= 1 && I <= mc - 1 && J >= 1 && J <= mc - 1) {
+            const int i = 2 * I - FX0, j = 2 * J - FY0;
+            const int p = j * W + i;
+            v = sd[p] + T(0.5) * (sd[p - 1] + sd[p + 1] + sd[p - W] + sd[p + W]) +
+                T(0.25) * (sd[p - W - 1] + sd[p - W + 1] + sd[p + W - 1] + sd[p + W + 1]);
+        }
+        bco[J * (mc + 1) + I] = v;
+    }
+    // smoothed x on the owned fine nodes [2 I0, 2 I0 + 2 TC)
+    T* xcol = xo + xmap.off(c);
+    for (int q = threadIdx.x; q < 4 * TC * TC; q += blockDim.x) {
+        const int X = 2 * I0 + q % (2 * TC), Y = 2 * J0 + q / (2 * TC);
+        if (X > m || Y > m) continue;
+        const int i = X - FX0, j = Y - FY0;
+        xcol[Y * N1 + X] = cur[j * W + i];
+    }
+}
+
+// up: fine tile of TF x TF nodes starting at (X0, Y0); region with halo NU.
+template <typename T, int TF, int NU>
+__global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict__ lev, int lvl,
+                                               const T* __restrict__ xin, ColMap xinmap, const T* __restrict__ ec,
+                                               const T* __restrict__ b, ColMap bmap, T* __restrict__ xo, ColMap xomap,
+                                               int cpm, int tiles_x) {
+    constexpr int W = TF + 2 * NU;
+    __shared__ T sb[W * W], sxa[W * W], sxb[W * W], sd[W * W];
+    const int c = blockIdx.y;
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int FX0 = tx * TF - NU, FY0 = ty * TF - NU;
+    const int mc = m / 2;
+    const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
+    const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
+    const int N1 = m + 1, C1 = mc + 1;
+    const T* xcol = xin + xinmap.off(c);
+    const T* bcol = b + bmap.off(c);
+    const T* ecol = ec + (int64_t)c * C1 * C1;
+    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+        const int X = FX0 + q % W, Y = FY0 + q / W;
+        const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+        T xv = T(0), bv = T(0);
+        if (inter) {
+            const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
+            const T e = T(0.25) * (ecol[J0 * C1 + I0] + ecol[J0 * C1 + I1] + ecol[J1 * C1 + I0] + ecol[J1 * C1 + I1]);
+            xv = xcol[Y * N1 + X] + e;
+            bv = bcol[Y * N1 + X];
+        }
+        sxa[q] = xv;
+        sb[q] = bv;
+        sd[q] = T(0);
+    }
+    __syncthreads();
+    T* cur = sxa;
+    T* nxt = sxb;
+#pragma unroll
+    for (int s = 0; s < NU; ++s) {
+        const T cd = T(L.post[s][0]), cr = T(L.post[s][1]);
+        const int lo = s + 1, hi = W - s - 1;
+        for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+            const int i = q % W, j = q / W;
+            if (i < lo || i >= hi || j < lo || j >= hi) continue;
+            const int X = FX0 + i, Y = FY0 + j;
+            const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+            T v = T(0);
+            if (inter) {
+                const T r = sb[q] - st9(cur, W, q, wc, we, wd);
+                const T dn = (s == 0 ? T(0) : cd * sd[q]) + cr * dinv * r;
+                sd[q] = dn;
+                v = cur[q] + dn;
+            }
+            nxt[q] = v;
+        }
+        __syncthreads();
+        T* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+    }
+    T* out = xo + xomap.off(c);
+    for (int q = threadIdx.x; q < TF * TF; q += blockDim.x) {
+        const int X = FX0 + NU + q % TF, Y = FY0 + NU + q / TF;
+        if (X > m || Y > m) continue;
+        out[Y * N1 + X] = cur[(Y - FY0) * W + (X - FX0)];
+    }
+}
+
+// Chebyshev semi-iteration on the mass matrix for the state and control
+// blocks, all steps in LDS (halo = steps - 1 nodes).  Column l of vector v
+// (l < 2 nt n_xi) is r[v*vstride + l*nodes ...]; the last step writes
+// z = x / (s tau D_t) with s = 1 (mean column) or 1+gamma (state), beta (control).
+struct ChebW {
+    float pad;
+    double omega[16];   // omega_{k+1} for k = 1..steps-1
+};
+
+template <typename T, int TF, int H>
+__global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt, int time, int64_t nodes, OpDev op,
+                                                         int64_t vstride, const T* __restrict__ r, T* __restrict__ z,
+                                                         ChebW cw, int tiles_x) {
+    constexpr int W = TF + 2 * H;     // H = steps - 1
+    __shared__ T sb[W * W], sp[W * W], sc[W * W];
+    const int l = blockIdx.y;
+    const int vec = blockIdx.z;
+    const int mem = op.mem_shared ? 0 : vec;
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int FX0 = tx * TF - H, FY0 = ty * TF - H;
+    const int N1 = n + 1;
+    const T h = T(1) / T(n);
+    const T h2_36 = h * h / T(36);
+    const T dinv = T(1) / (T(1.25) * T(4) * h * h / T(9));
+    const T* rc = r + (int64_t)vec * vstride + (int64_t)l * nodes;
+    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+        const int X = FX0 + q % W, Y = FY0 + q / W;
+        const bool inter = X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1;
+        const T bv = inter ? rc[Y * N1 + X] : T(0);
+        sb[q] = bv;
+        sp[q] = T(0);           // x_0
+        sc[q] = dinv * bv;      // x_1 (omega_1 = 1)
+    }
+    __syncthreads();
+    T* prev = sp;
+    T* cur = sc;
+#pragma unroll 1
+    for (int k = 1; k <= H; ++k) {
+        const T om = T(cw.omega[k - 1]);
+        const int lo = k, hi = W - k;
+        // x_{k+1} overwrites x_{k-1} in place (each node reads only its own x_{k-1})
+        for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+            const int i = q % W, j = q / W;
+            if (i < lo || i >= hi || j < lo || j >= hi) continue;
+            const int X = FX0 + i, Y = FY0 + j;
+            const bool inter = X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1;
+            T v = T(0);
+            if (inter) {
+                const T Mx = h2_36 * (T(16) * cur[q] + T(4) * (cur[q - 1] + cur[q + 1] + cur[q - W] + cur[q + W]) +
+                                      (cur[q - W - 1] + cur[q - W + 1] + cur[q + W - 1] + cur[q + W + 1]));
+                v = om * (dinv * (sb[q] - Mx) + cur[q] - prev[q]) + prev[q];
+            }
+            prev[q] = v;
+        }
+        __syncthreads();
+        T* tmp = prev;
+        prev = cur;
+        cur = tmp;
+    }
+    const MemberDev md = op.mem[mem];
+    const int var = l / (nt * nxi);
+    const int t = (l / nxi) % nt;
+    const int j = l % nxi;
+    const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
+    const T sc_ = var == 0 ? (j == 0 ? T(1) : T(md.hg)) : T(md.beta);
+    const T f = T(1) / (sc_ * T(md.tau) * Dt);
+    T* zc = z + (int64_t)vec * vstride + (int64_t)l * nodes;
+    for (int q = threadIdx.x; q < TF * TF; q += blockDim.x) {
+        const int X = FX0 + H + q % TF, Y = FY0 + H + q / TF;
+        if (X > n || Y > n) continue;
+        zc[Y * N1 + X] = f * cur[(Y - FY0) * W + (X - FX0)];
+    }
+}
+
+template <typename T, int H>
+void cheb_h(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, const ChebW& cw, hipStream_t st) {
+    constexpr int TF = 32;
+    const int tx = (s.n + 1 + TF - 1) / TF;
+    const int ncols = 2 * s.nt * s.nxi;
+    if (ncols > 65535 || nvec > 65535) throw Error(SG_ERR_INVALID, "Chebyshev: launch grid too large");
+    dim3 grid(tx * tx, ncols, nvec);
+    hipLaunchKernelGGL((k_mass_cheb_fused<T, TF, H>), grid, dim3(256), 0, st, s.n, s.nxi, s.nt, (int)s.time, s.nodes,
+                       op, 3 * s.blk, r, z, cw, tx);
+}
+
+constexpr int TCD = 16;   // coarse nodes per down tile side
+constexpr int TFU = 32;   // fine nodes per up tile side
+
+template <typename T, int NU>
+void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc, int ncols,
+             int cpm, hipStream_t st) {
+    const int mc = m / 2;
+    const int tx = (mc + 1 + TCD - 1) / TCD;
+    dim3 grid(tx * tx, ncols);
+    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, x, xmap, bc, cpm, tx);
+}
+
+template <typename T, int NU>
+void up_nu(int m, const LevelDev* lev, int lvl, const T* xin, ColMap xinmap, const T* ec, const T* b, ColMap bmap,
+           T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st) {
+    const int tx = (m + 1 + TFU - 1) / TFU;
+    dim3 grid(tx * tx, ncols);
+    hipLaunchKernelGGL((k_mg_up<T, TFU, NU>), grid, dim3(256), 0, st, m, lev, lvl, xin, xinmap, ec, b, bmap, xo,
+                       xomap, cpm, tx);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_mg_down(int m, const LevelDev* lev, int lvl, int nu, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc,
+                    int ncols, int cpm, hipStream_t st) {
+    if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
+    switch (nu) {
+        case 1: down_nu<T, 1>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
+        case 2: down_nu<T, 2>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
+        case 3: down_nu<T, 3>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
+        case 4: down_nu<T, 4>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
+        default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
+    }
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_mg_up(int m, const LevelDev* lev, int lvl, int nu, const T* xin, ColMap xinmap, const T* ec, const T* b,
+                  ColMap bmap, T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st) {
+    if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
+    switch (nu) {
+        case 1: up_nu<T, 1>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 2: up_nu<T, 2>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 3: up_nu<T, 3>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 4: up_nu<T, 4>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
+    }
+    SG_HIP(hipGetLastError());
+}
+
+// Returns false when the step count has no fused kernel (more than 9 steps).
+template <typename T>
+bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, int steps, hipStream_t st) {
+    if (steps < 1 || steps > 9) return false;
+    ChebW cw{};
+    const double rho = 0.8;
+    double omega = 1.0;
+    for (int k = 1; k < steps; ++k) {
+        omega = (k == 1) ? 1.0 / (1.0 - 0.5 * rho * rho) : 1.0 / (1.0 - 0.25 * rho * rho * omega);
+        cw.omega[k - 1] = omega;
+    }
+    switch (steps - 1) {
+        case 0: cheb_h<T, 0>(s, op, r, z, nvec, cw, st); break;
+        case 1: cheb_h<T, 1>(s, op, r, z, nvec, cw, st); break;
+        case 2: cheb_h<T, 2>(s, op, r, z, nvec, cw, st); break;
+        case 3: cheb_h<T, 3>(s, op, r, z, nvec, cw, st); break;
+        case 4: cheb_h<T, 4>(s, op, r, z, nvec, cw, st); break;
+        case 5: cheb_h<T, 5>(s, op, r, z, nvec, cw, st); break;
+        case 6: cheb_h<T, 6>(s, op, r, z, nvec, cw, st); break;
+        case 7: cheb_h<T, 7>(s, op, r, z, nvec, cw, st); break;
+        default: cheb_h<T, 8>(s, op, r, z, nvec, cw, st); break;
+    }
+    SG_HIP(hipGetLastError());
+    return true;
+}
+
+template bool launch_mass_cheb_fused<double>(const Shape&, const OpDev&, const double*, double*, int, int, hipStream_t);
+template bool launch_mass_cheb_fused<float>(const Shape&, const OpDev&, const float*, float*, int, int, hipStream_t);
+
+template void launch_mg_down<double>(int, const LevelDev*, int, int, const double*, ColMap, double*, ColMap, double*,
+                                     int, int, hipStream_t);
+template void launch_mg_down<float>(int, const LevelDev*, int, int, const float*, ColMap, float*, ColMap, float*, int,
+                                    int, hipStream_t);
+template void launch_mg_up<double>(int, const LevelDev*, int, int, const double*, ColMap, const double*,
+                                   const double*, ColMap, double*, ColMap, int, int, hipStream_t);
+template void launch_mg_up<float>(int, const LevelDev*, int, int, const float*, ColMap, const float*, const float*,
+                                  ColMap, float*, ColMap, int, int, hipStream_t);
+
+}  // namespace sg

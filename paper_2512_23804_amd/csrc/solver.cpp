@@ -85,66 +85,41 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         launch_mg_coarse<T>(h.ainv<T>(), b, bmap, x, xmap, ncols, cpm, st);
         return;
     }
-    // scratch per level: xa, xb, d, r, (levels >= 1: b)
-    std::vector<T*> xa(nl), xb(nl), dd(nl), rr(nl), bb(nl);
+    // per level: xs (after pre-smoothing), bs (restricted right-hand side, l >= 1),
+    // xf (after post-smoothing, l >= 1; level 0 writes to x)
+    std::vector<T*> xs(nl), bs(nl), xf(nl);
+    std::vector<ColMap> cm(nl);
     for (int l = 0; l < nl; ++l) {
         const int m = s.mg_n[l];
-        const size_t cnt = (size_t)ncols * (m + 1) * (m + 1);
+        const int64_t nodes = (int64_t)(m + 1) * (m + 1);
+        const size_t cnt = (size_t)ncols * nodes;
         const std::string tag = std::string("mg") + tname<T>() + "_" + std::to_string(l);
-        xa[l] = h.ws.get_t<T>(tag + "_xa", cnt);
-        xb[l] = h.ws.get_t<T>(tag + "_xb", cnt);
-        dd[l] = h.ws.get_t<T>(tag + "_d", cnt);
-        if (l < nl - 1) rr[l] = h.ws.get_t<T>(tag + "_r", cnt);
-        if (l > 0) bb[l] = h.ws.get_t<T>(tag + "_b", cnt);
+        cm[l] = contiguous_cols(ncols, nodes);
+        xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
+        if (l > 0) {
+            bs[l] = h.ws.get_t<T>(tag + "_bs", cnt);
+            xf[l] = h.ws.get_t<T>(tag + "_xf", cnt);
+        }
     }
-    // downward: pre-smoothing, residual, restriction
-    std::vector<T*> cur(nl);
     for (int l = 0; l < nl - 1; ++l) {
         const int m = s.mg_n[l];
-        const int64_t nodes = (int64_t)(m + 1) * (m + 1);
-        const ColMap cmap = contiguous_cols(ncols, nodes);
-        const T* bl = l == 0 ? b : bb[l];
-        const ColMap blm = l == 0 ? bmap : cmap;
-        T* a = xa[l];
-        T* o = xb[l];
-        launch_mg_cheb_first<T>(m, lev, l, 0, bl, blm, a, cmap, dd[l], ncols, cpm, st);
-        for (int k = 1; k < npre; ++k) {
-            const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
-            launch_mg_cheb_step<T>(m, lev, l, 0, k, bl, blm, a, cmap, o, cmap, dd[l], ncols, cpm, st);
-            if (tp) prof_end(h, st, 5.0 * sizeof(T) * ncols * (double)nodes);
-            std::swap(a, o);
-        }
-        cur[l] = a;
-        launch_mg_residual<T>(m, lev, l, bl, blm, a, cmap, rr[l], ncols, cpm, st);
-        launch_mg_restrict<T>(s.mg_n[l + 1], rr[l], bb[l + 1], ncols, st);
+        const double nodes = (double)(m + 1) * (m + 1);
+        const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
+        launch_mg_down<T>(m, lev, l, npre, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], xs[l], cm[l], bs[l + 1], ncols,
+                          cpm, st);
+        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);   // read b, write x, write b_coarse
     }
-    // coarsest
-    {
-        const int l = nl - 1;
-        const int m = s.mg_n[l];
-        const ColMap cmap = contiguous_cols(ncols, (int64_t)(m + 1) * (m + 1));
-        launch_mg_coarse<T>(h.ainv<T>(), bb[l], cmap, xa[l], cmap, ncols, cpm, st);
-        cur[l] = xa[l];
-    }
-    // upward: prolongation, post-smoothing
+    launch_mg_coarse<T>(h.ainv<T>(), bs[nl - 1], cm[nl - 1], xs[nl - 1], cm[nl - 1], ncols, cpm, st);
+    const T* e = xs[nl - 1];
     for (int l = nl - 2; l >= 0; --l) {
         const int m = s.mg_n[l];
-        const int64_t nodes = (int64_t)(m + 1) * (m + 1);
-        const ColMap cmap = contiguous_cols(ncols, nodes);
-        const T* bl = l == 0 ? b : bb[l];
-        const ColMap blm = l == 0 ? bmap : cmap;
-        T* a = cur[l];
-        T* o = (a == xa[l]) ? xb[l] : xa[l];
-        launch_mg_prolong_add<T>(s.mg_n[l + 1], cur[l + 1], a, ncols, st);
-        for (int k = 0; k < npost; ++k) {
-            const bool final_out = (l == 0 && k == npost - 1);
-            const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
-            launch_mg_cheb_step<T>(m, lev, l, 1, k, bl, blm, a, cmap, final_out ? x : o, final_out ? xmap : cmap,
-                                   dd[l], ncols, cpm, st);
-            if (tp) prof_end(h, st, 5.0 * sizeof(T) * ncols * (double)nodes);
-            if (!final_out) std::swap(a, o);
-        }
-        cur[l] = a;
+        const double nodes = (double)(m + 1) * (m + 1);
+        T* out = l == 0 ? x : xf[l];
+        const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
+        launch_mg_up<T>(m, lev, l, npost, xs[l], cm[l], e, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], out,
+                        l == 0 ? xmap : cm[l], ncols, cpm, st);
+        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 3.25);  // read x, b, e_coarse; write x
+        e = out;
     }
 }
 
