@@ -10,8 +10,14 @@ struct sg_handle {
 };
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace sg {
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace sg
+
+namespace {
 
 int fail(int code, const std::string& msg) {
     g_last_error = msg;

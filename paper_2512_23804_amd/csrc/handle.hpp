@@ -121,6 +121,9 @@ struct Handle {
     ~Handle();
 };
 
+// abi.cpp: message returned by sg_last_error() on this thread
+void set_last_error(const std::string& msg);
+
 // setup.cpp
 void default_options(sg_options* o);
 void validate(const sg_problem* probs, int count, const sg_options* opt);   // throws Error

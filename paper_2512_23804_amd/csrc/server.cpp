@@ -212,17 +212,14 @@ void sg_server::worker_loop(int) {
     (void)hipStreamDestroy(st);
 }
 
-namespace {
-thread_local std::string g_srv_error;
-}
-
 extern "C" {
 
 int sg_server_create(size_t hbm_budget_bytes, int32_t max_slots, sg_server** out) {
     try {
-        if (!out) return SG_ERR_INVALID;
+        sg::set_last_error("");
+        if (!out) throw sg::Error(SG_ERR_INVALID, "out is NULL");
         *out = nullptr;
-        if (max_slots < 1 || max_slots > 4096) return SG_ERR_INVALID;
+        if (max_slots < 1 || max_slots > 4096) throw sg::Error(SG_ERR_INVALID, "max_slots must be in [1, 4096]");
         auto s = std::make_unique<sg_server>();
         SG_HIP(hipGetDevice(&s->device));
         if (hbm_budget_bytes == 0) {
@@ -239,15 +236,18 @@ int sg_server_create(size_t hbm_budget_bytes, int32_t max_slots, sg_server** out
         *out = s.release();
         return SG_OK;
     } catch (const sg::Error& e) {
+        sg::set_last_error(e.what());
         return e.code;
     } catch (...) {
+        sg::set_last_error("unknown failure in sg_server_create");
         return SG_ERR_INVALID;
     }
 }
 
 int sg_submit(sg_server* s, const sg_problem* prob, const sg_options* opt, double* x_out, uint64_t* ticket) {
     try {
-        if (!s || !prob || !x_out || !ticket) return SG_ERR_INVALID;
+        sg::set_last_error("");
+        if (!s || !prob || !x_out || !ticket) throw sg::Error(SG_ERR_INVALID, "null argument");
         sg_options o;
         if (opt)
             o = *opt;
@@ -270,7 +270,7 @@ int sg_submit(sg_server* s, const sg_problem* prob, const sg_options* opt, doubl
         r->footprint = footprint_bytes(*prob, o);
         r->t_submit = Clock::now();
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stopping) return SG_ERR_INVALID;
+        if (s->stopping) throw sg::Error(SG_ERR_INVALID, "server is shutting down");
         if (r->footprint > s->budget)
             throw sg::Error(SG_ERR_NOMEM, "request footprint " + std::to_string(r->footprint) +
                                               " bytes exceeds the server budget");
@@ -285,9 +285,10 @@ int sg_submit(sg_server* s, const sg_problem* prob, const sg_options* opt, doubl
         s->cv_sched.notify_all();
         return SG_OK;
     } catch (const sg::Error& e) {
-        g_srv_error = e.what();
+        sg::set_last_error(e.what());
         return e.code;
     } catch (...) {
+        sg::set_last_error("unknown failure in sg_submit");
         return SG_ERR_INVALID;
     }
 }
