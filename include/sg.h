@@ -111,7 +111,8 @@ typedef struct sg_problem {
  *   gmg_pre/post Chebyshev smoothing degree before/after coarse correction [2,2]
  *   precision    SG_PREC_FP64 or SG_PREC_FP32_REFINE [SG_PREC_FP64]
  *   inner_rtol   FP32 inner solve reduction per refinement step [1e-5]
- *   use_graphs   capture per-iteration launch sequences in hipGraphs [1]
+ *   use_graphs   replay each FGMRES iteration from a cached hipGraph when the
+ *                handle has a stream other than the default stream [1]
  *   verbose      print per-cycle residuals to stderr [0]
  *   profile      time one kernel's launches with HIP events during sg_solve
  *                (SG_PROF_* below) and report them in sg_solve_info [0] */

@@ -30,6 +30,7 @@ class Workspace {
         }
         bufs_[name] = {p, bytes};
         total_ += bytes;
+        ++gen_;
         return p;
     }
     template <typename T>
@@ -42,10 +43,12 @@ class Workspace {
         total_ = 0;
     }
     size_t total() const { return total_; }
+    uint64_t generation() const { return gen_; }   // changes whenever a buffer is (re)allocated
 
   private:
     std::map<std::string, std::pair<void*, size_t>> bufs_;
     size_t total_ = 0;
+    uint64_t gen_ = 0;
 };
 
 // HIP-event timing of one kernel's launches (sg_options.profile).
@@ -64,6 +67,20 @@ struct Prof {
             (void)hipEventDestroy(e.second);
         }
     }
+};
+
+// Instantiated graphs of one FGMRES iteration, keyed by (restart position j,
+// FP32 inner path), valid for one workspace generation.
+struct GraphCache {
+    std::map<std::pair<int, int>, hipGraphExec_t> exec;
+    uint64_t gen = ~0ull;
+    bool warm[2] = {false, false};
+    void clear() {
+        for (auto& kv : exec) (void)hipGraphExecDestroy(kv.second);
+        exec.clear();
+        warm[0] = warm[1] = false;
+    }
+    ~GraphCache() { clear(); }
 };
 
 struct Handle {
@@ -94,6 +111,7 @@ struct Handle {
 
     Workspace ws;
     Prof prof;
+    GraphCache graphs;
     double* h_pinned = nullptr;        // host-pinned scratch for small readbacks
     size_t h_pinned_count = 0;
 

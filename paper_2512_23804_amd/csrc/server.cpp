@@ -138,6 +138,10 @@ void sg_server::run_batch(const std::vector<uint64_t>& ids, hipStream_t st) {
         for (uint64_t id : ids) probs.push_back(reqs[id]->prob);
         opt = reqs[ids[0]]->opt;
     }
+    // A batch handle lives for one solve, so per-iteration graphs would be
+    // captured once and replayed about once; workers also allocate while other
+    // workers would be capturing.  Launch directly.
+    opt.use_graphs = 0;
     const int B = (int)ids.size();
     std::vector<sg_solve_info> info(B);
     std::vector<int> status(B, SG_OK);

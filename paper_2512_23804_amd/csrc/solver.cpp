@@ -337,7 +337,8 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
         launch_cycle_start(K.kd, m, K.kd.nrm, B, st);    // kd.nrm holds ||r||^2 from residual()
         launch_copy_scale_rows(r, K.Vi(0), K.kd.nrm, N, B, N, st);
-        for (int j = 0; j < m; ++j) {
+        // one FGMRES iteration: preconditioner, KKT apply, CGS2 Arnoldi, Givens
+        auto iteration = [&](int j) {
             K.apply_prec(j);
             K.apply_op_z(j);
             const int nv = j + 1;
@@ -353,6 +354,39 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
             launch_reduce_partials(K.partial, K.nblk, 1, B, K.kd.nrm, 1, 0, st);
             launch_arnoldi_finish(K.kd, m, j, B, st);
             launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
+        };
+        const int zk = K.z32 ? 1 : 0;
+        // (capture needs a created stream; the legacy default stream cannot be captured)
+        const bool graphs = h.opt.use_graphs && st != nullptr && h.prof.kind == SG_PROF_NONE && h.opt.cheb_steps <= 9;
+        if (graphs && h.graphs.gen != h.ws.generation()) {
+            h.graphs.clear();
+            h.graphs.gen = h.ws.generation();
+        }
+        for (int j = 0; j < m; ++j) {
+            if (graphs && h.graphs.warm[zk]) {
+                auto key = std::make_pair(j, zk);
+                auto it = h.graphs.exec.find(key);
+                if (it == h.graphs.exec.end()) {
+                    hipGraph_t g = nullptr;
+                    SG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    try {
+                        iteration(j);
+                    } catch (...) {
+                        (void)hipStreamEndCapture(st, &g);
+                        if (g) (void)hipGraphDestroy(g);
+                        throw;
+                    }
+                    SG_HIP(hipStreamEndCapture(st, &g));
+                    hipGraphExec_t ex = nullptr;
+                    const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(g);
+                    SG_HIP(e);
+                    it = h.graphs.exec.emplace(key, ex).first;
+                }
+                SG_HIP(hipGraphLaunch(it->second, st));
+            } else {
+                iteration(j);
+            }
             K.readback(K.kd.resid, resid);    // synchronises the stream
             bool still = false, changed = false;
             for (int q = 0; q < B; ++q) {
@@ -377,6 +411,13 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         launch_back_solve(K.kd, m, K.d_jend, B, st);
         launch_multi_axpy(K.Z, K.z32 ? 1 : 0, (int64_t)B * N, m, K.d_jend, K.kd.y, m, x, N, B, N, st);
         SG_HIP(hipStreamSynchronize(st));     // the staging area is reused next cycle
+        if (graphs) {
+            if (h.graphs.gen != h.ws.generation()) {   // buffers allocated in this cycle: recapture later
+                h.graphs.clear();
+                h.graphs.gen = h.ws.generation();
+            }
+            h.graphs.warm[zk] = true;
+        }
     }
 }
 

@@ -224,3 +224,26 @@ def test_batch_results_equal_alone():
             rca, infa = ha.solve(xa)
             assert rca == 0 and infa[0].iters == infos[i].iters
             assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replay_matches_direct_launches(precision):
+    """Solves on a created stream replay cached per-iteration graphs after the
+    first cycle; three consecutive solves with graphs and one without must be
+    bit-identical."""
+    dev = _dev()
+    _say(f"graph replay precision={precision}")
+    sgl = _lib()
+    prob, kw = make_case(16, 3, 2, 0.3, 1e-3)
+    stream = torch.cuda.Stream()
+    outs = []
+    for use_graphs in (1, 1, 1, 0):
+        if not outs or use_graphs == 0:
+            h = sgl.Handle([sgl.ProblemData(**kw)], sgl.default_options(rtol=1e-10, precision=precision,
+                                                                        use_graphs=use_graphs), stream=stream)
+        x = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+        rc, info = h.solve(x)
+        assert rc == 0 and info[0].iters > 30      # more than one restart cycle
+        outs.append(x.clone())
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
