@@ -136,6 +136,7 @@ def main():
     ap.add_argument("--profile-kernel", default="kkt_apply", choices=sorted(PROF_KIND))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no HIP graph replay)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
@@ -151,16 +152,19 @@ def main():
     stream = torch.cuda.Stream()
     prof = PROF_KIND[args.profile_kernel]
 
+    graphs = 0 if args.no_graphs else 1
     # headline: FP64 batch (the whole beta sweep) per step
-    opts = sgl.default_options(rtol=1e-8, profile=prof)
+    opts = sgl.default_options(rtol=1e-8, use_graphs=graphs)
     dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream)
     nsolve = len(probs) * args.steps
     value = nsolve / dt
     iters = [i.iters for step in infos for i in step]
     rel = max(i.rel_res_true for step in infos for i in step)
-    pms = sum(step[0].prof_ms for step in infos)
-    pbytes = sum(step[0].prof_bytes for step in infos)
-    plaunch = sum(step[0].prof_launches for step in infos)
+    # roofline: one more solve of the same batch with HIP events around every
+    # launch of the profiled kernel (event pairs serialise the stream a little,
+    # so this solve is not part of the timed steps)
+    _, pinfo = timed_solves(torch, sgl, probs, sgl.default_options(rtol=1e-8, profile=prof), 1, 0, stream)
+    pms, pbytes, plaunch = pinfo[0][0].prof_ms, pinfo[0][0].prof_bytes, pinfo[0][0].prof_launches
     achieved = pbytes / pms / 1e6 if pms > 0 else 0.0
     out = {
         "metric": "KKT solves/s to rel-res 1e-8 (FP64 vs FP32+refine); SG apply HBM GB/s",
@@ -177,7 +181,7 @@ def main():
         "data": "synthetic (seeded Gaussian-bump targets, cosine random field)",
         "config": {"workload": args.workload, "n": wl["n"], "M": wl["M"], "P": wl["P"], "sigma": wl["sigma"],
                    "betas": list(wl["betas"]), "n_t": wl["n_t"], "batch": len(probs), "restart": 30,
-                   "rtol": 1e-8, "precision": "fp64"},
+                   "rtol": 1e-8, "precision": "fp64", "graphs": bool(graphs)},
         "iterations": iters[: len(probs)],
         "max_rel_res": rel,
         "roofline": {"bound": "hbm", "kernel": args.profile_kernel, "achieved": achieved, "peak": HBM_PEAK_GBPS,
@@ -186,7 +190,7 @@ def main():
                      "bytes_per_launch": pbytes / max(plaunch, 1)},
     }
     if not args.no_extras:
-        o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE)
+        o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE, use_graphs=graphs)
         dt32, inf32 = timed_solves(torch, sgl, probs, o32, args.steps, 1, stream)
         out["fp32_refine"] = {"value": nsolve / dt32, "unit": "solves/s", "dtype": "f32 operator/preconditioner, "
                               "f64 Arnoldi and refinement", "iterations": [i.iters for i in inf32[0]],
@@ -194,7 +198,8 @@ def main():
         single = []
         t_single = 0.0
         for p in probs:
-            dts, infs = timed_solves(torch, sgl, [p], sgl.default_options(rtol=1e-8), 1, 1, stream)
+            dts, infs = timed_solves(torch, sgl, [p], sgl.default_options(rtol=1e-8, use_graphs=graphs), 1, 1,
+                                     stream)
             t_single += dts
             single.append(infs[0][0].iters)
         out["fp64_single"] = {"value": len(probs) / t_single, "unit": "solves/s", "iterations": single}

@@ -467,14 +467,19 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Block-reduce `nv` per-thread accumulators into partial[(mem*nvmax + i)*nblk + blk].
-__device__ __forceinline__ void block_reduce_store(double* acc, int nv, double* partial, int mem, int nvmax,
+// Block-reduce the first `nv` of NA per-thread accumulators into
+// partial[(mem*nvmax + i)*nblk + blk].
+template <int NA>
+__device__ __forceinline__ void block_reduce_store(const double* acc, int nv, double* partial, int mem, int nvmax,
                                                    int nblk) {
     __shared__ double red[RB / 64][MAXV + 1];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int i = 0; i < nv; ++i) {
-        const double s = wave_sum(acc[i]);
-        if (lane == 0) red[wave][i] = s;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        if (i < nv) {
+            const double s = wave_sum(acc[i]);
+            if (lane == 0) red[wave][i] = s;
+        }
     }
     __syncthreads();
     if ((int)threadIdx.x < nv) {
@@ -490,28 +495,47 @@ __device__ __forceinline__ void chunk_range(int64_t n, int nblk, int blk, int64_
     hi = lo + per < n ? lo + per : n;
 }
 
-// partial[i] = V_i . w  (i < nv)
+// Basis vectors are streamed once per pass and are far larger than the
+// caches, so their loads bypass them.
+__device__ __forceinline__ double ld_stream(const double* p) { return __builtin_nontemporal_load(p); }
+
+// partial[i] = V_i . w  (i < nv <= NV).  Two elements per thread per trip keep
+// 2*nv loads in flight per lane.
+template <int NV>
 __global__ __launch_bounds__(RB) void k_multidot(const double* __restrict__ V, int64_t vstride, int nv,
                                                  const double* __restrict__ w, int64_t n, int64_t mstride,
                                                  double* __restrict__ partial, int nblk) {
     const int mem = blockIdx.y;
     int64_t lo, hi;
     chunk_range(n, nblk, blockIdx.x, lo, hi);
-    double acc[MAXV];
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     const double* wm = w + mem * mstride;
     const double* Vm = V + mem * mstride;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+    int64_t e = lo + threadIdx.x;
+    for (; e + RB < hi; e += 2 * RB) {
+        const double w0 = ld_stream(wm + e), w1 = ld_stream(wm + e + RB);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nv) {
+                const double* p = Vm + i * vstride + e;
+                acc[i] += ld_stream(p) * w0;
+                acc[i] += ld_stream(p + RB) * w1;
+            }
+        }
+    }
+    if (e < hi) {
         const double we = wm[e];
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i)
+        for (int i = 0; i < NV; ++i)
             if (i < nv) acc[i] += Vm[i * vstride + e] * we;
     }
-    block_reduce_store(acc, nv, partial, mem, MAXV, nblk);
+    block_reduce_store<NV>(acc, nv, partial, mem, MAXV, nblk);
 }
 
 // w1 = w - sum_i h_i V_i (written to w), partial[i] = V_i . w1
+template <int NV>
 __global__ __launch_bounds__(RB) void k_cgs_update_dot(const double* __restrict__ V, int64_t vstride, int nv,
                                                        const double* __restrict__ h, int hstride,
                                                        double* __restrict__ w, int64_t n, int64_t mstride,
@@ -519,30 +543,31 @@ __global__ __launch_bounds__(RB) void k_cgs_update_dot(const double* __restrict_
     const int mem = blockIdx.y;
     int64_t lo, hi;
     chunk_range(n, nblk, blockIdx.x, lo, hi);
-    double hc[MAXV], acc[MAXV];
+    double hc[NV], acc[NV];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) {
+    for (int i = 0; i < NV; ++i) {
         hc[i] = i < nv ? h[mem * hstride + i] : 0.0;
         acc[i] = 0.0;
     }
     double* wm = w + mem * mstride;
     const double* Vm = V + mem * mstride;
     for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
-        double v[MAXV];
+        double v[NV];
         double we = wm[e];
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i) {
-            v[i] = i < nv ? Vm[i * vstride + e] : 0.0;
+        for (int i = 0; i < NV; ++i) {
+            v[i] = i < nv ? ld_stream(Vm + i * vstride + e) : 0.0;
             we -= hc[i] * v[i];
         }
         wm[e] = we;
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i) acc[i] += v[i] * we;
+        for (int i = 0; i < NV; ++i) acc[i] += v[i] * we;
     }
-    block_reduce_store(acc, nv, partial, mem, MAXV, nblk);
+    block_reduce_store<NV>(acc, nv, partial, mem, MAXV, nblk);
 }
 
 // out = w - sum_i h_i V_i, partial[0] = ||out||^2
+template <int NV>
 __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict__ V, int64_t vstride, int nv,
                                                         const double* __restrict__ h, int hstride,
                                                         const double* __restrict__ w, double* __restrict__ out,
@@ -551,9 +576,9 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
     const int mem = blockIdx.y;
     int64_t lo, hi;
     chunk_range(n, nblk, blockIdx.x, lo, hi);
-    double hc[MAXV];
+    double hc[NV];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i) hc[i] = i < nv ? h[mem * hstride + i] : 0.0;
+    for (int i = 0; i < NV; ++i) hc[i] = i < nv ? h[mem * hstride + i] : 0.0;
     double acc[1] = {0.0};
     const double* wm = w + mem * mstride;
     double* om = out + mem * mstride;
@@ -561,12 +586,12 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
     for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
         double we = wm[e];
 #pragma unroll
-        for (int i = 0; i < MAXV; ++i)
-            if (i < nv) we -= hc[i] * Vm[i * vstride + e];
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) we -= hc[i] * ld_stream(Vm + i * vstride + e);
         om[e] = we;
         acc[0] += we * we;
     }
-    block_reduce_store(acc, 1, partial, mem, MAXV, nblk);
+    block_reduce_store<1>(acc, 1, partial, mem, MAXV, nblk);
 }
 
 // out[mem*out_stride + out_offset + i] = sum_blk partial[(mem*MAXV + i)*nblk + blk]
@@ -630,7 +655,7 @@ __global__ __launch_bounds__(RB) void k_sub_norm(const double* __restrict__ b, d
         r[mem * mstride + e] = v;
         acc[0] += v * v;
     }
-    block_reduce_store(acc, 1, partial, mem, MAXV, nblk);
+    block_reduce_store<1>(acc, 1, partial, mem, MAXV, nblk);
 }
 
 __global__ __launch_bounds__(RB) void k_norm(const double* __restrict__ x, int64_t n, int64_t mstride,
@@ -643,7 +668,7 @@ __global__ __launch_bounds__(RB) void k_norm(const double* __restrict__ x, int64
         const double v = x[mem * mstride + e];
         acc[0] += v * v;
     }
-    block_reduce_store(acc, 1, partial, mem, MAXV, nblk);
+    block_reduce_store<1>(acc, 1, partial, mem, MAXV, nblk);
 }
 
 __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t n) {
@@ -839,18 +864,31 @@ void launch_zero_ring(T* x, int n, int64_t ncols, hipStream_t st) {
     SG_HIP(hipGetLastError());
 }
 
+// Instantiations by basis-vector count: fewer accumulators for short bases.
+#define SG_NV_DISPATCH(KERNEL, nv, ...)                                                          \
+    do {                                                                                          \
+        if ((nv) <= 4)                                                                            \
+            hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__);                                           \
+        else if ((nv) <= 8)                                                                       \
+            hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__);                                           \
+        else if ((nv) <= 16)                                                                      \
+            hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__);                                          \
+        else                                                                                      \
+            hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__);                                          \
+    } while (0)
+
 void launch_multidot(const double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem, int64_t mstride,
                      double* partial, int nblk, hipStream_t st) {
     if (nv > MAXV) throw Error(SG_ERR_INVALID, "multidot: too many vectors");
-    hipLaunchKernelGGL(k_multidot, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, w, n, mstride, partial, nblk);
+    SG_NV_DISPATCH(k_multidot, nv, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, w, n, mstride, partial, nblk);
     SG_HIP(hipGetLastError());
 }
 
 void launch_cgs_update_dot(const double* V, int64_t vstride, int nv, const double* h, int hstride, double* w,
                            int64_t n, int nmem, int64_t mstride, double* partial, int nblk, hipStream_t st) {
     if (nv > MAXV) throw Error(SG_ERR_INVALID, "cgs: too many vectors");
-    hipLaunchKernelGGL(k_cgs_update_dot, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, h, hstride, w, n, mstride,
-                       partial, nblk);
+    SG_NV_DISPATCH(k_cgs_update_dot, nv, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, h, hstride, w, n,
+                   mstride, partial, nblk);
     SG_HIP(hipGetLastError());
 }
 
@@ -858,8 +896,8 @@ void launch_cgs_update_norm(const double* V, int64_t vstride, int nv, const doub
                             double* out, int64_t n, int nmem, int64_t mstride, double* partial, int nblk,
                             hipStream_t st) {
     if (nv > MAXV) throw Error(SG_ERR_INVALID, "cgs: too many vectors");
-    hipLaunchKernelGGL(k_cgs_update_norm, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, h, hstride, w, out, n,
-                       mstride, partial, nblk);
+    SG_NV_DISPATCH(k_cgs_update_norm, nv, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, h, hstride, w, out, n,
+                   mstride, partial, nblk);
     SG_HIP(hipGetLastError());
 }
 

@@ -224,7 +224,7 @@ struct Krylov {
         B = h.B;
         m = h.opt.restart;
         N = 3 * s.blk;
-        nblk = (int)std::min<int64_t>(1024, std::max<int64_t>(1, N / (256 * 16)));
+        nblk = (int)std::min<int64_t>(2048, std::max<int64_t>(1, N / (256 * 16)));
         z32 = fp32;
         V = h.ws.get_t<double>("kV", (size_t)(m + 1) * B * N);
         Z = z32 ? (void*)h.ws.get_t<float>("kZ32", (size_t)m * B * N) : (void*)h.ws.get_t<double>("kZ", (size_t)m * B * N);
