@@ -116,6 +116,8 @@ struct OpDev {                   // device pointers describing the operator of a
 template <typename T>
 bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
 template <typename T>
+bool launch_sgx_kkt(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
+template <typename T>
 bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
                         const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
                         hipStream_t st);

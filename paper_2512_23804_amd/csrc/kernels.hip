@@ -779,6 +779,7 @@ void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec
 
 template <typename T>
 void launch_kkt_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+    if (launch_sgx_kkt<T>(s, op, x, y, nvec, st)) return;
     dim3 g = tile_grid(s.n, (s.nxi + kJChunk - 1) / kJChunk, (int64_t)nvec * s.nt);
     hipLaunchKernelGGL(k_kkt_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, (int)s.time, s.nodes, op, x, y);
     SG_HIP(hipGetLastError());

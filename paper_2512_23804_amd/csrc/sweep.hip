@@ -297,6 +297,151 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_SWEEP_WA
     }
 }
 
+// Reference-element mass (h^2/36)[4 2 1 2; 2 4 2 1; 1 2 4 2; 2 1 2 4] on a
+// corner vector: m_a = w (2 s + 2 v_a - v_opp), w = h^2/36.
+template <typename T>
+__device__ __forceinline__ void mass_accumulate(T (&e)[RS + 1][4], const T (&vals)[RS + 2], const Strip& st, T w) {
+    T prev = vals[0];
+    T prevR = shdn(prev);
+#pragma unroll
+    for (int r = 0; r < RS + 1; ++r) {
+        const T top = vals[r + 1];
+        const T topR = shdn(top);
+        const T c = ((st.emask >> r) & 1u) ? w : T(0);
+        const T s2 = T(2) * ((prev + prevR) + (topR + top));
+        e[r][0] += c * (s2 + T(2) * prev - topR);
+        e[r][1] += c * (s2 + T(2) * prevR - top);
+        e[r][2] += c * (s2 + T(2) * topR - prev);
+        e[r][3] += c * (s2 + T(2) * top - prevR);
+        prev = top;
+        prevR = topR;
+    }
+}
+
+// Corner sums of the SG stiffness strip -> element results scaled by -s.
+template <typename T>
+__device__ __forceinline__ void stiff_to_element(T (&v)[RS + 1][4], T s) {
+#pragma unroll
+    for (int r = 0; r < RS + 1; ++r) {
+        T k0, k1, k2, k3;
+        kref(v[r][0], v[r][1], v[r][2], v[r][3], k0, k1, k2, k3);
+        v[r][0] = -s * k0;
+        v[r][1] = -s * k1;
+        v[r][2] = -s * k2;
+        v[r][3] = -s * k3;
+    }
+}
+
+// Node values from per-element results e[r][.] (element rows y0-1+r): node
+// (X, Y) sums corners 0 and 3 of its own lane's element rows r and r-1 and
+// corners 1 and 2 of the lane to the left; non-interior nodes get zero.
+template <typename T>
+__device__ __forceinline__ void emit_nodes(const T (&e)[RS + 1][4], const Strip& st, int gl, int X, int n,
+                                           T* __restrict__ out) {
+    const bool xout = gl >= 1 && gl <= GOUT && X <= n;
+#pragma unroll
+    for (int r = 1; r < RS + 1; ++r) {
+        const T A = e[r][0] + e[r - 1][3];
+        const T Bl = shup(e[r][1] + e[r - 1][2]);
+        const int Y = st.y0 - 1 + r;
+        if (xout && Y <= n) out[(int64_t)Y * (n + 1) + X] = ((st.nmask >> r) & 1u) ? A + Bl : T(0);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void zero_strip(T (&v)[RS + 1][4]) {
+#pragma unroll
+    for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
+}
+
+// Fused KKT apply, one output chaos column per wavefront, three residual blocks
+// in turn.  With the SG stiffness A (mean included) and Q1 mass M:
+//   steady (eq. stoch-system):  R^Y = M Y H^gamma - A L,  R^U = beta M U + M L,  R^L = M U - A Y
+//   time (eq. KKT:stoch-time-dependent, backward Euler, D = diag(1/2, 1, .., 1, 1/2)):
+//     R^Y_t = tau D_t M_gamma Y_t - M L_t - tau A L_t + M L_{t+1}
+//     R^U_t = beta tau D_t M U_t + tau M L_t
+//     R^L_t = -M Y_t - tau A Y_t + M Y_{t-1} + tau M U_t
+// Each block is (mass of a combination of diagonal columns) - s (stiffness strip),
+// formed per element and assembled once.
+#ifndef SG_KKT_WAVES
+#define SG_KKT_WAVES 3
+#endif
+template <typename T, bool TIME>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_KKT_WAVES))) void k_sgx_kkt(
+    int n, int M, int nxi, int nt, int64_t nodes, OpDev op, SweepGeom g, const T* __restrict__ x,
+    T* __restrict__ y) {
+    const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (lb >= g.nb) return;
+    const int chunk = lb % g.nchunks;
+    const int rest = lb / g.nchunks;
+    const int tiles = g.tiles_x * g.tiles_y;
+    const int tile = rest % tiles;
+    const int slice = rest / tiles;
+    const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = chunk * 4 + wave;
+    if (j >= nxi) return;                            // uniform per wavefront; no block barriers below
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & (GW - 1);
+    const int grp = lane / GW;
+    const int X = tx * GOUT + gl - 1;
+    const int y0 = (ty * 2 + grp) * RS;
+    const int vec = slice / nt;
+    const int t = slice % nt;
+    const int mem = op.mem_shared ? 0 : vec;
+    const MemberDev md = op.mem[mem];
+    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const int64_t cplane = (int64_t)n * n;
+    const int64_t blk = (int64_t)nt * nxi * nodes;
+    const int64_t tst = (int64_t)nxi * nodes;
+    const int64_t cj = (int64_t)j * nodes;
+    const T* Yt = x + (int64_t)vec * 3 * blk + t * tst;
+    const T* Ut = Yt + blk;
+    const T* Lt = Ut + blk;
+    T* RY = y + (int64_t)vec * 3 * blk + t * tst + cj;
+    T* RU = RY + blk;
+    T* RL = RU + blk;
+    const T hinv = T(1) / T(n);
+    const T w = hinv * hinv / T(36);
+    const T tau = TIME ? T(md.tau) : T(1);
+    const T Dt = (TIME && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
+    const T hgj = j == 0 ? T(1) : T(md.hg);
+    const T beta = T(md.beta);
+    const T c0 = T(md.c0);
+    Strip st;
+    st.init(n, X, y0);
+    T v[RS + 1][4];
+    T vals[RS + 2];
+    // R^Y
+    zero_strip(v);
+    sg_strip(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
+    stiff_to_element(v, tau);
+    load_col(vals, Yt + cj, st, tau * Dt * hgj, false);
+    if (TIME) {
+        load_col(vals, Lt + cj, st, T(-1), true);
+        if (t + 1 < nt) load_col(vals, Lt + tst + cj, st, T(1), true);
+    }
+    mass_accumulate(v, vals, st, w);
+    emit_nodes(v, st, gl, X, n, RY);
+    // R^L
+    zero_strip(v);
+    sg_strip(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
+    stiff_to_element(v, tau);
+    load_col(vals, Ut + cj, st, tau, false);
+    if (TIME) {
+        load_col(vals, Yt + cj, st, T(-1), true);
+        if (t > 0) load_col(vals, Yt - tst + cj, st, T(1), true);
+    }
+    mass_accumulate(v, vals, st, w);
+    emit_nodes(v, st, gl, X, n, RL);
+    // R^U
+    zero_strip(v);
+    load_col(vals, Ut + cj, st, beta * tau * Dt, false);
+    load_col(vals, Lt + cj, st, tau, true);
+    mass_accumulate(v, vals, st, w);
+    emit_nodes(v, st, gl, X, n, RU);
+}
+
 SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
     SweepGeom g;
     g.tiles_x = (n + 1 + GOUT - 1) / GOUT;
@@ -324,6 +469,21 @@ bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nve
 }
 
 template <typename T>
+bool launch_sgx_kkt(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+    if (s.M > KMAX) return false;
+    const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, RS);
+    const int grid = (g.nb + 7) / 8 * 8;
+    if (s.time)
+        hipLaunchKernelGGL((k_sgx_kkt<T, true>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, g,
+                           x, y);
+    else
+        hipLaunchKernelGGL((k_sgx_kkt<T, false>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op,
+                           g, x, y);
+    SG_HIP(hipGetLastError());
+    return true;
+}
+
+template <typename T>
 bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
                         const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
                         hipStream_t st) {
@@ -339,6 +499,8 @@ bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, i
 
 template bool launch_sgx_apply<double>(const Shape&, const OpDev&, const double*, double*, int, hipStream_t);
 template bool launch_sgx_apply<float>(const Shape&, const OpDev&, const float*, float*, int, hipStream_t);
+template bool launch_sgx_kkt<double>(const Shape&, const OpDev&, const double*, double*, int, hipStream_t);
+template bool launch_sgx_kkt<float>(const Shape&, const OpDev&, const float*, float*, int, hipStream_t);
 template bool launch_sgx_hgs_rhs<double>(const Shape&, const OpDev&, int, uint32_t, int, int, const double*, ColMap,
                                          const double*, ColMap, double*, ColMap, int, hipStream_t);
 template bool launch_sgx_hgs_rhs<float>(const Shape&, const OpDev&, int, uint32_t, int, int, const float*, ColMap,
