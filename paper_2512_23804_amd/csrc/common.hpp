@@ -154,6 +154,9 @@ template <typename T>
 void launch_mg_down(int m, const LevelDev* lev, int lvl, int nu, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc,
                     int ncols, int cpm, hipStream_t st);
 template <typename T>
+void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x,
+                    ColMap xmap, const T* ainv, int ncols, int cpm, hipStream_t st);
+template <typename T>
 void launch_mg_up(int m, const LevelDev* lev, int lvl, int nu, const T* xin, ColMap xinmap, const T* ec, const T* b,
                   ColMap bmap, T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st);
 

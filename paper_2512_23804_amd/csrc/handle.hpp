@@ -86,6 +86,7 @@ struct GraphCache {
 struct Handle {
     Shape s{};
     int B = 1;                          // members
+    int mg_tail_max = 64;               // finest multigrid level run by the fused single-workgroup tail
     sg_options opt{};
     hipStream_t stream = nullptr;
     int device = 0;

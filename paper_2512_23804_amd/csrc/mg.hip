@@ -249,6 +249,174 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     }
 }
 
+// --------------------------------------------------------------------------
+// Coarse end of the V-cycle in one workgroup per column.  Levels M0, M0/2, ..,
+// kCoarseN live in LDS (right-hand side and iterate per level, one residual
+// buffer): pre-smoothing from zero, residual and restriction on the way down,
+// the direct solve on the kCoarseN grid (dense inverse of the interior
+// operator), interpolation and post-smoothing on the way up.  Replaces
+// 2 log2(M0/kCoarseN) + 1 launches per V-cycle by one.  The Chebyshev step
+// direction of the nodes a thread owns stays in its registers.
+// --------------------------------------------------------------------------
+constexpr int kTailThreads = 512;
+
+__host__ __device__ constexpr int tail_levels(int m0) { return m0 <= kCoarseN ? 1 : 1 + tail_levels(m0 / 2); }
+__host__ __device__ constexpr int tail_offset(int m0, int k) {
+    return k == 0 ? 0 : (m0 + 1) * (m0 + 1) + tail_offset(m0 / 2, k - 1);
+}
+
+template <typename T, int M0>
+struct TailLds {
+    static constexpr int NL = tail_levels(M0);
+    static constexpr int W0 = M0 + 1;
+    static constexpr int total = tail_offset(M0, NL);    // sum of (m+1)^2 over the levels
+    T b[total];
+    T x[total];
+    T r[W0 * W0];
+};
+
+// One Chebyshev smoothing step on level (m, W = m + 1); `first` uses c_d = 0.
+template <typename T, int PPT>
+__device__ __forceinline__ void tail_smooth_step(const T* __restrict__ B, T* __restrict__ Xs, int m, T wc, T we, T wd,
+                                                 T dinv, T cd, T cr, bool first, T (&d)[PPT]) {
+    const int W = m + 1;
+    T xn[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + p * kTailThreads;
+        const int X = q % W, Y = q / W;
+        xn[p] = T(0);
+        if (q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) {
+            const T r = B[q] - st9(Xs, W, q, wc, we, wd);
+            const T dn = (first ? T(0) : cd * d[p]) + cr * dinv * r;
+            d[p] = dn;
+            xn[p] = Xs[q] + dn;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + p * kTailThreads;
+        const int X = q % W, Y = q / W;
+        if (q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) Xs[q] = xn[p];
+    }
+    __syncthreads();
+}
+
+template <typename T, int M0>
+__global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __restrict__ lev, int lvl0, int npre,
+                                                          int npost, const T* __restrict__ b, ColMap bmap,
+                                                          T* __restrict__ x, ColMap xmap, const T* __restrict__ ainv,
+                                                          int cpm) {
+    using Lds = TailLds<T, M0>;
+    constexpr int NL = Lds::NL;
+    constexpr int W0 = Lds::W0;
+    constexpr int PPT = (W0 * W0 + kTailThreads - 1) / kTailThreads;
+    __shared__ Lds s;
+    const int c = blockIdx.x;
+    const int mem = c / cpm;
+    const T* bcol = b + bmap.off(c);
+    for (int q = threadIdx.x; q < W0 * W0; q += kTailThreads) {
+        const int X = q % W0, Y = q / W0;
+        s.b[q] = (X >= 1 && X <= M0 - 1 && Y >= 1 && Y <= M0 - 1) ? bcol[q] : T(0);
+    }
+    __syncthreads();
+    T d[PPT];
+    // down: pre-smoothing from zero, residual, restriction
+#pragma unroll 1
+    for (int k = 0; k < NL - 1; ++k) {
+        const int m = M0 >> k, W = m + 1, mc = m / 2, C1 = mc + 1;
+        T* B = s.b + tail_offset(M0, k);
+        T* Xs = s.x + tail_offset(M0, k);
+        T* Bc = s.b + tail_offset(M0, k + 1);
+        const LevelDev& L = lev[mem * kMaxLevels + lvl0 + k];
+        const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
+        const T cr0 = T(L.pre[0][1]);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int q = threadIdx.x + p * kTailThreads;
+            if (q < W * W) {
+                const T x1 = cr0 * dinv * B[q];     // B is zero off the interior
+                d[p] = x1;
+                Xs[q] = x1;
+            }
+        }
+        __syncthreads();
+        for (int st = 1; st < npre; ++st)
+            tail_smooth_step<T, PPT>(B, Xs, m, wc, we, wd, dinv, T(L.pre[st][0]), T(L.pre[st][1]), false, d);
+        for (int q = threadIdx.x; q < W * W; q += kTailThreads) {
+            const int X = q % W, Y = q / W;
+            s.r[q] = (X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) ? B[q] - st9(Xs, W, q, wc, we, wd) : T(0);
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < C1 * C1; q += kTailThreads) {
+            const int I = q % C1, J = q / C1;
+            T v = T(0);
+            if (I >= 1 && I <= mc - 1 && J >= 1 && J <= mc - 1) {
+                const int pf = 2 * J * W + 2 * I;
+                const T* R = s.r;
+                v = R[pf] + T(0.5) * (R[pf - 1] + R[pf + 1] + R[pf - W] + R[pf + W]) +
+                    T(0.25) * (R[pf - W - 1] + R[pf - W + 1] + R[pf + W - 1] + R[pf + W + 1]);
+            }
+            Bc[q] = v;
+        }
+        __syncthreads();
+    }
+    // direct solve on the kCoarseN grid: four threads per interior unknown
+    {
+        constexpr int N1 = kCoarseN + 1, NU = (kCoarseN - 1) * (kCoarseN - 1);
+        const T* Bc = s.b + tail_offset(M0, NL - 1);
+        T* Xc = s.x + tail_offset(M0, NL - 1);
+        const T* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad;
+        const int row = threadIdx.x / 4, part = threadIdx.x % 4;
+        T acc = T(0);
+        if (row < NU) {
+            for (int k = part; k < NU; k += 4) {
+                const int ix = k % (kCoarseN - 1) + 1, iy = k / (kCoarseN - 1) + 1;
+                acc += A[row * kCoarsePad + k] * Bc[iy * N1 + ix];
+            }
+        }
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        for (int q = threadIdx.x; q < N1 * N1; q += kTailThreads) Xc[q] = T(0);
+        __syncthreads();
+        if (row < NU && part == 0) {
+            const int ix = row % (kCoarseN - 1) + 1, iy = row / (kCoarseN - 1) + 1;
+            Xc[iy * N1 + ix] = acc;
+        }
+        __syncthreads();
+    }
+    // up: interpolation of the coarse correction, post-smoothing
+#pragma unroll 1
+    for (int k = NL - 2; k >= 0; --k) {
+        const int m = M0 >> k, W = m + 1, C1 = m / 2 + 1;
+        const T* B = s.b + tail_offset(M0, k);
+        T* Xs = s.x + tail_offset(M0, k);
+        const T* E = s.x + tail_offset(M0, k + 1);
+        const LevelDev& L = lev[mem * kMaxLevels + lvl0 + k];
+        const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
+        for (int q = threadIdx.x; q < W * W; q += kTailThreads) {
+            const int X = q % W, Y = q / W;
+            if (X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) {
+                const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
+                Xs[q] += T(0.25) * (E[J0 * C1 + I0] + E[J0 * C1 + I1] + E[J1 * C1 + I0] + E[J1 * C1 + I1]);
+            }
+        }
+        __syncthreads();
+        for (int st = 0; st < npost; ++st)
+            tail_smooth_step<T, PPT>(B, Xs, m, wc, we, wd, dinv, T(L.post[st][0]), T(L.post[st][1]), st == 0, d);
+    }
+    T* xcol = x + xmap.off(c);
+    for (int q = threadIdx.x; q < W0 * W0; q += kTailThreads) xcol[q] = s.x[q];
+}
+
+template <typename T, int M0>
+void tail_m(const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x, ColMap xmap,
+            const T* ainv, int ncols, int cpm, hipStream_t st) {
+    hipLaunchKernelGGL((k_mg_tail<T, M0>), dim3(ncols), dim3(kTailThreads), 0, st, lev, lvl0, npre, npost, b, bmap,
+                       x, xmap, ainv, cpm);
+}
+
 template <typename T, int H>
 void cheb_h(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, const ChebW& cw, hipStream_t st) {
     constexpr int TF = 32;
@@ -311,6 +479,21 @@ void launch_mg_up(int m, const LevelDev* lev, int lvl, int nu, const T* xin, Col
     SG_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x,
+                    ColMap xmap, const T* ainv, int ncols, int cpm, hipStream_t st) {
+    if (ncols < 1) return;
+    if (npre < 1 || npre > kMaxSmooth || npost < 0 || npost > kMaxSmooth)
+        throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
+    switch (m0) {
+        case 16: tail_m<T, 16>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, st); break;
+        case 32: tail_m<T, 32>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, st); break;
+        case 64: tail_m<T, 64>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, st); break;
+        default: throw Error(SG_ERR_INVALID, "multigrid tail level must be 16, 32 or 64");
+    }
+    SG_HIP(hipGetLastError());
+}
+
 // Returns false when the step count has no fused kernel (more than 9 steps).
 template <typename T>
 bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, int steps, hipStream_t st) {
@@ -340,6 +523,10 @@ bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, i
 template bool launch_mass_cheb_fused<double>(const Shape&, const OpDev&, const double*, double*, int, int, hipStream_t);
 template bool launch_mass_cheb_fused<float>(const Shape&, const OpDev&, const float*, float*, int, int, hipStream_t);
 
+template void launch_mg_tail<double>(int, const LevelDev*, int, int, int, const double*, ColMap, double*, ColMap,
+                                     const double*, int, int, hipStream_t);
+template void launch_mg_tail<float>(int, const LevelDev*, int, int, int, const float*, ColMap, float*, ColMap,
+                                    const float*, int, int, hipStream_t);
 template void launch_mg_down<double>(int, const LevelDev*, int, int, const double*, ColMap, double*, ColMap, double*,
                                      int, int, hipStream_t);
 template void launch_mg_down<float>(int, const LevelDev*, int, int, const float*, ColMap, float*, ColMap, float*, int,

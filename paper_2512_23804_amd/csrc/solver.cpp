@@ -85,23 +85,29 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         launch_mg_coarse<T>(h.ainv<T>(), b, bmap, x, xmap, ncols, cpm, st);
         return;
     }
+    // Levels with at most tail_max intervals per side (and the direct solve)
+    // run in one fused launch; the finer levels have a down and an up launch each.
+    int l0 = 0;
+    while (l0 < nl - 1 && s.mg_n[l0] > h.mg_tail_max) ++l0;
+    const bool tail = l0 < nl - 1;
+    const int lc = tail ? l0 : nl - 1;      // first level handled by the fused tail or the direct solve
     // per level: xs (after pre-smoothing), bs (restricted right-hand side, l >= 1),
     // xf (after post-smoothing, l >= 1; level 0 writes to x)
     std::vector<T*> xs(nl), bs(nl), xf(nl);
     std::vector<ColMap> cm(nl);
-    for (int l = 0; l < nl; ++l) {
+    for (int l = 0; l <= lc; ++l) {
         const int m = s.mg_n[l];
         const int64_t nodes = (int64_t)(m + 1) * (m + 1);
         const size_t cnt = (size_t)ncols * nodes;
         const std::string tag = std::string("mg") + tname<T>() + "_" + std::to_string(l);
         cm[l] = contiguous_cols(ncols, nodes);
-        xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
+        if (l < lc || !tail) xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
         if (l > 0) {
             bs[l] = h.ws.get_t<T>(tag + "_bs", cnt);
             xf[l] = h.ws.get_t<T>(tag + "_xf", cnt);
         }
     }
-    for (int l = 0; l < nl - 1; ++l) {
+    for (int l = 0; l < lc; ++l) {
         const int m = s.mg_n[l];
         const double nodes = (double)(m + 1) * (m + 1);
         const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
@@ -109,9 +115,17 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
                           cpm, st);
         if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);   // read b, write x, write b_coarse
     }
-    launch_mg_coarse<T>(h.ainv<T>(), bs[nl - 1], cm[nl - 1], xs[nl - 1], cm[nl - 1], ncols, cpm, st);
-    const T* e = xs[nl - 1];
-    for (int l = nl - 2; l >= 0; --l) {
+    const T* e;
+    if (tail) {
+        T* out = lc == 0 ? x : xf[lc];
+        launch_mg_tail<T>(s.mg_n[lc], lev, lc, npre, npost, lc == 0 ? b : bs[lc], lc == 0 ? bmap : cm[lc], out,
+                          lc == 0 ? xmap : cm[lc], h.ainv<T>(), ncols, cpm, st);
+        e = out;
+    } else {
+        launch_mg_coarse<T>(h.ainv<T>(), bs[nl - 1], cm[nl - 1], xs[nl - 1], cm[nl - 1], ncols, cpm, st);
+        e = xs[nl - 1];
+    }
+    for (int l = lc - 1; l >= 0; --l) {
         const int m = s.mg_n[l];
         const double nodes = (double)(m + 1) * (m + 1);
         T* out = l == 0 ? x : xf[l];
