@@ -258,7 +258,10 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
 // 2 log2(M0/kCoarseN) + 1 launches per V-cycle by one.  The Chebyshev step
 // direction of the nodes a thread owns stays in its registers.
 // --------------------------------------------------------------------------
-constexpr int kTailThreads = 512;
+#ifndef SG_TAIL_THREADS
+#define SG_TAIL_THREADS 1024
+#endif
+constexpr int kTailThreads = SG_TAIL_THREADS;
 
 __host__ __device__ constexpr int tail_levels(int m0) { return m0 <= kCoarseN ? 1 : 1 + tail_levels(m0 / 2); }
 __host__ __device__ constexpr int tail_offset(int m0, int k) {
@@ -312,24 +315,42 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __rest
     constexpr int NL = Lds::NL;
     constexpr int W0 = Lds::W0;
     constexpr int PPT = (W0 * W0 + kTailThreads - 1) / kTailThreads;
+    constexpr int CN1 = kCoarseN + 1, CNU = (kCoarseN - 1) * (kCoarseN - 1);
+    constexpr int KPT = (CNU + 3) / 4;      // inverse entries per thread (four threads per row)
     __shared__ Lds s;
+    __shared__ LevelDev slev[NL > 1 ? NL - 1 : 1];
     const int c = blockIdx.x;
     const int mem = c / cpm;
+    // issue every global read first: the column, the level parameters, this
+    // thread's part of the coarse inverse (consumed only after the down sweep)
     const T* bcol = b + bmap.off(c);
     for (int q = threadIdx.x; q < W0 * W0; q += kTailThreads) {
         const int X = q % W0, Y = q / W0;
         s.b[q] = (X >= 1 && X <= M0 - 1 && Y >= 1 && Y <= M0 - 1) ? bcol[q] : T(0);
     }
+    constexpr int LW = sizeof(LevelDev) / sizeof(double);
+    for (int q = threadIdx.x; q < (NL - 1) * LW; q += kTailThreads)
+        ((double*)slev)[q] = ((const double*)(lev + mem * kMaxLevels + lvl0))[q];
+    const int row = threadIdx.x / 4, part = threadIdx.x % 4;
+    T arow[KPT];
+    {
+        const T* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad + (row < CNU ? row : 0) * kCoarsePad;
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) {
+            const int k = part + 4 * i;
+            arow[i] = (row < CNU && k < CNU) ? A[k] : T(0);
+        }
+    }
     __syncthreads();
     T d[PPT];
     // down: pre-smoothing from zero, residual, restriction
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < NL - 1; ++k) {
         const int m = M0 >> k, W = m + 1, mc = m / 2, C1 = mc + 1;
         T* B = s.b + tail_offset(M0, k);
         T* Xs = s.x + tail_offset(M0, k);
         T* Bc = s.b + tail_offset(M0, k + 1);
-        const LevelDev& L = lev[mem * kMaxLevels + lvl0 + k];
+        const LevelDev& L = slev[k];
         const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
         const T cr0 = T(L.pre[0][1]);
 #pragma unroll
@@ -364,36 +385,35 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __rest
     }
     // direct solve on the kCoarseN grid: four threads per interior unknown
     {
-        constexpr int N1 = kCoarseN + 1, NU = (kCoarseN - 1) * (kCoarseN - 1);
         const T* Bc = s.b + tail_offset(M0, NL - 1);
         T* Xc = s.x + tail_offset(M0, NL - 1);
-        const T* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad;
-        const int row = threadIdx.x / 4, part = threadIdx.x % 4;
         T acc = T(0);
-        if (row < NU) {
-            for (int k = part; k < NU; k += 4) {
+#pragma unroll
+        for (int i = 0; i < KPT; ++i) {
+            const int k = part + 4 * i;
+            if (k < CNU) {
                 const int ix = k % (kCoarseN - 1) + 1, iy = k / (kCoarseN - 1) + 1;
-                acc += A[row * kCoarsePad + k] * Bc[iy * N1 + ix];
+                acc += arow[i] * Bc[iy * CN1 + ix];
             }
         }
         acc += __shfl_xor(acc, 1, 64);
         acc += __shfl_xor(acc, 2, 64);
-        for (int q = threadIdx.x; q < N1 * N1; q += kTailThreads) Xc[q] = T(0);
+        for (int q = threadIdx.x; q < CN1 * CN1; q += kTailThreads) Xc[q] = T(0);
         __syncthreads();
-        if (row < NU && part == 0) {
+        if (row < CNU && part == 0) {
             const int ix = row % (kCoarseN - 1) + 1, iy = row / (kCoarseN - 1) + 1;
-            Xc[iy * N1 + ix] = acc;
+            Xc[iy * CN1 + ix] = acc;
         }
         __syncthreads();
     }
     // up: interpolation of the coarse correction, post-smoothing
-#pragma unroll 1
+#pragma unroll
     for (int k = NL - 2; k >= 0; --k) {
         const int m = M0 >> k, W = m + 1, C1 = m / 2 + 1;
         const T* B = s.b + tail_offset(M0, k);
         T* Xs = s.x + tail_offset(M0, k);
         const T* E = s.x + tail_offset(M0, k + 1);
-        const LevelDev& L = lev[mem * kMaxLevels + lvl0 + k];
+        const LevelDev& L = slev[k];
         const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
         for (int q = threadIdx.x; q < W * W; q += kTailThreads) {
             const int X = q % W, Y = q / W;
