@@ -10,6 +10,9 @@
 // V-cycle.  The smoother is the Chebyshev iteration
 //   r = b - A x;  d = c_d d + c_r D^{-1} r;  x = x + d
 // with per-member, per-level coefficients (c_d = 0 in the first step).
+// Tiles start at node 1 (the Dirichlet ring is zero), so 2^k - 1 interior
+// nodes per side take 2^k / tile tiles; the first tile row and column also
+// write the zero ring at index 0.
 #include "common.hpp"
 
 namespace sg {
@@ -22,7 +25,8 @@ __device__ __forceinline__ T st9(const T* s, int W, int i, T wc, T we, T wd) {
            wd * (s[i - W - 1] + s[i - W + 1] + s[i + W - 1] + s[i + W + 1]);
 }
 
-// down: coarse tile of TC x TC coarse nodes starting at (I0, J0).
+// down: coarse tile of TC x TC coarse nodes starting at (I0, J0) = 1 + TC (tx, ty),
+// owning the fine nodes [2 I0 - 1, 2 I0 + 2 TC - 1) per side.
 // Fine region: origin (2 I0 - 1 - NU, 2 J0 - 1 - NU), width W = 2 TC + 1 + 2 NU.
 template <typename T, int TC, int NU>
 __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restrict__ lev, int lvl,
@@ -32,7 +36,8 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
     __shared__ T sb[W * W], sxa[W * W], sxb[W * W], sd[W * W];
     const int c = blockIdx.y;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int I0 = tx * TC, J0 = ty * TC;
+    const int I0 = 1 + tx * TC, J0 = 1 + ty * TC;
+    const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;     // also write the ring at index 0
     const int FX0 = 2 * I0 - 1 - NU, FY0 = 2 * J0 - 1 - NU;
     const int mc = m / 2;
     const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
@@ -87,8 +92,8 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
     __syncthreads();
     // restriction (R = P^T: 1 centre, 1/2 edge partners, 1/4 corner partners)
     T* bco = bc + (int64_t)c * (mc + 1) * (mc + 1);
-    for (int q = threadIdx.x; q < TC * TC; q += blockDim.x) {
-        const int I = I0 + q % TC, J = J0 + q / TC;
+    for (int q = threadIdx.x; q < (TC + ex) * (TC + ey); q += blockDim.x) {
+        const int I = I0 - ex + q % (TC + ex), J = J0 - ey + q / (TC + ex);
         if (I > mc || J > mc) continue;
         T v = T(0);
         if (I >= 1 && I <= mc - 1 && J >= 1 && J <= mc - 1) {
@@ -99,17 +104,16 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
         }
         bco[J * (mc + 1) + I] = v;
     }
-    // smoothed x on the owned fine nodes [2 I0, 2 I0 + 2 TC)
+    // smoothed x on the owned fine nodes [2 I0 - 1, 2 I0 + 2 TC - 1)
     T* xcol = xo + xmap.off(c);
-    for (int q = threadIdx.x; q < 4 * TC * TC; q += blockDim.x) {
-        const int X = 2 * I0 + q % (2 * TC), Y = 2 * J0 + q / (2 * TC);
+    for (int q = threadIdx.x; q < (2 * TC + ex) * (2 * TC + ey); q += blockDim.x) {
+        const int X = 2 * I0 - 1 - ex + q % (2 * TC + ex), Y = 2 * J0 - 1 - ey + q / (2 * TC + ex);
         if (X > m || Y > m) continue;
-        const int i = X - FX0, j = Y - FY0;
-        xcol[Y * N1 + X] = cur[j * W + i];
+        xcol[Y * N1 + X] = (X == 0 || Y == 0) ? T(0) : cur[(Y - FY0) * W + (X - FX0)];
     }
 }
 
-// up: fine tile of TF x TF nodes starting at (X0, Y0); region with halo NU.
+// up: fine tile of TF x TF nodes starting at (X0, Y0) = 1 + TF (tx, ty); region with halo NU.
 template <typename T, int TF, int NU>
 __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict__ lev, int lvl,
                                                const T* __restrict__ xin, ColMap xinmap, const T* __restrict__ ec,
@@ -119,7 +123,8 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
     __shared__ T sb[W * W], sxa[W * W], sxb[W * W], sd[W * W];
     const int c = blockIdx.y;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int FX0 = tx * TF - NU, FY0 = ty * TF - NU;
+    const int FX0 = 1 + tx * TF - NU, FY0 = 1 + ty * TF - NU;
+    const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;
     const int mc = m / 2;
     const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
     const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
@@ -168,10 +173,10 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
         nxt = tmp;
     }
     T* out = xo + xomap.off(c);
-    for (int q = threadIdx.x; q < TF * TF; q += blockDim.x) {
-        const int X = FX0 + NU + q % TF, Y = FY0 + NU + q / TF;
+    for (int q = threadIdx.x; q < (TF + ex) * (TF + ey); q += blockDim.x) {
+        const int X = FX0 + NU - ex + q % (TF + ex), Y = FY0 + NU - ey + q / (TF + ex);
         if (X > m || Y > m) continue;
-        out[Y * N1 + X] = cur[(Y - FY0) * W + (X - FX0)];
+        out[Y * N1 + X] = (X == 0 || Y == 0) ? T(0) : cur[(Y - FY0) * W + (X - FX0)];
     }
 }
 
@@ -194,7 +199,8 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     const int vec = blockIdx.z;
     const int mem = op.mem_shared ? 0 : vec;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int FX0 = tx * TF - H, FY0 = ty * TF - H;
+    const int FX0 = 1 + tx * TF - H, FY0 = 1 + ty * TF - H;
+    const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;
     const int N1 = n + 1;
     const T h = T(1) / T(n);
     const T h2_36 = h * h / T(36);
@@ -242,10 +248,10 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     const T sc_ = var == 0 ? (j == 0 ? T(1) : T(md.hg)) : T(md.beta);
     const T f = T(1) / (sc_ * T(md.tau) * Dt);
     T* zc = z + (int64_t)vec * vstride + (int64_t)l * nodes;
-    for (int q = threadIdx.x; q < TF * TF; q += blockDim.x) {
-        const int X = FX0 + H + q % TF, Y = FY0 + H + q / TF;
+    for (int q = threadIdx.x; q < (TF + ex) * (TF + ey); q += blockDim.x) {
+        const int X = FX0 + H - ex + q % (TF + ex), Y = FY0 + H - ey + q / (TF + ex);
         if (X > n || Y > n) continue;
-        zc[Y * N1 + X] = f * cur[(Y - FY0) * W + (X - FX0)];
+        zc[Y * N1 + X] = (X == 0 || Y == 0) ? T(0) : f * cur[(Y - FY0) * W + (X - FX0)];
     }
 }
 
@@ -440,7 +446,7 @@ void tail_m(const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColM
 template <typename T, int H>
 void cheb_h(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, const ChebW& cw, hipStream_t st) {
     constexpr int TF = 32;
-    const int tx = (s.n + 1 + TF - 1) / TF;
+    const int tx = (s.n - 1 + TF - 1) / TF;
     const int ncols = 2 * s.nt * s.nxi;
     if (ncols > 65535 || nvec > 65535) throw Error(SG_ERR_INVALID, "Chebyshev: launch grid too large");
     dim3 grid(tx * tx, ncols, nvec);
@@ -455,7 +461,7 @@ template <typename T, int NU>
 void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc, int ncols,
              int cpm, hipStream_t st) {
     const int mc = m / 2;
-    const int tx = (mc + 1 + TCD - 1) / TCD;
+    const int tx = (mc - 1 + TCD - 1) / TCD;
     dim3 grid(tx * tx, ncols);
     hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, x, xmap, bc, cpm, tx);
 }
@@ -463,7 +469,7 @@ void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* x,
 template <typename T, int NU>
 void up_nu(int m, const LevelDev* lev, int lvl, const T* xin, ColMap xinmap, const T* ec, const T* b, ColMap bmap,
            T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st) {
-    const int tx = (m + 1 + TFU - 1) / TFU;
+    const int tx = (m - 1 + TFU - 1) / TFU;
     dim3 grid(tx * tx, ncols);
     hipLaunchKernelGGL((k_mg_up<T, TFU, NU>), grid, dim3(256), 0, st, m, lev, lvl, xin, xinmap, ec, b, bmap, xo,
                        xomap, cpm, tx);
