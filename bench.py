@@ -35,7 +35,8 @@ WORKLOADS = {
     "steady-512-M8-P3": dict(n=512, M=8, P=3, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(5,)),
 }
 DEFAULT = "steady-128-M6-P4"
-PROF_KIND = {"kkt_apply": 1, "mg_smooth": 2, "multidot": 3, "hgs_rhs": 4}
+PROF_KIND = {"kkt_apply": 1, "mg_smooth": 2, "multidot": 3, "hgs_rhs": 4, "arnoldi_update": 5}
+ARNOLDI = {"dcgs2": 0, "cgs2": 1}
 
 
 def make_problems(sgl, sg_inputs, wl):
@@ -137,6 +138,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no HIP graph replay)")
+    ap.add_argument("--arnoldi", default="dcgs2", choices=sorted(ARNOLDI),
+                    help="FGMRES orthogonalisation (delayed reorthogonalisation or Gram-Schmidt twice)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no multi-GPU path.",
@@ -154,7 +157,8 @@ def main():
 
     graphs = 0 if args.no_graphs else 1
     # headline: FP64 batch (the whole beta sweep) per step
-    opts = sgl.default_options(rtol=1e-8, use_graphs=graphs)
+    arn = ARNOLDI[args.arnoldi]
+    opts = sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn)
     dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream)
     nsolve = len(probs) * args.steps
     value = nsolve / dt
@@ -163,7 +167,7 @@ def main():
     # roofline: one more solve of the same batch with HIP events around every
     # launch of the profiled kernel (event pairs serialise the stream a little,
     # so this solve is not part of the timed steps)
-    _, pinfo = timed_solves(torch, sgl, probs, sgl.default_options(rtol=1e-8, profile=prof), 1, 0, stream)
+    _, pinfo = timed_solves(torch, sgl, probs, sgl.default_options(rtol=1e-8, profile=prof, arnoldi=arn), 1, 0, stream)
     pms, pbytes, plaunch = pinfo[0][0].prof_ms, pinfo[0][0].prof_bytes, pinfo[0][0].prof_launches
     achieved = pbytes / pms / 1e6 if pms > 0 else 0.0
     out = {
@@ -181,7 +185,8 @@ def main():
         "data": "synthetic (seeded Gaussian-bump targets, cosine random field)",
         "config": {"workload": args.workload, "n": wl["n"], "M": wl["M"], "P": wl["P"], "sigma": wl["sigma"],
                    "betas": list(wl["betas"]), "n_t": wl["n_t"], "batch": len(probs), "restart": 30,
-                   "rtol": 1e-8, "precision": "fp64", "graphs": bool(graphs)},
+                   "rtol": 1e-8, "precision": "fp64", "graphs": bool(graphs),
+                   "arnoldi": args.arnoldi},
         "iterations": iters[: len(probs)],
         "max_rel_res": rel,
         "roofline": {"bound": "hbm", "kernel": args.profile_kernel, "achieved": achieved, "peak": HBM_PEAK_GBPS,
@@ -190,7 +195,8 @@ def main():
                      "bytes_per_launch": pbytes / max(plaunch, 1)},
     }
     if not args.no_extras:
-        o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE, use_graphs=graphs)
+        o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE, use_graphs=graphs,
+                                  arnoldi=arn)
         dt32, inf32 = timed_solves(torch, sgl, probs, o32, args.steps, 1, stream)
         out["fp32_refine"] = {"value": nsolve / dt32, "unit": "solves/s", "dtype": "f32 operator/preconditioner, "
                               "f64 Arnoldi and refinement", "iterations": [i.iters for i in inf32[0]],
@@ -198,7 +204,7 @@ def main():
         single = []
         t_single = 0.0
         for p in probs:
-            dts, infs = timed_solves(torch, sgl, [p], sgl.default_options(rtol=1e-8, use_graphs=graphs), 1, 1,
+            dts, infs = timed_solves(torch, sgl, [p], sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn), 1, 1,
                                      stream)
             t_single += dts
             single.append(infs[0][0].iters)

@@ -115,21 +115,31 @@ typedef struct sg_problem {
  *                handle has a stream other than the default stream [1]
  *   verbose      print per-cycle residuals to stderr [0]
  *   profile      time one kernel's launches with HIP events during sg_solve
- *                (SG_PROF_* below) and report them in sg_solve_info [0] */
+ *                (SG_PROF_* below) and report them in sg_solve_info [0]
+ *   arnoldi      FGMRES orthogonalisation: SG_ARNOLDI_DCGS2 (classical
+ *                Gram-Schmidt with the reorthogonalisation of each basis
+ *                vector delayed to the next iteration: two passes over the
+ *                basis per iteration) or SG_ARNOLDI_CGS2 (classical
+ *                Gram-Schmidt applied twice: three passes) [SG_ARNOLDI_DCGS2] */
 typedef struct sg_options {
     double rtol;
     int32_t restart, max_iter, cheb_steps, truncation_r;
     int32_t gmg_pre, gmg_post, precision;
     double inner_rtol;
     int32_t use_graphs, verbose, profile;
+    int32_t arnoldi;
 } sg_options;
+
+#define SG_ARNOLDI_DCGS2 0
+#define SG_ARNOLDI_CGS2  1
 
 /* Kernels that sg_options.profile can time (HIP events around every launch). */
 #define SG_PROF_NONE        0
 #define SG_PROF_KKT_APPLY   1   /* fused KKT apply (two SG operator applies + mass terms) */
 #define SG_PROF_MG_SMOOTH   2   /* multigrid Chebyshev smoothing step, finest level */
-#define SG_PROF_MULTIDOT    3   /* Arnoldi multi-dot (first Gram-Schmidt pass) */
+#define SG_PROF_MULTIDOT    3   /* Arnoldi dot-product pass (read-only pass over the basis) */
 #define SG_PROF_HGS_RHS     4   /* hierarchical Gauss-Seidel off-level right-hand side */
+#define SG_PROF_ARNOLDI_UPD 5   /* Arnoldi update pass (DCGS2: finalise V_j, next candidate) */
 
 /* Per-solve report. */
 typedef struct sg_solve_info {

@@ -20,6 +20,8 @@ SG_ERR_NOMEM, SG_ERR_HIP, SG_ERR_CANCELLED, SG_ERR_UNKNOWN = -4, -5, -6, -7
 SG_FP64, SG_FP32 = 0, 1
 SG_PREC_FP64, SG_PREC_FP32_REFINE = 0, 1
 SG_PROF_NONE, SG_PROF_KKT_APPLY, SG_PROF_MG_SMOOTH, SG_PROF_MULTIDOT, SG_PROF_HGS_RHS = 0, 1, 2, 3, 4
+SG_PROF_ARNOLDI_UPD = 5
+SG_ARNOLDI_DCGS2, SG_ARNOLDI_CGS2 = 0, 1
 
 _DP = C.POINTER(C.c_double)
 
@@ -34,7 +36,8 @@ class sg_options(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("cheb_steps", C.c_int32), ("truncation_r", C.c_int32), ("gmg_pre", C.c_int32),
                 ("gmg_post", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
-                ("use_graphs", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32)]
+                ("use_graphs", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
+                ("arnoldi", C.c_int32)]
 
 
 class sg_solve_info(C.Structure):

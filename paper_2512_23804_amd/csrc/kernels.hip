@@ -461,6 +461,7 @@ __global__ void k_zero_ring(T* x, int n, int64_t ncols) {
 // --------------------------------------------------------------------------
 constexpr int RB = 256;      // threads per reduction block
 constexpr int MAXV = 32;     // basis vectors per multi-vector launch
+// partial sums: partial[(mem*kSlots + slot)*nblk + blk] (kSlots per member)
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -472,7 +473,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int NA>
 __device__ __forceinline__ void block_reduce_store(const double* acc, int nv, double* partial, int mem, int nvmax,
                                                    int nblk) {
-    __shared__ double red[RB / 64][MAXV + 1];
+    __shared__ double red[RB / 64][kSlots + 1];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
@@ -531,7 +532,7 @@ __global__ __launch_bounds__(RB) void k_multidot(const double* __restrict__ V, i
         for (int i = 0; i < NV; ++i)
             if (i < nv) acc[i] += Vm[i * vstride + e] * we;
     }
-    block_reduce_store<NV>(acc, nv, partial, mem, MAXV, nblk);
+    block_reduce_store<NV>(acc, nv, partial, mem, kSlots, nblk);
 }
 
 // w1 = w - sum_i h_i V_i (written to w), partial[i] = V_i . w1
@@ -563,7 +564,7 @@ __global__ __launch_bounds__(RB) void k_cgs_update_dot(const double* __restrict_
 #pragma unroll
         for (int i = 0; i < NV; ++i) acc[i] += v[i] * we;
     }
-    block_reduce_store<NV>(acc, nv, partial, mem, MAXV, nblk);
+    block_reduce_store<NV>(acc, nv, partial, mem, kSlots, nblk);
 }
 
 // out = w - sum_i h_i V_i, partial[0] = ||out||^2
@@ -591,16 +592,123 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
         om[e] = we;
         acc[0] += we * we;
     }
-    block_reduce_store<1>(acc, 1, partial, mem, MAXV, nblk);
+    block_reduce_store<1>(acc, 1, partial, mem, kSlots, nblk);
 }
 
-// out[mem*out_stride + out_offset + i] = sum_blk partial[(mem*MAXV + i)*nblk + blk]
+// ---- Arnoldi with delayed reorthogonalization (DCGS2) ----
+// Slot j of the basis holds the candidate u (one Gram-Schmidt pass, scaled by
+// an estimate of its norm) until the next iteration finalises it.
+//
+// Dots pass, with w: slots [0, nv) a_i = V_i.u, [nv, 2nv) t_i = V_i.w,
+// 2nv: u.u, 2nv+1: u.w, 2nv+2: w.w; without w: [0, nv) a_i, nv: u.u.
+// u is basis slot nv.  Members with neither flag set are skipped.
+template <int NV, bool WITH_W>
+__global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, int64_t vstride, int nv,
+                                                  const double* __restrict__ w, int64_t n, int64_t mstride,
+                                                  const int* __restrict__ active, const int* __restrict__ pending,
+                                                  double* __restrict__ partial, int nblk) {
+    const int mem = blockIdx.y;
+    if (!active[mem] && !pending[mem]) return;      // uniform per block, before any barrier
+    int64_t lo, hi;
+    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    constexpr int NA = WITH_W ? 2 * NV + 3 : NV + 1;
+    double acc[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i] = 0.0;
+    const double* Vm = V + mem * mstride;
+    const double* um = Vm + nv * vstride;
+    const double* wm = w + mem * mstride;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+        const double ue = ld_stream(um + e);
+        const double we = WITH_W ? ld_stream(wm + e) : 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nv) {
+                const double v = ld_stream(Vm + i * vstride + e);
+                acc[i] += v * ue;
+                if (WITH_W) acc[NV + i] += v * we;
+            }
+        }
+        if (WITH_W) {
+            acc[2 * NV] += ue * ue;
+            acc[2 * NV + 1] += ue * we;
+            acc[2 * NV + 2] += we * we;
+        } else {
+            acc[NV] += ue * ue;
+        }
+    }
+    __shared__ double red[RB / 64][kSlots + 1];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        int slot;
+        if (WITH_W)
+            slot = k < NV ? (k < nv ? k : -1) : k < 2 * NV ? (k - NV < nv ? nv + k - NV : -1) : 2 * nv + (k - 2 * NV);
+        else
+            slot = k < NV ? (k < nv ? k : -1) : nv;
+        if (slot >= 0) {
+            const double sm = wave_sum(acc[k]);
+            if (lane == 0) red[wave][slot] = sm;
+        }
+    }
+    __syncthreads();
+    const int nslots = WITH_W ? 2 * nv + 3 : nv + 1;
+    if ((int)threadIdx.x < nslots) {
+        double sm = 0.0;
+        for (int q = 0; q < RB / 64; ++q) sm += red[q][threadIdx.x];
+        partial[((int64_t)mem * kSlots + threadIdx.x) * nblk + blockIdx.x] = sm;
+    }
+}
+
+// Update pass: V_nv = (u - sum_i a_i V_i) / rho (in place over u, slot nv) and
+// slot nv+1 = (w - sum_i t_i V_i - c V_nv) / nu, with a_i, t_i from the dots
+// (dots[mem*kSlots + i], dots[mem*kSlots + nv + i]) and scal[mem*4 + 0..2] =
+// (1/rho, c, 1/nu).
+template <int NV>
+__global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int64_t vstride, int nv,
+                                                    const double* __restrict__ w, int64_t n, int64_t mstride,
+                                                    const double* __restrict__ dots, const double* __restrict__ scal,
+                                                    const int* __restrict__ active, int nblk) {
+    const int mem = blockIdx.y;
+    if (!active[mem]) return;
+    int64_t lo, hi;
+    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    double a[NV], t[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        a[i] = i < nv ? dots[mem * kSlots + i] : 0.0;
+        t[i] = i < nv ? dots[mem * kSlots + nv + i] : 0.0;
+    }
+    const double inv_rho = scal[mem * 4 + 0], c = scal[mem * 4 + 1], inv_nu = scal[mem * 4 + 2];
+    double* Vm = V + mem * mstride;
+    double* um = Vm + nv * vstride;
+    double* un = um + vstride;
+    const double* wm = w + mem * mstride;
+    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+        const double ue = ld_stream(um + e);
+        const double we = ld_stream(wm + e);
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nv) {
+                const double v = ld_stream(Vm + i * vstride + e);
+                s1 += a[i] * v;
+                s2 += t[i] * v;
+            }
+        }
+        const double vj = (ue - s1) * inv_rho;
+        um[e] = vj;
+        un[e] = (we - s2 - c * vj) * inv_nu;
+    }
+}
+
+// out[mem*out_stride + out_offset + i] = sum_blk partial[(mem*kSlots + i)*nblk + blk]
 __global__ __launch_bounds__(RB) void k_reduce_partials(const double* __restrict__ partial, int nblk, int nv,
                                                         double* __restrict__ out, int out_stride, int out_offset) {
     const int i = blockIdx.x, mem = blockIdx.y;
     __shared__ double red[RB];
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RB) s += partial[((int64_t)mem * MAXV + i) * nblk + b];
+    for (int b = threadIdx.x; b < nblk; b += RB) s += partial[((int64_t)mem * kSlots + i) * nblk + b];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int o = RB / 2; o > 0; o >>= 1) {
@@ -655,7 +763,7 @@ __global__ __launch_bounds__(RB) void k_sub_norm(const double* __restrict__ b, d
         r[mem * mstride + e] = v;
         acc[0] += v * v;
     }
-    block_reduce_store<1>(acc, 1, partial, mem, MAXV, nblk);
+    block_reduce_store<1>(acc, 1, partial, mem, kSlots, nblk);
 }
 
 __global__ __launch_bounds__(RB) void k_norm(const double* __restrict__ x, int64_t n, int64_t mstride,
@@ -668,7 +776,7 @@ __global__ __launch_bounds__(RB) void k_norm(const double* __restrict__ x, int64
         const double v = x[mem * mstride + e];
         acc[0] += v * v;
     }
-    block_reduce_store<1>(acc, 1, partial, mem, MAXV, nblk);
+    block_reduce_store<1>(acc, 1, partial, mem, kSlots, nblk);
 }
 
 __global__ void k_axpby(double a, const double* x, double b, double* y, int64_t n) {
@@ -722,6 +830,83 @@ __global__ void k_arnoldi_finish(KrylovDev k, int restart, int j, int nmem) {
     k.resid[mem] = fabs(g[j + 1]);
 }
 
+// Givens rotations 0..j-1 applied to a column, rotation j formed from (col[j], col[j+1]).
+__device__ void givens_column(double* col, double* cs, double* sn, double* g, int j) {
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = cs[i] * a + sn[i] * b;
+        col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = hypot(a, b);
+    const double c = den > 0.0 ? a / den : 1.0;
+    const double s = den > 0.0 ? b / den : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+}
+
+// DCGS2 bookkeeping of iteration j (mode 0) or of the last column (mode 1).
+// Commit: the candidate u_j of the previous iteration is u_j = sum_i a_i V_i +
+// rho V_j (rho^2 = u.u - |a|^2), so column j-1 (raw entries t, c, nu) becomes
+// [t + nu a, c + nu a_{j-1}, nu rho] and gets its Givens rotation.
+// Provisional (mode 0, active members): column j = [t, c, nu] with
+// c = (u.w - a.t) / rho and nu^2 = w.w - |t|^2 - c^2 (one Gram-Schmidt pass);
+// its rotation on a copy gives the residual estimate used to stop.
+__global__ void k_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem) {
+    const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mem >= nmem) return;
+    const int ld = restart + 1;
+    const int nv = j;
+    const double* D = k.dots + (int64_t)mem * kSlots;
+    double* H = k.H + (int64_t)mem * ld * restart;
+    double* cs = k.cs + mem * restart;
+    double* sn = k.sn + mem * restart;
+    double* g = k.g + mem * ld;
+    double* sc = k.scal + mem * 4;
+    double inv_rho = 1.0;
+    if (j >= 1 && k.pending[mem]) {
+        const double alpha = mode ? D[nv] : D[2 * nv];
+        double a2 = 0.0;
+        for (int i = 0; i < nv; ++i) a2 += D[i] * D[i];
+        const double rho = sqrt(fmax(alpha - a2, 0.0));
+        const double nu = sc[3];
+        double* col = H + (int64_t)(j - 1) * ld;
+        for (int i = 0; i < nv; ++i) col[i] += nu * D[i];
+        col[j] = nu * rho;
+        givens_column(col, cs, sn, g, j - 1);
+        k.resid[mem] = fabs(g[j]);
+        inv_rho = rho > 0.0 ? 1.0 / rho : 0.0;
+        k.pending[mem] = 0;
+    }
+    if (mode != 0 || !k.active[mem]) return;
+    double at = 0.0, t2 = 0.0;
+    for (int i = 0; i < nv; ++i) {
+        at += D[i] * D[nv + i];
+        t2 += D[nv + i] * D[nv + i];
+    }
+    const double c = (D[2 * nv + 1] - at) * inv_rho;
+    const double nu = sqrt(fmax(D[2 * nv + 2] - t2 - c * c, 0.0));
+    double* col = H + (int64_t)j * ld;
+    for (int i = 0; i < nv; ++i) col[i] = D[nv + i];
+    col[j] = c;
+    col[j + 1] = nu;
+    // provisional rotation: entry j of the column after rotations 0..j-1
+    double xr = col[0];
+    for (int i = 0; i < j; ++i) xr = -sn[i] * xr + cs[i] * col[i + 1];
+    const double den = hypot(xr, nu);
+    const double pr = den > 0.0 ? fabs(nu / den * g[j]) : 0.0;
+    k.resid[mem] = pr;
+    sc[0] = inv_rho;
+    sc[1] = c;
+    sc[2] = nu > 0.0 ? 1.0 / nu : 0.0;
+    sc[3] = nu;
+    k.pending[mem] = 1;
+}
+
 __global__ void k_cycle_start(KrylovDev k, int restart, const double* beta0sq, int nmem) {
     const int mem = blockIdx.x * blockDim.x + threadIdx.x;
     if (mem >= nmem) return;
@@ -732,6 +917,8 @@ __global__ void k_cycle_start(KrylovDev k, int restart, const double* beta0sq, i
     g[0] = b;
     k.nrm[mem] = b > 0.0 ? 1.0 / b : 0.0;
     k.resid[mem] = b;
+    k.pending[mem] = 0;
+    k.scal[mem * 4 + 3] = 1.0;     // V_0 = r / ||r|| is final as written
 }
 
 // y = R^{-1} g on the leading jend x jend block (upper triangular after Givens).
@@ -899,6 +1086,46 @@ void launch_cgs_update_norm(const double* V, int64_t vstride, int nv, const doub
     if (nv > MAXV) throw Error(SG_ERR_INVALID, "cgs: too many vectors");
     SG_NV_DISPATCH(k_cgs_update_norm, nv, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, h, hstride, w, out, n,
                    mstride, partial, nblk);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_dcgs_dots(const double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem,
+                      int64_t mstride, const int* active, const int* pending, double* partial, int nblk,
+                      hipStream_t st) {
+    if (nv > (w ? MAXV - 2 : MAXV)) throw Error(SG_ERR_INVALID, "dcgs: too many vectors");
+    const dim3 g(nblk, nmem), b(RB);
+    if (w) {
+        if (nv <= 4)
+            hipLaunchKernelGGL((k_dcgs_dots<4, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        else if (nv <= 8)
+            hipLaunchKernelGGL((k_dcgs_dots<8, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        else if (nv <= 16)
+            hipLaunchKernelGGL((k_dcgs_dots<16, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        else
+            hipLaunchKernelGGL((k_dcgs_dots<32, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+    } else {
+        if (nv <= 4)
+            hipLaunchKernelGGL((k_dcgs_dots<4, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        else if (nv <= 8)
+            hipLaunchKernelGGL((k_dcgs_dots<8, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        else if (nv <= 16)
+            hipLaunchKernelGGL((k_dcgs_dots<16, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        else
+            hipLaunchKernelGGL((k_dcgs_dots<32, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+    }
+    SG_HIP(hipGetLastError());
+}
+
+void launch_dcgs_update(double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem, int64_t mstride,
+                        const double* dots, const double* scal, const int* active, int nblk, hipStream_t st) {
+    if (nv > MAXV - 2) throw Error(SG_ERR_INVALID, "dcgs: too many vectors");
+    SG_NV_DISPATCH(k_dcgs_update, nv, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, w, n, mstride, dots, scal,
+                   active, nblk);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_dcgs_finish, dim3((nmem + 63) / 64), dim3(64), 0, st, k, restart, j, mode, nmem);
     SG_HIP(hipGetLastError());
 }
 

@@ -227,7 +227,7 @@ struct Krylov {
     void* Z;               // [m][B][N] (double or float)
     bool z32;
     double* w;             // [B][N]
-    double* partial;       // [B][32][nblk]
+    double* partial;       // [B][kSlots][nblk]
     KrylovDev kd;
     int* d_jend;
     float* v32;            // [B][N] FP32 staging (inner FP32 mode)
@@ -243,7 +243,7 @@ struct Krylov {
         V = h.ws.get_t<double>("kV", (size_t)(m + 1) * B * N);
         Z = z32 ? (void*)h.ws.get_t<float>("kZ32", (size_t)m * B * N) : (void*)h.ws.get_t<double>("kZ", (size_t)m * B * N);
         w = h.ws.get_t<double>("kw", (size_t)B * N);
-        partial = h.ws.get_t<double>("kpart", (size_t)B * 32 * nblk);
+        partial = h.ws.get_t<double>("kpart", (size_t)B * kSlots * nblk);
         const int ld = m + 1;
         kd.H = h.ws.get_t<double>("kH", (size_t)B * ld * m);
         kd.cs = h.ws.get_t<double>("kcs", (size_t)B * m);
@@ -255,6 +255,9 @@ struct Krylov {
         kd.y = h.ws.get_t<double>("ky", (size_t)B * m);
         kd.resid = h.ws.get_t<double>("kres", (size_t)B);
         kd.active = h.ws.get_t<int>("kact", (size_t)B);
+        kd.dots = h.ws.get_t<double>("kdots", (size_t)B * kSlots);
+        kd.scal = h.ws.get_t<double>("kscal", (size_t)B * 4);
+        kd.pending = h.ws.get_t<int>("kpend", (size_t)B);
         d_jend = h.ws.get_t<int>("kjend", (size_t)B);
         v32 = z32 ? h.ws.get_t<float>("kv32", (size_t)B * N) : nullptr;
         w32 = z32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
@@ -351,20 +354,35 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
         launch_cycle_start(K.kd, m, K.kd.nrm, B, st);    // kd.nrm holds ||r||^2 from residual()
         launch_copy_scale_rows(r, K.Vi(0), K.kd.nrm, N, B, N, st);
-        // one FGMRES iteration: preconditioner, KKT apply, CGS2 Arnoldi, Givens
+        const bool dcgs = h.opt.arnoldi == SG_ARNOLDI_DCGS2;
+        const int64_t vs = (int64_t)B * N;
+        // one FGMRES iteration: preconditioner, KKT apply, Arnoldi, Givens
         auto iteration = [&](int j) {
             K.apply_prec(j);
             K.apply_op_z(j);
+            if (dcgs) {
+                // DCGS2: slot j holds the candidate u_j; one read-only pass gives the
+                // reorthogonalisation of u_j and the projections of w, one update
+                // pass finalises V_j and writes the next candidate u_{j+1}
+                bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
+                launch_dcgs_dots(K.V, vs, j, K.w, N, B, N, K.kd.active, K.kd.pending, K.partial, K.nblk, st);
+                if (tp) prof_end(h, st, 8.0 * (j + 2) * (double)B * N);
+                launch_reduce_partials(K.partial, K.nblk, 2 * j + 3, B, K.kd.dots, kSlots, 0, st);
+                launch_dcgs_finish(K.kd, m, j, 0, B, st);
+                tp = prof_begin(h, SG_PROF_ARNOLDI_UPD, st);
+                launch_dcgs_update(K.V, vs, j, K.w, N, B, N, K.kd.dots, K.kd.scal, K.kd.active, K.nblk, st);
+                if (tp) prof_end(h, st, 8.0 * (j + 4) * (double)B * N);
+                return;
+            }
             const int nv = j + 1;
             // CGS2: h1 = V^T w; w1 = w - V h1; h2 = V^T w1; w2 = w1 - V h2
             const bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
-            launch_multidot(K.V, (int64_t)B * N, nv, K.w, N, B, N, K.partial, K.nblk, st);
+            launch_multidot(K.V, vs, nv, K.w, N, B, N, K.partial, K.nblk, st);
             if (tp) prof_end(h, st, 8.0 * (nv + 1) * (double)B * N);
             launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h1, m + 1, 0, st);
-            launch_cgs_update_dot(K.V, (int64_t)B * N, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
+            launch_cgs_update_dot(K.V, vs, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
             launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h2, m + 1, 0, st);
-            launch_cgs_update_norm(K.V, (int64_t)B * N, nv, K.kd.h2, m + 1, K.w, K.Vi(j + 1), N, B, N, K.partial,
-                                   K.nblk, st);
+            launch_cgs_update_norm(K.V, vs, nv, K.kd.h2, m + 1, K.w, K.Vi(j + 1), N, B, N, K.partial, K.nblk, st);
             launch_reduce_partials(K.partial, K.nblk, 1, B, K.kd.nrm, 1, 0, st);
             launch_arnoldi_finish(K.kd, m, j, B, st);
             launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
@@ -376,7 +394,9 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
             h.graphs.clear();
             h.graphs.gen = h.ws.generation();
         }
+        int jlast = -1;
         for (int j = 0; j < m; ++j) {
+            jlast = j;
             if (graphs && h.graphs.warm[zk]) {
                 auto key = std::make_pair(j, zk);
                 auto it = h.graphs.exec.find(key);
@@ -419,6 +439,13 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
                 for (int q = 0; q < B; ++q) pinned_i[q] = active[q];
                 SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
             }
+        }
+        if (dcgs && jlast >= 0) {
+            // reorthogonalise the last candidates (slot jlast + 1) of the members whose
+            // last column is still pending, and commit that column
+            launch_dcgs_dots(K.V, vs, jlast + 1, nullptr, N, B, N, K.kd.active, K.kd.pending, K.partial, K.nblk, st);
+            launch_reduce_partials(K.partial, K.nblk, jlast + 2, B, K.kd.dots, kSlots, 0, st);
+            launch_dcgs_finish(K.kd, m, jlast + 1, 1, B, st);
         }
         for (int q = 0; q < B; ++q) pinned_i[B + q] = jend[q];
         SG_HIP(hipMemcpyAsync(K.d_jend, pinned_i + B, sizeof(int) * B, hipMemcpyHostToDevice, st));

@@ -169,14 +169,17 @@ def test_precond_multi_rhs_shares_one_member():
         assert rel_max(canonical_to_kkt(sg, Z[i]), precond.precond_apply(sg, rs[i], inner)) < 1e-12
 
 
+@pytest.mark.parametrize("arnoldi", [0, 1])
 @pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[2], SHAPES[3]])
-def test_solve_matches_direct(shape):
+def test_solve_matches_direct(shape, arnoldi):
+    """FGMRES with either orthogonalisation (0: delayed reorthogonalisation,
+    1: Gram-Schmidt twice) reaches the oracle's direct solution."""
     n, M, P, sigma, beta, gamma, nt = shape
     dev = _dev()
-    _say(f"solve {shape}")
+    _say(f"solve {shape} arnoldi={arnoldi}")
     prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, y0=nt > 1)
     sg = kkt.setup(prob)
-    h = _setup([kw], rtol=1e-12, max_iter=400)
+    h = _setup([kw], rtol=1e-12, max_iter=400, arnoldi=arnoldi)
     xd = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
     rc, info = h.solve(xd)
     torch.cuda.synchronize()
@@ -224,6 +227,24 @@ def test_batch_results_equal_alone():
             rca, infa = ha.solve(xa)
             assert rca == 0 and infa[0].iters == infos[i].iters
             assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
+
+
+def test_delayed_reorthogonalisation_tracks_cgs2():
+    """Across restarts and a hard beta, the delayed-reorthogonalisation Arnoldi
+    needs about the iterations of Gram-Schmidt twice and reaches the same
+    true residual; a short restart exercises the end-of-cycle commit."""
+    dev = _dev()
+    _say("dcgs2 vs cgs2")
+    prob, kw = make_case(32, 4, 3, 0.3, 1e-6, seed=5)
+    for restart in (30, 7):
+        its = []
+        for arnoldi in (0, 1):
+            h = _setup([kw], rtol=1e-10, restart=restart, max_iter=600, arnoldi=arnoldi)
+            x = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+            rc, info = h.solve(x)
+            assert rc == 0 and info[0].converged == 1 and info[0].rel_res_true <= 1e-10
+            its.append(info[0].iters)
+        assert abs(its[0] - its[1]) <= 2 + its[1] // 10, its
 
 
 @pytest.mark.parametrize("precision", [0, 1])
