@@ -601,62 +601,64 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
 //
 // Dots pass, with w: slots [0, nv) a_i = V_i.u, [nv, 2nv) t_i = V_i.w,
 // 2nv: u.u, 2nv+1: u.w, 2nv+2: w.w; without w: [0, nv) a_i, nv: u.u.
-// u is basis slot nv.  Members with neither flag set are skipped.
-template <int NV, bool WITH_W>
+// u is basis slot nv.  The block's four wavefronts split the basis vectors
+// (vector i goes to wavefront i mod 4, at most NPW each) and each walks the
+// block's whole chunk, so a lane carries at most 2 NPW + 1 sums and keeps many
+// loads in flight; u and w are re-read by the four wavefronts from cache.
+// Members with neither flag set are skipped.
+template <int NPW, bool WITH_W>
 __global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, int64_t vstride, int nv,
                                                   const double* __restrict__ w, int64_t n, int64_t mstride,
                                                   const int* __restrict__ active, const int* __restrict__ pending,
                                                   double* __restrict__ partial, int nblk) {
     const int mem = blockIdx.y;
-    if (!active[mem] && !pending[mem]) return;      // uniform per block, before any barrier
+    if (!active[mem] && !pending[mem]) return;
     int64_t lo, hi;
     chunk_range(n, nblk, blockIdx.x, lo, hi);
-    constexpr int NA = WITH_W ? 2 * NV + 3 : NV + 1;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    // the wavefront's scalar product: wave 1 u.u (also without w), wave 2 u.w, wave 3 w.w
+    const int sdot = WITH_W ? wave : (wave == 1 ? 1 : 0);
+    constexpr int NA = WITH_W ? 2 * NPW + 1 : NPW + 1;
     double acc[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = 0.0;
     const double* Vm = V + mem * mstride;
     const double* um = Vm + nv * vstride;
     const double* wm = w + mem * mstride;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
-        const double ue = ld_stream(um + e);
-        const double we = WITH_W ? ld_stream(wm + e) : 0.0;
+    for (int64_t e = lo + lane; e < hi; e += 64) {
+        const double ue = um[e];
+        const double we = WITH_W ? wm[e] : 0.0;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
+        for (int k = 0; k < NPW; ++k) {
+            const int i = wave + 4 * k;
             if (i < nv) {
                 const double v = ld_stream(Vm + i * vstride + e);
-                acc[i] += v * ue;
-                if (WITH_W) acc[NV + i] += v * we;
+                acc[k] += v * ue;
+                if (WITH_W) acc[NPW + k] += v * we;
             }
         }
-        if (WITH_W) {
-            acc[2 * NV] += ue * ue;
-            acc[2 * NV + 1] += ue * we;
-            acc[2 * NV + 2] += we * we;
-        } else {
-            acc[NV] += ue * ue;
-        }
+        if (sdot == 1) acc[NA - 1] += ue * ue;
+        if (WITH_W && sdot == 2) acc[NA - 1] += ue * we;
+        if (WITH_W && sdot == 3) acc[NA - 1] += we * we;
     }
-    __shared__ double red[RB / 64][kSlots + 1];
-    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    double* pm = partial + (int64_t)mem * kSlots * nblk + blockIdx.x;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) {
-        int slot;
-        if (WITH_W)
-            slot = k < NV ? (k < nv ? k : -1) : k < 2 * NV ? (k - NV < nv ? nv + k - NV : -1) : 2 * nv + (k - 2 * NV);
-        else
-            slot = k < NV ? (k < nv ? k : -1) : nv;
-        if (slot >= 0) {
-            const double sm = wave_sum(acc[k]);
-            if (lane == 0) red[wave][slot] = sm;
+    for (int k = 0; k < NPW; ++k) {
+        const int i = wave + 4 * k;
+        if (i < nv) {
+            const double a = wave_sum(acc[k]);
+            if (lane == 0) pm[(int64_t)i * nblk] = a;
+            if (WITH_W) {
+                const double t = wave_sum(acc[NPW + k]);
+                if (lane == 0) pm[(int64_t)(nv + i) * nblk] = t;
+            }
         }
     }
-    __syncthreads();
-    const int nslots = WITH_W ? 2 * nv + 3 : nv + 1;
-    if ((int)threadIdx.x < nslots) {
-        double sm = 0.0;
-        for (int q = 0; q < RB / 64; ++q) sm += red[q][threadIdx.x];
-        partial[((int64_t)mem * kSlots + threadIdx.x) * nblk + blockIdx.x] = sm;
+    if (sdot >= 1) {
+        const double d = wave_sum(acc[NA - 1]);
+        const int slot = WITH_W ? 2 * nv + sdot - 1 : nv;
+        if (lane == 0) pm[(int64_t)slot * nblk] = d;
     }
 }
 
@@ -670,15 +672,15 @@ __global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int6
                                                     const double* __restrict__ dots, const double* __restrict__ scal,
                                                     const int* __restrict__ active, int nblk) {
     const int mem = blockIdx.y;
-    if (!active[mem]) return;
+    if (!active[mem]) return;                       // uniform per block, before the barrier
     int64_t lo, hi;
     chunk_range(n, nblk, blockIdx.x, lo, hi);
-    double a[NV], t[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        a[i] = i < nv ? dots[mem * kSlots + i] : 0.0;
-        t[i] = i < nv ? dots[mem * kSlots + nv + i] : 0.0;
+    __shared__ double a[NV], t[NV];                 // broadcast reads; keeps the lanes' registers for loads
+    if ((int)threadIdx.x < NV) {
+        a[threadIdx.x] = (int)threadIdx.x < nv ? dots[mem * kSlots + threadIdx.x] : 0.0;
+        t[threadIdx.x] = (int)threadIdx.x < nv ? dots[mem * kSlots + nv + threadIdx.x] : 0.0;
     }
+    __syncthreads();
     const double inv_rho = scal[mem * 4 + 0], c = scal[mem * 4 + 1], inv_nu = scal[mem * 4 + 2];
     double* Vm = V + mem * mstride;
     double* um = Vm + nv * vstride;
@@ -1094,25 +1096,21 @@ void launch_dcgs_dots(const double* V, int64_t vstride, int nv, const double* w,
                       hipStream_t st) {
     if (nv > (w ? MAXV - 2 : MAXV)) throw Error(SG_ERR_INVALID, "dcgs: too many vectors");
     const dim3 g(nblk, nmem), b(RB);
+#define SG_DOTS(NPW, WW)                                                                                        \
+    hipLaunchKernelGGL((k_dcgs_dots<NPW, WW>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, \
+                       nblk)
     if (w) {
-        if (nv <= 4)
-            hipLaunchKernelGGL((k_dcgs_dots<4, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
-        else if (nv <= 8)
-            hipLaunchKernelGGL((k_dcgs_dots<8, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
-        else if (nv <= 16)
-            hipLaunchKernelGGL((k_dcgs_dots<16, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
-        else
-            hipLaunchKernelGGL((k_dcgs_dots<32, true>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        if (nv <= 4) SG_DOTS(1, true);
+        else if (nv <= 8) SG_DOTS(2, true);
+        else if (nv <= 16) SG_DOTS(4, true);
+        else SG_DOTS(8, true);
     } else {
-        if (nv <= 4)
-            hipLaunchKernelGGL((k_dcgs_dots<4, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
-        else if (nv <= 8)
-            hipLaunchKernelGGL((k_dcgs_dots<8, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
-        else if (nv <= 16)
-            hipLaunchKernelGGL((k_dcgs_dots<16, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
-        else
-            hipLaunchKernelGGL((k_dcgs_dots<32, false>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, nblk);
+        if (nv <= 4) SG_DOTS(1, false);
+        else if (nv <= 8) SG_DOTS(2, false);
+        else if (nv <= 16) SG_DOTS(4, false);
+        else SG_DOTS(8, false);
     }
+#undef SG_DOTS
     SG_HIP(hipGetLastError());
 }
 
