@@ -599,6 +599,15 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
 // Slot j of the basis holds the candidate u (one Gram-Schmidt pass, scaled by
 // an estimate of its norm) until the next iteration finalises it.
 //
+#ifndef SG_DOTS_U
+#define SG_DOTS_U 4
+#endif
+#ifndef SG_UPD_U
+#define SG_UPD_U 2
+#endif
+constexpr int kDotsU = SG_DOTS_U;   // elements per lane per trip, dots pass
+constexpr int kUpdU = SG_UPD_U;     // elements per lane per trip, update pass
+
 // Dots pass, with w: slots [0, nv) a_i = V_i.u, [nv, 2nv) t_i = V_i.w,
 // 2nv: u.u, 2nv+1: u.w, 2nv+2: w.w; without w: [0, nv) a_i, nv: u.u.
 // u is basis slot nv.  The block's four wavefronts split the basis vectors
@@ -626,7 +635,34 @@ __global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, 
     const double* Vm = V + mem * mstride;
     const double* um = Vm + nv * vstride;
     const double* wm = w + mem * mstride;
-    for (int64_t e = lo + lane; e < hi; e += 64) {
+    int64_t e = lo + lane;
+    for (; e + (kDotsU - 1) * 64 < hi; e += kDotsU * 64) {
+        double ue[kDotsU], we[kDotsU];
+#pragma unroll
+        for (int u = 0; u < kDotsU; ++u) {
+            ue[u] = um[e + u * 64];
+            we[u] = WITH_W ? wm[e + u * 64] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NPW; ++k) {
+            const int i = wave + 4 * k;
+            if (i < nv) {
+#pragma unroll
+                for (int u = 0; u < kDotsU; ++u) {
+                    const double v = ld_stream(Vm + i * vstride + e + u * 64);
+                    acc[k] += v * ue[u];
+                    if (WITH_W) acc[NPW + k] += v * we[u];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kDotsU; ++u) {
+            if (sdot == 1) acc[NA - 1] += ue[u] * ue[u];
+            if (WITH_W && sdot == 2) acc[NA - 1] += ue[u] * we[u];
+            if (WITH_W && sdot == 3) acc[NA - 1] += we[u] * we[u];
+        }
+    }
+    for (; e < hi; e += 64) {
         const double ue = um[e];
         const double we = WITH_W ? wm[e] : 0.0;
 #pragma unroll
@@ -686,7 +722,35 @@ __global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int6
     double* um = Vm + nv * vstride;
     double* un = um + vstride;
     const double* wm = w + mem * mstride;
-    for (int64_t e = lo + threadIdx.x; e < hi; e += RB) {
+    int64_t e = lo + threadIdx.x;
+    for (; e + (kUpdU - 1) * RB < hi; e += kUpdU * RB) {
+        double ue[kUpdU], we[kUpdU], s1[kUpdU], s2[kUpdU];
+#pragma unroll
+        for (int u = 0; u < kUpdU; ++u) {
+            ue[u] = ld_stream(um + e + u * RB);
+            we[u] = ld_stream(wm + e + u * RB);
+            s1[u] = 0.0;
+            s2[u] = 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            if (i < nv) {
+#pragma unroll
+                for (int u = 0; u < kUpdU; ++u) {
+                    const double v = ld_stream(Vm + i * vstride + e + u * RB);
+                    s1[u] += a[i] * v;
+                    s2[u] += t[i] * v;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUpdU; ++u) {
+            const double vj = (ue[u] - s1[u]) * inv_rho;
+            um[e + u * RB] = vj;
+            un[e + u * RB] = (we[u] - s2[u] - c * vj) * inv_nu;
+        }
+    }
+    for (; e < hi; e += RB) {
         const double ue = ld_stream(um + e);
         const double we = ld_stream(wm + e);
         double s1 = 0.0, s2 = 0.0;
