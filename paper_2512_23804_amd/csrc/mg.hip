@@ -28,12 +28,16 @@ __device__ __forceinline__ T st9(const T* s, int W, int i, T wc, T we, T wd) {
 // down: coarse tile of TC x TC coarse nodes starting at (I0, J0) = 1 + TC (tx, ty),
 // owning the fine nodes [2 I0 - 1, 2 I0 + 2 TC - 1) per side.
 // Fine region: origin (2 I0 - 1 - NU, 2 J0 - 1 - NU), width W = 2 TC + 1 + 2 NU.
+// Only the iterate (read by the stencil) is in LDS; b, the step direction and
+// the new iterate of the region nodes a thread owns stay in its registers, and
+// the LDS array is reused for the residual that the restriction reads.
 template <typename T, int TC, int NU>
 __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restrict__ lev, int lvl,
                                                  const T* __restrict__ b, ColMap bmap, T* __restrict__ xo,
                                                  ColMap xmap, T* __restrict__ bc, int cpm, int tiles_x) {
     constexpr int W = 2 * TC + 1 + 2 * NU;
-    __shared__ T sb[W * W], sxa[W * W], sxb[W * W], sd[W * W];
+    constexpr int PPT = (W * W + 255) / 256;
+    __shared__ T sx[W * W];
     const int c = blockIdx.y;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int I0 = 1 + tx * TC, J0 = 1 + ty * TC;
@@ -44,50 +48,70 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
     const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
     const T* bcol = b + bmap.off(c);
     const int N1 = m + 1;
+    T breg[PPT], d[PPT], xr[PPT];
     // load b; x_1 = d_1 = c_r D^{-1} b
     const T cr0 = T(L.pre[0][1]);
-    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
         const int X = FX0 + q % W, Y = FY0 + q / W;
-        const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
-        const T bv = inter ? bcol[Y * N1 + X] : T(0);
-        sb[q] = bv;
-        const T x1 = cr0 * dinv * bv;
-        sxa[q] = x1;
-        sd[q] = x1;
+        const bool inter = q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+        breg[p] = inter ? bcol[Y * N1 + X] : T(0);
+        xr[p] = cr0 * dinv * breg[p];
+        d[p] = xr[p];
+        if (q < W * W) sx[q] = xr[p];
     }
     __syncthreads();
-    T* cur = sxa;
-    T* nxt = sxb;
 #pragma unroll
     for (int s = 1; s < NU; ++s) {
         const T cd = T(L.pre[s][0]), cr = T(L.pre[s][1]);
-        const int lo = s, hi = W - s;
-        for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int q = threadIdx.x + 256 * p;
             const int i = q % W, j = q / W;
-            if (i < lo || i >= hi || j < lo || j >= hi) continue;
             const int X = FX0 + i, Y = FY0 + j;
-            const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
-            T v = T(0);
-            if (inter) {
-                const T r = sb[q] - st9(cur, W, q, wc, we, wd);
-                const T dn = cd * sd[q] + cr * dinv * r;
-                sd[q] = dn;
-                v = cur[q] + dn;
+            if (q < W * W && i >= s && i < W - s && j >= s && j < W - s && X >= 1 && X <= m - 1 && Y >= 1 &&
+                Y <= m - 1) {
+                const T r = breg[p] - st9(sx, W, q, wc, we, wd);
+                d[p] = cd * d[p] + cr * dinv * r;
+                xr[p] += d[p];
             }
-            nxt[q] = v;
         }
         __syncthreads();
-        T* tmp = cur;
-        cur = nxt;
-        nxt = tmp;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int q = threadIdx.x + 256 * p;
+            if (q < W * W) sx[q] = xr[p];
+        }
+        __syncthreads();
     }
-    // residual on [NU, W-NU) into sd (the step direction is no longer needed)
-    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+    // residual on [NU, W-NU) (into registers, then over the iterate in LDS)
+    T rr[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
         const int i = q % W, j = q / W;
-        if (i < NU || i >= W - NU || j < NU || j >= W - NU) continue;
         const int X = FX0 + i, Y = FY0 + j;
-        const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
-        sd[q] = inter ? sb[q] - st9(cur, W, q, wc, we, wd) : T(0);
+        rr[p] = T(0);
+        if (q < W * W && i >= NU && i < W - NU && j >= NU && j < W - NU && X >= 1 && X <= m - 1 && Y >= 1 &&
+            Y <= m - 1)
+            rr[p] = breg[p] - st9(sx, W, q, wc, we, wd);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
+        if (q < W * W) sx[q] = rr[p];
+    }
+    // smoothed x on the owned fine nodes [2 I0 - 1, 2 I0 + 2 TC - 1) (ring nodes hold 0)
+    T* xcol = xo + xmap.off(c);
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
+        const int X = FX0 + q % W, Y = FY0 + q / W;
+        if (q < W * W && X >= 2 * I0 - 1 - ex && X < 2 * I0 + 2 * TC - 1 && Y >= 2 * J0 - 1 - ey &&
+            Y < 2 * J0 + 2 * TC - 1 && X <= m && Y <= m)
+            xcol[Y * N1 + X] = xr[p];
     }
     __syncthreads();
     // restriction (R = P^T: 1 centre, 1/2 edge partners, 1/4 corner partners)
@@ -98,29 +122,24 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
         T v = T(0);
         if (I >= 1 && I <= mc - 1 && J >= 1 && J <= mc - 1) {
             const int i = 2 * I - FX0, j = 2 * J - FY0;
-            const int p = j * W + i;
-            v = sd[p] + T(0.5) * (sd[p - 1] + sd[p + 1] + sd[p - W] + sd[p + W]) +
-                T(0.25) * (sd[p - W - 1] + sd[p - W + 1] + sd[p + W - 1] + sd[p + W + 1]);
+            const int pp = j * W + i;
+            v = sx[pp] + T(0.5) * (sx[pp - 1] + sx[pp + 1] + sx[pp - W] + sx[pp + W]) +
+                T(0.25) * (sx[pp - W - 1] + sx[pp - W + 1] + sx[pp + W - 1] + sx[pp + W + 1]);
         }
         bco[J * (mc + 1) + I] = v;
-    }
-    // smoothed x on the owned fine nodes [2 I0 - 1, 2 I0 + 2 TC - 1)
-    T* xcol = xo + xmap.off(c);
-    for (int q = threadIdx.x; q < (2 * TC + ex) * (2 * TC + ey); q += blockDim.x) {
-        const int X = 2 * I0 - 1 - ex + q % (2 * TC + ex), Y = 2 * J0 - 1 - ey + q / (2 * TC + ex);
-        if (X > m || Y > m) continue;
-        xcol[Y * N1 + X] = (X == 0 || Y == 0) ? T(0) : cur[(Y - FY0) * W + (X - FX0)];
     }
 }
 
 // up: fine tile of TF x TF nodes starting at (X0, Y0) = 1 + TF (tx, ty); region with halo NU.
+// The iterate is in LDS; b, the step direction and the new iterate in registers.
 template <typename T, int TF, int NU>
 __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict__ lev, int lvl,
                                                const T* __restrict__ xin, ColMap xinmap, const T* __restrict__ ec,
                                                const T* __restrict__ b, ColMap bmap, T* __restrict__ xo, ColMap xomap,
                                                int cpm, int tiles_x) {
     constexpr int W = TF + 2 * NU;
-    __shared__ T sb[W * W], sxa[W * W], sxb[W * W], sd[W * W];
+    constexpr int PPT = (W * W + 255) / 256;
+    __shared__ T sx[W * W];
     const int c = blockIdx.y;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int FX0 = 1 + tx * TF - NU, FY0 = 1 + ty * TF - NU;
@@ -132,9 +151,12 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
     const T* xcol = xin + xinmap.off(c);
     const T* bcol = b + bmap.off(c);
     const T* ecol = ec + (int64_t)c * C1 * C1;
-    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+    T breg[PPT], d[PPT], xr[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
         const int X = FX0 + q % W, Y = FY0 + q / W;
-        const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+        const bool inter = q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
         T xv = T(0), bv = T(0);
         if (inter) {
             const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
@@ -142,41 +164,46 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
             xv = xcol[Y * N1 + X] + e;
             bv = bcol[Y * N1 + X];
         }
-        sxa[q] = xv;
-        sb[q] = bv;
-        sd[q] = T(0);
+        xr[p] = xv;
+        breg[p] = bv;
+        d[p] = T(0);
+        if (q < W * W) sx[q] = xv;
     }
     __syncthreads();
-    T* cur = sxa;
-    T* nxt = sxb;
 #pragma unroll
     for (int s = 0; s < NU; ++s) {
         const T cd = T(L.post[s][0]), cr = T(L.post[s][1]);
         const int lo = s + 1, hi = W - s - 1;
-        for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int q = threadIdx.x + 256 * p;
             const int i = q % W, j = q / W;
-            if (i < lo || i >= hi || j < lo || j >= hi) continue;
             const int X = FX0 + i, Y = FY0 + j;
-            const bool inter = X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
-            T v = T(0);
-            if (inter) {
-                const T r = sb[q] - st9(cur, W, q, wc, we, wd);
-                const T dn = (s == 0 ? T(0) : cd * sd[q]) + cr * dinv * r;
-                sd[q] = dn;
-                v = cur[q] + dn;
+            if (q < W * W && i >= lo && i < hi && j >= lo && j < hi && X >= 1 && X <= m - 1 && Y >= 1 &&
+                Y <= m - 1) {
+                const T r = breg[p] - st9(sx, W, q, wc, we, wd);
+                d[p] = (s == 0 ? T(0) : cd * d[p]) + cr * dinv * r;
+                xr[p] += d[p];
             }
-            nxt[q] = v;
         }
-        __syncthreads();
-        T* tmp = cur;
-        cur = nxt;
-        nxt = tmp;
+        if (s + 1 < NU) {
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const int q = threadIdx.x + 256 * p;
+                if (q < W * W) sx[q] = xr[p];
+            }
+            __syncthreads();
+        }
     }
     T* out = xo + xomap.off(c);
-    for (int q = threadIdx.x; q < (TF + ex) * (TF + ey); q += blockDim.x) {
-        const int X = FX0 + NU - ex + q % (TF + ex), Y = FY0 + NU - ey + q / (TF + ex);
-        if (X > m || Y > m) continue;
-        out[Y * N1 + X] = (X == 0 || Y == 0) ? T(0) : cur[(Y - FY0) * W + (X - FX0)];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
+        const int X = FX0 + q % W, Y = FY0 + q / W;
+        if (q < W * W && X >= FX0 + NU - ex && X < FX0 + NU + TF && Y >= FY0 + NU - ey && Y < FY0 + NU + TF &&
+            X <= m && Y <= m)
+            out[Y * N1 + X] = xr[p];
     }
 }
 
@@ -194,7 +221,8 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
                                                          int64_t vstride, const T* __restrict__ r, T* __restrict__ z,
                                                          ChebW cw, int tiles_x) {
     constexpr int W = TF + 2 * H;     // H = steps - 1
-    __shared__ T sb[W * W], sp[W * W], sc[W * W];
+    constexpr int PPT = (W * W + 255) / 256;
+    __shared__ T sc[W * W];           // x_k (read by the mass stencil); b, x_{k-1}, x_k own nodes in registers
     const int l = blockIdx.y;
     const int vec = blockIdx.z;
     const int mem = op.mem_shared ? 0 : vec;
@@ -206,39 +234,45 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     const T h2_36 = h * h / T(36);
     const T dinv = T(1) / (T(1.25) * T(4) * h * h / T(9));
     const T* rc = r + (int64_t)vec * vstride + (int64_t)l * nodes;
-    for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+    T breg[PPT], xp[PPT], xc[PPT];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
         const int X = FX0 + q % W, Y = FY0 + q / W;
-        const bool inter = X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1;
-        const T bv = inter ? rc[Y * N1 + X] : T(0);
-        sb[q] = bv;
-        sp[q] = T(0);           // x_0
-        sc[q] = dinv * bv;      // x_1 (omega_1 = 1)
+        const bool inter = q < W * W && X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1;
+        breg[p] = inter ? rc[Y * N1 + X] : T(0);
+        xp[p] = T(0);                 // x_0
+        xc[p] = dinv * breg[p];       // x_1 (omega_1 = 1)
+        if (q < W * W) sc[q] = xc[p];
     }
     __syncthreads();
-    T* prev = sp;
-    T* cur = sc;
 #pragma unroll 1
     for (int k = 1; k <= H; ++k) {
         const T om = T(cw.omega[k - 1]);
         const int lo = k, hi = W - k;
-        // x_{k+1} overwrites x_{k-1} in place (each node reads only its own x_{k-1})
-        for (int q = threadIdx.x; q < W * W; q += blockDim.x) {
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int q = threadIdx.x + 256 * p;
             const int i = q % W, j = q / W;
-            if (i < lo || i >= hi || j < lo || j >= hi) continue;
             const int X = FX0 + i, Y = FY0 + j;
-            const bool inter = X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1;
-            T v = T(0);
-            if (inter) {
-                const T Mx = h2_36 * (T(16) * cur[q] + T(4) * (cur[q - 1] + cur[q + 1] + cur[q - W] + cur[q + W]) +
-                                      (cur[q - W - 1] + cur[q - W + 1] + cur[q + W - 1] + cur[q + W + 1]));
-                v = om * (dinv * (sb[q] - Mx) + cur[q] - prev[q]) + prev[q];
+            if (q < W * W && i >= lo && i < hi && j >= lo && j < hi && X >= 1 && X <= n - 1 && Y >= 1 &&
+                Y <= n - 1) {
+                const T Mx = h2_36 * (T(16) * sc[q] + T(4) * (sc[q - 1] + sc[q + 1] + sc[q - W] + sc[q + W]) +
+                                      (sc[q - W - 1] + sc[q - W + 1] + sc[q + W - 1] + sc[q + W + 1]));
+                const T v = om * (dinv * (breg[p] - Mx) + xc[p] - xp[p]) + xp[p];
+                xp[p] = xc[p];
+                xc[p] = v;
             }
-            prev[q] = v;
         }
-        __syncthreads();
-        T* tmp = prev;
-        prev = cur;
-        cur = tmp;
+        if (k < H) {
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < PPT; ++p) {
+                const int q = threadIdx.x + 256 * p;
+                if (q < W * W) sc[q] = xc[p];
+            }
+            __syncthreads();
+        }
     }
     const MemberDev md = op.mem[mem];
     const int var = l / (nt * nxi);
@@ -248,10 +282,13 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     const T sc_ = var == 0 ? (j == 0 ? T(1) : T(md.hg)) : T(md.beta);
     const T f = T(1) / (sc_ * T(md.tau) * Dt);
     T* zc = z + (int64_t)vec * vstride + (int64_t)l * nodes;
-    for (int q = threadIdx.x; q < (TF + ex) * (TF + ey); q += blockDim.x) {
-        const int X = FX0 + H - ex + q % (TF + ex), Y = FY0 + H - ey + q / (TF + ex);
-        if (X > n || Y > n) continue;
-        zc[Y * N1 + X] = (X == 0 || Y == 0) ? T(0) : f * cur[(Y - FY0) * W + (X - FX0)];
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
+        const int X = FX0 + q % W, Y = FY0 + q / W;
+        if (q < W * W && X >= FX0 + H - ex && X < FX0 + H + TF && Y >= FY0 + H - ey && Y < FY0 + H + TF &&
+            X <= n && Y <= n)
+            zc[Y * N1 + X] = f * xc[p];
     }
 }
 
