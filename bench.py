@@ -35,7 +35,10 @@ WORKLOADS = {
     "steady-512-M8-P3": dict(n=512, M=8, P=3, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(5,)),
 }
 DEFAULT = "steady-128-M6-P4"
-PROF_KIND = {"kkt_apply": 1, "mg_smooth": 2, "multidot": 3, "hgs_rhs": 4, "arnoldi_update": 5}
+# kernels timed with HIP events around every launch (sg_options.profile), with
+# the algorithmic bytes each launch must move
+PROF_KIND = {"kkt_apply": 1, "mg_smooth": 2, "arnoldi_dots": 3, "hgs_rhs": 4, "arnoldi_update": 5, "mg_tail": 6,
+             "mass_cheb": 7}
 ARNOLDI = {"dcgs2": 0, "cgs2": 1}
 
 
@@ -134,8 +137,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
-    ap.add_argument("--profile-kernel", default="kkt_apply", choices=sorted(PROF_KIND))
+    ap.add_argument("--profile-kernel", default="auto", choices=["auto"] + sorted(PROF_KIND),
+                    help="kernel reported as roofline (auto: the one with the largest measured total time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB FP64 tensor three times (calibrates hardware byte counters) and exit")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no HIP graph replay)")
     ap.add_argument("--arnoldi", default="dcgs2", choices=sorted(ARNOLDI),
@@ -147,13 +153,21 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_probe:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 8 << 27, "copy_probe_bytes_written": 8 << 27, "copies": 3}))
+        return
+
     import paper_2512_23804_amd as sgl
     import sg_inputs
 
     wl = WORKLOADS[args.workload]
     probs = make_problems(sgl, sg_inputs, wl)
     stream = torch.cuda.Stream()
-    prof = PROF_KIND[args.profile_kernel]
 
     graphs = 0 if args.no_graphs else 1
     # headline: FP64 batch (the whole beta sweep) per step
@@ -164,12 +178,23 @@ def main():
     value = nsolve / dt
     iters = [i.iters for step in infos for i in step]
     rel = max(i.rel_res_true for step in infos for i in step)
-    # roofline: one more solve of the same batch with HIP events around every
-    # launch of the profiled kernel (event pairs serialise the stream a little,
-    # so this solve is not part of the timed steps)
-    _, pinfo = timed_solves(torch, sgl, probs, sgl.default_options(rtol=1e-8, profile=prof, arnoldi=arn), 1, 0, stream)
-    pms, pbytes, plaunch = pinfo[0][0].prof_ms, pinfo[0][0].prof_bytes, pinfo[0][0].prof_launches
-    achieved = pbytes / pms / 1e6 if pms > 0 else 0.0
+    # per-kernel rooflines: one more solve of the same batch per kernel kind with
+    # HIP events around every launch of that kernel on the library's stream
+    # (event pairs serialise the stream a little, so these solves are not part
+    # of the timed steps)
+    kern = {}
+    kinds = PROF_KIND if args.profile_kernel == "auto" else {args.profile_kernel: PROF_KIND[args.profile_kernel]}
+    for name, kind in kinds.items():
+        _, pinfo = timed_solves(torch, sgl, probs, sgl.default_options(rtol=1e-8, profile=kind, arnoldi=arn), 1, 0,
+                                stream)
+        pms, pbytes, plaunch = pinfo[0][0].prof_ms, pinfo[0][0].prof_bytes, pinfo[0][0].prof_launches
+        if plaunch == 0:
+            continue
+        ach = pbytes / pms / 1e6 if pms > 0 else 0.0
+        kern[name] = {"ms_per_step": pms, "launches": plaunch, "avg_launch_ms": pms / plaunch,
+                      "bytes_per_launch": pbytes / plaunch, "achieved_GBps": ach, "frac": ach / HBM_PEAK_GBPS}
+    dom = args.profile_kernel if args.profile_kernel != "auto" else max(kern, key=lambda k: kern[k]["ms_per_step"])
+    kd = kern[dom]
     out = {
         "metric": "KKT solves/s to rel-res 1e-8 (FP64 vs FP32+refine); SG apply HBM GB/s",
         "value": value,
@@ -189,10 +214,11 @@ def main():
                    "arnoldi": args.arnoldi},
         "iterations": iters[: len(probs)],
         "max_rel_res": rel,
-        "roofline": {"bound": "hbm", "kernel": args.profile_kernel, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "launches": plaunch, "avg_launch_ms": pms / max(plaunch, 1),
-                     "bytes_per_launch": pbytes / max(plaunch, 1)},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": kd["achieved_GBps"] / HBM_PEAK_GBPS, "traffic": None,
+                     "launches": kd["launches"], "avg_launch_ms": kd["avg_launch_ms"],
+                     "bytes_per_launch": kd["bytes_per_launch"]},
+        "kernels": kern,
     }
     if not args.no_extras:
         o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE, use_graphs=graphs,

@@ -140,6 +140,8 @@ typedef struct sg_options {
 #define SG_PROF_MULTIDOT    3   /* Arnoldi dot-product pass (read-only pass over the basis) */
 #define SG_PROF_HGS_RHS     4   /* hierarchical Gauss-Seidel off-level right-hand side */
 #define SG_PROF_ARNOLDI_UPD 5   /* Arnoldi update pass (DCGS2: finalise V_j, next candidate) */
+#define SG_PROF_MG_TAIL     6   /* fused coarse end of the V-cycle (levels <= 64, direct solve) */
+#define SG_PROF_MASS_CHEB   7   /* Chebyshev semi-iteration on the mass blocks */
 
 /* Per-solve report. */
 typedef struct sg_solve_info {

@@ -156,7 +156,7 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
             fail(SG_ERR_INVALID, "gmg_pre/gmg_post must be in [1, 4]");
         if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32_REFINE)
             fail(SG_ERR_INVALID, "unknown precision mode");
-        if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_ARNOLDI_UPD) fail(SG_ERR_INVALID, "unknown profile kind");
+        if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_MASS_CHEB) fail(SG_ERR_INVALID, "unknown profile kind");
         if (opt->arnoldi != SG_ARNOLDI_DCGS2 && opt->arnoldi != SG_ARNOLDI_CGS2)
             fail(SG_ERR_INVALID, "arnoldi must be SG_ARNOLDI_DCGS2 or SG_ARNOLDI_CGS2");
         if (opt->precision == SG_PREC_FP32_REFINE && !(opt->inner_rtol > 0 && opt->inner_rtol < 1))

@@ -118,8 +118,11 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
     const T* e;
     if (tail) {
         T* out = lc == 0 ? x : xf[lc];
+        const bool tp = prof_begin(h, SG_PROF_MG_TAIL, st);
         launch_mg_tail<T>(s.mg_n[lc], lev, lc, npre, npost, lc == 0 ? b : bs[lc], lc == 0 ? bmap : cm[lc], out,
                           lc == 0 ? xmap : cm[lc], h.ainv<T>(), ncols, cpm, st);
+        // algorithmic bytes: read b, write x at the first fused level
+        if (tp) prof_end(h, st, 2.0 * sizeof(T) * ncols * (double)(s.mg_n[lc] + 1) * (s.mg_n[lc] + 1));
         e = out;
     } else {
         launch_mg_coarse<T>(h.ainv<T>(), bs[nl - 1], cm[nl - 1], xs[nl - 1], cm[nl - 1], ncols, cpm, st);
@@ -194,7 +197,9 @@ void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream
     // state and control blocks: Chebyshev semi-iteration on M with block scalings
     T* A = h.ws.get_t<T>(std::string("chebA") + tname<T>(), (size_t)nvec * 2 * s.blk);
     T* Bb = h.ws.get_t<T>(std::string("chebB") + tname<T>(), (size_t)nvec * 2 * s.blk);
+    const bool tp = prof_begin(h, SG_PROF_MASS_CHEB, st);
     launch_mass_cheb<T>(s, op, r, z, A, Bb, nvec, h.opt.cheb_steps, st);
+    if (tp) prof_end(h, st, 4.0 * sizeof(T) * nvec * (double)s.blk);   // read r_y, r_u; write z_y, z_u
     // adjoint block: S^{-1} r = Z^{-1} (tau D (x) M_gamma) Z^{-1} r
     T* V1 = h.ws.get_t<T>(std::string("schurV") + tname<T>(), (size_t)nvec * s.blk);
     T* W = h.ws.get_t<T>(std::string("schurW") + tname<T>(), (size_t)nvec * s.blk);
