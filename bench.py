@@ -42,6 +42,37 @@ PROF_KIND = {"kkt_apply": 1, "mg_smooth": 2, "arnoldi_dots": 3, "hgs_rhs": 4, "a
 ARNOLDI = {"dcgs2": 0, "cgs2": 1}
 
 
+# sources of the kernels whose HBM traffic is taken from a committed counter summary
+TRAFFIC_SOURCES = ("paper_2512_23804_amd/csrc/kernels.hip", "paper_2512_23804_amd/csrc/solver.cpp",
+                   "paper_2512_23804_amd/csrc/common.hpp")
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (profiles/*_traffic_*.md: FETCH_SIZE and WRITE_SIZE scaled by a
+    copy probe), or None when no summary covers this kernel and workload or the
+    kernel sources changed since the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic_*.md"))):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if ":" in line and line[:1].isalpha():
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel") != kernel or kv.get("workload") != workload:
+            continue
+        h = hashlib.sha256()
+        for src in TRAFFIC_SOURCES:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != kv.get("sources_sha256"):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def make_problems(sgl, sg_inputs, wl):
     probs = []
     for beta, seed in zip(wl["betas"], wl["seeds"]):
@@ -215,7 +246,8 @@ def main():
         "iterations": iters[: len(probs)],
         "max_rel_res": rel,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"], "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": kd["achieved_GBps"] / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": kd["achieved_GBps"] / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(dom, args.workload),
                      "launches": kd["launches"], "avg_launch_ms": kd["avg_launch_ms"],
                      "bytes_per_launch": kd["bytes_per_launch"]},
         "kernels": kern,
