@@ -259,6 +259,11 @@ def main():
         out["fp32_refine"] = {"value": nsolve / dt32, "unit": "solves/s", "dtype": "f32 operator/preconditioner, "
                               "f64 Arnoldi and refinement", "iterations": [i.iters for i in inf32[0]],
                               "max_rel_res": max(i.rel_res_true for st in inf32 for i in st)}
+        opc = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_PRECOND, use_graphs=graphs, arnoldi=arn)
+        dtp, infp = timed_solves(torch, sgl, probs, opc, args.steps, 1, stream)
+        out["fp32_precond"] = {"value": nsolve / dtp, "unit": "solves/s", "dtype": "f32 preconditioner, "
+                               "f64 operator, Arnoldi and restarts", "iterations": [i.iters for i in infp[0]],
+                               "max_rel_res": max(i.rel_res_true for st in infp for i in st)}
         single = []
         t_single = 0.0
         for p in probs:

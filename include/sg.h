@@ -74,6 +74,9 @@ extern "C" {
 #define SG_PREC_FP64         0  /* operator, preconditioner and Krylov in FP64 */
 #define SG_PREC_FP32_REFINE  1  /* FP32 operator + preconditioner inside FGMRES, FP64
                                    Arnoldi, FP64 outer residual and refinement */
+#define SG_PREC_FP32_PRECOND 2  /* FP32 preconditioner (basis Z in FP32) inside FP64
+                                   FGMRES: FP64 operator and Arnoldi; every restart
+                                   recomputes the FP64 residual */
 
 /* Problem data (Section 2.1 steady, Section 3 time-dependent), g = 0.
  *   n       elements per side (power of two, 4..4096)
@@ -109,7 +112,7 @@ typedef struct sg_problem {
  *   truncation_r hGS truncation: modes k = 1..r-1 are kept in the off-level
  *                products (r = 1 mean-based, r = M+1 all) [0 = M+1]
  *   gmg_pre/post Chebyshev smoothing degree before/after coarse correction [2,2]
- *   precision    SG_PREC_FP64 or SG_PREC_FP32_REFINE [SG_PREC_FP64]
+ *   precision    SG_PREC_FP64, SG_PREC_FP32_REFINE or SG_PREC_FP32_PRECOND [SG_PREC_FP64]
  *   inner_rtol   FP32 inner solve reduction per refinement step [1e-5]
  *   use_graphs   replay each FGMRES iteration from a cached hipGraph when the
  *                handle has a stream other than the default stream [1]

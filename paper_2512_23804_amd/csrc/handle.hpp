@@ -70,15 +70,16 @@ struct Prof {
 };
 
 // Instantiated graphs of one FGMRES iteration, keyed by (restart position j,
-// FP32 inner path), valid for one workspace generation.
+// precision variant: bit 0 FP32 preconditioner, bit 1 FP32 operator), valid
+// for one workspace generation.
 struct GraphCache {
     std::map<std::pair<int, int>, hipGraphExec_t> exec;
     uint64_t gen = ~0ull;
-    bool warm[2] = {false, false};
+    bool warm[4] = {false, false, false, false};
     void clear() {
         for (auto& kv : exec) (void)hipGraphExecDestroy(kv.second);
         exec.clear();
-        warm[0] = warm[1] = false;
+        for (bool& w : warm) w = false;
     }
     ~GraphCache() { clear(); }
 };

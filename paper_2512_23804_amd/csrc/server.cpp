@@ -44,11 +44,12 @@ size_t footprint_bytes(const sg_problem& p, const sg_options& o) {
     const double blk = nxi * nodes;
     const double N = 3 * blk;
     const int m = o.restart;
-    const double sz = o.precision == SG_PREC_FP32_REFINE ? 4.0 : 8.0;
+    const double sz = o.precision == SG_PREC_FP64 ? 8.0 : 4.0;
     double bytes = 8.0 * N * (m + 1) + sz * N * m + 8.0 * N * 6;   // V, Z, w/r/b/x/d staging
     // preconditioner scratch: Chebyshev 4 blocks, Schur 2, hGS 1, multigrid ~4 of the widest level
     bytes += sz * blk * 7 + sz * 4 * nodes * 1.4 * nxi * 0.6;
     if (o.precision == SG_PREC_FP32_REFINE) bytes += 4.0 * N * 2 + 8.0 * N * (m + 1) + 8.0 * N * m;  // FP64 fallback basis
+    if (o.precision == SG_PREC_FP32_PRECOND) bytes += 4.0 * N + 8.0 * N;   // FP32 staging, FP64 copy of Z_j
     return (size_t)bytes;
 }
 
@@ -56,7 +57,8 @@ bool same_shape(const Request& a, const Request& b) {
     return a.prob.n == b.prob.n && a.prob.M == b.prob.M && a.prob.P == b.prob.P && a.opt.precision == b.opt.precision &&
            a.opt.restart == b.opt.restart && a.opt.max_iter == b.opt.max_iter && a.opt.rtol == b.opt.rtol &&
            a.opt.cheb_steps == b.opt.cheb_steps && a.opt.truncation_r == b.opt.truncation_r &&
-           a.opt.gmg_pre == b.opt.gmg_pre && a.opt.gmg_post == b.opt.gmg_post && a.opt.inner_rtol == b.opt.inner_rtol;
+           a.opt.gmg_pre == b.opt.gmg_pre && a.opt.gmg_post == b.opt.gmg_post && a.opt.inner_rtol == b.opt.inner_rtol &&
+           a.opt.arnoldi == b.opt.arnoldi;
 }
 
 }  // namespace

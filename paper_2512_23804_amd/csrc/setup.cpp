@@ -154,7 +154,8 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
             fail(SG_ERR_INVALID, "truncation_r must be in [0, M+1]");
         if (opt->gmg_pre < 1 || opt->gmg_pre > kMaxSmooth || opt->gmg_post < 1 || opt->gmg_post > kMaxSmooth)
             fail(SG_ERR_INVALID, "gmg_pre/gmg_post must be in [1, 4]");
-        if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32_REFINE)
+        if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32_REFINE &&
+            opt->precision != SG_PREC_FP32_PRECOND)
             fail(SG_ERR_INVALID, "unknown precision mode");
         if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_MASS_CHEB) fail(SG_ERR_INVALID, "unknown profile kind");
         if (opt->arnoldi != SG_ARNOLDI_DCGS2 && opt->arnoldi != SG_ARNOLDI_CGS2)

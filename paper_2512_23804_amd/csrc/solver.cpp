@@ -230,7 +230,9 @@ struct Krylov {
     hipStream_t st;
     double* V;             // [m+1][B][N]
     void* Z;               // [m][B][N] (double or float)
-    bool z32;
+    bool z32;              // preconditioner in FP32, Z stored in FP32
+    bool op32;             // KKT operator on Z_j in FP32 too (refinement inner cycles)
+    double* zt;            // [B][N] FP64 copy of Z_j (z32 && !op32)
     double* w;             // [B][N]
     double* partial;       // [B][kSlots][nblk]
     KrylovDev kd;
@@ -238,13 +240,14 @@ struct Krylov {
     float* v32;            // [B][N] FP32 staging (inner FP32 mode)
     float* w32;
 
-    explicit Krylov(Handle& hh, bool fp32) : h(hh), st(hh.stream) {
+    Krylov(Handle& hh, bool fp32_precond, bool fp32_op) : h(hh), st(hh.stream) {
         const Shape& s = h.s;
         B = h.B;
         m = h.opt.restart;
         N = 3 * s.blk;
         nblk = (int)std::min<int64_t>(2048, std::max<int64_t>(1, N / (256 * 16)));
-        z32 = fp32;
+        z32 = fp32_precond;
+        op32 = fp32_precond && fp32_op;
         V = h.ws.get_t<double>("kV", (size_t)(m + 1) * B * N);
         Z = z32 ? (void*)h.ws.get_t<float>("kZ32", (size_t)m * B * N) : (void*)h.ws.get_t<double>("kZ", (size_t)m * B * N);
         w = h.ws.get_t<double>("kw", (size_t)B * N);
@@ -265,7 +268,8 @@ struct Krylov {
         kd.pending = h.ws.get_t<int>("kpend", (size_t)B);
         d_jend = h.ws.get_t<int>("kjend", (size_t)B);
         v32 = z32 ? h.ws.get_t<float>("kv32", (size_t)B * N) : nullptr;
-        w32 = z32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
+        w32 = op32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
+        zt = z32 && !op32 ? h.ws.get_t<double>("kzt", (size_t)B * N) : nullptr;
     }
     double* Vi(int i) { return V + (int64_t)i * B * N; }
 
@@ -292,6 +296,9 @@ struct Krylov {
     void apply_op_z(int j) {
         if (!z32) {
             kkt_apply<double>(h, (double*)Z + (int64_t)j * B * N, w, B, B == 1, st);
+        } else if (!op32) {
+            launch_cast_f2d((float*)Z + (int64_t)j * B * N, zt, (int64_t)B * N, st);
+            kkt_apply<double>(h, zt, w, B, B == 1, st);
         } else {
             kkt_apply<float>(h, (float*)Z + (int64_t)j * B * N, w32, B, B == 1, st);
             launch_cast_f2d(w32, w, (int64_t)B * N, st);
@@ -392,7 +399,7 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
             launch_arnoldi_finish(K.kd, m, j, B, st);
             launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
         };
-        const int zk = K.z32 ? 1 : 0;
+        const int zk = (K.z32 ? 1 : 0) + (K.op32 ? 2 : 0);
         // (capture needs a created stream; the legacy default stream cannot be captured)
         const bool graphs = h.opt.use_graphs && st != nullptr && h.prof.kind == SG_PROF_NONE && h.opt.cheb_steps <= 9;
         if (graphs && h.graphs.gen != h.ws.generation()) {
@@ -482,9 +489,10 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
     SG_HIP(hipMemsetAsync(x_dev, 0, sizeof(double) * B * N, st));
 
     const bool fp32 = h.opt.precision == SG_PREC_FP32_REFINE;
+    const bool pc32 = h.opt.precision == SG_PREC_FP32_PRECOND;
     h.prof.kind = h.opt.profile;
     h.prof.reset();
-    Krylov K(h, fp32);
+    Krylov K(h, fp32 || pc32, fp32);
     std::vector<double> bn2;
     K.norms2(b, bn2);
     std::vector<double> tol(B), res(B, 0.0);
@@ -529,7 +537,7 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
             std::vector<double> rin;
             if (any32) fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
             if (any64) {
-                if (!K64) K64.reset(new Krylov(h, false));
+                if (!K64) K64.reset(new Krylov(h, false, false));
                 fgmres(*K64, r, d, tol_in, todo64, false, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
             }
             launch_axpby(1.0, d, 1.0, x_dev, (int64_t)B * N, st);

@@ -209,6 +209,28 @@ def test_solve_fp32_refine_reaches_fp64_accuracy():
         assert rel_max(a, b) < 1e-8
 
 
+def test_solve_fp32_preconditioner_tracks_fp64():
+    """FP32 preconditioner inside FP64 FGMRES: reaches the direct solution and
+    needs about the FP64 iteration count (the operator stays FP64)."""
+    dev = _dev()
+    _say("solve fp32 preconditioner")
+    prob, kw = make_case(32, 4, 3, 0.3, 1e-4, seed=3)
+    sg = kkt.setup(prob)
+    its = {}
+    for prec in (0, 2):
+        h = _setup([kw], rtol=1e-12, max_iter=600, precision=prec)
+        xd = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+        rc, info = h.solve(xd)
+        assert rc == 0 and info[0].rel_res_true <= 1e-12
+        its[prec] = info[0].iters
+        if prec == 2:
+            x = canonical_to_kkt(sg, xd.cpu().numpy())
+            ref = kkt.solve_direct(sg)
+            for a, b in zip(kkt.split(sg, x), kkt.split(sg, ref)):
+                assert rel_max(a, b) < 1e-8
+    assert its[2] <= its[0] + 2 + its[0] // 10, its
+
+
 def test_batch_results_equal_alone():
     """Members of one batch (different sigma, beta, targets) give bit-identical
     results to solving each alone."""
@@ -216,7 +238,7 @@ def test_batch_results_equal_alone():
     _say("batch invariance")
     params = [(0.2, 1e-2, 0), (0.3, 1e-4, 1), (0.1, 1e-3, 2)]
     kws = [make_case(16, 3, 2, s, b, seed=sd)[1] for s, b, sd in params]
-    for prec in (0, 1):
+    for prec in (0, 1, 2):
         hb = _setup(kws, rtol=1e-8, precision=prec)
         xb = torch.zeros(3 * hb.kkt_elems, dtype=torch.float64, device=dev)
         rc, infos = hb.solve(xb)
@@ -247,7 +269,7 @@ def test_delayed_reorthogonalisation_tracks_cgs2():
         assert abs(its[0] - its[1]) <= 2 + its[1] // 10, its
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_graph_replay_matches_direct_launches(precision):
     """Solves on a created stream replay cached per-iteration graphs after the
     first cycle; three consecutive solves with graphs and one without must be

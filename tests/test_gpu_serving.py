@@ -53,7 +53,7 @@ def _wait(srv, tickets, timeout=120.0):
     return res
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 def test_server_results_equal_alone(precision):
     _need_gpu()
     sgl = _lib()
