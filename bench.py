@@ -84,8 +84,10 @@ def make_problems(sgl, sg_inputs, wl):
     return probs
 
 
-def timed_solves(torch, sgl, probs, opts, steps, warmup, stream):
+def timed_solves(torch, sgl, probs, opts, steps, warmup, stream, tuned=None):
     h = sgl.Handle(probs, opts, stream=stream)
+    if tuned is not None:
+        tuned.extend([list(r) for r in h.sizes.sweep_rows])
     x = torch.zeros(h.members * h.kkt_elems, dtype=torch.float64, device="cuda")
     for _ in range(warmup):
         h.solve(x)
@@ -204,7 +206,8 @@ def main():
     # headline: FP64 batch (the whole beta sweep) per step
     arn = ARNOLDI[args.arnoldi]
     opts = sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn)
-    dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream)
+    tuned = []
+    dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream, tuned)
     nsolve = len(probs) * args.steps
     value = nsolve / dt
     iters = [i.iters for step in infos for i in step]
@@ -242,7 +245,7 @@ def main():
         "config": {"workload": args.workload, "n": wl["n"], "M": wl["M"], "P": wl["P"], "sigma": wl["sigma"],
                    "betas": list(wl["betas"]), "n_t": wl["n_t"], "batch": len(probs), "restart": 30,
                    "rtol": 1e-8, "precision": "fp64", "graphs": bool(graphs),
-                   "arnoldi": args.arnoldi},
+                   "arnoldi": args.arnoldi, "sweep_rows_fp64": tuned[0]},
         "iterations": iters[: len(probs)],
         "max_rel_res": rel,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"], "peak": HBM_PEAK_GBPS,

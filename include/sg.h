@@ -123,7 +123,11 @@ typedef struct sg_problem {
  *                Gram-Schmidt with the reorthogonalisation of each basis
  *                vector delayed to the next iteration: two passes over the
  *                basis per iteration) or SG_ARNOLDI_CGS2 (classical
- *                Gram-Schmidt applied twice: three passes) [SG_ARNOLDI_DCGS2] */
+ *                Gram-Schmidt applied twice: three passes) [SG_ARNOLDI_DCGS2]
+ *   sweep_rows   node rows per strip of the SG/KKT/hGS sweep kernels: 2, 4
+ *                or 8, or 0 to let sg_setup time the three on the handle's
+ *                shape and keep the fastest (cached per process and shape;
+ *                every choice gives bit-identical results) [0] */
 typedef struct sg_options {
     double rtol;
     int32_t restart, max_iter, cheb_steps, truncation_r;
@@ -131,6 +135,7 @@ typedef struct sg_options {
     double inner_rtol;
     int32_t use_graphs, verbose, profile;
     int32_t arnoldi;
+    int32_t sweep_rows;
 } sg_options;
 
 #define SG_ARNOLDI_DCGS2 0
@@ -169,6 +174,7 @@ typedef struct sg_sizes {
     int64_t block_elems;        /* n_t * n_xi * nodes (one field) */
     int64_t kkt_elems;          /* 3 * block_elems (one KKT vector) */
     int32_t level_offsets[17];  /* degree d columns: [off[d], off[d+1]), d = 0..P */
+    int32_t sweep_rows[2][3];   /* strip rows in use: [FP64, FP32][SG apply, hGS rhs, KKT apply] */
 } sg_sizes;
 
 typedef struct sg_handle sg_handle;

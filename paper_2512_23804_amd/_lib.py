@@ -37,7 +37,7 @@ class sg_options(C.Structure):
                 ("cheb_steps", C.c_int32), ("truncation_r", C.c_int32), ("gmg_pre", C.c_int32),
                 ("gmg_post", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
                 ("use_graphs", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
-                ("arnoldi", C.c_int32)]
+                ("arnoldi", C.c_int32), ("sweep_rows", C.c_int32)]
 
 
 class sg_solve_info(C.Structure):
@@ -50,7 +50,8 @@ class sg_solve_info(C.Structure):
 class sg_sizes(C.Structure):
     _fields_ = [("n", C.c_int32), ("M", C.c_int32), ("P", C.c_int32), ("n_t", C.c_int32),
                 ("n_xi", C.c_int32), ("members", C.c_int32), ("nodes", C.c_int64),
-                ("block_elems", C.c_int64), ("kkt_elems", C.c_int64), ("level_offsets", C.c_int32 * 17)]
+                ("block_elems", C.c_int64), ("kkt_elems", C.c_int64), ("level_offsets", C.c_int32 * 17),
+                ("sweep_rows", (C.c_int32 * 3) * 2)]
 
 
 # Every exported symbol of include/sg.h with (restype, argtypes).

@@ -91,6 +91,8 @@ int sg_query(const sg_handle* h, sg_sizes* out) {
         out->block_elems = s.blk;
         out->kkt_elems = 3 * s.blk;
         for (int d = 0; d <= s.P + 1 && d < 17; ++d) out->level_offsets[d] = s.off[d];
+        for (int t = 0; t < 2; ++t)
+            for (int k = 0; k < 3; ++k) out->sweep_rows[t][k] = s.sweep_rows[t][k];
         return SG_OK;
     });
 }

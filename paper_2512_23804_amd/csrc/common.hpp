@@ -92,7 +92,12 @@ struct Shape {
     int off[kMaxP + 2];        // degree level offsets
     int nlev_mg;               // multigrid levels
     int mg_n[kMaxLevels];      // elements per side per multigrid level
+    // node rows per strip of the sweep kernels, per element type [0 FP64, 1 FP32]
+    // and kernel [SWEEP_APPLY, SWEEP_HGS, SWEEP_KKT]; chosen by the autotuner
+    int sweep_rows[2][3] = {{4, 4, 4}, {4, 4, 4}};
 };
+enum SweepKind { SWEEP_APPLY = 0, SWEEP_HGS = 1, SWEEP_KKT = 2 };
+constexpr int kSweepRowChoices[3] = {2, 4, 8};
 
 // Host-side tables built by setup.
 struct HostTables {

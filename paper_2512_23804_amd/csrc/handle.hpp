@@ -1,6 +1,7 @@
 // Handle: one batch of same-shape problems and its device state.
 #pragma once
 
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -147,6 +148,7 @@ void set_last_error(const std::string& msg);
 // setup.cpp
 void default_options(sg_options* o);
 void validate(const sg_problem* probs, int count, const sg_options* opt);   // throws Error
+void autotune(Handle& h);   // tune.cpp: strip heights of the sweep kernels (sg_options.sweep_rows)
 std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt, hipStream_t st);
 std::vector<int32_t> multi_indices(int M, int P);
 int binom(int n, int k);

@@ -32,6 +32,7 @@ void default_options(sg_options* o) {
     o->verbose = 0;
     o->profile = SG_PROF_NONE;
     o->arnoldi = SG_ARNOLDI_DCGS2;
+    o->sweep_rows = 0;
 }
 
 // Total-degree multi-indices, degree ascending, descending lexicographic order
@@ -158,6 +159,8 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
             opt->precision != SG_PREC_FP32_PRECOND)
             fail(SG_ERR_INVALID, "unknown precision mode");
         if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_MASS_CHEB) fail(SG_ERR_INVALID, "unknown profile kind");
+        if (opt->sweep_rows != 0 && opt->sweep_rows != 2 && opt->sweep_rows != 4 && opt->sweep_rows != 8)
+            fail(SG_ERR_INVALID, "sweep_rows must be 0 (autotune), 2, 4 or 8");
         if (opt->arnoldi != SG_ARNOLDI_DCGS2 && opt->arnoldi != SG_ARNOLDI_CGS2)
             fail(SG_ERR_INVALID, "arnoldi must be SG_ARNOLDI_DCGS2 or SG_ARNOLDI_CGS2");
         if (opt->precision == SG_PREC_FP32_REFINE && !(opt->inner_rtol > 0 && opt->inner_rtol < 1))
@@ -447,6 +450,8 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     h->rhs_host.shrink_to_fit();
     SG_HIP(hipHostMalloc((void**)&h->h_pinned, 4096 * sizeof(double), hipHostMallocDefault));
     h->h_pinned_count = 4096;
+    autotune(*h);
+    SG_HIP(hipStreamSynchronize(h->stream));
     h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return h;
 }

@@ -63,74 +63,9 @@ struct SweepGeom {
     int tiles_x, tiles_y, nchunks, nb;
 };
 
-#ifndef SG_SWEEP_ROWS
-#define SG_SWEEP_ROWS 4
-#endif
-#ifndef SG_SWEEP_WAVES
-#define SG_SWEEP_WAVES 4
-#endif
-constexpr int RS = SG_SWEEP_ROWS;   // node rows per strip (output rows per 32-lane group)
-
-// Per-lane strip geometry: node rows y0-1 .. y0+RS (RS+2 rows) and element
-// rows y0-1 .. y0+RS-1 (RS+1 rows) of node column X.  Offsets are clamped into
-// the grid so that every load is in bounds; the masks zero what lies on the
-// Dirichlet ring or outside the grid.
-struct Strip {
-    int n, xc, xe, y0;
-    uint32_t nmask, emask;
-    __device__ __forceinline__ void init(int n_, int X, int y0_) {
-        n = n_;
-        y0 = y0_;
-        xc = min(max(X, 0), n);
-        xe = min(max(X, 0), n - 1);
-        const bool xin = X >= 1 && X <= n - 1;
-        const bool xev = X >= 0 && X <= n - 1;
-        nmask = 0;
-        emask = 0;
-#pragma unroll
-        for (int r = 0; r < RS + 2; ++r) {
-            const int Y = y0 - 1 + r;
-            if (xin && Y >= 1 && Y <= n - 1) nmask |= 1u << r;
-        }
-#pragma unroll
-        for (int r = 0; r < RS + 1; ++r) {
-            const int ey = y0 - 1 + r;
-            if (xev && ey >= 0 && ey <= n - 1) emask |= 1u << r;
-        }
-    }
-    __device__ __forceinline__ int noff(int r) const { return min(max(y0 - 1 + r, 0), n) * (n + 1) + xc; }
-    __device__ __forceinline__ int eoff(int r) const { return min(max(y0 - 1 + r, 0), n - 1) * n + xe; }
-};
-
-// v[r] += c_r * (corner values of element row r) for one input column stream
-// (vals = node values of the column at the RS+2 strip rows, already scaled).
-template <typename T>
-__device__ __forceinline__ void corner_accumulate(T (&v)[RS + 1][4], const T (&vals)[RS + 2], const T (&c)[RS + 1]) {
-    T prev = vals[0];
-    T prevR = shdn(prev);
-#pragma unroll
-    for (int r = 0; r < RS + 1; ++r) {
-        const T top = vals[r + 1];
-        const T topR = shdn(top);
-        v[r][0] += c[r] * prev;
-        v[r][1] += c[r] * prevR;
-        v[r][2] += c[r] * topR;
-        v[r][3] += c[r] * top;
-        prev = top;
-        prevR = topR;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void load_col(T (&vals)[RS + 2], const T* __restrict__ col, const Strip& st, T g,
-                                         bool accumulate) {
-#pragma unroll
-    for (int r = 0; r < RS + 2; ++r) {
-        T x = col[st.noff(r)];
-        x = ((st.nmask >> r) & 1u) ? x : T(0);
-        vals[r] = accumulate ? vals[r] + g * x : g * x;
-    }
-}
+// Occupancy hints per strip height (registers grow with the rows per strip).
+constexpr int sweep_waves(int rs, int bytes) { return rs <= 2 ? 6 : rs <= 4 ? 4 : bytes == 8 ? 2 : 3; }
+constexpr int kkt_waves(int rs, int bytes) { return rs <= 2 ? 5 : rs <= 4 ? 3 : 2; }
 
 // Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
 // field F at output column j: c0 X_j (mean, if with_mean) plus, for every mode
@@ -174,52 +109,186 @@ __device__ __forceinline__ int next_term(int k, int j, int M, const int32_t* __r
     return M;
 }
 
-template <typename T>
-__device__ __forceinline__ void load_term(T (&vals)[RS + 2], const Term<T>& t, const T* __restrict__ F, int64_t nodes,
-                                          const Strip& st) {
-    if (t.ia >= 0) load_col(vals, F + (int64_t)t.ia * nodes, st, t.ga, false);
-    if (t.ib >= 0) load_col(vals, F + (int64_t)t.ib * nodes, st, t.gb, t.ia >= 0);
-}
-
-// Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
-// field F at output column j.  The loads of the next term are issued before
-// the current term is accumulated (two terms in flight per wavefront).
-template <typename T>
-__device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
-                                         int j, int M, const int32_t* __restrict__ nidx,
-                                         const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
-                                         bool with_mean, T c0, const T* __restrict__ coef, int64_t cplane) {
-    T vals[RS + 2], nvals[RS + 2];
-    T c[RS + 1];
-    Term<T> cur, nxt;
-    int k = next_term(with_mean ? -1 : 0, j, M, nidx, nval, mask, lower, upper, cur);
-    if (k >= M) return;
-    load_term(vals, cur, F, nodes, st);
-#pragma unroll 1
-    while (true) {
-        const int kn = next_term(k + 1, j, M, nidx, nval, mask, lower, upper, nxt);
-        const bool more = kn < M;
-        if (more) load_term(nvals, nxt, F, nodes, st);
-        const T* ck = coef + (int64_t)(k + 1) * cplane;
-#pragma unroll
-        for (int r = 0; r < RS + 1; ++r) {
-            const T cv = k < 0 ? c0 : ck[st.eoff(r)];
-            c[r] = ((st.emask >> r) & 1u) ? cv : T(0);
+// Row-strip helpers for strips of RS node rows per 32-lane group (RS is a
+// launch parameter chosen per shape by the autotuner; every choice sums the
+// same terms per node in the same order).
+template <int RS>
+struct Sweep {
+    // Per-lane strip geometry: node rows y0-1 .. y0+RS (RS+2 rows) and element
+    // rows y0-1 .. y0+RS-1 (RS+1 rows) of node column X.  Offsets are clamped into
+    // the grid so that every load is in bounds; the masks zero what lies on the
+    // Dirichlet ring or outside the grid.
+    struct Strip {
+        int n, xc, xe, y0;
+        uint32_t nmask, emask;
+        __device__ __forceinline__ void init(int n_, int X, int y0_) {
+            n = n_;
+            y0 = y0_;
+            xc = min(max(X, 0), n);
+            xe = min(max(X, 0), n - 1);
+            const bool xin = X >= 1 && X <= n - 1;
+            const bool xev = X >= 0 && X <= n - 1;
+            nmask = 0;
+            emask = 0;
+    #pragma unroll
+            for (int r = 0; r < RS + 2; ++r) {
+                const int Y = y0 - 1 + r;
+                if (xin && Y >= 1 && Y <= n - 1) nmask |= 1u << r;
+            }
+    #pragma unroll
+            for (int r = 0; r < RS + 1; ++r) {
+                const int ey = y0 - 1 + r;
+                if (xev && ey >= 0 && ey <= n - 1) emask |= 1u << r;
+            }
         }
-        corner_accumulate(v, vals, c);
-        if (!more) break;
-#pragma unroll
-        for (int r = 0; r < RS + 2; ++r) vals[r] = nvals[r];
-        cur = nxt;
-        k = kn;
+        __device__ __forceinline__ int noff(int r) const { return min(max(y0 - 1 + r, 0), n) * (n + 1) + xc; }
+        __device__ __forceinline__ int eoff(int r) const { return min(max(y0 - 1 + r, 0), n - 1) * n + xe; }
+    };
+
+    // v[r] += c_r * (corner values of element row r) for one input column stream
+    // (vals = node values of the column at the RS+2 strip rows, already scaled).
+    template <typename T>
+    static __device__ __forceinline__ void corner_accumulate(T (&v)[RS + 1][4], const T (&vals)[RS + 2], const T (&c)[RS + 1]) {
+        T prev = vals[0];
+        T prevR = shdn(prev);
+    #pragma unroll
+        for (int r = 0; r < RS + 1; ++r) {
+            const T top = vals[r + 1];
+            const T topR = shdn(top);
+            v[r][0] += c[r] * prev;
+            v[r][1] += c[r] * prevR;
+            v[r][2] += c[r] * topR;
+            v[r][3] += c[r] * top;
+            prev = top;
+            prevR = topR;
+        }
     }
-}
+
+    template <typename T>
+    static __device__ __forceinline__ void load_col(T (&vals)[RS + 2], const T* __restrict__ col, const Strip& st, T g,
+                                             bool accumulate) {
+    #pragma unroll
+        for (int r = 0; r < RS + 2; ++r) {
+            T x = col[st.noff(r)];
+            x = ((st.nmask >> r) & 1u) ? x : T(0);
+            vals[r] = accumulate ? vals[r] + g * x : g * x;
+        }
+    }
+
+    template <typename T>
+    static __device__ __forceinline__ void load_term(T (&vals)[RS + 2], const Term<T>& t, const T* __restrict__ F, int64_t nodes,
+                                              const Strip& st) {
+        if (t.ia >= 0) load_col(vals, F + (int64_t)t.ia * nodes, st, t.ga, false);
+        if (t.ib >= 0) load_col(vals, F + (int64_t)t.ib * nodes, st, t.gb, t.ia >= 0);
+    }
+
+    // Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
+    // field F at output column j.  The loads of the next term are issued before
+    // the current term is accumulated (two terms in flight per wavefront).
+    template <typename T>
+    static __device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
+                                             int j, int M, const int32_t* __restrict__ nidx,
+                                             const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
+                                             bool with_mean, T c0, const T* __restrict__ coef, int64_t cplane) {
+        T vals[RS + 2], nvals[RS + 2];
+        T c[RS + 1];
+        Term<T> cur, nxt;
+        int k = next_term(with_mean ? -1 : 0, j, M, nidx, nval, mask, lower, upper, cur);
+        if (k >= M) return;
+        load_term(vals, cur, F, nodes, st);
+    #pragma unroll 1
+        while (true) {
+            const int kn = next_term(k + 1, j, M, nidx, nval, mask, lower, upper, nxt);
+            const bool more = kn < M;
+            if (more) load_term(nvals, nxt, F, nodes, st);
+            const T* ck = coef + (int64_t)(k + 1) * cplane;
+    #pragma unroll
+            for (int r = 0; r < RS + 1; ++r) {
+                const T cv = k < 0 ? c0 : ck[st.eoff(r)];
+                c[r] = ((st.emask >> r) & 1u) ? cv : T(0);
+            }
+            corner_accumulate(v, vals, c);
+            if (!more) break;
+    #pragma unroll
+            for (int r = 0; r < RS + 2; ++r) vals[r] = nvals[r];
+            cur = nxt;
+            k = kn;
+        }
+    }
+
+    // Reference-element mass (h^2/36)[4 2 1 2; 2 4 2 1; 1 2 4 2; 2 1 2 4] on a
+    // corner vector: m_a = w (2 s + 2 v_a - v_opp), w = h^2/36.
+    template <typename T>
+    static __device__ __forceinline__ void mass_accumulate(T (&e)[RS + 1][4], const T (&vals)[RS + 2], const Strip& st, T w) {
+        T prev = vals[0];
+        T prevR = shdn(prev);
+    #pragma unroll
+        for (int r = 0; r < RS + 1; ++r) {
+            const T top = vals[r + 1];
+            const T topR = shdn(top);
+            const T c = ((st.emask >> r) & 1u) ? w : T(0);
+            const T s2 = T(2) * ((prev + prevR) + (topR + top));
+            e[r][0] += c * (s2 + T(2) * prev - topR);
+            e[r][1] += c * (s2 + T(2) * prevR - top);
+            e[r][2] += c * (s2 + T(2) * topR - prev);
+            e[r][3] += c * (s2 + T(2) * top - prevR);
+            prev = top;
+            prevR = topR;
+        }
+    }
+
+    // Corner sums of the SG stiffness strip -> element results scaled by -s.
+    template <typename T>
+    static __device__ __forceinline__ void stiff_to_element(T (&v)[RS + 1][4], T s) {
+    #pragma unroll
+        for (int r = 0; r < RS + 1; ++r) {
+            T k0, k1, k2, k3;
+            kref(v[r][0], v[r][1], v[r][2], v[r][3], k0, k1, k2, k3);
+            v[r][0] = -s * k0;
+            v[r][1] = -s * k1;
+            v[r][2] = -s * k2;
+            v[r][3] = -s * k3;
+        }
+    }
+
+    // Node values from per-element results e[r][.] (element rows y0-1+r): node
+    // (X, Y) sums corners 0 and 3 of its own lane's element rows r and r-1 and
+    // corners 1 and 2 of the lane to the left; non-interior nodes get zero.
+    template <typename T>
+    static __device__ __forceinline__ void emit_nodes(const T (&e)[RS + 1][4], const Strip& st, int gl, int X, int n,
+                                               T* __restrict__ out) {
+        const bool xout = gl >= 1 && gl <= GOUT && X <= n;
+    #pragma unroll
+        for (int r = 1; r < RS + 1; ++r) {
+            const T A = e[r][0] + e[r - 1][3];
+            const T Bl = shup(e[r][1] + e[r - 1][2]);
+            const int Y = st.y0 - 1 + r;
+            if (xout && Y <= n) out[(int64_t)Y * (n + 1) + X] = ((st.nmask >> r) & 1u) ? A + Bl : T(0);
+        }
+    }
+
+    template <typename T>
+    static __device__ __forceinline__ void zero_strip(T (&v)[RS + 1][4]) {
+    #pragma unroll
+        for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
+    }
+
+    // Fused KKT apply, one output chaos column per wavefront, three residual blocks
+    // in turn.  With the SG stiffness A (mean included) and Q1 mass M:
+    //   steady (eq. stoch-system):  R^Y = M Y H^gamma - A L,  R^U = beta M U + M L,  R^L = M U - A Y
+    //   time (eq. KKT:stoch-time-dependent, backward Euler, D = diag(1/2, 1, .., 1, 1/2)):
+    //     R^Y_t = tau D_t M_gamma Y_t - M L_t - tau A L_t + M L_{t+1}
+    //     R^U_t = beta tau D_t M U_t + tau M L_t
+    //     R^L_t = -M Y_t - tau A Y_t + M Y_{t-1} + tau M U_t
+    // Each block is (mass of a combination of diagonal columns) - s (stiffness strip),
+    // formed per element and assembled once.
+};
 
 // KIND 0: Y = A X (all modes, mean included) for nt*nvec slices.
 // KIND 1: hGS right-hand side of degree level d:
 //         out_j = base_j - off_scale * sum_{k in mask} K_k (g- V_{j-e_k} [lower] + g+ V_{j+e_k} [upper]).
-template <typename T, int KIND>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_SWEEP_WAVES))) void k_sgx(int n, int M, int nxi, int nt, int64_t nodes, OpDev op, SweepGeom g,
+template <typename T, int KIND, int RS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves(RS, sizeof(T))))) void k_sgx(int n, int M, int nxi, int nt, int64_t nodes, OpDev op, SweepGeom g,
                                              const T* __restrict__ x, T* __restrict__ y, int j0lvl, int L,
                                              uint32_t mask, int lower, int upper, const T* __restrict__ base,
                                              ColMap bmap, ColMap vmap, ColMap omap) {
@@ -249,12 +318,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_SWEEP_WA
     const int64_t cplane = (int64_t)n * n;
     const T* F = KIND == 0 ? x + (int64_t)slice * nxi * nodes
                            : x + (int64_t)mem_i * vmap.mstride + (int64_t)t * vmap.tstride;
-    Strip st;
+    using S = Sweep<RS>;
+    typename S::Strip st;
     st.init(n, X, y0);
     T v[RS + 1][4];
 #pragma unroll
     for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
-    sg_strip(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, KIND == 0 ? 0xffffffffu : mask,
+    S::sg_strip(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, KIND == 0 ? 0xffffffffu : mask,
              KIND == 0 ? true : lower != 0, KIND == 0 ? true : upper != 0, KIND == 0, T(op.mem[mem].c0), coef,
              cplane);
     T* out;
@@ -297,77 +367,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_SWEEP_WA
     }
 }
 
-// Reference-element mass (h^2/36)[4 2 1 2; 2 4 2 1; 1 2 4 2; 2 1 2 4] on a
-// corner vector: m_a = w (2 s + 2 v_a - v_opp), w = h^2/36.
-template <typename T>
-__device__ __forceinline__ void mass_accumulate(T (&e)[RS + 1][4], const T (&vals)[RS + 2], const Strip& st, T w) {
-    T prev = vals[0];
-    T prevR = shdn(prev);
-#pragma unroll
-    for (int r = 0; r < RS + 1; ++r) {
-        const T top = vals[r + 1];
-        const T topR = shdn(top);
-        const T c = ((st.emask >> r) & 1u) ? w : T(0);
-        const T s2 = T(2) * ((prev + prevR) + (topR + top));
-        e[r][0] += c * (s2 + T(2) * prev - topR);
-        e[r][1] += c * (s2 + T(2) * prevR - top);
-        e[r][2] += c * (s2 + T(2) * topR - prev);
-        e[r][3] += c * (s2 + T(2) * top - prevR);
-        prev = top;
-        prevR = topR;
-    }
-}
-
-// Corner sums of the SG stiffness strip -> element results scaled by -s.
-template <typename T>
-__device__ __forceinline__ void stiff_to_element(T (&v)[RS + 1][4], T s) {
-#pragma unroll
-    for (int r = 0; r < RS + 1; ++r) {
-        T k0, k1, k2, k3;
-        kref(v[r][0], v[r][1], v[r][2], v[r][3], k0, k1, k2, k3);
-        v[r][0] = -s * k0;
-        v[r][1] = -s * k1;
-        v[r][2] = -s * k2;
-        v[r][3] = -s * k3;
-    }
-}
-
-// Node values from per-element results e[r][.] (element rows y0-1+r): node
-// (X, Y) sums corners 0 and 3 of its own lane's element rows r and r-1 and
-// corners 1 and 2 of the lane to the left; non-interior nodes get zero.
-template <typename T>
-__device__ __forceinline__ void emit_nodes(const T (&e)[RS + 1][4], const Strip& st, int gl, int X, int n,
-                                           T* __restrict__ out) {
-    const bool xout = gl >= 1 && gl <= GOUT && X <= n;
-#pragma unroll
-    for (int r = 1; r < RS + 1; ++r) {
-        const T A = e[r][0] + e[r - 1][3];
-        const T Bl = shup(e[r][1] + e[r - 1][2]);
-        const int Y = st.y0 - 1 + r;
-        if (xout && Y <= n) out[(int64_t)Y * (n + 1) + X] = ((st.nmask >> r) & 1u) ? A + Bl : T(0);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void zero_strip(T (&v)[RS + 1][4]) {
-#pragma unroll
-    for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
-}
-
-// Fused KKT apply, one output chaos column per wavefront, three residual blocks
-// in turn.  With the SG stiffness A (mean included) and Q1 mass M:
-//   steady (eq. stoch-system):  R^Y = M Y H^gamma - A L,  R^U = beta M U + M L,  R^L = M U - A Y
-//   time (eq. KKT:stoch-time-dependent, backward Euler, D = diag(1/2, 1, .., 1, 1/2)):
-//     R^Y_t = tau D_t M_gamma Y_t - M L_t - tau A L_t + M L_{t+1}
-//     R^U_t = beta tau D_t M U_t + tau M L_t
-//     R^L_t = -M Y_t - tau A Y_t + M Y_{t-1} + tau M U_t
-// Each block is (mass of a combination of diagonal columns) - s (stiffness strip),
-// formed per element and assembled once.
-#ifndef SG_KKT_WAVES
-#define SG_KKT_WAVES 3
-#endif
-template <typename T, bool TIME>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_KKT_WAVES))) void k_sgx_kkt(
+template <typename T, bool TIME, int RS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(RS, sizeof(T))))) void k_sgx_kkt(
     int n, int M, int nxi, int nt, int64_t nodes, OpDev op, SweepGeom g, const T* __restrict__ x,
     T* __restrict__ y) {
     const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -408,38 +409,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SG_KKT_WAVE
     const T hgj = j == 0 ? T(1) : T(md.hg);
     const T beta = T(md.beta);
     const T c0 = T(md.c0);
-    Strip st;
+    using S = Sweep<RS>;
+    typename S::Strip st;
     st.init(n, X, y0);
     T v[RS + 1][4];
     T vals[RS + 2];
     // R^Y
-    zero_strip(v);
-    sg_strip(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
-    stiff_to_element(v, tau);
-    load_col(vals, Yt + cj, st, tau * Dt * hgj, false);
+    S::zero_strip(v);
+    S::sg_strip(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
+    S::stiff_to_element(v, tau);
+    S::load_col(vals, Yt + cj, st, tau * Dt * hgj, false);
     if (TIME) {
-        load_col(vals, Lt + cj, st, T(-1), true);
-        if (t + 1 < nt) load_col(vals, Lt + tst + cj, st, T(1), true);
+        S::load_col(vals, Lt + cj, st, T(-1), true);
+        if (t + 1 < nt) S::load_col(vals, Lt + tst + cj, st, T(1), true);
     }
-    mass_accumulate(v, vals, st, w);
-    emit_nodes(v, st, gl, X, n, RY);
+    S::mass_accumulate(v, vals, st, w);
+    S::emit_nodes(v, st, gl, X, n, RY);
     // R^L
-    zero_strip(v);
-    sg_strip(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
-    stiff_to_element(v, tau);
-    load_col(vals, Ut + cj, st, tau, false);
+    S::zero_strip(v);
+    S::sg_strip(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
+    S::stiff_to_element(v, tau);
+    S::load_col(vals, Ut + cj, st, tau, false);
     if (TIME) {
-        load_col(vals, Yt + cj, st, T(-1), true);
-        if (t > 0) load_col(vals, Yt - tst + cj, st, T(1), true);
+        S::load_col(vals, Yt + cj, st, T(-1), true);
+        if (t > 0) S::load_col(vals, Yt - tst + cj, st, T(1), true);
     }
-    mass_accumulate(v, vals, st, w);
-    emit_nodes(v, st, gl, X, n, RL);
+    S::mass_accumulate(v, vals, st, w);
+    S::emit_nodes(v, st, gl, X, n, RL);
     // R^U
-    zero_strip(v);
-    load_col(vals, Ut + cj, st, beta * tau * Dt, false);
-    load_col(vals, Lt + cj, st, tau, true);
-    mass_accumulate(v, vals, st, w);
-    emit_nodes(v, st, gl, X, n, RU);
+    S::zero_strip(v);
+    S::load_col(vals, Ut + cj, st, beta * tau * Dt, false);
+    S::load_col(vals, Lt + cj, st, tau, true);
+    S::mass_accumulate(v, vals, st, w);
+    S::emit_nodes(v, st, gl, X, n, RU);
 }
 
 SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
@@ -455,15 +457,25 @@ SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
 
 }  // namespace
 
+#define SG_ROWS_DISPATCH(rows, LAUNCH)                                                     \
+    do {                                                                                   \
+        switch (rows) {                                                                    \
+            case 2: { constexpr int R = 2; LAUNCH; } break;                                \
+            case 8: { constexpr int R = 8; LAUNCH; } break;                                \
+            default: { constexpr int R = 4; LAUNCH; } break;                               \
+        }                                                                                  \
+    } while (0)
+
 // Returns false when the sweep kernels do not cover the shape (M > 8).
 template <typename T>
 bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
     if (s.M > KMAX) return false;
     ColMap z{};
-    const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, RS);
+    const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_APPLY];
+    const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_sgx<T, 0>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, g, x, y, 0,
-                       0, 0u, 1, 1, (const T*)nullptr, z, z, z);
+    SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 0, R>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt,
+                                              s.nodes, op, g, x, y, 0, 0, 0u, 1, 1, (const T*)nullptr, z, z, z));
     SG_HIP(hipGetLastError());
     return true;
 }
@@ -471,14 +483,15 @@ bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nve
 template <typename T>
 bool launch_sgx_kkt(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
     if (s.M > KMAX) return false;
-    const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, RS);
+    const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_KKT];
+    const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
     if (s.time)
-        hipLaunchKernelGGL((k_sgx_kkt<T, true>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, g,
-                           x, y);
+        SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx_kkt<T, true, R>), dim3(grid), dim3(256), 0, st, s.n, s.M,
+                                                  s.nxi, s.nt, s.nodes, op, g, x, y));
     else
-        hipLaunchKernelGGL((k_sgx_kkt<T, false>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op,
-                           g, x, y);
+        SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx_kkt<T, false, R>), dim3(grid), dim3(256), 0, st, s.n, s.M,
+                                                  s.nxi, s.nt, s.nodes, op, g, x, y));
     SG_HIP(hipGetLastError());
     return true;
 }
@@ -489,10 +502,12 @@ bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, i
                         hipStream_t st) {
     if (s.M > KMAX) return false;
     const int L = s.off[d + 1] - s.off[d];
-    const SweepGeom g = make_geom(s.n, L, (int64_t)nmembers * s.nt, RS);
+    const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_HGS];
+    const SweepGeom g = make_geom(s.n, L, (int64_t)nmembers * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
-    hipLaunchKernelGGL((k_sgx<T, 1>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, g, V, out,
-                       s.off[d], L, mask, use_lower, use_upper, base, bmap, vmap, omap);
+    SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 1, R>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt,
+                                              s.nodes, op, g, V, out, s.off[d], L, mask, use_lower, use_upper, base,
+                                              bmap, vmap, omap));
     SG_HIP(hipGetLastError());
     return true;
 }

@@ -209,6 +209,50 @@ def test_solve_fp32_refine_reaches_fp64_accuracy():
         assert rel_max(a, b) < 1e-8
 
 
+@pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[3]])
+def test_sweep_rows_bit_identical(shape):
+    """The strip heights the autotuner chooses between (2, 4, 8 node rows) give
+    bit-identical operator, KKT and preconditioner applies, FP64 and FP32, and
+    identical solves; the autotuned handle reports a valid choice."""
+    n, M, P, sigma, beta, gamma, nt = shape
+    dev = _dev()
+    _say(f"sweep rows {shape}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, y0=nt > 1)
+    rng = np.random.default_rng(11)
+    outs = {}
+    for rows in (2, 4, 8, 0):
+        h = _setup([kw], rtol=1e-10, sweep_rows=rows, precision=2)
+        tuned = [list(r) for r in h.sizes.sweep_rows]
+        assert all(v in (2, 4, 8) for r in tuned for v in r), tuned
+        if rows:
+            assert all(v == rows for r in tuned for v in r), tuned
+        x = torch.from_numpy(rng.uniform(-1, 1, size=h.kkt_elems)) if not outs else outs["x"]
+        outs["x"] = x
+        xd = x.to(dev)
+        res = []
+        for dt in (torch.float64, torch.float32):
+            xi = xd.to(dt)
+            for fn in (h.apply_kkt, h.precond_apply):
+                y = torch.zeros_like(xi)
+                fn(xi, y)
+                res.append(y)
+            xo = xi[: h.sizes.block_elems].contiguous()
+            yo = torch.zeros_like(xo)
+            h.apply_operator(xo, yo)
+            res.append(yo)
+        sol = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+        rc, info = h.solve(sol)
+        assert rc == 0
+        res.append(sol)
+        torch.cuda.synchronize()
+        if "ref" not in outs:
+            outs["ref"] = res
+        else:
+            for a, b in zip(res, outs["ref"]):
+                assert torch.equal(a, b), rows
+        h.close()
+
+
 def test_solve_fp32_preconditioner_tracks_fp64():
     """FP32 preconditioner inside FP64 FGMRES: reaches the direct solution and
     needs about the FP64 iteration count (the operator stays FP64)."""
