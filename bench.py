@@ -129,6 +129,44 @@ def sg_apply_bandwidth(torch, sgl, probs, stream, min_bytes=1 << 30, reps=20):
     return dict(ms=ms, bytes=bytes_per, GBps=bytes_per / ms / 1e6, buffers=nbuf)
 
 
+def serving_run(sgl, sg_inputs, num, rate, grids, precision):
+    """Continuous-batching server (sg_submit / sg_poll) on a seeded Poisson
+    stream of mixed-shape steady requests; latency is submit -> completion
+    and includes the host <-> device copies of the request's arrays."""
+    from math import comb
+    reqs = sg_inputs.serving_stream(num, seed=7, rate_per_s=rate, grid_choices=grids)
+    srv = sgl.Server(hbm_budget_bytes=0, max_slots=16)
+    opts = sgl.default_options(rtol=1e-8, precision=precision)
+    pending, converged = {}, 0
+    t0 = time.perf_counter()
+
+    def drain():
+        nonlocal converged
+        for t in list(pending):
+            rc, info = srv.poll(t)
+            if rc != sgl.SG_PENDING:
+                converged += int(rc == sgl.SG_OK and info.converged == 1)
+                del pending[t]          # releases the host output array
+
+    for r in reqs:
+        while time.perf_counter() - t0 < r["arrival"]:
+            drain()
+            time.sleep(0.0005)
+        pd = sgl.ProblemData(r["n"], r["M"], r["P"], r["sigma"], r["beta"], sg_inputs.gaussian_bumps(r["n"], r["seed"]))
+        out = np.empty(3 * comb(r["M"] + r["P"], r["P"]) * (r["n"] + 1) ** 2)
+        pending[srv.submit(pd, out, opts)] = out
+    while pending:
+        drain()
+        time.sleep(0.001)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return {"requests": num, "arrival_rate_per_s": rate, "grids": list(grids), "M_range": [4, 8],
+            "P_range": [2, 4], "precision": {0: "fp64", 1: "fp32_refine", 2: "fp32_precond"}[precision],
+            "converged": converged, "wall_s": wall, "solves_per_s": num / wall, "p50_ms": st["p50_ms"],
+            "p99_ms": st["p99_ms"]}
+
+
 def cpu_baseline(wl, gpu_iters):
     """The oracle (plain FP64 numpy/scipy, single thread) timed on one
     preconditioned FGMRES iteration of the first member: one preconditioner
@@ -173,6 +211,9 @@ def main():
     ap.add_argument("--profile-kernel", default="auto", choices=["auto"] + sorted(PROF_KIND),
                     help="kernel reported as roofline (auto: the one with the largest measured total time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=32, help="requests in the serving stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=30.0, help="Poisson arrival rate of the serving stream")
+    ap.add_argument("--serve-grids", default="32,64", help="grid sizes n the serving stream draws from")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (calibrates hardware byte counters) and exit")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
@@ -277,6 +318,9 @@ def main():
         out["fp64_single"] = {"value": len(probs) / t_single, "unit": "solves/s", "iterations": single}
         out["sg_apply"] = sg_apply_bandwidth(torch, sgl, probs, stream)
         out["sg_apply"]["frac_of_hbm_peak"] = out["sg_apply"]["GBps"] / HBM_PEAK_GBPS
+    if not args.no_extras and args.serve_requests > 0:
+        grids = tuple(int(g) for g in args.serve_grids.split(","))
+        out["serving"] = serving_run(sgl, sg_inputs, args.serve_requests, args.serve_rate, grids, 0)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, float(np.mean(iters)))
     print(json.dumps(out), flush=True)
