@@ -114,6 +114,26 @@ __device__ __forceinline__ int next_term(int k, int j, int M, const int32_t* __r
 // same terms per node in the same order).
 template <int RS>
 struct Sweep {
+    static constexpr int ER = 2 * RS + 1;   // element rows of a block's tile (both strips)
+
+    // Coefficient modes 1..M of the block's element tile (element rows
+    // ybase-1 .. ybase+2RS-1, element columns of the 32 lanes), zero off the
+    // grid, into LDS as [mode-1][row][lane]: the block's four wavefronts then
+    // read them from LDS instead of through the vector memory path, which
+    // bounds the sweeps (it is close to fully busy while L2 is not).
+    template <typename T>
+    static __device__ __forceinline__ void stage_coef(T* sc, const T* __restrict__ coef, int64_t cplane, int M, int n,
+                                                      int tx, int ty) {
+        const int ybase = ty * 2 * RS;
+        const int total = M * ER * GW;
+        for (int q = threadIdx.x; q < total; q += 256) {
+            const int ln = q % GW, r = (q / GW) % ER, k = q / (GW * ER);
+            const int X = tx * GOUT + ln - 1;
+            const int ey = ybase - 1 + r;
+            const bool ok = X >= 0 && X <= n - 1 && ey >= 0 && ey <= n - 1;
+            sc[q] = ok ? coef[(int64_t)(k + 1) * cplane + (int64_t)ey * n + X] : T(0);
+        }
+    }
     // Per-lane strip geometry: node rows y0-1 .. y0+RS (RS+2 rows) and element
     // rows y0-1 .. y0+RS-1 (RS+1 rows) of node column X.  Offsets are clamped into
     // the grid so that every load is in bounds; the masks zero what lies on the
@@ -189,7 +209,8 @@ struct Sweep {
     static __device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
                                              int j, int M, const int32_t* __restrict__ nidx,
                                              const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
-                                             bool with_mean, T c0, const T* __restrict__ coef, int64_t cplane) {
+                                             bool with_mean, T c0, const T* __restrict__ sc, int grp, int gl,
+                                             const T* __restrict__ coef, int64_t cplane) {
         T vals[RS + 2], nvals[RS + 2];
         T c[RS + 1];
         Term<T> cur, nxt;
@@ -201,11 +222,17 @@ struct Sweep {
             const int kn = next_term(k + 1, j, M, nidx, nval, mask, lower, upper, nxt);
             const bool more = kn < M;
             if (more) load_term(nvals, nxt, F, nodes, st);
-            const T* ck = coef + (int64_t)(k + 1) * cplane;
+            if (k < 0) {
     #pragma unroll
-            for (int r = 0; r < RS + 1; ++r) {
-                const T cv = k < 0 ? c0 : ck[st.eoff(r)];
-                c[r] = ((st.emask >> r) & 1u) ? cv : T(0);
+                for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? c0 : T(0);
+            } else if (sc) {
+                const T* ck = sc + (k * ER + grp * RS) * GW + gl;    // staged, zero off the grid
+    #pragma unroll
+                for (int r = 0; r < RS + 1; ++r) c[r] = ck[r * GW];
+            } else {
+                const T* ck = coef + (int64_t)(k + 1) * cplane;
+    #pragma unroll
+                for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? ck[st.eoff(r)] : T(0);
             }
             corner_accumulate(v, vals, c);
             if (!more) break;
@@ -304,6 +331,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = chunk * 4 + wave;                  // output column index (in the level for KIND 1)
     const int ncols = KIND == 0 ? nxi : L;
+    using S = Sweep<RS>;
     if (l >= ncols) return;                          // uniform per wavefront; no block barriers below
     const int j = KIND == 0 ? l : j0lvl + l;
     const int lane = threadIdx.x & 63;
@@ -314,19 +342,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
     const int mem_i = slice / nt;
     const int t = slice % nt;
     const int mem = op.mem_shared ? 0 : mem_i;
-    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
-    const int64_t cplane = (int64_t)n * n;
     const T* F = KIND == 0 ? x + (int64_t)slice * nxi * nodes
                            : x + (int64_t)mem_i * vmap.mstride + (int64_t)t * vmap.tstride;
-    using S = Sweep<RS>;
     typename S::Strip st;
     st.init(n, X, y0);
     T v[RS + 1][4];
 #pragma unroll
     for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
     S::sg_strip(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, KIND == 0 ? 0xffffffffu : mask,
-             KIND == 0 ? true : lower != 0, KIND == 0 ? true : upper != 0, KIND == 0, T(op.mem[mem].c0), coef,
-             cplane);
+             KIND == 0 ? true : lower != 0, KIND == 0 ? true : upper != 0, KIND == 0, T(op.mem[mem].c0),
+             (const T*)nullptr, grp, gl, (const T*)op.coef + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
     T* out;
     const T* bas = nullptr;
     T scale = T(1);
@@ -381,6 +406,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int j = chunk * 4 + wave;
+    using S = Sweep<RS>;
+    // the block's four output columns run two full stiffness strips each over
+    // the same element tile: its coefficients are staged once in LDS
+    __shared__ T sc[KMAX * S::ER * GW];
+    {
+        const int mem_b = op.mem_shared ? 0 : (slice / nt);
+        S::stage_coef(sc, (const T*)op.coef + (int64_t)mem_b * op.coef_mstride, (int64_t)n * n, M, n, tx, ty);
+    }
+    __syncthreads();
     if (j >= nxi) return;                            // uniform per wavefront; no block barriers below
     const int lane = threadIdx.x & 63;
     const int gl = lane & (GW - 1);
@@ -391,8 +425,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     const int t = slice % nt;
     const int mem = op.mem_shared ? 0 : vec;
     const MemberDev md = op.mem[mem];
-    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
-    const int64_t cplane = (int64_t)n * n;
     const int64_t blk = (int64_t)nt * nxi * nodes;
     const int64_t tst = (int64_t)nxi * nodes;
     const int64_t cj = (int64_t)j * nodes;
@@ -409,14 +441,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     const T hgj = j == 0 ? T(1) : T(md.hg);
     const T beta = T(md.beta);
     const T c0 = T(md.c0);
-    using S = Sweep<RS>;
     typename S::Strip st;
     st.init(n, X, y0);
     T v[RS + 1][4];
     T vals[RS + 2];
     // R^Y
     S::zero_strip(v);
-    S::sg_strip(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
+    S::sg_strip(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc, grp, gl,
+                (const T*)nullptr, 0);
     S::stiff_to_element(v, tau);
     S::load_col(vals, Yt + cj, st, tau * Dt * hgj, false);
     if (TIME) {
@@ -427,7 +459,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     S::emit_nodes(v, st, gl, X, n, RY);
     // R^L
     S::zero_strip(v);
-    S::sg_strip(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, coef, cplane);
+    S::sg_strip(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc, grp, gl,
+                (const T*)nullptr, 0);
     S::stiff_to_element(v, tau);
     S::load_col(vals, Ut + cj, st, tau, false);
     if (TIME) {
