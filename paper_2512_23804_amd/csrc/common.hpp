@@ -217,7 +217,9 @@ struct KrylovDev {
     double* resid;    // [member] |g_{j+1}| (estimate)
     int* active;      // [member] 1 while iterating in the current cycle
     double* dots;     // [member][kSlots] reduced dot products of the current pass (DCGS2)
-    double* scal;     // [member][4] 1/rho, c, 1/nu, nu of the current candidate (DCGS2)
+    double* scal;     // [member][4] -, -, 1/nu, nu of the current candidate (DCGS2)
+    double* R;        // [member][(restart+1)^2] U = V R, upper triangular, column-major (DCGS2)
+    double* coef;     // [member][kSlots] update-pass coefficients s = R^{-1} [t; c] (DCGS2)
     int* pending;     // [member] 1 while the last Hessenberg column awaits its reorthogonalisation
 };
 void launch_arnoldi_finish(KrylovDev k, int restart, int j, int nmem, hipStream_t st);
@@ -225,7 +227,7 @@ void launch_dcgs_dots(const double* V, int64_t vstride, int nv, const double* w,
                       int64_t mstride, const int* active, const int* pending, double* partial, int nblk,
                       hipStream_t st);
 void launch_dcgs_update(double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem, int64_t mstride,
-                        const double* dots, const double* scal, const int* active, int nblk, hipStream_t st);
+                        const double* coef, const double* scal, const int* active, int nblk, hipStream_t st);
 void launch_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem, hipStream_t st);
 void launch_cycle_start(KrylovDev k, int restart, const double* beta0, int nmem, hipStream_t st);
 void launch_back_solve(KrylovDev k, int restart, const int* jend, int nmem, hipStream_t st);

@@ -698,73 +698,46 @@ __global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, 
     }
 }
 
-// Update pass: V_nv = (u - sum_i a_i V_i) / rho (in place over u, slot nv) and
-// slot nv+1 = (w - sum_i t_i V_i - c V_nv) / nu, with a_i, t_i from the dots
-// (dots[mem*kSlots + i], dots[mem*kSlots + nv + i]) and scal[mem*4 + 0..2] =
-// (1/rho, c, 1/nu).
-template <int NV>
+// Update pass: basis slot nv+1 = (w - sum_{i<=nv} s_i U_i) / nu with
+// s_i = coef[mem*kSlots + i] and 1/nu = scal[mem*4 + 2]; reads slots 0..nv and
+// w, writes slot nv+1 only.  NT >= nv + 1 terms.
+template <int NT>
 __global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int64_t vstride, int nv,
                                                     const double* __restrict__ w, int64_t n, int64_t mstride,
-                                                    const double* __restrict__ dots, const double* __restrict__ scal,
+                                                    const double* __restrict__ coef, const double* __restrict__ scal,
                                                     const int* __restrict__ active, int nblk) {
     const int mem = blockIdx.y;
     if (!active[mem]) return;                       // uniform per block, before the barrier
     int64_t lo, hi;
     chunk_range(n, nblk, blockIdx.x, lo, hi);
-    __shared__ double a[NV], t[NV];                 // broadcast reads; keeps the lanes' registers for loads
-    if ((int)threadIdx.x < NV) {
-        a[threadIdx.x] = (int)threadIdx.x < nv ? dots[mem * kSlots + threadIdx.x] : 0.0;
-        t[threadIdx.x] = (int)threadIdx.x < nv ? dots[mem * kSlots + nv + threadIdx.x] : 0.0;
-    }
+    __shared__ double sv[NT];                       // broadcast reads; keeps the lanes' registers for loads
+    if ((int)threadIdx.x < NT) sv[threadIdx.x] = (int)threadIdx.x <= nv ? coef[mem * kSlots + threadIdx.x] : 0.0;
     __syncthreads();
-    const double inv_rho = scal[mem * 4 + 0], c = scal[mem * 4 + 1], inv_nu = scal[mem * 4 + 2];
-    double* Vm = V + mem * mstride;
-    double* um = Vm + nv * vstride;
-    double* un = um + vstride;
+    const double inv_nu = scal[mem * 4 + 2];
+    const double* Vm = V + mem * mstride;
+    double* un = V + mem * mstride + (nv + 1) * vstride;
     const double* wm = w + mem * mstride;
     int64_t e = lo + threadIdx.x;
     for (; e + (kUpdU - 1) * RB < hi; e += kUpdU * RB) {
-        double ue[kUpdU], we[kUpdU], s1[kUpdU], s2[kUpdU];
+        double acc[kUpdU];
 #pragma unroll
-        for (int u = 0; u < kUpdU; ++u) {
-            ue[u] = ld_stream(um + e + u * RB);
-            we[u] = ld_stream(wm + e + u * RB);
-            s1[u] = 0.0;
-            s2[u] = 0.0;
-        }
+        for (int u = 0; u < kUpdU; ++u) acc[u] = ld_stream(wm + e + u * RB);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            if (i < nv) {
+        for (int i = 0; i < NT; ++i) {
+            if (i <= nv) {
 #pragma unroll
-                for (int u = 0; u < kUpdU; ++u) {
-                    const double v = ld_stream(Vm + i * vstride + e + u * RB);
-                    s1[u] += a[i] * v;
-                    s2[u] += t[i] * v;
-                }
+                for (int u = 0; u < kUpdU; ++u) acc[u] -= sv[i] * ld_stream(Vm + i * vstride + e + u * RB);
             }
         }
 #pragma unroll
-        for (int u = 0; u < kUpdU; ++u) {
-            const double vj = (ue[u] - s1[u]) * inv_rho;
-            um[e + u * RB] = vj;
-            un[e + u * RB] = (we[u] - s2[u] - c * vj) * inv_nu;
-        }
+        for (int u = 0; u < kUpdU; ++u) un[e + u * RB] = acc[u] * inv_nu;
     }
     for (; e < hi; e += RB) {
-        const double ue = ld_stream(um + e);
-        const double we = ld_stream(wm + e);
-        double s1 = 0.0, s2 = 0.0;
+        double acc = ld_stream(wm + e);
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            if (i < nv) {
-                const double v = ld_stream(Vm + i * vstride + e);
-                s1 += a[i] * v;
-                s2 += t[i] * v;
-            }
-        }
-        const double vj = (ue - s1) * inv_rho;
-        um[e] = vj;
-        un[e] = (we - s2 - c * vj) * inv_nu;
+        for (int i = 0; i < NT; ++i)
+            if (i <= nv) acc -= sv[i] * ld_stream(Vm + i * vstride + e);
+        un[e] = acc * inv_nu;
     }
 }
 
@@ -916,12 +889,16 @@ __device__ void givens_column(double* col, double* cs, double* sn, double* g, in
 }
 
 // DCGS2 bookkeeping of iteration j (mode 0) or of the last column (mode 1).
-// Commit: the candidate u_j of the previous iteration is u_j = sum_i a_i V_i +
-// rho V_j (rho^2 = u.u - |a|^2), so column j-1 (raw entries t, c, nu) becomes
-// [t + nu a, c + nu a_{j-1}, nu rho] and gets its Givens rotation.
-// Provisional (mode 0, active members): column j = [t, c, nu] with
+// The basis slots keep the candidates U_i (never rewritten); the orthonormal
+// basis is V = U R^{-1} with R upper triangular (R column i = [a; rho] from
+// U_i = sum_l a_l V_l + rho V_i), so dots against U become dots against V by a
+// triangular solve.  Commit: the candidate u_j of the previous iteration gives
+// a = V_{<j}^T u_j, rho^2 = u.u - |a|^2, and column j-1 (raw entries t, c, nu)
+// becomes [t + nu a, c + nu a_{j-1}, nu rho] and gets its Givens rotation.
+// Provisional (mode 0, active members): column j = [t, c, nu] with t = V^T w,
 // c = (u.w - a.t) / rho and nu^2 = w.w - |t|^2 - c^2 (one Gram-Schmidt pass);
-// its rotation on a copy gives the residual estimate used to stop.
+// its rotation on a copy gives the residual estimate used to stop.  The
+// update pass then needs s = R^{-1} [t; c]: u_{j+1} = (w - sum_{i<=j} s_i U_i) / nu.
 __global__ void k_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem) {
     const int mem = blockIdx.x * blockDim.x + threadIdx.x;
     if (mem >= nmem) return;
@@ -929,45 +906,64 @@ __global__ void k_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nme
     const int nv = j;
     const double* D = k.dots + (int64_t)mem * kSlots;
     double* H = k.H + (int64_t)mem * ld * restart;
+    double* R = k.R + (int64_t)mem * ld * ld;      // R[l + i*ld] = R(l, i)
     double* cs = k.cs + mem * restart;
     double* sn = k.sn + mem * restart;
     double* g = k.g + mem * ld;
     double* sc = k.scal + mem * 4;
-    double inv_rho = 1.0;
+    double a[32], t[32];
+    // out = R_{<j}^{-T} d (forward substitution)
+    auto lower_solve = [&](const double* d, double* out) {
+        for (int l = 0; l < nv; ++l) {
+            double v = d[l];
+            for (int p = 0; p < l; ++p) v -= R[p + l * ld] * out[p];
+            const double dl = R[l + l * ld];
+            out[l] = dl != 0.0 ? v / dl : 0.0;
+        }
+    };
+    double rho = 1.0;                              // R(0, 0) = 1: U_0 = V_0
     if (j >= 1 && k.pending[mem]) {
+        lower_solve(D, a);
         const double alpha = mode ? D[nv] : D[2 * nv];
         double a2 = 0.0;
-        for (int i = 0; i < nv; ++i) a2 += D[i] * D[i];
-        const double rho = sqrt(fmax(alpha - a2, 0.0));
+        for (int i = 0; i < nv; ++i) a2 += a[i] * a[i];
+        rho = sqrt(fmax(alpha - a2, 0.0));
+        for (int l = 0; l < nv; ++l) R[l + j * ld] = a[l];
+        R[j + j * ld] = rho;
         const double nu = sc[3];
         double* col = H + (int64_t)(j - 1) * ld;
-        for (int i = 0; i < nv; ++i) col[i] += nu * D[i];
+        for (int i = 0; i < nv; ++i) col[i] += nu * a[i];
         col[j] = nu * rho;
         givens_column(col, cs, sn, g, j - 1);
         k.resid[mem] = fabs(g[j]);
-        inv_rho = rho > 0.0 ? 1.0 / rho : 0.0;
         k.pending[mem] = 0;
     }
     if (mode != 0 || !k.active[mem]) return;
+    lower_solve(D + nv, t);
     double at = 0.0, t2 = 0.0;
     for (int i = 0; i < nv; ++i) {
-        at += D[i] * D[nv + i];
-        t2 += D[nv + i] * D[nv + i];
+        at += a[i] * t[i];
+        t2 += t[i] * t[i];
     }
-    const double c = (D[2 * nv + 1] - at) * inv_rho;
+    const double c = rho > 0.0 ? (D[2 * nv + 1] - at) / rho : 0.0;
     const double nu = sqrt(fmax(D[2 * nv + 2] - t2 - c * c, 0.0));
     double* col = H + (int64_t)j * ld;
-    for (int i = 0; i < nv; ++i) col[i] = D[nv + i];
+    for (int i = 0; i < nv; ++i) col[i] = t[i];
     col[j] = c;
     col[j + 1] = nu;
     // provisional rotation: entry j of the column after rotations 0..j-1
     double xr = col[0];
     for (int i = 0; i < j; ++i) xr = -sn[i] * xr + cs[i] * col[i + 1];
     const double den = hypot(xr, nu);
-    const double pr = den > 0.0 ? fabs(nu / den * g[j]) : 0.0;
-    k.resid[mem] = pr;
-    sc[0] = inv_rho;
-    sc[1] = c;
+    k.resid[mem] = den > 0.0 ? fabs(nu / den * g[j]) : 0.0;
+    // s = R_{<=j}^{-1} [t; c] (back substitution)
+    double* sv = k.coef + (int64_t)mem * kSlots;
+    for (int l = j; l >= 0; --l) {
+        double v = l == j ? c : t[l];
+        for (int p = l + 1; p <= j; ++p) v -= R[l + p * ld] * sv[p];
+        const double dl = R[l + l * ld];
+        sv[l] = dl != 0.0 ? v / dl : 0.0;
+    }
     sc[2] = nu > 0.0 ? 1.0 / nu : 0.0;
     sc[3] = nu;
     k.pending[mem] = 1;
@@ -985,6 +981,7 @@ __global__ void k_cycle_start(KrylovDev k, int restart, const double* beta0sq, i
     k.resid[mem] = b;
     k.pending[mem] = 0;
     k.scal[mem * 4 + 3] = 1.0;     // V_0 = r / ||r|| is final as written
+    k.R[(int64_t)mem * ld * ld] = 1.0;
 }
 
 // y = R^{-1} g on the leading jend x jend block (upper triangular after Givens).
@@ -1179,9 +1176,9 @@ void launch_dcgs_dots(const double* V, int64_t vstride, int nv, const double* w,
 }
 
 void launch_dcgs_update(double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem, int64_t mstride,
-                        const double* dots, const double* scal, const int* active, int nblk, hipStream_t st) {
+                        const double* coef, const double* scal, const int* active, int nblk, hipStream_t st) {
     if (nv > MAXV - 2) throw Error(SG_ERR_INVALID, "dcgs: too many vectors");
-    SG_NV_DISPATCH(k_dcgs_update, nv, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, w, n, mstride, dots, scal,
+    SG_NV_DISPATCH(k_dcgs_update, nv + 1, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, w, n, mstride, coef, scal,
                    active, nblk);
     SG_HIP(hipGetLastError());
 }

@@ -266,6 +266,8 @@ struct Krylov {
         kd.dots = h.ws.get_t<double>("kdots", (size_t)B * kSlots);
         kd.scal = h.ws.get_t<double>("kscal", (size_t)B * 4);
         kd.pending = h.ws.get_t<int>("kpend", (size_t)B);
+        kd.R = h.ws.get_t<double>("kR", (size_t)B * ld * ld);
+        kd.coef = h.ws.get_t<double>("kcoef", (size_t)B * kSlots);
         d_jend = h.ws.get_t<int>("kjend", (size_t)B);
         v32 = z32 ? h.ws.get_t<float>("kv32", (size_t)B * N) : nullptr;
         w32 = op32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
@@ -373,17 +375,17 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
             K.apply_prec(j);
             K.apply_op_z(j);
             if (dcgs) {
-                // DCGS2: slot j holds the candidate u_j; one read-only pass gives the
-                // reorthogonalisation of u_j and the projections of w, one update
-                // pass finalises V_j and writes the next candidate u_{j+1}
+                // DCGS2: the basis slots hold the candidates U (V = U R^{-1}); one
+                // read-only pass gives the reorthogonalisation of u_j and the
+                // projections of w, one update pass writes the next candidate u_{j+1}
                 bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
                 launch_dcgs_dots(K.V, vs, j, K.w, N, B, N, K.kd.active, K.kd.pending, K.partial, K.nblk, st);
                 if (tp) prof_end(h, st, 8.0 * (j + 2) * (double)B * N);
                 launch_reduce_partials(K.partial, K.nblk, 2 * j + 3, B, K.kd.dots, kSlots, 0, st);
                 launch_dcgs_finish(K.kd, m, j, 0, B, st);
                 tp = prof_begin(h, SG_PROF_ARNOLDI_UPD, st);
-                launch_dcgs_update(K.V, vs, j, K.w, N, B, N, K.kd.dots, K.kd.scal, K.kd.active, K.nblk, st);
-                if (tp) prof_end(h, st, 8.0 * (j + 4) * (double)B * N);
+                launch_dcgs_update(K.V, vs, j, K.w, N, B, N, K.kd.coef, K.kd.scal, K.kd.active, K.nblk, st);
+                if (tp) prof_end(h, st, 8.0 * (j + 3) * (double)B * N);   // read U_0..U_j and w, write u_{j+1}
                 return;
             }
             const int nv = j + 1;
