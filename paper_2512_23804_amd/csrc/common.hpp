@@ -152,18 +152,19 @@ template <typename T>
 void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap, T* W, ColMap wmap,
                         int ncols, int nvec_members, hipStream_t st);
 
-// Fused multigrid levels (mg.hip): down = nu pre-smoothing steps from zero +
-// residual + restriction; up = prolongation of the coarse correction + nu
-// post-smoothing steps.  Coarse arrays are contiguous [column][(m/2+1)^2].
+// Fused multigrid levels (mg.hip): down = npre pre-smoothing steps from zero +
+// residual + restriction; up = the same pre-smoothing recomputed from b +
+// prolongation of the coarse correction + npost post-smoothing steps.  Coarse
+// arrays are contiguous [column][(m/2+1)^2].
 template <typename T>
-void launch_mg_down(int m, const LevelDev* lev, int lvl, int nu, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc,
-                    int ncols, int cpm, hipStream_t st);
+void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, int ncols, int cpm,
+                    hipStream_t st);
+template <typename T>
+void launch_mg_up(int m, const LevelDev* lev, int lvl, int npre, int npost, const T* ec, const T* b, ColMap bmap,
+                  T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st);
 template <typename T>
 void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x,
                     ColMap xmap, const T* ainv, int ncols, int cpm, hipStream_t st);
-template <typename T>
-void launch_mg_up(int m, const LevelDev* lev, int lvl, int nu, const T* xin, ColMap xinmap, const T* ec, const T* b,
-                  ColMap bmap, T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st);
 
 // All Chebyshev mass steps in one LDS-tiled kernel; false when steps > 9.
 template <typename T>

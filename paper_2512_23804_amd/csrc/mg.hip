@@ -25,45 +25,26 @@ __device__ __forceinline__ T st9(const T* s, int W, int i, T wc, T we, T wd) {
            wd * (s[i - W - 1] + s[i - W + 1] + s[i + W - 1] + s[i + W + 1]);
 }
 
-// down: coarse tile of TC x TC coarse nodes starting at (I0, J0) = 1 + TC (tx, ty),
-// owning the fine nodes [2 I0 - 1, 2 I0 + 2 TC - 1) per side.
-// Fine region: origin (2 I0 - 1 - NU, 2 J0 - 1 - NU), width W = 2 TC + 1 + 2 NU.
-// Only the iterate (read by the stencil) is in LDS; b, the step direction and
-// the new iterate of the region nodes a thread owns stay in its registers, and
-// the LDS array is reused for the residual that the restriction reads.
-template <typename T, int TC, int NU>
-__global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restrict__ lev, int lvl,
-                                                 const T* __restrict__ b, ColMap bmap, T* __restrict__ xo,
-                                                 ColMap xmap, T* __restrict__ bc, int cpm, int tiles_x) {
-    constexpr int W = 2 * TC + 1 + 2 * NU;
-    constexpr int PPT = (W * W + 255) / 256;
-    __shared__ T sx[W * W];
-    const int c = blockIdx.y;
-    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int I0 = 1 + tx * TC, J0 = 1 + ty * TC;
-    const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;     // also write the ring at index 0
-    const int FX0 = 2 * I0 - 1 - NU, FY0 = 2 * J0 - 1 - NU;
-    const int mc = m / 2;
-    const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
-    const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
-    const T* bcol = b + bmap.off(c);
-    const int N1 = m + 1;
-    T breg[PPT], d[PPT], xr[PPT];
-    // load b; x_1 = d_1 = c_r D^{-1} b
+// Pre-smoothing from a zero guess on a W x W region: x_1 = c_r D^{-1} b, then
+// NPRE-1 Chebyshev steps, step s updating [s, W-s).  The iterate is in LDS
+// (sx, read by the stencil); b, the step direction and the iterate of the
+// thread's nodes are in registers.  Shared by the down kernel and by the up
+// kernel, which recomputes the pre-smoothed iterate from b (same arithmetic)
+// instead of reading it back from memory.
+template <typename T, int W, int PPT, int NPRE>
+__device__ __forceinline__ void pre_smooth(const T (&breg)[PPT], T (&d)[PPT], T (&xr)[PPT], T* sx, int FX0, int FY0,
+                                           int m, const LevelDev& L, T wc, T we, T wd, T dinv) {
     const T cr0 = T(L.pre[0][1]);
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int q = threadIdx.x + 256 * p;
-        const int X = FX0 + q % W, Y = FY0 + q / W;
-        const bool inter = q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
-        breg[p] = inter ? bcol[Y * N1 + X] : T(0);
-        xr[p] = cr0 * dinv * breg[p];
+        xr[p] = cr0 * dinv * breg[p];          // b is zero off the interior
         d[p] = xr[p];
         if (q < W * W) sx[q] = xr[p];
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 1; s < NU; ++s) {
+    for (int s = 1; s < NPRE; ++s) {
         const T cd = T(L.pre[s][0]), cr = T(L.pre[s][1]);
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
@@ -85,6 +66,42 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
         }
         __syncthreads();
     }
+}
+
+template <typename T, int W, int PPT>
+__device__ __forceinline__ void load_region(T (&breg)[PPT], const T* __restrict__ bcol, int FX0, int FY0, int m) {
+    const int N1 = m + 1;
+#pragma unroll
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
+        const int X = FX0 + q % W, Y = FY0 + q / W;
+        const bool inter = q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
+        breg[p] = inter ? bcol[Y * N1 + X] : T(0);
+    }
+}
+
+// down: coarse tile of TC x TC coarse nodes starting at (I0, J0) = 1 + TC (tx, ty).
+// Fine region: origin (2 I0 - 1 - NU, 2 J0 - 1 - NU), width W = 2 TC + 1 + 2 NU:
+// pre-smoothing from zero (NU steps), residual, restriction b_c = P^T r.  The
+// pre-smoothed iterate is not stored (the up kernel recomputes it).
+template <typename T, int TC, int NU>
+__global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restrict__ lev, int lvl,
+                                                 const T* __restrict__ b, ColMap bmap, T* __restrict__ bc, int cpm,
+                                                 int tiles_x) {
+    constexpr int W = 2 * TC + 1 + 2 * NU;
+    constexpr int PPT = (W * W + 255) / 256;
+    __shared__ T sx[W * W];
+    const int c = blockIdx.y;
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int I0 = 1 + tx * TC, J0 = 1 + ty * TC;
+    const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;     // also write the ring at index 0
+    const int FX0 = 2 * I0 - 1 - NU, FY0 = 2 * J0 - 1 - NU;
+    const int mc = m / 2;
+    const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
+    const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
+    T breg[PPT], d[PPT], xr[PPT];
+    load_region<T, W, PPT>(breg, b + bmap.off(c), FX0, FY0, m);
+    pre_smooth<T, W, PPT, NU>(breg, d, xr, sx, FX0, FY0, m, L, wc, we, wd, dinv);
     // residual on [NU, W-NU) (into registers, then over the iterate in LDS)
     T rr[PPT];
 #pragma unroll
@@ -103,16 +120,6 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
         const int q = threadIdx.x + 256 * p;
         if (q < W * W) sx[q] = rr[p];
     }
-    // smoothed x on the owned fine nodes [2 I0 - 1, 2 I0 + 2 TC - 1) (ring nodes hold 0)
-    T* xcol = xo + xmap.off(c);
-#pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const int q = threadIdx.x + 256 * p;
-        const int X = FX0 + q % W, Y = FY0 + q / W;
-        if (q < W * W && X >= 2 * I0 - 1 - ex && X < 2 * I0 + 2 * TC - 1 && Y >= 2 * J0 - 1 - ey &&
-            Y < 2 * J0 + 2 * TC - 1 && X <= m && Y <= m)
-            xcol[Y * N1 + X] = xr[p];
-    }
     __syncthreads();
     // restriction (R = P^T: 1 centre, 1/2 edge partners, 1/4 corner partners)
     T* bco = bc + (int64_t)c * (mc + 1) * (mc + 1);
@@ -130,50 +137,54 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
     }
 }
 
-// up: fine tile of TF x TF nodes starting at (X0, Y0) = 1 + TF (tx, ty); region with halo NU.
-// The iterate is in LDS; b, the step direction and the new iterate in registers.
-template <typename T, int TF, int NU>
+// up: fine tile of TF x TF nodes starting at (X0, Y0) = 1 + TF (tx, ty), region
+// with halo H = NPOST + NPRE - 1: the pre-smoothed iterate is recomputed from b
+// (valid on [NPRE-1, W-NPRE+1)), the interpolated coarse correction added, and
+// NPOST post-smoothing steps run; the owned tile is written.
+template <typename T, int TF, int NPRE, int NPOST>
 __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict__ lev, int lvl,
-                                               const T* __restrict__ xin, ColMap xinmap, const T* __restrict__ ec,
-                                               const T* __restrict__ b, ColMap bmap, T* __restrict__ xo, ColMap xomap,
-                                               int cpm, int tiles_x) {
-    constexpr int W = TF + 2 * NU;
+                                               const T* __restrict__ ec, const T* __restrict__ b, ColMap bmap,
+                                               T* __restrict__ xo, ColMap xomap, int cpm, int tiles_x) {
+    constexpr int H0 = NPRE - 1;
+    constexpr int H = NPOST + H0;
+    constexpr int W = TF + 2 * H;
     constexpr int PPT = (W * W + 255) / 256;
     __shared__ T sx[W * W];
     const int c = blockIdx.y;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int FX0 = 1 + tx * TF - NU, FY0 = 1 + ty * TF - NU;
+    const int FX0 = 1 + tx * TF - H, FY0 = 1 + ty * TF - H;
     const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;
     const int mc = m / 2;
     const LevelDev& L = lev[(c / cpm) * kMaxLevels + lvl];
     const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
     const int N1 = m + 1, C1 = mc + 1;
-    const T* xcol = xin + xinmap.off(c);
-    const T* bcol = b + bmap.off(c);
     const T* ecol = ec + (int64_t)c * C1 * C1;
     T breg[PPT], d[PPT], xr[PPT];
+    load_region<T, W, PPT>(breg, b + bmap.off(c), FX0, FY0, m);
+    pre_smooth<T, W, PPT, NPRE>(breg, d, xr, sx, FX0, FY0, m, L, wc, we, wd, dinv);
+    // x += P e_c on the nodes where the pre-smoothed iterate is valid
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int q = threadIdx.x + 256 * p;
-        const int X = FX0 + q % W, Y = FY0 + q / W;
-        const bool inter = q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1;
-        T xv = T(0), bv = T(0);
-        if (inter) {
+        const int i = q % W, j = q / W;
+        const int X = FX0 + i, Y = FY0 + j;
+        if (q < W * W && i >= H0 && i < W - H0 && j >= H0 && j < W - H0 && X >= 1 && X <= m - 1 && Y >= 1 &&
+            Y <= m - 1) {
             const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
-            const T e = T(0.25) * (ecol[J0 * C1 + I0] + ecol[J0 * C1 + I1] + ecol[J1 * C1 + I0] + ecol[J1 * C1 + I1]);
-            xv = xcol[Y * N1 + X] + e;
-            bv = bcol[Y * N1 + X];
+            xr[p] += T(0.25) * (ecol[J0 * C1 + I0] + ecol[J0 * C1 + I1] + ecol[J1 * C1 + I0] + ecol[J1 * C1 + I1]);
         }
-        xr[p] = xv;
-        breg[p] = bv;
-        d[p] = T(0);
-        if (q < W * W) sx[q] = xv;
     }
     __syncthreads();
 #pragma unroll
-    for (int s = 0; s < NU; ++s) {
+    for (int p = 0; p < PPT; ++p) {
+        const int q = threadIdx.x + 256 * p;
+        if (q < W * W) sx[q] = xr[p];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < NPOST; ++s) {
         const T cd = T(L.post[s][0]), cr = T(L.post[s][1]);
-        const int lo = s + 1, hi = W - s - 1;
+        const int lo = H0 + s + 1, hi = W - H0 - s - 1;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
             const int q = threadIdx.x + 256 * p;
@@ -186,7 +197,7 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
                 xr[p] += d[p];
             }
         }
-        if (s + 1 < NU) {
+        if (s + 1 < NPOST) {
             __syncthreads();
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
@@ -201,7 +212,7 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
     for (int p = 0; p < PPT; ++p) {
         const int q = threadIdx.x + 256 * p;
         const int X = FX0 + q % W, Y = FY0 + q / W;
-        if (q < W * W && X >= FX0 + NU - ex && X < FX0 + NU + TF && Y >= FY0 + NU - ey && Y < FY0 + NU + TF &&
+        if (q < W * W && X >= FX0 + H - ex && X < FX0 + H + TF && Y >= FY0 + H - ey && Y < FY0 + H + TF &&
             X <= m && Y <= m)
             out[Y * N1 + X] = xr[p];
     }
@@ -495,48 +506,59 @@ constexpr int TCD = 16;   // coarse nodes per down tile side
 constexpr int TFU = 32;   // fine nodes per up tile side
 
 template <typename T, int NU>
-void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc, int ncols,
-             int cpm, hipStream_t st) {
+void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* bc, int ncols, int cpm, hipStream_t st) {
     const int mc = m / 2;
     const int tx = (mc - 1 + TCD - 1) / TCD;
     dim3 grid(tx * tx, ncols);
-    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, x, xmap, bc, cpm, tx);
+    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, bc, cpm, tx);
 }
 
-template <typename T, int NU>
-void up_nu(int m, const LevelDev* lev, int lvl, const T* xin, ColMap xinmap, const T* ec, const T* b, ColMap bmap,
-           T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st) {
+template <typename T, int NPRE, int NPOST>
+void up_nu(int m, const LevelDev* lev, int lvl, const T* ec, const T* b, ColMap bmap, T* xo, ColMap xomap, int ncols,
+           int cpm, hipStream_t st) {
     const int tx = (m - 1 + TFU - 1) / TFU;
     dim3 grid(tx * tx, ncols);
-    hipLaunchKernelGGL((k_mg_up<T, TFU, NU>), grid, dim3(256), 0, st, m, lev, lvl, xin, xinmap, ec, b, bmap, xo,
-                       xomap, cpm, tx);
+    hipLaunchKernelGGL((k_mg_up<T, TFU, NPRE, NPOST>), grid, dim3(256), 0, st, m, lev, lvl, ec, b, bmap, xo, xomap,
+                       cpm, tx);
+}
+
+template <typename T, int NPRE>
+void up_pre(int m, const LevelDev* lev, int lvl, int npost, const T* ec, const T* b, ColMap bmap, T* xo, ColMap xomap,
+            int ncols, int cpm, hipStream_t st) {
+    switch (npost) {
+        case 1: up_nu<T, NPRE, 1>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 2: up_nu<T, NPRE, 2>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 3: up_nu<T, NPRE, 3>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 4: up_nu<T, NPRE, 4>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
+    }
 }
 
 }  // namespace
 
 template <typename T>
-void launch_mg_down(int m, const LevelDev* lev, int lvl, int nu, const T* b, ColMap bmap, T* x, ColMap xmap, T* bc,
-                    int ncols, int cpm, hipStream_t st) {
+void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, int ncols, int cpm,
+                    hipStream_t st) {
     if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
-    switch (nu) {
-        case 1: down_nu<T, 1>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
-        case 2: down_nu<T, 2>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
-        case 3: down_nu<T, 3>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
-        case 4: down_nu<T, 4>(m, lev, lvl, b, bmap, x, xmap, bc, ncols, cpm, st); break;
+    switch (npre) {
+        case 1: down_nu<T, 1>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
+        case 2: down_nu<T, 2>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
+        case 3: down_nu<T, 3>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
+        case 4: down_nu<T, 4>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
         default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     }
     SG_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_mg_up(int m, const LevelDev* lev, int lvl, int nu, const T* xin, ColMap xinmap, const T* ec, const T* b,
-                  ColMap bmap, T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st) {
+void launch_mg_up(int m, const LevelDev* lev, int lvl, int npre, int npost, const T* ec, const T* b, ColMap bmap,
+                  T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st) {
     if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
-    switch (nu) {
-        case 1: up_nu<T, 1>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 2: up_nu<T, 2>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 3: up_nu<T, 3>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 4: up_nu<T, 4>(m, lev, lvl, xin, xinmap, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+    switch (npre) {
+        case 1: up_pre<T, 1>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 2: up_pre<T, 2>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 3: up_pre<T, 3>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 4: up_pre<T, 4>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
         default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     }
     SG_HIP(hipGetLastError());
@@ -590,13 +612,13 @@ template void launch_mg_tail<double>(int, const LevelDev*, int, int, int, const 
                                      const double*, int, int, hipStream_t);
 template void launch_mg_tail<float>(int, const LevelDev*, int, int, int, const float*, ColMap, float*, ColMap,
                                     const float*, int, int, hipStream_t);
-template void launch_mg_down<double>(int, const LevelDev*, int, int, const double*, ColMap, double*, ColMap, double*,
-                                     int, int, hipStream_t);
-template void launch_mg_down<float>(int, const LevelDev*, int, int, const float*, ColMap, float*, ColMap, float*, int,
-                                    int, hipStream_t);
-template void launch_mg_up<double>(int, const LevelDev*, int, int, const double*, ColMap, const double*,
-                                   const double*, ColMap, double*, ColMap, int, int, hipStream_t);
-template void launch_mg_up<float>(int, const LevelDev*, int, int, const float*, ColMap, const float*, const float*,
-                                  ColMap, float*, ColMap, int, int, hipStream_t);
+template void launch_mg_down<double>(int, const LevelDev*, int, int, const double*, ColMap, double*, int, int,
+                                     hipStream_t);
+template void launch_mg_down<float>(int, const LevelDev*, int, int, const float*, ColMap, float*, int, int,
+                                    hipStream_t);
+template void launch_mg_up<double>(int, const LevelDev*, int, int, int, const double*, const double*, ColMap, double*,
+                                   ColMap, int, int, hipStream_t);
+template void launch_mg_up<float>(int, const LevelDev*, int, int, int, const float*, const float*, ColMap, float*,
+                                  ColMap, int, int, hipStream_t);
 
 }  // namespace sg

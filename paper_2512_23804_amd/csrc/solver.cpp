@@ -91,8 +91,9 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
     while (l0 < nl - 1 && s.mg_n[l0] > h.mg_tail_max) ++l0;
     const bool tail = l0 < nl - 1;
     const int lc = tail ? l0 : nl - 1;      // first level handled by the fused tail or the direct solve
-    // per level: xs (after pre-smoothing), bs (restricted right-hand side, l >= 1),
-    // xf (after post-smoothing, l >= 1; level 0 writes to x)
+    // per level: bs (restricted right-hand side, l >= 1), xf (after
+    // post-smoothing, l >= 1; level 0 writes to x); xs only for the coarsest
+    // level solved directly
     std::vector<T*> xs(nl), bs(nl), xf(nl);
     std::vector<ColMap> cm(nl);
     for (int l = 0; l <= lc; ++l) {
@@ -101,7 +102,7 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         const size_t cnt = (size_t)ncols * nodes;
         const std::string tag = std::string("mg") + tname<T>() + "_" + std::to_string(l);
         cm[l] = contiguous_cols(ncols, nodes);
-        if (l < lc || !tail) xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
+        if (l == lc && !tail) xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
         if (l > 0) {
             bs[l] = h.ws.get_t<T>(tag + "_bs", cnt);
             xf[l] = h.ws.get_t<T>(tag + "_xf", cnt);
@@ -111,9 +112,8 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         const int m = s.mg_n[l];
         const double nodes = (double)(m + 1) * (m + 1);
         const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
-        launch_mg_down<T>(m, lev, l, npre, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], xs[l], cm[l], bs[l + 1], ncols,
-                          cpm, st);
-        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);   // read b, write x, write b_coarse
+        launch_mg_down<T>(m, lev, l, npre, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], bs[l + 1], ncols, cpm, st);
+        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 1.25);   // read b, write b_coarse
     }
     const T* e;
     if (tail) {
@@ -133,9 +133,9 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         const double nodes = (double)(m + 1) * (m + 1);
         T* out = l == 0 ? x : xf[l];
         const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
-        launch_mg_up<T>(m, lev, l, npost, xs[l], cm[l], e, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], out,
+        launch_mg_up<T>(m, lev, l, npre, npost, e, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], out,
                         l == 0 ? xmap : cm[l], ncols, cpm, st);
-        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 3.25);  // read x, b, e_coarse; write x
+        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);  // read b, e_coarse; write x
         e = out;
     }
 }
