@@ -303,14 +303,61 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     }
 }
 
+// Thread -> node mapping of a W x W region in LDS for NT threads: each thread
+// owns K vertically consecutive nodes of one column (segment), K chosen so
+// that the segments cover the region with at most NT threads.  A 9-point
+// stencil over a segment keeps a sliding 3 x 3 window in registers: (K+2)*3
+// LDS reads for K nodes instead of 9K.
+template <int W, int NT>
+struct Seg {
+    static constexpr int SPC = NT / W < 1 ? 1 : NT / W;    // segments per column
+    static constexpr int K = (W + SPC - 1) / SPC;          // nodes per segment
+    static constexpr int NS = W * ((W + K - 1) / K);       // segments in use
+    int X, Y0;
+    bool on;
+    __device__ __forceinline__ Seg() {
+        const int t = threadIdx.x;
+        X = t % W;
+        Y0 = (t / W) * K;
+        on = t < NS;
+    }
+    __device__ __forceinline__ bool has(int k) const { return on && Y0 + k < W; }
+    __device__ __forceinline__ int q(int k) const { return (Y0 + k) * W + X; }
+};
+
+// out[k] = (A x)(X, Y0 + k), same summation order as st9; rows and columns
+// outside the region are clamped (their results are not used).
+template <typename T, int W, int K>
+__device__ __forceinline__ void st9_seg(const T* s, int X, int Y0, T wc, T we, T wd, T (&out)[K]) {
+    const int xl = X > 0 ? X - 1 : 0, xr = X < W - 1 ? X + 1 : W - 1;
+    auto row = [&](int y, T& l, T& c, T& r) {
+        const int yy = y < 0 ? 0 : (y > W - 1 ? W - 1 : y);
+        l = s[yy * W + xl];
+        c = s[yy * W + X];
+        r = s[yy * W + xr];
+    };
+    T l0, c0, r0, l1, c1, r1;
+    row(Y0 - 1, l0, c0, r0);
+    row(Y0, l1, c1, r1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        T l2, c2, r2;
+        row(Y0 + k + 1, l2, c2, r2);
+        out[k] = wc * c1 + we * (l1 + r1 + c0 + c2) + wd * (l0 + r0 + l2 + r2);
+        l0 = l1; c0 = c1; r0 = r1;
+        l1 = l2; c1 = c2; r1 = r2;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Coarse end of the V-cycle in one workgroup per column.  Levels M0, M0/2, ..,
 // kCoarseN live in LDS (right-hand side and iterate per level, one residual
 // buffer): pre-smoothing from zero, residual and restriction on the way down,
 // the direct solve on the kCoarseN grid (dense inverse of the interior
 // operator), interpolation and post-smoothing on the way up.  Replaces
-// 2 log2(M0/kCoarseN) + 1 launches per V-cycle by one.  The Chebyshev step
-// direction of the nodes a thread owns stays in its registers.
+// 2 log2(M0/kCoarseN) + 1 launches per V-cycle by one.  Each level is a
+// template instance (compile-time width); a thread's nodes are a vertical
+// segment (Seg) whose b, iterate and step direction stay in registers.
 // --------------------------------------------------------------------------
 #ifndef SG_TAIL_THREADS
 #define SG_TAIL_THREADS 1024
@@ -321,6 +368,9 @@ __host__ __device__ constexpr int tail_levels(int m0) { return m0 <= kCoarseN ? 
 __host__ __device__ constexpr int tail_offset(int m0, int k) {
     return k == 0 ? 0 : (m0 + 1) * (m0 + 1) + tail_offset(m0 / 2, k - 1);
 }
+// offset of level m in the per-level arrays of a tail starting at m0
+__host__ __device__ constexpr int level_offset(int m0, int m) { return m0 == m ? 0 : (m0 + 1) * (m0 + 1) + level_offset(m0 / 2, m); }
+__host__ __device__ constexpr int level_index(int m0, int m) { return m0 == m ? 0 : 1 + level_index(m0 / 2, m); }
 
 template <typename T, int M0>
 struct TailLds {
@@ -332,32 +382,122 @@ struct TailLds {
     T r[W0 * W0];
 };
 
-// One Chebyshev smoothing step on level (m, W = m + 1); `first` uses c_d = 0.
-template <typename T, int PPT>
-__device__ __forceinline__ void tail_smooth_step(const T* __restrict__ B, T* __restrict__ Xs, int m, T wc, T we, T wd,
-                                                 T dinv, T cd, T cr, bool first, T (&d)[PPT]) {
-    const int W = m + 1;
-    T xn[PPT];
+__device__ __forceinline__ bool interior(int X, int Y, int m) { return X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1; }
+
+// down at level M: pre-smoothing from zero, residual, restriction to level M/2
+template <typename T, int M, int M0>
+__device__ __forceinline__ void tail_down(TailLds<T, M0>& s, const LevelDev* slev, int npre) {
+    constexpr int W = M + 1, mc = M / 2, C1 = mc + 1;
+    using SG = Seg<W, kTailThreads>;
+    constexpr int K = SG::K;
+    const SG g;
+    T* B = s.b + level_offset(M0, M);
+    T* Xs = s.x + level_offset(M0, M);
+    T* Bc = s.b + level_offset(M0, mc);
+    const LevelDev& L = slev[level_index(M0, M)];
+    const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
+    const T cr0 = T(L.pre[0][1]);
+    T breg[K], d[K], xr[K];
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const int q = threadIdx.x + p * kTailThreads;
-        const int X = q % W, Y = q / W;
-        xn[p] = T(0);
-        if (q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) {
-            const T r = B[q] - st9(Xs, W, q, wc, we, wd);
-            const T dn = (first ? T(0) : cd * d[p]) + cr * dinv * r;
-            d[p] = dn;
-            xn[p] = Xs[q] + dn;
+    for (int k = 0; k < K; ++k) {
+        breg[k] = d[k] = xr[k] = T(0);
+        if (g.has(k)) {
+            breg[k] = B[g.q(k)];               // zero off the interior
+            xr[k] = cr0 * dinv * breg[k];
+            d[k] = xr[k];
+            Xs[g.q(k)] = xr[k];
+        }
+    }
+    __syncthreads();
+    for (int st = 1; st < npre; ++st) {
+        const T cd = T(L.pre[st][0]), cr = T(L.pre[st][1]);
+        T ax[K];
+        st9_seg<T, W, K>(Xs, g.X, g.Y0, wc, we, wd, ax);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (g.has(k) && interior(g.X, g.Y0 + k, M)) {
+                d[k] = cd * d[k] + cr * dinv * (breg[k] - ax[k]);
+                xr[k] += d[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (g.has(k)) Xs[g.q(k)] = xr[k];
+        __syncthreads();
+    }
+    {
+        T ax[K];
+        st9_seg<T, W, K>(Xs, g.X, g.Y0, wc, we, wd, ax);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (g.has(k)) s.r[g.q(k)] = interior(g.X, g.Y0 + k, M) ? breg[k] - ax[k] : T(0);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < C1 * C1; q += kTailThreads) {
+        const int I = q % C1, J = q / C1;
+        T v = T(0);
+        if (I >= 1 && I <= mc - 1 && J >= 1 && J <= mc - 1) {
+            const int pf = 2 * J * W + 2 * I;
+            const T* R = s.r;
+            v = R[pf] + T(0.5) * (R[pf - 1] + R[pf + 1] + R[pf - W] + R[pf + W]) +
+                T(0.25) * (R[pf - W - 1] + R[pf - W + 1] + R[pf + W - 1] + R[pf + W + 1]);
+        }
+        Bc[q] = v;
+    }
+    __syncthreads();
+    if constexpr (mc > kCoarseN) tail_down<T, mc, M0>(s, slev, npre);
+}
+
+// up at level M (coarser levels first): x += P e, post-smoothing
+template <typename T, int M, int M0>
+__device__ __forceinline__ void tail_up(TailLds<T, M0>& s, const LevelDev* slev, int npost) {
+    constexpr int W = M + 1, mc = M / 2, C1 = mc + 1;
+    if constexpr (mc > kCoarseN) tail_up<T, mc, M0>(s, slev, npost);
+    using SG = Seg<W, kTailThreads>;
+    constexpr int K = SG::K;
+    const SG g;
+    const T* B = s.b + level_offset(M0, M);
+    T* Xs = s.x + level_offset(M0, M);
+    const T* E = s.x + level_offset(M0, mc);
+    const LevelDev& L = slev[level_index(M0, M)];
+    const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
+    T breg[K], d[K], xr[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        breg[k] = d[k] = xr[k] = T(0);
+        if (g.has(k)) {
+            const int X = g.X, Y = g.Y0 + k;
+            breg[k] = B[g.q(k)];
+            xr[k] = Xs[g.q(k)];
+            if (interior(X, Y, M)) {
+                const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
+                xr[k] += T(0.25) * (E[J0 * C1 + I0] + E[J0 * C1 + I1] + E[J1 * C1 + I0] + E[J1 * C1 + I1]);
+            }
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const int q = threadIdx.x + p * kTailThreads;
-        const int X = q % W, Y = q / W;
-        if (q < W * W && X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) Xs[q] = xn[p];
-    }
+    for (int k = 0; k < K; ++k)
+        if (g.has(k)) Xs[g.q(k)] = xr[k];
     __syncthreads();
+    for (int st = 0; st < npost; ++st) {
+        const T cd = T(L.post[st][0]), cr = T(L.post[st][1]);
+        T ax[K];
+        st9_seg<T, W, K>(Xs, g.X, g.Y0, wc, we, wd, ax);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (g.has(k) && interior(g.X, g.Y0 + k, M)) {
+                d[k] = (st == 0 ? T(0) : cd * d[k]) + cr * dinv * (breg[k] - ax[k]);
+                xr[k] += d[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (g.has(k)) Xs[g.q(k)] = xr[k];
+        __syncthreads();
+    }
 }
 
 template <typename T, int M0>
@@ -368,86 +508,38 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __rest
     using Lds = TailLds<T, M0>;
     constexpr int NL = Lds::NL;
     constexpr int W0 = Lds::W0;
-    constexpr int PPT = (W0 * W0 + kTailThreads - 1) / kTailThreads;
     constexpr int CN1 = kCoarseN + 1, CNU = (kCoarseN - 1) * (kCoarseN - 1);
-    constexpr int KPT = (CNU + 3) / 4;      // inverse entries per thread (four threads per row)
     __shared__ Lds s;
     __shared__ LevelDev slev[NL > 1 ? NL - 1 : 1];
+    __shared__ T sA[CNU * CNU];             // interior block of the coarse inverse
     const int c = blockIdx.x;
     const int mem = c / cpm;
-    // issue every global read first: the column, the level parameters, this
-    // thread's part of the coarse inverse (consumed only after the down sweep)
+    // issue every global read first: the column, the level parameters and the
+    // coarse inverse (consumed only after the down sweep)
     const T* bcol = b + bmap.off(c);
     for (int q = threadIdx.x; q < W0 * W0; q += kTailThreads) {
         const int X = q % W0, Y = q / W0;
-        s.b[q] = (X >= 1 && X <= M0 - 1 && Y >= 1 && Y <= M0 - 1) ? bcol[q] : T(0);
+        s.b[q] = interior(X, Y, M0) ? bcol[q] : T(0);
     }
     constexpr int LW = sizeof(LevelDev) / sizeof(double);
     for (int q = threadIdx.x; q < (NL - 1) * LW; q += kTailThreads)
         ((double*)slev)[q] = ((const double*)(lev + mem * kMaxLevels + lvl0))[q];
-    const int row = threadIdx.x / 4, part = threadIdx.x % 4;
-    T arow[KPT];
     {
-        const T* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad + (row < CNU ? row : 0) * kCoarsePad;
-#pragma unroll
-        for (int i = 0; i < KPT; ++i) {
-            const int k = part + 4 * i;
-            arow[i] = (row < CNU && k < CNU) ? A[k] : T(0);
-        }
+        const T* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad;
+        for (int q = threadIdx.x; q < CNU * CNU; q += kTailThreads) sA[q] = A[(q / CNU) * kCoarsePad + q % CNU];
     }
     __syncthreads();
-    T d[PPT];
-    // down: pre-smoothing from zero, residual, restriction
-#pragma unroll
-    for (int k = 0; k < NL - 1; ++k) {
-        const int m = M0 >> k, W = m + 1, mc = m / 2, C1 = mc + 1;
-        T* B = s.b + tail_offset(M0, k);
-        T* Xs = s.x + tail_offset(M0, k);
-        T* Bc = s.b + tail_offset(M0, k + 1);
-        const LevelDev& L = slev[k];
-        const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
-        const T cr0 = T(L.pre[0][1]);
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            const int q = threadIdx.x + p * kTailThreads;
-            if (q < W * W) {
-                const T x1 = cr0 * dinv * B[q];     // B is zero off the interior
-                d[p] = x1;
-                Xs[q] = x1;
-            }
-        }
-        __syncthreads();
-        for (int st = 1; st < npre; ++st)
-            tail_smooth_step<T, PPT>(B, Xs, m, wc, we, wd, dinv, T(L.pre[st][0]), T(L.pre[st][1]), false, d);
-        for (int q = threadIdx.x; q < W * W; q += kTailThreads) {
-            const int X = q % W, Y = q / W;
-            s.r[q] = (X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) ? B[q] - st9(Xs, W, q, wc, we, wd) : T(0);
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < C1 * C1; q += kTailThreads) {
-            const int I = q % C1, J = q / C1;
-            T v = T(0);
-            if (I >= 1 && I <= mc - 1 && J >= 1 && J <= mc - 1) {
-                const int pf = 2 * J * W + 2 * I;
-                const T* R = s.r;
-                v = R[pf] + T(0.5) * (R[pf - 1] + R[pf + 1] + R[pf - W] + R[pf + W]) +
-                    T(0.25) * (R[pf - W - 1] + R[pf - W + 1] + R[pf + W - 1] + R[pf + W + 1]);
-            }
-            Bc[q] = v;
-        }
-        __syncthreads();
-    }
+    tail_down<T, M0, M0>(s, slev, npre);
     // direct solve on the kCoarseN grid: four threads per interior unknown
     {
+        const int row = threadIdx.x / 4, part = threadIdx.x % 4;
         const T* Bc = s.b + tail_offset(M0, NL - 1);
         T* Xc = s.x + tail_offset(M0, NL - 1);
         T acc = T(0);
-#pragma unroll
-        for (int i = 0; i < KPT; ++i) {
-            const int k = part + 4 * i;
-            if (k < CNU) {
+        if (row < CNU) {
+            for (int k = part; k < CNU; k += 4) {
                 const int ix = k % (kCoarseN - 1) + 1, iy = k / (kCoarseN - 1) + 1;
-                acc += arow[i] * Bc[iy * CN1 + ix];
+                acc += sA[row * CNU + k] * Bc[iy * CN1 + ix];
             }
         }
         acc += __shfl_xor(acc, 1, 64);
@@ -460,26 +552,7 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __rest
         }
         __syncthreads();
     }
-    // up: interpolation of the coarse correction, post-smoothing
-#pragma unroll
-    for (int k = NL - 2; k >= 0; --k) {
-        const int m = M0 >> k, W = m + 1, C1 = m / 2 + 1;
-        const T* B = s.b + tail_offset(M0, k);
-        T* Xs = s.x + tail_offset(M0, k);
-        const T* E = s.x + tail_offset(M0, k + 1);
-        const LevelDev& L = slev[k];
-        const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
-        for (int q = threadIdx.x; q < W * W; q += kTailThreads) {
-            const int X = q % W, Y = q / W;
-            if (X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1) {
-                const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
-                Xs[q] += T(0.25) * (E[J0 * C1 + I0] + E[J0 * C1 + I1] + E[J1 * C1 + I0] + E[J1 * C1 + I1]);
-            }
-        }
-        __syncthreads();
-        for (int st = 0; st < npost; ++st)
-            tail_smooth_step<T, PPT>(B, Xs, m, wc, we, wd, dinv, T(L.post[st][0]), T(L.post[st][1]), st == 0, d);
-    }
+    tail_up<T, M0, M0>(s, slev, npost);
     T* xcol = x + xmap.off(c);
     for (int q = threadIdx.x; q < W0 * W0; q += kTailThreads) xcol[q] = s.x[q];
 }

@@ -295,14 +295,15 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     h->stream = st;
     SG_HIP(hipGetDevice(&h->device));
     {
-        // the fused multigrid tail keeps every level up to 64 intervals per side in
-        // LDS (about 125 KB in FP64); with less LDS per workgroup it starts at 32
+        // the fused multigrid tail keeps every level up to 64 intervals per side and
+        // the coarse inverse in LDS (141 KiB in FP64); with less LDS per workgroup
+        // it starts at 32
         int lds = 0;
         SG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
 #ifdef SG_MG_TAIL_MAX
         h->mg_tail_max = SG_MG_TAIL_MAX;
 #else
-        h->mg_tail_max = lds >= 128 * 1024 ? 64 : 32;
+        h->mg_tail_max = lds >= 144 * 1024 ? 64 : 32;
 #endif
     }
     const sg_problem& p0 = probs[0];
