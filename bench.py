@@ -37,8 +37,8 @@ WORKLOADS = {
 DEFAULT = "steady-128-M6-P4"
 # kernels timed with HIP events around every launch (sg_options.profile), with
 # the algorithmic bytes each launch must move
-PROF_KIND = {"kkt_apply": 1, "mg_smooth": 2, "arnoldi_dots": 3, "hgs_rhs": 4, "arnoldi_update": 5, "mg_tail": 6,
-             "mass_cheb": 7}
+PROF_KIND = {"kkt_apply": 1, "mg_down": 2, "arnoldi_dots": 3, "hgs_rhs": 4, "arnoldi_update": 5, "mg_tail": 6,
+             "mass_cheb": 7, "mg_up": 8}
 ARNOLDI = {"dcgs2": 0, "cgs2": 1}
 
 

@@ -20,7 +20,7 @@ SG_ERR_NOMEM, SG_ERR_HIP, SG_ERR_CANCELLED, SG_ERR_UNKNOWN = -4, -5, -6, -7
 SG_FP64, SG_FP32 = 0, 1
 SG_PREC_FP64, SG_PREC_FP32_REFINE, SG_PREC_FP32_PRECOND = 0, 1, 2
 SG_PROF_NONE, SG_PROF_KKT_APPLY, SG_PROF_MG_SMOOTH, SG_PROF_MULTIDOT, SG_PROF_HGS_RHS = 0, 1, 2, 3, 4
-SG_PROF_ARNOLDI_UPD, SG_PROF_MG_TAIL, SG_PROF_MASS_CHEB = 5, 6, 7
+SG_PROF_ARNOLDI_UPD, SG_PROF_MG_TAIL, SG_PROF_MASS_CHEB, SG_PROF_MG_UP = 5, 6, 7, 8
 SG_ARNOLDI_DCGS2, SG_ARNOLDI_CGS2 = 0, 1
 
 _DP = C.POINTER(C.c_double)

@@ -158,7 +158,7 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
         if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32_REFINE &&
             opt->precision != SG_PREC_FP32_PRECOND)
             fail(SG_ERR_INVALID, "unknown precision mode");
-        if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_MASS_CHEB) fail(SG_ERR_INVALID, "unknown profile kind");
+        if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_MG_UP) fail(SG_ERR_INVALID, "unknown profile kind");
         if (opt->sweep_rows != 0 && opt->sweep_rows != 2 && opt->sweep_rows != 4 && opt->sweep_rows != 8)
             fail(SG_ERR_INVALID, "sweep_rows must be 0 (autotune), 2, 4 or 8");
         if (opt->arnoldi != SG_ARNOLDI_DCGS2 && opt->arnoldi != SG_ARNOLDI_CGS2)

@@ -132,7 +132,7 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         const int m = s.mg_n[l];
         const double nodes = (double)(m + 1) * (m + 1);
         T* out = l == 0 ? x : xf[l];
-        const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
+        const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_UP, st);
         launch_mg_up<T>(m, lev, l, npre, npost, e, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], out,
                         l == 0 ? xmap : cm[l], ncols, cpm, st);
         if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);  // read b, e_coarse; write x

@@ -84,7 +84,7 @@ def test_validate_options():
     import paper_2512_23804_amd as sgl
     for kw in (dict(restart=0), dict(restart=40), dict(cheb_steps=0), dict(truncation_r=6), dict(gmg_pre=0),
                dict(precision=3), dict(rtol=0.0), dict(sweep_rows=3), dict(sweep_rows=16), dict(arnoldi=2),
-               dict(profile=8)):
+               dict(profile=9)):
         assert sgl.validate(_pd(), sgl.default_options(**kw)) == sgl.SG_ERR_INVALID, kw
 
 
