@@ -384,54 +384,83 @@ struct TailLds {
 
 __device__ __forceinline__ bool interior(int X, int Y, int m) { return X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1; }
 
-// down at level M: pre-smoothing from zero, residual, restriction to level M/2
+// One Chebyshev step from buffer `in` to buffer `out` (ping-pong: a single
+// barrier per step): d = c_d d + c_r D^{-1} (b - A x), x += d on interior nodes.
+template <typename T, int W, int K>
+__device__ __forceinline__ void tail_step(const Seg<W, kTailThreads>& g, const T* in, T* out, int m, const T (&breg)[K],
+                                          T (&d)[K], T (&xr)[K], T wc, T we, T wd, T dinv, T cd, T cr, bool first) {
+    T ax[K];
+    st9_seg<T, W, K>(in, g.X, g.Y0, wc, we, wd, ax);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (g.has(k) && interior(g.X, g.Y0 + k, m)) {
+            d[k] = (first ? T(0) : cd * d[k]) + cr * dinv * (breg[k] - ax[k]);
+            xr[k] += d[k];
+        }
+        if (g.has(k)) out[g.q(k)] = xr[k];
+    }
+    __syncthreads();
+}
+
+// down at level M: pre-smoothing from zero, residual, restriction to level M/2.
+// The iterate ping-pongs between the level's array P and the shared buffer
+// Q = s.r so that the final pre-smoothed iterate lands in P (kept for the up
+// sweep); the first stencil step is taken straight from b (x_1 = c_r D^{-1} b).
 template <typename T, int M, int M0>
 __device__ __forceinline__ void tail_down(TailLds<T, M0>& s, const LevelDev* slev, int npre) {
     constexpr int W = M + 1, mc = M / 2, C1 = mc + 1;
     using SG = Seg<W, kTailThreads>;
     constexpr int K = SG::K;
     const SG g;
-    T* B = s.b + level_offset(M0, M);
-    T* Xs = s.x + level_offset(M0, M);
+    const T* B = s.b + level_offset(M0, M);
+    T* P = s.x + level_offset(M0, M);
+    T* Q = s.r;
     T* Bc = s.b + level_offset(M0, mc);
     const LevelDev& L = slev[level_index(M0, M)];
     const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
-    const T cr0 = T(L.pre[0][1]);
+    const T c1 = T(L.pre[0][1]) * dinv;
     T breg[K], d[K], xr[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        breg[k] = d[k] = xr[k] = T(0);
-        if (g.has(k)) {
-            breg[k] = B[g.q(k)];               // zero off the interior
-            xr[k] = cr0 * dinv * breg[k];
-            d[k] = xr[k];
-            Xs[g.q(k)] = xr[k];
-        }
+        breg[k] = g.has(k) ? B[g.q(k)] : T(0);   // zero off the interior
+        xr[k] = c1 * breg[k];
+        d[k] = xr[k];
     }
-    __syncthreads();
-    for (int st = 1; st < npre; ++st) {
-        const T cd = T(L.pre[st][0]), cr = T(L.pre[st][1]);
-        T ax[K];
-        st9_seg<T, W, K>(Xs, g.X, g.Y0, wc, we, wd, ax);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (g.has(k) && interior(g.X, g.Y0 + k, M)) {
-                d[k] = cd * d[k] + cr * dinv * (breg[k] - ax[k]);
-                xr[k] += d[k];
-            }
-        }
-        __syncthreads();
+    if (npre == 1) {
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (g.has(k)) Xs[g.q(k)] = xr[k];
+            if (g.has(k)) P[g.q(k)] = xr[k];
         __syncthreads();
+    } else {
+        // step 1 from b: A x_1 = c_1 A b; then steps 2..npre-1 alternate so that
+        // step npre-1 writes P
+        {
+            const T cd = T(L.pre[1][0]), cr = T(L.pre[1][1]);
+            T ab[K];
+            st9_seg<T, W, K>(B, g.X, g.Y0, wc, we, wd, ab);
+            T* out = (npre - 1) % 2 == 1 ? P : Q;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (g.has(k) && interior(g.X, g.Y0 + k, M)) {
+                    d[k] = cd * d[k] + cr * dinv * (breg[k] - c1 * ab[k]);
+                    xr[k] += d[k];
+                }
+                if (g.has(k)) out[g.q(k)] = xr[k];
+            }
+            __syncthreads();
+        }
+        for (int st = 2; st < npre; ++st) {
+            const bool to_p = (npre - 1 - st) % 2 == 0;
+            tail_step<T, W, K>(g, to_p ? Q : P, to_p ? P : Q, M, breg, d, xr, wc, we, wd, dinv, T(L.pre[st][0]),
+                               T(L.pre[st][1]), false);
+        }
     }
     {
         T ax[K];
-        st9_seg<T, W, K>(Xs, g.X, g.Y0, wc, we, wd, ax);
+        st9_seg<T, W, K>(P, g.X, g.Y0, wc, we, wd, ax);
 #pragma unroll
         for (int k = 0; k < K; ++k)
-            if (g.has(k)) s.r[g.q(k)] = interior(g.X, g.Y0 + k, M) ? breg[k] - ax[k] : T(0);
+            if (g.has(k)) Q[g.q(k)] = interior(g.X, g.Y0 + k, M) ? breg[k] - ax[k] : T(0);
     }
     __syncthreads();
     for (int q = threadIdx.x; q < C1 * C1; q += kTailThreads) {
@@ -439,9 +468,8 @@ __device__ __forceinline__ void tail_down(TailLds<T, M0>& s, const LevelDev* sle
         T v = T(0);
         if (I >= 1 && I <= mc - 1 && J >= 1 && J <= mc - 1) {
             const int pf = 2 * J * W + 2 * I;
-            const T* R = s.r;
-            v = R[pf] + T(0.5) * (R[pf - 1] + R[pf + 1] + R[pf - W] + R[pf + W]) +
-                T(0.25) * (R[pf - W - 1] + R[pf - W + 1] + R[pf + W - 1] + R[pf + W + 1]);
+            v = Q[pf] + T(0.5) * (Q[pf - 1] + Q[pf + 1] + Q[pf - W] + Q[pf + W]) +
+                T(0.25) * (Q[pf - W - 1] + Q[pf - W + 1] + Q[pf + W - 1] + Q[pf + W + 1]);
         }
         Bc[q] = v;
     }
@@ -449,7 +477,8 @@ __device__ __forceinline__ void tail_down(TailLds<T, M0>& s, const LevelDev* sle
     if constexpr (mc > kCoarseN) tail_down<T, mc, M0>(s, slev, npre);
 }
 
-// up at level M (coarser levels first): x += P e, post-smoothing
+// up at level M (coarser levels first): x += P e (pointwise, in place or into
+// Q), then post-smoothing steps alternating so that the last one writes P.
 template <typename T, int M, int M0>
 __device__ __forceinline__ void tail_up(TailLds<T, M0>& s, const LevelDev* slev, int npost) {
     constexpr int W = M + 1, mc = M / 2, C1 = mc + 1;
@@ -458,45 +487,32 @@ __device__ __forceinline__ void tail_up(TailLds<T, M0>& s, const LevelDev* slev,
     constexpr int K = SG::K;
     const SG g;
     const T* B = s.b + level_offset(M0, M);
-    T* Xs = s.x + level_offset(M0, M);
+    T* P = s.x + level_offset(M0, M);
+    T* Q = s.r;
     const T* E = s.x + level_offset(M0, mc);
     const LevelDev& L = slev[level_index(M0, M)];
     const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
     T breg[K], d[K], xr[K];
+    T* first = npost % 2 == 0 ? P : Q;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         breg[k] = d[k] = xr[k] = T(0);
         if (g.has(k)) {
             const int X = g.X, Y = g.Y0 + k;
             breg[k] = B[g.q(k)];
-            xr[k] = Xs[g.q(k)];
+            xr[k] = P[g.q(k)];
             if (interior(X, Y, M)) {
                 const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
                 xr[k] += T(0.25) * (E[J0 * C1 + I0] + E[J0 * C1 + I1] + E[J1 * C1 + I0] + E[J1 * C1 + I1]);
             }
+            first[g.q(k)] = xr[k];
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-        if (g.has(k)) Xs[g.q(k)] = xr[k];
-    __syncthreads();
     for (int st = 0; st < npost; ++st) {
-        const T cd = T(L.post[st][0]), cr = T(L.post[st][1]);
-        T ax[K];
-        st9_seg<T, W, K>(Xs, g.X, g.Y0, wc, we, wd, ax);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (g.has(k) && interior(g.X, g.Y0 + k, M)) {
-                d[k] = (st == 0 ? T(0) : cd * d[k]) + cr * dinv * (breg[k] - ax[k]);
-                xr[k] += d[k];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (g.has(k)) Xs[g.q(k)] = xr[k];
-        __syncthreads();
+        const bool to_p = (npost - 1 - st) % 2 == 0;
+        tail_step<T, W, K>(g, to_p ? Q : P, to_p ? P : Q, M, breg, d, xr, wc, we, wd, dinv, T(L.post[st][0]),
+                           T(L.post[st][1]), st == 0);
     }
 }
 
