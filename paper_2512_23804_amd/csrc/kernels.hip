@@ -608,22 +608,35 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
 constexpr int kDotsU = SG_DOTS_U;   // elements per lane per trip, dots pass
 constexpr int kUpdU = SG_UPD_U;     // elements per lane per trip, update pass
 
+// Element pairs (2p, 2p+1) of a member's vector, counted from the member's
+// first element: with AL the pair is 16-byte aligned and read by one load,
+// else by two 8-byte loads (same arithmetic either way, so a member's sums do
+// not depend on where the batch places it).
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+template <bool AL, bool NT>
+__device__ __forceinline__ dbl2 ld_pair(const double* base, int64_t p) {
+    if (AL) {
+        const dbl2* q = reinterpret_cast<const dbl2*>(base) + p;
+        return NT ? __builtin_nontemporal_load(q) : *q;
+    }
+    const double* q = base + 2 * p;
+    return NT ? dbl2{__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1)} : dbl2{q[0], q[1]};
+}
+
 // Dots pass, with w: slots [0, nv) a_i = V_i.u, [nv, 2nv) t_i = V_i.w,
 // 2nv: u.u, 2nv+1: u.w, 2nv+2: w.w; without w: [0, nv) a_i, nv: u.u.
 // u is basis slot nv.  The block's four wavefronts split the basis vectors
 // (vector i goes to wavefront i mod 4, at most NPW each) and each walks the
-// block's whole chunk, so a lane carries at most 2 NPW + 1 sums and keeps many
-// loads in flight; u and w are re-read by the four wavefronts from cache.
-// Members with neither flag set are skipped.
-template <int NPW, bool WITH_W>
-__global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, int64_t vstride, int nv,
-                                                  const double* __restrict__ w, int64_t n, int64_t mstride,
-                                                  const int* __restrict__ active, const int* __restrict__ pending,
-                                                  double* __restrict__ partial, int nblk) {
+// block's whole chunk of element pairs, so a lane carries at most 2 NPW + 1
+// sums and keeps many loads in flight; u and w are re-read by the four
+// wavefronts from cache.  Members with neither flag set are skipped.
+template <int NPW, bool WITH_W, bool AL>
+__device__ __forceinline__ void dcgs_dots_body(const double* __restrict__ V, int64_t vstride, int nv,
+                                               const double* __restrict__ w, int64_t n, int64_t mstride,
+                                               double* __restrict__ partial, int nblk) {
     const int mem = blockIdx.y;
-    if (!active[mem] && !pending[mem]) return;
     int64_t lo, hi;
-    chunk_range(n, nblk, blockIdx.x, lo, hi);
+    chunk_range(n / 2, nblk, blockIdx.x, lo, hi);      // pair range
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     // the wavefront's scalar product: wave 1 u.u (also without w), wave 2 u.w, wave 3 w.w
@@ -635,13 +648,20 @@ __global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, 
     const double* Vm = V + mem * mstride;
     const double* um = Vm + nv * vstride;
     const double* wm = w + mem * mstride;
-    int64_t e = lo + lane;
-    for (; e + (kDotsU - 1) * 64 < hi; e += kDotsU * 64) {
-        double ue[kDotsU], we[kDotsU];
+    auto add = [&](const dbl2* ue, const dbl2* we, int64_t p, int cnt) {
+        for (int u = 0; u < cnt; ++u) {
+            if (sdot == 1) acc[NA - 1] += ue[u].x * ue[u].x + ue[u].y * ue[u].y;
+            if (WITH_W && sdot == 2) acc[NA - 1] += ue[u].x * we[u].x + ue[u].y * we[u].y;
+            if (WITH_W && sdot == 3) acc[NA - 1] += we[u].x * we[u].x + we[u].y * we[u].y;
+        }
+    };
+    int64_t p = lo + lane;
+    for (; p + (kDotsU - 1) * 64 < hi; p += kDotsU * 64) {
+        dbl2 ue[kDotsU], we[kDotsU];
 #pragma unroll
         for (int u = 0; u < kDotsU; ++u) {
-            ue[u] = um[e + u * 64];
-            we[u] = WITH_W ? wm[e + u * 64] : 0.0;
+            ue[u] = ld_pair<AL, false>(um, p + u * 64);
+            we[u] = WITH_W ? ld_pair<AL, false>(wm, p + u * 64) : dbl2{0.0, 0.0};
         }
 #pragma unroll
         for (int k = 0; k < NPW; ++k) {
@@ -649,27 +669,36 @@ __global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, 
             if (i < nv) {
 #pragma unroll
                 for (int u = 0; u < kDotsU; ++u) {
-                    const double v = ld_stream(Vm + i * vstride + e + u * 64);
-                    acc[k] += v * ue[u];
-                    if (WITH_W) acc[NPW + k] += v * we[u];
+                    const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p + u * 64);
+                    acc[k] += v.x * ue[u].x + v.y * ue[u].y;
+                    if (WITH_W) acc[NPW + k] += v.x * we[u].x + v.y * we[u].y;
                 }
             }
         }
-#pragma unroll
-        for (int u = 0; u < kDotsU; ++u) {
-            if (sdot == 1) acc[NA - 1] += ue[u] * ue[u];
-            if (WITH_W && sdot == 2) acc[NA - 1] += ue[u] * we[u];
-            if (WITH_W && sdot == 3) acc[NA - 1] += we[u] * we[u];
-        }
+        add(ue, we, p, kDotsU);
     }
-    for (; e < hi; e += 64) {
-        const double ue = um[e];
-        const double we = WITH_W ? wm[e] : 0.0;
+    for (; p < hi; p += 64) {
+        const dbl2 ue = ld_pair<AL, false>(um, p);
+        const dbl2 we = WITH_W ? ld_pair<AL, false>(wm, p) : dbl2{0.0, 0.0};
 #pragma unroll
         for (int k = 0; k < NPW; ++k) {
             const int i = wave + 4 * k;
             if (i < nv) {
-                const double v = ld_stream(Vm + i * vstride + e);
+                const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p);
+                acc[k] += v.x * ue.x + v.y * ue.y;
+                if (WITH_W) acc[NPW + k] += v.x * we.x + v.y * we.y;
+            }
+        }
+        add(&ue, &we, p, 1);
+    }
+    if ((n & 1) && blockIdx.x == nblk - 1 && lane == 0) {   // odd length: the last element
+        const int64_t e = n - 1;
+        const double ue = um[e], we = WITH_W ? wm[e] : 0.0;
+#pragma unroll
+        for (int k = 0; k < NPW; ++k) {
+            const int i = wave + 4 * k;
+            if (i < nv) {
+                const double v = Vm[i * vstride + e];
                 acc[k] += v * ue;
                 if (WITH_W) acc[NPW + k] += v * we;
             }
@@ -698,9 +727,85 @@ __global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, 
     }
 }
 
+// 16-byte pair loads need the member's first element and the basis slot
+// stride to be even (allocations are 256-byte aligned).
+__device__ __forceinline__ bool pairs_aligned(int64_t vstride, int64_t mstride) {
+    return ((blockIdx.y * mstride) & 1) == 0 && (vstride & 1) == 0;
+}
+
+template <int NPW, bool WITH_W>
+__global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, int64_t vstride, int nv,
+                                                  const double* __restrict__ w, int64_t n, int64_t mstride,
+                                                  const int* __restrict__ active, const int* __restrict__ pending,
+                                                  double* __restrict__ partial, int nblk) {
+    const int mem = blockIdx.y;
+    if (!active[mem] && !pending[mem]) return;
+    if (pairs_aligned(vstride, mstride))
+        dcgs_dots_body<NPW, WITH_W, true>(V, vstride, nv, w, n, mstride, partial, nblk);
+    else
+        dcgs_dots_body<NPW, WITH_W, false>(V, vstride, nv, w, n, mstride, partial, nblk);
+}
+
 // Update pass: basis slot nv+1 = (w - sum_{i<=nv} s_i U_i) / nu with
 // s_i = coef[mem*kSlots + i] and 1/nu = scal[mem*4 + 2]; reads slots 0..nv and
-// w, writes slot nv+1 only.  NT >= nv + 1 terms.
+// w, writes slot nv+1 only.  NT >= nv + 1 terms; element pairs as above.
+template <int NT, bool AL>
+__device__ __forceinline__ void dcgs_update_body(double* __restrict__ V, int64_t vstride, int nv,
+                                                 const double* __restrict__ w, int64_t n, int64_t mstride,
+                                                 const double* sv, double inv_nu, int nblk) {
+    const int mem = blockIdx.y;
+    int64_t lo, hi;
+    chunk_range(n / 2, nblk, blockIdx.x, lo, hi);
+    const double* Vm = V + mem * mstride;
+    double* un = V + mem * mstride + (nv + 1) * vstride;
+    const double* wm = w + mem * mstride;
+    auto store = [&](int64_t p, dbl2 v) {
+        if (AL)
+            reinterpret_cast<dbl2*>(un)[p] = v;
+        else {
+            un[2 * p] = v.x;
+            un[2 * p + 1] = v.y;
+        }
+    };
+    int64_t p = lo + threadIdx.x;
+    for (; p + (kUpdU - 1) * RB < hi; p += kUpdU * RB) {
+        dbl2 acc[kUpdU];
+#pragma unroll
+        for (int u = 0; u < kUpdU; ++u) acc[u] = ld_pair<AL, true>(wm, p + u * RB);
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            if (i <= nv) {
+#pragma unroll
+                for (int u = 0; u < kUpdU; ++u) {
+                    const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p + u * RB);
+                    acc[u].x -= sv[i] * v.x;
+                    acc[u].y -= sv[i] * v.y;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kUpdU; ++u) store(p + u * RB, dbl2{acc[u].x * inv_nu, acc[u].y * inv_nu});
+    }
+    for (; p < hi; p += RB) {
+        dbl2 acc = ld_pair<AL, true>(wm, p);
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            if (i <= nv) {
+                const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p);
+                acc.x -= sv[i] * v.x;
+                acc.y -= sv[i] * v.y;
+            }
+        }
+        store(p, dbl2{acc.x * inv_nu, acc.y * inv_nu});
+    }
+    if ((n & 1) && blockIdx.x == nblk - 1 && threadIdx.x == 0) {   // odd length: the last element
+        const int64_t e = n - 1;
+        double acc = wm[e];
+        for (int i = 0; i <= nv; ++i) acc -= sv[i] * Vm[i * vstride + e];
+        un[e] = acc * inv_nu;
+    }
+}
+
 template <int NT>
 __global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int64_t vstride, int nv,
                                                     const double* __restrict__ w, int64_t n, int64_t mstride,
@@ -708,37 +813,14 @@ __global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int6
                                                     const int* __restrict__ active, int nblk) {
     const int mem = blockIdx.y;
     if (!active[mem]) return;                       // uniform per block, before the barrier
-    int64_t lo, hi;
-    chunk_range(n, nblk, blockIdx.x, lo, hi);
     __shared__ double sv[NT];                       // broadcast reads; keeps the lanes' registers for loads
     if ((int)threadIdx.x < NT) sv[threadIdx.x] = (int)threadIdx.x <= nv ? coef[mem * kSlots + threadIdx.x] : 0.0;
     __syncthreads();
     const double inv_nu = scal[mem * 4 + 2];
-    const double* Vm = V + mem * mstride;
-    double* un = V + mem * mstride + (nv + 1) * vstride;
-    const double* wm = w + mem * mstride;
-    int64_t e = lo + threadIdx.x;
-    for (; e + (kUpdU - 1) * RB < hi; e += kUpdU * RB) {
-        double acc[kUpdU];
-#pragma unroll
-        for (int u = 0; u < kUpdU; ++u) acc[u] = ld_stream(wm + e + u * RB);
-#pragma unroll
-        for (int i = 0; i < NT; ++i) {
-            if (i <= nv) {
-#pragma unroll
-                for (int u = 0; u < kUpdU; ++u) acc[u] -= sv[i] * ld_stream(Vm + i * vstride + e + u * RB);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kUpdU; ++u) un[e + u * RB] = acc[u] * inv_nu;
-    }
-    for (; e < hi; e += RB) {
-        double acc = ld_stream(wm + e);
-#pragma unroll
-        for (int i = 0; i < NT; ++i)
-            if (i <= nv) acc -= sv[i] * ld_stream(Vm + i * vstride + e);
-        un[e] = acc * inv_nu;
-    }
+    if (pairs_aligned(vstride, mstride))
+        dcgs_update_body<NT, true>(V, vstride, nv, w, n, mstride, sv, inv_nu, nblk);
+    else
+        dcgs_update_body<NT, false>(V, vstride, nv, w, n, mstride, sv, inv_nu, nblk);
 }
 
 // out[mem*out_stride + out_offset + i] = sum_blk partial[(mem*kSlots + i)*nblk + blk]

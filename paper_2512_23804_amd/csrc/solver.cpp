@@ -228,7 +228,8 @@ struct Krylov {
     int64_t N;             // KKT vector length per member
     int nblk;
     hipStream_t st;
-    double* V;             // [m+1][B][N]
+    double* V;             // [m+1][vs]: slot i holds the B member vectors back to back
+    int64_t vs;            // slot stride: B*N rounded up to 64 elements
     void* Z;               // [m][B][N] (double or float)
     bool z32;              // preconditioner in FP32, Z stored in FP32
     bool op32;             // KKT operator on Z_j in FP32 too (refinement inner cycles)
@@ -248,7 +249,8 @@ struct Krylov {
         nblk = (int)std::min<int64_t>(2048, std::max<int64_t>(1, N / (256 * 16)));
         z32 = fp32_precond;
         op32 = fp32_precond && fp32_op;
-        V = h.ws.get_t<double>("kV", (size_t)(m + 1) * B * N);
+        vs = ((int64_t)B * N + 63) / 64 * 64;
+        V = h.ws.get_t<double>("kV", (size_t)(m + 1) * vs);
         Z = z32 ? (void*)h.ws.get_t<float>("kZ32", (size_t)m * B * N) : (void*)h.ws.get_t<double>("kZ", (size_t)m * B * N);
         w = h.ws.get_t<double>("kw", (size_t)B * N);
         partial = h.ws.get_t<double>("kpart", (size_t)B * kSlots * nblk);
@@ -273,7 +275,7 @@ struct Krylov {
         w32 = op32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
         zt = z32 && !op32 ? h.ws.get_t<double>("kzt", (size_t)B * N) : nullptr;
     }
-    double* Vi(int i) { return V + (int64_t)i * B * N; }
+    double* Vi(int i) { return V + (int64_t)i * vs; }
 
     // y = K x for all members (FP64, or through FP32 when fp32)
     void apply_op(const double* x, double* y, bool fp32) {
@@ -369,7 +371,7 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         launch_cycle_start(K.kd, m, K.kd.nrm, B, st);    // kd.nrm holds ||r||^2 from residual()
         launch_copy_scale_rows(r, K.Vi(0), K.kd.nrm, N, B, N, st);
         const bool dcgs = h.opt.arnoldi == SG_ARNOLDI_DCGS2;
-        const int64_t vs = (int64_t)B * N;
+        const int64_t vs = K.vs;
         // one FGMRES iteration: preconditioner, KKT apply, Arnoldi, Givens
         auto iteration = [&](int j) {
             K.apply_prec(j);
