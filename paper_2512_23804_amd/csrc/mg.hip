@@ -159,9 +159,18 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
     const T wc = T(L.wc), we = T(L.we), wd = T(L.wd), dinv = T(L.dinv);
     const int N1 = m + 1, C1 = mc + 1;
     const T* ecol = ec + (int64_t)c * C1 * C1;
+    // the coarse correction under the region, staged once in LDS (the
+    // interpolation reads each coarse value up to nine times)
+    constexpr int CW = W / 2 + 2;
+    __shared__ T se[CW * CW];
+    const int CX0 = FX0 >= 0 ? FX0 / 2 : -((1 - FX0) / 2), CY0 = FY0 >= 0 ? FY0 / 2 : -((1 - FY0) / 2);
+    for (int q = threadIdx.x; q < CW * CW; q += 256) {
+        const int I = CX0 + q % CW, J = CY0 + q / CW;
+        se[q] = (I >= 0 && I <= mc && J >= 0 && J <= mc) ? ecol[J * C1 + I] : T(0);
+    }
     T breg[PPT], d[PPT], xr[PPT];
     load_region<T, W, PPT>(breg, b + bmap.off(c), FX0, FY0, m);
-    pre_smooth<T, W, PPT, NPRE>(breg, d, xr, sx, FX0, FY0, m, L, wc, we, wd, dinv);
+    pre_smooth<T, W, PPT, NPRE>(breg, d, xr, sx, FX0, FY0, m, L, wc, we, wd, dinv);   // (its barriers cover se)
     // x += P e_c on the nodes where the pre-smoothed iterate is valid
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
@@ -170,8 +179,8 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
         const int X = FX0 + i, Y = FY0 + j;
         if (q < W * W && i >= H0 && i < W - H0 && j >= H0 && j < W - H0 && X >= 1 && X <= m - 1 && Y >= 1 &&
             Y <= m - 1) {
-            const int I0 = X >> 1, J0 = Y >> 1, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
-            xr[p] += T(0.25) * (ecol[J0 * C1 + I0] + ecol[J0 * C1 + I1] + ecol[J1 * C1 + I0] + ecol[J1 * C1 + I1]);
+            const int I0 = (X >> 1) - CX0, J0 = (Y >> 1) - CY0, I1 = I0 + (X & 1), J1 = J0 + (Y & 1);
+            xr[p] += T(0.25) * (se[J0 * CW + I0] + se[J0 * CW + I1] + se[J1 * CW + I0] + se[J1 * CW + I1]);
         }
     }
     __syncthreads();
