@@ -9,8 +9,8 @@
 // corner a with opposite corner o and corner sum s this is (5 v_a - v_o - s)/6.
 //
 // Work mapping (64-wide wavefronts): a wavefront owns one output chaos column
-// j; its two 32-lane halves each walk a strip of R node rows of a 30-column
-// x-tile.  Lane l holds node column X = 30*tx + l - 1 (lanes 0 and 31 are
+// j; its two 32-lane halves each walk a strip of RS node rows (2, 4 or 8,
+// chosen per shape by the autotuner) of a 30-column x-tile.  Lane l holds node column X = 30*tx + l - 1 (lanes 0 and 31 are
 // halos), loads each input value once per row, gets the x+1 neighbour by a
 // lane shuffle and keeps the previous row in registers, so every input value
 // is read about once per output column.  The node value is the sum of the
@@ -19,6 +19,9 @@
 // Blocks (4 wavefronts = 4 consecutive output columns of one spatial tile) are
 // numbered so that each XCD receives a contiguous range of tiles with all
 // their chaos columns: the neighbour columns a tile reads stay in that XCD's L2.
+// These kernels are bound by the vector-memory data path (each neighbour
+// column is loaded once per output column that needs it), not by L2 or HBM;
+// the KKT kernel therefore reads its coefficient tile from LDS.
 #include "common.hpp"
 
 namespace sg {
@@ -32,11 +35,6 @@ constexpr int KMAX = 8;         // modes handled by the sweep kernels
 __device__ __forceinline__ int xcd_swizzle(int bid, int nb_padded) {
     const int per = nb_padded >> 3;
     return (bid & 7) * per + (bid >> 3);
-}
-
-template <typename T>
-__device__ __forceinline__ T ldn(const T* __restrict__ col, int n, int X, int Y) {
-    return (X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1) ? col[(int64_t)Y * (n + 1) + X] : T(0);
 }
 
 template <typename T>
