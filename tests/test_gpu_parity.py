@@ -334,3 +334,58 @@ def test_graph_replay_matches_direct_launches(precision):
         outs.append(x.clone())
     for o in outs[1:]:
         assert torch.equal(o, outs[0])
+
+
+OPTION_CASES = [
+    # (label, shape (n, M, P, sigma, beta, gamma, n_t), options)
+    ("M>8 gather kernels", (16, 10, 2, 0.2, 1e-2, 0.0, 1), {}),
+    ("M>8 time-dependent", (16, 9, 2, 0.15, 1e-3, 0.0, 3), {}),
+    ("unfused Chebyshev", (32, 3, 2, 0.25, 1e-3, 0.0, 1), dict(cheb_steps=12)),
+    ("smoothing 1/3", (32, 3, 2, 0.25, 1e-3, 0.0, 1), dict(gmg_pre=1, gmg_post=3)),
+    ("smoothing 3/1", (32, 3, 2, 0.25, 1e-3, 0.3, 1), dict(gmg_pre=3, gmg_post=1)),
+    ("smoothing 4/4", (16, 2, 2, 0.25, 1e-3, 0.0, 2), dict(gmg_pre=4, gmg_post=4)),
+    ("truncation r=3", (32, 4, 2, 0.25, 1e-3, 0.0, 1), dict(truncation_r=3)),
+    ("coarse-only hierarchy", (8, 2, 2, 0.2, 1e-2, 0.0, 1), {}),
+    ("three level kernels above the tail", (256, 2, 1, 0.2, 1e-2, 0.0, 1), {}),
+]
+
+
+@pytest.mark.parametrize("label,shape,opts", OPTION_CASES, ids=[c[0] for c in OPTION_CASES])
+def test_option_paths(label, shape, opts):
+    """Code paths the default workloads do not take: the gather kernels for
+    M > 8, the per-step Chebyshev kernel (more than 9 steps), other smoothing
+    degrees (separate kernel instances), intermediate truncation, the
+    hierarchy that is only the coarse grid, and several level kernels above
+    the fused tail.  KKT and preconditioner applies against the oracle, then
+    the solve (against the direct solution, or the oracle's true residual at
+    the large grid)."""
+    n, M, P, sigma, beta, gamma, nt = shape
+    dev = _dev()
+    _say(f"option path {label} {shape} {opts}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, y0=nt > 1)
+    sg = kkt.setup(prob)
+    # at 256 x 256 the FP64 residual floor of this system is a few 1e-12
+    rtol = 1e-12 if n <= 32 else 1e-10
+    h = _setup([kw], rtol=rtol, max_iter=600, **opts)
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-1, 1, size=kkt.rhs(sg).size)
+    xd = torch.from_numpy(kkt_to_canonical(sg, x)).to(dev)
+    yd = torch.zeros_like(xd)
+    h.apply_kkt(xd, yd)
+    zd = torch.zeros_like(xd)
+    h.precond_apply(xd, zd)
+    torch.cuda.synchronize()
+    assert rel_max(canonical_to_kkt(sg, yd.cpu().numpy()), kkt.kkt_apply_matricized(sg, x)) < 1e-12
+    inner = precond.make_inner(sg, nu_pre=opts.get("gmg_pre", 2), nu_post=opts.get("gmg_post", 2))
+    r = opts.get("truncation_r", 0) or M + 1
+    ref = precond.precond_apply(sg, x, inner, r, cheb_steps=opts.get("cheb_steps", 5))
+    assert rel_max(canonical_to_kkt(sg, zd.cpu().numpy()), ref) < 1e-12
+    sol = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+    rc, info = h.solve(sol)
+    assert rc == 0 and info[0].rel_res_true <= rtol, (rc, info[0].rel_res_true)
+    xs = canonical_to_kkt(sg, sol.cpu().numpy())
+    b = kkt.rhs(sg)
+    assert np.linalg.norm(b - kkt.kkt_apply_matricized(sg, xs)) / np.linalg.norm(b) < 10 * rtol
+    if n <= 32:
+        for a, bb in zip(kkt.split(sg, xs), kkt.split(sg, kkt.solve_direct(sg))):
+            assert rel_max(a, bb) < 1e-8
