@@ -236,18 +236,21 @@ struct ChebW {
     double omega[16];   // omega_{k+1} for k = 1..steps-1
 };
 
-template <typename T, int TF, int H>
-__global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt, int time, int64_t nodes, OpDev op,
+template <typename T, int TF, int H, int NT>
+__global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, int time, int64_t nodes, OpDev op,
                                                          int64_t vstride, const T* __restrict__ r, T* __restrict__ z,
                                                          ChebW cw, int tiles_x) {
-    constexpr int W = TF + 2 * H;     // H = steps - 1
-    constexpr int PPT = (W * W + 255) / 256;
+    // H = steps - 1 stencil steps; the region keeps a halo of at least one node
+    // so that the first tile row and column also hold the ring at index 0
+    constexpr int HR = H > 0 ? H : 1;
+    constexpr int W = TF + 2 * HR;
+    constexpr int PPT = (W * W + NT - 1) / NT;
     __shared__ T sc[W * W];           // x_k (read by the mass stencil); b, x_{k-1}, x_k own nodes in registers
     const int l = blockIdx.y;
     const int vec = blockIdx.z;
     const int mem = op.mem_shared ? 0 : vec;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-    const int FX0 = 1 + tx * TF - H, FY0 = 1 + ty * TF - H;
+    const int FX0 = 1 + tx * TF - HR, FY0 = 1 + ty * TF - HR;
     const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;
     const int N1 = n + 1;
     const T h = T(1) / T(n);
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     T breg[PPT], xp[PPT], xc[PPT];
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        const int q = threadIdx.x + 256 * p;
+        const int q = threadIdx.x + NT * p;
         const int X = FX0 + q % W, Y = FY0 + q / W;
         const bool inter = q < W * W && X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1;
         breg[p] = inter ? rc[Y * N1 + X] : T(0);
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
         const int lo = k, hi = W - k;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
-            const int q = threadIdx.x + 256 * p;
+            const int q = threadIdx.x + NT * p;
             const int i = q % W, j = q / W;
             const int X = FX0 + i, Y = FY0 + j;
             if (q < W * W && i >= lo && i < hi && j >= lo && j < hi && X >= 1 && X <= n - 1 && Y >= 1 &&
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
             __syncthreads();
 #pragma unroll
             for (int p = 0; p < PPT; ++p) {
-                const int q = threadIdx.x + 256 * p;
+                const int q = threadIdx.x + NT * p;
                 if (q < W * W) sc[q] = xc[p];
             }
             __syncthreads();
@@ -304,9 +307,9 @@ __global__ __launch_bounds__(256) void k_mass_cheb_fused(int n, int nxi, int nt,
     T* zc = z + (int64_t)vec * vstride + (int64_t)l * nodes;
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
-        const int q = threadIdx.x + 256 * p;
+        const int q = threadIdx.x + NT * p;
         const int X = FX0 + q % W, Y = FY0 + q / W;
-        if (q < W * W && X >= FX0 + H - ex && X < FX0 + H + TF && Y >= FY0 + H - ey && Y < FY0 + H + TF &&
+        if (q < W * W && X >= FX0 + HR - ex && X < FX0 + HR + TF && Y >= FY0 + HR - ey && Y < FY0 + HR + TF &&
             X <= n && Y <= n)
             zc[Y * N1 + X] = f * xc[p];
     }
@@ -591,13 +594,14 @@ void tail_m(const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColM
 
 template <typename T, int H>
 void cheb_h(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, const ChebW& cw, hipStream_t st) {
-    constexpr int TF = 32;
-    const int tx = (s.n - 1 + TF - 1) / TF;
     const int ncols = 2 * s.nt * s.nxi;
     if (ncols > 65535 || nvec > 65535) throw Error(SG_ERR_INVALID, "Chebyshev: launch grid too large");
-    dim3 grid(tx * tx, ncols, nvec);
-    hipLaunchKernelGGL((k_mass_cheb_fused<T, TF, H>), grid, dim3(256), 0, st, s.n, s.nxi, s.nt, (int)s.time, s.nodes,
-                       op, 3 * s.blk, r, z, cw, tx);
+    // 32-node tiles at every grid size: 64-node tiles (512 threads) fetch fewer
+    // halo nodes but measured slower at 128^2 and 512^2
+    constexpr int TF = 32;
+    const int tx = (s.n - 1 + TF - 1) / TF;
+    hipLaunchKernelGGL((k_mass_cheb_fused<T, TF, H, 256>), dim3(tx * tx, ncols, nvec), dim3(256), 0, st, s.n, s.nxi,
+                       s.nt, (int)s.time, s.nodes, op, 3 * s.blk, r, z, cw, tx);
 }
 
 constexpr int TCD = 16;   // coarse nodes per down tile side

@@ -341,6 +341,8 @@ OPTION_CASES = [
     ("M>8 gather kernels", (16, 10, 2, 0.2, 1e-2, 0.0, 1), {}),
     ("M>8 time-dependent", (16, 9, 2, 0.15, 1e-3, 0.0, 3), {}),
     ("unfused Chebyshev", (32, 3, 2, 0.25, 1e-3, 0.0, 1), dict(cheb_steps=12)),
+    ("Chebyshev one step", (16, 2, 2, 0.25, 1e-3, 0.0, 1), dict(cheb_steps=1)),
+    ("Chebyshev nine steps", (16, 2, 2, 0.25, 1e-3, 0.0, 2), dict(cheb_steps=9)),
     ("smoothing 1/3", (32, 3, 2, 0.25, 1e-3, 0.0, 1), dict(gmg_pre=1, gmg_post=3)),
     ("smoothing 3/1", (32, 3, 2, 0.25, 1e-3, 0.3, 1), dict(gmg_pre=3, gmg_post=1)),
     ("smoothing 4/4", (16, 2, 2, 0.25, 1e-3, 0.0, 2), dict(gmg_pre=4, gmg_post=4)),
@@ -366,15 +368,18 @@ def test_option_paths(label, shape, opts):
     sg = kkt.setup(prob)
     # at 256 x 256 the FP64 residual floor of this system is a few 1e-12
     rtol = 1e-12 if n <= 32 else 1e-10
+    if opts.get("cheb_steps", 5) == 1:
+        rtol = max(rtol, 1e-10)
     h = _setup([kw], rtol=rtol, max_iter=600, **opts)
     rng = np.random.default_rng(9)
     x = rng.uniform(-1, 1, size=kkt.rhs(sg).size)
     xd = torch.from_numpy(kkt_to_canonical(sg, x)).to(dev)
-    yd = torch.zeros_like(xd)
+    yd = torch.full_like(xd, np.nan)          # every output node, ring included, must be written
     h.apply_kkt(xd, yd)
-    zd = torch.zeros_like(xd)
+    zd = torch.full_like(xd, np.nan)
     h.precond_apply(xd, zd)
     torch.cuda.synchronize()
+    assert ring_is_zero(yd.cpu().numpy(), n) and ring_is_zero(zd.cpu().numpy(), n)
     assert rel_max(canonical_to_kkt(sg, yd.cpu().numpy()), kkt.kkt_apply_matricized(sg, x)) < 1e-12
     inner = precond.make_inner(sg, nu_pre=opts.get("gmg_pre", 2), nu_post=opts.get("gmg_post", 2))
     r = opts.get("truncation_r", 0) or M + 1
@@ -386,6 +391,7 @@ def test_option_paths(label, shape, opts):
     xs = canonical_to_kkt(sg, sol.cpu().numpy())
     b = kkt.rhs(sg)
     assert np.linalg.norm(b - kkt.kkt_apply_matricized(sg, xs)) / np.linalg.norm(b) < 10 * rtol
-    if n <= 32:
+    if n <= 32 and b.size <= 60000:     # the oracle's sparse LU takes minutes above this
         for a, bb in zip(kkt.split(sg, xs), kkt.split(sg, kkt.solve_direct(sg))):
-            assert rel_max(a, bb) < 1e-8
+            # forward error <= condition number x residual: 1e-8 at rtol 1e-12
+            assert rel_max(a, bb) < 1e4 * rtol
