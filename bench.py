@@ -222,6 +222,8 @@ def main():
                     help="only copy a 1 GiB FP64 tensor three times (calibrates hardware byte counters) and exit")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no HIP graph replay)")
+    ap.add_argument("--sweep-rows", type=int, default=0, choices=[0, 2, 4, 8],
+                    help="strip rows of the sweep kernels (0: autotuned)")
     ap.add_argument("--arnoldi", default="dcgs2", choices=sorted(ARNOLDI),
                     help="FGMRES orthogonalisation (delayed reorthogonalisation or Gram-Schmidt twice)")
     args = ap.parse_args()
@@ -250,7 +252,7 @@ def main():
     graphs = 0 if args.no_graphs else 1
     # headline: FP64 batch (the whole beta sweep) per step
     arn = ARNOLDI[args.arnoldi]
-    opts = sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn)
+    opts = sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn, sweep_rows=args.sweep_rows)
     tuned = []
     dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream, tuned)
     nsolve = len(probs) * args.steps
@@ -264,8 +266,8 @@ def main():
     kern = {}
     kinds = PROF_KIND if args.profile_kernel == "auto" else {args.profile_kernel: PROF_KIND[args.profile_kernel]}
     for name, kind in kinds.items():
-        _, pinfo = timed_solves(torch, sgl, probs, sgl.default_options(rtol=1e-8, profile=kind, arnoldi=arn), 1, 0,
-                                stream)
+        popt = sgl.default_options(rtol=1e-8, profile=kind, arnoldi=arn, sweep_rows=args.sweep_rows)
+        _, pinfo = timed_solves(torch, sgl, probs, popt, 1, 0, stream)
         pms, pbytes, plaunch = pinfo[0][0].prof_ms, pinfo[0][0].prof_bytes, pinfo[0][0].prof_launches
         if plaunch == 0:
             continue
@@ -302,12 +304,13 @@ def main():
     }
     if not args.no_extras:
         o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE, use_graphs=graphs,
-                                  arnoldi=arn)
+                                  arnoldi=arn, sweep_rows=args.sweep_rows)
         dt32, inf32 = timed_solves(torch, sgl, probs, o32, args.steps, 1, stream)
         out["fp32_refine"] = {"value": nsolve / dt32, "unit": "solves/s", "dtype": "f32 operator/preconditioner, "
                               "f64 Arnoldi and refinement", "iterations": [i.iters for i in inf32[0]],
                               "max_rel_res": max(i.rel_res_true for st in inf32 for i in st)}
-        opc = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_PRECOND, use_graphs=graphs, arnoldi=arn)
+        opc = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_PRECOND, use_graphs=graphs, arnoldi=arn,
+                                  sweep_rows=args.sweep_rows)
         dtp, infp = timed_solves(torch, sgl, probs, opc, args.steps, 1, stream)
         out["fp32_precond"] = {"value": nsolve / dtp, "unit": "solves/s", "dtype": "f32 preconditioner, "
                                "f64 operator, Arnoldi and restarts", "iterations": [i.iters for i in infp[0]],
@@ -315,8 +318,8 @@ def main():
         single = []
         t_single = 0.0
         for p in probs:
-            dts, infs = timed_solves(torch, sgl, [p], sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn), 1, 1,
-                                     stream)
+            sopt = sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn, sweep_rows=args.sweep_rows)
+            dts, infs = timed_solves(torch, sgl, [p], sopt, 1, 1, stream)
             t_single += dts
             single.append(infs[0][0].iters)
         out["fp64_single"] = {"value": len(probs) / t_single, "unit": "solves/s", "iterations": single}

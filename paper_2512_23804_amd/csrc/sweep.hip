@@ -24,6 +24,12 @@
 // the KKT kernel therefore reads its coefficient tile from LDS.
 #include "common.hpp"
 
+// No automatic contraction in this file: every fused multiply-add is written
+// out (fmadd), so each kernel's rounding sequence is the one in the source and
+// the strip variants give bit-identical results whatever the code around the
+// arithmetic looks like after inlining.
+#pragma clang fp contract(off)
+
 namespace sg {
 
 namespace {
@@ -46,15 +52,18 @@ __device__ __forceinline__ T shup(T v) {
     return __shfl_up(v, 1, GW);
 }
 
+__device__ __forceinline__ double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Reference-element stiffness on a corner vector: k_a = (5 v_a - v_opp - s)/6.
 template <typename T>
 __device__ __forceinline__ void kref(T v0, T v1, T v2, T v3, T& k0, T& k1, T& k2, T& k3) {
     const T s = (v0 + v1) + (v2 + v3);
     const T sixth = T(1.0 / 6.0);
-    k0 = (T(5) * v0 - v2 - s) * sixth;
-    k1 = (T(5) * v1 - v3 - s) * sixth;
-    k2 = (T(5) * v2 - v0 - s) * sixth;
-    k3 = (T(5) * v3 - v1 - s) * sixth;
+    k0 = (fmadd(T(5), v0, -v2) - s) * sixth;
+    k1 = (fmadd(T(5), v1, -v3) - s) * sixth;
+    k2 = (fmadd(T(5), v2, -v0) - s) * sixth;
+    k3 = (fmadd(T(5), v3, -v1) - s) * sixth;
 }
 
 struct SweepGeom {
@@ -173,10 +182,10 @@ struct Sweep {
         for (int r = 0; r < RS + 1; ++r) {
             const T top = vals[r + 1];
             const T topR = shdn(top);
-            v[r][0] += c[r] * prev;
-            v[r][1] += c[r] * prevR;
-            v[r][2] += c[r] * topR;
-            v[r][3] += c[r] * top;
+            v[r][0] = fmadd(c[r], prev, v[r][0]);
+            v[r][1] = fmadd(c[r], prevR, v[r][1]);
+            v[r][2] = fmadd(c[r], topR, v[r][2]);
+            v[r][3] = fmadd(c[r], top, v[r][3]);
             prev = top;
             prevR = topR;
         }
@@ -189,7 +198,7 @@ struct Sweep {
         for (int r = 0; r < RS + 2; ++r) {
             T x = col[st.noff(r)];
             x = ((st.nmask >> r) & 1u) ? x : T(0);
-            vals[r] = accumulate ? vals[r] + g * x : g * x;
+            vals[r] = accumulate ? fmadd(g, x, vals[r]) : g * x;
         }
     }
 
@@ -253,10 +262,10 @@ struct Sweep {
             const T topR = shdn(top);
             const T c = ((st.emask >> r) & 1u) ? w : T(0);
             const T s2 = T(2) * ((prev + prevR) + (topR + top));
-            e[r][0] += c * (s2 + T(2) * prev - topR);
-            e[r][1] += c * (s2 + T(2) * prevR - top);
-            e[r][2] += c * (s2 + T(2) * topR - prev);
-            e[r][3] += c * (s2 + T(2) * top - prevR);
+            e[r][0] = fmadd(c, fmadd(T(2), prev, s2) - topR, e[r][0]);
+            e[r][1] = fmadd(c, fmadd(T(2), prevR, s2) - top, e[r][1]);
+            e[r][2] = fmadd(c, fmadd(T(2), topR, s2) - prev, e[r][2]);
+            e[r][3] = fmadd(c, fmadd(T(2), top, s2) - prevR, e[r][3]);
             prev = top;
             prevR = topR;
         }
@@ -381,7 +390,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
             if (KIND == 0) {
                 if (inter) val = A + Bl;
             } else {
-                if (inter) val = bas[q] - scale * (A + Bl);
+                if (inter) val = fmadd(-scale, A + Bl, bas[q]);
             }
             out[q] = val;
         }

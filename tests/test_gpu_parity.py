@@ -209,7 +209,7 @@ def test_solve_fp32_refine_reaches_fp64_accuracy():
         assert rel_max(a, b) < 1e-8
 
 
-@pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[3]])
+@pytest.mark.parametrize("shape", [SHAPES[1], SHAPES[2], SHAPES[3], (64, 6, 2, 0.2, 1e-2, 0.0, 1)])
 def test_sweep_rows_bit_identical(shape):
     """The strip heights the autotuner chooses between (2, 4, 8 node rows) give
     bit-identical operator, KKT and preconditioner applies, FP64 and FP32, and
