@@ -981,11 +981,23 @@ __device__ void givens_column(double* col, double* cs, double* sn, double* g, in
 // c = (u.w - a.t) / rho and nu^2 = w.w - |t|^2 - c^2 (one Gram-Schmidt pass);
 // its rotation on a copy gives the residual estimate used to stop.  The
 // update pass then needs s = R^{-1} [t; c]: u_{j+1} = (w - sum_{i<=j} s_i U_i) / nu.
-__global__ void k_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem) {
-    const int mem = blockIdx.x * blockDim.x + threadIdx.x;
-    if (mem >= nmem) return;
+// One 64-thread block per member: the block stages the member's R (the
+// (j+1) x (j+1) leading part), reduced dots, rotations, right-hand side and the
+// two Hessenberg columns in LDS, lane 0 runs the O(j^2) recurrences there (no
+// dependent global loads) and the block writes the touched entries back.
+__global__ __launch_bounds__(64) void k_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem) {
+    constexpr int LR = 32;                         // LDS leading dimension (restart <= 31)
+    const int mem = blockIdx.x;
+    const int tid = threadIdx.x;
     const int ld = restart + 1;
     const int nv = j;
+    __shared__ double sR[LR * LR];                 // R(l, i) at [l + LR i], l, i <= j
+    __shared__ double sD[kSlots];
+    __shared__ double scs[LR], ssn[LR], sg[LR + 1];
+    __shared__ double sc0[LR + 1], sc1[LR + 1];    // Hessenberg columns j-1 and j
+    __shared__ double ssv[LR];                     // update coefficients s
+    __shared__ double a[LR], t[LR];                // V^T u_j and V^T w
+    __shared__ int flags[2];                       // [0]: committed column j-1, [1]: provisional column j
     const double* D = k.dots + (int64_t)mem * kSlots;
     double* H = k.H + (int64_t)mem * ld * restart;
     double* R = k.R + (int64_t)mem * ld * ld;      // R[l + i*ld] = R(l, i)
@@ -993,62 +1005,96 @@ __global__ void k_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nme
     double* sn = k.sn + mem * restart;
     double* g = k.g + mem * ld;
     double* sc = k.scal + mem * 4;
-    double a[32], t[32];
-    // out = R_{<j}^{-T} d (forward substitution)
-    auto lower_solve = [&](const double* d, double* out) {
-        for (int l = 0; l < nv; ++l) {
-            double v = d[l];
-            for (int p = 0; p < l; ++p) v -= R[p + l * ld] * out[p];
-            const double dl = R[l + l * ld];
-            out[l] = dl != 0.0 ? v / dl : 0.0;
+    for (int q = tid; q < (j + 1) * (j + 1); q += 64) {
+        const int l = q % (j + 1), i = q / (j + 1);
+        sR[l + LR * i] = R[l + i * ld];
+    }
+    for (int q = tid; q < kSlots; q += 64) sD[q] = D[q];
+    for (int q = tid; q < j; q += 64) {
+        scs[q] = cs[q];
+        ssn[q] = sn[q];
+    }
+    for (int q = tid; q <= j + 1 && q < ld; q += 64) sg[q] = g[q];
+    if (j >= 1)
+        for (int q = tid; q <= j; q += 64) sc0[q] = H[(int64_t)(j - 1) * ld + q];
+    __syncthreads();
+    if (tid == 0) {
+        // out = R_{<j}^{-T} d (forward substitution)
+        auto lower_solve = [&](const double* d, double* out) {
+            for (int l = 0; l < nv; ++l) {
+                double v = d[l];
+                for (int p = 0; p < l; ++p) v -= sR[p + l * LR] * out[p];
+                const double dl = sR[l + l * LR];
+                out[l] = dl != 0.0 ? v / dl : 0.0;
+            }
+        };
+        for (int i = 0; i < LR; ++i) a[i] = t[i] = 0.0;
+        flags[0] = flags[1] = 0;
+        double rho = 1.0;                          // R(0, 0) = 1: U_0 = V_0
+        if (j >= 1 && k.pending[mem]) {
+            lower_solve(sD, a);
+            const double alpha = mode ? sD[nv] : sD[2 * nv];
+            double a2 = 0.0;
+            for (int i = 0; i < nv; ++i) a2 += a[i] * a[i];
+            rho = sqrt(fmax(alpha - a2, 0.0));
+            for (int l = 0; l < nv; ++l) sR[l + j * LR] = a[l];
+            sR[j + j * LR] = rho;
+            const double nu = sc[3];
+            for (int i = 0; i < nv; ++i) sc0[i] += nu * a[i];
+            sc0[j] = nu * rho;
+            givens_column(sc0, scs, ssn, sg, j - 1);
+            k.resid[mem] = fabs(sg[j]);
+            k.pending[mem] = 0;
+            flags[0] = 1;
         }
-    };
-    double rho = 1.0;                              // R(0, 0) = 1: U_0 = V_0
-    if (j >= 1 && k.pending[mem]) {
-        lower_solve(D, a);
-        const double alpha = mode ? D[nv] : D[2 * nv];
-        double a2 = 0.0;
-        for (int i = 0; i < nv; ++i) a2 += a[i] * a[i];
-        rho = sqrt(fmax(alpha - a2, 0.0));
-        for (int l = 0; l < nv; ++l) R[l + j * ld] = a[l];
-        R[j + j * ld] = rho;
-        const double nu = sc[3];
-        double* col = H + (int64_t)(j - 1) * ld;
-        for (int i = 0; i < nv; ++i) col[i] += nu * a[i];
-        col[j] = nu * rho;
-        givens_column(col, cs, sn, g, j - 1);
-        k.resid[mem] = fabs(g[j]);
-        k.pending[mem] = 0;
+        if (mode == 0 && k.active[mem]) {
+            lower_solve(sD + nv, t);
+            double at = 0.0, t2 = 0.0;
+            for (int i = 0; i < nv; ++i) {
+                at += a[i] * t[i];
+                t2 += t[i] * t[i];
+            }
+            const double c = rho > 0.0 ? (sD[2 * nv + 1] - at) / rho : 0.0;
+            const double nu = sqrt(fmax(sD[2 * nv + 2] - t2 - c * c, 0.0));
+            for (int i = 0; i < nv; ++i) sc1[i] = t[i];
+            sc1[j] = c;
+            sc1[j + 1] = nu;
+            // provisional rotation: entry j of the column after rotations 0..j-1
+            double xr = sc1[0];
+            for (int i = 0; i < j; ++i) xr = -ssn[i] * xr + scs[i] * sc1[i + 1];
+            const double den = hypot(xr, nu);
+            k.resid[mem] = den > 0.0 ? fabs(nu / den * sg[j]) : 0.0;
+            // s = R_{<=j}^{-1} [t; c] (back substitution)
+            for (int l = j; l >= 0; --l) {
+                double v = l == j ? c : t[l];
+                for (int p = l + 1; p <= j; ++p) v -= sR[l + p * LR] * ssv[p];
+                const double dl = sR[l + l * LR];
+                ssv[l] = dl != 0.0 ? v / dl : 0.0;
+            }
+            sc[2] = nu > 0.0 ? 1.0 / nu : 0.0;
+            sc[3] = nu;
+            k.pending[mem] = 1;
+            flags[1] = 1;
+        }
     }
-    if (mode != 0 || !k.active[mem]) return;
-    lower_solve(D + nv, t);
-    double at = 0.0, t2 = 0.0;
-    for (int i = 0; i < nv; ++i) {
-        at += a[i] * t[i];
-        t2 += t[i] * t[i];
+    __syncthreads();
+    if (flags[0]) {
+        for (int q = tid; q <= j; q += 64) {
+            R[q + j * ld] = sR[q + j * LR];
+            H[(int64_t)(j - 1) * ld + q] = sc0[q];
+        }
+        if (tid == 0) {
+            cs[j - 1] = scs[j - 1];
+            sn[j - 1] = ssn[j - 1];
+            g[j - 1] = sg[j - 1];
+            g[j] = sg[j];
+        }
     }
-    const double c = rho > 0.0 ? (D[2 * nv + 1] - at) / rho : 0.0;
-    const double nu = sqrt(fmax(D[2 * nv + 2] - t2 - c * c, 0.0));
-    double* col = H + (int64_t)j * ld;
-    for (int i = 0; i < nv; ++i) col[i] = t[i];
-    col[j] = c;
-    col[j + 1] = nu;
-    // provisional rotation: entry j of the column after rotations 0..j-1
-    double xr = col[0];
-    for (int i = 0; i < j; ++i) xr = -sn[i] * xr + cs[i] * col[i + 1];
-    const double den = hypot(xr, nu);
-    k.resid[mem] = den > 0.0 ? fabs(nu / den * g[j]) : 0.0;
-    // s = R_{<=j}^{-1} [t; c] (back substitution)
-    double* sv = k.coef + (int64_t)mem * kSlots;
-    for (int l = j; l >= 0; --l) {
-        double v = l == j ? c : t[l];
-        for (int p = l + 1; p <= j; ++p) v -= R[l + p * ld] * sv[p];
-        const double dl = R[l + l * ld];
-        sv[l] = dl != 0.0 ? v / dl : 0.0;
+    if (flags[1]) {
+        for (int q = tid; q <= j + 1; q += 64) H[(int64_t)j * ld + q] = sc1[q];
+        double* sv = k.coef + (int64_t)mem * kSlots;
+        for (int q = tid; q <= j; q += 64) sv[q] = ssv[q];
     }
-    sc[2] = nu > 0.0 ? 1.0 / nu : 0.0;
-    sc[3] = nu;
-    k.pending[mem] = 1;
 }
 
 __global__ void k_cycle_start(KrylovDev k, int restart, const double* beta0sq, int nmem) {
@@ -1266,7 +1312,8 @@ void launch_dcgs_update(double* V, int64_t vstride, int nv, const double* w, int
 }
 
 void launch_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem, hipStream_t st) {
-    hipLaunchKernelGGL(k_dcgs_finish, dim3((nmem + 63) / 64), dim3(64), 0, st, k, restart, j, mode, nmem);
+    if (restart > 31) throw Error(SG_ERR_INVALID, "dcgs: restart above 31");
+    hipLaunchKernelGGL(k_dcgs_finish, dim3(nmem), dim3(64), 0, st, k, restart, j, mode, nmem);
     SG_HIP(hipGetLastError());
 }
 
