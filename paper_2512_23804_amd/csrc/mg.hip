@@ -25,6 +25,54 @@ __device__ __forceinline__ T st9(const T* s, int W, int i, T wc, T we, T wd) {
            wd * (s[i - W - 1] + s[i - W + 1] + s[i + W - 1] + s[i + W + 1]);
 }
 
+__device__ __forceinline__ bool interior(int X, int Y, int m) { return X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1; }
+
+// Thread -> node mapping of a W x W region in LDS for NT threads: each thread
+// owns K vertically consecutive nodes of one column (segment), K chosen so
+// that the segments cover the region with at most NT threads.  A 9-point
+// stencil over a segment keeps a sliding 3 x 3 window in registers: (K+2)*3
+// LDS reads for K nodes instead of 9K.
+template <int W, int NT>
+struct Seg {
+    static constexpr int SPC = NT / W < 1 ? 1 : NT / W;    // segments per column
+    static constexpr int K = (W + SPC - 1) / SPC;          // nodes per segment
+    static constexpr int NS = W * ((W + K - 1) / K);       // segments in use
+    int X, Y0;
+    bool on;
+    __device__ __forceinline__ Seg() {
+        const int t = threadIdx.x;
+        X = t % W;
+        Y0 = (t / W) * K;
+        on = t < NS;
+    }
+    __device__ __forceinline__ bool has(int k) const { return on && Y0 + k < W; }
+    __device__ __forceinline__ int q(int k) const { return (Y0 + k) * W + X; }
+};
+
+// out[k] = (A x)(X, Y0 + k), same summation order as st9; rows and columns
+// outside the region are clamped (their results are not used).
+template <typename T, int W, int K>
+__device__ __forceinline__ void st9_seg(const T* s, int X, int Y0, T wc, T we, T wd, T (&out)[K]) {
+    const int xl = X > 0 ? X - 1 : 0, xr = X < W - 1 ? X + 1 : W - 1;
+    auto row = [&](int y, T& l, T& c, T& r) {
+        const int yy = y < 0 ? 0 : (y > W - 1 ? W - 1 : y);
+        l = s[yy * W + xl];
+        c = s[yy * W + X];
+        r = s[yy * W + xr];
+    };
+    T l0, c0, r0, l1, c1, r1;
+    row(Y0 - 1, l0, c0, r0);
+    row(Y0, l1, c1, r1);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        T l2, c2, r2;
+        row(Y0 + k + 1, l2, c2, r2);
+        out[k] = wc * c1 + we * (l1 + r1 + c0 + c2) + wd * (l0 + r0 + l2 + r2);
+        l0 = l1; c0 = c1; r0 = r1;
+        l1 = l2; c1 = c2; r1 = r2;
+    }
+}
+
 // Pre-smoothing from a zero guess on a W x W region: x_1 = c_r D^{-1} b, then
 // NPRE-1 Chebyshev steps, step s updating [s, W-s).  The iterate is in LDS
 // (sx, read by the stencil); b, the step direction and the iterate of the
@@ -244,8 +292,11 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     // so that the first tile row and column also hold the ring at index 0
     constexpr int HR = H > 0 ? H : 1;
     constexpr int W = TF + 2 * HR;
-    constexpr int PPT = (W * W + NT - 1) / NT;
-    __shared__ T sc[W * W];           // x_k (read by the mass stencil); b, x_{k-1}, x_k own nodes in registers
+    using SG = Seg<W, NT>;
+    constexpr int K = SG::K;
+    __shared__ T sA[W * W];           // x_k (read by the mass stencil), two copies: one barrier per step
+    __shared__ T sB[W * W];
+    const SG g;
     const int l = blockIdx.y;
     const int vec = blockIdx.z;
     const int mem = op.mem_shared ? 0 : vec;
@@ -257,44 +308,41 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     const T h2_36 = h * h / T(36);
     const T dinv = T(1) / (T(1.25) * T(4) * h * h / T(9));
     const T* rc = r + (int64_t)vec * vstride + (int64_t)l * nodes;
-    T breg[PPT], xp[PPT], xc[PPT];
+    T breg[K], xp[K], xc[K];          // b, x_{k-1}, x_k of the thread's nodes
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const int q = threadIdx.x + NT * p;
-        const int X = FX0 + q % W, Y = FY0 + q / W;
-        const bool inter = q < W * W && X >= 1 && X <= n - 1 && Y >= 1 && Y <= n - 1;
-        breg[p] = inter ? rc[Y * N1 + X] : T(0);
-        xp[p] = T(0);                 // x_0
-        xc[p] = dinv * breg[p];       // x_1 (omega_1 = 1)
-        if (q < W * W) sc[q] = xc[p];
+    for (int k = 0; k < K; ++k) {
+        const int X = FX0 + g.X, Y = FY0 + g.Y0 + k;
+        breg[k] = g.has(k) && interior(X, Y, n) ? rc[Y * N1 + X] : T(0);
+        xp[k] = T(0);                 // x_0
+        xc[k] = dinv * breg[k];       // x_1 (omega_1 = 1)
+        if (g.has(k)) sA[g.q(k)] = xc[k];
     }
     __syncthreads();
+    T* cur = sA;
+    T* nxt = sB;
 #pragma unroll 1
-    for (int k = 1; k <= H; ++k) {
-        const T om = T(cw.omega[k - 1]);
-        const int lo = k, hi = W - k;
+    for (int s = 1; s <= H; ++s) {
+        const T om = T(cw.omega[s - 1]);
+        const int lo = s, hi = W - s;
+        T mx[K];
+        // mass stencil (h^2/36) [1 4 1; 4 16 4; 1 4 1]
+        st9_seg<T, W, K>(cur, g.X, g.Y0, T(16), T(4), T(1), mx);
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-            const int q = threadIdx.x + NT * p;
-            const int i = q % W, j = q / W;
-            const int X = FX0 + i, Y = FY0 + j;
-            if (q < W * W && i >= lo && i < hi && j >= lo && j < hi && X >= 1 && X <= n - 1 && Y >= 1 &&
-                Y <= n - 1) {
-                const T Mx = h2_36 * (T(16) * sc[q] + T(4) * (sc[q - 1] + sc[q + 1] + sc[q - W] + sc[q + W]) +
-                                      (sc[q - W - 1] + sc[q - W + 1] + sc[q + W - 1] + sc[q + W + 1]));
-                const T v = om * (dinv * (breg[p] - Mx) + xc[p] - xp[p]) + xp[p];
-                xp[p] = xc[p];
-                xc[p] = v;
+        for (int k = 0; k < K; ++k) {
+            const int i = g.X, j = g.Y0 + k;
+            if (g.has(k) && i >= lo && i < hi && j >= lo && j < hi && interior(FX0 + i, FY0 + j, n)) {
+                const T Mx = h2_36 * mx[k];
+                const T v = om * (dinv * (breg[k] - Mx) + xc[k] - xp[k]) + xp[k];
+                xp[k] = xc[k];
+                xc[k] = v;
             }
+            if (s < H && g.has(k)) nxt[g.q(k)] = xc[k];
         }
-        if (k < H) {
+        if (s < H) {
             __syncthreads();
-#pragma unroll
-            for (int p = 0; p < PPT; ++p) {
-                const int q = threadIdx.x + NT * p;
-                if (q < W * W) sc[q] = xc[p];
-            }
-            __syncthreads();
+            T* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
         }
     }
     const MemberDev md = op.mem[mem];
@@ -306,58 +354,11 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     const T f = T(1) / (sc_ * T(md.tau) * Dt);
     T* zc = z + (int64_t)vec * vstride + (int64_t)l * nodes;
 #pragma unroll
-    for (int p = 0; p < PPT; ++p) {
-        const int q = threadIdx.x + NT * p;
-        const int X = FX0 + q % W, Y = FY0 + q / W;
-        if (q < W * W && X >= FX0 + HR - ex && X < FX0 + HR + TF && Y >= FY0 + HR - ey && Y < FY0 + HR + TF &&
-            X <= n && Y <= n)
-            zc[Y * N1 + X] = f * xc[p];
-    }
-}
-
-// Thread -> node mapping of a W x W region in LDS for NT threads: each thread
-// owns K vertically consecutive nodes of one column (segment), K chosen so
-// that the segments cover the region with at most NT threads.  A 9-point
-// stencil over a segment keeps a sliding 3 x 3 window in registers: (K+2)*3
-// LDS reads for K nodes instead of 9K.
-template <int W, int NT>
-struct Seg {
-    static constexpr int SPC = NT / W < 1 ? 1 : NT / W;    // segments per column
-    static constexpr int K = (W + SPC - 1) / SPC;          // nodes per segment
-    static constexpr int NS = W * ((W + K - 1) / K);       // segments in use
-    int X, Y0;
-    bool on;
-    __device__ __forceinline__ Seg() {
-        const int t = threadIdx.x;
-        X = t % W;
-        Y0 = (t / W) * K;
-        on = t < NS;
-    }
-    __device__ __forceinline__ bool has(int k) const { return on && Y0 + k < W; }
-    __device__ __forceinline__ int q(int k) const { return (Y0 + k) * W + X; }
-};
-
-// out[k] = (A x)(X, Y0 + k), same summation order as st9; rows and columns
-// outside the region are clamped (their results are not used).
-template <typename T, int W, int K>
-__device__ __forceinline__ void st9_seg(const T* s, int X, int Y0, T wc, T we, T wd, T (&out)[K]) {
-    const int xl = X > 0 ? X - 1 : 0, xr = X < W - 1 ? X + 1 : W - 1;
-    auto row = [&](int y, T& l, T& c, T& r) {
-        const int yy = y < 0 ? 0 : (y > W - 1 ? W - 1 : y);
-        l = s[yy * W + xl];
-        c = s[yy * W + X];
-        r = s[yy * W + xr];
-    };
-    T l0, c0, r0, l1, c1, r1;
-    row(Y0 - 1, l0, c0, r0);
-    row(Y0, l1, c1, r1);
-#pragma unroll
     for (int k = 0; k < K; ++k) {
-        T l2, c2, r2;
-        row(Y0 + k + 1, l2, c2, r2);
-        out[k] = wc * c1 + we * (l1 + r1 + c0 + c2) + wd * (l0 + r0 + l2 + r2);
-        l0 = l1; c0 = c1; r0 = r1;
-        l1 = l2; c1 = c2; r1 = r2;
+        const int X = FX0 + g.X, Y = FY0 + g.Y0 + k;
+        if (g.has(k) && X >= FX0 + HR - ex && X < FX0 + HR + TF && Y >= FY0 + HR - ey && Y < FY0 + HR + TF &&
+            X <= n && Y <= n)
+            zc[Y * N1 + X] = f * xc[k];
     }
 }
 
@@ -393,8 +394,6 @@ struct TailLds {
     T x[total];
     T r[W0 * W0];
 };
-
-__device__ __forceinline__ bool interior(int X, int Y, int m) { return X >= 1 && X <= m - 1 && Y >= 1 && Y <= m - 1; }
 
 // One Chebyshev step from buffer `in` to buffer `out` (ping-pong: a single
 // barrier per step): d = c_d d + c_r D^{-1} (b - A x), x += d on interior nodes.
