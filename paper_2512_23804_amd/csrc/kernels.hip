@@ -321,33 +321,62 @@ __global__ __launch_bounds__(256) void k_mass_cheb_step(int n, int nxi, int nt, 
     }
 }
 
-// W = tau D_t (1 or hg) M V on the columns of a field block (Schur block middle factor).
+// W = tau D_t (1 or hg) M V on the columns of a field block (Schur block middle
+// factor).  A wavefront owns one column; each of its 32-lane halves computes
+// kMassRows node rows of a 30-node-wide tile (lanes 0 and 31 are halos): every
+// node value is loaded once per strip (plus two halo rows) and its x
+// neighbours come from one left and one right lane shuffle per row.  Values on
+// the boundary ring read as zero.
+constexpr int kMassRows = 8;
 template <typename T>
-__global__ __launch_bounds__(256) void k_mass_scaled(int n, int nxi, int nt, int time, int64_t nodes, OpDev op,
-                                                     const T* __restrict__ V, ColMap vmap, T* __restrict__ W,
-                                                     ColMap wmap, int ncols) {
-    int ix, iy;
-    tile_coords(n, blockIdx.x, ix, iy);
-    if (ix > n || iy > n) return;
-    const int64_t p = (int64_t)iy * (n + 1) + ix;
-    const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
+__global__ __launch_bounds__(256) void k_mass_scaled(int n, int nt, int time, OpDev op, const T* __restrict__ V,
+                                                     ColMap vmap, T* __restrict__ W, ColMap wmap, int ncols,
+                                                     int tiles_x) {
+    constexpr int R = kMassRows;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = blockIdx.y * 4 + wave;
+    if (c >= ncols) return;                          // uniform per wavefront; no barriers below
+    const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & 31, grp = lane >> 5;
+    const int X = tx * 30 + gl - 1;
+    const int y0 = (ty * 2 + grp) * R;               // output rows y0 .. y0+R-1
+    const int N1 = n + 1;
+    const int xc = min(max(X, 0), n);
+    const bool xin = X >= 1 && X <= n - 1;
+    const T* v = V + vmap.off(c);
+    T rc[R + 2], rl[R + 2], rr[R + 2];
+#pragma unroll
+    for (int k = 0; k < R + 2; ++k) {
+        const int Y = y0 - 1 + k;
+        const T val = v[(int64_t)min(max(Y, 0), n) * N1 + xc];
+        rc[k] = (xin && Y >= 1 && Y <= n - 1) ? val : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < R + 2; ++k) {
+        rl[k] = __shfl_up(rc[k], 1, 32);
+        rr[k] = __shfl_down(rc[k], 1, 32);
+    }
+    const int mem_i = vmap.member(c);
+    const int mem = op.mem_shared ? 0 : mem_i;
+    const MemberDev md = op.mem[mem];
+    const int t = vmap.tstep(c);
+    const int j = vmap.chaos(c);
+    const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
+    const T sc = T(md.tau) * Dt * (j == 0 ? T(1) : T(md.hg));
     const T h = T(1) / T(n);
     const T h2_36 = h * h / T(36);
-    const int c0 = blockIdx.y * kJChunk;
-    const int c1 = min(ncols, c0 + kJChunk);
-    for (int c = c0; c < c1; ++c) {
-        const int mem_i = vmap.member(c);
-        const int mem = op.mem_shared ? 0 : mem_i;
-        const MemberDev md = op.mem[mem];
-        const int t = vmap.tstep(c);
-        const int j = vmap.chaos(c);
-        T v = T(0);
-        if (interior) {
-            const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
-            const T s = T(md.tau) * Dt * (j == 0 ? T(1) : T(md.hg));
-            v = s * mass9(load9(V + vmap.off(c), n, ix, iy), h2_36);
+    T* w = W + wmap.off(c);
+    const bool xout = gl >= 1 && gl <= 30 && X <= n;
+#pragma unroll
+    for (int k = 1; k <= R; ++k) {
+        const int Y = y0 - 1 + k;
+        if (xout && Y <= n) {
+            const bool inter = xin && Y >= 1 && Y <= n - 1;
+            const T m9 = h2_36 * (T(16) * rc[k] + T(4) * (rl[k] + rr[k] + rc[k - 1] + rc[k + 1]) +
+                                  (rl[k - 1] + rr[k - 1] + rl[k + 1] + rr[k + 1]));
+            w[(int64_t)Y * N1 + X] = inter ? sc * m9 : T(0);
         }
-        W[wmap.off(c) + p] = v;
     }
 }
 
@@ -865,9 +894,19 @@ __global__ void k_multi_axpy(const TZ* __restrict__ Z, int64_t zstride, int nv_m
     const double* ym = y + mem * ystride;
     double* xm = x + mem * mstride;
     const TZ* Zm = Z + mem * mstride;
+    const int nvv = nv < nv_max ? nv : nv_max;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         double s = xm[e];
-        for (int i = 0; i < nv && i < nv_max; ++i) s += ym[i] * (double)Zm[i * zstride + e];
+        // loads eight vectors ahead of the (in-order) accumulation
+        int i = 0;
+        for (; i + 8 <= nvv; i += 8) {
+            double z[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) z[u] = (double)Zm[(int64_t)(i + u) * zstride + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += ym[i + u] * z[u];
+        }
+        for (; i < nvv; ++i) s += ym[i] * (double)Zm[(int64_t)i * zstride + e];
         xm[e] = s;
     }
 }
@@ -1208,9 +1247,11 @@ void launch_mass_cheb(const Shape& s, const OpDev& op, const T* r, T* z, T* bufA
 template <typename T>
 void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap, T* W, ColMap wmap, int ncols,
                         int, hipStream_t st) {
-    dim3 g = tile_grid(s.n, (ncols + kJChunk - 1) / kJChunk, 1);
-    hipLaunchKernelGGL(k_mass_scaled<T>, g, dim3(256), 0, st, s.n, s.nxi, s.nt, (int)s.time, s.nodes, op, V, vmap, W,
-                       wmap, ncols);
+    const int tiles_x = (s.n + 1 + 29) / 30, tiles_y = (s.n + 1 + 2 * kMassRows - 1) / (2 * kMassRows);
+    const int chunks = (ncols + 3) / 4;
+    if (chunks > 65535) throw Error(SG_ERR_INVALID, "mass apply: too many columns in one launch");
+    hipLaunchKernelGGL(k_mass_scaled<T>, dim3(tiles_x * tiles_y, chunks), dim3(256), 0, st, s.n, s.nt, (int)s.time,
+                       op, V, vmap, W, wmap, ncols, tiles_x);
     SG_HIP(hipGetLastError());
 }
 
