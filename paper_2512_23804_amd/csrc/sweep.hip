@@ -209,9 +209,30 @@ struct Sweep {
         if (t.ib >= 0) load_col(vals, F + (int64_t)t.ib * nodes, st, t.gb, t.ia >= 0);
     }
 
+    // Coefficients of term k on the strip's element rows (mean: c0; staged
+    // tile in LDS when sc is set, else the coefficient planes), zero off the grid.
+    template <typename T>
+    static __device__ __forceinline__ void load_coef(T (&c)[RS + 1], int k, const Strip& st, T c0,
+                                                     const T* __restrict__ sc, int grp, int gl,
+                                                     const T* __restrict__ coef, int64_t cplane) {
+        if (k < 0) {
+    #pragma unroll
+            for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? c0 : T(0);
+        } else if (sc) {
+            const T* ck = sc + (k * ER + grp * RS) * GW + gl;    // staged, zero off the grid
+    #pragma unroll
+            for (int r = 0; r < RS + 1; ++r) c[r] = ck[r * GW];
+        } else {
+            const T* ck = coef + (int64_t)(k + 1) * cplane;
+    #pragma unroll
+            for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? ck[st.eoff(r)] : T(0);
+        }
+    }
+
     // Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
     // field F at output column j.  The loads of the next term are issued before
-    // the current term is accumulated (two terms in flight per wavefront).
+    // the current term is accumulated (two terms in flight per wavefront; a
+    // deeper lookahead measured slower: it costs occupancy or spills).
     template <typename T>
     static __device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
                                              int j, int M, const int32_t* __restrict__ nidx,
@@ -229,18 +250,7 @@ struct Sweep {
             const int kn = next_term(k + 1, j, M, nidx, nval, mask, lower, upper, nxt);
             const bool more = kn < M;
             if (more) load_term(nvals, nxt, F, nodes, st);
-            if (k < 0) {
-    #pragma unroll
-                for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? c0 : T(0);
-            } else if (sc) {
-                const T* ck = sc + (k * ER + grp * RS) * GW + gl;    // staged, zero off the grid
-    #pragma unroll
-                for (int r = 0; r < RS + 1; ++r) c[r] = ck[r * GW];
-            } else {
-                const T* ck = coef + (int64_t)(k + 1) * cplane;
-    #pragma unroll
-                for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? ck[st.eoff(r)] : T(0);
-            }
+            load_coef(c, k, st, c0, sc, grp, gl, coef, cplane);
             corner_accumulate(v, vals, c);
             if (!more) break;
     #pragma unroll
