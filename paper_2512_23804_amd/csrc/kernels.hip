@@ -625,8 +625,9 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
 }
 
 // ---- Arnoldi with delayed reorthogonalization (DCGS2) ----
-// Slot j of the basis holds the candidate u (one Gram-Schmidt pass, scaled by
-// an estimate of its norm) until the next iteration finalises it.
+// Slot j of the basis holds the candidate u_j (one Gram-Schmidt pass, scaled
+// by an estimate of its norm) and is never rewritten: the orthonormal basis is
+// V = U R^{-1}, applied through R by the bookkeeping kernel (k_dcgs_finish).
 //
 #ifndef SG_DOTS_U
 #define SG_DOTS_U 4
