@@ -84,7 +84,9 @@ def make_problems(sgl, sg_inputs, wl):
     return probs
 
 
-def timed_solves(torch, sgl, probs, opts, steps, warmup, stream, tuned=None):
+def timed_solves(torch, sgl, probs, opts, steps, warmup, stream, tuned=None, keep=None):
+    """Time `steps` batched solves after `warmup` untimed ones; with `keep`,
+    append the last solution (device tensor, members x KKT length)."""
     h = sgl.Handle(probs, opts, stream=stream)
     if tuned is not None:
         tuned.extend([list(r) for r in h.sizes.sweep_rows])
@@ -99,8 +101,15 @@ def timed_solves(torch, sgl, probs, opts, steps, warmup, stream, tuned=None):
         infos.append(info)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if keep is not None:
+        keep.append(x.view(h.members, h.kkt_elems).clone())
     h.close()
     return dt, infos
+
+
+def max_rel_diff(a, b):
+    """max over members of ||a - b||_inf / ||b||_inf"""
+    return max(float((a[i] - b[i]).abs().max() / b[i].abs().max()) for i in range(b.shape[0]))
 
 
 def sg_apply_bandwidth(torch, sgl, probs, stream, min_bytes=1 << 30, reps=20):
@@ -254,7 +263,8 @@ def main():
     arn = ARNOLDI[args.arnoldi]
     opts = sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn, sweep_rows=args.sweep_rows)
     tuned = []
-    dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream, tuned)
+    x64 = []
+    dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream, tuned, keep=x64)
     nsolve = len(probs) * args.steps
     value = nsolve / dt
     iters = [i.iters for step in infos for i in step]
@@ -305,16 +315,21 @@ def main():
     if not args.no_extras:
         o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE, use_graphs=graphs,
                                   arnoldi=arn, sweep_rows=args.sweep_rows)
-        dt32, inf32 = timed_solves(torch, sgl, probs, o32, args.steps, 1, stream)
+        x32 = []
+        dt32, inf32 = timed_solves(torch, sgl, probs, o32, args.steps, 1, stream, keep=x32)
         out["fp32_refine"] = {"value": nsolve / dt32, "unit": "solves/s", "dtype": "f32 operator/preconditioner, "
                               "f64 Arnoldi and refinement", "iterations": [i.iters for i in inf32[0]],
-                              "max_rel_res": max(i.rel_res_true for st in inf32 for i in st)}
+                              "max_rel_res": max(i.rel_res_true for st in inf32 for i in st),
+                              "max_rel_diff_vs_fp64": max_rel_diff(x32[0], x64[0])}
         opc = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_PRECOND, use_graphs=graphs, arnoldi=arn,
                                   sweep_rows=args.sweep_rows)
-        dtp, infp = timed_solves(torch, sgl, probs, opc, args.steps, 1, stream)
+        xpc = []
+        dtp, infp = timed_solves(torch, sgl, probs, opc, args.steps, 1, stream, keep=xpc)
         out["fp32_precond"] = {"value": nsolve / dtp, "unit": "solves/s", "dtype": "f32 preconditioner, "
                                "f64 operator, Arnoldi and restarts", "iterations": [i.iters for i in infp[0]],
-                               "max_rel_res": max(i.rel_res_true for st in infp for i in st)}
+                               "max_rel_res": max(i.rel_res_true for st in infp for i in st),
+                               "max_rel_diff_vs_fp64": max_rel_diff(xpc[0], x64[0])}
+        del x32, xpc
         single = []
         t_single = 0.0
         for p in probs:

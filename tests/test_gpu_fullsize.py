@@ -77,12 +77,16 @@ def test_fullsize_applies(name):
             assert err < (1e-12 if dt == torch.float64 else 1e-5), (name, i, what, dt, err)
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp64", "fp32_refine", "fp32_precond"])
 @pytest.mark.parametrize("name", sorted(bench.WORKLOADS))
-def test_fullsize_solve_true_residual(name):
+def test_fullsize_solve_true_residual(name, precision):
+    """Each member's GPU solution at the benchmark size, in every precision
+    mode: the oracle's FP64 residual ||b - K x|| / ||b|| <= 1e-8 and within 1%
+    of the residual the solver reports."""
     _need_gpu()
-    _say(f"full-size solve {name}")
+    _say(f"full-size solve {name} precision={precision}")
     cases = _members(name)
-    h = _handle(cases, rtol=1e-8)
+    h = _handle(cases, rtol=1e-8, precision=precision)
     x = torch.zeros(h.members * h.kkt_elems, dtype=torch.float64, device="cuda")
     rc, infos = h.solve(x)
     torch.cuda.synchronize()
