@@ -71,8 +71,10 @@ struct SweepGeom {
 };
 
 // Occupancy hints per strip height (registers grow with the rows per strip).
-constexpr int sweep_waves(int rs, int bytes) { return rs <= 2 ? 6 : rs <= 4 ? 4 : bytes == 8 ? 2 : 3; }
-constexpr int kkt_waves(int rs, int bytes) { return rs <= 2 ? 5 : rs <= 4 ? 3 : 2; }
+constexpr int sweep_waves(int rs, int bytes, bool two) {
+    return two ? (rs <= 2 ? 5 : rs <= 4 ? 3 : 2) : (rs <= 2 ? 6 : rs <= 4 ? 4 : bytes == 8 ? 2 : 3);
+}
+constexpr int kkt_waves(int rs, int bytes) { return rs <= 2 ? 4 : rs <= 4 ? 3 : 2; }
 
 // Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
 // field F at output column j: c0 X_j (mean, if with_mean) plus, for every mode
@@ -104,7 +106,12 @@ __device__ __forceinline__ bool term_at(int k, int j, int M, const int32_t* __re
     t.ib = upper ? nidx[base + 1] : -1;
     t.ga = T(nval[base]);
     t.gb = T(nval[base + 1]);
-    return t.ia >= 0 || t.ib >= 0;
+    if (t.ia < 0) {             // a term with one input column keeps it in the first slot
+        t.ia = t.ib;
+        t.ga = t.gb;
+        t.ib = -1;
+    }
+    return t.ia >= 0;
 }
 
 template <typename T>
@@ -202,43 +209,168 @@ struct Sweep {
         }
     }
 
-    template <typename T>
-    static __device__ __forceinline__ void load_term(T (&vals)[RS + 2], const Term<T>& t, const T* __restrict__ F, int64_t nodes,
-                                              const Strip& st) {
-        if (t.ia >= 0) load_col(vals, F + (int64_t)t.ia * nodes, st, t.ga, false);
-        if (t.ib >= 0) load_col(vals, F + (int64_t)t.ib * nodes, st, t.gb, t.ia >= 0);
-    }
-
     // Coefficients of term k on the strip's element rows (mean: c0; staged
-    // tile in LDS when sc is set, else the coefficient planes), zero off the grid.
+    // tile in LDS when sc is set, else the coefficient planes), zero off the
+    // grid.  The global path always loads (the mean term reads plane 0 and
+    // discards it), so the number of loads in flight is the same for every
+    // term.
     template <typename T>
     static __device__ __forceinline__ void load_coef(T (&c)[RS + 1], int k, const Strip& st, T c0,
                                                      const T* __restrict__ sc, int grp, int gl,
                                                      const T* __restrict__ coef, int64_t cplane) {
-        if (k < 0) {
+        if (sc) {
+            if (k < 0) {
     #pragma unroll
-            for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? c0 : T(0);
-        } else if (sc) {
-            const T* ck = sc + (k * ER + grp * RS) * GW + gl;    // staged, zero off the grid
+                for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? c0 : T(0);
+            } else {
+                const T* ck = sc + (k * ER + grp * RS) * GW + gl;    // staged, zero off the grid
     #pragma unroll
-            for (int r = 0; r < RS + 1; ++r) c[r] = ck[r * GW];
+                for (int r = 0; r < RS + 1; ++r) c[r] = ck[r * GW];
+            }
         } else {
+            // masks applied by multiplication (a select would let the compiler
+            // branch around the load, and the branch join waits for every load)
             const T* ck = coef + (int64_t)(k + 1) * cplane;
+            const T sm = k < 0 ? T(0) : T(1), sk = k < 0 ? T(1) : T(0);
     #pragma unroll
-            for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? ck[st.eoff(r)] : T(0);
+            for (int r = 0; r < RS + 1; ++r) {
+                const T cv = ck[st.eoff(r)];
+                const T mf = ((st.emask >> r) & 1u) ? T(1) : T(0);
+                c[r] = (cv * sm + c0 * sk) * mf;
+            }
+        }
+    }
+
+    // Raw node values of a term's lower and upper input columns at the strip's
+    // RS+2 rows.  They are combined (masked, scaled, then summed)
+    // only when the term is accumulated, so that loads issued for the next term
+    // stay in flight while the current term is computed.
+    template <typename T>
+    struct Raw {
+        T a[RS + 2], b[RS + 2];
+    };
+    // TWO: terms may have two input columns (the second is then always loaded,
+    // from the first column when absent, and selected away); without TWO every
+    // term has exactly one.  Either way the loads per term are a fixed count.
+    template <bool TWO, typename T>
+    static __device__ __forceinline__ void load_raw(Raw<T>& R, const Term<T>& t, const T* __restrict__ F,
+                                                    int64_t nodes, const Strip& st) {
+        const T* ca = F + (int64_t)t.ia * nodes;       // every term has its first column
+    #pragma unroll
+        for (int r = 0; r < RS + 2; ++r) R.a[r] = ca[st.noff(r)];
+        if (TWO) {
+            const T* cb = F + (int64_t)(t.ib >= 0 ? t.ib : t.ia) * nodes;
+    #pragma unroll
+            for (int r = 0; r < RS + 2; ++r) R.b[r] = cb[st.noff(r)];
+        }
+    }
+    // value of the term at strip row r (masked, scaled, then summed)
+    template <bool TWO, typename T>
+    static __device__ __forceinline__ T combine_row(const Raw<T>& R, const Term<T>& t, const Strip& st, int r) {
+        const bool in = (st.nmask >> r) & 1u;
+        T val = t.ga * (in ? R.a[r] : T(0));
+        if (TWO) {
+            const T v2 = fmadd(t.gb, in ? R.b[r] : T(0), val);
+            val = t.ib >= 0 ? v2 : val;
+        }
+        return val;
+    }
+    // corner_accumulate of one term, its row values combined on the fly
+    template <bool TWO, typename T>
+    static __device__ __forceinline__ void accumulate_term(T (&v)[RS + 1][4], const Raw<T>& R, const Term<T>& t,
+                                                           const Strip& st, const T (&c)[RS + 1]) {
+        T prev = combine_row<TWO>(R, t, st, 0);
+        T prevR = shdn(prev);
+    #pragma unroll
+        for (int r = 0; r < RS + 1; ++r) {
+            const T top = combine_row<TWO>(R, t, st, r + 1);
+            const T topR = shdn(top);
+            v[r][0] = fmadd(c[r], prev, v[r][0]);
+            v[r][1] = fmadd(c[r], prevR, v[r][1]);
+            v[r][2] = fmadd(c[r], topR, v[r][2]);
+            v[r][3] = fmadd(c[r], top, v[r][3]);
+            prev = top;
+            prevR = topR;
         }
     }
 
     // Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
-    // field F at output column j.  The loads of the next term are issued before
-    // the current term is accumulated (two terms in flight per wavefront; a
-    // deeper lookahead measured slower: it costs occupancy or spills).
-    template <typename T>
+    // field F at output column j.  Two buffers alternate between the terms: the
+    // next term's node values are loaded into one while the current term, in
+    // the other, is accumulated; the current term's coefficients are loaded
+    // before the next term's values (loads complete in order), so the wait for
+    // them leaves the next term's loads in flight.  The per-node arithmetic is
+    // the same for every strip height.
+    template <bool TWO, typename T>
     static __device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
                                              int j, int M, const int32_t* __restrict__ nidx,
                                              const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
                                              bool with_mean, T c0, const T* __restrict__ sc, int grp, int gl,
                                              const T* __restrict__ coef, int64_t cplane) {
+        T c[RS + 1];
+        Raw<T> RA, RB;                                 // current and next term's raw node values
+        Term<T> tA, tB;
+        // the present modes as a bit set (one scalar pass before any vector
+        // load), so that no loop separates a term's loads from their use
+        uint32_t todo = 0;
+        for (int k = 0; k < M; ++k) {
+            Term<T> t;
+            if (term_at(k, j, M, nidx, nval, mask, lower, upper, t)) todo |= 1u << k;
+        }
+        auto pop = [&](Term<T>& t) -> int {
+            if (!todo) return M;
+            const int k = __builtin_ctz(todo);
+            todo &= todo - 1u;
+            term_at(k, j, M, nidx, nval, mask, lower, upper, t);
+            return k;
+        };
+        int kA = M;
+        if (with_mean) {
+            kA = -1;
+            term_at(-1, j, M, nidx, nval, mask, lower, upper, tA);
+        } else {
+            kA = pop(tA);
+        }
+        if (kA >= M) return;
+        load_raw<TWO>(RA, tA, F, nodes, st);
+        // each iteration decides whether a next term exists before issuing any
+        // load, so its loads and arithmetic are straight-line code; the copy of
+        // the next term's raw values comes after the current term's arithmetic
+    #pragma unroll 1
+        while (true) {
+            const int kB = pop(tB);
+            if (kB >= M) break;                        // A is the last term
+            load_coef(c, kA, st, c0, sc, grp, gl, coef, cplane);
+            load_raw<TWO>(RB, tB, F, nodes, st);
+            __builtin_amdgcn_sched_barrier(0);         // keep those loads ahead of the arithmetic
+            accumulate_term<TWO>(v, RA, tA, st, c);
+            __builtin_amdgcn_sched_barrier(0);
+            RA = RB;
+            tA = tB;
+            kA = kB;
+        }
+        load_coef(c, kA, st, c0, sc, grp, gl, coef, cplane);
+        accumulate_term<TWO>(v, RA, tA, st, c);
+    }
+
+    // The same sums without load pipelining: each term's node values are
+    // combined as they arrive (the next term's loads are issued before the
+    // current term is accumulated, but the compiler waits for them within the
+    // iteration).  Lighter on registers; used by the standalone SG apply, where
+    // it measured faster than the pipelined strip at the occupancy it allows.
+    template <typename T>
+    static __device__ __forceinline__ void load_term(T (&vals)[RS + 2], const Term<T>& t, const T* __restrict__ F,
+                                                     int64_t nodes, const Strip& st) {
+        load_col(vals, F + (int64_t)t.ia * nodes, st, t.ga, false);
+        if (t.ib >= 0) load_col(vals, F + (int64_t)t.ib * nodes, st, t.gb, true);
+    }
+    template <typename T>
+    static __device__ __forceinline__ void sg_strip_direct(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F,
+                                                           int64_t nodes, int j, int M, const int32_t* __restrict__ nidx,
+                                                           const double* __restrict__ nval, uint32_t mask, bool lower,
+                                                           bool upper, bool with_mean, T c0, const T* __restrict__ sc,
+                                                           int grp, int gl, const T* __restrict__ coef,
+                                                           int64_t cplane) {
         T vals[RS + 2], nvals[RS + 2];
         T c[RS + 1];
         Term<T> cur, nxt;
@@ -331,8 +463,8 @@ struct Sweep {
 // KIND 0: Y = A X (all modes, mean included) for nt*nvec slices.
 // KIND 1: hGS right-hand side of degree level d:
 //         out_j = base_j - off_scale * sum_{k in mask} K_k (g- V_{j-e_k} [lower] + g+ V_{j+e_k} [upper]).
-template <typename T, int KIND, int RS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves(RS, sizeof(T))))) void k_sgx(int n, int M, int nxi, int nt, int64_t nodes, OpDev op, SweepGeom g,
+template <typename T, int KIND, int RS, bool TWO>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves(RS, sizeof(T), TWO)))) void k_sgx(int n, int M, int nxi, int nt, int64_t nodes, OpDev op, SweepGeom g,
                                              const T* __restrict__ x, T* __restrict__ y, int j0lvl, int L,
                                              uint32_t mask, int lower, int upper, const T* __restrict__ base,
                                              ColMap bmap, ColMap vmap, ColMap omap) {
@@ -366,9 +498,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
     T v[RS + 1][4];
 #pragma unroll
     for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
-    S::sg_strip(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, KIND == 0 ? 0xffffffffu : mask,
-             KIND == 0 ? true : lower != 0, KIND == 0 ? true : upper != 0, KIND == 0, T(op.mem[mem].c0),
-             (const T*)nullptr, grp, gl, (const T*)op.coef + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
+    if constexpr (KIND == 0)
+        S::sg_strip_direct(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true,
+                           T(op.mem[mem].c0), (const T*)nullptr, grp, gl,
+                           (const T*)op.coef + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
+    else
+        S::template sg_strip<TWO>(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, mask, lower != 0, upper != 0, false,
+                                  T(op.mem[mem].c0), (const T*)nullptr, grp, gl,
+                                  (const T*)op.coef + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
     T* out;
     const T* bas = nullptr;
     T scale = T(1);
@@ -464,7 +601,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     T vals[RS + 2];
     // R^Y
     S::zero_strip(v);
-    S::sg_strip(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc, grp, gl,
+    S::template sg_strip<true>(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc,
+                               grp, gl,
                 (const T*)nullptr, 0);
     S::stiff_to_element(v, tau);
     S::load_col(vals, Yt + cj, st, tau * Dt * hgj, false);
@@ -476,7 +614,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     S::emit_nodes(v, st, gl, X, n, RY);
     // R^L
     S::zero_strip(v);
-    S::sg_strip(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc, grp, gl,
+    S::template sg_strip<true>(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc,
+                               grp, gl,
                 (const T*)nullptr, 0);
     S::stiff_to_element(v, tau);
     S::load_col(vals, Ut + cj, st, tau, false);
@@ -524,8 +663,8 @@ bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nve
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_APPLY];
     const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
-    SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 0, R>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt,
-                                              s.nodes, op, g, x, y, 0, 0, 0u, 1, 1, (const T*)nullptr, z, z, z));
+    SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 0, R, false>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi,
+                                              s.nt, s.nodes, op, g, x, y, 0, 0, 0u, 1, 1, (const T*)nullptr, z, z, z));
     SG_HIP(hipGetLastError());
     return true;
 }
@@ -555,9 +694,14 @@ bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, i
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_HGS];
     const SweepGeom g = make_geom(s.n, L, (int64_t)nmembers * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
-    SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 1, R>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt,
-                                              s.nodes, op, g, V, out, s.off[d], L, mask, use_lower, use_upper, base,
-                                              bmap, vmap, omap));
+    if (use_lower && use_upper)
+        SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 1, R, true>), dim3(grid), dim3(256), 0, st, s.n, s.M,
+                                                  s.nxi, s.nt, s.nodes, op, g, V, out, s.off[d], L, mask, use_lower,
+                                                  use_upper, base, bmap, vmap, omap));
+    else
+        SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 1, R, false>), dim3(grid), dim3(256), 0, st, s.n, s.M,
+                                                  s.nxi, s.nt, s.nodes, op, g, V, out, s.off[d], L, mask, use_lower,
+                                                  use_upper, base, bmap, vmap, omap));
     SG_HIP(hipGetLastError());
     return true;
 }
