@@ -309,10 +309,17 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     const T dinv = T(1) / (T(1.25) * T(4) * h * h / T(9));
     const T* rc = r + (int64_t)vec * vstride + (int64_t)l * nodes;
     T breg[K], xp[K], xc[K];          // b, x_{k-1}, x_k of the thread's nodes
+    // all loads first (clamped addresses, masked after), so that they are in
+    // flight together rather than one per LDS write
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int X = FX0 + g.X, Y = FY0 + g.Y0 + k;
-        breg[k] = g.has(k) && interior(X, Y, n) ? rc[Y * N1 + X] : T(0);
+        breg[k] = rc[min(max(Y, 0), n) * N1 + min(max(X, 0), n)];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int X = FX0 + g.X, Y = FY0 + g.Y0 + k;
+        breg[k] = g.has(k) && interior(X, Y, n) ? breg[k] : T(0);
         xp[k] = T(0);                 // x_0
         xc[k] = dinv * breg[k];       // x_1 (omega_1 = 1)
         if (g.has(k)) sA[g.q(k)] = xc[k];
@@ -541,19 +548,33 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __rest
     __shared__ T sA[CNU * CNU];             // interior block of the coarse inverse
     const int c = blockIdx.x;
     const int mem = c / cpm;
-    // issue every global read first: the column, the level parameters and the
-    // coarse inverse (consumed only after the down sweep)
+    // issue every global read first, into registers (clamped addresses): the
+    // column, the level parameters and the coarse inverse (consumed only after
+    // the down sweep); then mask and store them to LDS
     const T* bcol = b + bmap.off(c);
-    for (int q = threadIdx.x; q < W0 * W0; q += kTailThreads) {
-        const int X = q % W0, Y = q / W0;
-        s.b[q] = interior(X, Y, M0) ? bcol[q] : T(0);
-    }
+    constexpr int NB = (W0 * W0 + kTailThreads - 1) / kTailThreads;
+    constexpr int NA = (CNU * CNU + kTailThreads - 1) / kTailThreads;
     constexpr int LW = sizeof(LevelDev) / sizeof(double);
+    const T* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad;
+    T rb[NB], ra[NA];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) rb[i] = bcol[min((int)threadIdx.x + i * kTailThreads, W0 * W0 - 1)];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int q = min((int)threadIdx.x + i * kTailThreads, CNU * CNU - 1);
+        ra[i] = A[(q / CNU) * kCoarsePad + q % CNU];
+    }
     for (int q = threadIdx.x; q < (NL - 1) * LW; q += kTailThreads)
         ((double*)slev)[q] = ((const double*)(lev + mem * kMaxLevels + lvl0))[q];
-    {
-        const T* A = ainv + (int64_t)mem * kCoarsePad * kCoarsePad;
-        for (int q = threadIdx.x; q < CNU * CNU; q += kTailThreads) sA[q] = A[(q / CNU) * kCoarsePad + q % CNU];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int q = threadIdx.x + i * kTailThreads;
+        if (q < W0 * W0) s.b[q] = interior(q % W0, q / W0, M0) ? rb[i] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int q = threadIdx.x + i * kTailThreads;
+        if (q < CNU * CNU) sA[q] = ra[i];
     }
     __syncthreads();
     tail_down<T, M0, M0>(s, slev, npre);
