@@ -346,11 +346,14 @@ __global__ __launch_bounds__(256) void k_mass_scaled(int n, int nt, int time, Op
     const bool xin = X >= 1 && X <= n - 1;
     const T* v = V + vmap.off(c);
     T rc[R + 2], rl[R + 2], rr[R + 2];
+    // all row loads first, masked afterwards (a select next to each load lets
+    // the compiler branch around it and wait for every load in turn)
+#pragma unroll
+    for (int k = 0; k < R + 2; ++k) rc[k] = v[(int64_t)min(max(y0 - 1 + k, 0), n) * N1 + xc];
 #pragma unroll
     for (int k = 0; k < R + 2; ++k) {
         const int Y = y0 - 1 + k;
-        const T val = v[(int64_t)min(max(Y, 0), n) * N1 + xc];
-        rc[k] = (xin && Y >= 1 && Y <= n - 1) ? val : T(0);
+        rc[k] = (xin && Y >= 1 && Y <= n - 1) ? rc[k] : T(0);
     }
 #pragma unroll
     for (int k = 0; k < R + 2; ++k) {
