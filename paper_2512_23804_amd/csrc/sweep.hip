@@ -10,18 +10,19 @@
 //
 // Work mapping (64-wide wavefronts): a wavefront owns one output chaos column
 // j; its two 32-lane halves each walk a strip of RS node rows (2, 4 or 8,
-// chosen per shape by the autotuner) of a 30-column x-tile.  Lane l holds node column X = 30*tx + l - 1 (lanes 0 and 31 are
-// halos), loads each input value once per row, gets the x+1 neighbour by a
-// lane shuffle and keeps the previous row in registers, so every input value
-// is read about once per output column.  The node value is the sum of the
-// corner contributions of its four elements: two from its own lane (this and
-// the previous element row) and two from the lane to the left.
-// Blocks (4 wavefronts = 4 consecutive output columns of one spatial tile) are
-// numbered so that each XCD receives a contiguous range of tiles with all
-// their chaos columns: the neighbour columns a tile reads stay in that XCD's L2.
-// These kernels are bound by the vector-memory data path (each neighbour
-// column is loaded once per output column that needs it), not by L2 or HBM;
-// the KKT kernel therefore reads its coefficient tile from LDS.
+// chosen per shape by the autotuner) of a 30-column x-tile.  Lane l holds node
+// column X = 30*tx + l - 1 (lanes 0 and 31 are halos), loads each input value
+// once per row, gets the x+1 neighbour by a lane shuffle and keeps the previous
+// row in registers, so every input value is read about once per output
+// column.  The node value is the sum of the corner contributions of its four
+// elements: two from its own lane (this and the previous element row) and two
+// from the lane to the left.  Blocks (4 wavefronts = 4 consecutive output
+// columns of one spatial tile) are numbered so that each XCD receives a
+// contiguous range of tiles with all their chaos columns: the neighbour columns
+// a tile reads stay in that XCD's L2.  Each neighbour column is loaded once per
+// output column that needs it; the strips are limited by load latency more
+// than by bandwidth, so in the solve path the next chaos term's loads are kept
+// in flight while the current term is accumulated (sg_strip).
 #include "common.hpp"
 
 // No automatic contraction in this file: every fused multiply-add is written
@@ -76,11 +77,9 @@ constexpr int sweep_waves(int rs, int bytes, bool two) {
 }
 constexpr int kkt_waves(int rs, int bytes) { return rs <= 2 ? 4 : rs <= 4 ? 3 : 2; }
 
-// Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
-// field F at output column j: c0 X_j (mean, if with_mean) plus, for every mode
-// k in mask, c_{k,e} (g- F_{j-e_k} [lower] + g+ F_{j+e_k} [upper]).
 // One term of the SG sum at output column j: mean (k = -1: c0 X_j) or mode
 // k+1 (c_{k+1,e} (g- F_{j-e_k} + g+ F_{j+e_k}), restricted to lower/upper).
+// A term with a single input column holds it in the first slot (ia, ga).
 template <typename T>
 struct Term {
     int ia, ib;
@@ -133,8 +132,7 @@ struct Sweep {
     // Coefficient modes 1..M of the block's element tile (element rows
     // ybase-1 .. ybase+2RS-1, element columns of the 32 lanes), zero off the
     // grid, into LDS as [mode-1][row][lane]: the block's four wavefronts then
-    // read them from LDS instead of through the vector memory path, which
-    // bounds the sweeps (it is close to fully busy while L2 is not).
+    // read them from LDS instead of through the vector memory path.
     template <typename T>
     static __device__ __forceinline__ void stage_coef(T* sc, const T* __restrict__ coef, int64_t cplane, int M, int n,
                                                       int tx, int ty) {
@@ -295,12 +293,15 @@ struct Sweep {
     }
 
     // Corner vectors v[r][.] of element rows y0-1+r of the SG operator applied to
-    // field F at output column j.  Two buffers alternate between the terms: the
-    // next term's node values are loaded into one while the current term, in
-    // the other, is accumulated; the current term's coefficients are loaded
-    // before the next term's values (loads complete in order), so the wait for
-    // them leaves the next term's loads in flight.  The per-node arithmetic is
-    // the same for every strip height.
+    // field F at output column j: c0 X_j (mean, if with_mean) plus, for every
+    // mode k in mask, c_{k,e} (g- F_{j-e_k} [lower] + g+ F_{j+e_k} [upper]).
+    // The next term's raw node values are loaded into a second buffer while
+    // the current term is accumulated, and moved into the first afterwards.
+    // The current term's coefficients are loaded before the next term's
+    // values (loads complete in order, so the wait for them leaves the next
+    // term's loads in flight), the present modes are a bit set found before
+    // any vector load, and a scheduling barrier keeps the loads ahead of the
+    // arithmetic.  The per-node arithmetic is the same for every strip height.
     template <bool TWO, typename T>
     static __device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
                                              int j, int M, const int32_t* __restrict__ nidx,
