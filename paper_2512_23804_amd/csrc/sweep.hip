@@ -695,14 +695,12 @@ bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, i
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_HGS];
     const SweepGeom g = make_geom(s.n, L, (int64_t)nmembers * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
-    if (use_lower && use_upper)
-        SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 1, R, true>), dim3(grid), dim3(256), 0, st, s.n, s.M,
-                                                  s.nxi, s.nt, s.nodes, op, g, V, out, s.off[d], L, mask, use_lower,
-                                                  use_upper, base, bmap, vmap, omap));
-    else
-        SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 1, R, false>), dim3(grid), dim3(256), 0, st, s.n, s.M,
-                                                  s.nxi, s.nt, s.nodes, op, g, V, out, s.off[d], L, mask, use_lower,
-                                                  use_upper, base, bmap, vmap, omap));
+    // Alg. 1 sweeps one neighbour level at a time (forward: the lower level,
+    // backward: the upper level), so every term has a single input column
+    if (use_lower && use_upper) throw Error(SG_ERR_INVALID, "hGS right-hand side: one neighbour level at a time");
+    SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 1, R, false>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi,
+                                              s.nt, s.nodes, op, g, V, out, s.off[d], L, mask, use_lower, use_upper,
+                                              base, bmap, vmap, omap));
     SG_HIP(hipGetLastError());
     return true;
 }
