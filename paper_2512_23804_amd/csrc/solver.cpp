@@ -154,8 +154,14 @@ void hgs(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nmem, bool s
         const ColMap rm = level_map(s, d, rms), bm = level_map(s, d, s.blk), vm = level_map(s, d, vms);
         const int L = s.off[d + 1] - s.off[d];
         const int Ln = d > 0 ? s.off[d] - s.off[d - 1] : 0;
+        if (d == 0) {
+            // degree 0 has no lower level: its right-hand side is R_(0) itself (the
+            // multigrid reads interior nodes only), solved from R directly
+            vcycle<T>(h, R, rm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
+            continue;
+        }
         const bool tp = prof_begin(h, SG_PROF_HGS_RHS, st);
-        launch_hgs_rhs<T>(s, op, d, d > 0 ? mask : 0u, 1, 0, R, rm, V, vfull, Bs, bm, nmem, st);
+        launch_hgs_rhs<T>(s, op, d, mask, 1, 0, R, rm, V, vfull, Bs, bm, nmem, st);
         if (tp) prof_end(h, st, (double)sizeof(T) * (2 * L + (mask ? Ln : 0)) * s.nodes * s.nt * nmem);
         vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
     }
@@ -165,7 +171,11 @@ void hgs(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nmem, bool s
         const int L = s.off[d + 1] - s.off[d];
         const int Lu = s.off[d + 2] - s.off[d + 1];
         const bool tp = prof_begin(h, SG_PROF_HGS_RHS, st);
-        launch_hgs_rhs<T>(s, op, d, mask, 0, 1, Bs, bm, V, vfull, Bs, bm, nmem, st);
+        // base: the forward sweep's right-hand side of level d (R_(0) itself at d = 0)
+        if (d == 0)
+            launch_hgs_rhs<T>(s, op, d, mask, 0, 1, R, level_map(s, 0, rms), V, vfull, Bs, bm, nmem, st);
+        else
+            launch_hgs_rhs<T>(s, op, d, mask, 0, 1, Bs, bm, V, vfull, Bs, bm, nmem, st);
         if (tp) prof_end(h, st, (double)sizeof(T) * (2 * L + Lu) * s.nodes * s.nt * nmem);
         vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
     }
