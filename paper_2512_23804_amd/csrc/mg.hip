@@ -212,9 +212,20 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
     constexpr int CW = W / 2 + 2;
     __shared__ T se[CW * CW];
     const int CX0 = FX0 >= 0 ? FX0 / 2 : -((1 - FX0) / 2), CY0 = FY0 >= 0 ? FY0 / 2 : -((1 - FY0) / 2);
-    for (int q = threadIdx.x; q < CW * CW; q += 256) {
-        const int I = CX0 + q % CW, J = CY0 + q / CW;
-        se[q] = (I >= 0 && I <= mc && J >= 0 && J <= mc) ? ecol[J * C1 + I] : T(0);
+    {
+        constexpr int NE = (CW * CW + 255) / 256;
+        T te[NE];
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {      // loads first (clamped), masked stores after
+            const int q = min((int)threadIdx.x + 256 * i, CW * CW - 1);
+            te[i] = ecol[min(max(CY0 + q / CW, 0), mc) * C1 + min(max(CX0 + q % CW, 0), mc)];
+        }
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            const int I = CX0 + q % CW, J = CY0 + q / CW;
+            if (q < CW * CW) se[q] = (I >= 0 && I <= mc && J >= 0 && J <= mc) ? te[i] : T(0);
+        }
     }
     T breg[PPT], d[PPT], xr[PPT];
     load_region<T, W, PPT>(breg, b + bmap.off(c), FX0, FY0, m);

@@ -138,12 +138,28 @@ struct Sweep {
                                                       int tx, int ty) {
         const int ybase = ty * 2 * RS;
         const int total = M * ER * GW;
-        for (int q = threadIdx.x; q < total; q += 256) {
+        // every load first (clamped addresses), then the masked LDS stores: a
+        // masked load per store would cost one memory latency each
+        constexpr int NQ = (KMAX * ER * GW + 255) / 256;
+        T tmp[NQ];
+    #pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int q = min((int)threadIdx.x + 256 * i, total - 1);
             const int ln = q % GW, r = (q / GW) % ER, k = q / (GW * ER);
-            const int X = tx * GOUT + ln - 1;
-            const int ey = ybase - 1 + r;
-            const bool ok = X >= 0 && X <= n - 1 && ey >= 0 && ey <= n - 1;
-            sc[q] = ok ? coef[(int64_t)(k + 1) * cplane + (int64_t)ey * n + X] : T(0);
+            const int X = min(max(tx * GOUT + ln - 1, 0), n - 1);
+            const int ey = min(max(ybase - 1 + r, 0), n - 1);
+            tmp[i] = coef[(int64_t)(k + 1) * cplane + (int64_t)ey * n + X];
+        }
+    #pragma unroll
+        for (int i = 0; i < NQ; ++i) {
+            const int q = threadIdx.x + 256 * i;
+            if (q < total) {
+                const int ln = q % GW, r = (q / GW) % ER;
+                const int X = tx * GOUT + ln - 1;
+                const int ey = ybase - 1 + r;
+                const bool ok = X >= 0 && X <= n - 1 && ey >= 0 && ey <= n - 1;
+                sc[q] = ok ? tmp[i] : T(0);
+            }
         }
     }
     // Per-lane strip geometry: node rows y0-1 .. y0+RS (RS+2 rows) and element
