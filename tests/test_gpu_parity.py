@@ -194,6 +194,32 @@ def test_solve_matches_direct(shape, arnoldi):
     assert np.linalg.norm(b - K @ x) / np.linalg.norm(b) < 1e-11
 
 
+@pytest.mark.parametrize("shape", [(16, 3, 2, 0.0, 1e-2, 0.0, 1), (16, 2, 2, 0.0, 1e-3, 0.0, 3)])
+def test_deterministic_field_stays_in_the_mean(shape):
+    """sigma = 0: every fluctuation mode of the field vanishes, so neither the
+    KKT operator nor the preconditioner couples chaos columns, and the
+    right-hand side lives in column 0.  The solution is exactly zero in every
+    other column (steady and time-dependent) and column 0 is the oracle's
+    direct solution of the deterministic problem."""
+    n, M, P, sigma, beta, gamma, nt = shape
+    dev = _dev()
+    _say(f"deterministic field {shape}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, y0=nt > 1)
+    sg = kkt.setup(prob)
+    h = _setup([kw], rtol=1e-12, max_iter=400)
+    xd = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+    rc, info = h.solve(xd)
+    torch.cuda.synchronize()
+    assert rc == 0 and info[0].converged == 1 and info[0].rel_res_true <= 1e-12
+    x = canonical_to_kkt(sg, xd.cpu().numpy())
+    ref = kkt.solve_direct(sg)
+    for a, b in zip(kkt.split(sg, x), kkt.split(sg, ref)):
+        higher = a[1:] if nt == 1 else a[:, 1:]
+        assert np.all(higher == 0.0)
+        mean, mean_ref = (a[0], b[0]) if nt == 1 else (a[:, 0], b[:, 0])
+        assert rel_max(mean, mean_ref) < 1e-8
+
+
 def test_solve_fp32_refine_reaches_fp64_accuracy():
     dev = _dev()
     _say("solve fp32 refine")
