@@ -636,7 +636,7 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
 #define SG_DOTS_U 4
 #endif
 #ifndef SG_UPD_U
-#define SG_UPD_U 2
+#define SG_UPD_U 8
 #endif
 constexpr int kDotsU = SG_DOTS_U;   // elements per lane per trip, dots pass
 constexpr int kUpdU = SG_UPD_U;     // elements per lane per trip, update pass
