@@ -176,6 +176,30 @@ def serving_run(sgl, sg_inputs, num, rate, grids, precision):
             "p99_ms": st["p99_ms"]}
 
 
+def serving_sweep(sgl, sg_inputs, num, grids):
+    """The same seeded request mix (shapes do not depend on the arrival rate)
+    submitted all at once to measure the FP64 capacity, then as Poisson streams
+    at half and one and a half times that capacity; each arrival pattern in
+    FP64 and with FP32 refinement."""
+    runs = []
+
+    def one(rate, precision):
+        r = serving_run(sgl, sg_inputs, num, rate, grids, precision)
+        print(f"[serving] {r['precision']} rate {rate:.3g}/s: {r['converged']}/{num} converged, "
+              f"{r['solves_per_s']:.2f} solves/s, p50 {r['p50_ms']:.0f} ms, p99 {r['p99_ms']:.0f} ms",
+              file=sys.stderr, flush=True)
+        runs.append(r)
+        return r
+
+    cap = one(float("inf"), 0)["solves_per_s"]
+    one(float("inf"), 1)
+    for f in (0.5, 1.5):
+        for prec in (0, 1):
+            one(f * cap, prec)
+    return {"serving_sweep": {"requests": num, "grids": list(grids), "fp64_capacity_solves_per_s": cap,
+                              "runs": runs}}
+
+
 def cpu_baseline(wl, gpu_iters):
     """The oracle (plain FP64 numpy/scipy, single thread) timed on one
     preconditioned FGMRES iteration of the first member: one preconditioner
@@ -227,6 +251,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=32, help="requests in the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=30.0, help="Poisson arrival rate of the serving stream")
     ap.add_argument("--serve-grids", default="32,64", help="grid sizes n the serving stream draws from")
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only run the mixed serving protocol (saturated capacity, then Poisson arrivals at "
+                         "0.5x and 1.5x the FP64 capacity, FP64 and FP32 refinement) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (calibrates hardware byte counters) and exit")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
@@ -253,6 +280,11 @@ def main():
 
     import paper_2512_23804_amd as sgl
     import sg_inputs
+
+    if args.serve_sweep:
+        grids = tuple(int(g) for g in args.serve_grids.split(","))
+        print(json.dumps(serving_sweep(sgl, sg_inputs, args.serve_requests, grids)), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     probs = make_problems(sgl, sg_inputs, wl)
