@@ -33,6 +33,8 @@ WORKLOADS = {
     "steady-16-M4-P3": dict(n=16, M=4, P=3, sigma=0.2, betas=(1e-2,), n_t=1, seeds=(0,)),
     "heat-64-M4-P3-nt32": dict(n=64, M=4, P=3, sigma=0.2, betas=(1e-3,), n_t=32, seeds=(4,)),
     "steady-512-M8-P3": dict(n=512, M=8, P=3, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(5,)),
+    # the largest shape the serving stream draws (n_xi = 495, 98 M unknowns)
+    "steady-256-M8-P4": dict(n=256, M=8, P=4, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(6,)),
 }
 DEFAULT = "steady-128-M6-P4"
 # kernels timed with HIP events around every launch (sg_options.profile), with
