@@ -787,8 +787,6 @@ __device__ __forceinline__ void dcgs_update_body(double* __restrict__ V, int64_t
                                                  const double* __restrict__ w, int64_t n, int64_t mstride,
                                                  const double* sv, double inv_nu, int nblk) {
     const int mem = blockIdx.y;
-    int64_t lo, hi;
-    chunk_range(n / 2, nblk, blockIdx.x, lo, hi);
     const double* Vm = V + mem * mstride;
     double* un = V + mem * mstride + (nv + 1) * vstride;
     const double* wm = w + mem * mstride;
@@ -800,8 +798,16 @@ __device__ __forceinline__ void dcgs_update_body(double* __restrict__ V, int64_t
             un[2 * p + 1] = v.y;
         }
     };
-    int64_t p = lo + threadIdx.x;
-    for (; p + (kUpdU - 1) * RB < hi; p += kUpdU * RB) {
+    // Trips of kUpdU * RB element pairs are dealt to the blocks in turn (trip
+    // t to block t mod nblk), so the blocks in flight stream one contiguous
+    // window of every basis vector rather than nblk separate chunks of each
+    // (far fewer pages in use at once on large vectors).  No reduction here:
+    // each element's arithmetic is the same whatever block computes it.
+    const int64_t npair = n / 2;
+    constexpr int64_t TRIP = (int64_t)kUpdU * RB;
+    int64_t base = (int64_t)blockIdx.x * TRIP;
+    for (; base + TRIP <= npair; base += (int64_t)nblk * TRIP) {
+        const int64_t p = base + threadIdx.x;
         dbl2 acc[kUpdU];
 #pragma unroll
         for (int u = 0; u < kUpdU; ++u) acc[u] = ld_pair<AL, true>(wm, p + u * RB);
@@ -819,7 +825,8 @@ __device__ __forceinline__ void dcgs_update_body(double* __restrict__ V, int64_t
 #pragma unroll
         for (int u = 0; u < kUpdU; ++u) store(p + u * RB, dbl2{acc[u].x * inv_nu, acc[u].y * inv_nu});
     }
-    for (; p < hi; p += RB) {
+    // the partial last trip, if any, falls to exactly one block
+    for (int64_t p = base + threadIdx.x; p < npair; p += RB) {
         dbl2 acc = ld_pair<AL, true>(wm, p);
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
