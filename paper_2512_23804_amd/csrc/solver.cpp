@@ -256,7 +256,7 @@ struct Krylov {
         B = h.B;
         m = h.opt.restart;
         N = 3 * s.blk;
-        nblk = (int)std::min<int64_t>(2048, std::max<int64_t>(1, N / (256 * 16)));
+        nblk = (int)std::min<int64_t>(4096, std::max<int64_t>(1, N / (256 * 16)));
         z32 = fp32_precond;
         op32 = fp32_precond && fp32_op;
         vs = ((int64_t)B * N + 63) / 64 * 64;
