@@ -98,3 +98,26 @@ def test_setup_rejects_before_touching_the_device():
     assert rc == sgl.SG_ERR_NONCOERCIVE and not h.value
     rc = sgl.lib.sg_setup(C.byref(p.c), 0, None, None, C.byref(h))
     assert rc == sgl.SG_ERR_INVALID
+
+
+def test_serving_stream_shapes_do_not_depend_on_the_rate():
+    """The serving protocol replays one request mix at several arrival rates
+    (all at once for capacity, then Poisson streams): the drawn shapes, fields
+    and targets must be the same whatever the rate, and an infinite rate puts
+    every arrival at time zero."""
+    grids = (32, 64, 128, 256)
+    mixes = [sg_inputs.serving_stream(64, seed=7, rate_per_s=r, grid_choices=grids)
+             for r in (float("inf"), 4.5, 13.4)]
+    keys = ("n", "M", "P", "sigma", "beta", "seed")
+    for mix in mixes[1:]:
+        assert [tuple(q[k] for k in keys) for q in mix] == [tuple(q[k] for k in keys) for q in mixes[0]]
+    assert all(q["arrival"] == 0.0 for q in mixes[0])
+    for mix in mixes[1:]:
+        arr = np.array([q["arrival"] for q in mix])
+        assert arr[0] == 0.0 and np.all(np.diff(arr) >= 0.0)
+    # the protocol's ranges
+    q = mixes[0]
+    assert {r["n"] for r in q} <= set(grids)
+    assert all(4 <= r["M"] <= 8 and 2 <= r["P"] <= 4 and 0.1 <= r["sigma"] <= 0.3 for r in q)
+    assert all(1e-6 <= r["beta"] <= 1e-1 for r in q)
+    assert [r["seed"] for r in q] == list(range(1000, 1064))
