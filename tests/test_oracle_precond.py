@@ -209,3 +209,102 @@ def test_fgmres_solves_small_kkt_and_truncation_trend():
         assert info["converged"] and info["rel_res"] <= 1e-8
         its[r] = info["iters"]
     assert its[sg.prob.M + 1] <= its[1]
+
+
+def _exact_schur_pair(sg, r_trunc):
+    """(oracle S-approximation inverse as a dense matrix, exact Schur
+    complement of the oracle's KKT matrix): the KKT matrix is
+    [[A_bar, B^T], [B, 0]] with A_bar the (y, u) block, so the exact Schur
+    complement of the adjoint block is B A_bar^{-1} B^T, whatever the scale the
+    paper prints for it."""
+    K = kkt.kkt_matrix(sg).toarray()
+    m = K.shape[0] // 3
+    S_exact = K[2 * m:, :2 * m] @ np.linalg.solve(K[:2 * m, :2 * m], K[2 * m:, :2 * m].T)
+    inner = precond.make_inner(sg, "exact")
+    shp = kkt.block_shape(sg)
+    eye = np.eye(m)
+    Sinv = np.array([precond.schur_inverse(sg, eye[i].reshape(shp), inner, r_trunc).ravel()
+                     for i in range(m)]).T
+    return Sinv, S_exact
+
+
+@pytest.mark.parametrize("beta", [1e-2, 1e-4])
+def test_steady_schur_approximation_spectrum(beta):
+    """Steady, gamma = 0, deterministic field (so one hGS with exact inner
+    solves is Z^{-1} exactly): S = Z M^{-1} Z with Z = A + M/sqrt(beta) is the
+    matching approximation of S_exact = A M^{-1} A + M/beta, whose cross term
+    (A M^{-1} M + M M^{-1} A)/sqrt(beta) = 2A/sqrt(beta) is positive definite,
+    so the eigenvalues of S^{-1} S_exact lie in [1/2, 1] (eq. mathcalZ; the
+    bound of Theorem thm:approx in its steady form).  A slip in the scale of
+    either hGS, of the M_gamma product or of sqrt((1+gamma)/beta) leaves it."""
+    sg = kkt.setup(kkt.Problem(n=4, M=2, P=2, sigma=0.0, beta=beta, y_target=sg_inputs.gaussian_bumps(4, 2)))
+    Sinv, S_exact = _exact_schur_pair(sg, sg.prob.M + 1)
+    ev = np.linalg.eigvals(Sinv @ S_exact)
+    assert np.max(np.abs(ev.imag)) < 1e-10
+    assert ev.real.min() >= 0.5 - 1e-10 and ev.real.max() <= 1.0 + 1e-10
+
+
+@pytest.mark.parametrize("nt", [1, 8])
+@pytest.mark.parametrize("gamma", [0.0, 0.5])
+def test_schur_scale_in_the_small_beta_limit(gamma, nt):
+    """Deterministic field, exact inner solves (so the hGS is Z^{-1} /
+    Z-tilde^{-1} exactly).  Steady (eq. mathcalZ): for beta -> 0 both
+    S_exact = A M_gamma^{-1} A + M/beta and S = Z M_gamma^{-1} Z are dominated
+    by their 1/beta mass terms, M/beta and ((1+gamma)/beta) M M_gamma^{-1} M.
+    Time-dependent: for beta -> 0 with tau fixed (tau >> sqrt(beta), the regime
+    of Lemma lem:lower_bound) both the exact Schur complement
+    B A_bar^{-1} B^T and S-tilde = (1/tau) Z-tilde (D (x) M_gamma)^{-1} Z-tilde
+    are dominated by their (tau/beta) N (.)^{-1} N terms, which coincide up to
+    the variance weight: on chaos column 0 (h^gamma = 1) the ratio is
+    1/(1+gamma), on the other columns 1.  So the eigenvalues of
+    S-tilde^{-1} S_exact approach {1/(1+gamma), 1}.  Reading: S-tilde carries
+    the 1/tau of S-bar (eq. S hat); a tau^2, 1 or 1/tau in its place scales
+    every eigenvalue by tau^{+-1} (here 8) and fails; in either form a slip of
+    H^gamma in the middle factor moves the mean-column limit."""
+    tgt = sg_inputs.gaussian_bumps(4, 2) if nt <= 1 else sg_inputs.moving_bump(4, nt, 1.0, 2)
+    sg = kkt.setup(kkt.Problem(n=4, M=2, P=1, sigma=0.0, beta=1e-10, gamma=gamma, n_t=nt, y_target=tgt))
+    Sinv, S_exact = _exact_schur_pair(sg, sg.prob.M + 1)
+    ev = np.linalg.eigvals(Sinv @ S_exact)
+    assert np.max(np.abs(ev.imag)) < 1e-8
+    lo = 1.0 / (1.0 + gamma)
+    assert ev.real.min() >= lo - 0.01 and ev.real.max() <= 1.0 + 1e-8
+    if gamma > 0:
+        # both limits are attained: the mean column and the fluctuation columns
+        assert np.any(np.abs(ev.real - lo) < 0.01) and np.any(np.abs(ev.real - 1.0) < 0.01)
+
+
+@pytest.mark.parametrize("nt", [1, 3])
+def test_mass_blocks_invert_the_preconditioner_diagonal(nt):
+    """The state and control blocks of the preconditioner approximate the
+    inverses of the (1,1) and (2,2) blocks of eq. (stoch-prec) / eq. (precon
+    for time): (tau D (x) H^gamma (x) M) and (tau beta D (x) H_1 (x) M) (steady:
+    tau = D = 1).  With 60 Chebyshev steps the semi-iteration is exact to
+    rounding, so applied to those blocks times v the preconditioner returns v.
+    The block products are formed here from the interior mass matrix and
+    H^gamma = diag(1, 1+gamma, ..., 1+gamma) written out, not from the
+    oracle's KKT pieces; a slip of H^gamma <-> 1/H^gamma, beta <-> 1/beta or
+    tau <-> 1/tau fails."""
+    gamma, beta = 0.7, 3e-3
+    n, M, P = 8, 2, 2
+    target = sg_inputs.gaussian_bumps(n, 1) if nt <= 1 else sg_inputs.moving_bump(n, nt, 1.0, 3)
+    sg = kkt.setup(kkt.Problem(n=n, M=M, P=P, sigma=0.3, beta=beta, gamma=gamma, n_t=nt, y_target=target,
+                               T=0.6))
+    Mi = fem.restrict(fem.assemble_full(n, 1.0, "mass"), n)
+    hg = np.full(sg.n_xi, 1.0 + gamma)
+    hg[0] = 1.0
+    shp = kkt.block_shape(sg)
+    vy = sg_inputs.random_block(shp, 21)
+    vu = sg_inputs.random_block(shp, 22)
+    if nt <= 1:
+        ry = hg[:, None] * (Mi @ vy.T).T
+        ru = beta * (Mi @ vu.T).T
+    else:
+        tau = 0.6 / nt
+        D = np.ones(nt)
+        D[0] = D[-1] = 0.5
+        ry = np.stack([tau * D[t] * hg[:, None] * (Mi @ vy[t].T).T for t in range(nt)])
+        ru = np.stack([tau * beta * D[t] * (Mi @ vu[t].T).T for t in range(nt)])
+    rl = sg_inputs.random_block(shp, 23)
+    r = np.concatenate([ry.ravel(), ru.ravel(), rl.ravel()])
+    zy, zu, _ = kkt.split(sg, precond.precond_apply(sg, r, precond.make_inner(sg), cheb_steps=60))
+    assert np.max(np.abs(zy - vy)) < 1e-12 and np.max(np.abs(zu - vu)) < 1e-12
