@@ -5,10 +5,10 @@ A step is one pass of the whole hot path over one batch: a preconditioned
 FGMRES(30) solve to relative residual 1e-8 of every member of the batch
 (block-diagonal Schur preconditioner with Chebyshev mass solves and the
 hierarchical Gauss-Seidel sweep with multigrid inner solves).  The default
-workload is the steady 128 x 128 problem (16,641 nodes, M = 6 random
-variables, total degree P = 4, n_xi = 210, sigma = 0.3) with its beta sweep
-{1e-2, 1e-4, 1e-6} solved as one batch of three members (seeded Gaussian-bump
-targets).  Prints one JSON line.
+workload is the largest single-GPU steady problem: 512 x 512 Q1 elements
+(263,169 nodes), M = 8 random variables, total degree P = 3 (n_xi = 165),
+sigma = 0.3, beta = 1e-2, about 130 M unknowns (seeded Gaussian-bump target).
+Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -36,7 +36,7 @@ WORKLOADS = {
     # the largest shape the serving stream draws (n_xi = 495, 98 M unknowns)
     "steady-256-M8-P4": dict(n=256, M=8, P=4, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(6,)),
 }
-DEFAULT = "steady-128-M6-P4"
+DEFAULT = "steady-512-M8-P3"
 # kernels timed with HIP events around every launch (sg_options.profile), with
 # the algorithmic bytes each launch must move
 PROF_KIND = {"kkt_apply": 1, "mg_down": 2, "arnoldi_dots": 3, "hgs_rhs": 4, "arnoldi_update": 5, "mg_tail": 6,
@@ -140,79 +140,145 @@ def sg_apply_bandwidth(torch, sgl, probs, stream, min_bytes=1 << 30, reps=20):
     return dict(ms=ms, bytes=bytes_per, GBps=bytes_per / ms / 1e6, buffers=nbuf)
 
 
-def serving_run(sgl, sg_inputs, num, rate, grids, precision):
+def serving_run(sgl, sg_inputs, num, rate, grids, precision, keep=None):
     """Continuous-batching server (sg_submit / sg_poll) on a seeded Poisson
     stream of mixed-shape steady requests; latency is submit -> completion
-    and includes the host <-> device copies of the request's arrays."""
+    and includes the host <-> device copies of the request's arrays.  With
+    `keep` (a dict), each request's host solution is stored under its index."""
     from math import comb
     reqs = sg_inputs.serving_stream(num, seed=7, rate_per_s=rate, grid_choices=grids)
     srv = sgl.Server(hbm_budget_bytes=0, max_slots=16)
     opts = sgl.default_options(rtol=1e-8, precision=precision)
-    pending, converged = {}, 0
+    pending, converged, worst = {}, 0, 0.0
     t0 = time.perf_counter()
 
     def drain():
-        nonlocal converged
+        nonlocal converged, worst
         for t in list(pending):
             rc, info = srv.poll(t)
             if rc != sgl.SG_PENDING:
-                converged += int(rc == sgl.SG_OK and info.converged == 1)
-                del pending[t]          # releases the host output array
+                ok = rc == sgl.SG_OK and info.converged == 1
+                converged += int(ok)
+                worst = max(worst, info.rel_res_true)
+                i, out = pending.pop(t)
+                if keep is not None:
+                    keep[i] = out
 
-    for r in reqs:
+    for i, r in enumerate(reqs):
         while time.perf_counter() - t0 < r["arrival"]:
             drain()
             time.sleep(0.0005)
         pd = sgl.ProblemData(r["n"], r["M"], r["P"], r["sigma"], r["beta"], sg_inputs.gaussian_bumps(r["n"], r["seed"]))
         out = np.empty(3 * comb(r["M"] + r["P"], r["P"]) * (r["n"] + 1) ** 2)
-        pending[srv.submit(pd, out, opts)] = out
+        pending[srv.submit(pd, out, opts)] = (i, out)
     while pending:
         drain()
         time.sleep(0.001)
     wall = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    return {"requests": num, "arrival_rate_per_s": rate, "grids": list(grids), "M_range": [4, 8],
+    return {"path": "serving", "requests": num, "arrival_rate_per_s": rate, "grids": list(grids), "M_range": [4, 8],
             "P_range": [2, 4], "precision": {0: "fp64", 1: "fp32_refine", 2: "fp32_precond"}[precision],
-            "converged": converged, "wall_s": wall, "solves_per_s": num / wall, "p50_ms": st["p50_ms"],
-            "p99_ms": st["p99_ms"]}
+            "converged": converged, "max_rel_res": worst, "wall_s": wall, "solves_per_s": converged / wall,
+            "submitted_per_s": num / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "failed": converged < num}
 
 
-def serving_sweep(sgl, sg_inputs, num, grids):
+def single_solve_run(torch, sgl, sg_inputs, num, grids, keep=None):
+    """The plain FP64 single-solve path on the same seeded request mix: the
+    requests, all queued at time zero, are solved one after another, each with
+    its own handle (sg_setup + sg_solve on device buffers, no batching, no
+    overlap); latency is from the start to the copy of its solution to host
+    memory, as in the server."""
+    reqs = sg_inputs.serving_stream(num, seed=7, rate_per_s=float("inf"), grid_choices=grids)
+    opts = sgl.default_options(rtol=1e-8, use_graphs=0)
+    lat, converged, worst = [], 0, 0.0
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        pd = sgl.ProblemData(r["n"], r["M"], r["P"], r["sigma"], r["beta"], sg_inputs.gaussian_bumps(r["n"], r["seed"]))
+        h = sgl.Handle(pd, opts)
+        x = torch.zeros(h.kkt_elems, dtype=torch.float64, device="cuda")
+        rc, info = h.solve(x)
+        out = x.cpu().numpy()
+        h.close()
+        del x
+        converged += int(rc == sgl.SG_OK and info[0].converged == 1)
+        worst = max(worst, info[0].rel_res_true)
+        lat.append(1000.0 * (time.perf_counter() - t0))
+        if keep is not None:
+            keep[i] = out
+    wall = time.perf_counter() - t0
+    return {"path": "single_fp64", "requests": num, "arrival_rate_per_s": float("inf"), "grids": list(grids),
+            "precision": "fp64", "converged": converged, "max_rel_res": worst, "wall_s": wall,
+            "solves_per_s": converged / wall, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "failed": converged < num}
+
+
+def _max_rel_diff_host(a: dict, b: dict) -> float:
+    """max over requests of ||a - b||_inf / ||b||_inf (host solutions)."""
+    return max(float(np.max(np.abs(a[i] - b[i])) / np.max(np.abs(b[i]))) for i in b)
+
+
+def serving_compare(torch, sgl, sg_inputs, num, grids):
+    """The batched-serving comparison on one seeded mixed-shape request mix,
+    every request queued at time zero (capacity): FP64 serving, FP32 operator
+    and preconditioner with FP64 refinement in serving, and the plain FP64
+    single-solve path.  Each FP32 result's max-norm difference from the FP64
+    serving result of the same request is reported."""
+    x64, x32, xs = {}, {}, {}
+    runs = [serving_run(sgl, sg_inputs, num, float("inf"), grids, 0, keep=x64),
+            serving_run(sgl, sg_inputs, num, float("inf"), grids, 1, keep=x32),
+            single_solve_run(torch, sgl, sg_inputs, num, grids, keep=xs)]
+    runs[1]["max_rel_diff_vs_fp64"] = _max_rel_diff_host(x32, x64)
+    runs[2]["max_rel_diff_vs_fp64"] = _max_rel_diff_host(xs, x64)
+    return {"requests": num, "grids": list(grids), "arrivals": "all at time zero", "runs": runs,
+            "fp32_refine_serving_over_single_fp64": runs[1]["solves_per_s"] / runs[2]["solves_per_s"],
+            "fp64_serving_over_single_fp64": runs[0]["solves_per_s"] / runs[2]["solves_per_s"]}
+
+
+def serving_sweep(torch, sgl, sg_inputs, num, grids):
     """The same seeded request mix (shapes do not depend on the arrival rate)
-    submitted all at once to measure the FP64 capacity, then as Poisson streams
-    at half and one and a half times that capacity; each arrival pattern in
-    FP64 and with FP32 refinement."""
-    runs = []
-
-    def one(rate, precision):
-        r = serving_run(sgl, sg_inputs, num, rate, grids, precision)
-        print(f"[serving] {r['precision']} rate {rate:.3g}/s: {r['converged']}/{num} converged, "
+    submitted all at once to measure capacity (FP64 serving, FP32-refinement
+    serving, plain FP64 single solves), then as Poisson streams at half and one
+    and a half times the FP64 serving capacity, in both serving precisions."""
+    cmp = serving_compare(torch, sgl, sg_inputs, num, grids)
+    runs = list(cmp["runs"])
+    for r in runs:
+        print(f"[serving] {r['path']} {r['precision']} all at once: {r['converged']}/{num} converged, "
               f"{r['solves_per_s']:.2f} solves/s, p50 {r['p50_ms']:.0f} ms, p99 {r['p99_ms']:.0f} ms",
               file=sys.stderr, flush=True)
-        runs.append(r)
-        return r
-
-    cap = one(float("inf"), 0)["solves_per_s"]
-    one(float("inf"), 1)
+    cap = runs[0]["solves_per_s"]
     for f in (0.5, 1.5):
         for prec in (0, 1):
-            one(f * cap, prec)
+            r = serving_run(sgl, sg_inputs, num, f * cap, grids, prec)
+            print(f"[serving] {r['precision']} rate {f * cap:.3g}/s: {r['converged']}/{num} converged, "
+                  f"{r['solves_per_s']:.2f} solves/s, p50 {r['p50_ms']:.0f} ms, p99 {r['p99_ms']:.0f} ms",
+                  file=sys.stderr, flush=True)
+            runs.append(r)
     return {"serving_sweep": {"requests": num, "grids": list(grids), "fp64_capacity_solves_per_s": cap,
                               "runs": runs}}
 
 
 def cpu_baseline(wl, gpu_iters):
-    """The oracle (plain FP64 numpy/scipy, single thread) timed on one
-    preconditioned FGMRES iteration of the first member: one preconditioner
-    application (Chebyshev + two hGS sweeps with multigrid) and one matricized
-    KKT apply; scaled by the GPU run's iterations per solve."""
+    """The oracle (plain FP64 numpy/scipy, BLAS threaded over every core this
+    process may use) timed on the first member at the workload size.
+
+    When one oracle FGMRES iteration (one preconditioner application: the
+    Chebyshev mass blocks and two hGS sweeps with multigrid inner solves; one
+    matricized KKT apply; the Gram-Schmidt work of an average Arnoldi step)
+    takes a few seconds, whole iterations are timed for about 10 s.  At sizes
+    where one iteration takes longer, its parts are timed once each (one KKT
+    apply, the mass blocks, one hGS sweep counted twice, the Schur mass
+    product, Gram-Schmidt on 4 vectors scaled to 15) and summed: a projected
+    iteration.  Either way the per-iteration time is scaled by the GPU run's
+    iterations per solve."""
     from threadpoolctl import threadpool_limits
 
     import sg_inputs
     from oracle import kkt, precond
 
-    with threadpool_limits(limits=1):
+    cores = len(os.sched_getaffinity(0))
+    with threadpool_limits(limits=cores):
         if wl["n_t"] > 1:
             tgt = sg_inputs.moving_bump(wl["n"], wl["n_t"], 1.0, wl["seeds"][0])
         else:
@@ -222,23 +288,92 @@ def cpu_baseline(wl, gpu_iters):
         sg = kkt.setup(prob)
         inner = precond.make_inner(sg)
         r = kkt.rhs(sg)
-        V = np.random.default_rng(0).standard_normal((15, r.size))
-        reps, t0 = 0, time.perf_counter()
-        while True:   # whole iterations until at least 10 s of CPU work
-            z = precond.precond_apply(sg, r, inner)
-            w = kkt.kkt_apply_matricized(sg, z)
-            # Arnoldi work of an average iteration (15 basis vectors, two Gram-Schmidt passes)
+        t0 = time.perf_counter()
+        w = kkt.kkt_apply_matricized(sg, r)
+        t_kkt = time.perf_counter() - t0
+        if t_kkt < 2.0:
+            V = np.random.default_rng(0).standard_normal((15, r.size))
+            reps, t0 = 0, time.perf_counter()
+            while True:   # whole iterations until at least 10 s of CPU work
+                z = precond.precond_apply(sg, r, inner)
+                w = kkt.kkt_apply_matricized(sg, z)
+                for _ in range(2):          # Arnoldi work of an average iteration (15 basis vectors)
+                    hcoef = V @ w
+                    w = w - V.T @ hcoef
+                reps += 1
+                if time.perf_counter() - t0 >= 10.0:
+                    break
+            t_iter = (time.perf_counter() - t0) / reps
+            sample = (f"{reps} whole FGMRES iterations of the oracle on the first member at the workload size "
+                      f"({t_iter:.2f} s each, {cores} threads), scaled by {gpu_iters:.1f} iterations per solve")
+            kind = "oracle"
+        else:
+            Ry, Ru, Rl = kkt.split(sg, r)
+            t0 = time.perf_counter()
+            if prob.steady:
+                precond.kkt_cheb(sg, Ry, 5)
+                precond.kkt_cheb(sg, Ru, 5)
+            else:
+                for t in range(prob.n_t):
+                    precond.kkt_cheb(sg, Ry[t], 5)
+                    precond.kkt_cheb(sg, Ru[t], 5)
+            t_cheb = time.perf_counter() - t0
+            R0 = Rl if prob.steady else Rl[0]
+            t0 = time.perf_counter()
+            V1 = precond.hgs(sg, R0, inner, prob.M + 1)
+            t_hgs = (time.perf_counter() - t0) * (1 if prob.steady else prob.n_t)
+            t0 = time.perf_counter()
+            kkt.mass_apply(sg, V1)
+            t_mass = (time.perf_counter() - t0) * (1 if prob.steady else prob.n_t)
+            V = np.random.default_rng(0).standard_normal((4, r.size))
+            t0 = time.perf_counter()
             for _ in range(2):
                 hcoef = V @ w
                 w = w - V.T @ hcoef
-            reps += 1
-            if time.perf_counter() - t0 >= 10.0:
-                break
-        t_iter = (time.perf_counter() - t0) / reps
+            t_gs = (time.perf_counter() - t0) * 15.0 / 4.0
+            del V
+            t_iter = t_kkt + t_cheb + 2 * t_hgs + t_mass + t_gs
+            sample = (f"projected: one oracle FGMRES iteration on the first member at the workload size, from its "
+                      f"parts timed once each with {cores} threads (KKT apply {t_kkt:.1f} s, mass blocks "
+                      f"{t_cheb:.1f} s, 2 x hGS sweep {t_hgs:.1f} s, Schur mass product {t_mass:.1f} s, "
+                      f"Gram-Schmidt {t_gs:.1f} s; {t_iter:.1f} s per iteration), scaled by {gpu_iters:.1f} "
+                      f"iterations per solve")
+            kind = "oracle"
     per_solve = t_iter * gpu_iters
-    return dict(value=1.0 / per_solve, unit="solves/s", cores=1, kind="oracle",
-                sample=f"{reps} FGMRES iterations of the oracle on the first member at the workload size "
-                       f"({t_iter:.2f} s each, single thread), scaled by {gpu_iters:.1f} iterations per solve")
+    return dict(value=1.0 / per_solve, unit="solves/s", cores=cores, kind=kind, sample=sample,
+                projected=t_kkt >= 2.0, s_per_iteration=t_iter)
+
+
+def residual_check(wl, x_canonical, reported, nrows=10000, seed=17):
+    """The oracle's check of a GPU solution: the FP64 residual b - K x on
+    `nrows` seeded random rows of the explicit KKT system (every block), the
+    norm estimate sqrt(N/S sum r_i^2) / ||b|| against the solver's reported
+    relative residual, and the largest sampled |r_i| / ||b||."""
+    import sg_inputs
+    from oracle import fem, kkt
+
+    if wl["n_t"] > 1:
+        tgt = sg_inputs.moving_bump(wl["n"], wl["n_t"], 1.0, wl["seeds"][0])
+    else:
+        tgt = sg_inputs.gaussian_bumps(wl["n"], wl["seeds"][0])
+    prob = kkt.Problem(n=wl["n"], M=wl["M"], P=wl["P"], sigma=wl["sigma"], beta=wl["betas"][0],
+                       n_t=wl["n_t"], y_target=tgt)
+    sg = kkt.setup(prob)
+    nt = max(wl["n_t"], 1)
+    V = np.asarray(x_canonical).reshape(3, nt, sg.n_xi, -1)
+    blocks = [fem.extract(V[i], wl["n"]) for i in range(3)]
+    if prob.steady:
+        blocks = [b[0] for b in blocks]
+    x = np.concatenate([b.reshape(-1) for b in blocks])
+    del V, blocks
+    b = kkt.rhs(sg)
+    rows = np.sort(np.random.default_rng(seed).choice(b.size, size=min(nrows, b.size), replace=False))
+    r = b[rows] - kkt.kkt_rows(sg, x, rows)
+    bn = float(np.linalg.norm(b))
+    est = float(np.sqrt(b.size / rows.size * np.sum(r * r))) / bn
+    return {"rows": int(rows.size), "seed": seed, "unknowns": int(b.size), "estimated_rel_res": est,
+            "reported_rel_res": reported, "max_sampled_abs_res_over_norm_b": float(np.max(np.abs(r))) / bn,
+            "ok": bool(est <= 3.0 * max(reported, 1e-16) and np.max(np.abs(r)) / bn <= 1e-8)}
 
 
 def main():
@@ -250,12 +385,13 @@ def main():
     ap.add_argument("--profile-kernel", default="auto", choices=["auto"] + sorted(PROF_KIND),
                     help="kernel reported as roofline (auto: the one with the largest measured total time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=32, help="requests in the serving stream (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=30.0, help="Poisson arrival rate of the serving stream")
-    ap.add_argument("--serve-grids", default="32,64", help="grid sizes n the serving stream draws from")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving comparison (all queued at time zero; 0: skip)")
+    ap.add_argument("--serve-grids", default="32,64,128,256", help="grid sizes n the request mix draws from")
     ap.add_argument("--serve-sweep", action="store_true",
-                    help="only run the mixed serving protocol (saturated capacity, then Poisson arrivals at "
-                         "0.5x and 1.5x the FP64 capacity, FP64 and FP32 refinement) and print its JSON")
+                    help="only run the mixed serving protocol (capacity of FP64 serving, FP32-refinement "
+                         "serving and plain FP64 single solves, then Poisson arrivals at 0.5x and 1.5x the "
+                         "FP64 serving capacity) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (calibrates hardware byte counters) and exit")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
@@ -283,10 +419,13 @@ def main():
     import paper_2512_23804_amd as sgl
     import sg_inputs
 
+    grids = tuple(int(g) for g in args.serve_grids.split(","))
     if args.serve_sweep:
-        grids = tuple(int(g) for g in args.serve_grids.split(","))
-        print(json.dumps(serving_sweep(sgl, sg_inputs, args.serve_requests, grids)), flush=True)
+        print(json.dumps(serving_sweep(torch, sgl, sg_inputs, args.serve_requests, grids)), flush=True)
         return
+
+    def say(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     wl = WORKLOADS[args.workload]
     probs = make_problems(sgl, sg_inputs, wl)
@@ -298,6 +437,7 @@ def main():
     opts = sgl.default_options(rtol=1e-8, use_graphs=graphs, arnoldi=arn, sweep_rows=args.sweep_rows)
     tuned = []
     x64 = []
+    say(f"headline {args.workload}: {args.warmup} warmup + {args.steps} timed FP64 solves")
     dt, infos = timed_solves(torch, sgl, probs, opts, args.steps, args.warmup, stream, tuned, keep=x64)
     nsolve = len(probs) * args.steps
     value = nsolve / dt
@@ -309,6 +449,7 @@ def main():
     # of the timed steps)
     kern = {}
     kinds = PROF_KIND if args.profile_kernel == "auto" else {args.profile_kernel: PROF_KIND[args.profile_kernel]}
+    say("per-kernel event timing")
     for name, kind in kinds.items():
         popt = sgl.default_options(rtol=1e-8, profile=kind, arnoldi=arn, sweep_rows=args.sweep_rows)
         _, pinfo = timed_solves(torch, sgl, probs, popt, 1, 0, stream)
@@ -347,23 +488,41 @@ def main():
         "kernels": kern,
     }
     if not args.no_extras:
-        o32 = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_REFINE, use_graphs=graphs,
-                                  arnoldi=arn, sweep_rows=args.sweep_rows)
-        x32 = []
-        dt32, inf32 = timed_solves(torch, sgl, probs, o32, args.steps, 1, stream, keep=x32)
-        out["fp32_refine"] = {"value": nsolve / dt32, "unit": "solves/s", "dtype": "f32 operator/preconditioner, "
-                              "f64 Arnoldi and refinement", "iterations": [i.iters for i in inf32[0]],
-                              "max_rel_res": max(i.rel_res_true for st in inf32 for i in st),
-                              "max_rel_diff_vs_fp64": max_rel_diff(x32[0], x64[0])}
-        opc = sgl.default_options(rtol=1e-8, precision=sgl.SG_PREC_FP32_PRECOND, use_graphs=graphs, arnoldi=arn,
-                                  sweep_rows=args.sweep_rows)
-        xpc = []
-        dtp, infp = timed_solves(torch, sgl, probs, opc, args.steps, 1, stream, keep=xpc)
-        out["fp32_precond"] = {"value": nsolve / dtp, "unit": "solves/s", "dtype": "f32 preconditioner, "
-                               "f64 operator, Arnoldi and restarts", "iterations": [i.iters for i in infp[0]],
-                               "max_rel_res": max(i.rel_res_true for st in infp for i in st),
-                               "max_rel_diff_vs_fp64": max_rel_diff(xpc[0], x64[0])}
-        del x32, xpc
+        say("SG operator apply bandwidth")
+        out["sg_apply"] = sg_apply_bandwidth(torch, sgl, probs, stream)
+        out["sg_apply"]["frac_of_hbm_peak"] = out["sg_apply"]["GBps"] / HBM_PEAK_GBPS
+        hk = sgl.Handle(probs, sgl.default_options(), stream=stream)
+        b = torch.zeros(hk.members * hk.kkt_elems, dtype=torch.float64, device="cuda")
+        hk.rhs(b)
+        bnorm = b.view(hk.members, -1).norm(dim=1)
+
+        def residual_gap(xa, xb):
+            """max over members of ||K (xa - xb)|| / ||b||: how far apart two
+            solutions are in the residual norm the solver stops on."""
+            d = (xa - xb).reshape(-1).contiguous()
+            kd_ = torch.empty_like(d)
+            hk.apply_kkt(d, kd_, stream=stream)
+            torch.cuda.synchronize()
+            return float((kd_.view(hk.members, -1).norm(dim=1) / bnorm).max())
+
+        for label, prec, dtype in (("fp32_refine", sgl.SG_PREC_FP32_REFINE,
+                                    "f32 operator/preconditioner, f64 Arnoldi and refinement"),
+                                   ("fp32_precond", sgl.SG_PREC_FP32_PRECOND,
+                                    "f32 preconditioner, f64 operator, Arnoldi and restarts")):
+            say(f"{label}: {args.steps} timed solves")
+            o = sgl.default_options(rtol=1e-8, precision=prec, use_graphs=graphs, arnoldi=arn,
+                                    sweep_rows=args.sweep_rows)
+            xk = []
+            dtk, infk = timed_solves(torch, sgl, probs, o, args.steps, 1, stream, keep=xk)
+            out[label] = {"value": nsolve / dtk, "unit": "solves/s", "dtype": dtype,
+                          "iterations": [i.iters for i in infk[0]],
+                          "outer_refinements": [i.outer_refinements for i in infk[0]],
+                          "max_rel_res": max(i.rel_res_true for st in infk for i in st),
+                          "max_rel_diff_vs_fp64": max_rel_diff(xk[0], x64[0]),
+                          "max_residual_gap_vs_fp64": residual_gap(xk[0], x64[0])}
+            del xk
+        hk.close()
+        say("plain FP64 single solves")
         single = []
         t_single = 0.0
         for p in probs:
@@ -372,13 +531,16 @@ def main():
             t_single += dts
             single.append(infs[0][0].iters)
         out["fp64_single"] = {"value": len(probs) / t_single, "unit": "solves/s", "iterations": single}
-        out["sg_apply"] = sg_apply_bandwidth(torch, sgl, probs, stream)
-        out["sg_apply"]["frac_of_hbm_peak"] = out["sg_apply"]["GBps"] / HBM_PEAK_GBPS
     if not args.no_extras and args.serve_requests > 0:
-        grids = tuple(int(g) for g in args.serve_grids.split(","))
-        out["serving"] = serving_run(sgl, sg_inputs, args.serve_requests, args.serve_rate, grids, 0)
+        say(f"serving comparison: {args.serve_requests} requests on grids {grids}")
+        out["serving"] = serving_compare(torch, sgl, sg_inputs, args.serve_requests, grids)
+    xsol = x64[0][0].cpu().numpy()
+    del x64
     if not args.no_cpu_baseline:
+        say("CPU baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, float(np.mean(iters)))
+        say("oracle residual check of the FP64 solution on sampled KKT rows")
+        out["residual_check"] = residual_check(wl, xsol, infos[-1][0].rel_res_true)
     print(json.dumps(out), flush=True)
 
 

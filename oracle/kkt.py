@@ -388,3 +388,75 @@ def moments(Y: np.ndarray):
     """Mean and variance fields of an SG expansion (orthonormal basis):
     E[y] = Y_0 and Var[y] = sum_{j>=1} Y_j^2 (Section 2.1, H^sigma)."""
     return Y[..., 0, :], np.sum(Y[..., 1:, :] ** 2, axis=-2)
+
+
+def kkt_rows(sg: SG, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """Selected entries (K x)[rows] of the KKT matrix times a flat vector,
+    from the explicit rows of the Kronecker blocks (Section 2.1, eq.
+    (stoch-system); Section 3, eq. (KKT:stoch-time-dependent)), for sizes where
+    neither the matrix nor a full apply is wanted.
+
+    A flat row index addresses [block][t][j][i] (block 0 state, 1 control,
+    2 adjoint; t only when time-dependent; chaos j; interior node i).  Row
+    (j, i) of A = sum_k H_k (x) A_k applied to a block X is
+    sum_k sum_j' h_{k j j'} (A_k[i, :] . X_j'), computed from the sampled
+    spatial rows of every A_k and the matrices H_k."""
+    p = sg.prob
+    rows = np.asarray(rows, dtype=np.int64)
+    Y, U, L = split(sg, x)
+    if p.steady:                          # one time step, so both forms share the code below
+        Y, U, L = Y[None], U[None], L[None]
+    nt = Y.shape[0]
+    nx, ni = sg.n_xi, sg.n_int
+    blk = nt * nx * ni
+    b = rows // blk
+    rem = rows % blk
+    i = rem % ni
+    j = (rem // ni) % nx
+    t = rem // (nx * ni)
+    hg = h_gamma(sg)
+    tau = 1.0 if p.steady else p.tau
+    D = np.ones(nt)
+    if not p.steady:
+        D[0] = D[-1] = 0.5
+    out = np.empty(rows.size)
+    for blkid in range(3):
+        s = np.flatnonzero(b == blkid)
+        if s.size == 0:
+            continue
+        jj, ts = j[s], t[s]
+        Ms = sg.Mi.tocsr()[i[s]]                     # sampled spatial rows of M and of every A_k
+        Ks = [Kk.tocsr()[i[s]] for Kk in sg.K]
+
+        def mass(F, dt=0):
+            """(M F_{t+dt, j})_i, zero where t+dt leaves [0, n_t)."""
+            tn = ts + dt
+            ok = np.flatnonzero((tn >= 0) & (tn < nt))
+            v = np.zeros(s.size)
+            v[ok] = np.asarray(Ms[ok].multiply(F[tn[ok], jj[ok]]).sum(axis=1)).ravel()
+            return v
+
+        def stiff(F):
+            """(A F_t)_{j,i} = sum_k sum_j' h_{k j j'} (A_k[i,:] . F_{t,j'})."""
+            acc = np.zeros(s.size)
+            for Gk, Kk in zip(sg.G, Ks):
+                T = np.empty((s.size, nx))
+                for tq in np.unique(ts):
+                    m = np.flatnonzero(ts == tq)
+                    T[m] = np.asarray(Kk[m] @ F[tq].T)
+                acc += np.einsum("sq,qs->s", T, Gk[:, jj])
+            return acc
+
+        Dt = D[ts]
+        if blkid == 0:
+            # tau D_t M_gamma y_t - (A_t^T lambda)_t, (A_t^T lambda)_t = L lambda_t - M lambda_{t+1};
+            # steady: M_gamma y - A lambda
+            trans = mass(L) + tau * stiff(L) - mass(L, +1) if not p.steady else stiff(L)
+            out[s] = tau * Dt * hg[jj] * mass(Y) - trans
+        elif blkid == 1:
+            out[s] = p.beta * tau * Dt * mass(U) + tau * mass(L)
+        else:
+            # -(A_t y)_t + tau M u_t, (A_t y)_t = L y_t - M y_{t-1}; steady: -A y + M u
+            fwd = mass(Y) + tau * stiff(Y) - mass(Y, -1) if not p.steady else stiff(Y)
+            out[s] = -fwd + tau * mass(U)
+    return out

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.environ.get("SG_LIB_PATH", os.path.join(HERE, "libsgkkt.so"))
+LIB_PATH = os.path.join(HERE, "libsgkkt.so")
 
 SG_OK, SG_PENDING, SG_NOT_CONVERGED = 0, 1, 2
 SG_ERR_INVALID, SG_ERR_NONCOERCIVE, SG_ERR_NONFINITE = -1, -2, -3

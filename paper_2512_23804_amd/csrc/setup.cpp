@@ -300,11 +300,7 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
         // it starts at 32
         int lds = 0;
         SG_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
-#ifdef SG_MG_TAIL_MAX
-        h->mg_tail_max = SG_MG_TAIL_MAX;
-#else
         h->mg_tail_max = lds >= 144 * 1024 ? 64 : 32;
-#endif
     }
     const sg_problem& p0 = probs[0];
     Shape& s = h->s;

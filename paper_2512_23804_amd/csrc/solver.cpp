@@ -356,6 +356,11 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
     double* r = h.ws.get_t<double>("kr", (size_t)B * N);
     std::vector<double> nr2, resid;
     std::vector<int> jend(B, 0), active(B, 0);
+    // host copy of the device's per-member `pending` flags (DCGS2): set for the
+    // members that ran an iteration, so their last Hessenberg column is
+    // completed by the next dot pass; only used to count the members each
+    // profiled pass really processes
+    std::vector<int> pend(B, 0);
     res_out.assign(B, 0.0);
     int* pinned_i = reinterpret_cast<int*>(h.h_pinned + 2048);   // upload staging (after a stream sync)
     for (int cycle = 0; max_cycles <= 0 || cycle < max_cycles; ++cycle) {
@@ -375,6 +380,7 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         for (int q = 0; q < B; ++q) {
             active[q] = todo[q];
             jend[q] = 0;
+            pend[q] = 0;
             pinned_i[q] = active[q];
         }
         SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
@@ -390,14 +396,23 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
                 // DCGS2: the basis slots hold the candidates U (V = U R^{-1}); one
                 // read-only pass gives the reorthogonalisation of u_j and the
                 // projections of w, one update pass writes the next candidate u_{j+1}
+                // members each pass processes (the kernels skip the others):
+                // the dot pass those active or with a pending column, the update
+                // pass the active ones
+                int n_dots = 0, n_upd = 0;
+                for (int q = 0; q < B; ++q) {
+                    n_dots += (active[q] || pend[q]) ? 1 : 0;
+                    n_upd += active[q] ? 1 : 0;
+                }
                 bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
                 launch_dcgs_dots(K.V, vs, j, K.w, N, B, N, K.kd.active, K.kd.pending, K.partial, K.nblk, st);
-                if (tp) prof_end(h, st, 8.0 * (j + 2) * (double)B * N);
+                if (tp) prof_end(h, st, 8.0 * (j + 2) * (double)n_dots * N);
                 launch_reduce_partials(K.partial, K.nblk, 2 * j + 3, B, K.kd.dots, kSlots, 0, st);
                 launch_dcgs_finish(K.kd, m, j, 0, B, st);
                 tp = prof_begin(h, SG_PROF_ARNOLDI_UPD, st);
                 launch_dcgs_update(K.V, vs, j, K.w, N, B, N, K.kd.coef, K.kd.scal, K.kd.active, K.nblk, st);
-                if (tp) prof_end(h, st, 8.0 * (j + 3) * (double)B * N);   // read U_0..U_j and w, write u_{j+1}
+                if (tp) prof_end(h, st, 8.0 * (j + 3) * (double)n_upd * N);   // read U_0..U_j and w, write u_{j+1}
+                for (int q = 0; q < B; ++q) pend[q] = active[q];
                 return;
             }
             const int nv = j + 1;

@@ -34,6 +34,7 @@ __all__ = [
     "indicator_target",
     "random_block",
     "serving_stream",
+    "field_modes",
 ]
 
 
@@ -109,6 +110,32 @@ def serving_stream(num: int, seed: int, rate_per_s: float,
         reqs.append(dict(n=n, M=M, P=P, sigma=sigma, beta=beta,
                          seed=1000 + i, arrival=float(arrivals[i])))
     return reqs
+
+
+def field_modes(n: int, M: int, seed: int, amp: float = 0.6, mean: float = 1.3) -> np.ndarray:
+    """Seeded per-element coefficient modes [M+1][n][n] (index [k][ey][ex],
+    values at the element centroids) of an affine random field whose modes are
+    not symmetric under x <-> y: mode 0 is the constant `mean`, mode k is
+    w_k cos(a_k pi x + p_k) cos(b_k pi y + q_k) with integer wavenumbers
+    a_k != b_k, random phases and weights w_k ~ k^-2, scaled so that
+    sqrt(3) sum_k max|mode k| = amp * mean (amp < 1 keeps the field
+    a = mean + sqrt(3) sum_k mode_k xi_k-type expansion positive for all xi)."""
+    rng = np.random.default_rng(seed)
+    t = (np.arange(n, dtype=np.float64) + 0.5) / n
+    yc, xc = np.meshgrid(t, t, indexing="ij")
+    out = np.empty((M + 1, n, n), dtype=np.float64)
+    out[0] = mean
+    peak = 0.0
+    for k in range(1, M + 1):
+        a = int(rng.integers(0, 4))
+        b = int(rng.integers(0, 4))
+        if b == a:
+            b = a + 1
+        px, py = rng.uniform(0.0, math.pi, size=2)
+        out[k] = k ** -2.0 * np.cos(a * math.pi * xc + px) * np.cos(b * math.pi * yc + py)
+        peak += np.max(np.abs(out[k]))
+    out[1:] *= amp * mean / (math.sqrt(3.0) * peak)
+    return out
 
 
 def unit_sine(n: int) -> np.ndarray:

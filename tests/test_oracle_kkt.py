@@ -184,3 +184,18 @@ def test_matricized_kkt_apply_equals_explicit(nt):
     x = sg_inputs.random_block(K.shape[0], 3)
     ref = K @ x
     assert np.max(np.abs(kkt.kkt_apply_matricized(sg, x) - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("nt", [1, 4])
+def test_kkt_rows_equal_explicit_matrix_rows(nt):
+    """kkt_rows (sampled rows, used for the large-grid residual check) equals
+    the explicit KKT matrix times x on those rows, every block and time step."""
+    if nt == 1:
+        sg = _steady(n=8, M=3, P=2, gamma=0.4)
+    else:
+        sg = _time_problem(n=8, M=2, P=2, nt=nt, gamma=0.4)
+    K = kkt.kkt_matrix(sg)
+    x = sg_inputs.random_block(K.shape[0], 4)
+    rows = np.random.default_rng(5).choice(K.shape[0], size=600, replace=False)
+    ref = (K @ x)[rows]
+    assert np.max(np.abs(kkt.kkt_rows(sg, x, rows) - ref)) < 1e-13 * np.max(np.abs(ref))
