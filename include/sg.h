@@ -240,6 +240,23 @@ int sg_apply_kkt(sg_handle* h, const void* x_dev, void* y_dev, int32_t nvec,
 int sg_precond_apply(sg_handle* h, const void* r_dev, void* z_dev, int32_t nvec,
                      int32_t dtype, void* stream);
 
+/* sg_precond_apply for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same operation and kernels, bit-identical results, but
+ * every scratch buffer (iterates of the hGS sweeps, the Schur mass product,
+ * multigrid levels) is carved from a fixed 64 MiB device array that the
+ * library holds on each device until the process ends; no hipMalloc,
+ * hipFree or memset is issued.  The handle must have been set up beforehand
+ * (sg_setup allocates; this call does not) and its device must be current.
+ * Arguments as sg_precond_apply.  Returns SG_ERR_NOMEM, before launching
+ * anything, when the scratch nvec vectors need exceeds the fixed size
+ * (about 7 field blocks of the handle's shape per vector).  All calls on one
+ * device share the array and it keeps the last call's contents: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller. */
+int sg_precond_apply_noalloc(sg_handle* h, const void* r_dev, void* z_dev, int32_t nvec,
+                             int32_t dtype, void* stream);
+
 /* Solve K x = b for every member with preconditioned FGMRES(restart) from
  * x = 0.  b_dev: FP64 KKT vectors (NULL = the problems' own right-hand
  * sides); x_dev: FP64 output KKT vectors; info: array of `members` reports

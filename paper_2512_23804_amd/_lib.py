@@ -67,6 +67,8 @@ SIGNATURES = {
     "sg_apply_operator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "sg_apply_kkt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "sg_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "sg_precond_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                           C.c_void_p]),
     "sg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(sg_solve_info)]),
     "sg_destroy": (None, [C.c_void_p]),
     "sg_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]),
@@ -219,6 +221,12 @@ class Handle:
         check(lib.sg_precond_apply(self._h, _ptr(r), _ptr(z), self._nvec(r, self.kkt_elems), _dtype_code(r),
                                    _stream_ptr(stream)))
         return z
+
+    def precond_apply_noalloc(self, r, z, stream=None, allow=(SG_OK,)):
+        """sg_precond_apply_noalloc: the preconditioner with the library's fixed
+        device scratch (no device allocation); returns the status code."""
+        return check(lib.sg_precond_apply_noalloc(self._h, _ptr(r), _ptr(z), self._nvec(r, self.kkt_elems),
+                                                  _dtype_code(r), _stream_ptr(stream)), allow=allow)
 
     def solve(self, x, b=None):
         infos = (sg_solve_info * self.members)()

@@ -166,6 +166,35 @@ int sg_precond_apply(sg_handle* h, const void* r_dev, void* z_dev, int32_t nvec,
     });
 }
 
+int sg_precond_apply_noalloc(sg_handle* h, const void* r_dev, void* z_dev, int32_t nvec, int32_t dtype,
+                             void* stream) {
+    return guarded([&] {
+        int rc = check_vec_args(h, r_dev, z_dev, nvec, dtype);
+        if (rc) return rc;
+        sg::Handle& H = *h->h;
+        int dev = -1;
+        SG_HIP(hipGetDevice(&dev));
+        if (dev != H.device) return fail(SG_ERR_INVALID, "the handle's device must be current");
+        void* base = sg::noalloc_scratch(dev);
+        hipStream_t st = stream ? (hipStream_t)stream : H.stream;
+        struct ArenaGuard {
+            sg::Workspace& ws;
+            ~ArenaGuard() { ws.end_arena(); }
+        } guard{H.ws};
+        H.ws.begin_arena(base, sg::noalloc_scratch_bytes());
+        // every scratch buffer is carved before the first launch: a call that
+        // does not fit fails here with SG_ERR_NOMEM and launches nothing
+        if (dtype == SG_FP64) {
+            sg::precond_reserve<double>(H, nvec);
+            sg::precond_apply<double>(H, (const double*)r_dev, (double*)z_dev, nvec, H.B == 1, st);
+        } else {
+            sg::precond_reserve<float>(H, nvec);
+            sg::precond_apply<float>(H, (const float*)r_dev, (float*)z_dev, nvec, H.B == 1, st);
+        }
+        return SG_OK;
+    });
+}
+
 int sg_solve(sg_handle* h, const double* b_dev, double* x_dev, sg_solve_info* info) {
     return guarded([&] {
         if (!h || !h->h || !x_dev) return fail(SG_ERR_INVALID, "null argument");

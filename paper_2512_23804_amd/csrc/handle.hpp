@@ -11,11 +11,28 @@
 
 namespace sg {
 
-// Grow-only named device buffers owned by a handle.
+// Grow-only named device buffers owned by a handle.  While an arena is set
+// (begin_arena), named buffers are carved from that caller-provided device
+// memory instead (256-byte aligned, same name -> same buffer for the arena's
+// lifetime) and nothing is allocated; a request beyond the arena's capacity
+// throws SG_ERR_NOMEM.
 class Workspace {
   public:
     ~Workspace() { release(); }
+    void begin_arena(void* base, size_t cap) {
+        arena_ = static_cast<char*>(base);
+        arena_cap_ = cap;
+        arena_used_ = 0;
+        arena_bufs_.clear();
+    }
+    void end_arena() {
+        arena_ = nullptr;
+        arena_cap_ = arena_used_ = 0;
+        arena_bufs_.clear();
+    }
+    bool in_arena() const { return arena_ != nullptr; }
     void* get(const std::string& name, size_t bytes) {
+        if (arena_) return carve(name, bytes);
         auto it = bufs_.find(name);
         if (it != bufs_.end() && it->second.second >= bytes) return it->second.first;
         if (it != bufs_.end()) {
@@ -47,9 +64,24 @@ class Workspace {
     uint64_t generation() const { return gen_; }   // changes whenever a buffer is (re)allocated
 
   private:
+    void* carve(const std::string& name, size_t bytes) {
+        auto it = arena_bufs_.find(name);
+        if (it != arena_bufs_.end() && it->second.second >= bytes) return it->second.first;
+        const size_t start = (arena_used_ + 255) / 256 * 256;
+        if (start > arena_cap_ || bytes > arena_cap_ - start)
+            throw Error(SG_ERR_NOMEM, "scratch of " + std::to_string(start + bytes) + " bytes needed ('" + name +
+                                          "'), above the fixed maximum of " + std::to_string(arena_cap_) + " bytes");
+        void* p = arena_ + start;
+        arena_used_ = start + bytes;
+        arena_bufs_[name] = {p, bytes};
+        return p;
+    }
     std::map<std::string, std::pair<void*, size_t>> bufs_;
     size_t total_ = 0;
     uint64_t gen_ = 0;
+    char* arena_ = nullptr;
+    size_t arena_cap_ = 0, arena_used_ = 0;
+    std::map<std::string, std::pair<void*, size_t>> arena_bufs_;
 };
 
 // HIP-event timing of one kernel's launches (sg_options.profile).
@@ -160,7 +192,15 @@ double prof_collect_ms(Handle& h);                           // waits for the ev
 template <typename T>
 void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st);
 template <typename T>
+void precond_reserve(Handle& h, int nvec);                   // request precond_apply's scratch up front
+template <typename T>
 void kkt_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st);
+
+// noalloc.hip: the library's fixed device scratch array (for the entry point
+// that allocates nothing): its address on `device` (resolved once per device,
+// with that device current) and its size in bytes
+void* noalloc_scratch(int device);
+size_t noalloc_scratch_bytes();
 template <typename T>
 void operator_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st);
 int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info);

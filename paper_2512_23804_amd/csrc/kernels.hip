@@ -470,6 +470,12 @@ __global__ __launch_bounds__(64) void k_mg_coarse_f32(const float* __restrict__ 
 }
 
 template <typename T>
+__global__ void k_fill_zero(T* x, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = T(0);
+}
+
+template <typename T>
 __global__ void k_zero_ring(T* x, int n, int64_t ncols) {
     const int64_t nodes = (int64_t)(n + 1) * (n + 1);
     const int64_t per = 4 * (int64_t)n;
@@ -1241,8 +1247,11 @@ void launch_mass_cheb(const Shape& s, const OpDev& op, const T* r, T* z, T* bufA
                        r, (const T*)nullptr, (const T*)nullptr, steps == 1 ? z : cur, T(1), 1, steps == 1 ? 1 : 0);
     SG_HIP(hipGetLastError());
     if (steps == 1) return;
-    // prev holds x_0 = 0
-    SG_HIP(hipMemsetAsync(prev, 0, sizeof(T) * (size_t)nvec * ncols * s.nodes, st));
+    // prev holds x_0 = 0 (a fill kernel, not a memset node, so that the
+    // sequence can be captured in a graph)
+    const int64_t cnt = (int64_t)nvec * ncols * s.nodes;
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3(grid1d(cnt)), dim3(256), 0, st, prev, cnt);
+    SG_HIP(hipGetLastError());
     double omega = 1.0;
     for (int k = 1; k < steps; ++k) {
         omega = (k == 1) ? 1.0 / (1.0 - 0.5 * rho * rho) : 1.0 / (1.0 - 0.25 * rho * rho * omega);

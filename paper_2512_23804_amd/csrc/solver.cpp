@@ -71,6 +71,47 @@ ColMap block_map(const Shape& s, int64_t mstride) {
     return m;
 }
 
+// Levels with at most mg_tail_max intervals per side (and the direct solve)
+// run in one fused launch; the finer levels have a down and an up launch each.
+// Returns the first level handled by the fused tail (or the direct solve) and
+// whether the tail is used.
+int mg_first_fused(const Handle& h, bool& tail) {
+    const Shape& s = h.s;
+    const int nl = s.nlev_mg;
+    int l0 = 0;
+    while (l0 < nl - 1 && s.mg_n[l0] > h.mg_tail_max) ++l0;
+    tail = l0 < nl - 1;
+    return tail ? l0 : nl - 1;
+}
+
+// Per-level multigrid scratch of a V-cycle over ncols columns: bs (restricted
+// right-hand side, l >= 1), xf (after post-smoothing, l >= 1; level 0 writes
+// to x); xs only for the coarsest level solved directly.
+template <typename T>
+void mg_buffers(Handle& h, int ncols, std::vector<T*>& xs, std::vector<T*>& bs, std::vector<T*>& xf,
+                std::vector<ColMap>& cm) {
+    const Shape& s = h.s;
+    const int nl = s.nlev_mg;
+    bool tail = false;
+    const int lc = mg_first_fused(h, tail);
+    xs.assign(nl, nullptr);
+    bs.assign(nl, nullptr);
+    xf.assign(nl, nullptr);
+    cm.assign(nl, ColMap{});
+    for (int l = 0; l <= lc; ++l) {
+        const int m = s.mg_n[l];
+        const int64_t nodes = (int64_t)(m + 1) * (m + 1);
+        const size_t cnt = (size_t)ncols * nodes;
+        const std::string tag = std::string("mg") + tname<T>() + "_" + std::to_string(l);
+        cm[l] = contiguous_cols(ncols, nodes);
+        if (l == lc && !tail) xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
+        if (l > 0) {
+            bs[l] = h.ws.get_t<T>(tag + "_bs", cnt);
+            xf[l] = h.ws.get_t<T>(tag + "_xf", cnt);
+        }
+    }
+}
+
 // One multigrid V-cycle for the columns of degree level d (all members, all
 // time steps): b (level-d columns through bmap) -> x (through xmap).  Column c
 // uses the constants of member c / cpm (cpm = ncols when all columns share
@@ -85,29 +126,11 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         launch_mg_coarse<T>(h.ainv<T>(), b, bmap, x, xmap, ncols, cpm, st);
         return;
     }
-    // Levels with at most tail_max intervals per side (and the direct solve)
-    // run in one fused launch; the finer levels have a down and an up launch each.
-    int l0 = 0;
-    while (l0 < nl - 1 && s.mg_n[l0] > h.mg_tail_max) ++l0;
-    const bool tail = l0 < nl - 1;
-    const int lc = tail ? l0 : nl - 1;      // first level handled by the fused tail or the direct solve
-    // per level: bs (restricted right-hand side, l >= 1), xf (after
-    // post-smoothing, l >= 1; level 0 writes to x); xs only for the coarsest
-    // level solved directly
-    std::vector<T*> xs(nl), bs(nl), xf(nl);
-    std::vector<ColMap> cm(nl);
-    for (int l = 0; l <= lc; ++l) {
-        const int m = s.mg_n[l];
-        const int64_t nodes = (int64_t)(m + 1) * (m + 1);
-        const size_t cnt = (size_t)ncols * nodes;
-        const std::string tag = std::string("mg") + tname<T>() + "_" + std::to_string(l);
-        cm[l] = contiguous_cols(ncols, nodes);
-        if (l == lc && !tail) xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
-        if (l > 0) {
-            bs[l] = h.ws.get_t<T>(tag + "_bs", cnt);
-            xf[l] = h.ws.get_t<T>(tag + "_xf", cnt);
-        }
-    }
+    bool tail = false;
+    const int lc = mg_first_fused(h, tail);
+    std::vector<T*> xs, bs, xf;
+    std::vector<ColMap> cm;
+    mg_buffers<T>(h, ncols, xs, bs, xf, cm);
     for (int l = 0; l < lc; ++l) {
         const int m = s.mg_n[l];
         const double nodes = (double)(m + 1) * (m + 1);
@@ -205,8 +228,10 @@ void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream
     const OpDev op = h.op<T>(shared);
     const int64_t kkt = 3 * s.blk;
     // state and control blocks: Chebyshev semi-iteration on M with block scalings
-    T* A = h.ws.get_t<T>(std::string("chebA") + tname<T>(), (size_t)nvec * 2 * s.blk);
-    T* Bb = h.ws.get_t<T>(std::string("chebB") + tname<T>(), (size_t)nvec * 2 * s.blk);
+    // (the per-step Chebyshev kernel, used above 9 steps, needs two iterate buffers)
+    const bool cheb_bufs = h.opt.cheb_steps > 9;
+    T* A = cheb_bufs ? h.ws.get_t<T>(std::string("chebA") + tname<T>(), (size_t)nvec * 2 * s.blk) : nullptr;
+    T* Bb = cheb_bufs ? h.ws.get_t<T>(std::string("chebB") + tname<T>(), (size_t)nvec * 2 * s.blk) : nullptr;
     const bool tp = prof_begin(h, SG_PROF_MASS_CHEB, st);
     launch_mass_cheb<T>(s, op, r, z, A, Bb, nvec, h.opt.cheb_steps, st);
     if (tp) prof_end(h, st, 4.0 * sizeof(T) * nvec * (double)s.blk);   // read r_y, r_u; write z_y, z_u
@@ -219,6 +244,31 @@ void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream
     hgs<T>(h, W, s.blk, z + 2 * s.blk, kkt, nvec, shared, st);
 }
 
+// Every scratch buffer precond_apply<T> uses for nvec vectors, requested at
+// its largest size (the multigrid levels are sized for the largest degree
+// level), so that in arena mode a call that does not fit fails here, before
+// any launch.
+template <typename T>
+void precond_reserve(Handle& h, int nvec) {
+    const Shape& s = h.s;
+    if (h.opt.cheb_steps > 9) {
+        h.ws.get_t<T>(std::string("chebA") + tname<T>(), (size_t)nvec * 2 * s.blk);
+        h.ws.get_t<T>(std::string("chebB") + tname<T>(), (size_t)nvec * 2 * s.blk);
+    }
+    h.ws.get_t<T>(std::string("schurV") + tname<T>(), (size_t)nvec * s.blk);
+    h.ws.get_t<T>(std::string("schurW") + tname<T>(), (size_t)nvec * s.blk);
+    h.ws.get_t<T>(std::string("hgsB") + tname<T>(), (size_t)nvec * s.blk);
+    if (s.nlev_mg > 1) {
+        int lmax = 0;
+        for (int d = 0; d <= s.P; ++d) lmax = std::max(lmax, s.off[d + 1] - s.off[d]);
+        std::vector<T*> xs, bs, xf;
+        std::vector<ColMap> cm;
+        mg_buffers<T>(h, lmax * s.nt * nvec, xs, bs, xf, cm);
+    }
+}
+
+template void precond_reserve<double>(Handle&, int);
+template void precond_reserve<float>(Handle&, int);
 template void operator_apply<double>(Handle&, const double*, double*, int, bool, hipStream_t);
 template void operator_apply<float>(Handle&, const float*, float*, int, bool, hipStream_t);
 template void kkt_apply<double>(Handle&, const double*, double*, int, bool, hipStream_t);
