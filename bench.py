@@ -150,6 +150,7 @@ def serving_run(sgl, sg_inputs, num, rate, grids, precision, keep=None):
     srv = sgl.Server(hbm_budget_bytes=0, max_slots=16)
     opts = sgl.default_options(rtol=1e-8, precision=precision)
     pending, converged, worst = {}, 0, 0.0
+    setup_ms, solve_ms, iters = [], [], []
     t0 = time.perf_counter()
 
     def drain():
@@ -160,6 +161,9 @@ def serving_run(sgl, sg_inputs, num, rate, grids, precision, keep=None):
                 ok = rc == sgl.SG_OK and info.converged == 1
                 converged += int(ok)
                 worst = max(worst, info.rel_res_true)
+                setup_ms.append(info.t_setup_ms)
+                solve_ms.append(info.t_solve_ms)
+                iters.append(info.iters)
                 i, out = pending.pop(t)
                 if keep is not None:
                     keep[i] = out
@@ -181,6 +185,9 @@ def serving_run(sgl, sg_inputs, num, rate, grids, precision, keep=None):
             "P_range": [2, 4], "precision": {0: "fp64", 1: "fp32_refine", 2: "fp32_precond"}[precision],
             "converged": converged, "max_rel_res": worst, "wall_s": wall, "solves_per_s": converged / wall,
             "submitted_per_s": num / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+            "mean_batch_setup_ms": float(np.mean(setup_ms)) if setup_ms else None,
+            "mean_batch_solve_ms": float(np.mean(solve_ms)) if solve_ms else None,
+            "mean_iterations": float(np.mean(iters)) if iters else None,
             "failed": converged < num}
 
 
@@ -505,13 +512,18 @@ def main():
             torch.cuda.synchronize()
             return float((kd_.view(hk.members, -1).norm(dim=1) / bnorm).max())
 
-        for label, prec, dtype in (("fp32_refine", sgl.SG_PREC_FP32_REFINE,
-                                    "f32 operator/preconditioner, f64 Arnoldi and refinement"),
-                                   ("fp32_precond", sgl.SG_PREC_FP32_PRECOND,
-                                    "f32 preconditioner, f64 operator, Arnoldi and restarts")):
+        for label, prec, basis32, dtype in (
+                ("fp32_refine", sgl.SG_PREC_FP32_REFINE, 1,
+                 "inner cycles: f32 storage of operator input/output, preconditioner and Arnoldi basis, f64 stiffness "
+                 "and Arnoldi sums; f64 residual and refinement"),
+                ("fp32_refine_f64_basis", sgl.SG_PREC_FP32_REFINE, 0,
+                 "inner cycles: f32 storage of operator input/output and preconditioner, f64 Arnoldi basis; f64 "
+                 "residual and refinement"),
+                ("fp32_precond", sgl.SG_PREC_FP32_PRECOND, 1,
+                 "f32 preconditioner, f64 operator, Arnoldi and restarts")):
             say(f"{label}: {args.steps} timed solves")
             o = sgl.default_options(rtol=1e-8, precision=prec, use_graphs=graphs, arnoldi=arn,
-                                    sweep_rows=args.sweep_rows)
+                                    sweep_rows=args.sweep_rows, basis_fp32=basis32)
             xk = []
             dtk, infk = timed_solves(torch, sgl, probs, o, args.steps, 1, stream, keep=xk)
             out[label] = {"value": nsolve / dtk, "unit": "solves/s", "dtype": dtype,

@@ -72,8 +72,9 @@ extern "C" {
 #define SG_FP64 0
 #define SG_FP32 1
 #define SG_PREC_FP64         0  /* operator, preconditioner and Krylov in FP64 */
-#define SG_PREC_FP32_REFINE  1  /* FP32 operator + preconditioner inside FGMRES, FP64
-                                   Arnoldi, FP64 outer residual and refinement */
+#define SG_PREC_FP32_REFINE  1  /* FP32 storage for the operator and preconditioner inside
+                                   FGMRES (their arithmetic as below), FP64 Arnoldi sums,
+                                   FP64 outer residual and refinement */
 #define SG_PREC_FP32_PRECOND 2  /* FP32 preconditioner (basis Z in FP32) inside FP64
                                    FGMRES: FP64 operator and Arnoldi; every restart
                                    recomputes the FP64 residual */
@@ -127,7 +128,18 @@ typedef struct sg_problem {
  *   sweep_rows   node rows per strip of the SG/KKT/hGS sweep kernels: 2, 4
  *                or 8, or 0 to let sg_setup time the three on the handle's
  *                shape and keep the fastest (cached per process and shape;
- *                every choice gives bit-identical results) [0] */
+ *                every choice gives bit-identical results) [0]
+ *   basis_fp32   SG_PREC_FP32_REFINE with DCGS2 only: 1 stores the inner
+ *                cycles' Arnoldi basis and operator output in FP32 (every dot
+ *                product, projection and Hessenberg entry is still formed in
+ *                FP64), 0 stores them in FP64 [1]
+ *
+ * Arithmetic precision.  The stiffness sums of the SG operator, KKT apply and
+ * hGS right-hand sides are formed in FP64 for FP32 storage too (an FP32
+ * vector is widened on load, results rounded on store): summed in FP32, the
+ * Q1 stencil's cancellation on fine grids (relative error growing like
+ * eps / h^2) would cap what an FP32 refinement step can gain.  The mass,
+ * Chebyshev and multigrid kernels compute in the storage precision. */
 typedef struct sg_options {
     double rtol;
     int32_t restart, max_iter, cheb_steps, truncation_r;
@@ -136,6 +148,7 @@ typedef struct sg_options {
     int32_t use_graphs, verbose, profile;
     int32_t arnoldi;
     int32_t sweep_rows;
+    int32_t basis_fp32;
 } sg_options;
 
 #define SG_ARNOLDI_DCGS2 0

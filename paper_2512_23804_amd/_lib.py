@@ -37,7 +37,7 @@ class sg_options(C.Structure):
                 ("cheb_steps", C.c_int32), ("truncation_r", C.c_int32), ("gmg_pre", C.c_int32),
                 ("gmg_post", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
                 ("use_graphs", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
-                ("arnoldi", C.c_int32), ("sweep_rows", C.c_int32)]
+                ("arnoldi", C.c_int32), ("sweep_rows", C.c_int32), ("basis_fp32", C.c_int32)]
 
 
 class sg_solve_info(C.Structure):

@@ -111,6 +111,7 @@ struct OpDev {                   // device pointers describing the operator of a
     const int32_t* nbr_idx;      // [nxi][M][2]
     const double* nbr_val;       // [nxi][M][2]
     const void* coef;            // [member][M+1][n][n] in T
+    const double* coef64;        // the same in FP64 (the sweep kernels compute in FP64 for every storage type)
     int64_t coef_mstride;        // elements per member (0 = shared)
     const MemberDev* mem;        // [member]
     int mem_shared;              // 1 = all vectors use member 0
@@ -198,10 +199,13 @@ void launch_norm(const double* x, int64_t n, int nmem, int64_t mstride, double* 
 void launch_axpby(double a, const double* x, double b, double* y, int64_t n, hipStream_t st);
 void launch_cast_d2f(const double* x, float* y, int64_t n, hipStream_t st);
 void launch_cast_f2d(const float* x, double* y, int64_t n, hipStream_t st);
-void launch_copy_scale_rows(const double* src, double* dst, const double* inv_norm, int64_t n,
+template <typename TD>
+void launch_copy_scale_rows(const double* src, TD* dst, const double* inv_norm, int64_t n,
                             int nmem, int64_t mstride, hipStream_t st);
 template <typename T>
 void launch_zero_ring(T* x, int n, int64_t ncols, hipStream_t st);
+template <typename T>
+void launch_fill_zero(T* x, int64_t count, hipStream_t st);   // x[0..count) = 0 (a kernel, capturable)
 
 // Arnoldi bookkeeping on the device (one thread per member).
 constexpr int kSlots = 64;   // partial-sum slots per member in Krylov reductions
@@ -224,10 +228,14 @@ struct KrylovDev {
     int* pending;     // [member] 1 while the last Hessenberg column awaits its reorthogonalisation
 };
 void launch_arnoldi_finish(KrylovDev k, int restart, int j, int nmem, hipStream_t st);
-void launch_dcgs_dots(const double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem,
+// DCGS2 passes over a basis stored in TV (double, or float in the FP32
+// inner cycles of iterative refinement); sums are formed in double.
+template <typename TV>
+void launch_dcgs_dots(const TV* V, int64_t vstride, int nv, const TV* w, int64_t n, int nmem,
                       int64_t mstride, const int* active, const int* pending, double* partial, int nblk,
                       hipStream_t st);
-void launch_dcgs_update(double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem, int64_t mstride,
+template <typename TV>
+void launch_dcgs_update(TV* V, int64_t vstride, int nv, const TV* w, int64_t n, int nmem, int64_t mstride,
                         const double* coef, const double* scal, const int* active, int nblk, hipStream_t st);
 void launch_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem, hipStream_t st);
 void launch_cycle_start(KrylovDev k, int restart, const double* beta0, int nmem, hipStream_t st);

@@ -4,12 +4,78 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "common.hpp"
 
 namespace sg {
+
+// Device blocks kept for reuse instead of being freed.  The server builds and
+// releases a handle per batch; hipFree synchronises the whole device, so its
+// handles take their memory from one pool that frees nothing until it is
+// trimmed (on an allocation failure, or when the server is destroyed).  A
+// request is served by the smallest cached block that is at least as large
+// and at most 25% (or 8 MiB) larger; blocks are handed out only by the thread
+// whose stream has finished with them (a handle releases its memory after its
+// stream synchronised).
+class DevicePool {
+  public:
+    ~DevicePool() { trim(); }
+    void* alloc(size_t bytes) {
+        bytes = (bytes + 255) / 256 * 256;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            auto it = free_.lower_bound(bytes);
+            if (it != free_.end() && it->first <= bytes + std::max<size_t>(bytes / 4, size_t(8) << 20)) {
+                void* p = it->second;
+                cached_ -= it->first;
+                free_.erase(it);
+                return p;
+            }
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            trim();
+            e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(SG_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed: " +
+                                              hipGetErrorString(e));
+            }
+        }
+        std::lock_guard<std::mutex> lk(mu_);
+        size_of_[p] = bytes;
+        return p;
+    }
+    void release(void* p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = size_of_.find(p);
+        if (it == size_of_.end()) return;
+        free_.emplace(it->second, p);
+        cached_ += it->second;
+    }
+    void trim() {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto& kv : free_) {
+            (void)hipFree(kv.second);
+            size_of_.erase(kv.second);
+        }
+        free_.clear();
+        cached_ = 0;
+    }
+    size_t cached() const { return cached_; }
+
+  private:
+    std::mutex mu_;
+    std::multimap<size_t, void*> free_;
+    std::map<void*, size_t> size_of_;
+    size_t cached_ = 0;
+};
 
 // Grow-only named device buffers owned by a handle.  While an arena is set
 // (begin_arena), named buffers are carved from that caller-provided device
@@ -19,6 +85,7 @@ namespace sg {
 class Workspace {
   public:
     ~Workspace() { release(); }
+    void set_pool(DevicePool* pool) { pool_ = pool; }
     void begin_arena(void* base, size_t cap) {
         arena_ = static_cast<char*>(base);
         arena_cap_ = cap;
@@ -36,15 +103,19 @@ class Workspace {
         auto it = bufs_.find(name);
         if (it != bufs_.end() && it->second.second >= bytes) return it->second.first;
         if (it != bufs_.end()) {
-            (void)hipFree(it->second.first);
+            free_block(it->second.first);
             bufs_.erase(it);
         }
         void* p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes < 256 ? 256 : bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            throw Error(SG_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes for '" + name +
-                                          "' failed: " + hipGetErrorString(e));
+        if (pool_) {
+            p = pool_->alloc(bytes < 256 ? 256 : bytes);
+        } else {
+            hipError_t e = hipMalloc(&p, bytes < 256 ? 256 : bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(SG_ERR_NOMEM, "device allocation of " + std::to_string(bytes) + " bytes for '" + name +
+                                              "' failed: " + hipGetErrorString(e));
+            }
         }
         bufs_[name] = {p, bytes};
         total_ += bytes;
@@ -56,7 +127,7 @@ class Workspace {
         return static_cast<T*>(get(name, count * sizeof(T)));
     }
     void release() {
-        for (auto& kv : bufs_) (void)hipFree(kv.second.first);
+        for (auto& kv : bufs_) free_block(kv.second.first);
         bufs_.clear();
         total_ = 0;
     }
@@ -64,6 +135,12 @@ class Workspace {
     uint64_t generation() const { return gen_; }   // changes whenever a buffer is (re)allocated
 
   private:
+    void free_block(void* p) {
+        if (pool_)
+            pool_->release(p);
+        else
+            (void)hipFree(p);
+    }
     void* carve(const std::string& name, size_t bytes) {
         auto it = arena_bufs_.find(name);
         if (it != arena_bufs_.end() && it->second.second >= bytes) return it->second.first;
@@ -81,6 +158,7 @@ class Workspace {
     uint64_t gen_ = 0;
     char* arena_ = nullptr;
     size_t arena_cap_ = 0, arena_used_ = 0;
+    DevicePool* pool_ = nullptr;
     std::map<std::string, std::pair<void*, size_t>> arena_bufs_;
 };
 
@@ -103,12 +181,12 @@ struct Prof {
 };
 
 // Instantiated graphs of one FGMRES iteration, keyed by (restart position j,
-// precision variant: bit 0 FP32 preconditioner, bit 1 FP32 operator), valid
-// for one workspace generation.
+// precision variant: bit 0 FP32 preconditioner, bit 1 FP32 operator, bit 2
+// FP32 basis), valid for one workspace generation.
 struct GraphCache {
     std::map<std::pair<int, int>, hipGraphExec_t> exec;
     uint64_t gen = ~0ull;
-    bool warm[4] = {false, false, false, false};
+    bool warm[8] = {false, false, false, false, false, false, false, false};
     void clear() {
         for (auto& kv : exec) (void)hipGraphExecDestroy(kv.second);
         exec.clear();
@@ -125,13 +203,17 @@ struct Handle {
     hipStream_t stream = nullptr;
     int device = 0;
     double t_setup_ms = 0.0;
+    DevicePool* pool = nullptr;         // device memory source (nullptr: hipMalloc / hipFree)
 
     HostTables ht;
     std::vector<MemberDev> mem_host;
     std::vector<LevelDev> lev_host;     // [member][kMaxLevels]
     std::vector<double> coef_host;      // [member][M+1][n][n]
     std::vector<double> ainv_host;      // [member][64][64]
-    std::vector<double> rhs_host;       // [member][3][nt][nxi][nodes] (sparse in practice)
+    // nonzero chaos columns of the right-hand sides: [member][2][nt][nodes]
+    // (state block, column 0, every t; adjoint block, column 0, every t);
+    // every other entry of a KKT right-hand side is zero
+    std::vector<double> rhs_host;
 
     // device-resident constant data
     int32_t* d_nbr_idx = nullptr;
@@ -162,6 +244,7 @@ struct Handle {
         o.nbr_idx = d_nbr_idx;
         o.nbr_val = d_nbr_val;
         o.coef = sizeof(T) == 8 ? (const void*)d_coef64 : (const void*)d_coef32;
+        o.coef64 = d_coef64;
         o.coef_mstride = shared ? 0 : (int64_t)(s.M + 1) * s.n * s.n;
         o.mem = d_mem;
         o.mem_shared = shared ? 1 : 0;
@@ -181,7 +264,8 @@ void set_last_error(const std::string& msg);
 void default_options(sg_options* o);
 void validate(const sg_problem* probs, int count, const sg_options* opt);   // throws Error
 void autotune(Handle& h);   // tune.cpp: strip heights of the sweep kernels (sg_options.sweep_rows)
-std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt, hipStream_t st);
+std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt, hipStream_t st,
+                                     DevicePool* pool = nullptr);
 std::vector<int32_t> multi_indices(int M, int P);
 int binom(int n, int k);
 

@@ -27,21 +27,23 @@ struct Nine {
 
 // Load the 3x3 neighbourhood of interior node (ix, iy); neighbours on the
 // boundary ring read as zero.
+// Values are widened to FP64 (the SG stencils compute in FP64 whatever the
+// storage type).
 template <typename T>
-__device__ __forceinline__ Nine<T> load9(const T* __restrict__ x, int n, int ix, int iy) {
+__device__ __forceinline__ Nine<double> load9(const T* __restrict__ x, int n, int ix, int iy) {
     const int N1 = n + 1;
     const int64_t p = (int64_t)iy * N1 + ix;
     const bool w = ix > 1, e = ix < n - 1, s = iy > 1, nn = iy < n - 1;
-    Nine<T> v;
-    v.c = x[p];
-    v.w = w ? x[p - 1] : T(0);
-    v.e = e ? x[p + 1] : T(0);
-    v.s = s ? x[p - N1] : T(0);
-    v.n = nn ? x[p + N1] : T(0);
-    v.sw = (s && w) ? x[p - N1 - 1] : T(0);
-    v.se = (s && e) ? x[p - N1 + 1] : T(0);
-    v.nw = (nn && w) ? x[p + N1 - 1] : T(0);
-    v.ne = (nn && e) ? x[p + N1 + 1] : T(0);
+    Nine<double> v;
+    v.c = (double)x[p];
+    v.w = w ? (double)x[p - 1] : 0.0;
+    v.e = e ? (double)x[p + 1] : 0.0;
+    v.s = s ? (double)x[p - N1] : 0.0;
+    v.n = nn ? (double)x[p + N1] : 0.0;
+    v.sw = (s && w) ? (double)x[p - N1 - 1] : 0.0;
+    v.se = (s && e) ? (double)x[p - N1 + 1] : 0.0;
+    v.nw = (nn && w) ? (double)x[p + N1 - 1] : 0.0;
+    v.ne = (nn && e) ? (double)x[p + N1 + 1] : 0.0;
     return v;
 }
 
@@ -83,12 +85,12 @@ __device__ __forceinline__ T var_stiff(const T* __restrict__ c, int n, int ix, i
 // (A X)_j at interior node (ix, iy) for one (member, t) block X [j][node]:
 //   c0 K_unit X_j + sum_{k in mask} K_k (g- X_{j-e_k} + g+ X_{j+e_k})
 template <typename T>
-__device__ __forceinline__ T sg_node(const T* __restrict__ X, int64_t nodes, int j, int n, int ix, int iy,
-                                     int M, const int32_t* __restrict__ nidx,
-                                     const double* __restrict__ nval, const T* __restrict__ coef,
-                                     int64_t cplane, T c0, bool with_mean, uint32_t mask,
-                                     bool lower, bool upper) {
-    T acc = T(0);
+__device__ __forceinline__ double sg_node(const T* __restrict__ X, int64_t nodes, int j, int n, int ix, int iy,
+                                          int M, const int32_t* __restrict__ nidx,
+                                          const double* __restrict__ nval, const double* __restrict__ coef,
+                                          int64_t cplane, double c0, bool with_mean, uint32_t mask,
+                                          bool lower, bool upper) {
+    double acc = 0.0;
     if (with_mean) acc = c0 * unit_stiff(load9(X + (int64_t)j * nodes, n, ix, iy));
     for (int k = 1; k <= M; ++k) {
         if (!((mask >> (k - 1)) & 1u)) continue;
@@ -96,12 +98,12 @@ __device__ __forceinline__ T sg_node(const T* __restrict__ X, int64_t nodes, int
         const int im = lower ? nidx[base] : -1;
         const int ip = upper ? nidx[base + 1] : -1;
         if (im < 0 && ip < 0) continue;
-        Nine<T> w;
+        Nine<double> w;
         if (im >= 0) {
-            w = scale9(T(nval[base]), load9(X + (int64_t)im * nodes, n, ix, iy));
-            if (ip >= 0) axpy9(w, T(nval[base + 1]), load9(X + (int64_t)ip * nodes, n, ix, iy));
+            w = scale9(nval[base], load9(X + (int64_t)im * nodes, n, ix, iy));
+            if (ip >= 0) axpy9(w, nval[base + 1], load9(X + (int64_t)ip * nodes, n, ix, iy));
         } else {
-            w = scale9(T(nval[base + 1]), load9(X + (int64_t)ip * nodes, n, ix, iy));
+            w = scale9(nval[base + 1], load9(X + (int64_t)ip * nodes, n, ix, iy));
         }
         acc += var_stiff(coef + (int64_t)k * cplane, n, ix, iy, w);
     }
@@ -135,19 +137,19 @@ __global__ __launch_bounds__(256) void k_sg_apply(int n, int M, int nxi, int nt,
     const int64_t off = (int64_t)slice * nxi * nodes;
     const T* X = x + off;
     T* Y = y + off;
-    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const double* coef = op.coef64 + (int64_t)mem * op.coef_mstride;
     const int64_t cplane = (int64_t)n * n;
-    const T c0 = T(op.mem[mem].c0);
+    const double c0 = op.mem[mem].c0;
     const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
     const int64_t p = (int64_t)iy * (n + 1) + ix;
     const int j0 = blockIdx.y * kJChunk;
     const int j1 = min(nxi, j0 + kJChunk);
     for (int j = j0; j < j1; ++j) {
-        T v = T(0);
+        double v = 0.0;
         if (interior)
             v = sg_node<T>(X, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0, true,
                            0xffffffffu, true, true);
-        Y[(int64_t)j * nodes + p] = v;
+        Y[(int64_t)j * nodes + p] = (T)v;
     }
 }
 
@@ -179,17 +181,17 @@ __global__ __launch_bounds__(256) void k_kkt_apply(int n, int M, int nxi, int nt
     T* RU = RY + blk;
     T* RL = RU + blk;
     const MemberDev md = op.mem[mem];
-    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const double* coef = op.coef64 + (int64_t)mem * op.coef_mstride;
     const int64_t cplane = (int64_t)n * n;
-    const T c0 = T(md.c0);
-    const T h = T(1) / T(n);
-    const T h2_36 = h * h / T(36);
+    const double c0 = md.c0;
+    const double h = 1.0 / (double)n;
+    const double h2_36 = h * h / 36.0;
     const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
     const int64_t p = (int64_t)iy * (n + 1) + ix;
-    const T tau = T(md.tau);
-    const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
-    const T beta = T(md.beta);
-    const T hg = T(md.hg);
+    const double tau = md.tau;
+    const double Dt = (time && (t == 0 || t == nt - 1)) ? 0.5 : 1.0;
+    const double beta = md.beta;
+    const double hg = md.hg;
     const int j0 = blockIdx.y * kJChunk;
     const int j1 = min(nxi, j0 + kJChunk);
     const T* Yt = Yv + t * tst;
@@ -197,22 +199,22 @@ __global__ __launch_bounds__(256) void k_kkt_apply(int n, int M, int nxi, int nt
     const T* Lt = Lv + t * tst;
     for (int j = j0; j < j1; ++j) {
         const int64_t q = (int64_t)j * nodes + p;
-        T ry = T(0), ru = T(0), rl = T(0);
+        double ry = 0.0, ru = 0.0, rl = 0.0;
         if (interior) {
-            const T AY = sg_node<T>(Yt, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0,
-                                    true, 0xffffffffu, true, true);
-            const T AL = sg_node<T>(Lt, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0,
-                                    true, 0xffffffffu, true, true);
-            const T MY = mass9(load9(Yt + (int64_t)j * nodes, n, ix, iy), h2_36);
-            const T MU = mass9(load9(Ut + (int64_t)j * nodes, n, ix, iy), h2_36);
-            const T ML = mass9(load9(Lt + (int64_t)j * nodes, n, ix, iy), h2_36);
-            const T hgj = j == 0 ? T(1) : hg;
+            const double AY = sg_node<T>(Yt, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0,
+                                         true, 0xffffffffu, true, true);
+            const double AL = sg_node<T>(Lt, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0,
+                                         true, 0xffffffffu, true, true);
+            const double MY = mass9(load9(Yt + (int64_t)j * nodes, n, ix, iy), h2_36);
+            const double MU = mass9(load9(Ut + (int64_t)j * nodes, n, ix, iy), h2_36);
+            const double ML = mass9(load9(Lt + (int64_t)j * nodes, n, ix, iy), h2_36);
+            const double hgj = j == 0 ? 1.0 : hg;
             if (!time) {
                 ry = hgj * MY - AL;
                 ru = beta * MU + ML;
                 rl = MU - AY;
             } else {
-                T MLn = T(0), MYp = T(0);
+                double MLn = 0.0, MYp = 0.0;
                 if (t + 1 < nt) MLn = mass9(load9(Lt + tst + (int64_t)j * nodes, n, ix, iy), h2_36);
                 if (t > 0) MYp = mass9(load9(Yt - tst + (int64_t)j * nodes, n, ix, iy), h2_36);
                 ry = tau * Dt * hgj * MY - (ML + tau * AL) + MLn;
@@ -220,9 +222,9 @@ __global__ __launch_bounds__(256) void k_kkt_apply(int n, int M, int nxi, int nt
                 rl = -(MY + tau * AY) + MYp + tau * MU;
             }
         }
-        RY[t * tst + q] = ry;
-        RU[t * tst + q] = ru;
-        RL[t * tst + q] = rl;
+        RY[t * tst + q] = (T)ry;
+        RU[t * tst + q] = (T)ru;
+        RL[t * tst + q] = (T)rl;
     }
 }
 
@@ -244,9 +246,9 @@ __global__ __launch_bounds__(256) void k_hgs_rhs(int n, int M, int nxi, int nt, 
     const int mem_i = slice / nt;
     const int t = slice % nt;
     const int mem = op.mem_shared ? 0 : mem_i;
-    const T* coef = (const T*)op.coef + (int64_t)mem * op.coef_mstride;
+    const double* coef = op.coef64 + (int64_t)mem * op.coef_mstride;
     const int64_t cplane = (int64_t)n * n;
-    const T scale = T(op.mem[mem].off_scale);
+    const double scale = op.mem[mem].off_scale;
     const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
     const int64_t p = (int64_t)iy * (n + 1) + ix;
     const T* Vb = V + (int64_t)mem_i * vmap.mstride + (int64_t)t * vmap.tstride;
@@ -255,14 +257,14 @@ __global__ __launch_bounds__(256) void k_hgs_rhs(int n, int M, int nxi, int nt, 
     for (int l = l0; l < l1; ++l) {
         const int c = slice * L + l;
         const int j = j0lvl + l;
-        T v = T(0);
+        double v = 0.0;
         if (interior) {
-            v = base[bmap.off(c) + p];
+            v = (double)base[bmap.off(c) + p];
             if (mask)
                 v -= scale * sg_node<T>(Vb, vmap.nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane,
-                                        T(0), false, mask, lower != 0, upper != 0);
+                                        0.0, false, mask, lower != 0, upper != 0);
         }
-        out[omap.off(c) + p] = v;
+        out[omap.off(c) + p] = (T)v;
     }
 }
 
@@ -301,7 +303,7 @@ __global__ __launch_bounds__(256) void k_mass_cheb_step(int n, int nxi, int nt, 
             if (first) {
                 v = dinv * b;
             } else {
-                const T res = b - mass9(load9(xk + ((int64_t)vec * ncols + l) * nodes, n, ix, iy), h2_36);
+                const T res = b - (T)mass9(load9(xk + ((int64_t)vec * ncols + l) * nodes, n, ix, iy), (double)h2_36);
                 v = omega * (dinv * res + xk[qs] - xkm1[qs]) + xkm1[qs];
             }
             if (last) {
@@ -638,44 +640,84 @@ __global__ __launch_bounds__(RB) void k_cgs_update_norm(const double* __restrict
 // by an estimate of its norm) and is never rewritten: the orthonormal basis is
 // V = U R^{-1}, applied through R by the bookkeeping kernel (k_dcgs_finish).
 //
-#ifndef SG_DOTS_U
-#define SG_DOTS_U 4
-#endif
-#ifndef SG_UPD_U
-#define SG_UPD_U 8
-#endif
-constexpr int kDotsU = SG_DOTS_U;   // elements per lane per trip, dots pass
-constexpr int kUpdU = SG_UPD_U;     // elements per lane per trip, update pass
+constexpr int kDotsU = 4;   // 16-byte groups per lane per trip, dots pass
+constexpr int kUpdU = 8;    // 16-byte groups per lane per trip, update pass
 
-// Element pairs (2p, 2p+1) of a member's vector, counted from the member's
-// first element: with AL the pair is 16-byte aligned and read by one load,
-// else by two 8-byte loads (same arithmetic either way, so a member's sums do
-// not depend on where the batch places it).
+// The basis (and w) are stored in TV = double or float; every product and
+// sum is formed in double.  A member's vector is read in 16-byte groups of
+// GW = 16 / sizeof(TV) consecutive elements, counted from the member's first
+// element: with AL the group is 16-byte aligned and read by one load, else
+// element by element (same arithmetic either way, so a member's sums do not
+// depend on where the batch places it).  A group is held as GW doubles.
+template <typename TV>
+struct Grp {
+    static constexpr int GW = 16 / (int)sizeof(TV);
+    double v[GW];
+};
 typedef double dbl2 __attribute__((ext_vector_type(2)));
-template <bool AL, bool NT>
-__device__ __forceinline__ dbl2 ld_pair(const double* base, int64_t p) {
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <bool AL, bool NT, typename TV>
+__device__ __forceinline__ Grp<TV> ld_grp(const TV* base, int64_t p) {
+    Grp<TV> g;
+    constexpr int GW = Grp<TV>::GW;
     if (AL) {
-        const dbl2* q = reinterpret_cast<const dbl2*>(base) + p;
-        return NT ? __builtin_nontemporal_load(q) : *q;
+        if constexpr (sizeof(TV) == 8) {
+            const dbl2* q = reinterpret_cast<const dbl2*>(base) + p;
+            const dbl2 x = NT ? __builtin_nontemporal_load(q) : *q;
+            g.v[0] = x.x;
+            g.v[1] = x.y;
+        } else {
+            const flt4* q = reinterpret_cast<const flt4*>(base) + p;
+            const flt4 x = NT ? __builtin_nontemporal_load(q) : *q;
+            g.v[0] = x.x;
+            g.v[1] = x.y;
+            g.v[2] = x.z;
+            g.v[3] = x.w;
+        }
+    } else {
+        const TV* q = base + GW * p;
+#pragma unroll
+        for (int u = 0; u < GW; ++u) g.v[u] = (double)(NT ? __builtin_nontemporal_load(q + u) : q[u]);
     }
-    const double* q = base + 2 * p;
-    return NT ? dbl2{__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1)} : dbl2{q[0], q[1]};
+    return g;
+}
+template <bool AL, typename TV>
+__device__ __forceinline__ void st_grp(TV* base, int64_t p, const Grp<TV>& g) {
+    constexpr int GW = Grp<TV>::GW;
+    if (AL) {
+        if constexpr (sizeof(TV) == 8)
+            reinterpret_cast<dbl2*>(base)[p] = dbl2{g.v[0], g.v[1]};
+        else
+            reinterpret_cast<flt4*>(base)[p] = flt4{(float)g.v[0], (float)g.v[1], (float)g.v[2], (float)g.v[3]};
+    } else {
+#pragma unroll
+        for (int u = 0; u < GW; ++u) base[GW * p + u] = (TV)g.v[u];
+    }
+}
+template <typename TV>
+__device__ __forceinline__ double grp_dot(const Grp<TV>& a, const Grp<TV>& b) {
+    double s = a.v[0] * b.v[0];
+#pragma unroll
+    for (int u = 1; u < Grp<TV>::GW; ++u) s += a.v[u] * b.v[u];
+    return s;
 }
 
 // Dots pass, with w: slots [0, nv) a_i = V_i.u, [nv, 2nv) t_i = V_i.w,
 // 2nv: u.u, 2nv+1: u.w, 2nv+2: w.w; without w: [0, nv) a_i, nv: u.u.
 // u is basis slot nv.  The block's four wavefronts split the basis vectors
 // (vector i goes to wavefront i mod 4, at most NPW each) and each walks the
-// block's whole chunk of element pairs, so a lane carries at most 2 NPW + 1
+// block's whole chunk of element groups, so a lane carries at most 2 NPW + 1
 // sums and keeps many loads in flight; u and w are re-read by the four
 // wavefronts from cache.  Members with neither flag set are skipped.
-template <int NPW, bool WITH_W, bool AL>
-__device__ __forceinline__ void dcgs_dots_body(const double* __restrict__ V, int64_t vstride, int nv,
-                                               const double* __restrict__ w, int64_t n, int64_t mstride,
+template <int NPW, bool WITH_W, bool AL, typename TV>
+__device__ __forceinline__ void dcgs_dots_body(const TV* __restrict__ V, int64_t vstride, int nv,
+                                               const TV* __restrict__ w, int64_t n, int64_t mstride,
                                                double* __restrict__ partial, int nblk) {
+    constexpr int GW = Grp<TV>::GW;
     const int mem = blockIdx.y;
     int64_t lo, hi;
-    chunk_range(n / 2, nblk, blockIdx.x, lo, hi);      // pair range
+    chunk_range(n / GW, nblk, blockIdx.x, lo, hi);      // group range
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     // the wavefront's scalar product: wave 1 u.u (also without w), wave 2 u.w, wave 3 w.w
@@ -684,23 +726,23 @@ __device__ __forceinline__ void dcgs_dots_body(const double* __restrict__ V, int
     double acc[NA];
 #pragma unroll
     for (int i = 0; i < NA; ++i) acc[i] = 0.0;
-    const double* Vm = V + mem * mstride;
-    const double* um = Vm + nv * vstride;
-    const double* wm = w + mem * mstride;
-    auto add = [&](const dbl2* ue, const dbl2* we, int64_t p, int cnt) {
+    const TV* Vm = V + mem * mstride;
+    const TV* um = Vm + nv * vstride;
+    const TV* wm = WITH_W ? w + mem * mstride : um;
+    auto add = [&](const Grp<TV>* ue, const Grp<TV>* we, int cnt) {
         for (int u = 0; u < cnt; ++u) {
-            if (sdot == 1) acc[NA - 1] += ue[u].x * ue[u].x + ue[u].y * ue[u].y;
-            if (WITH_W && sdot == 2) acc[NA - 1] += ue[u].x * we[u].x + ue[u].y * we[u].y;
-            if (WITH_W && sdot == 3) acc[NA - 1] += we[u].x * we[u].x + we[u].y * we[u].y;
+            if (sdot == 1) acc[NA - 1] += grp_dot(ue[u], ue[u]);
+            if (WITH_W && sdot == 2) acc[NA - 1] += grp_dot(ue[u], we[u]);
+            if (WITH_W && sdot == 3) acc[NA - 1] += grp_dot(we[u], we[u]);
         }
     };
     int64_t p = lo + lane;
     for (; p + (kDotsU - 1) * 64 < hi; p += kDotsU * 64) {
-        dbl2 ue[kDotsU], we[kDotsU];
+        Grp<TV> ue[kDotsU], we[kDotsU];
 #pragma unroll
         for (int u = 0; u < kDotsU; ++u) {
-            ue[u] = ld_pair<AL, false>(um, p + u * 64);
-            we[u] = WITH_W ? ld_pair<AL, false>(wm, p + u * 64) : dbl2{0.0, 0.0};
+            ue[u] = ld_grp<AL, false>(um, p + u * 64);
+            if (WITH_W) we[u] = ld_grp<AL, false>(wm, p + u * 64);
         }
 #pragma unroll
         for (int k = 0; k < NPW; ++k) {
@@ -708,43 +750,45 @@ __device__ __forceinline__ void dcgs_dots_body(const double* __restrict__ V, int
             if (i < nv) {
 #pragma unroll
                 for (int u = 0; u < kDotsU; ++u) {
-                    const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p + u * 64);
-                    acc[k] += v.x * ue[u].x + v.y * ue[u].y;
-                    if (WITH_W) acc[NPW + k] += v.x * we[u].x + v.y * we[u].y;
+                    const Grp<TV> v = ld_grp<AL, true>(Vm + i * vstride, p + u * 64);
+                    acc[k] += grp_dot(v, ue[u]);
+                    if (WITH_W) acc[NPW + k] += grp_dot(v, we[u]);
                 }
             }
         }
-        add(ue, we, p, kDotsU);
+        add(ue, we, kDotsU);
     }
     for (; p < hi; p += 64) {
-        const dbl2 ue = ld_pair<AL, false>(um, p);
-        const dbl2 we = WITH_W ? ld_pair<AL, false>(wm, p) : dbl2{0.0, 0.0};
+        Grp<TV> ue = ld_grp<AL, false>(um, p), we;
+        if (WITH_W) we = ld_grp<AL, false>(wm, p);
 #pragma unroll
         for (int k = 0; k < NPW; ++k) {
             const int i = wave + 4 * k;
             if (i < nv) {
-                const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p);
-                acc[k] += v.x * ue.x + v.y * ue.y;
-                if (WITH_W) acc[NPW + k] += v.x * we.x + v.y * we.y;
+                const Grp<TV> v = ld_grp<AL, true>(Vm + i * vstride, p);
+                acc[k] += grp_dot(v, ue);
+                if (WITH_W) acc[NPW + k] += grp_dot(v, we);
             }
         }
-        add(&ue, &we, p, 1);
+        add(&ue, &we, 1);
     }
-    if ((n & 1) && blockIdx.x == nblk - 1 && lane == 0) {   // odd length: the last element
-        const int64_t e = n - 1;
-        const double ue = um[e], we = WITH_W ? wm[e] : 0.0;
+    // the n mod GW last elements, by lane 0 of the last block
+    if (blockIdx.x == nblk - 1 && lane == 0) {
+        for (int64_t e = (n / GW) * GW; e < n; ++e) {
+            const double ue = (double)um[e], we = WITH_W ? (double)wm[e] : 0.0;
 #pragma unroll
-        for (int k = 0; k < NPW; ++k) {
-            const int i = wave + 4 * k;
-            if (i < nv) {
-                const double v = Vm[i * vstride + e];
-                acc[k] += v * ue;
-                if (WITH_W) acc[NPW + k] += v * we;
+            for (int k = 0; k < NPW; ++k) {
+                const int i = wave + 4 * k;
+                if (i < nv) {
+                    const double v = (double)Vm[i * vstride + e];
+                    acc[k] += v * ue;
+                    if (WITH_W) acc[NPW + k] += v * we;
+                }
             }
+            if (sdot == 1) acc[NA - 1] += ue * ue;
+            if (WITH_W && sdot == 2) acc[NA - 1] += ue * we;
+            if (WITH_W && sdot == 3) acc[NA - 1] += we * we;
         }
-        if (sdot == 1) acc[NA - 1] += ue * ue;
-        if (WITH_W && sdot == 2) acc[NA - 1] += ue * we;
-        if (WITH_W && sdot == 3) acc[NA - 1] += we * we;
     }
     double* pm = partial + (int64_t)mem * kSlots * nblk + blockIdx.x;
 #pragma unroll
@@ -766,20 +810,22 @@ __device__ __forceinline__ void dcgs_dots_body(const double* __restrict__ V, int
     }
 }
 
-// 16-byte pair loads need the member's first element and the basis slot
-// stride to be even (allocations are 256-byte aligned).
-__device__ __forceinline__ bool pairs_aligned(int64_t vstride, int64_t mstride) {
-    return ((blockIdx.y * mstride) & 1) == 0 && (vstride & 1) == 0;
+// 16-byte group loads need the member's first element and the basis slot
+// stride to be multiples of the group (allocations are 256-byte aligned).
+template <typename TV>
+__device__ __forceinline__ bool groups_aligned(int64_t vstride, int64_t mstride) {
+    constexpr int GW = Grp<TV>::GW;
+    return ((blockIdx.y * mstride) % GW) == 0 && (vstride % GW) == 0;
 }
 
-template <int NPW, bool WITH_W>
-__global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, int64_t vstride, int nv,
-                                                  const double* __restrict__ w, int64_t n, int64_t mstride,
+template <int NPW, bool WITH_W, typename TV>
+__global__ __launch_bounds__(RB) void k_dcgs_dots(const TV* __restrict__ V, int64_t vstride, int nv,
+                                                  const TV* __restrict__ w, int64_t n, int64_t mstride,
                                                   const int* __restrict__ active, const int* __restrict__ pending,
                                                   double* __restrict__ partial, int nblk) {
     const int mem = blockIdx.y;
     if (!active[mem] && !pending[mem]) return;
-    if (pairs_aligned(vstride, mstride))
+    if (groups_aligned<TV>(vstride, mstride))
         dcgs_dots_body<NPW, WITH_W, true>(V, vstride, nv, w, n, mstride, partial, nblk);
     else
         dcgs_dots_body<NPW, WITH_W, false>(V, vstride, nv, w, n, mstride, partial, nblk);
@@ -787,74 +833,74 @@ __global__ __launch_bounds__(RB) void k_dcgs_dots(const double* __restrict__ V, 
 
 // Update pass: basis slot nv+1 = (w - sum_{i<=nv} s_i U_i) / nu with
 // s_i = coef[mem*kSlots + i] and 1/nu = scal[mem*4 + 2]; reads slots 0..nv and
-// w, writes slot nv+1 only.  NT >= nv + 1 terms; element pairs as above.
-template <int NT, bool AL>
-__device__ __forceinline__ void dcgs_update_body(double* __restrict__ V, int64_t vstride, int nv,
-                                                 const double* __restrict__ w, int64_t n, int64_t mstride,
+// w, writes slot nv+1 only.  NT >= nv + 1 terms; element groups as above.
+template <int NT, bool AL, typename TV>
+__device__ __forceinline__ void dcgs_update_body(TV* __restrict__ V, int64_t vstride, int nv,
+                                                 const TV* __restrict__ w, int64_t n, int64_t mstride,
                                                  const double* sv, double inv_nu, int nblk) {
+    constexpr int GW = Grp<TV>::GW;
     const int mem = blockIdx.y;
-    const double* Vm = V + mem * mstride;
-    double* un = V + mem * mstride + (nv + 1) * vstride;
-    const double* wm = w + mem * mstride;
-    auto store = [&](int64_t p, dbl2 v) {
-        if (AL)
-            reinterpret_cast<dbl2*>(un)[p] = v;
-        else {
-            un[2 * p] = v.x;
-            un[2 * p + 1] = v.y;
-        }
-    };
-    // Trips of kUpdU * RB element pairs are dealt to the blocks in turn (trip
+    const TV* Vm = V + mem * mstride;
+    TV* un = V + mem * mstride + (nv + 1) * vstride;
+    const TV* wm = w + mem * mstride;
+    // Trips of kUpdU * RB element groups are dealt to the blocks in turn (trip
     // t to block t mod nblk), so the blocks in flight stream one contiguous
     // window of every basis vector rather than nblk separate chunks of each
     // (far fewer pages in use at once on large vectors).  No reduction here:
     // each element's arithmetic is the same whatever block computes it.
-    const int64_t npair = n / 2;
+    const int64_t ngrp = n / GW;
     constexpr int64_t TRIP = (int64_t)kUpdU * RB;
     int64_t base = (int64_t)blockIdx.x * TRIP;
-    for (; base + TRIP <= npair; base += (int64_t)nblk * TRIP) {
+    for (; base + TRIP <= ngrp; base += (int64_t)nblk * TRIP) {
         const int64_t p = base + threadIdx.x;
-        dbl2 acc[kUpdU];
+        Grp<TV> acc[kUpdU];
 #pragma unroll
-        for (int u = 0; u < kUpdU; ++u) acc[u] = ld_pair<AL, true>(wm, p + u * RB);
+        for (int u = 0; u < kUpdU; ++u) acc[u] = ld_grp<AL, true>(wm, p + u * RB);
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
             if (i <= nv) {
 #pragma unroll
                 for (int u = 0; u < kUpdU; ++u) {
-                    const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p + u * RB);
-                    acc[u].x -= sv[i] * v.x;
-                    acc[u].y -= sv[i] * v.y;
+                    const Grp<TV> v = ld_grp<AL, true>(Vm + i * vstride, p + u * RB);
+#pragma unroll
+                    for (int e = 0; e < GW; ++e) acc[u].v[e] -= sv[i] * v.v[e];
                 }
             }
         }
 #pragma unroll
-        for (int u = 0; u < kUpdU; ++u) store(p + u * RB, dbl2{acc[u].x * inv_nu, acc[u].y * inv_nu});
+        for (int u = 0; u < kUpdU; ++u) {
+#pragma unroll
+            for (int e = 0; e < GW; ++e) acc[u].v[e] *= inv_nu;
+            st_grp<AL>(un, p + u * RB, acc[u]);
+        }
     }
     // the partial last trip, if any, falls to exactly one block
-    for (int64_t p = base + threadIdx.x; p < npair; p += RB) {
-        dbl2 acc = ld_pair<AL, true>(wm, p);
+    for (int64_t p = base + threadIdx.x; p < ngrp; p += RB) {
+        Grp<TV> acc = ld_grp<AL, true>(wm, p);
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
             if (i <= nv) {
-                const dbl2 v = ld_pair<AL, true>(Vm + i * vstride, p);
-                acc.x -= sv[i] * v.x;
-                acc.y -= sv[i] * v.y;
+                const Grp<TV> v = ld_grp<AL, true>(Vm + i * vstride, p);
+#pragma unroll
+                for (int e = 0; e < GW; ++e) acc.v[e] -= sv[i] * v.v[e];
             }
         }
-        store(p, dbl2{acc.x * inv_nu, acc.y * inv_nu});
+#pragma unroll
+        for (int e = 0; e < GW; ++e) acc.v[e] *= inv_nu;
+        st_grp<AL>(un, p, acc);
     }
-    if ((n & 1) && blockIdx.x == nblk - 1 && threadIdx.x == 0) {   // odd length: the last element
-        const int64_t e = n - 1;
-        double acc = wm[e];
-        for (int i = 0; i <= nv; ++i) acc -= sv[i] * Vm[i * vstride + e];
-        un[e] = acc * inv_nu;
+    if (blockIdx.x == nblk - 1 && threadIdx.x == 0) {   // the n mod GW last elements
+        for (int64_t e = ngrp * GW; e < n; ++e) {
+            double acc = (double)wm[e];
+            for (int i = 0; i <= nv; ++i) acc -= sv[i] * (double)Vm[i * vstride + e];
+            un[e] = (TV)(acc * inv_nu);
+        }
     }
 }
 
-template <int NT>
-__global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int64_t vstride, int nv,
-                                                    const double* __restrict__ w, int64_t n, int64_t mstride,
+template <int NT, typename TV>
+__global__ __launch_bounds__(RB) void k_dcgs_update(TV* __restrict__ V, int64_t vstride, int nv,
+                                                    const TV* __restrict__ w, int64_t n, int64_t mstride,
                                                     const double* __restrict__ coef, const double* __restrict__ scal,
                                                     const int* __restrict__ active, int nblk) {
     const int mem = blockIdx.y;
@@ -863,7 +909,7 @@ __global__ __launch_bounds__(RB) void k_dcgs_update(double* __restrict__ V, int6
     if ((int)threadIdx.x < NT) sv[threadIdx.x] = (int)threadIdx.x <= nv ? coef[mem * kSlots + threadIdx.x] : 0.0;
     __syncthreads();
     const double inv_nu = scal[mem * 4 + 2];
-    if (pairs_aligned(vstride, mstride))
+    if (groups_aligned<TV>(vstride, mstride))
         dcgs_update_body<NT, true>(V, vstride, nv, w, n, mstride, sv, inv_nu, nblk);
     else
         dcgs_update_body<NT, false>(V, vstride, nv, w, n, mstride, sv, inv_nu, nblk);
@@ -893,11 +939,12 @@ __global__ void k_scale_vec(double* v, const double* sdev, int sstride, int64_t 
         vm[e] *= s;
 }
 
-__global__ void k_copy_scale(const double* src, double* dst, const double* s, int64_t n, int64_t mstride) {
+template <typename TD>
+__global__ void k_copy_scale(const double* src, TD* dst, const double* s, int64_t n, int64_t mstride) {
     const int mem = blockIdx.y;
     const double f = s[mem];
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        dst[mem * mstride + e] = f * src[mem * mstride + e];
+        dst[mem * mstride + e] = (TD)(f * src[mem * mstride + e]);
 }
 
 // x += sum_{i < nv_mem[mem]} y_i Z_i
@@ -1299,6 +1346,15 @@ void launch_mg_coarse<float>(const float* ainv, const float* bc, ColMap bmap, fl
 }
 
 template <typename T>
+void launch_fill_zero(T* x, int64_t count, hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_fill_zero<T>, dim3(grid1d(count)), dim3(256), 0, st, x, count);
+    SG_HIP(hipGetLastError());
+}
+template void launch_fill_zero<double>(double*, int64_t, hipStream_t);
+template void launch_fill_zero<float>(float*, int64_t, hipStream_t);
+
+template <typename T>
 void launch_zero_ring(T* x, int n, int64_t ncols, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_ring<T>, dim3(grid1d(4 * (int64_t)n * ncols)), dim3(256), 0, st, x, n, ncols);
     SG_HIP(hipGetLastError());
@@ -1341,14 +1397,14 @@ void launch_cgs_update_norm(const double* V, int64_t vstride, int nv, const doub
     SG_HIP(hipGetLastError());
 }
 
-void launch_dcgs_dots(const double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem,
-                      int64_t mstride, const int* active, const int* pending, double* partial, int nblk,
-                      hipStream_t st) {
+template <typename TV>
+void launch_dcgs_dots(const TV* V, int64_t vstride, int nv, const TV* w, int64_t n, int nmem, int64_t mstride,
+                      const int* active, const int* pending, double* partial, int nblk, hipStream_t st) {
     if (nv > (w ? MAXV - 2 : MAXV)) throw Error(SG_ERR_INVALID, "dcgs: too many vectors");
     const dim3 g(nblk, nmem), b(RB);
-#define SG_DOTS(NPW, WW)                                                                                        \
-    hipLaunchKernelGGL((k_dcgs_dots<NPW, WW>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending, partial, \
-                       nblk)
+#define SG_DOTS(NPW, WW)                                                                                            \
+    hipLaunchKernelGGL((k_dcgs_dots<NPW, WW, TV>), g, b, 0, st, V, vstride, nv, w, n, mstride, active, pending,     \
+                       partial, nblk)
     if (w) {
         if (nv <= 4) SG_DOTS(1, true);
         else if (nv <= 8) SG_DOTS(2, true);
@@ -1364,13 +1420,29 @@ void launch_dcgs_dots(const double* V, int64_t vstride, int nv, const double* w,
     SG_HIP(hipGetLastError());
 }
 
-void launch_dcgs_update(double* V, int64_t vstride, int nv, const double* w, int64_t n, int nmem, int64_t mstride,
+template <typename TV>
+void launch_dcgs_update(TV* V, int64_t vstride, int nv, const TV* w, int64_t n, int nmem, int64_t mstride,
                         const double* coef, const double* scal, const int* active, int nblk, hipStream_t st) {
     if (nv > MAXV - 2) throw Error(SG_ERR_INVALID, "dcgs: too many vectors");
-    SG_NV_DISPATCH(k_dcgs_update, nv + 1, dim3(nblk, nmem), dim3(RB), 0, st, V, vstride, nv, w, n, mstride, coef, scal,
-                   active, nblk);
+    const dim3 g(nblk, nmem), b(RB);
+    const int nt = nv + 1;
+#define SG_UPD(NT) hipLaunchKernelGGL((k_dcgs_update<NT, TV>), g, b, 0, st, V, vstride, nv, w, n, mstride, coef, scal, \
+                                      active, nblk)
+    if (nt <= 4) SG_UPD(4);
+    else if (nt <= 8) SG_UPD(8);
+    else if (nt <= 16) SG_UPD(16);
+    else SG_UPD(32);
+#undef SG_UPD
     SG_HIP(hipGetLastError());
 }
+template void launch_dcgs_dots<double>(const double*, int64_t, int, const double*, int64_t, int, int64_t, const int*,
+                                       const int*, double*, int, hipStream_t);
+template void launch_dcgs_dots<float>(const float*, int64_t, int, const float*, int64_t, int, int64_t, const int*,
+                                      const int*, double*, int, hipStream_t);
+template void launch_dcgs_update<double>(double*, int64_t, int, const double*, int64_t, int, int64_t, const double*,
+                                         const double*, const int*, int, hipStream_t);
+template void launch_dcgs_update<float>(float*, int64_t, int, const float*, int64_t, int, int64_t, const double*,
+                                        const double*, const int*, int, hipStream_t);
 
 void launch_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem, hipStream_t st) {
     if (restart > 31) throw Error(SG_ERR_INVALID, "dcgs: restart above 31");
@@ -1391,11 +1463,15 @@ void launch_scale_vec(double* v, const double* sdev, int sstride, int64_t n, int
     SG_HIP(hipGetLastError());
 }
 
-void launch_copy_scale_rows(const double* src, double* dst, const double* inv_norm, int64_t n, int nmem,
-                            int64_t mstride, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy_scale, dim3(grid1d(n), nmem), dim3(256), 0, st, src, dst, inv_norm, n, mstride);
+template <typename TD>
+void launch_copy_scale_rows(const double* src, TD* dst, const double* inv_norm, int64_t n, int nmem, int64_t mstride,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_scale<TD>, dim3(grid1d(n), nmem), dim3(256), 0, st, src, dst, inv_norm, n, mstride);
     SG_HIP(hipGetLastError());
 }
+template void launch_copy_scale_rows<double>(const double*, double*, const double*, int64_t, int, int64_t,
+                                             hipStream_t);
+template void launch_copy_scale_rows<float>(const double*, float*, const double*, int64_t, int, int64_t, hipStream_t);
 
 void launch_multi_axpy(const void* Z, int zfp32, int64_t zstride, int nv_max, const int* nv_mem, const double* y,
                        int ystride, double* x, int64_t n, int nmem, int64_t mstride, hipStream_t st) {

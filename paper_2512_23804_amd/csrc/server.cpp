@@ -44,11 +44,14 @@ size_t footprint_bytes(const sg_problem& p, const sg_options& o) {
     const double blk = nxi * nodes;
     const double N = 3 * blk;
     const int m = o.restart;
-    const double sz = o.precision == SG_PREC_FP64 ? 8.0 : 4.0;
-    double bytes = 8.0 * N * (m + 1) + sz * N * m + 8.0 * N * 6;   // V, Z, w/r/b/x/d staging
-    // preconditioner scratch: Chebyshev 4 blocks, Schur 2, hGS 1, multigrid ~4 of the widest level
-    bytes += sz * blk * 7 + sz * 4 * nodes * 1.4 * nxi * 0.6;
-    if (o.precision == SG_PREC_FP32_REFINE) bytes += 4.0 * N * 2 + 8.0 * N * (m + 1) + 8.0 * N * m;  // FP64 fallback basis
+    const bool refine = o.precision == SG_PREC_FP32_REFINE;
+    const bool v32 = refine && o.basis_fp32 && o.arnoldi == SG_ARNOLDI_DCGS2;
+    const double sz = o.precision == SG_PREC_FP64 ? 8.0 : 4.0;       // Z and preconditioner scratch
+    double bytes = (v32 ? 4.0 : 8.0) * N * (m + 1) + sz * N * m;      // basis V, preconditioned vectors Z
+    bytes += 8.0 * N * (v32 ? 5 : 6);                                 // FP64 b, x, r (+ w), refinement r, d
+    // preconditioner scratch: Schur 2 blocks, hGS 1, multigrid ~0.6 of the widest degree level at 1.4 nodes
+    bytes += sz * blk * 3 + sz * 4 * nodes * 1.4 * nxi * 0.6;
+    if (refine) bytes += 4.0 * N * (v32 ? 2 : 3);                      // FP32 operator output and staging
     if (o.precision == SG_PREC_FP32_PRECOND) bytes += 4.0 * N + 8.0 * N;   // FP32 staging, FP64 copy of Z_j
     return (size_t)bytes;
 }
@@ -58,7 +61,7 @@ bool same_shape(const Request& a, const Request& b) {
            a.opt.restart == b.opt.restart && a.opt.max_iter == b.opt.max_iter && a.opt.rtol == b.opt.rtol &&
            a.opt.cheb_steps == b.opt.cheb_steps && a.opt.truncation_r == b.opt.truncation_r &&
            a.opt.gmg_pre == b.opt.gmg_pre && a.opt.gmg_post == b.opt.gmg_post && a.opt.inner_rtol == b.opt.inner_rtol &&
-           a.opt.arnoldi == b.opt.arnoldi;
+           a.opt.arnoldi == b.opt.arnoldi && a.opt.basis_fp32 == b.opt.basis_fp32;
 }
 
 }  // namespace
@@ -83,6 +86,7 @@ struct sg_server {
     Clock::time_point t_first{}, t_last{};
     bool have_first = false;
     std::string worker_error;
+    sg::DevicePool pool;    // device memory of every batch handle (freed when the server is deleted, after the workers joined)
 
     void schedule_loop();
     void worker_loop(int id);
@@ -148,7 +152,7 @@ void sg_server::run_batch(const std::vector<uint64_t>& ids, hipStream_t st) {
     std::vector<sg_solve_info> info(B);
     std::vector<int> status(B, SG_OK);
     try {
-        auto h = sg::build_handle(probs.data(), B, &opt, st);
+        auto h = sg::build_handle(probs.data(), B, &opt, st, &pool);
         const int64_t N = 3 * h->s.blk;
         double* x = h->ws.get_t<double>("serve_x", (size_t)B * N);
         sg::solve(*h, nullptr, x, info.data());

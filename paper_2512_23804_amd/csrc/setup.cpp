@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 
 #include "handle.hpp"
 
@@ -33,6 +34,7 @@ void default_options(sg_options* o) {
     o->profile = SG_PROF_NONE;
     o->arnoldi = SG_ARNOLDI_DCGS2;
     o->sweep_rows = 0;
+    o->basis_fp32 = 1;
 }
 
 // Total-degree multi-indices, degree ascending, descending lexicographic order
@@ -161,6 +163,7 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
         if (opt->profile < SG_PROF_NONE || opt->profile > SG_PROF_MG_UP) fail(SG_ERR_INVALID, "unknown profile kind");
         if (opt->sweep_rows != 0 && opt->sweep_rows != 2 && opt->sweep_rows != 4 && opt->sweep_rows != 8)
             fail(SG_ERR_INVALID, "sweep_rows must be 0 (autotune), 2, 4 or 8");
+        if (opt->basis_fp32 != 0 && opt->basis_fp32 != 1) fail(SG_ERR_INVALID, "basis_fp32 must be 0 or 1");
         if (opt->arnoldi != SG_ARNOLDI_DCGS2 && opt->arnoldi != SG_ARNOLDI_CGS2)
             fail(SG_ERR_INVALID, "arnoldi must be SG_ARNOLDI_DCGS2 or SG_ARNOLDI_CGS2");
         if (opt->precision == SG_PREC_FP32_REFINE && !(opt->inner_rtol > 0 && opt->inner_rtol < 1))
@@ -260,27 +263,67 @@ static void coarse_inverse(double a, double b, double* out) {
         for (int c = 0; c < nu; ++c) out[r * kCoarsePad + c] = I[(size_t)r * nu + c];
 }
 
+// Pinned host staging buffers (4096 doubles) are kept for reuse: the server
+// builds a handle per batch, and pinned allocations are slow.
+namespace {
+std::mutex g_pinned_mu;
+std::vector<double*> g_pinned_free;
+}  // namespace
+
+static double* pinned_get() {
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        if (!g_pinned_free.empty()) {
+            double* p = g_pinned_free.back();
+            g_pinned_free.pop_back();
+            return p;
+        }
+    }
+    double* p = nullptr;
+    SG_HIP(hipHostMalloc((void**)&p, 4096 * sizeof(double), hipHostMallocDefault));
+    return p;
+}
+
+static void pinned_put(double* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (g_pinned_free.size() < 64)
+        g_pinned_free.push_back(p);
+    else
+        (void)hipHostFree(p);
+}
+
 Handle::~Handle() {
     ws.release();
     for (void* p : {(void*)d_nbr_idx, (void*)d_nbr_val, (void*)d_coef64, (void*)d_coef32, (void*)d_mem,
                     (void*)d_lev, (void*)d_ainv64, (void*)d_ainv32, (void*)d_rhs})
-        if (p) (void)hipFree(p);
-    if (h_pinned) (void)hipHostFree(h_pinned);
+        if (p) {
+            if (pool)
+                pool->release(p);
+            else
+                (void)hipFree(p);
+        }
+    pinned_put(h_pinned);
 }
 
 template <typename T>
-static T* upload(const T* src, size_t count) {
+static T* upload(const T* src, size_t count, DevicePool* pool = nullptr) {
     T* d = nullptr;
-    hipError_t e = hipMalloc(&d, std::max<size_t>(count, 1) * sizeof(T));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        throw Error(SG_ERR_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    if (pool) {
+        d = static_cast<T*>(pool->alloc(std::max<size_t>(count, 1) * sizeof(T)));
+    } else {
+        hipError_t e = hipMalloc(&d, std::max<size_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error(SG_ERR_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+        }
     }
-    if (count) SG_HIP(hipMemcpy(d, src, count * sizeof(T), hipMemcpyHostToDevice));
+    if (count && src) SG_HIP(hipMemcpy(d, src, count * sizeof(T), hipMemcpyHostToDevice));
     return d;
 }
 
-std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt_in, hipStream_t st) {
+std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt_in, hipStream_t st,
+                                     DevicePool* pool) {
     auto t0 = std::chrono::steady_clock::now();
     sg_options opt;
     if (opt_in)
@@ -293,6 +336,8 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     h->opt = opt;
     h->B = count;
     h->stream = st;
+    h->pool = pool;
+    h->ws.set_pool(pool);
     SG_HIP(hipGetDevice(&h->device));
     {
         // the fused multigrid tail keeps every level up to 64 intervals per side and
@@ -357,7 +402,8 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     h->lev_host.assign((size_t)count * kMaxLevels, LevelDev{});
     h->ainv_host.resize((size_t)count * kCoarsePad * kCoarsePad);
     const int64_t kkt = 3 * s.blk;
-    h->rhs_host.assign((size_t)count * kkt, 0.0);
+    const size_t rcols = (size_t)2 * s.nt * s.nodes;    // per member: state and adjoint column 0, every t
+    h->rhs_host.assign((size_t)count * rcols, 0.0);
     for (int b = 0; b < count; ++b) {
         const sg_problem& p = probs[b];
         std::vector<double> c = coefficient_modes(p);
@@ -395,7 +441,7 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
 
         // right-hand side: b_y = tau D_t (M_full y_d)_interior in chaos column 0;
         // time with y0: b_lambda(t=0, j=0) = -(M_II y0)
-        double* rb = h->rhs_host.data() + (size_t)b * kkt;
+        double* rb = h->rhs_host.data() + (size_t)b * rcols;
         const double hh = 1.0 / n;
         const double w = hh * hh / 36.0;
         const int N1 = n + 1;
@@ -408,11 +454,11 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
                     const int q = iy * N1 + ix;
                     const double v = 16.0 * yd[q] + 4.0 * (yd[q - 1] + yd[q + 1] + yd[q - N1] + yd[q + N1]) +
                                      (yd[q - N1 - 1] + yd[q - N1 + 1] + yd[q + N1 - 1] + yd[q + N1 + 1]);
-                    rb[(size_t)t * s.tstride + q] = f * w * v;
+                    rb[(size_t)t * s.nodes + q] = f * w * v;
                 }
         }
         if (s.time && p.y0) {
-            double* rl = rb + 2 * s.blk;
+            double* rl = rb + (size_t)s.nt * s.nodes;   // adjoint block, t = 0
             for (int iy = 1; iy < n; ++iy)
                 for (int ix = 1; ix < n; ++ix) {
                     auto y0i = [&](int jx, int jy) {
@@ -428,24 +474,38 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     }
 
     // upload
-    h->d_nbr_idx = upload(h->ht.nbr_idx.data(), h->ht.nbr_idx.size());
-    h->d_nbr_val = upload(h->ht.nbr_val.data(), h->ht.nbr_val.size());
-    h->d_coef64 = upload(h->coef_host.data(), h->coef_host.size());
+    h->d_nbr_idx = upload(h->ht.nbr_idx.data(), h->ht.nbr_idx.size(), pool);
+    h->d_nbr_val = upload(h->ht.nbr_val.data(), h->ht.nbr_val.size(), pool);
+    h->d_coef64 = upload(h->coef_host.data(), h->coef_host.size(), pool);
     {
         std::vector<float> c32(h->coef_host.begin(), h->coef_host.end());
-        h->d_coef32 = upload(c32.data(), c32.size());
+        h->d_coef32 = upload(c32.data(), c32.size(), pool);
     }
-    h->d_mem = upload(h->mem_host.data(), h->mem_host.size());
-    h->d_lev = upload(h->lev_host.data(), h->lev_host.size());
-    h->d_ainv64 = upload(h->ainv_host.data(), h->ainv_host.size());
+    h->d_mem = upload(h->mem_host.data(), h->mem_host.size(), pool);
+    h->d_lev = upload(h->lev_host.data(), h->lev_host.size(), pool);
+    h->d_ainv64 = upload(h->ainv_host.data(), h->ainv_host.size(), pool);
     {
         std::vector<float> a32(h->ainv_host.begin(), h->ainv_host.end());
-        h->d_ainv32 = upload(a32.data(), a32.size());
+        h->d_ainv32 = upload(a32.data(), a32.size(), pool);
     }
-    h->d_rhs = upload(h->rhs_host.data(), h->rhs_host.size());
-    h->rhs_host.clear();
-    h->rhs_host.shrink_to_fit();
-    SG_HIP(hipHostMalloc((void**)&h->h_pinned, 4096 * sizeof(double), hipHostMallocDefault));
+    {
+        // right-hand sides: zero everywhere but chaos column 0 of the state
+        // and adjoint blocks, so only those columns cross the bus
+        double* cols = upload(h->rhs_host.data(), h->rhs_host.size(), pool);
+        h->d_rhs = upload<double>(nullptr, (size_t)count * kkt, pool);
+        launch_fill_zero<double>(h->d_rhs, (int64_t)count * kkt, st);
+        for (int b = 0; b < count; ++b)
+            for (int v = 0; v < 2; ++v)
+                SG_HIP(hipMemcpy2DAsync(h->d_rhs + (size_t)b * kkt + (size_t)(2 * v) * s.blk,
+                                        sizeof(double) * s.tstride, cols + ((size_t)b * 2 + v) * s.nt * s.nodes,
+                                        sizeof(double) * s.nodes, sizeof(double) * s.nodes, s.nt,
+                                        hipMemcpyDeviceToDevice, st));
+        SG_HIP(hipStreamSynchronize(st));
+        if (pool) pool->release(cols); else (void)hipFree(cols);
+        h->rhs_host.clear();
+        h->rhs_host.shrink_to_fit();
+    }
+    h->h_pinned = pinned_get();
     h->h_pinned_count = 4096;
     autotune(*h);
     SG_HIP(hipStreamSynchronize(h->stream));

@@ -71,6 +71,10 @@ ColMap block_map(const Shape& s, int64_t mstride) {
     return m;
 }
 
+// One multigrid V-cycle for the columns of degree level d (all members, all
+// time steps): b (level-d columns through bmap) -> x (through xmap).  Column c
+// uses the constants of member c / cpm (cpm = ncols when all columns share
+// member 0).
 // Levels with at most mg_tail_max intervals per side (and the direct solve)
 // run in one fused launch; the finer levels have a down and an up launch each.
 // Returns the first level handled by the fused tail (or the direct solve) and
@@ -288,20 +292,23 @@ struct Krylov {
     int64_t N;             // KKT vector length per member
     int nblk;
     hipStream_t st;
-    double* V;             // [m+1][vs]: slot i holds the B member vectors back to back
+    void* V;               // [m+1][vs]: slot i holds the B member vectors back to back (double, or float if v32)
     int64_t vs;            // slot stride: B*N rounded up to 64 elements
     void* Z;               // [m][B][N] (double or float)
     bool z32;              // preconditioner in FP32, Z stored in FP32
-    bool op32;             // KKT operator on Z_j in FP32 too (refinement inner cycles)
+    bool op32;             // KKT operator on Z_j from FP32 storage too (refinement inner cycles)
+    bool v32;              // basis and w in FP32 storage as well (refinement inner cycles, DCGS2)
     double* zt;            // [B][N] FP64 copy of Z_j (z32 && !op32)
     double* w;             // [B][N]
     double* partial;       // [B][kSlots][nblk]
     KrylovDev kd;
     int* d_jend;
-    float* v32;            // [B][N] FP32 staging (inner FP32 mode)
-    float* w32;
+    float* v32buf;         // [B][N] FP32 staging (FP32 preconditioner on an FP64 basis)
+    float* w32;            // [B][N] FP32 operator output (op32)
 
-    Krylov(Handle& hh, bool fp32_precond, bool fp32_op) : h(hh), st(hh.stream) {
+    // fp32_precond: Z in FP32; fp32_op: the operator on Z also from FP32
+    // storage; fp32_basis (with fp32_op, DCGS2 only): V and w in FP32 too.
+    Krylov(Handle& hh, bool fp32_precond, bool fp32_op, bool fp32_basis) : h(hh), st(hh.stream) {
         const Shape& s = h.s;
         B = h.B;
         m = h.opt.restart;
@@ -309,10 +316,11 @@ struct Krylov {
         nblk = (int)std::min<int64_t>(4096, std::max<int64_t>(1, N / (256 * 16)));
         z32 = fp32_precond;
         op32 = fp32_precond && fp32_op;
+        v32 = op32 && fp32_basis && h.opt.arnoldi == SG_ARNOLDI_DCGS2;
         vs = ((int64_t)B * N + 63) / 64 * 64;
-        V = h.ws.get_t<double>("kV", (size_t)(m + 1) * vs);
+        V = v32 ? (void*)h.ws.get_t<float>("kV32", (size_t)(m + 1) * vs) : (void*)h.ws.get_t<double>("kV", (size_t)(m + 1) * vs);
         Z = z32 ? (void*)h.ws.get_t<float>("kZ32", (size_t)m * B * N) : (void*)h.ws.get_t<double>("kZ", (size_t)m * B * N);
-        w = h.ws.get_t<double>("kw", (size_t)B * N);
+        w = v32 ? nullptr : h.ws.get_t<double>("kw", (size_t)B * N);
         partial = h.ws.get_t<double>("kpart", (size_t)B * kSlots * nblk);
         const int ld = m + 1;
         kd.H = h.ws.get_t<double>("kH", (size_t)B * ld * m);
@@ -331,43 +339,74 @@ struct Krylov {
         kd.R = h.ws.get_t<double>("kR", (size_t)B * ld * ld);
         kd.coef = h.ws.get_t<double>("kcoef", (size_t)B * kSlots);
         d_jend = h.ws.get_t<int>("kjend", (size_t)B);
-        v32 = z32 ? h.ws.get_t<float>("kv32", (size_t)B * N) : nullptr;
+        v32buf = z32 && !v32 ? h.ws.get_t<float>("kv32", (size_t)B * N) : nullptr;
         w32 = op32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
         zt = z32 && !op32 ? h.ws.get_t<double>("kzt", (size_t)B * N) : nullptr;
     }
-    double* Vi(int i) { return V + (int64_t)i * vs; }
+    double* Vi(int i) { return (double*)V + (int64_t)i * vs; }
+    float* Vi32(int i) { return (float*)V + (int64_t)i * vs; }
 
-    // y = K x for all members (FP64, or through FP32 when fp32)
+    // y = K x for all members (FP64, or through FP32 storage when fp32)
     void apply_op(const double* x, double* y, bool fp32) {
         if (!fp32) {
             kkt_apply<double>(h, x, y, B, B == 1, st);
         } else {
-            launch_cast_d2f(x, v32, (int64_t)B * N, st);
-            kkt_apply<float>(h, v32, w32, B, B == 1, st);
-            launch_cast_f2d(w32, y, (int64_t)B * N, st);
+            float* xs = w32;   // staging: x in FP32, product in FP32
+            float* ys = v32buf ? v32buf : h.ws.get_t<float>("kv32", (size_t)B * N);
+            launch_cast_d2f(x, xs, (int64_t)B * N, st);
+            kkt_apply<float>(h, xs, ys, B, B == 1, st);
+            launch_cast_f2d(ys, y, (int64_t)B * N, st);
         }
     }
     // Z_j = P^{-1} V_j
     void apply_prec(int j) {
-        if (!z32) {
+        if (v32) {
+            precond_apply<float>(h, Vi32(j), (float*)Z + (int64_t)j * B * N, B, B == 1, st);
+        } else if (!z32) {
             precond_apply<double>(h, Vi(j), (double*)Z + (int64_t)j * B * N, B, B == 1, st);
         } else {
-            launch_cast_d2f(Vi(j), v32, (int64_t)B * N, st);
-            precond_apply<float>(h, v32, (float*)Z + (int64_t)j * B * N, B, B == 1, st);
+            launch_cast_d2f(Vi(j), v32buf, (int64_t)B * N, st);
+            precond_apply<float>(h, v32buf, (float*)Z + (int64_t)j * B * N, B, B == 1, st);
         }
     }
-    // w = K Z_j
+    // w = K Z_j (in w32 when v32)
     void apply_op_z(int j) {
         if (!z32) {
             kkt_apply<double>(h, (double*)Z + (int64_t)j * B * N, w, B, B == 1, st);
         } else if (!op32) {
             launch_cast_f2d((float*)Z + (int64_t)j * B * N, zt, (int64_t)B * N, st);
             kkt_apply<double>(h, zt, w, B, B == 1, st);
+        } else if (v32) {
+            kkt_apply<float>(h, (float*)Z + (int64_t)j * B * N, w32, B, B == 1, st);
         } else {
             kkt_apply<float>(h, (float*)Z + (int64_t)j * B * N, w32, B, B == 1, st);
             launch_cast_f2d(w32, w, (int64_t)B * N, st);
         }
     }
+    // V_0 = r / ||r|| per member (kd.nrm holds ||r||^2; the cycle-start kernel
+    // leaves 1/||r|| there)
+    void start_basis(const double* r) {
+        if (v32)
+            launch_copy_scale_rows<float>(r, Vi32(0), kd.nrm, N, B, N, st);
+        else
+            launch_copy_scale_rows<double>(r, Vi(0), kd.nrm, N, B, N, st);
+    }
+    void dcgs_dots(int nv, bool with_w) {
+        if (v32)
+            launch_dcgs_dots<float>((const float*)V, vs, nv, with_w ? w32 : nullptr, N, B, N, kd.active, kd.pending,
+                                    partial, nblk, st);
+        else
+            launch_dcgs_dots<double>((const double*)V, vs, nv, with_w ? w : nullptr, N, B, N, kd.active, kd.pending,
+                                     partial, nblk, st);
+    }
+    void dcgs_update(int nv) {
+        if (v32)
+            launch_dcgs_update<float>((float*)V, vs, nv, w32, N, B, N, kd.coef, kd.scal, kd.active, nblk, st);
+        else
+            launch_dcgs_update<double>((double*)V, vs, nv, w, N, B, N, kd.coef, kd.scal, kd.active, nblk, st);
+    }
+    // bytes per element of the basis
+    double vbytes() const { return v32 ? 4.0 : 8.0; }
     // per-member squared norms of x (FP64) -> host
     void norms2(const double* x, std::vector<double>& out) {
         launch_norm(x, N, B, N, partial, nblk, st);
@@ -435,7 +474,7 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         }
         SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
         launch_cycle_start(K.kd, m, K.kd.nrm, B, st);    // kd.nrm holds ||r||^2 from residual()
-        launch_copy_scale_rows(r, K.Vi(0), K.kd.nrm, N, B, N, st);
+        K.start_basis(r);
         const bool dcgs = h.opt.arnoldi == SG_ARNOLDI_DCGS2;
         const int64_t vs = K.vs;
         // one FGMRES iteration: preconditioner, KKT apply, Arnoldi, Givens
@@ -455,30 +494,30 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
                     n_upd += active[q] ? 1 : 0;
                 }
                 bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
-                launch_dcgs_dots(K.V, vs, j, K.w, N, B, N, K.kd.active, K.kd.pending, K.partial, K.nblk, st);
-                if (tp) prof_end(h, st, 8.0 * (j + 2) * (double)n_dots * N);
+                K.dcgs_dots(j, true);
+                if (tp) prof_end(h, st, K.vbytes() * (j + 2) * (double)n_dots * N);
                 launch_reduce_partials(K.partial, K.nblk, 2 * j + 3, B, K.kd.dots, kSlots, 0, st);
                 launch_dcgs_finish(K.kd, m, j, 0, B, st);
                 tp = prof_begin(h, SG_PROF_ARNOLDI_UPD, st);
-                launch_dcgs_update(K.V, vs, j, K.w, N, B, N, K.kd.coef, K.kd.scal, K.kd.active, K.nblk, st);
-                if (tp) prof_end(h, st, 8.0 * (j + 3) * (double)n_upd * N);   // read U_0..U_j and w, write u_{j+1}
+                K.dcgs_update(j);
+                if (tp) prof_end(h, st, K.vbytes() * (j + 3) * (double)n_upd * N);   // read U_0..U_j and w, write u_{j+1}
                 for (int q = 0; q < B; ++q) pend[q] = active[q];
                 return;
             }
             const int nv = j + 1;
             // CGS2: h1 = V^T w; w1 = w - V h1; h2 = V^T w1; w2 = w1 - V h2
             const bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
-            launch_multidot(K.V, vs, nv, K.w, N, B, N, K.partial, K.nblk, st);
+            launch_multidot(K.Vi(0), vs, nv, K.w, N, B, N, K.partial, K.nblk, st);
             if (tp) prof_end(h, st, 8.0 * (nv + 1) * (double)B * N);
             launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h1, m + 1, 0, st);
-            launch_cgs_update_dot(K.V, vs, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
+            launch_cgs_update_dot(K.Vi(0), vs, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
             launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h2, m + 1, 0, st);
-            launch_cgs_update_norm(K.V, vs, nv, K.kd.h2, m + 1, K.w, K.Vi(j + 1), N, B, N, K.partial, K.nblk, st);
+            launch_cgs_update_norm(K.Vi(0), vs, nv, K.kd.h2, m + 1, K.w, K.Vi(j + 1), N, B, N, K.partial, K.nblk, st);
             launch_reduce_partials(K.partial, K.nblk, 1, B, K.kd.nrm, 1, 0, st);
             launch_arnoldi_finish(K.kd, m, j, B, st);
             launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
         };
-        const int zk = (K.z32 ? 1 : 0) + (K.op32 ? 2 : 0);
+        const int zk = (K.z32 ? 1 : 0) + (K.op32 ? 2 : 0) + (K.v32 ? 4 : 0);
         // (capture needs a created stream; the legacy default stream cannot be captured)
         const bool graphs = h.opt.use_graphs && st != nullptr && h.prof.kind == SG_PROF_NONE && h.opt.cheb_steps <= 9;
         if (graphs && h.graphs.gen != h.ws.generation()) {
@@ -534,7 +573,7 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         if (dcgs && jlast >= 0) {
             // reorthogonalise the last candidates (slot jlast + 1) of the members whose
             // last column is still pending, and commit that column
-            launch_dcgs_dots(K.V, vs, jlast + 1, nullptr, N, B, N, K.kd.active, K.kd.pending, K.partial, K.nblk, st);
+            K.dcgs_dots(jlast + 1, false);
             launch_reduce_partials(K.partial, K.nblk, jlast + 2, B, K.kd.dots, kSlots, 0, st);
             launch_dcgs_finish(K.kd, m, jlast + 1, 1, B, st);
         }
@@ -565,13 +604,13 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
     double* b = h.ws.get_t<double>("sb", (size_t)B * N);
     SG_HIP(hipMemcpyAsync(b, b_dev ? b_dev : h.d_rhs, sizeof(double) * B * N, hipMemcpyDeviceToDevice, st));
     launch_zero_ring<double>(b, s.n, (int64_t)B * 3 * s.nt * s.nxi, st);
-    SG_HIP(hipMemsetAsync(x_dev, 0, sizeof(double) * B * N, st));
+    launch_fill_zero<double>(x_dev, (int64_t)B * N, st);
 
     const bool fp32 = h.opt.precision == SG_PREC_FP32_REFINE;
     const bool pc32 = h.opt.precision == SG_PREC_FP32_PRECOND;
     h.prof.kind = h.opt.profile;
     h.prof.reset();
-    Krylov K(h, fp32 || pc32, fp32);
+    Krylov K(h, fp32 || pc32, fp32, fp32 && h.opt.basis_fp32 != 0);
     std::vector<double> bn2;
     K.norms2(b, bn2);
     std::vector<double> tol(B), res(B, 0.0);
@@ -581,49 +620,33 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
     if (!fp32) {
         fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, 0, res, member_iters, h.opt.verbose);
     } else {
-        // FP64 iterative refinement: r = b - K64 x (FP64); one inner FGMRES
-        // cycle with the FP32 operator and preconditioner (FP64 Arnoldi) on
-        // K d = r, stopping on its estimate at inner_rtol ||r||; x += d.  A
-        // member whose FP32 step reduces its true residual by less than
-        // kKeepFp32 continues with FP64 inner cycles: the FP32 products then
-        // limit what a cycle can deliver (on fine grids a cycle whose estimate
-        // falls by 1e-5 gains only a factor of about 20 in the true residual),
-        // and a further FP32 cycle would mostly spend iterations.  Every
-        // decision is per member (batch invariant).
-        constexpr double kKeepFp32 = 1e-2;
+        // FP64 iterative refinement: r = b - K64 x (FP64 storage and sums);
+        // one inner FGMRES cycle on K d = r with the operator and the
+        // preconditioner on FP32 storage (the operator's stiffness sums in
+        // FP64, so its products are accurate to FP32 rounding of the stored
+        // vectors) and the Arnoldi basis in FP32 storage with FP64 sums
+        // (basis_fp32), stopping on its estimate at inner_rtol ||r||; x += d
+        // in FP64.  Every decision is per member (batch invariant).
         double* r = h.ws.get_t<double>("sr", (size_t)B * N);
         double* d = h.ws.get_t<double>("sd", (size_t)B * N);
-        std::vector<double> nr2, prev(B, INFINITY);
-        std::vector<int> fallback(B, 0);
-        std::unique_ptr<Krylov> K64;
+        std::vector<double> nr2;
         while (true) {
             K.residual(b, x_dev, r, false, nr2);
-            std::vector<int> todo32(B, 0), todo64(B, 0);
+            std::vector<int> todo32(B, 0);
             std::vector<double> tol_in(B, 0.0);
-            bool any32 = false, any64 = false;
+            bool any = false;
             for (int q = 0; q < B; ++q) {
                 res[q] = std::sqrt(nr2[q]);
                 if (res[q] <= tol[q] || member_iters[q] >= h.opt.max_iter) continue;
-                if (res[q] > kKeepFp32 * prev[q]) fallback[q] = 1;
-                prev[q] = res[q];
                 tol_in[q] = std::max(h.opt.inner_rtol * res[q], 0.5 * tol[q]);
                 ++member_outer[q];
-                if (fallback[q]) {
-                    todo64[q] = 1;
-                    any64 = true;
-                } else {
-                    todo32[q] = 1;
-                    any32 = true;
-                }
+                todo32[q] = 1;
+                any = true;
             }
-            if (!any32 && !any64) break;
-            SG_HIP(hipMemsetAsync(d, 0, sizeof(double) * B * N, st));
+            if (!any) break;
+            launch_fill_zero<double>(d, (int64_t)B * N, st);
             std::vector<double> rin;
-            if (any32) fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
-            if (any64) {
-                if (!K64) K64.reset(new Krylov(h, false, false));
-                fgmres(*K64, r, d, tol_in, todo64, false, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
-            }
+            fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
             launch_axpby(1.0, d, 1.0, x_dev, (int64_t)B * N, st);
         }
     }

@@ -57,14 +57,14 @@ __device__ __forceinline__ double fmadd(double a, double b, double c) { return _
 __device__ __forceinline__ float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // Reference-element stiffness on a corner vector: k_a = (5 v_a - v_opp - s)/6.
-template <typename T>
-__device__ __forceinline__ void kref(T v0, T v1, T v2, T v3, T& k0, T& k1, T& k2, T& k3) {
-    const T s = (v0 + v1) + (v2 + v3);
-    const T sixth = T(1.0 / 6.0);
-    k0 = (fmadd(T(5), v0, -v2) - s) * sixth;
-    k1 = (fmadd(T(5), v1, -v3) - s) * sixth;
-    k2 = (fmadd(T(5), v2, -v0) - s) * sixth;
-    k3 = (fmadd(T(5), v3, -v1) - s) * sixth;
+__device__ __forceinline__ void kref(double v0, double v1, double v2, double v3, double& k0, double& k1, double& k2,
+                                     double& k3) {
+    const double s = (v0 + v1) + (v2 + v3);
+    const double sixth = 1.0 / 6.0;
+    k0 = (fmadd(5.0, v0, -v2) - s) * sixth;
+    k1 = (fmadd(5.0, v1, -v3) - s) * sixth;
+    k2 = (fmadd(5.0, v2, -v0) - s) * sixth;
+    k3 = (fmadd(5.0, v3, -v1) - s) * sixth;
 }
 
 struct SweepGeom {
@@ -80,31 +80,29 @@ constexpr int kkt_waves(int rs, int bytes) { return rs <= 2 ? 4 : rs <= 4 ? 3 : 
 // One term of the SG sum at output column j: mean (k = -1: c0 X_j) or mode
 // k+1 (c_{k+1,e} (g- F_{j-e_k} + g+ F_{j+e_k}), restricted to lower/upper).
 // A term with a single input column holds it in the first slot (ia, ga).
-template <typename T>
 struct Term {
     int ia, ib;
-    T ga, gb;
+    double ga, gb;
     int k;
 };
 
-template <typename T>
 __device__ __forceinline__ bool term_at(int k, int j, int M, const int32_t* __restrict__ nidx,
                                         const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
-                                        Term<T>& t) {
+                                        Term& t) {
     t.k = k;
     if (k < 0) {
         t.ia = j;
         t.ib = -1;
-        t.ga = T(1);
-        t.gb = T(0);
+        t.ga = 1.0;
+        t.gb = 0.0;
         return true;
     }
     if (!((mask >> k) & 1u)) return false;
     const int base = (j * M + k) * 2;
     t.ia = lower ? nidx[base] : -1;
     t.ib = upper ? nidx[base + 1] : -1;
-    t.ga = T(nval[base]);
-    t.gb = T(nval[base + 1]);
+    t.ga = nval[base];
+    t.gb = nval[base + 1];
     if (t.ia < 0) {             // a term with one input column keeps it in the first slot
         t.ia = t.ib;
         t.ga = t.gb;
@@ -113,10 +111,9 @@ __device__ __forceinline__ bool term_at(int k, int j, int M, const int32_t* __re
     return t.ia >= 0;
 }
 
-template <typename T>
 __device__ __forceinline__ int next_term(int k, int j, int M, const int32_t* __restrict__ nidx,
                                          const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
-                                         Term<T>& t) {
+                                         Term& t) {
     for (; k < M; ++k)
         if (term_at(k, j, M, nidx, nval, mask, lower, upper, t)) return k;
     return M;
@@ -133,15 +130,14 @@ struct Sweep {
     // ybase-1 .. ybase+2RS-1, element columns of the 32 lanes), zero off the
     // grid, into LDS as [mode-1][row][lane]: the block's four wavefronts then
     // read them from LDS instead of through the vector memory path.
-    template <typename T>
-    static __device__ __forceinline__ void stage_coef(T* sc, const T* __restrict__ coef, int64_t cplane, int M, int n,
+    static __device__ __forceinline__ void stage_coef(double* sc, const double* __restrict__ coef, int64_t cplane, int M, int n,
                                                       int tx, int ty) {
         const int ybase = ty * 2 * RS;
         const int total = M * ER * GW;
         // every load first (clamped addresses), then the masked LDS stores: a
         // masked load per store would cost one memory latency each
         constexpr int NQ = (KMAX * ER * GW + 255) / 256;
-        T tmp[NQ];
+        double tmp[NQ];
     #pragma unroll
         for (int i = 0; i < NQ; ++i) {
             const int q = min((int)threadIdx.x + 256 * i, total - 1);
@@ -158,7 +154,7 @@ struct Sweep {
                 const int X = tx * GOUT + ln - 1;
                 const int ey = ybase - 1 + r;
                 const bool ok = X >= 0 && X <= n - 1 && ey >= 0 && ey <= n - 1;
-                sc[q] = ok ? tmp[i] : T(0);
+                sc[q] = ok ? tmp[i] : 0.0;
             }
         }
     }
@@ -195,14 +191,14 @@ struct Sweep {
 
     // v[r] += c_r * (corner values of element row r) for one input column stream
     // (vals = node values of the column at the RS+2 strip rows, already scaled).
-    template <typename T>
-    static __device__ __forceinline__ void corner_accumulate(T (&v)[RS + 1][4], const T (&vals)[RS + 2], const T (&c)[RS + 1]) {
-        T prev = vals[0];
-        T prevR = shdn(prev);
+    static __device__ __forceinline__ void corner_accumulate(double (&v)[RS + 1][4], const double (&vals)[RS + 2],
+                                                             const double (&c)[RS + 1]) {
+        double prev = vals[0];
+        double prevR = shdn(prev);
     #pragma unroll
         for (int r = 0; r < RS + 1; ++r) {
-            const T top = vals[r + 1];
-            const T topR = shdn(top);
+            const double top = vals[r + 1];
+            const double topR = shdn(top);
             v[r][0] = fmadd(c[r], prev, v[r][0]);
             v[r][1] = fmadd(c[r], prevR, v[r][1]);
             v[r][2] = fmadd(c[r], topR, v[r][2]);
@@ -213,12 +209,12 @@ struct Sweep {
     }
 
     template <typename T>
-    static __device__ __forceinline__ void load_col(T (&vals)[RS + 2], const T* __restrict__ col, const Strip& st, T g,
-                                             bool accumulate) {
+    static __device__ __forceinline__ void load_col(double (&vals)[RS + 2], const T* __restrict__ col, const Strip& st,
+                                                    double g, bool accumulate) {
     #pragma unroll
         for (int r = 0; r < RS + 2; ++r) {
-            T x = col[st.noff(r)];
-            x = ((st.nmask >> r) & 1u) ? x : T(0);
+            double x = (double)col[st.noff(r)];
+            x = ((st.nmask >> r) & 1u) ? x : 0.0;
             vals[r] = accumulate ? fmadd(g, x, vals[r]) : g * x;
         }
     }
@@ -228,28 +224,27 @@ struct Sweep {
     // grid.  The global path always loads (the mean term reads plane 0 and
     // discards it), so the number of loads in flight is the same for every
     // term.
-    template <typename T>
-    static __device__ __forceinline__ void load_coef(T (&c)[RS + 1], int k, const Strip& st, T c0,
-                                                     const T* __restrict__ sc, int grp, int gl,
-                                                     const T* __restrict__ coef, int64_t cplane) {
+    static __device__ __forceinline__ void load_coef(double (&c)[RS + 1], int k, const Strip& st, double c0,
+                                                     const double* __restrict__ sc, int grp, int gl,
+                                                     const double* __restrict__ coef, int64_t cplane) {
         if (sc) {
             if (k < 0) {
     #pragma unroll
-                for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? c0 : T(0);
+                for (int r = 0; r < RS + 1; ++r) c[r] = ((st.emask >> r) & 1u) ? c0 : 0.0;
             } else {
-                const T* ck = sc + (k * ER + grp * RS) * GW + gl;    // staged, zero off the grid
+                const double* ck = sc + (k * ER + grp * RS) * GW + gl;    // staged, zero off the grid
     #pragma unroll
                 for (int r = 0; r < RS + 1; ++r) c[r] = ck[r * GW];
             }
         } else {
             // masks applied by multiplication (a select would let the compiler
             // branch around the load, and the branch join waits for every load)
-            const T* ck = coef + (int64_t)(k + 1) * cplane;
-            const T sm = k < 0 ? T(0) : T(1), sk = k < 0 ? T(1) : T(0);
+            const double* ck = coef + (int64_t)(k + 1) * cplane;
+            const double sm = k < 0 ? 0.0 : 1.0, sk = k < 0 ? 1.0 : 0.0;
     #pragma unroll
             for (int r = 0; r < RS + 1; ++r) {
-                const T cv = ck[st.eoff(r)];
-                const T mf = ((st.emask >> r) & 1u) ? T(1) : T(0);
+                const double cv = ck[st.eoff(r)];
+                const double mf = ((st.emask >> r) & 1u) ? 1.0 : 0.0;
                 c[r] = (cv * sm + c0 * sk) * mf;
             }
         }
@@ -267,7 +262,7 @@ struct Sweep {
     // from the first column when absent, and selected away); without TWO every
     // term has exactly one.  Either way the loads per term are a fixed count.
     template <bool TWO, typename T>
-    static __device__ __forceinline__ void load_raw(Raw<T>& R, const Term<T>& t, const T* __restrict__ F,
+    static __device__ __forceinline__ void load_raw(Raw<T>& R, const Term& t, const T* __restrict__ F,
                                                     int64_t nodes, const Strip& st) {
         const T* ca = F + (int64_t)t.ia * nodes;       // every term has its first column
     #pragma unroll
@@ -280,25 +275,25 @@ struct Sweep {
     }
     // value of the term at strip row r (masked, scaled, then summed)
     template <bool TWO, typename T>
-    static __device__ __forceinline__ T combine_row(const Raw<T>& R, const Term<T>& t, const Strip& st, int r) {
+    static __device__ __forceinline__ double combine_row(const Raw<T>& R, const Term& t, const Strip& st, int r) {
         const bool in = (st.nmask >> r) & 1u;
-        T val = t.ga * (in ? R.a[r] : T(0));
+        double val = t.ga * (in ? (double)R.a[r] : 0.0);
         if (TWO) {
-            const T v2 = fmadd(t.gb, in ? R.b[r] : T(0), val);
+            const double v2 = fmadd(t.gb, in ? (double)R.b[r] : 0.0, val);
             val = t.ib >= 0 ? v2 : val;
         }
         return val;
     }
     // corner_accumulate of one term, its row values combined on the fly
     template <bool TWO, typename T>
-    static __device__ __forceinline__ void accumulate_term(T (&v)[RS + 1][4], const Raw<T>& R, const Term<T>& t,
-                                                           const Strip& st, const T (&c)[RS + 1]) {
-        T prev = combine_row<TWO>(R, t, st, 0);
-        T prevR = shdn(prev);
+    static __device__ __forceinline__ void accumulate_term(double (&v)[RS + 1][4], const Raw<T>& R, const Term& t,
+                                                           const Strip& st, const double (&c)[RS + 1]) {
+        double prev = combine_row<TWO>(R, t, st, 0);
+        double prevR = shdn(prev);
     #pragma unroll
         for (int r = 0; r < RS + 1; ++r) {
-            const T top = combine_row<TWO>(R, t, st, r + 1);
-            const T topR = shdn(top);
+            const double top = combine_row<TWO>(R, t, st, r + 1);
+            const double topR = shdn(top);
             v[r][0] = fmadd(c[r], prev, v[r][0]);
             v[r][1] = fmadd(c[r], prevR, v[r][1]);
             v[r][2] = fmadd(c[r], topR, v[r][2]);
@@ -319,22 +314,23 @@ struct Sweep {
     // any vector load, and a scheduling barrier keeps the loads ahead of the
     // arithmetic.  The per-node arithmetic is the same for every strip height.
     template <bool TWO, typename T>
-    static __device__ __forceinline__ void sg_strip(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F, int64_t nodes,
-                                             int j, int M, const int32_t* __restrict__ nidx,
-                                             const double* __restrict__ nval, uint32_t mask, bool lower, bool upper,
-                                             bool with_mean, T c0, const T* __restrict__ sc, int grp, int gl,
-                                             const T* __restrict__ coef, int64_t cplane) {
-        T c[RS + 1];
+    static __device__ __forceinline__ void sg_strip(double (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F,
+                                                    int64_t nodes, int j, int M, const int32_t* __restrict__ nidx,
+                                                    const double* __restrict__ nval, uint32_t mask, bool lower,
+                                                    bool upper, bool with_mean, double c0,
+                                                    const double* __restrict__ sc, int grp, int gl,
+                                                    const double* __restrict__ coef, int64_t cplane) {
+        double c[RS + 1];
         Raw<T> RA, RB;                                 // current and next term's raw node values
-        Term<T> tA, tB;
+        Term tA, tB;
         // the present modes as a bit set (one scalar pass before any vector
         // load), so that no loop separates a term's loads from their use
         uint32_t todo = 0;
         for (int k = 0; k < M; ++k) {
-            Term<T> t;
+            Term t;
             if (term_at(k, j, M, nidx, nval, mask, lower, upper, t)) todo |= 1u << k;
         }
-        auto pop = [&](Term<T>& t) -> int {
+        auto pop = [&](Term& t) -> int {
             if (!todo) return M;
             const int k = __builtin_ctz(todo);
             todo &= todo - 1u;
@@ -376,21 +372,21 @@ struct Sweep {
     // iteration).  Lighter on registers; used by the standalone SG apply, where
     // it measured faster than the pipelined strip at the occupancy it allows.
     template <typename T>
-    static __device__ __forceinline__ void load_term(T (&vals)[RS + 2], const Term<T>& t, const T* __restrict__ F,
+    static __device__ __forceinline__ void load_term(double (&vals)[RS + 2], const Term& t, const T* __restrict__ F,
                                                      int64_t nodes, const Strip& st) {
         load_col(vals, F + (int64_t)t.ia * nodes, st, t.ga, false);
         if (t.ib >= 0) load_col(vals, F + (int64_t)t.ib * nodes, st, t.gb, true);
     }
     template <typename T>
-    static __device__ __forceinline__ void sg_strip_direct(T (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F,
+    static __device__ __forceinline__ void sg_strip_direct(double (&v)[RS + 1][4], const Strip& st, const T* __restrict__ F,
                                                            int64_t nodes, int j, int M, const int32_t* __restrict__ nidx,
                                                            const double* __restrict__ nval, uint32_t mask, bool lower,
-                                                           bool upper, bool with_mean, T c0, const T* __restrict__ sc,
-                                                           int grp, int gl, const T* __restrict__ coef,
-                                                           int64_t cplane) {
-        T vals[RS + 2], nvals[RS + 2];
-        T c[RS + 1];
-        Term<T> cur, nxt;
+                                                           bool upper, bool with_mean, double c0,
+                                                           const double* __restrict__ sc, int grp, int gl,
+                                                           const double* __restrict__ coef, int64_t cplane) {
+        double vals[RS + 2], nvals[RS + 2];
+        double c[RS + 1];
+        Term cur, nxt;
         int k = next_term(with_mean ? -1 : 0, j, M, nidx, nval, mask, lower, upper, cur);
         if (k >= M) return;
         load_term(vals, cur, F, nodes, st);
@@ -411,31 +407,30 @@ struct Sweep {
 
     // Reference-element mass (h^2/36)[4 2 1 2; 2 4 2 1; 1 2 4 2; 2 1 2 4] on a
     // corner vector: m_a = w (2 s + 2 v_a - v_opp), w = h^2/36.
-    template <typename T>
-    static __device__ __forceinline__ void mass_accumulate(T (&e)[RS + 1][4], const T (&vals)[RS + 2], const Strip& st, T w) {
-        T prev = vals[0];
-        T prevR = shdn(prev);
+    static __device__ __forceinline__ void mass_accumulate(double (&e)[RS + 1][4], const double (&vals)[RS + 2],
+                                                           const Strip& st, double w) {
+        double prev = vals[0];
+        double prevR = shdn(prev);
     #pragma unroll
         for (int r = 0; r < RS + 1; ++r) {
-            const T top = vals[r + 1];
-            const T topR = shdn(top);
-            const T c = ((st.emask >> r) & 1u) ? w : T(0);
-            const T s2 = T(2) * ((prev + prevR) + (topR + top));
-            e[r][0] = fmadd(c, fmadd(T(2), prev, s2) - topR, e[r][0]);
-            e[r][1] = fmadd(c, fmadd(T(2), prevR, s2) - top, e[r][1]);
-            e[r][2] = fmadd(c, fmadd(T(2), topR, s2) - prev, e[r][2]);
-            e[r][3] = fmadd(c, fmadd(T(2), top, s2) - prevR, e[r][3]);
+            const double top = vals[r + 1];
+            const double topR = shdn(top);
+            const double c = ((st.emask >> r) & 1u) ? w : 0.0;
+            const double s2 = 2.0 * ((prev + prevR) + (topR + top));
+            e[r][0] = fmadd(c, fmadd(2.0, prev, s2) - topR, e[r][0]);
+            e[r][1] = fmadd(c, fmadd(2.0, prevR, s2) - top, e[r][1]);
+            e[r][2] = fmadd(c, fmadd(2.0, topR, s2) - prev, e[r][2]);
+            e[r][3] = fmadd(c, fmadd(2.0, top, s2) - prevR, e[r][3]);
             prev = top;
             prevR = topR;
         }
     }
 
     // Corner sums of the SG stiffness strip -> element results scaled by -s.
-    template <typename T>
-    static __device__ __forceinline__ void stiff_to_element(T (&v)[RS + 1][4], T s) {
+    static __device__ __forceinline__ void stiff_to_element(double (&v)[RS + 1][4], double s) {
     #pragma unroll
         for (int r = 0; r < RS + 1; ++r) {
-            T k0, k1, k2, k3;
+            double k0, k1, k2, k3;
             kref(v[r][0], v[r][1], v[r][2], v[r][3], k0, k1, k2, k3);
             v[r][0] = -s * k0;
             v[r][1] = -s * k1;
@@ -448,22 +443,21 @@ struct Sweep {
     // (X, Y) sums corners 0 and 3 of its own lane's element rows r and r-1 and
     // corners 1 and 2 of the lane to the left; non-interior nodes get zero.
     template <typename T>
-    static __device__ __forceinline__ void emit_nodes(const T (&e)[RS + 1][4], const Strip& st, int gl, int X, int n,
+    static __device__ __forceinline__ void emit_nodes(const double (&e)[RS + 1][4], const Strip& st, int gl, int X, int n,
                                                T* __restrict__ out) {
         const bool xout = gl >= 1 && gl <= GOUT && X <= n;
     #pragma unroll
         for (int r = 1; r < RS + 1; ++r) {
-            const T A = e[r][0] + e[r - 1][3];
-            const T Bl = shup(e[r][1] + e[r - 1][2]);
+            const double A = e[r][0] + e[r - 1][3];
+            const double Bl = shup(e[r][1] + e[r - 1][2]);
             const int Y = st.y0 - 1 + r;
-            if (xout && Y <= n) out[(int64_t)Y * (n + 1) + X] = ((st.nmask >> r) & 1u) ? A + Bl : T(0);
+            if (xout && Y <= n) out[(int64_t)Y * (n + 1) + X] = (T)(((st.nmask >> r) & 1u) ? A + Bl : 0.0);
         }
     }
 
-    template <typename T>
-    static __device__ __forceinline__ void zero_strip(T (&v)[RS + 1][4]) {
+    static __device__ __forceinline__ void zero_strip(double (&v)[RS + 1][4]) {
     #pragma unroll
-        for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
+        for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0.0;
     }
 
     // Fused KKT apply, one output chaos column per wavefront, three residual blocks
@@ -512,51 +506,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
                            : x + (int64_t)mem_i * vmap.mstride + (int64_t)t * vmap.tstride;
     typename S::Strip st;
     st.init(n, X, y0);
-    T v[RS + 1][4];
+    double v[RS + 1][4];
 #pragma unroll
-    for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = T(0);
+    for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0.0;
     if constexpr (KIND == 0)
         S::sg_strip_direct(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true,
-                           T(op.mem[mem].c0), (const T*)nullptr, grp, gl,
-                           (const T*)op.coef + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
+                           op.mem[mem].c0, (const double*)nullptr, grp, gl,
+                           op.coef64 + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
     else
         S::template sg_strip<TWO>(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, mask, lower != 0, upper != 0, false,
-                                  T(op.mem[mem].c0), (const T*)nullptr, grp, gl,
-                                  (const T*)op.coef + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
+                                  op.mem[mem].c0, (const double*)nullptr, grp, gl,
+                                  op.coef64 + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
     T* out;
     const T* bas = nullptr;
-    T scale = T(1);
+    double scale = 1.0;
     if (KIND == 0) {
         out = y + (int64_t)slice * nxi * nodes + (int64_t)j * nodes;
     } else {
         const int c = slice * L + l;
         out = y + omap.off(c);
         bas = base + bmap.off(c);
-        scale = T(op.mem[mem].off_scale);
+        scale = op.mem[mem].off_scale;
     }
     const bool xout = gl >= 1 && gl <= GOUT && X <= n;
-    T k2p, k3p;
+    double k2p, k3p;
     {
-        T k0, k1;
+        double k0, k1;
         kref(v[0][0], v[0][1], v[0][2], v[0][3], k0, k1, k2p, k3p);
     }
 #pragma unroll
     for (int r = 1; r < RS + 1; ++r) {
-        T k0, k1, k2, k3;
+        double k0, k1, k2, k3;
         kref(v[r][0], v[r][1], v[r][2], v[r][3], k0, k1, k2, k3);
-        const T A = k0 + k3p;
-        const T Bl = shup(k1 + k2p);
+        const double A = k0 + k3p;
+        const double Bl = shup(k1 + k2p);
         const int Y = y0 - 1 + r;                 // node row of this output
         if (xout && Y <= n) {
             const bool inter = (st.nmask >> r) & 1u;    // node (X, Y) is interior (strip row r)
             const int64_t q = (int64_t)Y * (n + 1) + X;
-            T val = T(0);
+            double val = 0.0;
             if (KIND == 0) {
                 if (inter) val = A + Bl;
             } else {
-                if (inter) val = fmadd(-scale, A + Bl, bas[q]);
+                if (inter) val = fmadd(-scale, A + Bl, (double)bas[q]);
             }
-            out[q] = val;
+            out[q] = (T)val;
         }
         k2p = k2;
         k3p = k3;
@@ -580,10 +574,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     using S = Sweep<RS>;
     // the block's four output columns run two full stiffness strips each over
     // the same element tile: its coefficients are staged once in LDS
-    __shared__ T sc[KMAX * S::ER * GW];
+    __shared__ double sc[KMAX * S::ER * GW];
     {
         const int mem_b = op.mem_shared ? 0 : (slice / nt);
-        S::stage_coef(sc, (const T*)op.coef + (int64_t)mem_b * op.coef_mstride, (int64_t)n * n, M, n, tx, ty);
+        S::stage_coef(sc, op.coef64 + (int64_t)mem_b * op.coef_mstride, (int64_t)n * n, M, n, tx, ty);
     }
     __syncthreads();
     if (j >= nxi) return;                            // uniform per wavefront; no block barriers below
@@ -605,27 +599,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     T* RY = y + (int64_t)vec * 3 * blk + t * tst + cj;
     T* RU = RY + blk;
     T* RL = RU + blk;
-    const T hinv = T(1) / T(n);
-    const T w = hinv * hinv / T(36);
-    const T tau = TIME ? T(md.tau) : T(1);
-    const T Dt = (TIME && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
-    const T hgj = j == 0 ? T(1) : T(md.hg);
-    const T beta = T(md.beta);
-    const T c0 = T(md.c0);
+    const double hinv = 1.0 / (double)n;
+    const double w = hinv * hinv / 36.0;
+    const double tau = TIME ? md.tau : 1.0;
+    const double Dt = (TIME && (t == 0 || t == nt - 1)) ? 0.5 : 1.0;
+    const double hgj = j == 0 ? 1.0 : md.hg;
+    const double beta = md.beta;
+    const double c0 = md.c0;
     typename S::Strip st;
     st.init(n, X, y0);
-    T v[RS + 1][4];
-    T vals[RS + 2];
+    double v[RS + 1][4];
+    double vals[RS + 2];
     // R^Y
     S::zero_strip(v);
     S::template sg_strip<true>(v, st, Lt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc,
                                grp, gl,
-                (const T*)nullptr, 0);
+                (const double*)nullptr, 0);
     S::stiff_to_element(v, tau);
     S::load_col(vals, Yt + cj, st, tau * Dt * hgj, false);
     if (TIME) {
-        S::load_col(vals, Lt + cj, st, T(-1), true);
-        if (t + 1 < nt) S::load_col(vals, Lt + tst + cj, st, T(1), true);
+        S::load_col(vals, Lt + cj, st, -1.0, true);
+        if (t + 1 < nt) S::load_col(vals, Lt + tst + cj, st, 1.0, true);
     }
     S::mass_accumulate(v, vals, st, w);
     S::emit_nodes(v, st, gl, X, n, RY);
@@ -633,12 +627,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     S::zero_strip(v);
     S::template sg_strip<true>(v, st, Yt, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true, c0, sc,
                                grp, gl,
-                (const T*)nullptr, 0);
+                (const double*)nullptr, 0);
     S::stiff_to_element(v, tau);
     S::load_col(vals, Ut + cj, st, tau, false);
     if (TIME) {
-        S::load_col(vals, Yt + cj, st, T(-1), true);
-        if (t > 0) S::load_col(vals, Yt - tst + cj, st, T(1), true);
+        S::load_col(vals, Yt + cj, st, -1.0, true);
+        if (t > 0) S::load_col(vals, Yt - tst + cj, st, 1.0, true);
     }
     S::mass_accumulate(v, vals, st, w);
     S::emit_nodes(v, st, gl, X, n, RL);

@@ -2,7 +2,7 @@
 // for the SG operator apply, the hGS off-level right-hand side and the fused
 // KKT apply.  Every candidate evaluates the same sums per node in the same
 // order, so the choice changes timing only, never results.  Choices are cached
-// per process by (device, shape, members, element type).
+// per process by (device, shape, single member or batch, element type).
 #include <array>
 #include <map>
 #include <mutex>
@@ -90,7 +90,9 @@ void autotune(Handle& h) {
     if (forced > 0 || s.M > 8) return;      // fixed by the caller, or no sweep kernels for this shape
     const bool need32 = h.opt.precision != SG_PREC_FP64;
     for (int t = 0; t < (need32 ? 2 : 1); ++t) {
-        const TuneKey key{h.device, s.n, s.M, s.P, s.nt, s.time ? 1 : 0, h.B, t};
+        // batches of any size above one share a choice (the serving loop forms
+        // batches of every size; a new size should not time the kernels again)
+        const TuneKey key{h.device, s.n, s.M, s.P, s.nt, s.time ? 1 : 0, h.B > 1 ? 2 : 1, t};
         std::array<int, 3> rows;
         bool hit = false;
         {

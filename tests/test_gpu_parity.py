@@ -220,12 +220,15 @@ def test_deterministic_field_stays_in_the_mean(shape):
         assert rel_max(mean, mean_ref) < 1e-8
 
 
-def test_solve_fp32_refine_reaches_fp64_accuracy():
+@pytest.mark.parametrize("basis_fp32", [1, 0])
+def test_solve_fp32_refine_reaches_fp64_accuracy(basis_fp32):
+    """FP64 refinement around FP32-storage inner cycles (the basis in FP32 or
+    FP64 storage) reaches the direct solution to FP64 accuracy."""
     dev = _dev()
-    _say("solve fp32 refine")
+    _say(f"solve fp32 refine, basis_fp32={basis_fp32}")
     prob, kw = make_case(16, 4, 3, 0.2, 1e-2)
     sg = kkt.setup(prob)
-    h = _setup([kw], rtol=1e-12, max_iter=600, precision=1)
+    h = _setup([kw], rtol=1e-12, max_iter=600, precision=1, basis_fp32=basis_fp32)
     xd = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
     rc, info = h.solve(xd)
     assert rc == 0 and info[0].rel_res_true <= 1e-12 and info[0].outer_refinements >= 1
