@@ -327,3 +327,135 @@ def z_truncated(sg: kkt.SG, r_trunc: int) -> sp.csr_matrix:
     for k in range(1, min(r_trunc, sg.prob.M + 1)):
         Z = Z + scale * sp.kron(sp.csr_matrix(sg.G[k]), sg.K[k], format="csr")
     return Z.tocsr()
+
+
+# ----------------------------------------------------------------------------
+# hGSoc: hierarchical Gauss-Seidel on the coupled KKT system (Algorithms 2-3)
+# ----------------------------------------------------------------------------
+
+class PtildeSolve:
+    """Solves with P-tilde = blkdiag(M, beta M, A-tilde_1) column by column
+    (Section 2.3, the auxiliary block-diagonal matrix of Algorithms 2-3).
+
+    mode "exact": sparse LU of M and A-tilde_1 (the paper factorises P-tilde
+    once); mode "cheb": Chebyshev semi-iteration with `cheb_steps` steps for
+    M (the mass solves of the block preconditioner) and one multigrid V-cycle
+    for A-tilde_1 (the solver's choice).
+
+    adjoint "literal": the third block is A-tilde_1 as printed.  adjoint
+    "schur": the third block is the mean Schur approximation A-tilde_1
+    M^{-1} A-tilde_1 (applied as A-tilde_1^{-1} M A-tilde_1^{-1}), the
+    adjoint block of the block-diagonal preconditioner restricted to one
+    chaos column: the adjoint row of the level-diagonal KKT block has no
+    entry on the adjoint itself, so A-tilde_1 alone does not approximate it
+    (with it the coupled sweep stagnates; see the iteration counts)."""
+
+    def __init__(self, sg: kkt.SG, mode: str = "cheb", cheb_steps: int = 5, nu_pre: int = 2, nu_post: int = 2,
+                 adjoint: str = "literal"):
+        self.sg, self.mode, self.cheb_steps, self.adjoint = sg, mode, cheb_steps, adjoint
+        self.inner = make_inner(sg, "exact" if mode == "exact" else "gmg", nu_pre, nu_post)
+        if mode == "exact":
+            self.mlu = spla.splu(sg.Mi.tocsc())
+
+    def mass_inv(self, R: np.ndarray) -> np.ndarray:
+        R = np.atleast_2d(R)
+        if self.mode == "exact":
+            return self.mlu.solve(np.ascontiguousarray(R.T)).T
+        return cheb_mass(self.sg.Mi, R, self.cheb_steps)
+
+    def apply(self, BY: np.ndarray, BU: np.ndarray, BL: np.ndarray):
+        VL = self.inner.apply(BL)
+        if self.adjoint == "schur":
+            VL = self.inner.apply(kkt.mass_apply(self.sg, VL))
+        return self.mass_inv(BY), self.mass_inv(BU) / self.sg.prob.beta, VL
+
+
+def hgsoc(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int) -> np.ndarray:
+    """Algorithms 2-3 applied to a flat steady KKT residual (zero initial
+    guess), returning the flat preconditioned vector.
+
+    The unknowns are swept level by level, degrees d = 0..P and back
+    P-1..0; at level d the three blocks solve with P-tilde against the level's
+    residual rows minus the KKT couplings to every other level, taken with
+    the current values:
+      state row    R^Y - C + D,   C = M V^Y [h^gamma off-level],  D = sum_tau A_tau V^L [h_tau],
+      control row  R^U - E - F,   E = beta M V^U [h_1 off-level],  F = M V^L [h_1 off-level],
+      adjoint row  R^L + G - H,   G = sum_tau A_tau V^Y [h_tau],   H = M V^U [h_1 off-level],
+    tau over the kept modes I_tau (k = 1..r-1).  H^gamma and H_1 = I are
+    diagonal, so C, E, F and H vanish; they are formed anyway from the
+    off-level parts of those matrices."""
+    p = sg.prob
+    assert p.steady, "hGSoc is defined for the steady KKT system"
+    Ry, Ru, Rl = (b.copy() for b in kkt.split(sg, r))
+    off = sg.offsets
+    P = len(off) - 2
+    modes = list(range(1, min(r_trunc, p.M + 1)))
+    hg = np.diag(kkt.h_gamma(sg))
+    H1 = np.eye(sg.n_xi)
+    VY, VU, VL = np.zeros_like(Ry), np.zeros_like(Ru), np.zeros_like(Rl)
+    order = list(range(P + 1)) + list(range(P - 1, -1, -1))
+    for d in order:
+        lo, hi = int(off[d]), int(off[d + 1])
+
+        def others(V):
+            W = V.copy()
+            W[lo:hi] = 0.0
+            return W
+
+        def couple(Hm, V):
+            # columns lo:hi of V_mat Hm, as rows: (Hm[:, lo:hi])^T applied to the chaos rows of V
+            return Hm[:, lo:hi].T @ V
+
+        Yo, Uo, Lo = others(VY), others(VU), others(VL)
+        C = kkt.mass_apply(sg, couple(hg, Yo))
+        E = p.beta * kkt.mass_apply(sg, couple(H1, Uo))
+        F = kkt.mass_apply(sg, couple(H1, Lo))
+        Hh = kkt.mass_apply(sg, couple(H1, Uo))
+        D = np.zeros((hi - lo, Ry.shape[1]))
+        G = np.zeros_like(D)
+        for k in modes:
+            D += (sg.K[k] @ couple(sg.G[k], Lo).T).T
+            G += (sg.K[k] @ couple(sg.G[k], Yo).T).T
+        by = Ry[lo:hi] - C + D
+        bu = Ru[lo:hi] - E - F
+        bl = Rl[lo:hi] + G - Hh
+        VY[lo:hi], VU[lo:hi], VL[lo:hi] = ptilde.apply(by, bu, bl)
+    return np.concatenate([VY.ravel(), VU.ravel(), VL.ravel()])
+
+
+def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int) -> tuple:
+    """The matrices behind Algorithms 2-3 with exact P-tilde solves: the level
+    splitting K_r = D + L + U of the KKT matrix with every level-diagonal
+    block replaced by P-tilde (per chaos column) and the off-level couplings
+    truncated to the kept modes; one forward and one backward block
+    Gauss-Seidel sweep from zero then equal (D + U)^{-1} D (D + L)^{-1}.
+    ptilde_blocks = (M, beta M, A-tilde_1) as sparse matrices.  Returns
+    (D, L, U) over the unknown order [Y | U | Lambda], chaos-major inside a block."""
+    p = sg.prob
+    nxi, ni = sg.n_xi, sg.n_int
+    Mb, bMb, A1 = ptilde_blocks
+    off = sg.offsets
+    level = np.zeros(nxi, dtype=int)
+    for d in range(len(off) - 1):
+        level[int(off[d]):int(off[d + 1])] = d
+    modes = list(range(1, min(r_trunc, p.M + 1)))
+    I = sp.identity(nxi, format="csr")
+    Dg = sp.block_diag([sp.kron(I, Mb), sp.kron(I, bMb), sp.kron(I, A1)], format="csr")
+    # off-level couplings of the KKT rows (state: -A Lambda; adjoint: -A Y)
+    Aoff = None
+    for k in modes:
+        t = sp.kron(sp.csr_matrix(sg.G[k]), sg.K[k], format="csr")
+        Aoff = t if Aoff is None else Aoff + t
+    Z = sp.csr_matrix((nxi * ni, nxi * ni))
+    if Aoff is None:
+        Aoff = Z
+    Koff = sp.bmat([[None, None, -Aoff], [None, Z, None], [-Aoff, None, None]], format="csr")
+    # level of each unknown (row / column)
+    lev = np.tile(np.repeat(level, ni), 3)
+    Kc = Koff.tocoo()
+    lower = lev[Kc.row] > lev[Kc.col]
+    upper = lev[Kc.row] < lev[Kc.col]
+    n3 = 3 * nxi * ni
+    L = sp.csr_matrix((Kc.data[lower], (Kc.row[lower], Kc.col[lower])), shape=(n3, n3))
+    U = sp.csr_matrix((Kc.data[upper], (Kc.row[upper], Kc.col[upper])), shape=(n3, n3))
+    return Dg, L, U

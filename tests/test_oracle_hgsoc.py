@@ -1,0 +1,117 @@
+"""Pins of the oracle's hGSoc preconditioner (Algorithms 2-3): the coupled
+state/control/adjoint hierarchical Gauss-Seidel sweep over degree levels with
+P-tilde = blkdiag(M, beta M, A-tilde_1) solves on each level.
+
+The sweep is checked against the algebra it stands for, built independently
+with explicit sparse matrices: one forward and one backward block
+Gauss-Seidel sweep from zero on the KKT matrix split by degree levels
+(level-diagonal blocks replaced by P-tilde, off-level couplings truncated to
+the kept modes) equals (D + U)^{-1} D (D + L)^{-1}."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import sg_inputs
+from oracle import fem, fgmres, kkt, precond
+
+
+def _case(n, M, P, sigma, beta, gamma=0.0):
+    prob = kkt.Problem(n=n, M=M, P=P, sigma=sigma, beta=beta, gamma=gamma, y_target=sg_inputs.gaussian_bumps(n, 0))
+    return kkt.setup(prob)
+
+
+def _ptilde_blocks(sg):
+    a, b, _ = precond.mean_operator_coeffs(sg)
+    K = fem.restrict(fem.assemble_full(sg.prob.n, 1.0, "stiffness"), sg.prob.n)
+    return sg.Mi, sg.prob.beta * sg.Mi, (a * K + b * sg.Mi).tocsr()
+
+
+@pytest.mark.parametrize("shape", [(8, 3, 3, 0.3, 1e-2, 0.0, 4), (8, 2, 4, 0.25, 1e-4, 0.5, 3),
+                                   (8, 4, 2, 0.2, 1e-1, 0.0, 2), (4, 3, 2, 0.3, 1e-3, 0.0, 4)])
+def test_hgsoc_equals_symmetric_block_gauss_seidel(shape):
+    n, M, P, sigma, beta, gamma, r_trunc = shape
+    sg = _case(n, M, P, sigma, beta, gamma)
+    r = sg_inputs.random_block((3 * sg.n_xi * sg.n_int,), 3)
+    z = precond.hgsoc(sg, r, precond.PtildeSolve(sg, "exact"), r_trunc)
+    D, L, U = precond.hgsoc_matrix_form(sg, _ptilde_blocks(sg), r_trunc)
+    x1 = spla.spsolve((D + L).tocsc(), r)
+    zz = spla.spsolve((D + U).tocsc(), D @ x1)
+    assert np.max(np.abs(z - zz)) < 1e-12 * np.max(np.abs(zz))
+
+
+def test_hgsoc_splitting_reproduces_the_kkt_couplings():
+    """D + L + U minus the level-diagonal P-tilde blocks plus the KKT's own
+    level-diagonal blocks is the KKT matrix (all modes kept): the sweep sees
+    exactly the KKT's off-level couplings."""
+    sg = _case(8, 3, 2, 0.3, 1e-2)
+    D, L, U = precond.hgsoc_matrix_form(sg, _ptilde_blocks(sg), sg.prob.M + 1)
+    Kkkt = kkt.kkt_steady(sg)
+    nxi, ni = sg.n_xi, sg.n_int
+    lev = np.zeros(nxi, dtype=int)
+    off = sg.offsets
+    for d in range(len(off) - 1):
+        lev[int(off[d]):int(off[d + 1])] = d
+    levu = np.tile(np.repeat(lev, ni), 3)
+    Kc = Kkkt.tocoo()
+    same = levu[Kc.row] == levu[Kc.col]
+    n3 = 3 * nxi * ni
+    Kdiag = sp.csr_matrix((Kc.data[same], (Kc.row[same], Kc.col[same])), shape=(n3, n3))
+    rebuilt = (Kdiag + L + U).toarray()
+    assert np.max(np.abs(rebuilt - Kkkt.toarray())) < 1e-13 * abs(Kkkt).max()
+
+
+def test_hgsoc_mean_based_is_ptilde():
+    """r = 1 (no modes kept): every level is solved independently, so hGSoc is
+    P-tilde^{-1} column by column."""
+    sg = _case(8, 3, 2, 0.3, 1e-2)
+    r = sg_inputs.random_block((3 * sg.n_xi * sg.n_int,), 5)
+    pt = precond.PtildeSolve(sg, "exact")
+    z = precond.hgsoc(sg, r, pt, 1)
+    Ry, Ru, Rl = kkt.split(sg, r)
+    Mb, bMb, A1 = _ptilde_blocks(sg)
+    ref = [spla.spsolve(B.tocsc(), R.T).T for B, R in ((Mb, Ry), (bMb, Ru), (A1, Rl))]
+    assert np.max(np.abs(z - np.concatenate([x.ravel() for x in ref]))) < 1e-12 * np.max(np.abs(z))
+
+
+def test_hgsoc_flags_a_wrong_coupling_sign():
+    """A plausible slip (adding instead of subtracting the state row's adjoint
+    coupling, i.e. the sign of D) moves the result off the block Gauss-Seidel
+    algebra by far more than rounding."""
+    sg = _case(8, 3, 3, 0.3, 1e-2)
+    r = sg_inputs.random_block((3 * sg.n_xi * sg.n_int,), 7)
+    D, L, U = precond.hgsoc_matrix_form(sg, _ptilde_blocks(sg), sg.prob.M + 1)
+    Dm, Lm, Um = D, -L, -U           # the mistake: couplings with the wrong sign
+    x1 = spla.spsolve((Dm + Lm).tocsc(), r)
+    wrong = spla.spsolve((Dm + Um).tocsc(), Dm @ x1)
+    z = precond.hgsoc(sg, r, precond.PtildeSolve(sg, "exact"), sg.prob.M + 1)
+    assert np.max(np.abs(z - wrong)) > 1e-3 * np.max(np.abs(z))
+
+
+def test_hgsoc_schur_reading_equals_block_gauss_seidel():
+    """With the Schur-type adjoint block the sweep is the same block
+    Gauss-Seidel algebra with that block on the diagonal."""
+    sg = _case(8, 3, 3, 0.3, 1e-2)
+    r = sg_inputs.random_block((3 * sg.n_xi * sg.n_int,), 9)
+    z = precond.hgsoc(sg, r, precond.PtildeSolve(sg, "exact", adjoint="schur"), sg.prob.M + 1)
+    Mb, bMb, A1 = _ptilde_blocks(sg)
+    S = (A1 @ spla.spsolve(sg.Mi.tocsc(), A1.tocsc())).tocsr()
+    D, L, U = precond.hgsoc_matrix_form(sg, (Mb, bMb, S), sg.prob.M + 1)
+    x1 = spla.spsolve((D + L).tocsc(), r)
+    zz = spla.spsolve((D + U).tocsc(), D @ x1)
+    assert np.max(np.abs(z - zz)) < 1e-10 * np.max(np.abs(zz))
+
+
+def test_hgsoc_preconditioned_fgmres_converges():
+    """FGMRES with hGSoc (Schur-type adjoint block; multigrid and Chebyshev
+    solves inside, as on the GPU) reaches the direct solution; iteration
+    counts are context only."""
+    sg = _case(8, 3, 3, 0.3, 1e-2)
+    b = kkt.rhs(sg)
+    K = kkt.kkt_steady(sg)
+    pt = precond.PtildeSolve(sg, "cheb", adjoint="schur")
+    x, info = fgmres.fgmres(lambda v: K @ v, lambda v: precond.hgsoc(sg, v, pt, sg.prob.M + 1), b, tol=1e-10,
+                            restart=30, max_iter=400)
+    assert info["converged"]
+    ref = kkt.solve_direct(sg)
+    assert np.max(np.abs(x - ref)) < 1e-7 * np.max(np.abs(ref))
