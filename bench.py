@@ -401,6 +401,11 @@ def main():
                          "FP64 serving capacity) and print its JSON")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB FP64 tensor three times (calibrates hardware byte counters) and exit")
+    ap.add_argument("--kernel-probe", choices=["apply", "kkt", "precond"],
+                    help="only apply the SG operator, the KKT matrix or the preconditioner (FP64, one vector of the "
+                         "workload's first problem, strips of --sweep-rows or autotuned) --probe-reps times after one "
+                         "warm-up, and exit (the kernels' hardware counters are taken on this)")
+    ap.add_argument("--probe-reps", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no HIP graph replay)")
     ap.add_argument("--sweep-rows", type=int, default=0, choices=[0, 2, 4, 8],
@@ -425,6 +430,25 @@ def main():
 
     import paper_2512_23804_amd as sgl
     import sg_inputs
+
+    if args.kernel_probe:
+        wl = WORKLOADS[args.workload]
+        h = sgl.Handle(make_problems(sgl, sg_inputs, wl)[:1], sgl.default_options(sweep_rows=args.sweep_rows))
+        per = h.block_elems if args.kernel_probe == "apply" else h.kkt_elems
+        x = torch.rand(per, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        fn = {"apply": h.apply_operator, "kkt": h.apply_kkt, "precond": h.precond_apply}[args.kernel_probe]
+        fn(x, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.probe_reps):
+            fn(x, y)
+        torch.cuda.synchronize()
+        print(json.dumps({"kernel_probe": args.kernel_probe, "workload": args.workload, "reps": args.probe_reps,
+                          "ms_per_apply": 1000.0 * (time.perf_counter() - t0) / args.probe_reps,
+                          "sweep_rows": [list(r) for r in h.sizes.sweep_rows]}))
+        h.close()
+        return
 
     grids = tuple(int(g) for g in args.serve_grids.split(","))
     if args.serve_sweep:
