@@ -123,6 +123,7 @@ def sg_apply_bandwidth(torch, sgl, probs, stream, min_bytes=1 << 30, reps=20):
     nbuf = max(2, int(np.ceil(min_bytes / (16 * blk))))
     xs = [torch.rand(blk, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
     ys = [torch.empty(blk, dtype=torch.float64, device="cuda") for _ in range(nbuf)]
+    torch.cuda.synchronize()     # the inputs are written on torch's stream, read on `stream`
     with torch.cuda.stream(stream):
         for i in range(nbuf):
             h.apply_operator(xs[i], ys[i], stream=stream)
@@ -272,6 +273,37 @@ def serving_sweep(torch, sgl, sg_inputs, num, grids):
                               "runs": runs}}
 
 
+# preconditioner variants (Section 5: Chebyshev-5 / Chebyshev-10 / direct mass
+# solves with hGS-1; the truncations n_tau = 1 and m + 1; Algorithm 5 with N > 1)
+# as sg_options overrides
+PRECOND_VARIANTS = [
+    ("cheb5 + hGS-1 (multigrid mean blocks)", {}),
+    ("cheb10 + hGS-1", dict(cheb_steps=10)),
+    ("exact mass + hGS-1", dict(cheb_steps=0)),
+    ("cheb5 + hGS-1 (exact mean blocks)", dict(mean_solver=1)),
+    ("exact mass + hGS-1 (exact mean blocks)", dict(cheb_steps=0, mean_solver=1)),
+    ("cheb5 + Richardson N=2", dict(richardson_steps=2)),
+    ("cheb5 + hGS-1, mean-based (r = 1)", dict(truncation_r=1)),
+]
+
+
+def precond_variants(torch, sgl, sg_inputs, workload, steps, warmup):
+    wl = WORKLOADS[workload]
+    probs = make_problems(sgl, sg_inputs, wl)
+    stream = torch.cuda.Stream()
+    rows = []
+    for label, over in PRECOND_VARIANTS:
+        print(f"[bench] variant {label}", file=sys.stderr, flush=True)
+        opts = sgl.default_options(rtol=1e-8, **over)
+        dt, infos = timed_solves(torch, sgl, probs, opts, steps, warmup, stream)
+        last = infos[-1]
+        rows.append({"variant": label, "options": over, "iterations": [i.iters for i in last],
+                     "solves_per_s": steps * len(probs) / dt, "ms_per_step": 1000.0 * dt / steps,
+                     "max_rel_res": max(i.rel_res_true for i in last),
+                     "converged": all(i.converged == 1 for i in last)})
+    return {"precond_variants": workload, "steps": steps, "rows": rows}
+
+
 def cpu_baseline(wl, gpu_iters):
     """The oracle (plain FP64 numpy/scipy, BLAS threaded over every core this
     process may use) timed on the first member at the workload size.
@@ -412,6 +444,10 @@ def main():
                          "workload's first problem, strips of --sweep-rows or autotuned) --probe-reps times after one "
                          "warm-up, and exit (the kernels' hardware counters are taken on this)")
     ap.add_argument("--probe-reps", type=int, default=5)
+    ap.add_argument("--precond-variants", action="store_true",
+                    help="iterations and solves/s of the preconditioner variants of Section 5 on --workload "
+                         "(Chebyshev 5/10 or exact mass solves; multigrid or exact mean-block solves; "
+                         "Richardson steps; truncation)")
     ap.add_argument("--no-extras", action="store_true", help="skip the FP32 and single-solve comparisons")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no HIP graph replay)")
     ap.add_argument("--sweep-rows", type=int, default=0, choices=[0, 2, 4, 8],
@@ -454,6 +490,10 @@ def main():
                           "ms_per_apply": 1000.0 * (time.perf_counter() - t0) / args.probe_reps,
                           "sweep_rows": [list(r) for r in h.sizes.sweep_rows]}))
         h.close()
+        return
+
+    if args.precond_variants:
+        print(json.dumps(precond_variants(torch, sgl, sg_inputs, args.workload, args.steps, args.warmup)), flush=True)
         return
 
     grids = tuple(int(g) for g in args.serve_grids.split(","))
@@ -538,6 +578,7 @@ def main():
             solutions are in the residual norm the solver stops on."""
             d = (xa - xb).reshape(-1).contiguous()
             kd_ = torch.empty_like(d)
+            torch.cuda.synchronize()     # d is formed on torch's stream, the library reads it on `stream`
             hk.apply_kkt(d, kd_, stream=stream)
             torch.cuda.synchronize()
             return float((kd_.view(hk.members, -1).norm(dim=1) / bnorm).max())

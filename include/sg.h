@@ -109,7 +109,9 @@ typedef struct sg_problem {
  *   rtol         relative residual ||b - K x|| / ||b|| to reach [1e-8]
  *   restart      FGMRES restart length [30]
  *   max_iter     total FGMRES iterations over all cycles [600]
- *   cheb_steps   Chebyshev semi-iteration steps for mass solves [5]
+ *   cheb_steps   Chebyshev semi-iteration steps for mass solves, or 0 for
+ *                exact mass solves by the 2D sine transform (the direct
+ *                factorisation variant of Section 5) [5]
  *   truncation_r hGS truncation: modes k = 1..r-1 are kept in the off-level
  *                products (r = 1 mean-based, r = M+1 all) [0 = M+1]
  *   gmg_pre/post Chebyshev smoothing degree before/after coarse correction [2,2]
@@ -133,6 +135,16 @@ typedef struct sg_problem {
  *                cycles' Arnoldi basis and operator output in FP32 (every dot
  *                product, projection and Hessenberg entry is still formed in
  *                FP64), 0 stores them in FP64 [1]
+ *   mean_solver  solves with the mean block A-tilde_1 (eq. mathcalZ) /
+ *                A-hat_1 (eq. A_hat) inside hGS: SG_MEAN_MULTIGRID (one
+ *                geometric-multigrid V-cycle) or SG_MEAN_EXACT (exact, by the
+ *                2D sine transform on FP64 MFMA; the mean coefficient is
+ *                constant, so the block is a K + b M on the uniform grid)
+ *                [SG_MEAN_MULTIGRID]
+ *   richardson_steps  N of the preconditioned Richardson iteration of
+ *                Algorithm 5 for each Z^{-1} of the Schur block, each step
+ *                preconditioned by one hGS sweep (Algorithm 1); N = 1 is one
+ *                hGS application, as in the paper's runs [1]
  *
  * Arithmetic precision.  The stiffness sums of the SG operator, KKT apply and
  * hGS right-hand sides are formed in FP64 for FP32 storage too (an FP32
@@ -149,7 +161,12 @@ typedef struct sg_options {
     int32_t arnoldi;
     int32_t sweep_rows;
     int32_t basis_fp32;
+    int32_t mean_solver;
+    int32_t richardson_steps;
 } sg_options;
+
+#define SG_MEAN_MULTIGRID 0
+#define SG_MEAN_EXACT     1
 
 #define SG_ARNOLDI_DCGS2 0
 #define SG_ARNOLDI_CGS2  1
@@ -179,6 +196,8 @@ typedef struct sg_solve_info {
     double prof_ms;             /* profiled kernel: summed launch durations (HIP events) */
     double prof_bytes;          /* profiled kernel: summed algorithmic bytes of those launches */
     int32_t prof_launches;      /* profiled kernel: number of launches */
+    int32_t joined_batch;       /* serving: 1 if the request took the slot of a finished member of a
+                                   running batch at a restart boundary (0 otherwise, and in sg_solve) */
 } sg_solve_info;
 
 /* Sizes of a handle's problems. */
@@ -285,7 +304,13 @@ void sg_destroy(sg_handle* h);
 /* Create a server that owns a scheduler thread and its own HIP streams on the
  * current device.  hbm_budget_bytes bounds the summed footprint of admitted
  * requests (0 = 80% of free device memory); max_slots bounds requests in
- * flight.  A request whose footprint exceeds the budget is rejected. */
+ * flight.  A request whose footprint exceeds the budget is rejected.
+ * Requests of one shape (n, M, P and options) admitted together run as the
+ * members of one batch on one worker stream; batches on different workers
+ * overlap on the device.  At each restart boundary of a running batch, the
+ * slot of a member whose solve has ended is reported and handed to the oldest
+ * queued request of the batch's shape, which starts there from x = 0; its
+ * arithmetic is that of an alone solve. */
 int sg_server_create(size_t hbm_budget_bytes, int32_t max_slots, sg_server** out);
 
 /* Queue one request (problem + options are copied).  x_out: caller-owned host

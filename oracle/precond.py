@@ -13,8 +13,11 @@ Paper passages followed
   * Algorithm 1 (hGS): symmetric block Gauss-Seidel over the degree levels,
     diagonal blocks A-tilde_1, off-diagonal products truncated to the modes in
     I_tau (eq. matvec-block).
-  * Algorithm 5 with N = 1 (Section 5): each Z^{-1} is one hGS application
-    from a zero initial guess.
+  * Algorithm 5 (preconditioned Richardson): each Z^{-1} is N steps from a
+    zero initial guess, x <- x + hGS(b - Z_r x); N = 1 (the paper's runs) is
+    one hGS application.
+  * Section 5: the mass blocks by Chebyshev semi-iteration (5 or 10 steps) or
+    by a direct (Cholesky) factorisation of M.
   * Section 3.1, eq. (precon for time), eq. (Z hat approx), eq. (A_hat) and
     Algorithm 4: the time-dependent preconditioner
     blkdiag(tau D (x) M_gamma, tau beta D (x) M, S-tilde) with Z-tilde
@@ -199,7 +202,9 @@ class GMG:
 
 
 class ExactSolve:
-    """Exact inverse of A = a K + b M (sparse LU), for the ideal preconditioner."""
+    """Exact inverse of A = a K + b M (sparse LU with one step of iterative
+    refinement, so the result is the exact solve to rounding), for the ideal
+    preconditioner and the exact mean-block option."""
 
     def __init__(self, n: int, a: float, b: float):
         K = fem.restrict(fem.assemble_full(n, 1.0, "stiffness"), n)
@@ -208,8 +213,10 @@ class ExactSolve:
         self.lu = spla.splu(self.A)
 
     def apply(self, B: np.ndarray) -> np.ndarray:
-        B = np.atleast_2d(B)
-        return self.lu.solve(np.ascontiguousarray(B.T)).T
+        B = np.ascontiguousarray(np.atleast_2d(B).T)
+        X = self.lu.solve(B)
+        X = X + self.lu.solve(np.ascontiguousarray(B - self.A @ X))
+        return X.T
 
 
 # ----------------------------------------------------------------------------
@@ -265,31 +272,46 @@ def hgs(sg: kkt.SG, R: np.ndarray, inner, r_trunc: int) -> np.ndarray:
     return V
 
 
-def schur_inverse(sg: kkt.SG, R: np.ndarray, inner, r_trunc: int) -> np.ndarray:
-    """Steady: S^{-1} r ~ Z^{-1} M_gamma Z^{-1} r with each Z^{-1} one hGS.
-    Time-dependent (R has a leading n_t axis): per step t,
-    tau Z_t^{-1} (D_tt M_gamma) Z_t^{-1} r_t."""
+def richardson(sg: kkt.SG, R: np.ndarray, inner, r_trunc: int, steps: int = 1) -> np.ndarray:
+    """Algorithm 5: N = steps preconditioned Richardson steps on Z_r X = R
+    (R, X of shape (n_xi, n_int)) from X = 0, each preconditioned by one hGS
+    (Algorithm 1): X <- X + hGS(R - Z_r X)."""
+    X = hgs(sg, R, inner, r_trunc)
+    if steps > 1:
+        Z = z_truncated(sg, r_trunc)
+        for _ in range(steps - 1):
+            res = R - (Z @ X.ravel()).reshape(R.shape)
+            X = X + hgs(sg, res, inner, r_trunc)
+    return X
+
+
+def schur_inverse(sg: kkt.SG, R: np.ndarray, inner, r_trunc: int, richardson_steps: int = 1) -> np.ndarray:
+    """Steady: S^{-1} r ~ Z^{-1} M_gamma Z^{-1} r with each Z^{-1} Richardson
+    (one hGS for N = 1).  Time-dependent (R has a leading n_t axis): per step
+    t, tau Z_t^{-1} (D_tt M_gamma) Z_t^{-1} r_t."""
     p = sg.prob
     hg = kkt.h_gamma(sg)[:, None]
+    zinv = lambda B: richardson(sg, B, inner, r_trunc, richardson_steps)   # noqa: E731
     if p.steady:
-        V = hgs(sg, R, inner, r_trunc)
+        V = zinv(R)
         W = hg * kkt.mass_apply(sg, V)
-        return hgs(sg, W, inner, r_trunc)
+        return zinv(W)
     nt, tau = p.n_t, p.tau
     D = np.ones(nt)
     D[0] = D[-1] = 0.5
     out = np.empty_like(R)
     for t in range(nt):
-        V = hgs(sg, R[t], inner, r_trunc)
+        V = zinv(R[t])
         W = D[t] * hg * kkt.mass_apply(sg, V)
-        out[t] = tau * hgs(sg, W, inner, r_trunc)
+        out[t] = tau * zinv(W)
     return out
 
 
 def precond_apply(sg: kkt.SG, r: np.ndarray, inner=None, r_trunc: int | None = None,
-                  cheb_steps: int = 5) -> np.ndarray:
+                  cheb_steps: int = 5, richardson_steps: int = 1) -> np.ndarray:
     """Block-diagonal preconditioner of eq. (stoch-prec) / eq. (precon for time)
-    applied to a flat KKT vector."""
+    applied to a flat KKT vector.  cheb_steps = 0: the mass blocks by a direct
+    factorisation of M (the paper's Cholesky variant)."""
     p = sg.prob
     if inner is None:
         inner = make_inner(sg)
@@ -309,11 +331,19 @@ def precond_apply(sg: kkt.SG, r: np.ndarray, inner=None, r_trunc: int | None = N
         for t in range(nt):
             Zy[t] = kkt_cheb(sg, Ry[t], cheb_steps) / (tau * D[t] * hg)
             Zu[t] = kkt_cheb(sg, Ru[t], cheb_steps) / (p.beta * tau * D[t])
-    Zl = schur_inverse(sg, Rl, inner, r_trunc)
+    Zl = schur_inverse(sg, Rl, inner, r_trunc, richardson_steps)
     return np.concatenate([Zy.ravel(), Zu.ravel(), Zl.ravel()])
 
 
 def kkt_cheb(sg: kkt.SG, R: np.ndarray, steps: int) -> np.ndarray:
+    """M^{-1} applied to the rows of R: Chebyshev with `steps` steps, or
+    exactly (sparse Cholesky-equivalent LU of M) when steps == 0."""
+    if steps == 0:
+        Mc = sp.csc_matrix(sg.Mi)
+        lu = spla.splu(Mc)
+        B = np.ascontiguousarray(np.atleast_2d(R).T)
+        X = lu.solve(B)
+        return (X + lu.solve(np.ascontiguousarray(B - Mc @ X))).T
     return cheb_mass(sg.Mi, R, steps)
 
 

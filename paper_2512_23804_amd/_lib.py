@@ -22,6 +22,7 @@ SG_PREC_FP64, SG_PREC_FP32_REFINE, SG_PREC_FP32_PRECOND = 0, 1, 2
 SG_PROF_NONE, SG_PROF_KKT_APPLY, SG_PROF_MG_SMOOTH, SG_PROF_MULTIDOT, SG_PROF_HGS_RHS = 0, 1, 2, 3, 4
 SG_PROF_ARNOLDI_UPD, SG_PROF_MG_TAIL, SG_PROF_MASS_CHEB, SG_PROF_MG_UP = 5, 6, 7, 8
 SG_ARNOLDI_DCGS2, SG_ARNOLDI_CGS2 = 0, 1
+SG_MEAN_MULTIGRID, SG_MEAN_EXACT = 0, 1
 
 _DP = C.POINTER(C.c_double)
 
@@ -37,14 +38,16 @@ class sg_options(C.Structure):
                 ("cheb_steps", C.c_int32), ("truncation_r", C.c_int32), ("gmg_pre", C.c_int32),
                 ("gmg_post", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
                 ("use_graphs", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
-                ("arnoldi", C.c_int32), ("sweep_rows", C.c_int32), ("basis_fp32", C.c_int32)]
+                ("arnoldi", C.c_int32), ("sweep_rows", C.c_int32), ("basis_fp32", C.c_int32),
+                ("mean_solver", C.c_int32), ("richardson_steps", C.c_int32)]
 
 
 class sg_solve_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer_refinements", C.c_int32), ("converged", C.c_int32),
                 ("status", C.c_int32), ("rel_res_true", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_solve_ms", C.c_double), ("latency_ms", C.c_double), ("bytes_moved", C.c_double),
-                ("prof_ms", C.c_double), ("prof_bytes", C.c_double), ("prof_launches", C.c_int32)]
+                ("prof_ms", C.c_double), ("prof_bytes", C.c_double), ("prof_launches", C.c_int32),
+                ("joined_batch", C.c_int32)]
 
 
 class sg_sizes(C.Structure):

@@ -39,6 +39,7 @@ constexpr int kMaxSmooth = 4;    // Chebyshev smoothing degree per side
 constexpr int kCoarseN = 8;      // coarsest multigrid grid (elements per side)
 constexpr int kCoarsePad = 64;   // (kCoarseN-1)^2 = 49 unknowns padded for MFMA tiles
 constexpr int kMaxRestart = 64;
+constexpr int kPinnedDoubles = 16384;   // host-pinned scratch per handle (readbacks and uploads, up to 2048 members)
 
 // Per-member scalars used by the kernels (device array, one entry per member).
 struct MemberDev {
@@ -115,12 +116,13 @@ struct OpDev {                   // device pointers describing the operator of a
     int64_t coef_mstride;        // elements per member (0 = shared)
     const MemberDev* mem;        // [member]
     int mem_shared;              // 1 = all vectors use member 0
+    const int* active;           // [vector] skip vectors whose flag is 0 (null: process all)
 };
 
 // Element-sweep kernels (sweep.hip); return false when the shape needs the
 // generic kernels (more than 8 random variables).
 template <typename T>
-bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
+bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, uint32_t mask, hipStream_t st);
 template <typename T>
 bool launch_sgx_kkt(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
 template <typename T>
@@ -128,10 +130,11 @@ bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, i
                         const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
                         hipStream_t st);
 
-// SG apply family.  `modes_mask` selects modes 1..M (bit k-1); mode 0 (mean,
-// constant coefficient) is applied when with_mean != 0.
+// SG apply y = sum_k (G_k (x) K_k) x: the mean (k = 0) and the modes k with
+// bit k-1 of `mask` set (all ones: the full operator; the truncated Z_r of
+// Richardson steps keeps k < r).
 template <typename T>
-void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
+void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, uint32_t mask, hipStream_t st);
 
 template <typename T>
 void launch_kkt_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st);
@@ -157,19 +160,40 @@ void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap
 // residual + restriction; up = the same pre-smoothing recomputed from b +
 // prolongation of the coarse correction + npost post-smoothing steps.  Coarse
 // arrays are contiguous [column][(m/2+1)^2].
+// Columns c with act != null and act[c / cpv] == 0 are skipped (cpv: columns
+// per vector).
 template <typename T>
 void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, int ncols, int cpm,
-                    hipStream_t st);
+                    const int* act, int cpv, hipStream_t st);
 template <typename T>
 void launch_mg_up(int m, const LevelDev* lev, int lvl, int npre, int npost, const T* ec, const T* b, ColMap bmap,
-                  T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st);
+                  T* xo, ColMap xomap, int ncols, int cpm, const int* act, int cpv, hipStream_t st);
 template <typename T>
 void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x,
-                    ColMap xmap, const T* ainv, int ncols, int cpm, hipStream_t st);
+                    ColMap xmap, const T* ainv, int ncols, int cpm, const int* act, int cpv, hipStream_t st);
 
 // All Chebyshev mass steps in one LDS-tiled kernel; false when steps > 9.
 template <typename T>
 bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, int steps, hipStream_t st);
+
+// Exact solve by the 2D sine transform (dst.hip) on ncols columns:
+// mode 1: x = (a1 K + b1 M)^{-1} b with the scalars of member c / cpm;
+// mode 2: the mass blocks, x = f M^{-1} b with the column scale f of the
+// Chebyshev mass kernels (columns of [y | u] of nt * nxi each per vector).
+// sintab: sin(pi m / n), m < 2n; eig: [2][n+1] 1D stiffness / mass
+// eigenvalues; s1, s2: FP64 scratch of ncols * (n+1)^2 each.
+template <typename T>
+void launch_dst_solve(int n, int mode, const MemberDev* mem, int shared, const double* sintab, const double* eig,
+                      const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, int cpm, int nt, int nxi, int time, double* s1,
+                      double* s2, const int* act, int cpv, hipStream_t st);
+// Richardson residual out = R - off_scale Y - b1 M V per column (member c / cpv).
+template <typename T>
+void launch_z_residual(int n, const T* R, ColMap rmap, const T* Y, const T* V, ColMap vmap, T* out, ColMap omap,
+                       const MemberDev* mem, int ncols, int cpv, int shared, const int* act, hipStream_t st);
+// out = A + B column by column.
+template <typename T>
+void launch_cols_add(int64_t nodes, const T* A, ColMap amap, const T* Bv, ColMap bmap, T* out, ColMap omap, int ncols,
+                     int cpv, const int* act, hipStream_t st);
 
 // Multigrid coarsest level: x = A_c^{-1} b (FP64 MFMA, FP32 plain).
 template <typename T>
@@ -220,7 +244,11 @@ struct KrylovDev {
     double* nrm;      // [member] ||w2||^2 then 1/||w2||
     double* y;        // [member][restart]
     double* resid;    // [member] |g_{j+1}| (estimate)
-    int* active;      // [member] 1 while iterating in the current cycle
+    int* active;      // [member] 1 while iterating in the current cycle (cleared by k_conv_check)
+    int* iters;       // [member] iterations so far (all cycles of the solve)
+    const int* itmax; // [member] iteration limit
+    int* jend;        // [member] iterations of the current cycle
+    const double* tol;   // [member] stop when the estimate reaches this
     double* dots;     // [member][kSlots] reduced dot products of the current pass (DCGS2)
     double* scal;     // [member][4] -, -, 1/nu, nu of the current candidate (DCGS2)
     double* R;        // [member][(restart+1)^2] U = V R, upper triangular, column-major (DCGS2)
@@ -240,5 +268,10 @@ void launch_dcgs_update(TV* V, int64_t vstride, int nv, const TV* w, int64_t n, 
 void launch_dcgs_finish(KrylovDev k, int restart, int j, int mode, int nmem, hipStream_t st);
 void launch_cycle_start(KrylovDev k, int restart, const double* beta0, int nmem, hipStream_t st);
 void launch_back_solve(KrylovDev k, int restart, const int* jend, int nmem, hipStream_t st);
+// End of iteration j: every active member counts the iteration (jend = j + 1,
+// iters + 1) and stops once its estimate reaches tol or iters reaches itmax.
+// Launched after the iteration's last pass, so every pass of iteration j saw
+// the flags of its start.
+void launch_conv_check(KrylovDev k, int j, int nmem, hipStream_t st);
 
 }  // namespace sg

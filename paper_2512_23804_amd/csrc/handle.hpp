@@ -225,12 +225,16 @@ struct Handle {
     double* d_ainv64 = nullptr;
     float* d_ainv32 = nullptr;
     double* d_rhs = nullptr;
+    double* d_dst = nullptr;            // sine-transform tables: [2n] sin(pi m / n), [n+1] k_p, [n+1] m_p
 
     Workspace ws;
     Prof prof;
     GraphCache graphs;
-    double* h_pinned = nullptr;        // host-pinned scratch for small readbacks
+    double* h_pinned = nullptr;        // host-pinned scratch for small readbacks and uploads
     size_t h_pinned_count = 0;
+    // per-vector activity flags the operator and preconditioner kernels honour
+    // (set by FGMRES around its iterations; null: every vector is processed)
+    const int* active = nullptr;
 
     uint32_t modes_mask() const {
         const int r = opt.truncation_r <= 0 ? s.M + 1 : opt.truncation_r;
@@ -248,6 +252,7 @@ struct Handle {
         o.coef_mstride = shared ? 0 : (int64_t)(s.M + 1) * s.n * s.n;
         o.mem = d_mem;
         o.mem_shared = shared ? 1 : 0;
+        o.active = active;
         return o;
     }
     template <typename T>
@@ -266,6 +271,10 @@ void validate(const sg_problem* probs, int count, const sg_options* opt);   // t
 void autotune(Handle& h);   // tune.cpp: strip heights of the sweep kernels (sg_options.sweep_rows)
 std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt, hipStream_t st,
                                      DevicePool* pool = nullptr);
+// Replace member b's problem (same n, M, P, n_t and options as the handle):
+// its coefficient modes, scalars, multigrid constants, coarse inverse and
+// right-hand side, on the handle's stream (returns after the copies).
+void set_member(Handle& h, int b, const sg_problem& p);
 std::vector<int32_t> multi_indices(int M, int P);
 int binom(int n, int k);
 
@@ -287,6 +296,23 @@ void* noalloc_scratch(int device);
 size_t noalloc_scratch_bytes();
 template <typename T>
 void operator_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st);
-int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info);
+// Source of problems for the member slots of a running solve (serving).  At
+// every restart boundary the solve reports each member whose solve has ended
+// (done) and then asks for a problem for every free slot (next); a slot
+// filled there starts from x = 0 with the problem's own right-hand side, so
+// its arithmetic is that of an alone solve.
+struct SlotFeed {
+    virtual ~SlotFeed() = default;
+    // slot q ended: its FP64 solution is x_member (device, one KKT vector,
+    // valid until the slot is refilled), its report info
+    virtual void done(int q, const double* x_member, const sg_solve_info& info, hipStream_t st) = 0;
+    // a problem for free slot q, of the handle's shape and options (its arrays
+    // stay valid until done(q) reports it), or false
+    virtual bool next(int q, sg_problem& p) = 0;
+};
+// b_dev null: the handle's own right-hand sides.  With a feed, x_dev is the
+// batch's working solution and the members' results go through the feed;
+// info may then be null.
+int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, SlotFeed* feed = nullptr);
 
 }  // namespace sg

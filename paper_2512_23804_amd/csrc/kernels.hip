@@ -127,7 +127,7 @@ constexpr int kJChunk = 8;
 // --------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_sg_apply(int n, int M, int nxi, int nt, int64_t nodes,
-                                                  OpDev op, const T* __restrict__ x, T* __restrict__ y) {
+                                                  OpDev op, const T* __restrict__ x, T* __restrict__ y, uint32_t mask) {
     int ix, iy;
     tile_coords(n, blockIdx.x, ix, iy);
     if (ix > n || iy > n) return;
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_sg_apply(int n, int M, int nxi, int nt,
         double v = 0.0;
         if (interior)
             v = sg_node<T>(X, nodes, j, n, ix, iy, M, op.nbr_idx, op.nbr_val, coef, cplane, c0, true,
-                           0xffffffffu, true, true);
+                           mask, true, true);
         Y[(int64_t)j * nodes + p] = (T)v;
     }
 }
@@ -170,6 +170,7 @@ __global__ __launch_bounds__(256) void k_kkt_apply(int n, int M, int nxi, int nt
     if (ix > n || iy > n) return;
     const int slice = blockIdx.z;
     const int vec = slice / nt;
+    if (op.active && !op.active[vec]) return;
     const int t = slice % nt;
     const int mem = op.mem_shared ? 0 : vec;
     const int64_t blk = (int64_t)nt * nxi * nodes;
@@ -244,6 +245,7 @@ __global__ __launch_bounds__(256) void k_hgs_rhs(int n, int M, int nxi, int nt, 
     if (ix > n || iy > n) return;
     const int slice = blockIdx.z;           // member*nt + t
     const int mem_i = slice / nt;
+    if (op.active && !op.active[mem_i]) return;
     const int t = slice % nt;
     const int mem = op.mem_shared ? 0 : mem_i;
     const double* coef = op.coef64 + (int64_t)mem * op.coef_mstride;
@@ -284,6 +286,7 @@ __global__ __launch_bounds__(256) void k_mass_cheb_step(int n, int nxi, int nt, 
     tile_coords(n, blockIdx.x, ix, iy);
     if (ix > n || iy > n) return;
     const int vec = blockIdx.z;
+    if (op.active && !op.active[vec]) return;
     const int mem = op.mem_shared ? 0 : vec;
     const int64_t p = (int64_t)iy * (n + 1) + ix;
     const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
@@ -338,6 +341,7 @@ __global__ __launch_bounds__(256) void k_mass_scaled(int n, int nt, int time, Op
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c = blockIdx.y * 4 + wave;
     if (c >= ncols) return;                          // uniform per wavefront; no barriers below
+    if (op.active && !op.active[vmap.member(c)]) return;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int lane = threadIdx.x & 63;
     const int gl = lane & 31, grp = lane >> 5;
@@ -1232,6 +1236,59 @@ __global__ void k_back_solve(KrylovDev k, int restart, const int* jend, int nmem
     }
 }
 
+// Richardson residual on field columns: out = R - off_scale Y - b1 M V (the
+// mean block's mass part and the off-level SG products Y = SG_r(V) of
+// Z_r = I (x) (a1 K + b1 M) + off_scale sum_k G_k (x) K_k, whose a1 K part Y
+// also carries); member of column c = c / cpv (0 when shared).
+template <typename T>
+__global__ void k_z_residual(int n, const T* __restrict__ R, ColMap rmap, const T* __restrict__ Y,
+                             const T* __restrict__ V, ColMap vmap, T* __restrict__ out, ColMap omap,
+                             const MemberDev* __restrict__ mem, int cpv, int shared, const int* __restrict__ act) {
+    const int c = blockIdx.y;
+    const int vec = c / cpv;
+    if (act && !act[vec]) return;
+    const int N1 = n + 1;
+    const int64_t nodes = (int64_t)N1 * N1;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nodes) return;
+    const int ix = (int)(q % N1), iy = (int)(q / N1);
+    T* o = out + omap.off(c);
+    if (ix == 0 || iy == 0 || ix == n || iy == n) {
+        o[q] = T(0);
+        return;
+    }
+    const MemberDev md = mem[shared ? 0 : vec];
+    const T* v = V + vmap.off(c);
+    const double h = 1.0 / n;
+    const double w = h * h / 36.0;
+    const double m9 = w * (16.0 * (double)v[q] +
+                           4.0 * ((double)v[q - 1] + (double)v[q + 1] + (double)v[q - N1] + (double)v[q + N1]) +
+                           ((double)v[q - N1 - 1] + (double)v[q - N1 + 1] + (double)v[q + N1 - 1] +
+                            (double)v[q + N1 + 1]));
+    const double y = (double)Y[vmap.off(c) + q];
+    o[q] = (T)((double)R[rmap.off(c) + q] - md.off_scale * y - md.b1 * m9);
+}
+
+// out = A + B column by column (every node)
+template <typename T>
+__global__ void k_cols_add(int64_t nodes, const T* __restrict__ A, ColMap amap, const T* __restrict__ Bv, ColMap bmap,
+                           T* __restrict__ out, ColMap omap, int cpv, const int* __restrict__ act) {
+    const int c = blockIdx.y;
+    if (act && !act[c / cpv]) return;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nodes) return;
+    out[omap.off(c) + q] = A[amap.off(c) + q] + Bv[bmap.off(c) + q];
+}
+
+__global__ void k_conv_check(KrylovDev k, int j, int nmem) {
+    const int mem = blockIdx.x * blockDim.x + threadIdx.x;
+    if (mem >= nmem || !k.active[mem]) return;
+    k.jend[mem] = j + 1;
+    const int it = k.iters[mem] + 1;
+    k.iters[mem] = it;
+    if (k.resid[mem] <= k.tol[mem] || it >= k.itmax[mem]) k.active[mem] = 0;
+}
+
 int grid1d(int64_t n) {
     int64_t b = (n + 255) / 256;
     if (b > 8192) b = 8192;
@@ -1251,10 +1308,10 @@ dim3 tile_grid(int n, int nchunks, int64_t slices) {
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T>
-void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
-    if (launch_sgx_apply<T>(s, op, x, y, nvec, st)) return;
+void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, uint32_t mask, hipStream_t st) {
+    if (launch_sgx_apply<T>(s, op, x, y, nvec, mask, st)) return;
     dim3 g = tile_grid(s.n, (s.nxi + kJChunk - 1) / kJChunk, (int64_t)nvec * s.nt);
-    hipLaunchKernelGGL(k_sg_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, x, y);
+    hipLaunchKernelGGL(k_sg_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, x, y, mask);
     SG_HIP(hipGetLastError());
 }
 
@@ -1525,9 +1582,35 @@ void launch_back_solve(KrylovDev k, int restart, const int* jend, int nmem, hipS
     SG_HIP(hipGetLastError());
 }
 
+template <typename T>
+void launch_z_residual(int n, const T* R, ColMap rmap, const T* Y, const T* V, ColMap vmap, T* out, ColMap omap,
+                       const MemberDev* mem, int ncols, int cpv, int shared, const int* act, hipStream_t st) {
+    if (ncols < 1) return;
+    if (ncols > 65535) throw Error(SG_ERR_INVALID, "Richardson residual: too many columns in one launch");
+    const int64_t nodes = (int64_t)(n + 1) * (n + 1);
+    hipLaunchKernelGGL(k_z_residual<T>, dim3((unsigned)((nodes + 255) / 256), ncols), dim3(256), 0, st, n, R, rmap, Y,
+                       V, vmap, out, omap, mem, cpv, shared, act);
+    SG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_cols_add(int64_t nodes, const T* A, ColMap amap, const T* Bv, ColMap bmap, T* out, ColMap omap, int ncols,
+                     int cpv, const int* act, hipStream_t st) {
+    if (ncols < 1) return;
+    if (ncols > 65535) throw Error(SG_ERR_INVALID, "column add: too many columns in one launch");
+    hipLaunchKernelGGL(k_cols_add<T>, dim3((unsigned)((nodes + 255) / 256), ncols), dim3(256), 0, st, nodes, A, amap,
+                       Bv, bmap, out, omap, cpv, act);
+    SG_HIP(hipGetLastError());
+}
+
+void launch_conv_check(KrylovDev k, int j, int nmem, hipStream_t st) {
+    hipLaunchKernelGGL(k_conv_check, dim3((nmem + 63) / 64), dim3(64), 0, st, k, j, nmem);
+    SG_HIP(hipGetLastError());
+}
+
 // explicit instantiations
 #define SG_INST(T)                                                                                          \
-    template void launch_sg_apply<T>(const Shape&, const OpDev&, const T*, T*, int, hipStream_t);           \
+    template void launch_sg_apply<T>(const Shape&, const OpDev&, const T*, T*, int, uint32_t, hipStream_t); \
     template void launch_kkt_apply<T>(const Shape&, const OpDev&, const T*, T*, int, hipStream_t);          \
     template void launch_hgs_rhs<T>(const Shape&, const OpDev&, int, uint32_t, int, int, const T*, ColMap,  \
                                     const T*, ColMap, T*, ColMap, int, hipStream_t);                        \
@@ -1535,7 +1618,11 @@ void launch_back_solve(KrylovDev k, int restart, const int* jend, int nmem, hipS
                                       hipStream_t);                                                         \
     template void launch_mass_scaled<T>(const Shape&, const OpDev&, const T*, ColMap, T*, ColMap, int, int, \
                                         hipStream_t);                                                       \
-    template void launch_zero_ring<T>(T*, int, int64_t, hipStream_t);
+    template void launch_zero_ring<T>(T*, int, int64_t, hipStream_t);                                      \
+    template void launch_z_residual<T>(int, const T*, ColMap, const T*, const T*, ColMap, T*, ColMap,        \
+                                       const MemberDev*, int, int, int, const int*, hipStream_t);           \
+    template void launch_cols_add<T>(int64_t, const T*, ColMap, const T*, ColMap, T*, ColMap, int, int,    \
+                                     const int*, hipStream_t);
 SG_INST(double)
 SG_INST(float)
 

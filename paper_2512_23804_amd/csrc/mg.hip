@@ -19,6 +19,14 @@ namespace sg {
 
 namespace {
 
+// Column skip of the multigrid kernels: column c is skipped when act != null
+// and act[c / cpv] == 0 (cpv: columns per vector).
+struct Skip {
+    const int* act;
+    int cpv;
+};
+
+
 template <typename T>
 __device__ __forceinline__ T st9(const T* s, int W, int i, T wc, T we, T wd) {
     return wc * s[i] + we * (s[i - 1] + s[i + 1] + s[i - W] + s[i + W]) +
@@ -135,11 +143,12 @@ __device__ __forceinline__ void load_region(T (&breg)[PPT], const T* __restrict_
 template <typename T, int TC, int NU>
 __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restrict__ lev, int lvl,
                                                  const T* __restrict__ b, ColMap bmap, T* __restrict__ bc, int cpm,
-                                                 int tiles_x) {
+                                                 int tiles_x, Skip sk) {
     constexpr int W = 2 * TC + 1 + 2 * NU;
     constexpr int PPT = (W * W + 255) / 256;
     __shared__ T sx[W * W];
     const int c = blockIdx.y;
+    if (sk.act && !sk.act[c / sk.cpv]) return;       // uniform per block, before any barrier
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int I0 = 1 + tx * TC, J0 = 1 + ty * TC;
     const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;     // also write the ring at index 0
@@ -192,13 +201,14 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
 template <typename T, int TF, int NPRE, int NPOST>
 __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict__ lev, int lvl,
                                                const T* __restrict__ ec, const T* __restrict__ b, ColMap bmap,
-                                               T* __restrict__ xo, ColMap xomap, int cpm, int tiles_x) {
+                                               T* __restrict__ xo, ColMap xomap, int cpm, int tiles_x, Skip sk) {
     constexpr int H0 = NPRE - 1;
     constexpr int H = NPOST + H0;
     constexpr int W = TF + 2 * H;
     constexpr int PPT = (W * W + 255) / 256;
     __shared__ T sx[W * W];
     const int c = blockIdx.y;
+    if (sk.act && !sk.act[c / sk.cpv]) return;       // uniform per block, before any barrier
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int FX0 = 1 + tx * TF - H, FY0 = 1 + ty * TF - H;
     const int ex = tx == 0 ? 1 : 0, ey = ty == 0 ? 1 : 0;
@@ -310,6 +320,7 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     const SG g;
     const int l = blockIdx.y;
     const int vec = blockIdx.z;
+    if (op.active && !op.active[vec]) return;        // uniform per block, before any barrier
     const int mem = op.mem_shared ? 0 : vec;
     const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
     const int FX0 = 1 + tx * TF - HR, FY0 = 1 + ty * TF - HR;
@@ -549,7 +560,7 @@ template <typename T, int M0>
 __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __restrict__ lev, int lvl0, int npre,
                                                           int npost, const T* __restrict__ b, ColMap bmap,
                                                           T* __restrict__ x, ColMap xmap, const T* __restrict__ ainv,
-                                                          int cpm) {
+                                                          int cpm, Skip sk) {
     using Lds = TailLds<T, M0>;
     constexpr int NL = Lds::NL;
     constexpr int W0 = Lds::W0;
@@ -558,6 +569,7 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __rest
     __shared__ LevelDev slev[NL > 1 ? NL - 1 : 1];
     __shared__ T sA[CNU * CNU];             // interior block of the coarse inverse
     const int c = blockIdx.x;
+    if (sk.act && !sk.act[c / sk.cpv]) return;       // uniform per block, before any barrier
     const int mem = c / cpm;
     // issue every global read first, into registers (clamped addresses): the
     // column, the level parameters and the coarse inverse (consumed only after
@@ -618,9 +630,9 @@ __global__ __launch_bounds__(kTailThreads) void k_mg_tail(const LevelDev* __rest
 
 template <typename T, int M0>
 void tail_m(const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x, ColMap xmap,
-            const T* ainv, int ncols, int cpm, hipStream_t st) {
+            const T* ainv, int ncols, int cpm, Skip sk, hipStream_t st) {
     hipLaunchKernelGGL((k_mg_tail<T, M0>), dim3(ncols), dim3(kTailThreads), 0, st, lev, lvl0, npre, npost, b, bmap,
-                       x, xmap, ainv, cpm);
+                       x, xmap, ainv, cpm, sk);
 }
 
 template <typename T, int H>
@@ -639,30 +651,31 @@ constexpr int TCD = 16;   // coarse nodes per down tile side
 constexpr int TFU = 32;   // fine nodes per up tile side
 
 template <typename T, int NU>
-void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* bc, int ncols, int cpm, hipStream_t st) {
+void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* bc, int ncols, int cpm, Skip sk,
+             hipStream_t st) {
     const int mc = m / 2;
     const int tx = (mc - 1 + TCD - 1) / TCD;
     dim3 grid(tx * tx, ncols);
-    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, bc, cpm, tx);
+    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, bc, cpm, tx, sk);
 }
 
 template <typename T, int NPRE, int NPOST>
 void up_nu(int m, const LevelDev* lev, int lvl, const T* ec, const T* b, ColMap bmap, T* xo, ColMap xomap, int ncols,
-           int cpm, hipStream_t st) {
+           int cpm, Skip sk, hipStream_t st) {
     const int tx = (m - 1 + TFU - 1) / TFU;
     dim3 grid(tx * tx, ncols);
     hipLaunchKernelGGL((k_mg_up<T, TFU, NPRE, NPOST>), grid, dim3(256), 0, st, m, lev, lvl, ec, b, bmap, xo, xomap,
-                       cpm, tx);
+                       cpm, tx, sk);
 }
 
 template <typename T, int NPRE>
 void up_pre(int m, const LevelDev* lev, int lvl, int npost, const T* ec, const T* b, ColMap bmap, T* xo, ColMap xomap,
-            int ncols, int cpm, hipStream_t st) {
+            int ncols, int cpm, Skip sk, hipStream_t st) {
     switch (npost) {
-        case 1: up_nu<T, NPRE, 1>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 2: up_nu<T, NPRE, 2>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 3: up_nu<T, NPRE, 3>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 4: up_nu<T, NPRE, 4>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 1: up_nu<T, NPRE, 1>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
+        case 2: up_nu<T, NPRE, 2>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
+        case 3: up_nu<T, NPRE, 3>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
+        case 4: up_nu<T, NPRE, 4>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
         default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     }
 }
@@ -671,13 +684,14 @@ void up_pre(int m, const LevelDev* lev, int lvl, int npost, const T* ec, const T
 
 template <typename T>
 void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, int ncols, int cpm,
-                    hipStream_t st) {
+                    const int* act, int cpv, hipStream_t st) {
     if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
+    const Skip sk{act, cpv};
     switch (npre) {
-        case 1: down_nu<T, 1>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
-        case 2: down_nu<T, 2>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
-        case 3: down_nu<T, 3>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
-        case 4: down_nu<T, 4>(m, lev, lvl, b, bmap, bc, ncols, cpm, st); break;
+        case 1: down_nu<T, 1>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
+        case 2: down_nu<T, 2>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
+        case 3: down_nu<T, 3>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
+        case 4: down_nu<T, 4>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
         default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     }
     SG_HIP(hipGetLastError());
@@ -685,13 +699,14 @@ void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, C
 
 template <typename T>
 void launch_mg_up(int m, const LevelDev* lev, int lvl, int npre, int npost, const T* ec, const T* b, ColMap bmap,
-                  T* xo, ColMap xomap, int ncols, int cpm, hipStream_t st) {
+                  T* xo, ColMap xomap, int ncols, int cpm, const int* act, int cpv, hipStream_t st) {
     if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
+    const Skip sk{act, cpv};
     switch (npre) {
-        case 1: up_pre<T, 1>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 2: up_pre<T, 2>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 3: up_pre<T, 3>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
-        case 4: up_pre<T, 4>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, st); break;
+        case 1: up_pre<T, 1>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
+        case 2: up_pre<T, 2>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
+        case 3: up_pre<T, 3>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
+        case 4: up_pre<T, 4>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
         default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     }
     SG_HIP(hipGetLastError());
@@ -699,14 +714,15 @@ void launch_mg_up(int m, const LevelDev* lev, int lvl, int npre, int npost, cons
 
 template <typename T>
 void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x,
-                    ColMap xmap, const T* ainv, int ncols, int cpm, hipStream_t st) {
+                    ColMap xmap, const T* ainv, int ncols, int cpm, const int* act, int cpv, hipStream_t st) {
     if (ncols < 1) return;
+    const Skip sk{act, cpv};
     if (npre < 1 || npre > kMaxSmooth || npost < 0 || npost > kMaxSmooth)
         throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     switch (m0) {
-        case 16: tail_m<T, 16>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, st); break;
-        case 32: tail_m<T, 32>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, st); break;
-        case 64: tail_m<T, 64>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, st); break;
+        case 16: tail_m<T, 16>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, sk, st); break;
+        case 32: tail_m<T, 32>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, sk, st); break;
+        case 64: tail_m<T, 64>(lev, lvl0, npre, npost, b, bmap, x, xmap, ainv, ncols, cpm, sk, st); break;
         default: throw Error(SG_ERR_INVALID, "multigrid tail level must be 16, 32 or 64");
     }
     SG_HIP(hipGetLastError());
@@ -742,16 +758,16 @@ template bool launch_mass_cheb_fused<double>(const Shape&, const OpDev&, const d
 template bool launch_mass_cheb_fused<float>(const Shape&, const OpDev&, const float*, float*, int, int, hipStream_t);
 
 template void launch_mg_tail<double>(int, const LevelDev*, int, int, int, const double*, ColMap, double*, ColMap,
-                                     const double*, int, int, hipStream_t);
+                                     const double*, int, int, const int*, int, hipStream_t);
 template void launch_mg_tail<float>(int, const LevelDev*, int, int, int, const float*, ColMap, float*, ColMap,
-                                    const float*, int, int, hipStream_t);
+                                    const float*, int, int, const int*, int, hipStream_t);
 template void launch_mg_down<double>(int, const LevelDev*, int, int, const double*, ColMap, double*, int, int,
-                                     hipStream_t);
+                                     const int*, int, hipStream_t);
 template void launch_mg_down<float>(int, const LevelDev*, int, int, const float*, ColMap, float*, int, int,
-                                    hipStream_t);
+                                    const int*, int, hipStream_t);
 template void launch_mg_up<double>(int, const LevelDev*, int, int, int, const double*, const double*, ColMap, double*,
-                                   ColMap, int, int, hipStream_t);
+                                   ColMap, int, int, const int*, int, hipStream_t);
 template void launch_mg_up<float>(int, const LevelDev*, int, int, int, const float*, const float*, ColMap, float*,
-                                  ColMap, int, int, hipStream_t);
+                                  ColMap, int, int, const int*, int, hipStream_t);
 
 }  // namespace sg

@@ -35,6 +35,7 @@ struct Request {
     Clock::time_point t_submit;
     int state = 0;          // 0 queued, 1 running, 2 done, 3 cancelled
     int status = SG_PENDING;
+    int joined = 0;         // 1: took a finished member's slot in a running batch
     sg_solve_info info{};
 };
 
@@ -91,7 +92,83 @@ struct sg_server {
     void schedule_loop();
     void worker_loop(int id);
     void run_batch(const std::vector<uint64_t>& ids, hipStream_t st);
+    // completion of request r (lock held)
+    void finish(Request& r, const sg_solve_info& info, int status, Clock::time_point now);
 };
+
+namespace {
+
+// The member slots of one running batch.  At each restart boundary a slot
+// whose request has ended is reported (done) and handed to the oldest queued
+// request of the batch's shape (next), which starts from x = 0 in that slot;
+// same shape means the same footprint, so the memory budget is unchanged.
+struct BatchFeed : sg::SlotFeed {
+    sg_server* srv;
+    Request shape;                  // n, M, P and options of the batch
+    std::vector<uint64_t> slot;     // request in each slot (0: free)
+
+    BatchFeed(sg_server* s, const std::vector<uint64_t>& ids) : srv(s), slot(ids) {
+        const Request& r0 = *s->reqs[ids[0]];
+        shape.prob = r0.prob;
+        shape.opt = r0.opt;
+    }
+    void done(int q, const double* x_member, const sg_solve_info& info, hipStream_t st) override {
+        double* dst;
+        size_t n;
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            Request& r = *srv->reqs[slot[q]];
+            dst = r.x_out;
+            n = (size_t)3 * sg::binom(r.prob.M + r.prob.P, r.prob.P) * (r.prob.n + 1) * (r.prob.n + 1);
+        }
+        SG_HIP(hipMemcpyAsync(dst, x_member, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        SG_HIP(hipStreamSynchronize(st));
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->finish(*srv->reqs[slot[q]], info, info.status, Clock::now());
+    }
+    bool next(int q, sg_problem& p) override {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (slot[q]) {      // release the reported request's slot and memory
+            srv->in_use -= srv->reqs[slot[q]]->footprint;
+            srv->running_slots -= 1;
+            slot[q] = 0;
+        }
+        for (auto it = srv->queue.begin(); it != srv->queue.end(); ++it) {
+            Request& r = *srv->reqs[*it];
+            if (r.state != 0 || !same_shape(r, shape)) continue;
+            if (srv->running_slots >= srv->max_slots || srv->in_use + r.footprint > srv->budget) break;
+            r.state = 1;
+            r.joined = 1;
+            srv->in_use += r.footprint;
+            srv->running_slots += 1;
+            slot[q] = r.ticket;
+            srv->queue.erase(it);
+            p = r.prob;
+            return true;
+        }
+        srv->cv_sched.notify_all();
+        return false;
+    }
+};
+
+}  // namespace
+
+void sg_server::finish(Request& r, const sg_solve_info& info, int status, Clock::time_point now) {
+    r.info = info;
+    r.info.status = status;
+    r.info.latency_ms = std::chrono::duration<double, std::milli>(now - r.t_submit).count();
+    r.info.joined_batch = r.joined;
+    r.status = status;
+    r.state = 2;
+    latencies.push_back(r.info.latency_ms);
+    t_last = now;
+    // release the host copies of the inputs
+    r.target.clear();
+    r.target.shrink_to_fit();
+    r.kappa.clear();
+    r.kappa.shrink_to_fit();
+    cv_done.notify_all();
+}
 
 void sg_server::schedule_loop() {
     std::unique_lock<std::mutex> lk(mu);
@@ -139,61 +216,50 @@ void sg_server::schedule_loop() {
 void sg_server::run_batch(const std::vector<uint64_t>& ids, hipStream_t st) {
     std::vector<sg_problem> probs;
     sg_options opt;
+    std::unique_ptr<BatchFeed> feed;
     {
         std::lock_guard<std::mutex> lk(mu);
         for (uint64_t id : ids) probs.push_back(reqs[id]->prob);
         opt = reqs[ids[0]]->opt;
+        feed = std::make_unique<BatchFeed>(this, ids);
     }
-    // A batch handle lives for one solve, so per-iteration graphs would be
-    // captured once and replayed about once; workers also allocate while other
-    // workers would be capturing.  Launch directly.
+    // Batches run without per-iteration graphs: workers allocate while other
+    // workers would be capturing.
     opt.use_graphs = 0;
     const int B = (int)ids.size();
-    std::vector<sg_solve_info> info(B);
-    std::vector<int> status(B, SG_OK);
+    int code = SG_OK;
+    std::string msg;
     try {
         auto h = sg::build_handle(probs.data(), B, &opt, st, &pool);
         const int64_t N = 3 * h->s.blk;
         double* x = h->ws.get_t<double>("serve_x", (size_t)B * N);
-        sg::solve(*h, nullptr, x, info.data());
-        for (int q = 0; q < B; ++q) {
-            status[q] = info[q].status;
-            double* dst;
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                dst = reqs[ids[q]]->x_out;
-            }
-            SG_HIP(hipMemcpyAsync(dst, x + q * N, sizeof(double) * N, hipMemcpyDeviceToHost, st));
-        }
+        sg::solve(*h, nullptr, x, nullptr, feed.get());
         SG_HIP(hipStreamSynchronize(st));
     } catch (const sg::Error& e) {
-        for (int q = 0; q < B; ++q) status[q] = e.code;
-        std::lock_guard<std::mutex> lk(mu);
-        worker_error = e.what();
+        code = e.code;
+        msg = e.what();
     } catch (const std::exception& e) {
-        for (int q = 0; q < B; ++q) status[q] = SG_ERR_INVALID;
-        std::lock_guard<std::mutex> lk(mu);
-        worker_error = e.what();
+        code = SG_ERR_INVALID;
+        msg = e.what();
     }
-    const auto now = Clock::now();
     std::lock_guard<std::mutex> lk(mu);
-    for (int q = 0; q < B; ++q) {
-        Request& r = *reqs[ids[q]];
-        r.info = info[q];
-        r.info.status = status[q];
-        r.info.latency_ms = std::chrono::duration<double, std::milli>(now - r.t_submit).count();
-        r.status = status[q];
-        r.state = 2;
-        in_use -= r.footprint;
-        latencies.push_back(r.info.latency_ms);
-        // release the host copies of the inputs
-        r.target.clear();
-        r.target.shrink_to_fit();
-        r.kappa.clear();
-        r.kappa.shrink_to_fit();
+    if (code != SG_OK) {
+        // the requests still in the batch's slots fail with the error
+        worker_error = msg;
+        const auto now = Clock::now();
+        for (uint64_t& id : feed->slot) {
+            if (!id) continue;
+            Request& r = *reqs[id];
+            if (r.state != 2) {
+                sg_solve_info info{};
+                info.status = code;
+                finish(r, info, code, now);
+            }
+            in_use -= r.footprint;
+            running_slots -= 1;
+            id = 0;
+        }
     }
-    running_slots -= B;
-    t_last = now;
     cv_sched.notify_all();
     cv_done.notify_all();
 }

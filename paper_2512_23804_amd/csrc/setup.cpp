@@ -35,6 +35,8 @@ void default_options(sg_options* o) {
     o->arnoldi = SG_ARNOLDI_DCGS2;
     o->sweep_rows = 0;
     o->basis_fp32 = 1;
+    o->mean_solver = SG_MEAN_MULTIGRID;
+    o->richardson_steps = 1;
 }
 
 // Total-degree multi-indices, degree ascending, descending lexicographic order
@@ -152,7 +154,12 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
         if (!(opt->rtol > 0) || !std::isfinite(opt->rtol)) fail(SG_ERR_INVALID, "rtol must be > 0");
         if (opt->restart < 1 || opt->restart > 31) fail(SG_ERR_INVALID, "restart must be in [1, 31]");
         if (opt->max_iter < 1) fail(SG_ERR_INVALID, "max_iter must be >= 1");
-        if (opt->cheb_steps < 1 || opt->cheb_steps > 64) fail(SG_ERR_INVALID, "cheb_steps must be in [1, 64]");
+        if (opt->cheb_steps < 0 || opt->cheb_steps > 64)
+            fail(SG_ERR_INVALID, "cheb_steps must be in [0, 64] (0: exact mass solves)");
+        if (opt->mean_solver != SG_MEAN_MULTIGRID && opt->mean_solver != SG_MEAN_EXACT)
+            fail(SG_ERR_INVALID, "mean_solver must be SG_MEAN_MULTIGRID or SG_MEAN_EXACT");
+        if (opt->richardson_steps < 1 || opt->richardson_steps > 16)
+            fail(SG_ERR_INVALID, "richardson_steps must be in [1, 16]");
         if (opt->truncation_r < 0 || opt->truncation_r > p0.M + 1)
             fail(SG_ERR_INVALID, "truncation_r must be in [0, M+1]");
         if (opt->gmg_pre < 1 || opt->gmg_pre > kMaxSmooth || opt->gmg_post < 1 || opt->gmg_post > kMaxSmooth)
@@ -280,7 +287,7 @@ static double* pinned_get() {
         }
     }
     double* p = nullptr;
-    SG_HIP(hipHostMalloc((void**)&p, 4096 * sizeof(double), hipHostMallocDefault));
+    SG_HIP(hipHostMalloc((void**)&p, kPinnedDoubles * sizeof(double), hipHostMallocDefault));
     return p;
 }
 
@@ -296,7 +303,7 @@ static void pinned_put(double* p) {
 Handle::~Handle() {
     ws.release();
     for (void* p : {(void*)d_nbr_idx, (void*)d_nbr_val, (void*)d_coef64, (void*)d_coef32, (void*)d_mem,
-                    (void*)d_lev, (void*)d_ainv64, (void*)d_ainv32, (void*)d_rhs})
+                    (void*)d_lev, (void*)d_ainv64, (void*)d_ainv32, (void*)d_rhs, (void*)d_dst})
         if (p) {
             if (pool)
                 pool->release(p);
@@ -320,6 +327,112 @@ static T* upload(const T* src, size_t count, DevicePool* pool = nullptr) {
     }
     if (count && src) SG_HIP(hipMemcpy(d, src, count * sizeof(T), hipMemcpyHostToDevice));
     return d;
+}
+
+// Host-side data of member b (coefficient modes, scalars, multigrid
+// constants, coarse inverse) into the handle's host arrays, and the nonzero
+// right-hand-side columns of the member into rb ([2][nt][nodes]).
+static void fill_member(Handle* h, int b, const sg_problem& p, double* rb) {
+    const Shape& s = h->s;
+    const sg_options& opt = h->opt;
+    const int M = s.M, n = s.n;
+    const size_t cm = (size_t)(M + 1) * n * n;
+    std::vector<double> c = coefficient_modes(p);
+    std::copy(c.begin(), c.end(), h->coef_host.begin() + cm * b);
+    MemberDev& md = h->mem_host[b];
+    md.beta = p.beta;
+    md.gamma = p.gamma;
+    md.hg = 1.0 + p.gamma;
+    md.c0 = c[0];
+    const double sq = std::sqrt((1.0 + p.gamma) / p.beta);
+    if (!s.time) {
+        md.tau = 1.0;
+        md.a1 = md.c0;          // A-tilde_1 = A_1 + sqrt((1+gamma)/beta) M  (eq. mathcalZ)
+        md.b1 = sq;
+        md.off_scale = 1.0;
+    } else {
+        md.tau = p.T / s.nt;    // A-hat_1 = (1 + tau sqrt((1+gamma)/beta)) M + tau A_1  (eq. A_hat)
+        md.a1 = md.tau * md.c0;
+        md.b1 = 1.0 + md.tau * sq;
+        md.off_scale = md.tau;
+    }
+    for (int l = 0; l < s.nlev_mg; ++l) {
+        LevelDev& L = h->lev_host[(size_t)b * kMaxLevels + l];
+        const int m = s.mg_n[l];
+        const double hh = 1.0 / m;
+        L.wc = md.a1 * 8.0 / 3.0 + md.b1 * 16.0 * hh * hh / 36.0;
+        L.we = -md.a1 / 3.0 + md.b1 * 4.0 * hh * hh / 36.0;
+        L.wd = -md.a1 / 3.0 + md.b1 * hh * hh / 36.0;
+        L.dinv = 1.0 / L.wc;
+        const double lmax = lambda_max(m, md.a1, md.b1);
+        smoother_coeffs(lmax, opt.gmg_pre, L.pre);
+        smoother_coeffs(lmax, opt.gmg_post, L.post);
+    }
+    coarse_inverse(md.a1, md.b1, h->ainv_host.data() + (size_t)b * kCoarsePad * kCoarsePad);
+
+    // right-hand side: b_y = tau D_t (M_full y_d)_interior in chaos column 0;
+    // time with y0: b_lambda(t=0, j=0) = -(M_II y0)
+    const double hh = 1.0 / n;
+    const double w = hh * hh / 36.0;
+    const int N1 = n + 1;
+    for (int t = 0; t < s.nt; ++t) {
+        const double* yd = p.y_target + (size_t)t * s.nodes;
+        const double Dt = (s.time && (t == 0 || t == s.nt - 1)) ? 0.5 : 1.0;
+        const double f = md.tau * Dt;
+        for (int iy = 1; iy < n; ++iy)
+            for (int ix = 1; ix < n; ++ix) {
+                const int q = iy * N1 + ix;
+                const double v = 16.0 * yd[q] + 4.0 * (yd[q - 1] + yd[q + 1] + yd[q - N1] + yd[q + N1]) +
+                                 (yd[q - N1 - 1] + yd[q - N1 + 1] + yd[q + N1 - 1] + yd[q + N1 + 1]);
+                rb[(size_t)t * s.nodes + q] = f * w * v;
+            }
+    }
+    if (s.time && p.y0) {
+        double* rl = rb + (size_t)s.nt * s.nodes;   // adjoint block, t = 0
+        for (int iy = 1; iy < n; ++iy)
+            for (int ix = 1; ix < n; ++ix) {
+                auto y0i = [&](int jx, int jy) {
+                    return (jx < 1 || jx > n - 1 || jy < 1 || jy > n - 1) ? 0.0 : p.y0[jy * N1 + jx];
+                };
+                const double v = 16.0 * y0i(ix, iy) +
+                                 4.0 * (y0i(ix - 1, iy) + y0i(ix + 1, iy) + y0i(ix, iy - 1) + y0i(ix, iy + 1)) +
+                                 (y0i(ix - 1, iy - 1) + y0i(ix + 1, iy - 1) + y0i(ix - 1, iy + 1) +
+                                  y0i(ix + 1, iy + 1));
+                rl[iy * N1 + ix] = -w * v;
+            }
+    }
+}
+
+void set_member(Handle& h, int b, const sg_problem& p) {
+    const Shape& s = h.s;
+    if (b < 0 || b >= h.B) throw Error(SG_ERR_INVALID, "member index out of range");
+    validate(&p, 1, &h.opt);
+    if (p.n != s.n || p.M != s.M || p.P != s.P || (p.n_t >= 2 ? p.n_t : 1) != s.nt)
+        throw Error(SG_ERR_INVALID, "a member's problem must have the handle's n, M, P and n_t");
+    const size_t rcols = (size_t)2 * s.nt * s.nodes;
+    std::vector<double> rb(rcols, 0.0);
+    fill_member(&h, b, p, rb.data());
+    hipStream_t st = h.stream;
+    const size_t cm = (size_t)(s.M + 1) * s.n * s.n;
+    std::vector<float> c32(h.coef_host.begin() + cm * b, h.coef_host.begin() + cm * (b + 1));
+    const size_t ca = (size_t)kCoarsePad * kCoarsePad;
+    std::vector<float> a32(h.ainv_host.begin() + ca * b, h.ainv_host.begin() + ca * (b + 1));
+    SG_HIP(hipMemcpyAsync(h.d_coef64 + cm * b, h.coef_host.data() + cm * b, sizeof(double) * cm,
+                          hipMemcpyHostToDevice, st));
+    SG_HIP(hipMemcpyAsync(h.d_coef32 + cm * b, c32.data(), sizeof(float) * cm, hipMemcpyHostToDevice, st));
+    SG_HIP(hipMemcpyAsync(h.d_mem + b, h.mem_host.data() + b, sizeof(MemberDev), hipMemcpyHostToDevice, st));
+    SG_HIP(hipMemcpyAsync(h.d_lev + (size_t)b * kMaxLevels, h.lev_host.data() + (size_t)b * kMaxLevels,
+                          sizeof(LevelDev) * kMaxLevels, hipMemcpyHostToDevice, st));
+    SG_HIP(hipMemcpyAsync(h.d_ainv64 + ca * b, h.ainv_host.data() + ca * b, sizeof(double) * ca,
+                          hipMemcpyHostToDevice, st));
+    SG_HIP(hipMemcpyAsync(h.d_ainv32 + ca * b, a32.data(), sizeof(float) * ca, hipMemcpyHostToDevice, st));
+    const int64_t kkt = 3 * s.blk;
+    launch_fill_zero<double>(h.d_rhs + (size_t)b * kkt, kkt, st);
+    for (int v = 0; v < 2; ++v)
+        SG_HIP(hipMemcpy2DAsync(h.d_rhs + (size_t)b * kkt + (size_t)(2 * v) * s.blk, sizeof(double) * s.tstride,
+                                rb.data() + (size_t)v * s.nt * s.nodes, sizeof(double) * s.nodes,
+                                sizeof(double) * s.nodes, s.nt, hipMemcpyHostToDevice, st));
+    SG_HIP(hipStreamSynchronize(st));   // the host arrays above go out of scope
 }
 
 std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt_in, hipStream_t st,
@@ -404,74 +517,7 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     const int64_t kkt = 3 * s.blk;
     const size_t rcols = (size_t)2 * s.nt * s.nodes;    // per member: state and adjoint column 0, every t
     h->rhs_host.assign((size_t)count * rcols, 0.0);
-    for (int b = 0; b < count; ++b) {
-        const sg_problem& p = probs[b];
-        std::vector<double> c = coefficient_modes(p);
-        std::copy(c.begin(), c.end(), h->coef_host.begin() + cm * b);
-        MemberDev& md = h->mem_host[b];
-        md.beta = p.beta;
-        md.gamma = p.gamma;
-        md.hg = 1.0 + p.gamma;
-        md.c0 = c[0];
-        const double sq = std::sqrt((1.0 + p.gamma) / p.beta);
-        if (!s.time) {
-            md.tau = 1.0;
-            md.a1 = md.c0;          // A-tilde_1 = A_1 + sqrt((1+gamma)/beta) M  (eq. mathcalZ)
-            md.b1 = sq;
-            md.off_scale = 1.0;
-        } else {
-            md.tau = p.T / s.nt;    // A-hat_1 = (1 + tau sqrt((1+gamma)/beta)) M + tau A_1  (eq. A_hat)
-            md.a1 = md.tau * md.c0;
-            md.b1 = 1.0 + md.tau * sq;
-            md.off_scale = md.tau;
-        }
-        for (int l = 0; l < s.nlev_mg; ++l) {
-            LevelDev& L = h->lev_host[(size_t)b * kMaxLevels + l];
-            const int m = s.mg_n[l];
-            const double hh = 1.0 / m;
-            L.wc = md.a1 * 8.0 / 3.0 + md.b1 * 16.0 * hh * hh / 36.0;
-            L.we = -md.a1 / 3.0 + md.b1 * 4.0 * hh * hh / 36.0;
-            L.wd = -md.a1 / 3.0 + md.b1 * hh * hh / 36.0;
-            L.dinv = 1.0 / L.wc;
-            const double lmax = lambda_max(m, md.a1, md.b1);
-            smoother_coeffs(lmax, opt.gmg_pre, L.pre);
-            smoother_coeffs(lmax, opt.gmg_post, L.post);
-        }
-        coarse_inverse(md.a1, md.b1, h->ainv_host.data() + (size_t)b * kCoarsePad * kCoarsePad);
-
-        // right-hand side: b_y = tau D_t (M_full y_d)_interior in chaos column 0;
-        // time with y0: b_lambda(t=0, j=0) = -(M_II y0)
-        double* rb = h->rhs_host.data() + (size_t)b * rcols;
-        const double hh = 1.0 / n;
-        const double w = hh * hh / 36.0;
-        const int N1 = n + 1;
-        for (int t = 0; t < s.nt; ++t) {
-            const double* yd = p.y_target + (size_t)t * s.nodes;
-            const double Dt = (s.time && (t == 0 || t == s.nt - 1)) ? 0.5 : 1.0;
-            const double f = md.tau * Dt;
-            for (int iy = 1; iy < n; ++iy)
-                for (int ix = 1; ix < n; ++ix) {
-                    const int q = iy * N1 + ix;
-                    const double v = 16.0 * yd[q] + 4.0 * (yd[q - 1] + yd[q + 1] + yd[q - N1] + yd[q + N1]) +
-                                     (yd[q - N1 - 1] + yd[q - N1 + 1] + yd[q + N1 - 1] + yd[q + N1 + 1]);
-                    rb[(size_t)t * s.nodes + q] = f * w * v;
-                }
-        }
-        if (s.time && p.y0) {
-            double* rl = rb + (size_t)s.nt * s.nodes;   // adjoint block, t = 0
-            for (int iy = 1; iy < n; ++iy)
-                for (int ix = 1; ix < n; ++ix) {
-                    auto y0i = [&](int jx, int jy) {
-                        return (jx < 1 || jx > n - 1 || jy < 1 || jy > n - 1) ? 0.0 : p.y0[jy * N1 + jx];
-                    };
-                    const double v = 16.0 * y0i(ix, iy) +
-                                     4.0 * (y0i(ix - 1, iy) + y0i(ix + 1, iy) + y0i(ix, iy - 1) + y0i(ix, iy + 1)) +
-                                     (y0i(ix - 1, iy - 1) + y0i(ix + 1, iy - 1) + y0i(ix - 1, iy + 1) +
-                                      y0i(ix + 1, iy + 1));
-                    rl[iy * N1 + ix] = -w * v;
-                }
-        }
-    }
+    for (int b = 0; b < count; ++b) fill_member(h.get(), b, probs[b], h->rhs_host.data() + (size_t)b * rcols);
 
     // upload
     h->d_nbr_idx = upload(h->ht.nbr_idx.data(), h->ht.nbr_idx.size(), pool);
@@ -487,6 +533,19 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     {
         std::vector<float> a32(h->ainv_host.begin(), h->ainv_host.end());
         h->d_ainv32 = upload(a32.data(), a32.size(), pool);
+    }
+    {
+        // sine-transform tables of the exact solves: sin(pi m / n), m < 2n, then
+        // the 1D stiffness and mass eigenvalues k_p = 4n sin^2(pi p / 2n),
+        // m_p = (2 + cos(pi p / n)) / (3n), p = 0..n
+        std::vector<double> t((size_t)2 * n + 2 * (n + 1));
+        for (int m = 0; m < 2 * n; ++m) t[m] = std::sin(M_PI * (double)m / n);
+        for (int q = 0; q <= n; ++q) {
+            const double sh = std::sin(M_PI * q / (2.0 * n));
+            t[2 * n + q] = 4.0 * n * sh * sh;
+            t[2 * n + (n + 1) + q] = (2.0 + std::cos(M_PI * q / n)) / (3.0 * n);
+        }
+        h->d_dst = upload(t.data(), t.size(), pool);
     }
     {
         // right-hand sides: zero everywhere but chaos column 0 of the state
@@ -506,7 +565,7 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
         h->rhs_host.shrink_to_fit();
     }
     h->h_pinned = pinned_get();
-    h->h_pinned_count = 4096;
+    h->h_pinned_count = kPinnedDoubles;
     autotune(*h);
     SG_HIP(hipStreamSynchronize(h->stream));
     h->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();

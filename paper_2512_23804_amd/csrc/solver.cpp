@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 
 #include "handle.hpp"
 
@@ -121,7 +122,7 @@ void mg_buffers(Handle& h, int ncols, std::vector<T*>& xs, std::vector<T*>& bs, 
 // uses the constants of member c / cpm (cpm = ncols when all columns share
 // member 0).
 template <typename T>
-void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, int cpm, hipStream_t st) {
+void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, int cpm, int cpv, hipStream_t st) {
     const Shape& s = h.s;
     const LevelDev* lev = h.d_lev;
     const int nl = s.nlev_mg;
@@ -139,7 +140,8 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         const int m = s.mg_n[l];
         const double nodes = (double)(m + 1) * (m + 1);
         const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
-        launch_mg_down<T>(m, lev, l, npre, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], bs[l + 1], ncols, cpm, st);
+        launch_mg_down<T>(m, lev, l, npre, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], bs[l + 1], ncols, cpm, h.active,
+                          cpv, st);
         if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 1.25);   // read b, write b_coarse
     }
     const T* e;
@@ -147,7 +149,7 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         T* out = lc == 0 ? x : xf[lc];
         const bool tp = prof_begin(h, SG_PROF_MG_TAIL, st);
         launch_mg_tail<T>(s.mg_n[lc], lev, lc, npre, npost, lc == 0 ? b : bs[lc], lc == 0 ? bmap : cm[lc], out,
-                          lc == 0 ? xmap : cm[lc], h.ainv<T>(), ncols, cpm, st);
+                          lc == 0 ? xmap : cm[lc], h.ainv<T>(), ncols, cpm, h.active, cpv, st);
         // algorithmic bytes: read b, write x at the first fused level
         if (tp) prof_end(h, st, 2.0 * sizeof(T) * ncols * (double)(s.mg_n[lc] + 1) * (s.mg_n[lc] + 1));
         e = out;
@@ -161,10 +163,38 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         T* out = l == 0 ? x : xf[l];
         const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_UP, st);
         launch_mg_up<T>(m, lev, l, npre, npost, e, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], out,
-                        l == 0 ? xmap : cm[l], ncols, cpm, st);
+                        l == 0 ? xmap : cm[l], ncols, cpm, h.active, cpv, st);
         if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);  // read b, e_coarse; write x
         e = out;
     }
+}
+
+// FP64 scratch of the sine-transform solves: two buffers of the largest
+// column count a preconditioner application of nvec vectors uses (the mass
+// blocks, 2 n_t n_xi columns per vector, or the widest degree level).
+void dst_scratch(Handle& h, int nvec, double*& s1, double*& s2) {
+    const Shape& s = h.s;
+    int lmax = 0;
+    for (int d = 0; d <= s.P; ++d) lmax = std::max(lmax, s.off[d + 1] - s.off[d]);
+    const size_t cols = (size_t)nvec * s.nt * std::max(2 * s.nxi, lmax);
+    s1 = h.ws.get_t<double>("dst1", cols * s.nodes);
+    s2 = h.ws.get_t<double>("dst2", cols * s.nodes);
+}
+
+// Solves with the mean block A-tilde_1 (eq. mathcalZ) / A-hat_1 (eq. A_hat)
+// on ncols columns: one multigrid V-cycle, or exactly by the sine transform.
+template <typename T>
+void mean_solve(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, int cpm, int cpv, int nvec,
+                hipStream_t st) {
+    if (h.opt.mean_solver == SG_MEAN_EXACT) {
+        double *s1, *s2;
+        dst_scratch(h, nvec, s1, s2);
+        const Shape& s = h.s;
+        launch_dst_solve<T>(s.n, 1, h.d_mem, 0, h.d_dst, h.d_dst + 2 * s.n, b, bmap, x, xmap, ncols, cpm, s.nt,
+                            s.nxi, (int)s.time, s1, s2, h.active, cpv, st);
+        return;
+    }
+    vcycle<T>(h, b, bmap, x, xmap, ncols, cpm, cpv, st);
 }
 
 // hGS (Algorithm 1): V = Z_r^{-1}-approximation applied to R, zero initial
@@ -184,13 +214,13 @@ void hgs(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nmem, bool s
         if (d == 0) {
             // degree 0 has no lower level: its right-hand side is R_(0) itself (the
             // multigrid reads interior nodes only), solved from R directly
-            vcycle<T>(h, R, rm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
+            mean_solve<T>(h, R, rm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, L * s.nt, nmem, st);
             continue;
         }
         const bool tp = prof_begin(h, SG_PROF_HGS_RHS, st);
         launch_hgs_rhs<T>(s, op, d, mask, 1, 0, R, rm, V, vfull, Bs, bm, nmem, st);
         if (tp) prof_end(h, st, (double)sizeof(T) * (2 * L + (mask ? Ln : 0)) * s.nodes * s.nt * nmem);
-        vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
+        mean_solve<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, L * s.nt, nmem, st);
     }
     if (mask == 0) return;   // mean-based: the backward sweep repeats the forward solves exactly
     for (int d = s.P - 1; d >= 0; --d) {
@@ -204,7 +234,7 @@ void hgs(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nmem, bool s
         else
             launch_hgs_rhs<T>(s, op, d, mask, 0, 1, Bs, bm, V, vfull, Bs, bm, nmem, st);
         if (tp) prof_end(h, st, (double)sizeof(T) * (2 * L + Lu) * s.nodes * s.nt * nmem);
-        vcycle<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, st);
+        mean_solve<T>(h, Bs, bm, V, vm, L * s.nt * nmem, shared ? L * s.nt * nmem : L * s.nt, L * s.nt, nmem, st);
     }
 }
 
@@ -212,7 +242,7 @@ void hgs(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nmem, bool s
 
 template <typename T>
 void operator_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st) {
-    launch_sg_apply<T>(h.s, h.op<T>(shared), x, y, nvec, st);
+    launch_sg_apply<T>(h.s, h.op<T>(shared), x, y, nvec, 0xffffffffu, st);
 }
 
 template <typename T>
@@ -225,27 +255,74 @@ void kkt_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t s
                  (double)sizeof(T) * nvec * (6.0 * h.s.blk + (shared ? 1.0 / nvec : 1.0) * (h.s.M + 1) * h.s.n * h.s.n));
 }
 
+// Z^{-1} of the Schur block on nvec field blocks: Algorithm 5 with N =
+// richardson_steps from a zero initial guess, each step preconditioned by
+// one hGS (Algorithm 1): X <- X + hGS(R - Z_r X), Z_r = I (x) A-tilde_1 +
+// off_scale sum_{k<r} G_k (x) K_k.  N = 1 is one hGS, written to V directly.
+template <typename T>
+void zinv(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nvec, bool shared, hipStream_t st) {
+    const int N = h.opt.richardson_steps;
+    if (N <= 1) {
+        hgs<T>(h, R, rms, V, vms, nvec, shared, st);
+        return;
+    }
+    const Shape& s = h.s;
+    const size_t cnt = (size_t)nvec * s.blk;
+    T* X = h.ws.get_t<T>(std::string("richX") + tname<T>(), cnt);
+    T* Y = h.ws.get_t<T>(std::string("richY") + tname<T>(), cnt);
+    T* Rr = h.ws.get_t<T>(std::string("richR") + tname<T>(), cnt);
+    T* D = h.ws.get_t<T>(std::string("richD") + tname<T>(), cnt);
+    const ColMap bm = block_map(s, s.blk), rm = block_map(s, rms), vm = block_map(s, vms);
+    const int ncols = nvec * s.nt * s.nxi, cpv = s.nt * s.nxi;
+    const OpDev op = h.op<T>(shared);
+    hgs<T>(h, R, rms, X, s.blk, nvec, shared, st);
+    for (int k = 1; k < N; ++k) {
+        launch_sg_apply<T>(s, op, X, Y, nvec, h.modes_mask(), st);
+        launch_z_residual<T>(s.n, R, rm, Y, X, bm, Rr, bm, h.d_mem, ncols, cpv, shared ? 1 : 0, h.active, st);
+        hgs<T>(h, Rr, s.blk, D, s.blk, nvec, shared, st);
+        if (k + 1 < N)
+            launch_cols_add<T>(s.nodes, X, bm, D, bm, X, bm, ncols, cpv, h.active, st);
+        else
+            launch_cols_add<T>(s.nodes, X, bm, D, bm, V, vm, ncols, cpv, h.active, st);
+    }
+}
+
 // Block-diagonal preconditioner (eq. stoch-prec / eq. precon for time).
 template <typename T>
 void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st) {
     const Shape& s = h.s;
     const OpDev op = h.op<T>(shared);
     const int64_t kkt = 3 * s.blk;
-    // state and control blocks: Chebyshev semi-iteration on M with block scalings
-    // (the per-step Chebyshev kernel, used above 9 steps, needs two iterate buffers)
-    const bool cheb_bufs = h.opt.cheb_steps > 9;
-    T* A = cheb_bufs ? h.ws.get_t<T>(std::string("chebA") + tname<T>(), (size_t)nvec * 2 * s.blk) : nullptr;
-    T* Bb = cheb_bufs ? h.ws.get_t<T>(std::string("chebB") + tname<T>(), (size_t)nvec * 2 * s.blk) : nullptr;
+    // state and control blocks: Chebyshev semi-iteration on M with block
+    // scalings, or (cheb_steps = 0) exact solves by the sine transform
     const bool tp = prof_begin(h, SG_PROF_MASS_CHEB, st);
-    launch_mass_cheb<T>(s, op, r, z, A, Bb, nvec, h.opt.cheb_steps, st);
+    if (h.opt.cheb_steps == 0) {
+        double *s1, *s2;
+        dst_scratch(h, nvec, s1, s2);
+        ColMap ym;       // columns [y | u] of each vector: n_t n_xi state columns, then the control columns
+        ym.mstride = kkt;
+        ym.tstride = 0;
+        ym.nodes = s.nodes;
+        ym.L = 2 * s.nt * s.nxi;
+        ym.nt = 1;
+        ym.j0 = 0;
+        launch_dst_solve<T>(s.n, 2, h.d_mem, shared ? 1 : 0, h.d_dst, h.d_dst + 2 * s.n, r, ym, z, ym,
+                            nvec * 2 * s.nt * s.nxi, 1, s.nt, s.nxi, (int)s.time, s1, s2, h.active, ym.L, st);
+    } else {
+        // (the per-step Chebyshev kernel, used above 9 steps, needs two iterate buffers)
+        const bool cheb_bufs = h.opt.cheb_steps > 9;
+        T* A = cheb_bufs ? h.ws.get_t<T>(std::string("chebA") + tname<T>(), (size_t)nvec * 2 * s.blk) : nullptr;
+        T* Bb = cheb_bufs ? h.ws.get_t<T>(std::string("chebB") + tname<T>(), (size_t)nvec * 2 * s.blk) : nullptr;
+        launch_mass_cheb<T>(s, op, r, z, A, Bb, nvec, h.opt.cheb_steps, st);
+    }
     if (tp) prof_end(h, st, 4.0 * sizeof(T) * nvec * (double)s.blk);   // read r_y, r_u; write z_y, z_u
     // adjoint block: S^{-1} r = Z^{-1} (tau D (x) M_gamma) Z^{-1} r
     T* V1 = h.ws.get_t<T>(std::string("schurV") + tname<T>(), (size_t)nvec * s.blk);
     T* W = h.ws.get_t<T>(std::string("schurW") + tname<T>(), (size_t)nvec * s.blk);
-    hgs<T>(h, r + 2 * s.blk, kkt, V1, s.blk, nvec, shared, st);
+    zinv<T>(h, r + 2 * s.blk, kkt, V1, s.blk, nvec, shared, st);
     const ColMap vm = block_map(s, s.blk);
     launch_mass_scaled<T>(s, op, V1, vm, W, vm, nvec * s.nt * s.nxi, nvec, st);
-    hgs<T>(h, W, s.blk, z + 2 * s.blk, kkt, nvec, shared, st);
+    zinv<T>(h, W, s.blk, z + 2 * s.blk, kkt, nvec, shared, st);
 }
 
 // Every scratch buffer precond_apply<T> uses for nvec vectors, requested at
@@ -262,6 +339,13 @@ void precond_reserve(Handle& h, int nvec) {
     h.ws.get_t<T>(std::string("schurV") + tname<T>(), (size_t)nvec * s.blk);
     h.ws.get_t<T>(std::string("schurW") + tname<T>(), (size_t)nvec * s.blk);
     h.ws.get_t<T>(std::string("hgsB") + tname<T>(), (size_t)nvec * s.blk);
+    if (h.opt.cheb_steps == 0 || h.opt.mean_solver == SG_MEAN_EXACT) {
+        double *s1, *s2;
+        dst_scratch(h, nvec, s1, s2);
+    }
+    if (h.opt.richardson_steps > 1)
+        for (const char* nm : {"richX", "richY", "richR", "richD"})
+            h.ws.get_t<T>(std::string(nm) + tname<T>(), (size_t)nvec * s.blk);
     if (s.nlev_mg > 1) {
         int lmax = 0;
         for (int d = 0; d <= s.P; ++d) lmax = std::max(lmax, s.off[d + 1] - s.off[d]);
@@ -302,7 +386,7 @@ struct Krylov {
     double* w;             // [B][N]
     double* partial;       // [B][kSlots][nblk]
     KrylovDev kd;
-    int* d_jend;
+    int* ctl;              // [4][B] device: active, iters, itmax, jend (one upload per cycle)
     float* v32buf;         // [B][N] FP32 staging (FP32 preconditioner on an FP64 basis)
     float* w32;            // [B][N] FP32 operator output (op32)
 
@@ -332,13 +416,17 @@ struct Krylov {
         kd.nrm = h.ws.get_t<double>("knrm", (size_t)B);
         kd.y = h.ws.get_t<double>("ky", (size_t)B * m);
         kd.resid = h.ws.get_t<double>("kres", (size_t)B);
-        kd.active = h.ws.get_t<int>("kact", (size_t)B);
+        ctl = h.ws.get_t<int>("kctl", (size_t)4 * B);
+        kd.active = ctl;
+        kd.iters = ctl + B;
+        kd.itmax = ctl + 2 * B;
+        kd.jend = ctl + 3 * B;
+        kd.tol = h.ws.get_t<double>("ktol", (size_t)B);
         kd.dots = h.ws.get_t<double>("kdots", (size_t)B * kSlots);
         kd.scal = h.ws.get_t<double>("kscal", (size_t)B * 4);
         kd.pending = h.ws.get_t<int>("kpend", (size_t)B);
         kd.R = h.ws.get_t<double>("kR", (size_t)B * ld * ld);
         kd.coef = h.ws.get_t<double>("kcoef", (size_t)B * kSlots);
-        d_jend = h.ws.get_t<int>("kjend", (size_t)B);
         v32buf = z32 && !v32 ? h.ws.get_t<float>("kv32", (size_t)B * N) : nullptr;
         w32 = op32 ? h.ws.get_t<float>("kw32", (size_t)B * N) : nullptr;
         zt = z32 && !op32 ? h.ws.get_t<double>("kzt", (size_t)B * N) : nullptr;
@@ -435,24 +523,42 @@ struct Krylov {
 // solves of iterative refinement run one cycle and stop on the Arnoldi
 // estimate).  All stopping decisions are per member, so a member's arithmetic
 // never depends on the other members of the batch.
+//
+// Inside a cycle the decisions are taken on the device: after each iteration
+// k_conv_check clears a member's flag once its estimate reaches its tolerance
+// or its iteration limit, and every later launch of the operator, the
+// preconditioner and the Arnoldi passes skips that member.  The host reads the
+// flags back only every few iterations (fewer when the estimates' recent
+// reduction rate predicts convergence is still far off), and stops launching
+// once no member is left.
+//
+// boundary (optional) runs after each cycle-start decision; when it returns
+// true it has changed members' right-hand sides or iterates (refilled slots),
+// and the residual is formed again before the cycle starts.
 void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol_abs, std::vector<int>& todo,
             bool fp32, int max_iter, int max_cycles, std::vector<double>& res_out, std::vector<int>& member_iters,
-            int verbose) {
+            int verbose, const std::function<bool()>& boundary = nullptr) {
     Handle& h = K.h;
     const int B = K.B, m = K.m;
     const int64_t N = K.N;
     hipStream_t st = K.st;
     double* r = h.ws.get_t<double>("kr", (size_t)B * N);
     std::vector<double> nr2, resid;
-    std::vector<int> jend(B, 0), active(B, 0);
+    std::vector<int> active(B, 0);
     // host copy of the device's per-member `pending` flags (DCGS2): set for the
     // members that ran an iteration, so their last Hessenberg column is
     // completed by the next dot pass; only used to count the members each
-    // profiled pass really processes
+    // profiled pass really processes (profiling reads the flags back after
+    // every iteration)
     std::vector<int> pend(B, 0);
     res_out.assign(B, 0.0);
-    int* pinned_i = reinterpret_cast<int*>(h.h_pinned + 2048);   // upload staging (after a stream sync)
-    for (int cycle = 0; max_cycles <= 0 || cycle < max_cycles; ++cycle) {
+    // pinned staging: [0, 2048) readbacks (double), [2048, 4096) tolerances,
+    // ints from 4096: control upload [4][B]; ints from 8192: control readback [2][B]
+    double* tol_up = h.h_pinned + 2048;
+    int* ctl_up = reinterpret_cast<int*>(h.h_pinned + 4096);
+    int* ctl_dn = reinterpret_cast<int*>(h.h_pinned + 8192);
+    const bool profiling = h.prof.kind != SG_PROF_NONE;
+    for (int cycle = 0; max_cycles <= 0 || cycle < max_cycles;) {
         K.residual(b, x, r, fp32, nr2);       // synchronises the stream
         bool any = false;
         for (int q = 0; q < B; ++q) {
@@ -464,23 +570,32 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
             for (int q = 0; q < B; ++q)
                 std::fprintf(stderr, "[sg] member %d iters %d true residual %.3e (tol %.3e)%s\n", q, member_iters[q],
                              res_out[q], tol_abs[q], fp32 ? " [fp32 inner]" : "");
+        if (boundary && boundary()) continue;
         if (!any) break;
-        // cycle start: g = (beta, 0, ...), V_0 = r / beta
+        ++cycle;
+        // cycle start: g = (beta, 0, ...), V_0 = r / beta; the control block
+        // (flags, iteration counts, limits, cycle lengths) and the tolerances
         for (int q = 0; q < B; ++q) {
             active[q] = todo[q];
-            jend[q] = 0;
             pend[q] = 0;
-            pinned_i[q] = active[q];
+            ctl_up[q] = active[q];
+            ctl_up[B + q] = member_iters[q];
+            ctl_up[2 * B + q] = max_iter;
+            ctl_up[3 * B + q] = 0;
+            tol_up[q] = tol_abs[q];
         }
-        SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
+        SG_HIP(hipMemcpyAsync(K.ctl, ctl_up, sizeof(int) * 4 * B, hipMemcpyHostToDevice, st));
+        SG_HIP(hipMemcpyAsync((void*)K.kd.tol, tol_up, sizeof(double) * B, hipMemcpyHostToDevice, st));
         launch_cycle_start(K.kd, m, K.kd.nrm, B, st);    // kd.nrm holds ||r||^2 from residual()
         K.start_basis(r);
         const bool dcgs = h.opt.arnoldi == SG_ARNOLDI_DCGS2;
         const int64_t vs = K.vs;
-        // one FGMRES iteration: preconditioner, KKT apply, Arnoldi, Givens
+        // one FGMRES iteration: preconditioner, KKT apply, Arnoldi, Givens, stop test
         auto iteration = [&](int j) {
+            h.active = K.kd.active;
             K.apply_prec(j);
             K.apply_op_z(j);
+            h.active = nullptr;
             if (dcgs) {
                 // DCGS2: the basis slots hold the candidates U (V = U R^{-1}); one
                 // read-only pass gives the reorthogonalisation of u_j and the
@@ -502,28 +617,36 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
                 K.dcgs_update(j);
                 if (tp) prof_end(h, st, K.vbytes() * (j + 3) * (double)n_upd * N);   // read U_0..U_j and w, write u_{j+1}
                 for (int q = 0; q < B; ++q) pend[q] = active[q];
-                return;
+            } else {
+                const int nv = j + 1;
+                // CGS2: h1 = V^T w; w1 = w - V h1; h2 = V^T w1; w2 = w1 - V h2
+                const bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
+                launch_multidot(K.Vi(0), vs, nv, K.w, N, B, N, K.partial, K.nblk, st);
+                if (tp) prof_end(h, st, 8.0 * (nv + 1) * (double)B * N);
+                launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h1, m + 1, 0, st);
+                launch_cgs_update_dot(K.Vi(0), vs, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
+                launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h2, m + 1, 0, st);
+                launch_cgs_update_norm(K.Vi(0), vs, nv, K.kd.h2, m + 1, K.w, K.Vi(j + 1), N, B, N, K.partial,
+                                       K.nblk, st);
+                launch_reduce_partials(K.partial, K.nblk, 1, B, K.kd.nrm, 1, 0, st);
+                launch_arnoldi_finish(K.kd, m, j, B, st);
+                launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
             }
-            const int nv = j + 1;
-            // CGS2: h1 = V^T w; w1 = w - V h1; h2 = V^T w1; w2 = w1 - V h2
-            const bool tp = prof_begin(h, SG_PROF_MULTIDOT, st);
-            launch_multidot(K.Vi(0), vs, nv, K.w, N, B, N, K.partial, K.nblk, st);
-            if (tp) prof_end(h, st, 8.0 * (nv + 1) * (double)B * N);
-            launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h1, m + 1, 0, st);
-            launch_cgs_update_dot(K.Vi(0), vs, nv, K.kd.h1, m + 1, K.w, N, B, N, K.partial, K.nblk, st);
-            launch_reduce_partials(K.partial, K.nblk, nv, B, K.kd.h2, m + 1, 0, st);
-            launch_cgs_update_norm(K.Vi(0), vs, nv, K.kd.h2, m + 1, K.w, K.Vi(j + 1), N, B, N, K.partial, K.nblk, st);
-            launch_reduce_partials(K.partial, K.nblk, 1, B, K.kd.nrm, 1, 0, st);
-            launch_arnoldi_finish(K.kd, m, j, B, st);
-            launch_scale_vec(K.Vi(j + 1), K.kd.nrm, 1, N, B, N, st);
+            launch_conv_check(K.kd, j, B, st);
         };
         const int zk = (K.z32 ? 1 : 0) + (K.op32 ? 2 : 0) + (K.v32 ? 4 : 0);
         // (capture needs a created stream; the legacy default stream cannot be captured)
-        const bool graphs = h.opt.use_graphs && st != nullptr && h.prof.kind == SG_PROF_NONE && h.opt.cheb_steps <= 9;
+        const bool graphs = h.opt.use_graphs && st != nullptr && !profiling && h.opt.cheb_steps <= 9;
         if (graphs && h.graphs.gen != h.ws.generation()) {
             h.graphs.clear();
             h.graphs.gen = h.ws.generation();
         }
+        // host checks: the estimate and iteration of each active member at the
+        // last check (the cycle start: the true residual)
+        std::vector<double> est_prev(B), est(B);
+        std::vector<int> it_prev(B, -1);
+        for (int q = 0; q < B; ++q) est_prev[q] = res_out[q];
+        int next_check = 0;
         int jlast = -1;
         for (int j = 0; j < m; ++j) {
             jlast = j;
@@ -536,6 +659,7 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
                     try {
                         iteration(j);
                     } catch (...) {
+                        h.active = nullptr;
                         (void)hipStreamEndCapture(st, &g);
                         if (g) (void)hipGraphDestroy(g);
                         throw;
@@ -551,24 +675,31 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
             } else {
                 iteration(j);
             }
+            if (!profiling && j < next_check && j < m - 1) continue;
+            // read the flags, iteration counts and estimates back
+            SG_HIP(hipMemcpyAsync(ctl_dn, K.ctl, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, st));
             K.readback(K.kd.resid, resid);    // synchronises the stream
-            bool still = false, changed = false;
+            bool still = false;
+            int ahead = 8;                     // iterations until the next check
             for (int q = 0; q < B; ++q) {
                 if (!active[q]) continue;
-                jend[q] = j + 1;
-                ++member_iters[q];
-                if (resid[q] <= tol_abs[q] || member_iters[q] >= max_iter) {
-                    active[q] = 0;
-                    changed = true;
-                } else {
-                    still = true;
+                member_iters[q] = ctl_dn[B + q];
+                active[q] = ctl_dn[q];
+                if (!active[q]) continue;
+                still = true;
+                // iterations the estimate still needs at its recent reduction rate
+                const int done = j - it_prev[q];
+                double need = 1.0;
+                if (resid[q] > tol_abs[q] && resid[q] < est_prev[q] && done > 0) {
+                    const double rate = std::log(resid[q] / est_prev[q]) / done;   // < 0
+                    need = std::log(tol_abs[q] / resid[q]) / rate;
                 }
+                est_prev[q] = resid[q];
+                it_prev[q] = j;
+                ahead = std::min(ahead, std::max(1, (int)std::floor(0.8 * need)));
             }
             if (!still) break;
-            if (changed) {
-                for (int q = 0; q < B; ++q) pinned_i[q] = active[q];
-                SG_HIP(hipMemcpyAsync(K.kd.active, pinned_i, sizeof(int) * B, hipMemcpyHostToDevice, st));
-            }
+            next_check = j + ahead;
         }
         if (dcgs && jlast >= 0) {
             // reorthogonalise the last candidates (slot jlast + 1) of the members whose
@@ -577,11 +708,13 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
             launch_reduce_partials(K.partial, K.nblk, jlast + 2, B, K.kd.dots, kSlots, 0, st);
             launch_dcgs_finish(K.kd, m, jlast + 1, 1, B, st);
         }
-        for (int q = 0; q < B; ++q) pinned_i[B + q] = jend[q];
-        SG_HIP(hipMemcpyAsync(K.d_jend, pinned_i + B, sizeof(int) * B, hipMemcpyHostToDevice, st));
-        launch_back_solve(K.kd, m, K.d_jend, B, st);
-        launch_multi_axpy(K.Z, K.z32 ? 1 : 0, (int64_t)B * N, m, K.d_jend, K.kd.y, m, x, N, B, N, st);
+        launch_back_solve(K.kd, m, K.kd.jend, B, st);
+        launch_multi_axpy(K.Z, K.z32 ? 1 : 0, (int64_t)B * N, m, K.kd.jend, K.kd.y, m, x, N, B, N, st);
+        // iteration counts of the members still active at the last check
+        SG_HIP(hipMemcpyAsync(ctl_dn, K.ctl, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, st));
         SG_HIP(hipStreamSynchronize(st));     // the staging area is reused next cycle
+        for (int q = 0; q < B; ++q)
+            if (todo[q]) member_iters[q] = ctl_dn[B + q];
         if (graphs) {
             if (h.graphs.gen != h.ws.generation()) {   // buffers allocated in this cycle: recapture later
                 h.graphs.clear();
@@ -594,8 +727,9 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
 
 }  // namespace
 
-int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
-    auto t0 = std::chrono::steady_clock::now();
+int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, SlotFeed* feed) {
+    using Clock = std::chrono::steady_clock;
+    const auto t0 = Clock::now();
     const Shape& s = h.s;
     const int B = h.B;
     const int64_t N = 3 * s.blk;
@@ -617,8 +751,61 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
     std::vector<int> todo(B, 1);
     for (int q = 0; q < B; ++q) tol[q] = h.opt.rtol * std::sqrt(bn2[q]);
     std::vector<int> member_iters(B, 0), member_outer(B, 0);
+    std::vector<Clock::time_point> t_start(B, t0);
+    std::vector<int> live(B, 1);    // slot holds a problem whose solve has not been reported (feed)
+
+    auto report = [&](int q, double ms) {
+        sg_solve_info r{};
+        const double bn = std::sqrt(bn2[q]);
+        const double rel = bn > 0 ? res[q] / bn : 0.0;
+        const bool conv = rel <= h.opt.rtol;
+        r.iters = member_iters[q];
+        r.outer_refinements = member_outer[q];
+        r.converged = conv ? 1 : 0;
+        r.status = conv ? SG_OK : SG_NOT_CONVERGED;
+        r.rel_res_true = rel;
+        r.t_setup_ms = h.t_setup_ms;
+        r.t_solve_ms = ms;
+        r.latency_ms = ms;
+        return r;
+    };
+    // restart boundary with a feed: report the members whose solve ended,
+    // then load new problems into the free slots (x = 0, their own b)
+    auto boundary = [&]() -> bool {
+        if (!feed) return false;
+        const auto now = Clock::now();
+        for (int q = 0; q < B; ++q)
+            if (live[q] && !todo[q]) {
+                feed->done(q, x_dev + q * N,
+                           report(q, std::chrono::duration<double, std::milli>(now - t_start[q]).count()), st);
+                live[q] = 0;
+            }
+        bool refilled = false;
+        for (int q = 0; q < B; ++q) {
+            if (live[q]) continue;
+            sg_problem p{};
+            if (!feed->next(q, p)) continue;
+            set_member(h, q, p);
+            SG_HIP(hipMemcpyAsync(b + q * N, h.d_rhs + q * N, sizeof(double) * N, hipMemcpyDeviceToDevice, st));
+            launch_zero_ring<double>(b + q * N, s.n, (int64_t)3 * s.nt * s.nxi, st);
+            launch_fill_zero<double>(x_dev + q * N, N, st);
+            live[q] = 1;
+            todo[q] = 1;
+            member_iters[q] = 0;
+            member_outer[q] = 0;
+            t_start[q] = Clock::now();
+            refilled = true;
+        }
+        if (refilled) {
+            K.norms2(b, bn2);
+            for (int q = 0; q < B; ++q)
+                if (todo[q]) tol[q] = h.opt.rtol * std::sqrt(bn2[q]);
+        }
+        return refilled;
+    };
+
     if (!fp32) {
-        fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, 0, res, member_iters, h.opt.verbose);
+        fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, 0, res, member_iters, h.opt.verbose, boundary);
     } else {
         // FP64 iterative refinement: r = b - K64 x (FP64 storage and sums);
         // one inner FGMRES cycle on K d = r with the operator and the
@@ -632,12 +819,16 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
         std::vector<double> nr2;
         while (true) {
             K.residual(b, x_dev, r, false, nr2);
+            for (int q = 0; q < B; ++q) {
+                res[q] = std::sqrt(nr2[q]);
+                if (todo[q] && (res[q] <= tol[q] || member_iters[q] >= h.opt.max_iter)) todo[q] = 0;
+            }
+            if (boundary()) continue;
             std::vector<int> todo32(B, 0);
             std::vector<double> tol_in(B, 0.0);
             bool any = false;
             for (int q = 0; q < B; ++q) {
-                res[q] = std::sqrt(nr2[q]);
-                if (res[q] <= tol[q] || member_iters[q] >= h.opt.max_iter) continue;
+                if (!todo[q]) continue;
                 tol_in[q] = std::max(h.opt.inner_rtol * res[q], 0.5 * tol[q]);
                 ++member_outer[q];
                 todo32[q] = 1;
@@ -651,24 +842,15 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info) {
         }
     }
     SG_HIP(hipStreamSynchronize(st));
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    const auto t1 = Clock::now();
     const double pms = prof_collect_ms(h);
     h.prof.kind = SG_PROF_NONE;     // only sg_solve is profiled
     bool all = true;
     for (int q = 0; q < B; ++q) {
-        const double bn = std::sqrt(bn2[q]);
-        const double rel = bn > 0 ? res[q] / bn : 0.0;
-        const bool conv = rel <= h.opt.rtol;
-        all = all && conv;
+        const sg_solve_info r = report(q, std::chrono::duration<double, std::milli>(t1 - t_start[q]).count());
+        if (live[q]) all = all && r.converged;
         if (info) {
-            info[q].iters = member_iters[q];
-            info[q].outer_refinements = member_outer[q];
-            info[q].converged = conv ? 1 : 0;
-            info[q].status = conv ? SG_OK : SG_NOT_CONVERGED;
-            info[q].rel_res_true = rel;
-            info[q].t_setup_ms = h.t_setup_ms;
-            info[q].t_solve_ms = ms;
-            info[q].latency_ms = ms;
+            info[q] = r;
             info[q].bytes_moved = 0.0;
             info[q].prof_ms = pms;
             info[q].prof_bytes = h.prof.bytes;

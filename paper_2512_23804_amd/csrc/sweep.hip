@@ -486,6 +486,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
     const int tiles = g.tiles_x * g.tiles_y;
     const int tile = rest % tiles;
     const int slice = rest / tiles;
+    if (op.active && !op.active[slice / nt]) return;
     const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
     // wavefront index is uniform: keep it (and everything derived from it) in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -510,7 +511,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
 #pragma unroll
     for (int r = 0; r < RS + 1; ++r) v[r][0] = v[r][1] = v[r][2] = v[r][3] = 0.0;
     if constexpr (KIND == 0)
-        S::sg_strip_direct(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, 0xffffffffu, true, true, true,
+        S::sg_strip_direct(v, st, F, nodes, j, M, op.nbr_idx, op.nbr_val, mask, true, true, true,
                            op.mem[mem].c0, (const double*)nullptr, grp, gl,
                            op.coef64 + (int64_t)mem * op.coef_mstride, (int64_t)n * n);
     else
@@ -568,6 +569,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     const int tiles = g.tiles_x * g.tiles_y;
     const int tile = rest % tiles;
     const int slice = rest / tiles;
+    if (op.active && !op.active[slice / nt]) return;   // uniform per block, before the barrier below
     const int tx = tile % g.tiles_x, ty = tile / g.tiles_x;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int j = chunk * 4 + wave;
@@ -668,14 +670,15 @@ SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
 
 // Returns false when the sweep kernels do not cover the shape (M > 8).
 template <typename T>
-bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, uint32_t mask, hipStream_t st) {
     if (s.M > KMAX) return false;
     ColMap z{};
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_APPLY];
     const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
     SG_ROWS_DISPATCH(rows, hipLaunchKernelGGL((k_sgx<T, 0, R, false>), dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi,
-                                              s.nt, s.nodes, op, g, x, y, 0, 0, 0u, 1, 1, (const T*)nullptr, z, z, z));
+                                              s.nt, s.nodes, op, g, x, y, 0, 0, mask, 1, 1, (const T*)nullptr, z, z,
+                                              z));
     SG_HIP(hipGetLastError());
     return true;
 }
@@ -715,8 +718,8 @@ bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, i
     return true;
 }
 
-template bool launch_sgx_apply<double>(const Shape&, const OpDev&, const double*, double*, int, hipStream_t);
-template bool launch_sgx_apply<float>(const Shape&, const OpDev&, const float*, float*, int, hipStream_t);
+template bool launch_sgx_apply<double>(const Shape&, const OpDev&, const double*, double*, int, uint32_t, hipStream_t);
+template bool launch_sgx_apply<float>(const Shape&, const OpDev&, const float*, float*, int, uint32_t, hipStream_t);
 template bool launch_sgx_kkt<double>(const Shape&, const OpDev&, const double*, double*, int, hipStream_t);
 template bool launch_sgx_kkt<float>(const Shape&, const OpDev&, const float*, float*, int, hipStream_t);
 template bool launch_sgx_hgs_rhs<double>(const Shape&, const OpDev&, int, uint32_t, int, int, const double*, ColMap,

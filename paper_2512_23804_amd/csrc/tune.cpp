@@ -57,7 +57,7 @@ std::array<int, 3> tune_type(Handle& h, hipStream_t st) {
                 s.sweep_rows[sizeof(T) == 4][kind] = rows;
                 const float ms = time_launch(st, e0, e1, [&] {
                     if (kind == SWEEP_APPLY)
-                        launch_sgx_apply<T>(s, op, x, y, B, st);
+                        launch_sgx_apply<T>(s, op, x, y, B, 0xffffffffu, st);
                     else if (kind == SWEEP_HGS)
                         launch_sgx_hgs_rhs<T>(s, op, d, h.modes_mask(), 1, 0, x, lm, x, bm, y, lm, B, st);
                     else

@@ -36,6 +36,7 @@ def test_default_options():
     assert o.rtol == 1e-8 and o.restart == 30 and o.cheb_steps == 5 and o.gmg_pre == 2 and o.gmg_post == 2
     assert o.precision == sgl.SG_PREC_FP64 and o.truncation_r == 0
     assert o.arnoldi == sgl.SG_ARNOLDI_DCGS2 and o.sweep_rows == 0 and o.use_graphs == 1
+    assert o.mean_solver == sgl.SG_MEAN_MULTIGRID and o.richardson_steps == 1
 
 
 def _pd(**kw):
@@ -82,10 +83,14 @@ def test_validate_nonfinite_target_and_custom_kappa():
 
 def test_validate_options():
     import paper_2512_23804_amd as sgl
-    for kw in (dict(restart=0), dict(restart=40), dict(cheb_steps=0), dict(truncation_r=6), dict(gmg_pre=0),
-               dict(precision=3), dict(rtol=0.0), dict(sweep_rows=3), dict(sweep_rows=16), dict(arnoldi=2),
-               dict(profile=9)):
+    for kw in (dict(restart=0), dict(restart=40), dict(cheb_steps=-1), dict(cheb_steps=65), dict(truncation_r=6),
+               dict(gmg_pre=0), dict(precision=3), dict(rtol=0.0), dict(sweep_rows=3), dict(sweep_rows=16),
+               dict(arnoldi=2), dict(profile=9), dict(mean_solver=2), dict(richardson_steps=0),
+               dict(richardson_steps=17)):
         assert sgl.validate(_pd(), sgl.default_options(**kw)) == sgl.SG_ERR_INVALID, kw
+    # exact mass solves (cheb_steps = 0), exact mean-block solves and Richardson steps are valid
+    for kw in (dict(cheb_steps=0), dict(mean_solver=sgl.SG_MEAN_EXACT), dict(richardson_steps=4)):
+        assert sgl.validate(_pd(), sgl.default_options(**kw)) == sgl.SG_OK, kw
 
 
 def test_setup_rejects_before_touching_the_device():

@@ -324,6 +324,37 @@ def test_batch_results_equal_alone():
             assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_members_stop_on_the_device(precision):
+    """A batch whose members need very different iteration counts (several
+    restart cycles for one, one cycle for another), on a created stream with
+    per-iteration graphs: the device clears each member's flag when its
+    estimate converges and later launches skip it; every member still gives
+    the iterations and the bit-identical result of its alone solve."""
+    dev = _dev()
+    _say(f"device-side stop precision={precision}")
+    sgl = _lib()
+    params = [(0.1, 1e-1, 3), (0.3, 1e-6, 4), (0.2, 1e-3, 5)]
+    kws = [make_case(16, 3, 2, s, b, seed=sd)[1] for s, b, sd in params]
+    stream = torch.cuda.Stream()
+    opts = dict(rtol=1e-10, precision=precision, use_graphs=1, max_iter=400)
+    hb = sgl.Handle([sgl.ProblemData(**kw) for kw in kws], sgl.default_options(**opts), stream=stream)
+    xb = torch.zeros(3 * hb.kkt_elems, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()              # the solve writes xb on `stream`
+    for _ in range(2):                    # the second solve replays the captured graphs
+        rc, infos = hb.solve(xb)
+        assert rc == 0
+    its = [inf.iters for inf in infos]
+    assert max(its) > 30 and min(its) < max(its), its
+    for i, kw in enumerate(kws):
+        ha = sgl.Handle([sgl.ProblemData(**kw)], sgl.default_options(**opts), stream=stream)
+        xa = torch.zeros(ha.kkt_elems, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        rca, infa = ha.solve(xa)
+        assert rca == 0 and infa[0].iters == infos[i].iters
+        assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
+
+
 def test_delayed_reorthogonalisation_tracks_cgs2():
     """Across restarts and a hard beta, the delayed-reorthogonalisation Arnoldi
     needs about the iterations of Gram-Schmidt twice and reaches the same
@@ -358,6 +389,7 @@ def test_graph_replay_matches_direct_launches(precision):
             h = sgl.Handle([sgl.ProblemData(**kw)], sgl.default_options(rtol=1e-10, precision=precision,
                                                                         use_graphs=use_graphs), stream=stream)
         x = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()          # x is read and written on `stream`
         rc, info = h.solve(x)
         assert rc == 0 and info[0].iters > 30      # more than one restart cycle
         outs.append(x.clone())
@@ -378,6 +410,15 @@ OPTION_CASES = [
     ("truncation r=3", (32, 4, 2, 0.25, 1e-3, 0.0, 1), dict(truncation_r=3)),
     ("coarse-only hierarchy", (8, 2, 2, 0.2, 1e-2, 0.0, 1), {}),
     ("three level kernels above the tail", (256, 2, 1, 0.2, 1e-2, 0.0, 1), {}),
+    ("exact mean-block solves", (32, 3, 2, 0.25, 1e-3, 0.0, 1), dict(mean_solver=1)),
+    ("exact mean-block solves, time", (16, 3, 2, 0.25, 1e-3, 0.0, 3), dict(mean_solver=1)),
+    ("exact mass solves", (32, 3, 2, 0.25, 1e-3, 0.3, 1), dict(cheb_steps=0)),
+    ("exact mass solves, time", (16, 2, 2, 0.25, 1e-3, 0.3, 3), dict(cheb_steps=0)),
+    ("exact solves, two tiles", (128, 2, 2, 0.2, 1e-2, 0.0, 1), dict(cheb_steps=0, mean_solver=1)),
+    ("Richardson N=3", (32, 3, 2, 0.25, 1e-3, 0.0, 1), dict(richardson_steps=3)),
+    ("Richardson N=2 exact, time, r=2", (16, 3, 2, 0.25, 1e-3, 0.0, 2),
+     dict(richardson_steps=2, mean_solver=1, truncation_r=2)),
+    ("Richardson M>8, r=4", (16, 10, 2, 0.2, 1e-2, 0.0, 1), dict(richardson_steps=2, truncation_r=4)),
 ]
 
 
@@ -410,9 +451,11 @@ def test_option_paths(label, shape, opts):
     torch.cuda.synchronize()
     assert ring_is_zero(yd.cpu().numpy(), n) and ring_is_zero(zd.cpu().numpy(), n)
     assert rel_max(canonical_to_kkt(sg, yd.cpu().numpy()), kkt.kkt_apply_matricized(sg, x)) < 1e-12
-    inner = precond.make_inner(sg, nu_pre=opts.get("gmg_pre", 2), nu_post=opts.get("gmg_post", 2))
+    inner = precond.make_inner(sg, "exact" if opts.get("mean_solver", 0) == 1 else "gmg",
+                               nu_pre=opts.get("gmg_pre", 2), nu_post=opts.get("gmg_post", 2))
     r = opts.get("truncation_r", 0) or M + 1
-    ref = precond.precond_apply(sg, x, inner, r, cheb_steps=opts.get("cheb_steps", 5))
+    ref = precond.precond_apply(sg, x, inner, r, cheb_steps=opts.get("cheb_steps", 5),
+                                richardson_steps=opts.get("richardson_steps", 1))
     assert rel_max(canonical_to_kkt(sg, zd.cpu().numpy()), ref) < 1e-12
     sol = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
     rc, info = h.solve(sol)

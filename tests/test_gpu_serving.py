@@ -113,3 +113,38 @@ def test_server_cancel_and_admission():
         tiny.submit(big, out_big)
     assert e.value.code == sgl.SG_ERR_NOMEM
     tiny.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_request_joins_running_batch(precision):
+    """Two slots, three same-shape requests queued at once: a fast and a slow
+    request run, the third waits; when the fast one ends, the third takes its
+    slot in the running batch at the next restart boundary.  Every result
+    equals its alone solve bit for bit."""
+    _need_gpu()
+    sgl = _lib()
+    _say(f"serving join at restart precision={precision}")
+    n, M, P = 32, 3, 2
+    params = [(0.1, 1e-1, 11), (0.3, 1e-6, 12), (0.2, 1e-3, 13)]    # fast, slow (several cycles), joiner
+    opts = sgl.default_options(rtol=1e-9, precision=precision, max_iter=600)
+    srv = sgl.Server(hbm_budget_bytes=0, max_slots=2)
+    tickets, items = [], []
+    for sigma, beta, seed in params:
+        pd = sgl.ProblemData(n, M, P, sigma, beta, sg_inputs.gaussian_bumps(n, seed))
+        out = np.full(_kkt_len(n, M, P), np.nan)
+        tickets.append(srv.submit(pd, out, opts))
+        items.append((pd, out))
+    res = _wait(srv, tickets)
+    srv.close()
+    infos = [res[t][1] for t in tickets]
+    assert all(res[t][0] == sgl.SG_OK for t in tickets)
+    assert [i.joined_batch for i in infos] == [0, 0, 1], [i.joined_batch for i in infos]
+    assert infos[1].iters > infos[0].iters, [i.iters for i in infos]
+    dev = torch.device("cuda:0")
+    for (pd, out), info in zip(items, infos):
+        h = sgl.Handle(pd, opts)
+        x = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+        rca, infa = h.solve(x)
+        assert rca == sgl.SG_OK and infa[0].iters == info.iters
+        assert np.array_equal(x.cpu().numpy(), out)
+        h.close()

@@ -308,3 +308,33 @@ def test_mass_blocks_invert_the_preconditioner_diagonal(nt):
     r = np.concatenate([ry.ravel(), ru.ravel(), rl.ravel()])
     zy, zu, _ = kkt.split(sg, precond.precond_apply(sg, r, precond.make_inner(sg), cheb_steps=60))
     assert np.max(np.abs(zy - vy)) < 1e-12 and np.max(np.abs(zu - vu)) < 1e-12
+
+
+def test_richardson_converges_to_truncated_z_solve():
+    """Algorithm 5: N preconditioned Richardson steps with hGS (exact inner
+    solves) approach Z_r^{-1} R, Z_r assembled independently as explicit
+    Kronecker sums, geometrically; N = 1 is one hGS."""
+    for r_trunc in (2, 3):
+        prob = kkt.Problem(n=8, M=2, P=2, sigma=0.3, beta=1e-2, gamma=0.0, n_t=1, T=1.0,
+                           y_target=sg_inputs.gaussian_bumps(8, 0))
+        sg = kkt.setup(prob)
+        inner = precond.make_inner(sg, "exact")
+        R = np.random.default_rng(1).standard_normal((sg.n_xi, sg.Mi.shape[0]))
+        ex = spla.spsolve(precond.z_truncated(sg, r_trunc).tocsc(), R.ravel()).reshape(R.shape)
+        assert np.array_equal(precond.richardson(sg, R, inner, r_trunc, 1), precond.hgs(sg, R, inner, r_trunc))
+        errs = [np.linalg.norm(precond.richardson(sg, R, inner, r_trunc, N) - ex) / np.linalg.norm(ex)
+                for N in (1, 2, 3, 6)]
+        assert errs[0] < 0.05 and errs[1] < 0.1 * errs[0] and errs[2] < 0.1 * errs[1] and errs[3] < 1e-11, errs
+
+
+def test_exact_mass_solve():
+    """cheb_steps = 0: the mass blocks by a direct solve; M applied to the
+    result gives back the right-hand side, while 5 Chebyshev steps do not."""
+    prob = kkt.Problem(n=8, M=2, P=2, sigma=0.3, beta=1e-2, gamma=0.0, n_t=1, T=1.0,
+                       y_target=sg_inputs.gaussian_bumps(8, 0))
+    sg = kkt.setup(prob)
+    R = np.random.default_rng(2).standard_normal((4, sg.Mi.shape[0]))
+    X = precond.kkt_cheb(sg, R, 0)
+    assert np.max(np.abs((sg.Mi @ X.T).T - R)) < 1e-13 * np.max(np.abs(R))
+    X5 = precond.kkt_cheb(sg, R, 5)
+    assert np.max(np.abs((sg.Mi @ X5.T).T - R)) > 1e-6 * np.max(np.abs(R))
