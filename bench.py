@@ -35,6 +35,13 @@ WORKLOADS = {
     "steady-512-M8-P3": dict(n=512, M=8, P=3, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(5,)),
     # the largest shape the serving stream draws (n_xi = 495, 98 M unknowns)
     "steady-256-M8-P4": dict(n=256, M=8, P=4, sigma=0.3, betas=(1e-2,), n_t=1, seeds=(6,)),
+    # Section 5's own workload: log-normal field (KL of the exponential covariance, correlation length 1
+    # on [-1,1]^2), Hermite chaos m = 3, p = 3 (n_xi = 20, n_A = 84 terms), sigma = 0.2, gamma = 1,
+    # indicator target, 32 x 32 elements, the beta sweep of its Table (deter beta)
+    "lognormal-32-M3-P3": dict(n=32, M=3, P=3, sigma=0.2, betas=(1e-2, 1e-3, 1e-4, 1e-5), n_t=1, seeds=(0, 0, 0, 0),
+                               field="lognormal", gamma=1.0),
+    "lognormal-128-M3-P3": dict(n=128, M=3, P=3, sigma=0.2, betas=(1e-4,), n_t=1, seeds=(0,),
+                                field="lognormal", gamma=1.0),
 }
 DEFAULT = "steady-512-M8-P3"
 # kernels timed with HIP events around every launch (sg_options.profile), with
@@ -77,12 +84,17 @@ def measured_traffic(kernel, workload):
 
 def make_problems(sgl, sg_inputs, wl):
     probs = []
+    lognormal = wl.get("field") == "lognormal"
     for beta, seed in zip(wl["betas"], wl["seeds"]):
         if wl["n_t"] > 1:
             tgt = sg_inputs.moving_bump(wl["n"], wl["n_t"], 1.0, seed)
+        elif lognormal:
+            tgt = sg_inputs.indicator_target(wl["n"])
         else:
             tgt = sg_inputs.gaussian_bumps(wl["n"], seed)
-        probs.append(sgl.ProblemData(wl["n"], wl["M"], wl["P"], wl["sigma"], beta, tgt, n_t=wl["n_t"], T=1.0))
+        probs.append(sgl.ProblemData(wl["n"], wl["M"], wl["P"], wl["sigma"], beta, tgt, n_t=wl["n_t"], T=1.0,
+                                     gamma=wl.get("gamma", 0.0),
+                                     field=sgl.SG_FIELD_LOGNORMAL if lognormal else sgl.SG_FIELD_AFFINE))
     return probs
 
 
@@ -292,7 +304,15 @@ def precond_variants(torch, sgl, sg_inputs, workload, steps, warmup):
     probs = make_problems(sgl, sg_inputs, wl)
     stream = torch.cuda.Stream()
     rows = []
-    for label, over in PRECOND_VARIANTS:
+    variants = list(PRECOND_VARIANTS)
+    if wl.get("field") == "lognormal":
+        # Section 5's three truncations n_tau = 1, m + 1, n_A with each mass-block variant
+        variants = [(f"{mass} + hGS-1, n_tau = {name}", dict(truncation_r=r, **mo))
+                    for mass, mo in (("cheb5", {}), ("cheb10", dict(cheb_steps=10)), ("exact mass", dict(cheb_steps=0)))
+                    for name, r in (("1", 1), ("m+1", wl["M"] + 1), ("n_A", 0))]
+        variants.append(("cheb5 + hGS-1 (exact mean blocks), n_tau = m+1", dict(truncation_r=wl["M"] + 1,
+                                                                               mean_solver=1)))
+    for label, over in variants:
         print(f"[bench] variant {label}", file=sys.stderr, flush=True)
         opts = sgl.default_options(rtol=1e-8, **over)
         dt, infos = timed_solves(torch, sgl, probs, opts, steps, warmup, stream)

@@ -96,14 +96,30 @@ extern "C" {
  *           steady); the target enters the right-hand side as the full-grid
  *           mass matrix times the target, restricted to interior rows
  *   y0      optional host array [(n+1)^2] initial state (time-dependent);
- *           NULL means zero */
+ *           NULL means zero
+ *   field   SG_FIELD_AFFINE (0): the affine coefficient 1 + sigma sum_k
+ *           k^-2 cos(k pi x1) cos(k pi x2) xi_k (or kappa) with orthonormal
+ *           Legendre chaos in xi ~ U(-1, 1)^M, so G_k couples alpha with
+ *           alpha +- e_k; SG_FIELD_LOGNORMAL (1): the log-normal coefficient
+ *           of Section 5 with orthonormal Hermite chaos in Gaussian xi: the
+ *           exponential of the M-term Karhunen-Loeve expansion of a Gaussian
+ *           field with covariance sigma^2 exp(-|x1-y1|/corr_len -
+ *           |x2-y2|/corr_len) on [-1, 1]^2 (mapped onto the unit square of
+ *           the grid), mean coefficient 1, expanded to total degree 2P
+ *           (n_A = C(M+2P, 2P) terms H_l (x) A_l); kappa must be NULL
+ *   corr_len correlation length of the log-normal field (Section 5: 1) */
 typedef struct sg_problem {
     int32_t n, M, P, n_t;
     double T, beta, gamma, sigma;
     const double* kappa;
     const double* y_target;
     const double* y0;
+    int32_t field;
+    double corr_len;
 } sg_problem;
+
+#define SG_FIELD_AFFINE    0
+#define SG_FIELD_LOGNORMAL 1
 
 /* Solver options.  sg_default_options() fills the defaults in brackets.
  *   rtol         relative residual ||b - K x|| / ||b|| to reach [1e-8]
@@ -112,8 +128,10 @@ typedef struct sg_problem {
  *   cheb_steps   Chebyshev semi-iteration steps for mass solves, or 0 for
  *                exact mass solves by the 2D sine transform (the direct
  *                factorisation variant of Section 5) [5]
- *   truncation_r hGS truncation: modes k = 1..r-1 are kept in the off-level
- *                products (r = 1 mean-based, r = M+1 all) [0 = M+1]
+ *   truncation_r hGS truncation: coefficient terms k = 1..r-1 are kept in the
+ *                off-level products (r = 1 mean-based, r = M+1 all modes of
+ *                the affine field, r = n_A all terms of the log-normal field;
+ *                Section 5's n_tau) [0 = all]
  *   gmg_pre/post Chebyshev smoothing degree before/after coarse correction [2,2]
  *   precision    SG_PREC_FP64, SG_PREC_FP32_REFINE or SG_PREC_FP32_PRECOND [SG_PREC_FP64]
  *   inner_rtol   FP32 inner solve reduction per refinement step [1e-5]

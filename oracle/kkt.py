@@ -57,6 +57,9 @@ class Problem:
     T: float = 1.0
     kappa: np.ndarray | None = None  # (M+1, n, n) per-element modes; None = cosine field
     y0: np.ndarray | None = None     # (n+1)^2 initial state (time-dependent only)
+    field: str = "affine"            # "affine": Legendre chaos, sigma-scaled cosine (or kappa) modes;
+                                     # "lognormal": Hermite chaos, log-normal field of Section 5
+    corr: float = 1.0                # log-normal: correlation length on [-1, 1]^2
 
     @property
     def steady(self) -> bool:
@@ -73,11 +76,11 @@ class SG:
     prob: Problem
     alpha: np.ndarray                    # multi-indices (n_xi, M)
     offsets: np.ndarray                  # degree level offsets (P+2,)
-    G: list                              # dense triple-product matrices, k = 0..M
-    K: list                              # interior stiffness matrices K_k, k = 0..M
+    G: list                              # dense triple-product matrices H_l, l = 0..n_terms-1
+    K: list                              # interior stiffness matrices A_l of the coefficient terms
     Mi: sp.csr_matrix                    # interior mass matrix
     Mfull: sp.csr_matrix                 # full-grid mass matrix
-    kappa: np.ndarray                    # (M+1, n, n)
+    kappa: np.ndarray                    # (n_terms, n, n): M+1 (affine) or n_A (log-normal)
     _cache: dict = field(default_factory=dict)
 
     @property
@@ -94,9 +97,14 @@ def setup(prob: Problem) -> SG:
     n, M, P = prob.n, prob.M, prob.P
     alpha = basis.multi_indices(M, P)
     offsets = basis.level_offsets(M, P)
-    G = basis.triple_product_matrices(M, P)
-    kappa = prob.kappa if prob.kappa is not None else fem.cosine_modes(n, M, prob.sigma)
-    K = [fem.restrict(fem.assemble_full(n, kappa[k], "stiffness"), n) for k in range(M + 1)]
+    if prob.field == "lognormal":
+        from . import hermite
+        G = hermite.h_matrices(M, P)
+        kappa = hermite.lognormal_modes(n, M, P, prob.sigma, prob.corr)
+    else:
+        G = basis.triple_product_matrices(M, P)
+        kappa = prob.kappa if prob.kappa is not None else fem.cosine_modes(n, M, prob.sigma)
+    K = [fem.restrict(fem.assemble_full(n, kappa[k], "stiffness"), n) for k in range(len(G))]
     Mfull = fem.assemble_full(n, 1.0, "mass")
     Mi = fem.restrict(Mfull, n)
     return SG(prob, alpha, offsets, G, K, Mi, Mfull, np.asarray(kappa, dtype=np.float64))

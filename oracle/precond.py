@@ -32,7 +32,8 @@ Readings (the paper is silent or ambiguous):
   * S-tilde carries the 1/tau of S-bar, so S-tilde^{-1} = tau Z-tilde^{-1}
     (D (x) M_gamma) Z-tilde^{-1};
   * truncation r keeps the modes k = 1..r-1 (r = 1 is the mean-based
-    preconditioner, r = M+1 keeps every mode of the affine field);
+    preconditioner, r = M+1 keeps every mode of the affine field, r = n_A
+    every term of the log-normal field);
   * the A-tilde_1 / A-hat_1 solves inside hGS are either exact (sparse LU,
     the "ideal" preconditioner of the analysis) or one geometric-multigrid
     V-cycle (the solver's choice in place of the paper's direct solves); the
@@ -254,7 +255,7 @@ def hgs(sg: kkt.SG, R: np.ndarray, inner, r_trunc: int) -> np.ndarray:
     off = sg.offsets
     P = len(off) - 2
     _, _, scale = mean_operator_coeffs(sg)
-    modes = list(range(1, min(r_trunc, sg.prob.M + 1)))
+    modes = list(range(1, min(r_trunc, len(sg.G))))
     V = np.zeros_like(R)
     order = list(range(P + 1)) + list(range(P - 1, -1, -1))
     for d in order:
@@ -316,7 +317,7 @@ def precond_apply(sg: kkt.SG, r: np.ndarray, inner=None, r_trunc: int | None = N
     if inner is None:
         inner = make_inner(sg)
     if r_trunc is None:
-        r_trunc = p.M + 1
+        r_trunc = len(sg.G)
     Ry, Ru, Rl = kkt.split(sg, r)
     hg = kkt.h_gamma(sg)[:, None]
     if p.steady:
@@ -354,7 +355,7 @@ def z_truncated(sg: kkt.SG, r_trunc: int) -> sp.csr_matrix:
     K = fem.restrict(fem.assemble_full(n, 1.0, "stiffness"), n)
     A1 = (a * K + b * sg.Mi).tocsr()
     Z = sp.kron(sp.identity(sg.n_xi), A1, format="csr")
-    for k in range(1, min(r_trunc, sg.prob.M + 1)):
+    for k in range(1, min(r_trunc, len(sg.G))):
         Z = Z + scale * sp.kron(sp.csr_matrix(sg.G[k]), sg.K[k], format="csr")
     return Z.tocsr()
 
@@ -419,7 +420,7 @@ def hgsoc(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int) -> np.nd
     Ry, Ru, Rl = (b.copy() for b in kkt.split(sg, r))
     off = sg.offsets
     P = len(off) - 2
-    modes = list(range(1, min(r_trunc, p.M + 1)))
+    modes = list(range(1, min(r_trunc, len(sg.G))))
     hg = np.diag(kkt.h_gamma(sg))
     H1 = np.eye(sg.n_xi)
     VY, VU, VL = np.zeros_like(Ry), np.zeros_like(Ru), np.zeros_like(Rl)
@@ -468,7 +469,7 @@ def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int) -> tuple:
     level = np.zeros(nxi, dtype=int)
     for d in range(len(off) - 1):
         level[int(off[d]):int(off[d + 1])] = d
-    modes = list(range(1, min(r_trunc, p.M + 1)))
+    modes = list(range(1, min(r_trunc, len(sg.G))))
     I = sp.identity(nxi, format="csr")
     Dg = sp.block_diag([sp.kron(I, Mb), sp.kron(I, bMb), sp.kron(I, A1)], format="csr")
     # off-level couplings of the KKT rows (state: -A Lambda; adjoint: -A Y)

@@ -23,6 +23,7 @@ SG_PROF_NONE, SG_PROF_KKT_APPLY, SG_PROF_MG_SMOOTH, SG_PROF_MULTIDOT, SG_PROF_HG
 SG_PROF_ARNOLDI_UPD, SG_PROF_MG_TAIL, SG_PROF_MASS_CHEB, SG_PROF_MG_UP = 5, 6, 7, 8
 SG_ARNOLDI_DCGS2, SG_ARNOLDI_CGS2 = 0, 1
 SG_MEAN_MULTIGRID, SG_MEAN_EXACT = 0, 1
+SG_FIELD_AFFINE, SG_FIELD_LOGNORMAL = 0, 1
 
 _DP = C.POINTER(C.c_double)
 
@@ -30,7 +31,7 @@ _DP = C.POINTER(C.c_double)
 class sg_problem(C.Structure):
     _fields_ = [("n", C.c_int32), ("M", C.c_int32), ("P", C.c_int32), ("n_t", C.c_int32),
                 ("T", C.c_double), ("beta", C.c_double), ("gamma", C.c_double), ("sigma", C.c_double),
-                ("kappa", _DP), ("y_target", _DP), ("y0", _DP)]
+                ("kappa", _DP), ("y_target", _DP), ("y0", _DP), ("field", C.c_int32), ("corr_len", C.c_double)]
 
 
 class sg_options(C.Structure):
@@ -128,12 +129,13 @@ def _dptr(a):
 class ProblemData:
     """Host-side problem holder that keeps the arrays alive for the C struct."""
 
-    def __init__(self, n, M, P, sigma, beta, y_target, gamma=0.0, n_t=1, T=1.0, kappa=None, y0=None):
+    def __init__(self, n, M, P, sigma, beta, y_target, gamma=0.0, n_t=1, T=1.0, kappa=None, y0=None,
+                 field=0, corr_len=1.0):
         self.y_target = np.ascontiguousarray(y_target, dtype=np.float64)
         self.kappa = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
         self.y0 = None if y0 is None else np.ascontiguousarray(y0, dtype=np.float64)
         self.c = sg_problem(int(n), int(M), int(P), int(n_t), float(T), float(beta), float(gamma), float(sigma),
-                            _dptr(self.kappa), _dptr(self.y_target), _dptr(self.y0))
+                            _dptr(self.kappa), _dptr(self.y_target), _dptr(self.y0), int(field), float(corr_len))
 
 
 def _ptr(t) -> int:

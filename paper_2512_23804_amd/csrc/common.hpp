@@ -86,6 +86,8 @@ inline ColMap contiguous_cols(int ncols, int64_t nodes) {
 struct Shape {
     int n, M, P, nt;           // nt = 1 for steady
     bool time;
+    int field = SG_FIELD_AFFINE;   // coefficient model of the batch
+    int nA = 0;                    // coefficient terms: M + 1 (affine) or C(M + 2P, 2P) (log-normal)
     int nxi;
     int64_t nodes;             // (n+1)^2
     int64_t tstride;           // nxi * nodes
@@ -117,6 +119,12 @@ struct OpDev {                   // device pointers describing the operator of a
     const MemberDev* mem;        // [member]
     int mem_shared;              // 1 = all vectors use member 0
     const int* active;           // [vector] skip vectors whose flag is 0 (null: process all)
+    // general chaos coupling (log-normal field): per-element B_e = sum_l kappa_l(e) H_l,
+    // [member][e][i][j]; genBr keeps the terms l < truncation r (genB when r = n_A)
+    const double* genB;
+    const double* genBr;
+    int64_t gen_mstride;         // elements per member (0 = shared)
+    int gen;                     // 1: the general-coupling kernels
 };
 
 // Element-sweep kernels (sweep.hip); return false when the shape needs the
@@ -145,6 +153,19 @@ template <typename T>
 void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t modes_mask, int use_lower,
                     int use_upper, const T* base, ColMap base_map, const T* V, ColMap v_map, T* out,
                     ColMap out_map, int nmembers, hipStream_t st);
+
+// General chaos coupling (gen.hip): out_j = base_j + s sum_{i in [ilo1, ihi1) u
+// [ilo2, ihi2)} sum_e (B_e[i][j] + [i == j] mean_c) (K_ref X_i|e) for the L
+// output columns j0.. of every (vector, t) slice, B = genBr if trunc else genB,
+// s = scale or (scale_off) -off_scale of the member; X field blocks of member
+// stride xms and time stride xts.
+template <typename T>
+void launch_gen_sg(const Shape& s, const OpDev& op, bool trunc, const T* X, int64_t xms, int64_t xts, int ilo1,
+                   int ihi1, int ilo2, int ihi2, int j0, int L, const T* base, ColMap bmap, T* out, ColMap omap,
+                   double scale, int scale_off, double mean_c, int nvec, hipStream_t st);
+// KKT apply with the general coupling; T1, T2: scratch of one field block per vector each.
+template <typename T>
+void launch_gen_kkt(const Shape& s, const OpDev& op, const T* x, T* y, T* T1, T* T2, int nvec, hipStream_t st);
 
 // Chebyshev semi-iteration for the mass blocks (state + control) of nvec KKT vectors.
 template <typename T>

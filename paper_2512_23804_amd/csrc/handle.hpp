@@ -226,6 +226,8 @@ struct Handle {
     float* d_ainv32 = nullptr;
     double* d_rhs = nullptr;
     double* d_dst = nullptr;            // sine-transform tables: [2n] sin(pi m / n), [n+1] k_p, [n+1] m_p
+    double* d_genB = nullptr;           // general coupling: [member][e][i][j] B_e over all terms
+    double* d_genBr = nullptr;          // the same over the terms l < truncation r (null when r = n_A)
 
     Workspace ws;
     Prof prof;
@@ -236,7 +238,14 @@ struct Handle {
     // (set by FGMRES around its iterations; null: every vector is processed)
     const int* active = nullptr;
 
+    // coefficient terms kept by the hGS truncation (Section 5's n_tau)
+    int trunc_r() const {
+        const int nA = s.field == SG_FIELD_LOGNORMAL ? s.nA : s.M + 1;
+        return opt.truncation_r <= 0 ? nA : opt.truncation_r;
+    }
     uint32_t modes_mask() const {
+        // log-normal field: 0 mean-based, all ones every term, else the truncated terms (genBr)
+        if (s.field == SG_FIELD_LOGNORMAL) return trunc_r() <= 1 ? 0u : trunc_r() < s.nA ? 0x7fffffffu : 0xffffffffu;
         const int r = opt.truncation_r <= 0 ? s.M + 1 : opt.truncation_r;
         uint32_t m = 0;
         for (int k = 1; k < r && k <= s.M; ++k) m |= 1u << (k - 1);
@@ -253,6 +262,10 @@ struct Handle {
         o.mem = d_mem;
         o.mem_shared = shared ? 1 : 0;
         o.active = active;
+        o.genB = d_genB;
+        o.genBr = d_genBr ? d_genBr : d_genB;
+        o.gen_mstride = shared ? 0 : (int64_t)s.n * s.n * s.nxi * s.nxi;
+        o.gen = s.field == SG_FIELD_LOGNORMAL ? 1 : 0;
         return o;
     }
     template <typename T>
@@ -275,6 +288,13 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
 // its coefficient modes, scalars, multigrid constants, coarse inverse and
 // right-hand side, on the handle's stream (returns after the copies).
 void set_member(Handle& h, int b, const sg_problem& p);
+// lognormal.cpp: Hermite triple-product matrices H [n_A][nxi][nxi] and the
+// per-element chaos coefficients kappa [n_A][n][n] of the log-normal field,
+// and the element couplings B_e = sum_{l < r} kappa_l(e) H_l ([e][i][j])
+void lognormal_tables(const sg_problem& p, int nxi, const std::vector<int32_t>& alpha, std::vector<double>& H,
+                      std::vector<double>& kappa, int& nA);
+void lognormal_element_matrices(int n, int nxi, int nA, int r, const std::vector<double>& H,
+                                const std::vector<double>& kappa, double* B);
 std::vector<int32_t> multi_indices(int M, int P);
 int binom(int n, int k);
 

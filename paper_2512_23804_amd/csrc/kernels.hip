@@ -1309,6 +1309,22 @@ dim3 tile_grid(int n, int nchunks, int64_t slices) {
 // ---------------------------------------------------------------------------
 template <typename T>
 void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, uint32_t mask, hipStream_t st) {
+    if (op.gen) {
+        // general coupling: all terms, or (mask below all ones) the terms l < r of genBr
+        const ColMap full = [&] {
+            ColMap m;
+            m.mstride = s.blk;
+            m.tstride = s.tstride;
+            m.nodes = s.nodes;
+            m.L = s.nxi;
+            m.nt = s.nt;
+            m.j0 = 0;
+            return m;
+        }();
+        launch_gen_sg<T>(s, op, mask != 0xffffffffu, x, s.blk, s.tstride, 0, s.nxi, 0, 0, 0, s.nxi, (const T*)nullptr,
+                         full, y, full, 1.0, 0, 0.0, nvec, st);
+        return;
+    }
     if (launch_sgx_apply<T>(s, op, x, y, nvec, mask, st)) return;
     dim3 g = tile_grid(s.n, (s.nxi + kJChunk - 1) / kJChunk, (int64_t)nvec * s.nt);
     hipLaunchKernelGGL(k_sg_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, x, y, mask);
@@ -1317,6 +1333,7 @@ void launch_sg_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec
 
 template <typename T>
 void launch_kkt_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
+    if (op.gen) throw Error(SG_ERR_INVALID, "internal: the general-coupling KKT apply needs scratch (launch_gen_kkt)");
     if (launch_sgx_kkt<T>(s, op, x, y, nvec, st)) return;
     dim3 g = tile_grid(s.n, (s.nxi + kJChunk - 1) / kJChunk, (int64_t)nvec * s.nt);
     hipLaunchKernelGGL(k_kkt_apply<T>, g, dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, (int)s.time, s.nodes, op, x, y);
@@ -1327,6 +1344,13 @@ template <typename T>
 void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
                     const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
                     hipStream_t st) {
+    if (op.gen) {
+        // the coupled columns of every other level: all lower ones and/or all upper ones
+        const int lo = s.off[d], hi = s.off[d + 1];
+        launch_gen_sg<T>(s, op, true, V, vmap.mstride, vmap.tstride, 0, use_lower ? lo : 0, hi, use_upper ? s.nxi : hi,
+                         lo, hi - lo, base, bmap, out, omap, 0.0, 1, 0.0, nmembers, st);
+        return;
+    }
     if (launch_sgx_hgs_rhs<T>(s, op, d, mask, use_lower, use_upper, base, bmap, V, vmap, out, omap, nmembers, st))
         return;
     const int L = s.off[d + 1] - s.off[d];

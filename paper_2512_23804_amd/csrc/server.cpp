@@ -54,11 +54,16 @@ size_t footprint_bytes(const sg_problem& p, const sg_options& o) {
     bytes += sz * blk * 3 + sz * 4 * nodes * 1.4 * nxi * 0.6;
     if (refine) bytes += 4.0 * N * (v32 ? 2 : 3);                      // FP32 operator output and staging
     if (o.precision == SG_PREC_FP32_PRECOND) bytes += 4.0 * N + 8.0 * N;   // FP32 staging, FP64 copy of Z_j
+    if (p.field == SG_FIELD_LOGNORMAL) {
+        // element coupling tables (all terms, and the truncated ones) and the KKT stiffness scratch
+        bytes += 8.0 * (double)p.n * p.n * nxi * nxi * (o.truncation_r > 0 ? 2 : 1) + 8.0 * 2 * blk;
+    }
     return (size_t)bytes;
 }
 
 bool same_shape(const Request& a, const Request& b) {
-    return a.prob.n == b.prob.n && a.prob.M == b.prob.M && a.prob.P == b.prob.P && a.opt.precision == b.opt.precision &&
+    return a.prob.n == b.prob.n && a.prob.M == b.prob.M && a.prob.P == b.prob.P && a.prob.field == b.prob.field &&
+           a.opt.precision == b.opt.precision &&
            a.opt.restart == b.opt.restart && a.opt.max_iter == b.opt.max_iter && a.opt.rtol == b.opt.rtol &&
            a.opt.cheb_steps == b.opt.cheb_steps && a.opt.truncation_r == b.opt.truncation_r &&
            a.opt.gmg_pre == b.opt.gmg_pre && a.opt.gmg_post == b.opt.gmg_post && a.opt.inner_rtol == b.opt.inner_rtol &&

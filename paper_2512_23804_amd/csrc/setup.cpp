@@ -70,6 +70,12 @@ static void fail(int code, const std::string& m) { throw Error(code, m); }
 static std::vector<double> coefficient_modes(const sg_problem& p) {
     const int n = p.n, M = p.M;
     std::vector<double> c((size_t)(M + 1) * n * n);
+    if (p.field == SG_FIELD_LOGNORMAL) {
+        // the mean coefficient (kappa_1 = 1); the log-normal terms live in the
+        // element couplings of the general kernels
+        std::fill(c.begin(), c.begin() + (size_t)n * n, 1.0);
+        return c;
+    }
     if (p.kappa) {
         std::memcpy(c.data(), p.kappa, c.size() * sizeof(double));
         return c;
@@ -103,6 +109,9 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
         if (p.n_t > 4096) fail(SG_ERR_INVALID, who + "n_t above 4096");
         if (p.n != p0.n || p.M != p0.M || p.P != p0.P || std::max(p.n_t, 1) != std::max(p0.n_t, 1))
             fail(SG_ERR_INVALID, who + "members of one batch must share n, M, P, n_t");
+        if (p.field != SG_FIELD_AFFINE && p.field != SG_FIELD_LOGNORMAL)
+            fail(SG_ERR_INVALID, who + "field must be SG_FIELD_AFFINE or SG_FIELD_LOGNORMAL");
+        if (p.field != p0.field) fail(SG_ERR_INVALID, who + "members of one batch must share the field model");
         if (!std::isfinite(p.beta) || !std::isfinite(p.gamma) || !std::isfinite(p.sigma) ||
             (p.n_t >= 2 && !std::isfinite(p.T)))
             fail(SG_ERR_NONFINITE, who + "non-finite scalar parameter");
@@ -119,6 +128,18 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
             if (p.n_t < 2) fail(SG_ERR_INVALID, who + "y0 given for a steady problem");
             for (size_t q = 0; q < nodes; ++q)
                 if (!std::isfinite(p.y0[q])) fail(SG_ERR_NONFINITE, who + "non-finite initial state");
+        }
+        if (p.field == SG_FIELD_LOGNORMAL) {
+            // exp of a Gaussian field: positive for every xi, and its degree-2P chaos
+            // projection gives positive definite element couplings (lognormal.cpp)
+            if (p.kappa) fail(SG_ERR_INVALID, who + "kappa must be NULL for the log-normal field");
+            if (!std::isfinite(p.corr_len) || !(p.corr_len > 0)) fail(SG_ERR_INVALID, who + "corr_len must be > 0");
+            if (!(p.sigma >= 0)) fail(SG_ERR_INVALID, who + "sigma must be >= 0");
+            const double nxi = binom(p.M + p.P, p.P);
+            if (nxi > 256) fail(SG_ERR_INVALID, who + "log-normal field: chaos dimension above 256");
+            if ((double)p.n * p.n * nxi * nxi * 8.0 > 8.0 * (1ull << 30))
+                fail(SG_ERR_INVALID, who + "log-normal field: element coupling tables above 8 GiB per member");
+            continue;
         }
         // coefficient: finite, constant positive mean, bounded away from zero for all xi
         const size_t ne = (size_t)p.n * p.n;
@@ -160,8 +181,10 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
             fail(SG_ERR_INVALID, "mean_solver must be SG_MEAN_MULTIGRID or SG_MEAN_EXACT");
         if (opt->richardson_steps < 1 || opt->richardson_steps > 16)
             fail(SG_ERR_INVALID, "richardson_steps must be in [1, 16]");
-        if (opt->truncation_r < 0 || opt->truncation_r > p0.M + 1)
-            fail(SG_ERR_INVALID, "truncation_r must be in [0, M+1]");
+        const int nterms = p0.field == SG_FIELD_LOGNORMAL ? binom(p0.M + 2 * p0.P, 2 * p0.P) : p0.M + 1;
+        if (opt->truncation_r < 0 || opt->truncation_r > nterms)
+            fail(SG_ERR_INVALID, "truncation_r must be in [0, number of coefficient terms] (M+1 affine, "
+                                 "C(M+2P, 2P) log-normal)");
         if (opt->gmg_pre < 1 || opt->gmg_pre > kMaxSmooth || opt->gmg_post < 1 || opt->gmg_post > kMaxSmooth)
             fail(SG_ERR_INVALID, "gmg_pre/gmg_post must be in [1, 4]");
         if (opt->precision != SG_PREC_FP64 && opt->precision != SG_PREC_FP32_REFINE &&
@@ -303,7 +326,8 @@ static void pinned_put(double* p) {
 Handle::~Handle() {
     ws.release();
     for (void* p : {(void*)d_nbr_idx, (void*)d_nbr_val, (void*)d_coef64, (void*)d_coef32, (void*)d_mem,
-                    (void*)d_lev, (void*)d_ainv64, (void*)d_ainv32, (void*)d_rhs, (void*)d_dst})
+                    (void*)d_lev, (void*)d_ainv64, (void*)d_ainv32, (void*)d_rhs, (void*)d_dst, (void*)d_genB,
+                    (void*)d_genBr})
         if (p) {
             if (pool)
                 pool->release(p);
@@ -403,12 +427,33 @@ static void fill_member(Handle* h, int b, const sg_problem& p, double* rb) {
     }
 }
 
+// Element couplings of member b (log-normal field), computed on the host and
+// copied to the member's slices of the device tables (synchronously).
+static void upload_lognormal_member(Handle& h, int b, const sg_problem& p) {
+    const Shape& s = h.s;
+    std::vector<double> H, kappa;
+    int nA = 0;
+    lognormal_tables(p, s.nxi, h.ht.alpha, H, kappa, nA);
+    const size_t per = (size_t)s.n * s.n * s.nxi * s.nxi;
+    std::vector<double> B(per);
+    lognormal_element_matrices(s.n, s.nxi, nA, nA, H, kappa, B.data());
+    SG_HIP(hipMemcpy(h.d_genB + per * b, B.data(), sizeof(double) * per, hipMemcpyHostToDevice));
+    if (h.d_genBr) {
+        lognormal_element_matrices(s.n, s.nxi, nA, h.trunc_r(), H, kappa, B.data());
+        SG_HIP(hipMemcpy(h.d_genBr + per * b, B.data(), sizeof(double) * per, hipMemcpyHostToDevice));
+    }
+}
+
 void set_member(Handle& h, int b, const sg_problem& p) {
     const Shape& s = h.s;
     if (b < 0 || b >= h.B) throw Error(SG_ERR_INVALID, "member index out of range");
     validate(&p, 1, &h.opt);
-    if (p.n != s.n || p.M != s.M || p.P != s.P || (p.n_t >= 2 ? p.n_t : 1) != s.nt)
-        throw Error(SG_ERR_INVALID, "a member's problem must have the handle's n, M, P and n_t");
+    if (p.n != s.n || p.M != s.M || p.P != s.P || (p.n_t >= 2 ? p.n_t : 1) != s.nt || p.field != s.field)
+        throw Error(SG_ERR_INVALID, "a member's problem must have the handle's n, M, P, n_t and field model");
+    if (s.field == SG_FIELD_LOGNORMAL) {
+        SG_HIP(hipStreamSynchronize(h.stream));     // the tables may be in use by earlier launches
+        upload_lognormal_member(h, b, p);
+    }
     const size_t rcols = (size_t)2 * s.nt * s.nodes;
     std::vector<double> rb(rcols, 0.0);
     fill_member(&h, b, p, rb.data());
@@ -474,6 +519,8 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
     for (int d = 0; d <= s.P + 1; ++d) s.off[d] = d == 0 ? 0 : binom(s.M + d - 1, d - 1);
     s.nlev_mg = 0;
     for (int m = s.n; m >= kCoarseN; m /= 2) s.mg_n[s.nlev_mg++] = m;
+    s.field = p0.field;
+    s.nA = s.field == SG_FIELD_LOGNORMAL ? binom(s.M + 2 * s.P, 2 * s.P) : s.M + 1;
 
     // multi-index set and triple-product neighbour table:
     // E[psi_{e_k} psi_a psi_{a+e_k}] = sqrt(3) m / sqrt(4 m^2 - 1), m = a_k + 1
@@ -546,6 +593,13 @@ std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const s
             t[2 * n + (n + 1) + q] = (2.0 + std::cos(M_PI * q / n)) / (3.0 * n);
         }
         h->d_dst = upload(t.data(), t.size(), pool);
+    }
+    if (s.field == SG_FIELD_LOGNORMAL) {
+        const size_t per = (size_t)n * n * s.nxi * s.nxi;
+        const int r = h->trunc_r();
+        h->d_genB = upload<double>(nullptr, per * count, pool);
+        if (r < s.nA) h->d_genBr = upload<double>(nullptr, per * count, pool);
+        for (int b = 0; b < count; ++b) upload_lognormal_member(*h, b, probs[b]);
     }
     {
         // right-hand sides: zero everywhere but chaos column 0 of the state

@@ -248,7 +248,13 @@ void operator_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStrea
 template <typename T>
 void kkt_apply(Handle& h, const T* x, T* y, int nvec, bool shared, hipStream_t st) {
     const bool tp = prof_begin(h, SG_PROF_KKT_APPLY, st);
-    launch_kkt_apply<T>(h.s, h.op<T>(shared), x, y, nvec, st);
+    if (h.s.field == SG_FIELD_LOGNORMAL) {
+        T* T1 = h.ws.get_t<T>(std::string("genT1") + tname<T>(), (size_t)nvec * h.s.blk);
+        T* T2 = h.ws.get_t<T>(std::string("genT2") + tname<T>(), (size_t)nvec * h.s.blk);
+        launch_gen_kkt<T>(h.s, h.op<T>(shared), x, y, T1, T2, nvec, st);
+    } else {
+        launch_kkt_apply<T>(h.s, h.op<T>(shared), x, y, nvec, st);
+    }
     // algorithmic bytes: read the three fields, write the three results, read the coefficient modes
     if (tp)
         prof_end(h, st,

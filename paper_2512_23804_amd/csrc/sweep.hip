@@ -671,7 +671,7 @@ SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
 // Returns false when the sweep kernels do not cover the shape (M > 8).
 template <typename T>
 bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, uint32_t mask, hipStream_t st) {
-    if (s.M > KMAX) return false;
+    if (s.M > KMAX || s.field != SG_FIELD_AFFINE) return false;
     ColMap z{};
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_APPLY];
     const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, rows);
@@ -685,7 +685,7 @@ bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nve
 
 template <typename T>
 bool launch_sgx_kkt(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, hipStream_t st) {
-    if (s.M > KMAX) return false;
+    if (s.M > KMAX || s.field != SG_FIELD_AFFINE) return false;
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_KKT];
     const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, rows);
     const int grid = (g.nb + 7) / 8 * 8;
@@ -703,7 +703,7 @@ template <typename T>
 bool launch_sgx_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int use_lower, int use_upper,
                         const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
                         hipStream_t st) {
-    if (s.M > KMAX) return false;
+    if (s.M > KMAX || s.field != SG_FIELD_AFFINE) return false;
     const int L = s.off[d + 1] - s.off[d];
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_HGS];
     const SweepGeom g = make_geom(s.n, L, (int64_t)nmembers * s.nt, rows);

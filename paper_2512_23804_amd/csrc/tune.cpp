@@ -87,7 +87,7 @@ void autotune(Handle& h) {
     const int forced = h.opt.sweep_rows;
     for (int t = 0; t < 2; ++t)
         for (int k = 0; k < 3; ++k) s.sweep_rows[t][k] = forced > 0 ? forced : 4;
-    if (forced > 0 || s.M > 8) return;      // fixed by the caller, or no sweep kernels for this shape
+    if (forced > 0 || s.field != SG_FIELD_AFFINE || s.M > 8) return;      // fixed by the caller, or no sweep kernels for this shape
     const bool need32 = h.opt.precision != SG_PREC_FP64;
     for (int t = 0; t < (need32 ? 2 : 1); ++t) {
         // batches of any size above one share a choice (the serving loop forms

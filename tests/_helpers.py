@@ -8,10 +8,14 @@ import sg_inputs
 from oracle import fem, kkt
 
 
-def make_case(n, M, P, sigma, beta, gamma=0.0, n_t=1, T=1.0, seed=0, y0=False, kappa=None):
+def make_case(n, M, P, sigma, beta, gamma=0.0, n_t=1, T=1.0, seed=0, y0=False, kappa=None, field="affine",
+              corr=1.0):
     """Return (oracle Problem, dict of library ProblemData kwargs) built from the
-    same seeded inputs."""
-    if n_t <= 1:
+    same seeded inputs.  field="lognormal": the log-normal coefficient with
+    Hermite chaos and, when steady, the indicator target of Section 5."""
+    if field == "lognormal" and n_t <= 1:
+        target = sg_inputs.indicator_target(n)
+    elif n_t <= 1:
         target = sg_inputs.gaussian_bumps(n, seed)
     else:
         target = sg_inputs.moving_bump(n, n_t, T, seed)
@@ -19,9 +23,9 @@ def make_case(n, M, P, sigma, beta, gamma=0.0, n_t=1, T=1.0, seed=0, y0=False, k
     if y0:
         y0v = sg_inputs.gaussian_bumps(n, seed + 100) * sg_inputs.unit_sine(n)
     prob = kkt.Problem(n=n, M=M, P=P, sigma=sigma, beta=beta, gamma=gamma, n_t=n_t, T=T,
-                       y_target=target, kappa=kappa, y0=y0v)
+                       y_target=target, kappa=kappa, y0=y0v, field=field, corr=corr)
     lib_kw = dict(n=n, M=M, P=P, sigma=sigma, beta=beta, y_target=target, gamma=gamma, n_t=n_t, T=T,
-                  kappa=kappa, y0=y0v)
+                  kappa=kappa, y0=y0v, field=1 if field == "lognormal" else 0, corr_len=corr)
     return prob, lib_kw
 
 

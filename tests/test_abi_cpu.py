@@ -126,3 +126,19 @@ def test_serving_stream_shapes_do_not_depend_on_the_rate():
     assert all(4 <= r["M"] <= 8 and 2 <= r["P"] <= 4 and 0.1 <= r["sigma"] <= 0.3 for r in q)
     assert all(1e-6 <= r["beta"] <= 1e-1 for r in q)
     assert [r["seed"] for r in q] == list(range(1000, 1064))
+
+
+def test_validate_lognormal_field():
+    import paper_2512_23804_amd as sgl
+    ln = dict(field=sgl.SG_FIELD_LOGNORMAL, y_target=sg_inputs.indicator_target(16))
+    assert sgl.validate(_pd(**ln)) == sgl.SG_OK
+    assert sgl.validate(_pd(field=2)) == sgl.SG_ERR_INVALID
+    assert sgl.validate(_pd(corr_len=0.0, **ln)) == sgl.SG_ERR_INVALID
+    kap = np.ones((5, 16, 16))
+    assert sgl.validate(_pd(kappa=kap, **ln)) == sgl.SG_ERR_INVALID
+    # a log-normal field may use sigma large enough to break the affine field's coercivity
+    assert sgl.validate(_pd(sigma=2.0, **ln)) == sgl.SG_OK
+    # truncation up to n_A = C(M + 2P, 2P) terms (M = 4, P = 3: 210), the affine field up to M + 1
+    assert sgl.validate(_pd(**ln), sgl.default_options(truncation_r=210)) == sgl.SG_OK
+    assert sgl.validate(_pd(**ln), sgl.default_options(truncation_r=211)) == sgl.SG_ERR_INVALID
+    assert sgl.validate(_pd(), sgl.default_options(truncation_r=6)) == sgl.SG_ERR_INVALID

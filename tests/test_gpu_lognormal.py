@@ -1,0 +1,128 @@
+"""GPU parity for the log-normal coefficient with Hermite chaos (Section 5's
+workload): the general-coupling kernels (every H_l, intra-level couplings
+included) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from oracle import kkt, precond
+from tests._helpers import canonical_to_kkt, kkt_to_canonical, make_case, rel_max
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _lib():
+    import paper_2512_23804_amd as sgl
+    return sgl
+
+
+def ring_is_zero(v, n):
+    V = v.reshape(-1, n + 1, n + 1)
+    return (np.all(V[:, 0, :] == 0) and np.all(V[:, -1, :] == 0) and np.all(V[:, :, 0] == 0)
+            and np.all(V[:, :, -1] == 0))
+
+
+CASES = [
+    # n, M, P, sigma, beta, gamma, n_t
+    (16, 2, 2, 0.3, 1e-2, 1.0, 1),
+    (32, 3, 2, 0.2, 1e-3, 1.0, 1),
+    (16, 3, 3, 0.2, 1e-2, 0.0, 1),
+    (16, 2, 2, 0.25, 1e-3, 1.0, 3),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_lognormal_applies(case):
+    """Operator, KKT and preconditioner applies (three truncations: mean-based,
+    the linear terms, every term) against the oracle, element by element."""
+    n, M, P, sigma, beta, gamma, nt = case
+    dev = _dev()
+    sgl = _lib()
+    _say(f"lognormal applies {case}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, field="lognormal")
+    sg = kkt.setup(prob)
+    nA = len(sg.G)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1, 1, size=kkt.rhs(sg).size)
+    xd = torch.from_numpy(kkt_to_canonical(sg, x)).to(dev)
+    # the SG operator on the state block
+    h = sgl.Handle(sgl.ProblemData(**kw), sgl.default_options())
+    Xs = kkt.split(sg, x)[0]
+    xs_d = xd[: h.block_elems].clone()
+    ys_d = torch.full_like(xs_d, np.nan)
+    h.apply_operator(xs_d, ys_d)
+    yd = torch.full_like(xd, np.nan)
+    h.apply_kkt(xd, yd)
+    torch.cuda.synchronize()
+    if prob.steady:
+        ref_op = kkt.operator_apply(sg, Xs)
+    else:
+        ref_op = np.stack([kkt.operator_apply(sg, Xs[t]) for t in range(nt)])
+    got_op = canonical_to_kkt(sg, np.concatenate([ys_d.cpu().numpy()] * 3))[: ref_op.size].reshape(ref_op.shape)
+    assert rel_max(got_op, ref_op) < 1e-12
+    assert ring_is_zero(ys_d.cpu().numpy(), n) and ring_is_zero(yd.cpu().numpy(), n)
+    assert rel_max(canonical_to_kkt(sg, yd.cpu().numpy()), kkt.kkt_apply_matricized(sg, x)) < 1e-12
+    h.close()
+    for r in (1, M + 1, nA):
+        h = sgl.Handle(sgl.ProblemData(**kw), sgl.default_options(truncation_r=r))
+        zd = torch.full_like(xd, np.nan)
+        h.precond_apply(xd, zd)
+        torch.cuda.synchronize()
+        ref = precond.precond_apply(sg, x, precond.make_inner(sg), r)
+        assert rel_max(canonical_to_kkt(sg, zd.cpu().numpy()), ref) < 1e-12, r
+        assert ring_is_zero(zd.cpu().numpy(), n)
+        h.close()
+
+
+@pytest.mark.parametrize("case,opts", [
+    (CASES[0], {}),
+    (CASES[1], dict(truncation_r=4)),
+    (CASES[3], {}),
+    (CASES[0], dict(precision=1)),
+    (CASES[0], dict(mean_solver=1, richardson_steps=2, truncation_r=3)),
+])
+def test_lognormal_solve_matches_direct(case, opts):
+    n, M, P, sigma, beta, gamma, nt = case
+    dev = _dev()
+    sgl = _lib()
+    _say(f"lognormal solve {case} {opts}")
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, field="lognormal")
+    sg = kkt.setup(prob)
+    h = sgl.Handle(sgl.ProblemData(**kw), sgl.default_options(rtol=1e-12, max_iter=800, **opts))
+    xd = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+    rc, info = h.solve(xd)
+    assert rc == 0 and info[0].rel_res_true <= 1e-12
+    xs = canonical_to_kkt(sg, xd.cpu().numpy())
+    for a, b in zip(kkt.split(sg, xs), kkt.split(sg, kkt.solve_direct(sg))):
+        assert rel_max(a, b) < 1e-8
+    h.close()
+
+
+def test_lognormal_batch_equals_alone():
+    """Members with different sigma and correlation length in one batch give
+    bit-identical results to their alone solves."""
+    dev = _dev()
+    sgl = _lib()
+    _say("lognormal batch invariance")
+    kws = [make_case(16, 3, 2, s, b, 1.0, field="lognormal", corr=c)[1]
+           for s, b, c in ((0.2, 1e-2, 1.0), (0.3, 1e-4, 0.5), (0.1, 1e-3, 2.0))]
+    hb = sgl.Handle([sgl.ProblemData(**kw) for kw in kws], sgl.default_options(rtol=1e-10))
+    xb = torch.zeros(3 * hb.kkt_elems, dtype=torch.float64, device=dev)
+    rc, infos = hb.solve(xb)
+    assert rc == 0
+    for i, kw in enumerate(kws):
+        ha = sgl.Handle([sgl.ProblemData(**kw)], sgl.default_options(rtol=1e-10))
+        xa = torch.zeros(ha.kkt_elems, dtype=torch.float64, device=dev)
+        rca, infa = ha.solve(xa)
+        assert rca == 0 and infa[0].iters == infos[i].iters
+        assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
