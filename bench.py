@@ -51,9 +51,28 @@ PROF_KIND = {"kkt_apply": 1, "mg_down": 2, "arnoldi_dots": 3, "hgs_rhs": 4, "arn
 ARNOLDI = {"dcgs2": 0, "cgs2": 1}
 
 
-# sources of the kernels whose HBM traffic is taken from a committed counter summary
-TRAFFIC_SOURCES = ("paper_2512_23804_amd/csrc/kernels.hip", "paper_2512_23804_amd/csrc/solver.cpp",
-                   "paper_2512_23804_amd/csrc/common.hpp")
+# the source text behind the Arnoldi passes whose HBM traffic is taken from a committed
+# counter summary: the DCGS2 kernels and their launchers in kernels.hip, and the
+# launch shape (blocks per member vector) in solver.cpp
+TRAFFIC_REGIONS = (
+    ("paper_2512_23804_amd/csrc/kernels.hip", "constexpr int kDotsU", "void k_dcgs_finish("),
+    ("paper_2512_23804_amd/csrc/kernels.hip", "void launch_dcgs_dots(", "void launch_dcgs_finish("),
+    ("paper_2512_23804_amd/csrc/solver.cpp", "nblk = ", "\n"),
+)
+
+
+def traffic_source_digest() -> str:
+    """sha256 over the source regions in TRAFFIC_REGIONS (start marker up to,
+    not including, the end marker)."""
+    import hashlib
+    h = hashlib.sha256()
+    for src, start, end in TRAFFIC_REGIONS:
+        with open(os.path.join(ROOT, src)) as f:
+            text = f.read()
+        i = text.index(start)
+        j = text.index(end.encode().decode("unicode_escape"), i + len(start))
+        h.update(text[i:j].encode())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, workload):
@@ -62,7 +81,6 @@ def measured_traffic(kernel, workload):
     copy probe), or None when no summary covers this kernel and workload or the
     kernel sources changed since the counters were taken."""
     import glob
-    import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic_*.md"))):
         kv = {}
         with open(path) as f:
@@ -72,11 +90,7 @@ def measured_traffic(kernel, workload):
                     kv[k.strip()] = v.strip()
         if kv.get("kernel") != kernel or kv.get("workload") != workload:
             continue
-        h = hashlib.sha256()
-        for src in TRAFFIC_SOURCES:
-            with open(os.path.join(ROOT, src), "rb") as f:
-                h.update(f.read())
-        if h.hexdigest() != kv.get("sources_sha256"):
+        if traffic_source_digest() != kv.get("sources_sha256"):
             return None
         return float(kv["traffic_bytes_per_launch"])
     return None
