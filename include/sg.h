@@ -159,6 +159,14 @@ typedef struct sg_problem {
  *                2D sine transform on FP64 MFMA; the mean coefficient is
  *                constant, so the block is a K + b M on the uniform grid)
  *                [SG_MEAN_MULTIGRID]
+ *   precond      SG_PRECOND_BLOCK_DIAGONAL: the block-diagonal preconditioner
+ *                of eq. (stoch-prec) / eq. (precon for time); SG_PRECOND_HGSOC:
+ *                the coupled level sweep of Algorithms 2-3 (steady problems,
+ *                cheb_steps 1..9), each level solved with the block-diagonal
+ *                preconditioner restricted to its chaos columns (the adjoint
+ *                by A-tilde_1^{-1} h^gamma_j M A-tilde_1^{-1}: the printed
+ *                third block A-tilde_1 does not approximate the adjoint row)
+ *                [SG_PRECOND_BLOCK_DIAGONAL]
  *   richardson_steps  N of the preconditioned Richardson iteration of
  *                Algorithm 5 for each Z^{-1} of the Schur block, each step
  *                preconditioned by one hGS sweep (Algorithm 1); N = 1 is one
@@ -181,7 +189,11 @@ typedef struct sg_options {
     int32_t basis_fp32;
     int32_t mean_solver;
     int32_t richardson_steps;
+    int32_t precond;
 } sg_options;
+
+#define SG_PRECOND_BLOCK_DIAGONAL 0
+#define SG_PRECOND_HGSOC          1
 
 #define SG_MEAN_MULTIGRID 0
 #define SG_MEAN_EXACT     1

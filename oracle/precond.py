@@ -373,13 +373,14 @@ class PtildeSolve:
     M (the mass solves of the block preconditioner) and one multigrid V-cycle
     for A-tilde_1 (the solver's choice).
 
-    adjoint "literal": the third block is A-tilde_1 as printed.  adjoint
-    "schur": the third block is the mean Schur approximation A-tilde_1
-    M^{-1} A-tilde_1 (applied as A-tilde_1^{-1} M A-tilde_1^{-1}), the
-    adjoint block of the block-diagonal preconditioner restricted to one
-    chaos column: the adjoint row of the level-diagonal KKT block has no
-    entry on the adjoint itself, so A-tilde_1 alone does not approximate it
-    (with it the coupled sweep stagnates; see the iteration counts)."""
+    adjoint "literal": P-tilde = blkdiag(M, beta M, A-tilde_1) as printed.
+    adjoint "schur": the block-diagonal preconditioner of eq. (stoch-prec)
+    restricted to chaos column j: blkdiag(h^gamma_j M, beta M, A-tilde_1
+    (h^gamma_j M)^{-1} A-tilde_1), the third block applied as A-tilde_1^{-1}
+    h^gamma_j M A-tilde_1^{-1}.  The adjoint row of the level-diagonal KKT
+    block has no entry on the adjoint itself, so A-tilde_1 alone does not
+    approximate it (with it the coupled sweep stagnates; see the iteration
+    counts)."""
 
     def __init__(self, sg: kkt.SG, mode: str = "cheb", cheb_steps: int = 5, nu_pre: int = 2, nu_post: int = 2,
                  adjoint: str = "literal"):
@@ -394,10 +395,13 @@ class PtildeSolve:
             return self.mlu.solve(np.ascontiguousarray(R.T)).T
         return cheb_mass(self.sg.Mi, R, self.cheb_steps)
 
-    def apply(self, BY: np.ndarray, BU: np.ndarray, BL: np.ndarray):
+    def apply(self, BY: np.ndarray, BU: np.ndarray, BL: np.ndarray, lo: int = 0, hi: int | None = None):
+        """Rows of BY, BU, BL are the chaos columns lo..hi-1."""
         VL = self.inner.apply(BL)
         if self.adjoint == "schur":
-            VL = self.inner.apply(kkt.mass_apply(self.sg, VL))
+            hg = kkt.h_gamma(self.sg)[lo:hi if hi is not None else lo + np.atleast_2d(BL).shape[0]][:, None]
+            VL = self.inner.apply(hg * kkt.mass_apply(self.sg, VL))
+            return self.mass_inv(BY) / hg, self.mass_inv(BU) / self.sg.prob.beta, VL
         return self.mass_inv(BY), self.mass_inv(BU) / self.sg.prob.beta, VL
 
 
@@ -450,17 +454,18 @@ def hgsoc(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int) -> np.nd
         by = Ry[lo:hi] - C + D
         bu = Ru[lo:hi] - E - F
         bl = Rl[lo:hi] + G - Hh
-        VY[lo:hi], VU[lo:hi], VL[lo:hi] = ptilde.apply(by, bu, bl)
+        VY[lo:hi], VU[lo:hi], VL[lo:hi] = ptilde.apply(by, bu, bl, lo, hi)
     return np.concatenate([VY.ravel(), VU.ravel(), VL.ravel()])
 
 
-def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int) -> tuple:
+def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int, col_weights: tuple | None = None) -> tuple:
     """The matrices behind Algorithms 2-3 with exact P-tilde solves: the level
     splitting K_r = D + L + U of the KKT matrix with every level-diagonal
     block replaced by P-tilde (per chaos column) and the off-level couplings
     truncated to the kept modes; one forward and one backward block
     Gauss-Seidel sweep from zero then equal (D + U)^{-1} D (D + L)^{-1}.
-    ptilde_blocks = (M, beta M, A-tilde_1) as sparse matrices.  Returns
+    ptilde_blocks = (M, beta M, A-tilde_1) as sparse matrices, scaled per
+    chaos column by col_weights = (w_Y, w_U, w_Lambda) when given.  Returns
     (D, L, U) over the unknown order [Y | U | Lambda], chaos-major inside a block."""
     p = sg.prob
     nxi, ni = sg.n_xi, sg.n_int
@@ -471,7 +476,10 @@ def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int) -> tuple:
         level[int(off[d]):int(off[d + 1])] = d
     modes = list(range(1, min(r_trunc, len(sg.G))))
     I = sp.identity(nxi, format="csr")
-    Dg = sp.block_diag([sp.kron(I, Mb), sp.kron(I, bMb), sp.kron(I, A1)], format="csr")
+    if col_weights is None:
+        Dg = sp.block_diag([sp.kron(I, Mb), sp.kron(I, bMb), sp.kron(I, A1)], format="csr")
+    else:
+        Dg = sp.block_diag([sp.kron(sp.diags(w), B) for w, B in zip(col_weights, (Mb, bMb, A1))], format="csr")
     # off-level couplings of the KKT rows (state: -A Lambda; adjoint: -A Y)
     Aoff = None
     for k in modes:

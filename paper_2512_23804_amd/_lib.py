@@ -24,6 +24,7 @@ SG_PROF_ARNOLDI_UPD, SG_PROF_MG_TAIL, SG_PROF_MASS_CHEB, SG_PROF_MG_UP = 5, 6, 7
 SG_ARNOLDI_DCGS2, SG_ARNOLDI_CGS2 = 0, 1
 SG_MEAN_MULTIGRID, SG_MEAN_EXACT = 0, 1
 SG_FIELD_AFFINE, SG_FIELD_LOGNORMAL = 0, 1
+SG_PRECOND_BLOCK_DIAGONAL, SG_PRECOND_HGSOC = 0, 1
 
 _DP = C.POINTER(C.c_double)
 
@@ -40,7 +41,7 @@ class sg_options(C.Structure):
                 ("gmg_post", C.c_int32), ("precision", C.c_int32), ("inner_rtol", C.c_double),
                 ("use_graphs", C.c_int32), ("verbose", C.c_int32), ("profile", C.c_int32),
                 ("arnoldi", C.c_int32), ("sweep_rows", C.c_int32), ("basis_fp32", C.c_int32),
-                ("mean_solver", C.c_int32), ("richardson_steps", C.c_int32)]
+                ("mean_solver", C.c_int32), ("richardson_steps", C.c_int32), ("precond", C.c_int32)]
 
 
 class sg_solve_info(C.Structure):

@@ -266,6 +266,7 @@ struct Handle {
         o.genBr = d_genBr ? d_genBr : d_genB;
         o.gen_mstride = shared ? 0 : (int64_t)s.n * s.n * s.nxi * s.nxi;
         o.gen = s.field == SG_FIELD_LOGNORMAL ? 1 : 0;
+        o.off_sign = 1.0;
         return o;
     }
     template <typename T>

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_hgs_rhs(int n, int M, int nxi, int nt, 
     const int mem = op.mem_shared ? 0 : mem_i;
     const double* coef = op.coef64 + (int64_t)mem * op.coef_mstride;
     const int64_t cplane = (int64_t)n * n;
-    const double scale = op.mem[mem].off_scale;
+    const double scale = op.off_sign * op.mem[mem].off_scale;
     const bool interior = ix > 0 && ix < n && iy > 0 && iy < n;
     const int64_t p = (int64_t)iy * (n + 1) + ix;
     const T* Vb = V + (int64_t)mem_i * vmap.mstride + (int64_t)t * vmap.tstride;
@@ -1347,8 +1347,13 @@ void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int u
     if (op.gen) {
         // the coupled columns of every other level: all lower ones and/or all upper ones
         const int lo = s.off[d], hi = s.off[d + 1];
-        launch_gen_sg<T>(s, op, true, V, vmap.mstride, vmap.tstride, 0, use_lower ? lo : 0, hi, use_upper ? s.nxi : hi,
-                         lo, hi - lo, base, bmap, out, omap, 0.0, 1, 0.0, nmembers, st);
+        if (op.off_sign == 1.0)
+            launch_gen_sg<T>(s, op, true, V, vmap.mstride, vmap.tstride, 0, use_lower ? lo : 0, hi,
+                             use_upper ? s.nxi : hi, lo, hi - lo, base, bmap, out, omap, 0.0, 1, 0.0, nmembers, st);
+        else      // (steady: off_scale = 1)
+            launch_gen_sg<T>(s, op, true, V, vmap.mstride, vmap.tstride, 0, use_lower ? lo : 0, hi,
+                             use_upper ? s.nxi : hi, lo, hi - lo, base, bmap, out, omap, -op.off_sign, 0, 0.0, nmembers,
+                             st);
         return;
     }
     if (launch_sgx_hgs_rhs<T>(s, op, d, mask, use_lower, use_upper, base, bmap, V, vmap, out, omap, nmembers, st))

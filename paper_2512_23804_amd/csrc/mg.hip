@@ -308,7 +308,7 @@ struct ChebW {
 template <typename T, int TF, int H, int NT>
 __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, int time, int64_t nodes, OpDev op,
                                                          int64_t vstride, const T* __restrict__ r, T* __restrict__ z,
-                                                         ChebW cw, int tiles_x) {
+                                                         ChebW cw, int tiles_x, int64_t zstride, int l0) {
     // H = steps - 1 stencil steps; the region keeps a halo of at least one node
     // so that the first tile row and column also hold the ring at index 0
     constexpr int HR = H > 0 ? H : 1;
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     __shared__ T sA[W * W];           // x_k (read by the mass stencil), two copies: one barrier per step
     __shared__ T sB[W * W];
     const SG g;
-    const int l = blockIdx.y;
+    const int l = l0 + blockIdx.y;                   // column of [y | u]: n_t n_xi state columns, then control
     const int vec = blockIdx.z;
     if (op.active && !op.active[vec]) return;        // uniform per block, before any barrier
     const int mem = op.mem_shared ? 0 : vec;
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     const T Dt = (time && (t == 0 || t == nt - 1)) ? T(0.5) : T(1);
     const T sc_ = var == 0 ? (j == 0 ? T(1) : T(md.hg)) : T(md.beta);
     const T f = T(1) / (sc_ * T(md.tau) * Dt);
-    T* zc = z + (int64_t)vec * vstride + (int64_t)l * nodes;
+    T* zc = z + (int64_t)vec * zstride + (int64_t)l * nodes;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int X = FX0 + g.X, Y = FY0 + g.Y0 + k;
@@ -636,15 +636,15 @@ void tail_m(const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColM
 }
 
 template <typename T, int H>
-void cheb_h(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, const ChebW& cw, hipStream_t st) {
-    const int ncols = 2 * s.nt * s.nxi;
+void cheb_h(const Shape& s, const OpDev& op, const T* r, int64_t rstride, T* z, int64_t zstride, int l0, int ncols,
+            int nvec, const ChebW& cw, hipStream_t st) {
     if (ncols > 65535 || nvec > 65535) throw Error(SG_ERR_INVALID, "Chebyshev: launch grid too large");
     // 32-node tiles at every grid size: 64-node tiles (512 threads) fetch fewer
     // halo nodes but measured slower at 128^2 and 512^2
     constexpr int TF = 32;
     const int tx = (s.n - 1 + TF - 1) / TF;
     hipLaunchKernelGGL((k_mass_cheb_fused<T, TF, H, 256>), dim3(tx * tx, ncols, nvec), dim3(256), 0, st, s.n, s.nxi,
-                       s.nt, (int)s.time, s.nodes, op, 3 * s.blk, r, z, cw, tx);
+                       s.nt, (int)s.time, s.nodes, op, rstride, r, z, cw, tx, zstride, l0);
 }
 
 constexpr int TCD = 16;   // coarse nodes per down tile side
@@ -731,6 +731,12 @@ void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, 
 // Returns false when the step count has no fused kernel (more than 9 steps).
 template <typename T>
 bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, int steps, hipStream_t st) {
+    return launch_mass_cheb_cols<T>(s, op, r, 3 * s.blk, z, 3 * s.blk, 0, 2 * s.nt * s.nxi, nvec, steps, st);
+}
+
+template <typename T>
+bool launch_mass_cheb_cols(const Shape& s, const OpDev& op, const T* r, int64_t rstride, T* z, int64_t zstride, int l0,
+                           int ncols, int nvec, int steps, hipStream_t st) {
     if (steps < 1 || steps > 9) return false;
     ChebW cw{};
     const double rho = 0.8;
@@ -740,15 +746,15 @@ bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, i
         cw.omega[k - 1] = omega;
     }
     switch (steps - 1) {
-        case 0: cheb_h<T, 0>(s, op, r, z, nvec, cw, st); break;
-        case 1: cheb_h<T, 1>(s, op, r, z, nvec, cw, st); break;
-        case 2: cheb_h<T, 2>(s, op, r, z, nvec, cw, st); break;
-        case 3: cheb_h<T, 3>(s, op, r, z, nvec, cw, st); break;
-        case 4: cheb_h<T, 4>(s, op, r, z, nvec, cw, st); break;
-        case 5: cheb_h<T, 5>(s, op, r, z, nvec, cw, st); break;
-        case 6: cheb_h<T, 6>(s, op, r, z, nvec, cw, st); break;
-        case 7: cheb_h<T, 7>(s, op, r, z, nvec, cw, st); break;
-        default: cheb_h<T, 8>(s, op, r, z, nvec, cw, st); break;
+        case 0: cheb_h<T, 0>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 1: cheb_h<T, 1>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 2: cheb_h<T, 2>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 3: cheb_h<T, 3>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 4: cheb_h<T, 4>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 5: cheb_h<T, 5>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 6: cheb_h<T, 6>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 7: cheb_h<T, 7>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        default: cheb_h<T, 8>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
     }
     SG_HIP(hipGetLastError());
     return true;
@@ -756,6 +762,10 @@ bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, i
 
 template bool launch_mass_cheb_fused<double>(const Shape&, const OpDev&, const double*, double*, int, int, hipStream_t);
 template bool launch_mass_cheb_fused<float>(const Shape&, const OpDev&, const float*, float*, int, int, hipStream_t);
+template bool launch_mass_cheb_cols<double>(const Shape&, const OpDev&, const double*, int64_t, double*, int64_t, int,
+                                            int, int, int, hipStream_t);
+template bool launch_mass_cheb_cols<float>(const Shape&, const OpDev&, const float*, int64_t, float*, int64_t, int, int,
+                                           int, int, hipStream_t);
 
 template void launch_mg_tail<double>(int, const LevelDev*, int, int, int, const double*, ColMap, double*, ColMap,
                                      const double*, int, int, const int*, int, hipStream_t);

@@ -54,6 +54,11 @@ size_t footprint_bytes(const sg_problem& p, const sg_options& o) {
     bytes += sz * blk * 3 + sz * 4 * nodes * 1.4 * nxi * 0.6;
     if (refine) bytes += 4.0 * N * (v32 ? 2 : 3);                      // FP32 operator output and staging
     if (o.precision == SG_PREC_FP32_PRECOND) bytes += 4.0 * N + 8.0 * N;   // FP32 staging, FP64 copy of Z_j
+    // scratch of the preconditioner options: hGSoc level right-hand sides and
+    // adjoint intermediates, Richardson iterates, sine-transform solves (FP64)
+    if (o.precond == SG_PRECOND_HGSOC) bytes += sz * blk * 4;
+    if (o.richardson_steps > 1) bytes += sz * blk * 4;
+    if (o.cheb_steps == 0 || o.mean_solver == SG_MEAN_EXACT) bytes += 8.0 * 2 * 2 * blk;
     if (p.field == SG_FIELD_LOGNORMAL) {
         // element coupling tables (all terms, and the truncated ones) and the KKT stiffness scratch
         bytes += 8.0 * (double)p.n * p.n * nxi * nxi * (o.truncation_r > 0 ? 2 : 1) + 8.0 * 2 * blk;
@@ -67,7 +72,9 @@ bool same_shape(const Request& a, const Request& b) {
            a.opt.restart == b.opt.restart && a.opt.max_iter == b.opt.max_iter && a.opt.rtol == b.opt.rtol &&
            a.opt.cheb_steps == b.opt.cheb_steps && a.opt.truncation_r == b.opt.truncation_r &&
            a.opt.gmg_pre == b.opt.gmg_pre && a.opt.gmg_post == b.opt.gmg_post && a.opt.inner_rtol == b.opt.inner_rtol &&
-           a.opt.arnoldi == b.opt.arnoldi && a.opt.basis_fp32 == b.opt.basis_fp32;
+           a.opt.arnoldi == b.opt.arnoldi && a.opt.basis_fp32 == b.opt.basis_fp32 &&
+           a.opt.mean_solver == b.opt.mean_solver && a.opt.richardson_steps == b.opt.richardson_steps &&
+           a.opt.precond == b.opt.precond;
 }
 
 }  // namespace

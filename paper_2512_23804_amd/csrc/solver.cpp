@@ -293,9 +293,71 @@ void zinv(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nvec, bool 
     }
 }
 
+// hGSoc (Algorithms 2-3, steady): one forward (degrees 0..P) and one backward
+// (P-1..0) sweep over the degree levels of the whole KKT vector, zero initial
+// guess.  At level d the state and adjoint rows take the KKT couplings to the
+// other levels with their current values (R^Y_d + sum_k K_k Lambda and R^L_d +
+// sum_k K_k Y over the kept modes; the control row has none), and the level
+// is solved with the block-diagonal preconditioner restricted to its chaos
+// columns: h^gamma_j M and beta M by Chebyshev, the adjoint by A-tilde_1^{-1}
+// h^gamma_j M A-tilde_1^{-1} (the Schur-type reading of P-tilde; the printed
+// third block A-tilde_1 stagnates).  As in Alg. 1 the backward sweep reuses
+// the forward right-hand side of each level and adds the upper levels.
+template <typename T>
+void hgsoc_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st) {
+    const Shape& s = h.s;
+    OpDev op = h.op<T>(shared);
+    op.off_sign = -1.0;                      // the couplings enter the level right-hand sides with +
+    const uint32_t mask = h.modes_mask();
+    const int64_t kkt = 3 * s.blk;
+    const size_t cnt = (size_t)nvec * s.blk;
+    T* BY = h.ws.get_t<T>(std::string("socY") + tname<T>(), cnt);
+    T* BL = h.ws.get_t<T>(std::string("socL") + tname<T>(), cnt);
+    T* T1 = h.ws.get_t<T>(std::string("socT1") + tname<T>(), cnt);
+    T* T2 = h.ws.get_t<T>(std::string("socT2") + tname<T>(), cnt);
+    const ColMap vfull = block_map(s, kkt);
+    auto level = [&](int d, bool fwd) {
+        const ColMap rm = level_map(s, d, kkt), bm = level_map(s, d, s.blk);
+        const int L = s.off[d + 1] - s.off[d];
+        const int ncols = L * nvec, cpm = shared ? ncols : L, cpv = L;
+        // right-hand sides of the state and adjoint rows (base: the residual, or
+        // backward the forward right-hand side of this level)
+        const T* bY = r;
+        const T* bL = r + 2 * s.blk;
+        ColMap bYm = rm, bLm = rm;
+        if (mask != 0 && (d > 0 || !fwd)) {
+            const bool from_r = fwd || d == 0;
+            launch_hgs_rhs<T>(s, op, d, mask, fwd ? 1 : 0, fwd ? 0 : 1, from_r ? r : BY, from_r ? rm : bm,
+                              z + 2 * s.blk, vfull, BY, bm, nvec, st);
+            launch_hgs_rhs<T>(s, op, d, mask, fwd ? 1 : 0, fwd ? 0 : 1, from_r ? r + 2 * s.blk : BL, from_r ? rm : bm,
+                              z, vfull, BL, bm, nvec, st);
+            bY = BY;
+            bL = BL;
+            bYm = bLm = bm;
+        }
+        // state and control columns of the level: Chebyshev with the block scalings
+        const bool yb = bY == BY;
+        if (!launch_mass_cheb_cols<T>(s, op, yb ? BY : r, yb ? s.blk : kkt, z, kkt, s.off[d], L, nvec,
+                                      h.opt.cheb_steps, st) ||
+            !launch_mass_cheb_cols<T>(s, op, r, kkt, z, kkt, s.nxi + s.off[d], L, nvec, h.opt.cheb_steps, st))
+            throw Error(SG_ERR_INVALID, "hGSoc needs cheb_steps in [1, 9]");
+        // adjoint columns: A-tilde_1^{-1} h^gamma_j M A-tilde_1^{-1}
+        mean_solve<T>(h, bL, bLm, T1, bm, ncols, cpm, cpv, nvec, st);
+        launch_mass_scaled<T>(s, op, T1, bm, T2, bm, ncols, nvec, st);
+        mean_solve<T>(h, T2, bm, z + 2 * s.blk, rm, ncols, cpm, cpv, nvec, st);
+    };
+    for (int d = 0; d <= s.P; ++d) level(d, true);
+    if (mask == 0) return;   // mean-based: the backward sweep repeats the forward solves exactly
+    for (int d = s.P - 1; d >= 0; --d) level(d, false);
+}
+
 // Block-diagonal preconditioner (eq. stoch-prec / eq. precon for time).
 template <typename T>
 void precond_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st) {
+    if (h.opt.precond == SG_PRECOND_HGSOC) {
+        hgsoc_apply<T>(h, r, z, nvec, shared, st);
+        return;
+    }
     const Shape& s = h.s;
     const OpDev op = h.op<T>(shared);
     const int64_t kkt = 3 * s.blk;
@@ -351,6 +413,9 @@ void precond_reserve(Handle& h, int nvec) {
     }
     if (h.opt.richardson_steps > 1)
         for (const char* nm : {"richX", "richY", "richR", "richD"})
+            h.ws.get_t<T>(std::string(nm) + tname<T>(), (size_t)nvec * s.blk);
+    if (h.opt.precond == SG_PRECOND_HGSOC)
+        for (const char* nm : {"socY", "socL", "socT1", "socT2"})
             h.ws.get_t<T>(std::string(nm) + tname<T>(), (size_t)nvec * s.blk);
     if (s.nlev_mg > 1) {
         int lmax = 0;

@@ -527,7 +527,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves
         const int c = slice * L + l;
         out = y + omap.off(c);
         bas = base + bmap.off(c);
-        scale = op.mem[mem].off_scale;
+        scale = op.off_sign * op.mem[mem].off_scale;
     }
     const bool xout = gl >= 1 && gl <= GOUT && X <= n;
     double k2p, k3p;

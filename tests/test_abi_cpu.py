@@ -142,3 +142,15 @@ def test_validate_lognormal_field():
     assert sgl.validate(_pd(**ln), sgl.default_options(truncation_r=210)) == sgl.SG_OK
     assert sgl.validate(_pd(**ln), sgl.default_options(truncation_r=211)) == sgl.SG_ERR_INVALID
     assert sgl.validate(_pd(), sgl.default_options(truncation_r=6)) == sgl.SG_ERR_INVALID
+
+
+def test_validate_hgsoc_option():
+    import paper_2512_23804_amd as sgl
+    o = sgl.default_options
+    assert sgl.validate(_pd(), o(precond=sgl.SG_PRECOND_HGSOC)) == sgl.SG_OK
+    assert sgl.validate(_pd(), o(precond=2)) == sgl.SG_ERR_INVALID
+    # steady problems with the fused Chebyshev mass solves only
+    assert sgl.validate(_pd(), o(precond=sgl.SG_PRECOND_HGSOC, cheb_steps=12)) == sgl.SG_ERR_INVALID
+    assert sgl.validate(_pd(), o(precond=sgl.SG_PRECOND_HGSOC, cheb_steps=0)) == sgl.SG_ERR_INVALID
+    tgt = np.stack([sg_inputs.gaussian_bumps(16, 0)] * 3)
+    assert sgl.validate(_pd(n_t=3, y_target=tgt), o(precond=sgl.SG_PRECOND_HGSOC)) == sgl.SG_ERR_INVALID

@@ -88,15 +88,20 @@ def test_hgsoc_flags_a_wrong_coupling_sign():
     assert np.max(np.abs(z - wrong)) > 1e-3 * np.max(np.abs(z))
 
 
-def test_hgsoc_schur_reading_equals_block_gauss_seidel():
-    """With the Schur-type adjoint block the sweep is the same block
-    Gauss-Seidel algebra with that block on the diagonal."""
-    sg = _case(8, 3, 3, 0.3, 1e-2)
+@pytest.mark.parametrize("gamma", [0.0, 0.5])
+def test_hgsoc_schur_reading_equals_block_gauss_seidel(gamma):
+    """With the Schur-type reading (the block-diagonal preconditioner
+    restricted to each chaos column: h^gamma_j M, beta M, A-tilde_1
+    (h^gamma_j M)^{-1} A-tilde_1) the sweep is the same block Gauss-Seidel
+    algebra with those blocks on the diagonal."""
+    sg = _case(8, 3, 3, 0.3, 1e-2, gamma)
     r = sg_inputs.random_block((3 * sg.n_xi * sg.n_int,), 9)
     z = precond.hgsoc(sg, r, precond.PtildeSolve(sg, "exact", adjoint="schur"), sg.prob.M + 1)
     Mb, bMb, A1 = _ptilde_blocks(sg)
     S = (A1 @ spla.spsolve(sg.Mi.tocsc(), A1.tocsc())).tocsr()
-    D, L, U = precond.hgsoc_matrix_form(sg, (Mb, bMb, S), sg.prob.M + 1)
+    hg = kkt.h_gamma(sg)
+    D, L, U = precond.hgsoc_matrix_form(sg, (Mb, bMb, S), sg.prob.M + 1,
+                                        col_weights=(hg, np.ones(sg.n_xi), 1.0 / hg))
     x1 = spla.spsolve((D + L).tocsc(), r)
     zz = spla.spsolve((D + U).tocsc(), D @ x1)
     assert np.max(np.abs(z - zz)) < 1e-10 * np.max(np.abs(zz))
