@@ -482,6 +482,8 @@ def main():
                          "workload's first problem, strips of --sweep-rows or autotuned) --probe-reps times after one "
                          "warm-up, and exit (the kernels' hardware counters are taken on this)")
     ap.add_argument("--probe-reps", type=int, default=5)
+    ap.add_argument("--probe-options", default="{}",
+                    help='sg_options overrides for --kernel-probe as JSON, e.g. \'{"mean_solver": 1}\'')
     ap.add_argument("--precond-variants", action="store_true",
                     help="iterations and solves/s of the preconditioner variants of Section 5 on --workload "
                          "(Chebyshev 5/10 or exact mass solves; multigrid or exact mean-block solves; "
@@ -513,7 +515,8 @@ def main():
 
     if args.kernel_probe:
         wl = WORKLOADS[args.workload]
-        h = sgl.Handle(make_problems(sgl, sg_inputs, wl)[:1], sgl.default_options(sweep_rows=args.sweep_rows))
+        h = sgl.Handle(make_problems(sgl, sg_inputs, wl)[:1],
+                       sgl.default_options(sweep_rows=args.sweep_rows, **json.loads(args.probe_options)))
         per = h.block_elems if args.kernel_probe == "apply" else h.kkt_elems
         x = torch.rand(per, dtype=torch.float64, device="cuda")
         y = torch.empty_like(x)
@@ -525,6 +528,7 @@ def main():
             fn(x, y)
         torch.cuda.synchronize()
         print(json.dumps({"kernel_probe": args.kernel_probe, "workload": args.workload, "reps": args.probe_reps,
+                          "options": json.loads(args.probe_options),
                           "ms_per_apply": 1000.0 * (time.perf_counter() - t0) / args.probe_reps,
                           "sweep_rows": [list(r) for r in h.sizes.sweep_rows]}))
         h.close()
