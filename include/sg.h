@@ -15,16 +15,19 @@
  *     eq. (constraint:stochastic-time-dependent); backward Euler all-at-once
  *     KKT system eq. (KKT:stoch-time-dependent);
  *   - preconditioner: block-diagonal Schur preconditioner eq. (stoch-prec) /
- *     eq. (precon for time) with Chebyshev mass solves and the hierarchical
- *     Gauss-Seidel sweep of Algorithm 1 inside the Schur block (Algorithm 5
- *     with N = 1); Krylov solver: flexible GMRES (Section 5).
+ *     eq. (precon for time) with Chebyshev (or exact) mass solves and the
+ *     hierarchical Gauss-Seidel sweep of Algorithm 1 inside the Schur block
+ *     (Algorithm 5 with N steps, N = 1 by default), or the coupled sweep of
+ *     Algorithms 2-3 (hGSoc); Krylov solver: flexible GMRES (Section 5).
  *
  * Problem data.  Domain [0,1]^2 split into n x n square elements (n a power of
- * two, 4 <= n <= 4096), homogeneous Dirichlet data (g = 0).  Random input
- * xi ~ U(-1,1)^M, orthonormal Legendre chaos of total degree P.  The random
- * coefficient is affine, a(x, xi) = kappa_0(x) + sum_k kappa_k(x) psi_{e_k}(xi),
- * with each kappa_k constant per element; by default
- * a = 1 + sigma sum_{k=1}^{M} k^-2 cos(k pi x1) cos(k pi x2) xi_k.
+ * two, 4 <= n <= 4096), homogeneous Dirichlet data (g = 0).  Two coefficient
+ * models (sg_problem.field): the affine field, random input xi ~ U(-1,1)^M
+ * with orthonormal Legendre chaos of total degree P and a(x, xi) = kappa_0(x)
+ * + sum_k kappa_k(x) psi_{e_k}(xi), each kappa_k constant per element (by
+ * default a = 1 + sigma sum_{k=1}^{M} k^-2 cos(k pi x1) cos(k pi x2) xi_k);
+ * or the log-normal field of Section 5, Gaussian xi with orthonormal Hermite
+ * chaos of total degree P for the solution and 2P for the coefficient.
  *
  * Vector layout ("canonical layout").  One field block (state y, control u or
  * adjoint lambda) is an array [t][j][node] of n_t * n_xi * (n+1)^2 values:

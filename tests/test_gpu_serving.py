@@ -148,3 +148,36 @@ def test_request_joins_running_batch(precision):
         assert rca == sgl.SG_OK and infa[0].iters == info.iters
         assert np.array_equal(x.cpu().numpy(), out)
         h.close()
+
+
+def test_server_lognormal_requests_join_and_equal_alone():
+    """Log-normal requests (Hermite chaos; each member's element couplings
+    are rebuilt when a request takes a finished member's slot): every result
+    equals its alone solve bit for bit."""
+    _need_gpu()
+    sgl = _lib()
+    _say("serving log-normal requests")
+    n, M, P = 16, 2, 2
+    params = [(0.1, 1e-1, 1.0), (0.3, 1e-5, 0.5), (0.2, 1e-3, 2.0)]   # fast, slow, joiner (sigma, beta, corr)
+    opts = sgl.default_options(rtol=1e-9, max_iter=600)
+    srv = sgl.Server(hbm_budget_bytes=0, max_slots=2)
+    tickets, items = [], []
+    for sigma, beta, corr in params:
+        pd = sgl.ProblemData(n, M, P, sigma, beta, sg_inputs.indicator_target(n), gamma=1.0,
+                             field=sgl.SG_FIELD_LOGNORMAL, corr_len=corr)
+        out = np.full(_kkt_len(n, M, P), np.nan)
+        tickets.append(srv.submit(pd, out, opts))
+        items.append((pd, out))
+    res = _wait(srv, tickets)
+    srv.close()
+    infos = [res[t][1] for t in tickets]
+    assert all(res[t][0] == sgl.SG_OK for t in tickets)
+    assert infos[2].joined_batch == 1, [i.joined_batch for i in infos]
+    dev = torch.device("cuda:0")
+    for (pd, out), info in zip(items, infos):
+        h = sgl.Handle(pd, opts)
+        x = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+        rca, infa = h.solve(x)
+        assert rca == sgl.SG_OK and infa[0].iters == info.iters
+        assert np.array_equal(x.cpu().numpy(), out)
+        h.close()
