@@ -150,8 +150,9 @@ typedef struct sg_problem {
  *                Gram-Schmidt applied twice: three passes) [SG_ARNOLDI_DCGS2]
  *   sweep_rows   node rows per strip of the SG/KKT/hGS sweep kernels: 2, 4
  *                or 8, or 0 to let sg_setup time the three on the handle's
- *                shape and keep the fastest (cached per process and shape;
- *                every choice gives bit-identical results) [0]
+ *                shape and keep the fastest (cached per device model and
+ *                shape, in memory and in the file SG_TUNE_CACHE names, see
+ *                sg_tune_save; every choice gives bit-identical results) [0]
  *   basis_fp32   SG_PREC_FP32_REFINE with DCGS2 only: 1 stores the inner
  *                cycles' Arnoldi basis and operator output in FP32 (every dot
  *                product, projection and Hessenberg entry is still formed in
@@ -369,6 +370,34 @@ int sg_server_stats(sg_server* s, int64_t* completed, double* p50_ms, double* p9
 /* Block until every submitted request finished, then stop the scheduler and
  * free all device memory (NULL is ignored). */
 void sg_server_destroy(sg_server* s);
+
+/* ---- strip-height autotuner cache -------------------------------------- */
+
+/* The choices of sg_options.sweep_rows = 0 are kept per process, keyed by
+ * device model (architecture name and compute-unit count), n, M, P, n_t,
+ * steady or time-dependent, one member or a batch, and element type.  When
+ * the environment variable SG_TUNE_CACHE names a file, the first tuning (or
+ * any call below) of the process merges that file if it exists, and every new
+ * choice rewrites it (temporary file, then rename).  The file is text: the
+ * line "sgkkt-tune 1", then one entry per line, "<arch> <CUs> <n> <M> <P>
+ * <n_t> <time 0/1> <batch 1/2> <fp32 0/1> <apply> <hgs> <kkt>" with strip
+ * heights in {2, 4, 8}.  These calls touch no device. */
+
+/* Write every cached choice to `path`.  SG_ERR_INVALID: NULL or empty path,
+ * or the file cannot be written. */
+int sg_tune_save(const char* path);
+
+/* Merge the choices in `path` into the cache (an entry replaces the cached
+ * one with the same key); a later sg_setup with sweep_rows = 0 and a matching
+ * key uses it without timing.  SG_ERR_INVALID: NULL or empty path, unreadable
+ * file, wrong first line or a malformed entry (then nothing is merged). */
+int sg_tune_load(const char* path);
+
+/* Number of cached choices (>= 0). */
+int sg_tune_count(void);
+
+/* Empty the cache (the SG_TUNE_CACHE file is not read again by this process). */
+int sg_tune_clear(void);
 
 /* Thread-local message of the last failure on this thread ("" if none). */
 const char* sg_last_error(void);

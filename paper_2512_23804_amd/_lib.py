@@ -83,6 +83,10 @@ SIGNATURES = {
     "sg_cancel": (C.c_int, [C.c_void_p, C.c_uint64]),
     "sg_server_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), _DP, _DP, _DP]),
     "sg_server_destroy": (None, [C.c_void_p]),
+    "sg_tune_save": (C.c_int, [C.c_char_p]),
+    "sg_tune_load": (C.c_int, [C.c_char_p]),
+    "sg_tune_count": (C.c_int, []),
+    "sg_tune_clear": (C.c_int, []),
     "sg_last_error": (C.c_char_p, []),
 }
 
@@ -121,6 +125,27 @@ def default_options(**kw) -> sg_options:
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def tune_save(path: str) -> None:
+    """Write the strip-height autotuner's cached choices to a text file."""
+    check(lib.sg_tune_save(os.fsencode(path)))
+
+
+def tune_load(path: str) -> None:
+    """Merge a file written by tune_save into the autotuner's cache."""
+    check(lib.sg_tune_load(os.fsencode(path)))
+
+
+def tune_count() -> int:
+    rc = lib.sg_tune_count()
+    if rc < 0:
+        check(rc)
+    return rc
+
+
+def tune_clear() -> None:
+    check(lib.sg_tune_clear())
 
 
 def _dptr(a):

@@ -211,6 +211,31 @@ void sg_destroy(sg_handle* h) {
     }
 }
 
+int sg_tune_save(const char* path) {
+    return guarded([&] {
+        sg::tune_save(path);
+        return SG_OK;
+    });
+}
+
+int sg_tune_load(const char* path) {
+    return guarded([&] {
+        sg::tune_load(path);
+        return SG_OK;
+    });
+}
+
+int sg_tune_count(void) {
+    return guarded([&] { return sg::tune_count(); });
+}
+
+int sg_tune_clear(void) {
+    return guarded([&] {
+        sg::tune_clear();
+        return SG_OK;
+    });
+}
+
 const char* sg_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

@@ -283,6 +283,10 @@ void set_last_error(const std::string& msg);
 void default_options(sg_options* o);
 void validate(const sg_problem* probs, int count, const sg_options* opt);   // throws Error
 void autotune(Handle& h);   // tune.cpp: strip heights of the sweep kernels (sg_options.sweep_rows)
+void tune_save(const char* path);   // tune.cpp: the strip-height cache as a text file
+void tune_load(const char* path);
+int tune_count();
+void tune_clear();
 std::unique_ptr<Handle> build_handle(const sg_problem* probs, int count, const sg_options* opt, hipStream_t st,
                                      DevicePool* pool = nullptr);
 // Replace member b's problem (same n, M, P, n_t and options as the handle):

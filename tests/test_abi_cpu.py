@@ -154,3 +154,72 @@ def test_validate_hgsoc_option():
     assert sgl.validate(_pd(), o(precond=sgl.SG_PRECOND_HGSOC, cheb_steps=0)) == sgl.SG_ERR_INVALID
     tgt = np.stack([sg_inputs.gaussian_bumps(16, 0)] * 3)
     assert sgl.validate(_pd(n_t=3, y_target=tgt), o(precond=sgl.SG_PRECOND_HGSOC)) == sgl.SG_ERR_INVALID
+
+
+TUNE_LINES = ["gfx950:sramecc+:xnack- 256 128 6 4 1 0 1 0 4 4 8",
+              "gfx950:sramecc+:xnack- 256 512 8 3 1 0 2 1 2 4 4"]
+
+
+def _tune_file(path, lines, magic="sgkkt-tune 1"):
+    with open(path, "w") as f:
+        f.write(magic + "\n" + "\n".join(lines) + "\n")
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """The strip-height cache file: a load merges its entries, a save writes
+    them back in the same format, a clear empties the cache (no device)."""
+    import paper_2512_23804_amd as sgl
+    sgl.tune_clear()
+    assert sgl.tune_count() == 0
+    src = tmp_path / "in.txt"
+    _tune_file(src, TUNE_LINES)
+    sgl.tune_load(str(src))
+    assert sgl.tune_count() == 2
+    out = tmp_path / "out.txt"
+    sgl.tune_save(str(out))
+    lines = open(out).read().splitlines()
+    assert lines[0] == "sgkkt-tune 1" and sorted(lines[1:]) == sorted(TUNE_LINES)
+    # an entry with the same key replaces the cached one
+    _tune_file(src, [TUNE_LINES[0].rsplit(" ", 3)[0] + " 2 2 2"])
+    sgl.tune_load(str(src))
+    assert sgl.tune_count() == 2
+    sgl.tune_save(str(out))
+    assert TUNE_LINES[0].rsplit(" ", 3)[0] + " 2 2 2" in open(out).read().splitlines()
+    sgl.tune_clear()
+    assert sgl.tune_count() == 0
+
+
+@pytest.mark.parametrize("lines,magic", [
+    (["gfx950 256 128 6 4 1 0 1 0 4 4 3"], "sgkkt-tune 1"),        # strip height not in {2, 4, 8}
+    (["gfx950 256 128 6 4 1 0 1 0 4 4"], "sgkkt-tune 1"),          # missing field
+    (["gfx950 256 128 6 4 1 0 1 0 4 4 8 1"], "sgkkt-tune 1"),      # extra field
+    (["gfx950 256 128 6 4 1 0 3 0 4 4 8"], "sgkkt-tune 1"),        # batch class 3
+    (TUNE_LINES, "sgkkt-tune 2"),                                   # wrong version line
+])
+def test_tune_cache_rejects_malformed_files(tmp_path, lines, magic):
+    import paper_2512_23804_amd as sgl
+    sgl.tune_clear()
+    _tune_file(tmp_path / "bad.txt", [TUNE_LINES[1]] + lines, magic)
+    with pytest.raises(sgl.SGError) as e:
+        sgl.tune_load(str(tmp_path / "bad.txt"))
+    assert e.value.code == sgl.SG_ERR_INVALID
+    assert sgl.tune_count() == 0          # nothing merged from a file that does not parse
+    with pytest.raises(sgl.SGError):
+        sgl.tune_load(str(tmp_path / "missing.txt"))
+    with pytest.raises(sgl.SGError):
+        sgl.tune_save(str(tmp_path / "no_such_dir" / "x.txt"))
+
+
+def test_tune_cache_environment_file(tmp_path):
+    """SG_TUNE_CACHE: a fresh process merges the file it names at its first
+    use of the cache (here a count, which touches no device)."""
+    import subprocess
+    import sys
+    src = tmp_path / "cache.txt"
+    _tune_file(src, TUNE_LINES)
+    env = dict(os.environ, SG_TUNE_CACHE=str(src))
+    code = ("import paper_2512_23804_amd as s; print(s.tune_count())")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "2"
