@@ -646,6 +646,248 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kkt_waves(R
     S::emit_nodes(v, st, gl, X, n, RU);
 }
 
+// ---------------------------------------------------------------------------
+// SG apply on FP64 storage with two nodes per lane.
+//
+// Y_j = c0 X_j (stiffness of the mean) + sum_k sum_{s = -,+} g K_k X_{j +- e_k}
+// per slice (vector, time step).  A lane owns a pair of neighbouring node
+// columns (one 16-byte load per node row), a 32-lane half owns 62 output node
+// columns and PR node rows, the two halves of a wavefront sit one above the
+// other, and the four wavefronts of a block take output columns chunk*16 +
+// wave + 4q, q < 4, over the same element tile, whose coefficient modes are
+// staged once in LDS.  Each wavefront streams one input column per item (the
+// mean term, then every present neighbour of each mode in mask) with the next
+// column's loads in flight while the current one is accumulated at the
+// element corners; the element results become node values once per output
+// column (the reference stiffness k_a = (5 v_a - v_opp - s)/6, then the sum of
+// the four elements at each node, the left one through a lane shift).  Input
+// nodes on the boundary ring are masked to zero as they are read, output ring
+// nodes are written as zero.
+// ---------------------------------------------------------------------------
+constexpr int PR = 4;            // node rows per 32-lane half
+constexpr int PNC = 4;           // output columns per wavefront
+constexpr int PGX = 62;          // output node columns per tile (two per lane, 31 lanes)
+constexpr int PER = 2 * PR + 1;  // element rows of a tile
+constexpr int PEC = 64;          // element columns staged per tile
+
+typedef double pd2 __attribute__((ext_vector_type(2)));
+typedef pd2 pd2u __attribute__((aligned(8)));   // node pairs start on any 8-byte boundary
+
+// lane l <- lane l+1, and lane l <- lane l-1 (64-bit values, row shifts by DPP)
+__device__ __forceinline__ double dpp_from_right(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double dpp_from_left(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+struct PairItem {
+    int col, k, j;   // input column, mode (-1: mean), output column
+    double g;
+    bool last, valid;
+};
+
+__global__ __launch_bounds__(256) void k_sgx_pair(int n, int M, int nxi, int nt, int64_t nodes, OpDev op,
+                                                  uint32_t mask, const double* __restrict__ x,
+                                                  double* __restrict__ y, int tiles_x, int tiles_y, int nchunks,
+                                                  int nb) {
+    __shared__ double sc[KMAX * PER * PEC];
+    const int lb = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (lb >= nb) return;
+    const int chunk = lb % nchunks;
+    const int rest = lb / nchunks;
+    const int tile = rest % (tiles_x * tiles_y);
+    const int slice = rest / (tiles_x * tiles_y);
+    if (op.active && !op.active[slice / nt]) return;   // uniform per block, before the barrier below
+    const int tx = tile % tiles_x, ty = tile / tiles_x;
+    const int mem = op.mem_shared ? 0 : slice / nt;
+    const double* coef = op.coef64 + (int64_t)mem * op.coef_mstride;
+    const double c0 = op.mem[mem].c0;
+    const int ex0 = PGX * tx;            // first element column of the tile
+    const int ey0 = ty * 2 * PR - 1;     // first element row
+    {
+        // modes 1..M of the tile, clamped to the grid (elements off the grid
+        // meet only masked ring nodes, so their coefficients never count)
+        const int total = M * PER * PEC;
+        for (int q = threadIdx.x; q < total; q += 256) {
+            const int ec = q % PEC, r = (q / PEC) % PER, k = q / (PEC * PER);
+            const int ex = min(ex0 + ec, n - 1);
+            const int ey = min(max(ey0 + r, 0), n - 1);
+            sc[q] = coef[(int64_t)(k + 1) * n * n + (int64_t)ey * n + ex];
+        }
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int jbase = chunk * 4 * PNC + wave;
+    if (jbase >= nxi) return;            // uniform per wavefront; no block barriers below
+    const int lane = threadIdx.x & 63;
+    const int gl = lane & 31;
+    const int grp = lane >> 5;
+    const int x0 = ex0 + 2 * gl;          // first node column of the lane's pair
+    const int y0 = (2 * ty + grp) * PR;   // first output node row of the half
+    const double* F = x + (int64_t)slice * nxi * nodes;
+    double* Yo = y + (int64_t)slice * nxi * nodes;
+    // per strip row: the pair's offset (rows clamped to the grid, pairs past the
+    // row end clamped into the column) and the masks of interior input nodes
+    int rowoff[PR + 2];
+    bool ok0[PR + 2], ok1[PR + 2];
+#pragma unroll
+    for (int r = 0; r < PR + 2; ++r) {
+        const int Yr = y0 - 1 + r;
+        rowoff[r] = (int)min((int64_t)min(max(Yr, 0), n) * (n + 1) + x0, nodes - 2);
+        const bool yin = Yr >= 1 && Yr <= n - 1;
+        ok0[r] = yin && x0 >= 1 && x0 <= n - 1;
+        ok1[r] = yin && x0 + 1 <= n - 1;
+    }
+    const double* scl = sc + (grp * PR) * PEC + 2 * gl;
+    // the wavefront's items, generated in scalar registers
+    int q = 0, jc = jbase;
+    uint32_t todo = 0;
+    auto present = [&](int j) -> uint32_t {
+        uint32_t m = 0;
+        for (int k = 0; k < M; ++k) {
+            if (!((mask >> k) & 1u)) continue;
+            const int b = (j * M + k) * 2;
+            if (op.nbr_idx[b] >= 0) m |= 1u << (2 * k);
+            if (op.nbr_idx[b + 1] >= 0) m |= 1u << (2 * k + 1);
+        }
+        return m;
+    };
+    auto next_item = [&]() -> PairItem {
+        PairItem it;
+        if (todo) {
+            const int sl = __builtin_ctz(todo);
+            todo &= todo - 1u;
+            const int b = (jc * M + (sl >> 1)) * 2 + (sl & 1);
+            it.col = op.nbr_idx[b];
+            it.g = op.nbr_val[b];
+            it.k = sl >> 1;
+            it.j = jc;
+            it.last = todo == 0;
+            it.valid = true;
+            return it;
+        }
+        ++q;
+        jc = jbase + 4 * q;
+        if (q >= PNC || jc >= nxi) {
+            it.col = 0; it.g = 0.0; it.k = -1; it.j = -1; it.last = false; it.valid = false;
+            return it;
+        }
+        todo = present(jc);
+        it.col = jc; it.g = c0; it.k = -1; it.j = jc; it.last = todo == 0; it.valid = true;
+        return it;
+    };
+    // element-corner sums [row][element of the pair][corner]
+    double acc[PR + 1][2][4];
+#pragma unroll
+    for (int r = 0; r < PR + 1; ++r)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) acc[r][e][0] = acc[r][e][1] = acc[r][e][2] = acc[r][e][3] = 0.0;
+    auto load = [&](pd2 (&V)[PR + 2], int col) {
+        const double* p = F + (int64_t)col * nodes;
+#pragma unroll
+        for (int r = 0; r < PR + 2; ++r) V[r] = *(const pd2u*)(p + rowoff[r]);
+    };
+    auto accumulate = [&](const pd2 (&V)[PR + 2], const PairItem& it) {
+        const double g = it.g;
+        double w0[PR + 2], w1[PR + 2], w2[PR + 2];
+#pragma unroll
+        for (int r = 0; r < PR + 2; ++r) {
+            w0[r] = g * (ok0[r] ? V[r].x : 0.0);
+            w1[r] = g * (ok1[r] ? V[r].y : 0.0);
+            w2[r] = dpp_from_right(w0[r]);   // the right neighbour pair's first node
+        }
+        if (it.k < 0) {
+#pragma unroll
+            for (int r = 0; r < PR + 1; ++r) {
+                acc[r][0][0] += w0[r]; acc[r][0][1] += w1[r]; acc[r][0][2] += w1[r + 1]; acc[r][0][3] += w0[r + 1];
+                acc[r][1][0] += w1[r]; acc[r][1][1] += w2[r]; acc[r][1][2] += w2[r + 1]; acc[r][1][3] += w1[r + 1];
+            }
+        } else {
+            const double* ck = scl + it.k * PER * PEC;
+#pragma unroll
+            for (int r = 0; r < PR + 1; ++r) {
+                const pd2 c = *(const pd2*)(ck + r * PEC);
+                acc[r][0][0] = fmadd(c.x, w0[r], acc[r][0][0]);
+                acc[r][0][1] = fmadd(c.x, w1[r], acc[r][0][1]);
+                acc[r][0][2] = fmadd(c.x, w1[r + 1], acc[r][0][2]);
+                acc[r][0][3] = fmadd(c.x, w0[r + 1], acc[r][0][3]);
+                acc[r][1][0] = fmadd(c.y, w1[r], acc[r][1][0]);
+                acc[r][1][1] = fmadd(c.y, w2[r], acc[r][1][1]);
+                acc[r][1][2] = fmadd(c.y, w2[r + 1], acc[r][1][2]);
+                acc[r][1][3] = fmadd(c.y, w1[r + 1], acc[r][1][3]);
+            }
+        }
+    };
+    auto emit = [&](int j) {
+        double* out = Yo + (int64_t)j * nodes;
+        double kp[2][4];
+#pragma unroll
+        for (int r = 0; r < PR + 1; ++r) {
+            double ka[4], kb[4];
+            kref(acc[r][0][0], acc[r][0][1], acc[r][0][2], acc[r][0][3], ka[0], ka[1], ka[2], ka[3]);
+            kref(acc[r][1][0], acc[r][1][1], acc[r][1][2], acc[r][1][3], kb[0], kb[1], kb[2], kb[3]);
+            if (r > 0) {
+                // node (x0, Y): elements (x0-1 | x0) x (Y-1 | Y); node (x0+1, Y): the pair's two elements
+                const double left = dpp_from_left(kb[1] + kp[1][2]);
+                const double n0 = (ka[0] + kp[0][3]) + left;
+                const double n1 = (ka[1] + kp[0][2]) + (kb[0] + kp[1][3]);
+                const int Yr = y0 - 1 + r;
+                const bool yin = Yr >= 1 && Yr <= n - 1;
+                if (Yr <= n) {
+                    const int64_t qo = (int64_t)Yr * (n + 1) + x0;
+                    const bool x0out = (gl >= 1 || x0 == 0) && x0 <= n;
+                    const bool x1out = gl <= 30 && x0 + 1 <= n;
+                    if (x0out) out[qo] = (yin && x0 >= 1 && x0 <= n - 1) ? n0 : 0.0;
+                    if (x1out) out[qo + 1] = (yin && x0 + 1 <= n - 1) ? n1 : 0.0;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                kp[0][c] = ka[c];
+                kp[1][c] = kb[c];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < PR + 1; ++r)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) acc[r][e][0] = acc[r][e][1] = acc[r][e][2] = acc[r][e][3] = 0.0;
+    };
+    // two input buffers: the loads of the next item are issued (unconditionally:
+    // a branch around them would make the join wait for every load) before the
+    // current item is accumulated
+    pd2 A[PR + 2], B[PR + 2];
+    todo = present(jc);
+    PairItem cur;
+    cur.col = jc; cur.g = c0; cur.k = -1; cur.j = jc; cur.last = todo == 0; cur.valid = true;
+    load(A, cur.col);
+#pragma unroll 1
+    while (true) {
+        PairItem nx = next_item();
+        load(B, nx.valid ? nx.col : cur.col);
+        __builtin_amdgcn_sched_barrier(0);
+        accumulate(A, cur);
+        if (cur.last) emit(cur.j);
+        __builtin_amdgcn_sched_barrier(0);
+        if (!nx.valid) break;
+        cur = nx;
+        nx = next_item();
+        load(A, nx.valid ? nx.col : cur.col);
+        __builtin_amdgcn_sched_barrier(0);
+        accumulate(B, cur);
+        if (cur.last) emit(cur.j);
+        __builtin_amdgcn_sched_barrier(0);
+        if (!nx.valid) break;
+        cur = nx;
+    }
+}
+
 SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
     SweepGeom g;
     g.tiles_x = (n + 1 + GOUT - 1) / GOUT;
@@ -672,6 +914,20 @@ SweepGeom make_geom(int n, int ncols, int64_t slices, int rows) {
 template <typename T>
 bool launch_sgx_apply(const Shape& s, const OpDev& op, const T* x, T* y, int nvec, uint32_t mask, hipStream_t st) {
     if (s.M > KMAX || s.field != SG_FIELD_AFFINE) return false;
+    if constexpr (sizeof(T) == 8) {
+        // FP64 storage: the paired-node kernel (strip height fixed)
+        int tiles_x = 0;
+        while (PGX * tiles_x + 1 <= s.n - 1) ++tiles_x;        // tile tx outputs node columns 62 tx + 1 .. 62 tx + 62
+        const int tiles_y = (s.n + 1 + 2 * PR - 1) / (2 * PR);
+        const int nchunks = (s.nxi + 4 * PNC - 1) / (4 * PNC);
+        const int64_t nb = (int64_t)nvec * s.nt * tiles_x * tiles_y * nchunks;
+        if (nb > (int64_t)1 << 30) throw Error(SG_ERR_INVALID, "SG apply launch grid too large");
+        const int grid = (int)((nb + 7) / 8 * 8);
+        hipLaunchKernelGGL(k_sgx_pair, dim3(grid), dim3(256), 0, st, s.n, s.M, s.nxi, s.nt, s.nodes, op, mask,
+                           (const double*)x, (double*)y, tiles_x, tiles_y, nchunks, (int)nb);
+        SG_HIP(hipGetLastError());
+        return true;
+    }
     ColMap z{};
     const int rows = s.sweep_rows[sizeof(T) == 4][SWEEP_APPLY];
     const SweepGeom g = make_geom(s.n, s.nxi, (int64_t)nvec * s.nt, rows);

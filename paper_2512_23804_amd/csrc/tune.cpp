@@ -149,6 +149,7 @@ std::array<int, 3> tune_type(Handle& h, hipStream_t st) {
         ColMap lm{s.blk, s.tstride, s.nodes, s.off[d + 1] - s.off[d], s.nt, s.off[d]};
         ColMap bm{s.blk, s.tstride, s.nodes, s.nxi, s.nt, 0};
         for (int kind = 0; kind < 3; ++kind) {
+            if (sizeof(T) == 8 && kind == SWEEP_APPLY) continue;   // FP64 SG apply: paired-node kernel, no strip choice
             float tbest = 1e30f;
             for (int rows : kSweepRowChoices) {
                 s.sweep_rows[sizeof(T) == 4][kind] = rows;
