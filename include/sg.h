@@ -148,7 +148,9 @@ typedef struct sg_problem {
  *                vector delayed to the next iteration: two passes over the
  *                basis per iteration) or SG_ARNOLDI_CGS2 (classical
  *                Gram-Schmidt applied twice: three passes) [SG_ARNOLDI_DCGS2]
- *   sweep_rows   node rows per strip of the SG/KKT/hGS sweep kernels: 2, 4
+ *   sweep_rows   node rows per strip of the SG/KKT/hGS sweep kernels (the
+ *                SG apply on FP64 storage uses a paired-node kernel with a
+ *                fixed shape and ignores it): 2, 4
  *                or 8, or 0 to let sg_setup time the three on the handle's
  *                shape and keep the fastest (cached per device model and
  *                shape, in memory and in the file SG_TUNE_CACHE names, see
@@ -241,7 +243,8 @@ typedef struct sg_sizes {
     int64_t block_elems;        /* n_t * n_xi * nodes (one field) */
     int64_t kkt_elems;          /* 3 * block_elems (one KKT vector) */
     int32_t level_offsets[17];  /* degree d columns: [off[d], off[d+1]), d = 0..P */
-    int32_t sweep_rows[2][3];   /* strip rows in use: [FP64, FP32][SG apply, hGS rhs, KKT apply] */
+    int32_t sweep_rows[2][3];   /* strip rows in use: [FP64, FP32][SG apply, hGS rhs, KKT apply]
+                                   ([FP64][SG apply] is unused: paired-node kernel) */
 } sg_sizes;
 
 typedef struct sg_handle sg_handle;
