@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -342,6 +343,42 @@ def precond_variants(torch, sgl, sg_inputs, workload, steps, warmup):
     return {"precond_variants": workload, "steps": steps, "rows": rows}
 
 
+def paper_tables(torch, sgl, sg_inputs, grids, mean="direct"):
+    """The grid of the paper's tables of sigma variations (Section 5): log-normal
+    field with Hermite chaos, beta = 1e-4, gamma = 1, indicator target;
+    n_xi = 20 (m = 3, p = 3), 70 (4, 4), 84 (6, 3); truncations n_tau = 1,
+    m + 1, n_A; Chebyshev-5 or direct (sine-transform) mass solves with hGS-1,
+    whose mean-block solves are direct as in the paper (exact sine-transform
+    solves; `mean` = "multigrid" switches them to one V-cycle); sigma = 0.01,
+    0.1, 0.4 as the three members of one batch.  One untimed solve, then one
+    timed; the time per member is the batch's solve time over three.
+    FGMRES(30) to relative residual 1e-8."""
+    rows = []
+    stream = torch.cuda.Stream()
+    sigmas = (0.01, 0.1, 0.4)
+    for n in grids:
+        tgt = sg_inputs.indicator_target(n)
+        for M, P in ((3, 3), (4, 4), (6, 3)):
+            probs = [sgl.ProblemData(n, M, P, sg, 1e-4, tgt, gamma=1.0, field=sgl.SG_FIELD_LOGNORMAL)
+                     for sg in sigmas]
+            for mass, mo in (("cheb5", {}), ("direct", dict(cheb_steps=0))):
+                for name, r in (("1", 1), ("m+1", M + 1), ("n_A", 0)):
+                    print(f"[bench] paper table n={n} m={M} p={P} {mass} n_tau={name}", file=sys.stderr,
+                          flush=True)
+                    opts = sgl.default_options(rtol=1e-8, truncation_r=r,
+                                               mean_solver=1 if mean == "direct" else 0, **mo)
+                    dt, infos = timed_solves(torch, sgl, probs, opts, 1, 1, stream)
+                    last = infos[-1]
+                    rows.append({"n": n, "nodes": (n + 1) ** 2, "m": M, "p": P, "n_xi": math.comb(M + P, P),
+                                 "mass": mass, "mean_blocks": mean, "n_tau": name, "sigma": list(sigmas),
+                                 "iterations": [i.iters for i in last],
+                                 "ms_per_solve": 1000.0 * dt / len(probs),
+                                 "max_rel_res": max(i.rel_res_true for i in last),
+                                 "converged": all(i.converged == 1 for i in last)})
+                    print(json.dumps(rows[-1]), flush=True)
+    return {"paper_tables": rows}
+
+
 def cpu_baseline(wl, gpu_iters):
     """The oracle (plain FP64 numpy/scipy, BLAS threaded over every core this
     process may use) timed on the first member at the workload size.
@@ -471,6 +508,13 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving comparison (all queued at time zero; 0: skip)")
     ap.add_argument("--serve-grids", default="32,64,128,256", help="grid sizes n the request mix draws from")
+    ap.add_argument("--paper-tables", action="store_true",
+                    help="iterations and time per solve on the grid of the paper's tables of sigma variations "
+                         "(log-normal field, n_xi = 20 / 70 / 84, n_tau = 1 / m+1 / n_A, Chebyshev-5 or direct "
+                         "mass solves, sigma = 0.01 / 0.1 / 0.4), one JSON line per setting")
+    ap.add_argument("--paper-grids", default="16,32,64,128", help="element counts per side for --paper-tables")
+    ap.add_argument("--paper-mean", default="direct", choices=["direct", "multigrid"],
+                    help="mean-block solves for --paper-tables")
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only run the mixed serving protocol (capacity of FP64 serving, FP32-refinement "
                          "serving and plain FP64 single solves, then Poisson arrivals at 0.5x and 1.5x the "
@@ -536,6 +580,9 @@ def main():
 
     if args.precond_variants:
         print(json.dumps(precond_variants(torch, sgl, sg_inputs, args.workload, args.steps, args.warmup)), flush=True)
+        return
+    if args.paper_tables:
+        paper_tables(torch, sgl, sg_inputs, tuple(int(g) for g in args.paper_grids.split(",")), args.paper_mean)
         return
 
     grids = tuple(int(g) for g in args.serve_grids.split(","))
