@@ -646,6 +646,12 @@ def main():
                    "arnoldi": args.arnoldi, "sweep_rows_fp64": tuned[0]},
         "iterations": iters[: len(probs)],
         "max_rel_res": rel,
+        # the library's model of every member's algorithmic HBM bytes (sg_solve_info.bytes_moved),
+        # over the timed steps' wall time: the whole solve's average bandwidth
+        "solve_model": {"bytes_per_step": sum(i.bytes_moved for i in infos[-1]),
+                        "GBps": sum(i.bytes_moved for step in infos for i in step) / dt / 1e9,
+                        "frac_of_hbm_peak": sum(i.bytes_moved for step in infos for i in step) / dt / 1e9
+                        / HBM_PEAK_GBPS},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kd["achieved_GBps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": kd["achieved_GBps"] / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(dom, args.workload),

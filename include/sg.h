@@ -228,7 +228,13 @@ typedef struct sg_solve_info {
     double t_setup_ms;          /* handle setup time (host + device) */
     double t_solve_ms;          /* wall time of the solve */
     double latency_ms;          /* serving: submit -> completion */
-    double bytes_moved;         /* algorithmic HBM bytes of the solve (model) */
+    double bytes_moved;         /* model of this member's algorithmic HBM bytes: every
+                                   launch counted as the streaming passes its kernels
+                                   make (each input and output node once) on their
+                                   storage types, per FGMRES iteration the KKT apply,
+                                   the preconditioner and the Arnoldi passes, per
+                                   cycle the true residual, the start vector and the
+                                   update of x */
     double prof_ms;             /* profiled kernel: summed launch durations (HIP events) */
     double prof_bytes;          /* profiled kernel: summed algorithmic bytes of those launches */
     int32_t prof_launches;      /* profiled kernel: number of launches */

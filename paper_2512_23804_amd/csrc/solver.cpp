@@ -436,6 +436,74 @@ template void precond_apply<double>(Handle&, const double*, double*, int, bool, 
 template void precond_apply<float>(Handle&, const float*, float*, int, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Model of the algorithmic HBM bytes of a solve (sg_solve_info.bytes_moved):
+// every launch counted as the streaming passes its kernels must make, each
+// input and output node once, per member.
+// ---------------------------------------------------------------------------
+namespace {
+
+// one mean-block solve of one column: a multigrid V-cycle reads b and writes
+// the coarse right-hand side going down (1.25 node passes), reads b and the
+// coarse correction and writes x going up (2.25), over levels shrinking by
+// four (x 4/3); the sine-transform solve makes four FP64 passes, each reading
+// and writing the column
+double mean_solve_bytes(const Handle& h, double sz) {
+    const double nodes = (double)h.s.nodes;
+    if (h.opt.mean_solver == SG_MEAN_EXACT) return 8.0 * 8.0 * nodes;
+    return sz * nodes * 3.5 * 4.0 / 3.0;
+}
+
+// one hGS sweep pair (Alg. 1) on one member's field block: the level
+// right-hand sides and one mean-block solve per level column, forward and
+// (unless mean-based) backward
+double hgs_bytes(const Handle& h, double sz) {
+    const Shape& s = h.s;
+    const double col = sz * (double)s.nodes * s.nt;
+    const bool back = h.modes_mask() != 0;
+    double b = 0.0;
+    for (int d = 0; d <= s.P; ++d) {
+        const int L = s.off[d + 1] - s.off[d];
+        const int Ln = d > 0 ? s.off[d] - s.off[d - 1] : 0;
+        if (d > 0) b += (2.0 * L + (back ? Ln : 0)) * col;
+        b += L * s.nt * mean_solve_bytes(h, sz);
+    }
+    if (!back) return b;
+    for (int d = s.P - 1; d >= 0; --d) {
+        const int L = s.off[d + 1] - s.off[d];
+        const int Lu = s.off[d + 2] - s.off[d + 1];
+        b += (2.0 * L + Lu) * col + L * s.nt * mean_solve_bytes(h, sz);
+    }
+    return b;
+}
+
+double model_operator_bytes(const Handle& h, double sz) {
+    const Shape& s = h.s;
+    double b = sz * (6.0 * s.blk + (s.M + 1.0) * s.n * s.n);
+    if (s.field == SG_FIELD_LOGNORMAL) b += 2.0 * 8.0 * s.n * s.n * (double)s.nxi * s.nxi;   // element tables, two products
+    return b;
+}
+
+double model_precond_bytes(const Handle& h, double sz) {
+    const Shape& s = h.s;
+    const double blk = (double)s.blk;
+    // state and control blocks: read r, write z (Chebyshev, fused); the
+    // sine-transform solves: four FP64 passes reading and writing each column
+    double b = h.opt.cheb_steps == 0 ? 2.0 * 8.0 * 8.0 * blk : 4.0 * sz * blk;
+    if (h.opt.precond == SG_PRECOND_HGSOC) {
+        // coupled sweep: both right-hand sides, the state/control Chebyshev and two
+        // mean-block solves with the scaled mass between them, per level column
+        return b + 2.0 * hgs_bytes(h, sz) + 2.0 * sz * blk;
+    }
+    // Schur block: two Z^{-1} (each N hGS, and between them an SG apply, the
+    // residual and the update), the scaled mass in the middle
+    const int N = std::max(1, h.opt.richardson_steps);
+    const double zinv = N * hgs_bytes(h, sz) + (N - 1) * (sz * 2.0 * blk + sz * 3.0 * blk + sz * 3.0 * blk);
+    return b + 2.0 * zinv + 2.0 * sz * blk;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Flexible GMRES
 // ---------------------------------------------------------------------------
 namespace {
@@ -608,7 +676,7 @@ struct Krylov {
 // and the residual is formed again before the cycle starts.
 void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& tol_abs, std::vector<int>& todo,
             bool fp32, int max_iter, int max_cycles, std::vector<double>& res_out, std::vector<int>& member_iters,
-            int verbose, const std::function<bool()>& boundary = nullptr) {
+            std::vector<double>& member_bytes, int verbose, const std::function<bool()>& boundary = nullptr) {
     Handle& h = K.h;
     const int B = K.B, m = K.m;
     const int64_t N = K.N;
@@ -629,8 +697,16 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
     int* ctl_up = reinterpret_cast<int*>(h.h_pinned + 4096);
     int* ctl_dn = reinterpret_cast<int*>(h.h_pinned + 8192);
     const bool profiling = h.prof.kind != SG_PROF_NONE;
+    // bytes model: the operator and preconditioner on their storage types, the
+    // Arnoldi passes on the basis storage
+    const double s_op = K.op32 ? 4.0 : 8.0, s_pc = K.z32 ? 4.0 : 8.0, s_v = K.vbytes();
+    const double it_bytes = model_operator_bytes(h, s_op) + model_precond_bytes(h, s_pc);
+    const double res_bytes = model_operator_bytes(h, fp32 && K.op32 ? 4.0 : 8.0) + 3.0 * 8.0 * N;
+    std::vector<int> it_start(B, 0);
     for (int cycle = 0; max_cycles <= 0 || cycle < max_cycles;) {
         K.residual(b, x, r, fp32, nr2);       // synchronises the stream
+        for (int q = 0; q < B; ++q)
+            if (todo[q]) member_bytes[q] += res_bytes;
         bool any = false;
         for (int q = 0; q < B; ++q) {
             res_out[q] = std::sqrt(nr2[q]);
@@ -644,6 +720,7 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         if (boundary && boundary()) continue;
         if (!any) break;
         ++cycle;
+        for (int q = 0; q < B; ++q) it_start[q] = member_iters[q];
         // cycle start: g = (beta, 0, ...), V_0 = r / beta; the control block
         // (flags, iteration counts, limits, cycle lengths) and the tolerances
         for (int q = 0; q < B; ++q) {
@@ -785,7 +862,15 @@ void fgmres(Krylov& K, const double* b, double* x, const std::vector<double>& to
         SG_HIP(hipMemcpyAsync(ctl_dn, K.ctl, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, st));
         SG_HIP(hipStreamSynchronize(st));     // the staging area is reused next cycle
         for (int q = 0; q < B; ++q)
-            if (todo[q]) member_iters[q] = ctl_dn[B + q];
+            if (todo[q]) {
+                member_iters[q] = ctl_dn[B + q];
+                // k iterations: k (operator + preconditioner), the Arnoldi passes of
+                // steps 0..k-1 (DCGS2: (j+2) + (j+3) vectors, CGS2 one more update
+                // pass), the start vector and the cycle-end combination of k Z vectors
+                const double k = member_iters[q] - it_start[q];
+                const double arn = dcgs ? k * k + 4.0 * k : 1.5 * k * k + 6.5 * k;
+                member_bytes[q] += k * it_bytes + s_v * N * arn + 2.0 * s_v * N + (k * s_pc + 16.0) * N;
+            }
         if (graphs) {
             if (h.graphs.gen != h.ws.generation()) {   // buffers allocated in this cycle: recapture later
                 h.graphs.clear();
@@ -822,6 +907,7 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, Sl
     std::vector<int> todo(B, 1);
     for (int q = 0; q < B; ++q) tol[q] = h.opt.rtol * std::sqrt(bn2[q]);
     std::vector<int> member_iters(B, 0), member_outer(B, 0);
+    std::vector<double> member_bytes(B, 0.0);   // model of the algorithmic HBM bytes per member
     std::vector<Clock::time_point> t_start(B, t0);
     std::vector<int> live(B, 1);    // slot holds a problem whose solve has not been reported (feed)
 
@@ -838,6 +924,7 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, Sl
         r.t_setup_ms = h.t_setup_ms;
         r.t_solve_ms = ms;
         r.latency_ms = ms;
+        r.bytes_moved = member_bytes[q];
         return r;
     };
     // restart boundary with a feed: report the members whose solve ended,
@@ -864,6 +951,7 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, Sl
             todo[q] = 1;
             member_iters[q] = 0;
             member_outer[q] = 0;
+            member_bytes[q] = 0.0;
             t_start[q] = Clock::now();
             refilled = true;
         }
@@ -876,7 +964,8 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, Sl
     };
 
     if (!fp32) {
-        fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, 0, res, member_iters, h.opt.verbose, boundary);
+        fgmres(K, b, x_dev, tol, todo, false, h.opt.max_iter, 0, res, member_iters, member_bytes, h.opt.verbose,
+               boundary);
     } else {
         // FP64 iterative refinement: r = b - K64 x (FP64 storage and sums);
         // one inner FGMRES cycle on K d = r with the operator and the
@@ -888,9 +977,11 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, Sl
         double* r = h.ws.get_t<double>("sr", (size_t)B * N);
         double* d = h.ws.get_t<double>("sd", (size_t)B * N);
         std::vector<double> nr2;
+        const double res_bytes = model_operator_bytes(h, 8.0) + 3.0 * 8.0 * N;
         while (true) {
             K.residual(b, x_dev, r, false, nr2);
             for (int q = 0; q < B; ++q) {
+                if (todo[q]) member_bytes[q] += res_bytes;
                 res[q] = std::sqrt(nr2[q]);
                 if (todo[q] && (res[q] <= tol[q] || member_iters[q] >= h.opt.max_iter)) todo[q] = 0;
             }
@@ -908,8 +999,10 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, Sl
             if (!any) break;
             launch_fill_zero<double>(d, (int64_t)B * N, st);
             std::vector<double> rin;
-            fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter, 1, rin, member_iters, h.opt.verbose);
+            fgmres(K, r, d, tol_in, todo32, true, h.opt.max_iter, 1, rin, member_iters, member_bytes, h.opt.verbose);
             launch_axpby(1.0, d, 1.0, x_dev, (int64_t)B * N, st);
+            for (int q = 0; q < B; ++q)
+                if (todo32[q]) member_bytes[q] += 3.0 * 8.0 * N;   // x += d
         }
     }
     SG_HIP(hipStreamSynchronize(st));
@@ -922,7 +1015,6 @@ int solve(Handle& h, const double* b_dev, double* x_dev, sg_solve_info* info, Sl
         if (live[q]) all = all && r.converged;
         if (info) {
             info[q] = r;
-            info[q].bytes_moved = 0.0;
             info[q].prof_ms = pms;
             info[q].prof_bytes = h.prof.bytes;
             info[q].prof_launches = (int32_t)h.prof.used;

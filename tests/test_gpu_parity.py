@@ -322,6 +322,10 @@ def test_batch_results_equal_alone():
             rca, infa = ha.solve(xa)
             assert rca == 0 and infa[0].iters == infos[i].iters
             assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
+            # the bytes model is per member: the same alone and in the batch, and at
+            # least an operator apply and a preconditioner of KKT-apply size per iteration
+            assert infa[0].bytes_moved == infos[i].bytes_moved
+            assert infos[i].bytes_moved > infos[i].iters * 2 * 6 * 4 * hb.block_elems
 
 
 @pytest.mark.parametrize("precision", [0, 1])
