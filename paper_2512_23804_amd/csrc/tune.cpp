@@ -21,6 +21,8 @@
 #include <string>
 #include <tuple>
 
+#include <unistd.h>
+
 #include "handle.hpp"
 
 namespace sg {
@@ -61,9 +63,11 @@ void parse_file(const std::string& path, TuneMap& out) {
     }
 }
 
-// write the cache atomically (temporary file, then rename); lock held by caller
+// write the cache atomically (a temporary file named for this process and
+// call, then rename); lock held by caller
 void write_file(const std::string& path, const TuneMap& m) {
-    const std::string tmp = path + ".tmp" + std::to_string((long)std::rand());
+    static unsigned long calls = 0;
+    const std::string tmp = path + ".tmp." + std::to_string((long)getpid()) + "." + std::to_string(++calls);
     {
         std::ofstream f(tmp, std::ios::trunc);
         if (!f) throw Error(SG_ERR_INVALID, "tuning cache: cannot write " + tmp);
@@ -207,7 +211,21 @@ void autotune(Handle& h) {
             rows = t == 0 ? tune_type<double>(h, h.stream) : tune_type<float>(h, h.stream);
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune_cache[key] = rows;
-            if (const char* p = env_path()) write_file(p, g_tune_cache);
+            if (const char* p = env_path()) {
+                // merge what other processes wrote since this one read the file
+                TuneMap disk;
+                std::ifstream probe(p);
+                if (probe) {
+                    probe.close();
+                    try {
+                        parse_file(p, disk);
+                    } catch (const Error&) {
+                        disk.clear();      // a file that no longer parses is replaced
+                    }
+                }
+                for (auto& kv : disk) g_tune_cache.insert(kv);
+                write_file(p, g_tune_cache);
+            }
         }
         for (int k = 0; k < 3; ++k) s.sweep_rows[t][k] = rows[k];
     }
