@@ -379,6 +379,42 @@ def paper_tables(torch, sgl, sg_inputs, grids, mean="direct"):
     return {"paper_tables": rows}
 
 
+def paper_parabolic(torch, sgl, sg_inputs):
+    """The settings of the paper's time-dependent tables (Section 5): log-normal
+    field with Hermite chaos, gamma = 1, the indicator target at every time step,
+    y_0 = 0, T = 1; Chebyshev-5 + hGS-1 with direct (sine-transform) mean-block
+    solves; truncations n_tau = 1, m + 1, n_A; relative tolerances 1e-6 and
+    1e-4; FGMRES(30).  Defaults m = p = 3, sigma = 0.2, beta = 1e-4, 32 x 32
+    elements, n_t = 8; each table varies one of them (its values as the members
+    of one batch where only sigma or beta change).  One untimed solve, then one
+    timed; the time per member is the batch's solve time over its members."""
+    base = dict(n=32, M=3, P=3, n_t=8, members=[(0.2, 1e-4)])
+    tables = [("mesh", dict(base, n=nn)) for nn in (8, 16, 32, 64)]
+    tables += [("beta", dict(base, members=[(0.2, b) for b in (1e-2, 1e-3, 1e-6)]))]
+    tables += [("sigma", dict(base, members=[(sg, 1e-4) for sg in (0.01, 0.02, 0.05, 0.1, 0.2, 0.4)]))]
+    tables += [("n_t", dict(base, n_t=nt)) for nt in (4, 16, 64)]
+    tables += [("(m, p)", dict(base, M=M, P=P)) for M, P in ((4, 4), (6, 3))]
+    stream = torch.cuda.Stream()
+    rows = []
+    for table, c in tables:
+        tgt = np.tile(sg_inputs.indicator_target(c["n"]), (c["n_t"], 1))
+        probs = [sgl.ProblemData(c["n"], c["M"], c["P"], sg, b, tgt, gamma=1.0, n_t=c["n_t"], T=1.0,
+                                 field=sgl.SG_FIELD_LOGNORMAL) for sg, b in c["members"]]
+        for tol in (1e-6, 1e-4):
+            for name, r in (("1", 1), ("m+1", c["M"] + 1), ("n_A", 0)):
+                print(f"[bench] paper parabolic {table}: n={c['n']} m={c['M']} p={c['P']} n_t={c['n_t']} "
+                      f"tol={tol:g} n_tau={name}", file=sys.stderr, flush=True)
+                opts = sgl.default_options(rtol=tol, truncation_r=r, mean_solver=1, max_iter=600)
+                dt, infos = timed_solves(torch, sgl, probs, opts, 1, 1, stream)
+                last = infos[-1]
+                rows.append({"table": table, "n": c["n"], "m": c["M"], "p": c["P"], "n_t": c["n_t"],
+                             "members": [list(mb) for mb in c["members"]], "tol": tol, "n_tau": name,
+                             "iterations": [i.iters for i in last], "ms_per_solve": 1000.0 * dt / len(probs),
+                             "converged": all(i.converged == 1 for i in last)})
+                print(json.dumps(rows[-1]), flush=True)
+    return {"paper_parabolic": rows}
+
+
 def cpu_baseline(wl, gpu_iters):
     """The oracle (plain FP64 numpy/scipy, BLAS threaded over every core this
     process may use) timed on the first member at the workload size.
@@ -512,6 +548,10 @@ def main():
                     help="iterations and time per solve on the grid of the paper's tables of sigma variations "
                          "(log-normal field, n_xi = 20 / 70 / 84, n_tau = 1 / m+1 / n_A, Chebyshev-5 or direct "
                          "mass solves, sigma = 0.01 / 0.1 / 0.4), one JSON line per setting")
+    ap.add_argument("--paper-parabolic", action="store_true",
+                    help="iterations and time per solve on the settings of the paper's time-dependent tables "
+                         "(log-normal field; mesh, beta, sigma, n_t and (m, p) variations; tolerances 1e-6 and "
+                         "1e-4; n_tau = 1 / m+1 / n_A), one JSON line per setting")
     ap.add_argument("--paper-grids", default="16,32,64,128", help="element counts per side for --paper-tables")
     ap.add_argument("--paper-mean", default="direct", choices=["direct", "multigrid"],
                     help="mean-block solves for --paper-tables")
@@ -580,6 +620,9 @@ def main():
 
     if args.precond_variants:
         print(json.dumps(precond_variants(torch, sgl, sg_inputs, args.workload, args.steps, args.warmup)), flush=True)
+        return
+    if args.paper_parabolic:
+        paper_parabolic(torch, sgl, sg_inputs)
         return
     if args.paper_tables:
         paper_tables(torch, sgl, sg_inputs, tuple(int(g) for g in args.paper_grids.split(",")), args.paper_mean)
