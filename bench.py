@@ -311,7 +311,7 @@ PRECOND_VARIANTS = [
     ("exact mass + hGS-1 (exact mean blocks)", dict(cheb_steps=0, mean_solver=1)),
     ("cheb5 + Richardson N=2", dict(richardson_steps=2)),
     ("cheb5 + hGS-1, mean-based (r = 1)", dict(truncation_r=1)),
-    ("hGSoc (Alg. 2-3), cheb5 level solves", dict(precond=1)),
+    ("hGSoc (Alg. 2-3; Alg. 4 on time steps), cheb5 level solves", dict(precond=1)),
 ]
 
 
@@ -329,8 +329,6 @@ def precond_variants(torch, sgl, sg_inputs, workload, steps, warmup):
         variants.append(("cheb5 + hGS-1 (exact mean blocks), n_tau = m+1", dict(truncation_r=wl["M"] + 1,
                                                                                mean_solver=1)))
         variants.append(("hGSoc (Alg. 2-3), n_tau = m+1", dict(truncation_r=wl["M"] + 1, precond=1)))
-    if wl["n_t"] > 1:      # hGSoc is defined for steady problems
-        variants = [v for v in variants if v[1].get("precond", 0) == 0]
     for label, over in variants:
         print(f"[bench] variant {label}", file=sys.stderr, flush=True)
         opts = sgl.default_options(rtol=1e-8, **over)

@@ -167,8 +167,11 @@ typedef struct sg_problem {
  *                [SG_MEAN_MULTIGRID]
  *   precond      SG_PRECOND_BLOCK_DIAGONAL: the block-diagonal preconditioner
  *                of eq. (stoch-prec) / eq. (precon for time); SG_PRECOND_HGSOC:
- *                the coupled level sweep of Algorithms 2-3 (steady problems,
- *                cheb_steps 1..9), each level solved with the block-diagonal
+ *                the coupled level sweep of Algorithms 2-3 (cheb_steps 1..9;
+ *                time-dependent problems take it on every time step at once,
+ *                the couplings between steps left out: Algorithm 4, with the
+ *                step's blocks tau D_tt h^gamma_j M, beta tau D_tt M and the
+ *                mean block A-hat_1), each level solved with the block-diagonal
  *                preconditioner restricted to its chaos columns (the adjoint
  *                by A-tilde_1^{-1} h^gamma_j M A-tilde_1^{-1}: the printed
  *                third block A-tilde_1 does not approximate the adjoint row)

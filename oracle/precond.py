@@ -395,17 +395,37 @@ class PtildeSolve:
             return self.mlu.solve(np.ascontiguousarray(R.T)).T
         return cheb_mass(self.sg.Mi, R, self.cheb_steps)
 
-    def apply(self, BY: np.ndarray, BU: np.ndarray, BL: np.ndarray, lo: int = 0, hi: int | None = None):
-        """Rows of BY, BU, BL are the chaos columns lo..hi-1."""
+    def apply(self, BY: np.ndarray, BU: np.ndarray, BL: np.ndarray, lo: int = 0, hi: int | None = None,
+              w: float = 1.0):
+        """Rows of BY, BU, BL are the chaos columns lo..hi-1.  w scales the
+        state and control mass blocks: 1 for the steady system, tau D_tt for
+        time step t of the all-at-once system (whose mean block is A-hat_1,
+        eq. A_hat)."""
         VL = self.inner.apply(BL)
+        beta = self.sg.prob.beta
         if self.adjoint == "schur":
             hg = kkt.h_gamma(self.sg)[lo:hi if hi is not None else lo + np.atleast_2d(BL).shape[0]][:, None]
-            VL = self.inner.apply(hg * kkt.mass_apply(self.sg, VL))
-            return self.mass_inv(BY) / hg, self.mass_inv(BU) / self.sg.prob.beta, VL
-        return self.mass_inv(BY), self.mass_inv(BU) / self.sg.prob.beta, VL
+            VL = self.inner.apply(w * hg * kkt.mass_apply(self.sg, VL))
+            return self.mass_inv(BY) / (w * hg), self.mass_inv(BU) / (w * beta), VL
+        return self.mass_inv(BY) / w, self.mass_inv(BU) / (w * beta), VL
 
 
-def hgsoc(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int) -> np.ndarray:
+def _step_scalings(sg: kkt.SG, t: int | None):
+    """(w, c): the state and control mass blocks of the level system are w
+    (h^gamma M, beta M), and the KKT couplings between levels (the off-level
+    part of A, and the control-adjoint mass) carry the factor c.  Steady: (1,
+    1).  Time step t of eq. (KKT:stoch-time-dependent) without its couplings
+    to the neighbouring steps: (tau D_tt, tau): state row tau D_tt M_gamma y -
+    L lambda, control row beta tau D_tt M u + tau M lambda, adjoint row -L y +
+    tau M u, with L = I (x) (M + tau A_1) + tau sum_{l>=2} H_l (x) A_l."""
+    if t is None:
+        return 1.0, 1.0
+    p = sg.prob
+    D = 0.5 if t in (0, p.n_t - 1) else 1.0
+    return p.tau * D, p.tau
+
+
+def hgsoc(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int, t: int | None = None) -> np.ndarray:
     """Algorithms 2-3 applied to a flat steady KKT residual (zero initial
     guess), returning the flat preconditioned vector.
 
@@ -420,8 +440,12 @@ def hgsoc(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int) -> np.nd
     diagonal, so C, E, F and H vanish; they are formed anyway from the
     off-level parts of those matrices."""
     p = sg.prob
-    assert p.steady, "hGSoc is defined for the steady KKT system"
-    Ry, Ru, Rl = (b.copy() for b in kkt.split(sg, r))
+    assert p.steady == (t is None), "steady system, or one time step t of the all-at-once system"
+    w, c = _step_scalings(sg, t)
+    if t is None:
+        Ry, Ru, Rl = (b.copy() for b in kkt.split(sg, r))
+    else:
+        Ry, Ru, Rl = (b.copy() for b in r.reshape(3, sg.n_xi, sg.n_int))
     off = sg.offsets
     P = len(off) - 2
     modes = list(range(1, min(r_trunc, len(sg.G))))
@@ -442,31 +466,50 @@ def hgsoc(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int) -> np.nd
             return Hm[:, lo:hi].T @ V
 
         Yo, Uo, Lo = others(VY), others(VU), others(VL)
-        C = kkt.mass_apply(sg, couple(hg, Yo))
-        E = p.beta * kkt.mass_apply(sg, couple(H1, Uo))
-        F = kkt.mass_apply(sg, couple(H1, Lo))
-        Hh = kkt.mass_apply(sg, couple(H1, Uo))
+        C = w * kkt.mass_apply(sg, couple(hg, Yo))
+        E = w * p.beta * kkt.mass_apply(sg, couple(H1, Uo))
+        F = c * kkt.mass_apply(sg, couple(H1, Lo))
+        Hh = c * kkt.mass_apply(sg, couple(H1, Uo))
         D = np.zeros((hi - lo, Ry.shape[1]))
         G = np.zeros_like(D)
         for k in modes:
-            D += (sg.K[k] @ couple(sg.G[k], Lo).T).T
-            G += (sg.K[k] @ couple(sg.G[k], Yo).T).T
+            D += c * (sg.K[k] @ couple(sg.G[k], Lo).T).T
+            G += c * (sg.K[k] @ couple(sg.G[k], Yo).T).T
         by = Ry[lo:hi] - C + D
         bu = Ru[lo:hi] - E - F
         bl = Rl[lo:hi] + G - Hh
-        VY[lo:hi], VU[lo:hi], VL[lo:hi] = ptilde.apply(by, bu, bl, lo, hi)
+        VY[lo:hi], VU[lo:hi], VL[lo:hi] = ptilde.apply(by, bu, bl, lo, hi, w)
     return np.concatenate([VY.ravel(), VU.ravel(), VL.ravel()])
 
 
-def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int, col_weights: tuple | None = None) -> tuple:
+def hgsoc_pint(sg: kkt.SG, r: np.ndarray, ptilde: PtildeSolve, r_trunc: int) -> np.ndarray:
+    """Algorithm 4 (hGSoc-PINT): Algorithms 2-3 applied to each time step's
+    subvector of the all-at-once residual independently (see _step_scalings
+    for the step's blocks; the mean block is A-hat_1), the results
+    concatenated in the flat time-dependent layout [block][t][j][node]."""
+    p = sg.prob
+    assert not p.steady
+    nt, nx, ni = p.n_t, sg.n_xi, sg.n_int
+    R = r.reshape(3, nt, nx, ni)
+    out = np.empty_like(R)
+    for t in range(nt):
+        z = hgsoc(sg, R[:, t].reshape(-1), ptilde, r_trunc, t)
+        out[:, t] = z.reshape(3, nx, ni)
+    return out.reshape(-1)
+
+
+def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int, col_weights: tuple | None = None,
+                      coupling: float = 1.0) -> tuple:
     """The matrices behind Algorithms 2-3 with exact P-tilde solves: the level
     splitting K_r = D + L + U of the KKT matrix with every level-diagonal
     block replaced by P-tilde (per chaos column) and the off-level couplings
     truncated to the kept modes; one forward and one backward block
     Gauss-Seidel sweep from zero then equal (D + U)^{-1} D (D + L)^{-1}.
     ptilde_blocks = (M, beta M, A-tilde_1) as sparse matrices, scaled per
-    chaos column by col_weights = (w_Y, w_U, w_Lambda) when given.  Returns
-    (D, L, U) over the unknown order [Y | U | Lambda], chaos-major inside a block."""
+    chaos column by col_weights = (w_Y, w_U, w_Lambda) when given; the
+    off-level couplings -A are scaled by `coupling` (tau for a time step of
+    the all-at-once system).  Returns (D, L, U) over the unknown order
+    [Y | U | Lambda], chaos-major inside a block."""
     p = sg.prob
     nxi, ni = sg.n_xi, sg.n_int
     Mb, bMb, A1 = ptilde_blocks
@@ -488,7 +531,7 @@ def hgsoc_matrix_form(sg: kkt.SG, ptilde_blocks: tuple, r_trunc: int, col_weight
     Z = sp.csr_matrix((nxi * ni, nxi * ni))
     if Aoff is None:
         Aoff = Z
-    Koff = sp.bmat([[None, None, -Aoff], [None, Z, None], [-Aoff, None, None]], format="csr")
+    Koff = sp.bmat([[None, None, -coupling * Aoff], [None, Z, None], [-coupling * Aoff, None, None]], format="csr")
     # level of each unknown (row / column)
     lev = np.tile(np.repeat(level, ni), 3)
     Kc = Koff.tocoo()

@@ -23,7 +23,8 @@ constexpr int GTX = 16;    // node tile (GTX x GTX threads per block)
 
 // out_j = base_j + s * sum_{i in [ilo1, ihi1) u [ilo2, ihi2)} sum_e (B_e[i][j] + [i == j] mean_c) kr_e(X_i)
 // for the L output columns j = j0 .. j0+L-1 of each slice (vector, t); s =
-// scale, or -off_scale of the slice's member when scale_off; base may be null.
+// scale, or -scale_off * off_scale of the slice's member when scale_off != 0 (1:
+// subtract the couplings, -1: add them); base may be null.
 // X: field blocks with member stride xms and time stride xts ([t][i][node]).
 template <typename T>
 __global__ __launch_bounds__(GTX* GTX) void k_gen_sg(int n, int nxi, int nt, const double* __restrict__ B, int64_t bms,
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(GTX* GTX) void k_gen_sg(int n, int nxi, int nt, con
         return;
     }
     const int mm = shared ? 0 : vec;
-    const double s = scale_off ? -mem[mm].off_scale : scale;
+    const double s = scale_off ? -(double)scale_off * mem[mm].off_scale : scale;
     const double* Bm = B + (int64_t)mm * bms;
     const int64_t nn = (int64_t)nxi * nxi;
     // the four elements at the node: (ex, ey) = (ix-1, iy-1), (ix, iy-1), (ix-1, iy), (ix, iy)

@@ -1345,15 +1345,12 @@ void launch_hgs_rhs(const Shape& s, const OpDev& op, int d, uint32_t mask, int u
                     const T* base, ColMap bmap, const T* V, ColMap vmap, T* out, ColMap omap, int nmembers,
                     hipStream_t st) {
     if (op.gen) {
-        // the coupled columns of every other level: all lower ones and/or all upper ones
+        // the coupled columns of every other level: all lower ones and/or all upper ones;
+        // base - off_sign * off_scale (couplings) with the member's off_scale
         const int lo = s.off[d], hi = s.off[d + 1];
-        if (op.off_sign == 1.0)
-            launch_gen_sg<T>(s, op, true, V, vmap.mstride, vmap.tstride, 0, use_lower ? lo : 0, hi,
-                             use_upper ? s.nxi : hi, lo, hi - lo, base, bmap, out, omap, 0.0, 1, 0.0, nmembers, st);
-        else      // (steady: off_scale = 1)
-            launch_gen_sg<T>(s, op, true, V, vmap.mstride, vmap.tstride, 0, use_lower ? lo : 0, hi,
-                             use_upper ? s.nxi : hi, lo, hi - lo, base, bmap, out, omap, -op.off_sign, 0, 0.0, nmembers,
-                             st);
+        launch_gen_sg<T>(s, op, true, V, vmap.mstride, vmap.tstride, 0, use_lower ? lo : 0, hi,
+                         use_upper ? s.nxi : hi, lo, hi - lo, base, bmap, out, omap, 0.0, op.off_sign > 0 ? 1 : -1,
+                         0.0, nmembers, st);
         return;
     }
     if (launch_sgx_hgs_rhs<T>(s, op, d, mask, use_lower, use_upper, base, bmap, V, vmap, out, omap, nmembers, st))

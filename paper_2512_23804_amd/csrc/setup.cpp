@@ -184,8 +184,8 @@ void validate(const sg_problem* probs, int count, const sg_options* opt) {
             fail(SG_ERR_INVALID, "richardson_steps must be in [1, 16]");
         if (opt->precond != SG_PRECOND_BLOCK_DIAGONAL && opt->precond != SG_PRECOND_HGSOC)
             fail(SG_ERR_INVALID, "precond must be SG_PRECOND_BLOCK_DIAGONAL or SG_PRECOND_HGSOC");
-        if (opt->precond == SG_PRECOND_HGSOC && (p0.n_t >= 2 || opt->cheb_steps < 1 || opt->cheb_steps > 9))
-            fail(SG_ERR_INVALID, "hGSoc is defined for steady problems with cheb_steps in [1, 9]");
+        if (opt->precond == SG_PRECOND_HGSOC && (opt->cheb_steps < 1 || opt->cheb_steps > 9))
+            fail(SG_ERR_INVALID, "hGSoc needs cheb_steps in [1, 9]");
         const int nterms = p0.field == SG_FIELD_LOGNORMAL ? binom(p0.M + 2 * p0.P, 2 * p0.P) : p0.M + 1;
         if (opt->truncation_r < 0 || opt->truncation_r > nterms)
             fail(SG_ERR_INVALID, "truncation_r must be in [0, number of coefficient terms] (M+1 affine, "

@@ -293,16 +293,21 @@ void zinv(Handle& h, const T* R, int64_t rms, T* V, int64_t vms, int nvec, bool 
     }
 }
 
-// hGSoc (Algorithms 2-3, steady): one forward (degrees 0..P) and one backward
-// (P-1..0) sweep over the degree levels of the whole KKT vector, zero initial
-// guess.  At level d the state and adjoint rows take the KKT couplings to the
+// hGSoc (Algorithms 2-3; on the all-at-once time-dependent system applied to
+// every time step at once, Algorithm 4): one forward (degrees 0..P) and one
+// backward (P-1..0) sweep over the degree levels of the whole KKT vector, zero
+// initial guess.  At level d the state and adjoint rows take the KKT couplings to the
 // other levels with their current values (R^Y_d + sum_k K_k Lambda and R^L_d +
 // sum_k K_k Y over the kept modes; the control row has none), and the level
 // is solved with the block-diagonal preconditioner restricted to its chaos
 // columns: h^gamma_j M and beta M by Chebyshev, the adjoint by A-tilde_1^{-1}
 // h^gamma_j M A-tilde_1^{-1} (the Schur-type reading of P-tilde; the printed
 // third block A-tilde_1 stagnates).  As in Alg. 1 the backward sweep reuses
-// the forward right-hand side of each level and adds the upper levels.
+// the forward right-hand side of each level and adds the upper levels.  For a
+// time step t the level blocks are tau D_tt h^gamma_j M, beta tau D_tt M and
+// A-hat_1 (tau D_tt h^gamma_j M)^{-1} A-hat_1 and the couplings carry tau
+// (the member's off_scale); the couplings to the neighbouring steps are left
+// out, so the steps are independent.
 template <typename T>
 void hgsoc_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t st) {
     const Shape& s = h.s;
@@ -319,7 +324,7 @@ void hgsoc_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t
     auto level = [&](int d, bool fwd) {
         const ColMap rm = level_map(s, d, kkt), bm = level_map(s, d, s.blk);
         const int L = s.off[d + 1] - s.off[d];
-        const int ncols = L * nvec, cpm = shared ? ncols : L, cpv = L;
+        const int ncols = L * s.nt * nvec, cpm = shared ? ncols : L * s.nt, cpv = L * s.nt;
         // right-hand sides of the state and adjoint rows (base: the residual, or
         // backward the forward right-hand side of this level)
         const T* bY = r;
@@ -335,12 +340,16 @@ void hgsoc_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t
             bL = BL;
             bYm = bLm = bm;
         }
-        // state and control columns of the level: Chebyshev with the block scalings
+        // state and control columns of the level, per time step (a level's
+        // columns are contiguous within a step): Chebyshev with the block scalings
         const bool yb = bY == BY;
-        if (!launch_mass_cheb_cols<T>(s, op, yb ? BY : r, yb ? s.blk : kkt, z, kkt, s.off[d], L, nvec,
-                                      h.opt.cheb_steps, st) ||
-            !launch_mass_cheb_cols<T>(s, op, r, kkt, z, kkt, s.nxi + s.off[d], L, nvec, h.opt.cheb_steps, st))
-            throw Error(SG_ERR_INVALID, "hGSoc needs cheb_steps in [1, 9]");
+        for (int t = 0; t < s.nt; ++t) {
+            const int c0 = t * s.nxi + s.off[d];
+            if (!launch_mass_cheb_cols<T>(s, op, yb ? BY : r, yb ? s.blk : kkt, z, kkt, c0, L, nvec,
+                                          h.opt.cheb_steps, st) ||
+                !launch_mass_cheb_cols<T>(s, op, r, kkt, z, kkt, s.nt * s.nxi + c0, L, nvec, h.opt.cheb_steps, st))
+                throw Error(SG_ERR_INVALID, "hGSoc needs cheb_steps in [1, 9]");
+        }
         // adjoint columns: A-tilde_1^{-1} h^gamma_j M A-tilde_1^{-1}
         mean_solve<T>(h, bL, bLm, T1, bm, ncols, cpm, cpv, nvec, st);
         launch_mass_scaled<T>(s, op, T1, bm, T2, bm, ncols, nvec, st);

@@ -480,6 +480,47 @@ HGSOC_CASES = [
     (16, 3, 2, 0.3, 1e-2, 0.0, "affine", dict(mean_solver=1)),
 ]
 
+HGSOC_PINT_CASES = [
+    # n, M, P, sigma, beta, gamma, n_t, field, options
+    (16, 3, 2, 0.3, 1e-2, 0.0, 3, "affine", {}),
+    (16, 2, 3, 0.25, 1e-3, 0.5, 4, "affine", dict(truncation_r=2)),
+    (16, 2, 2, 0.3, 1e-2, 1.0, 3, "lognormal", dict(mean_solver=1)),
+]
+
+
+@pytest.mark.parametrize("case", HGSOC_PINT_CASES)
+def test_hgsoc_pint_preconditioner(case):
+    """SG_PRECOND_HGSOC on the all-at-once time-dependent system (Algorithm 4:
+    Algorithms 2-3 on every time step, with the step's blocks and A-hat_1):
+    the preconditioner apply against the oracle's hgsoc_pint at 1e-12 (FP32
+    at 1e-5), and a solve within 1e-8 of the direct solution."""
+    n, M, P, sigma, beta, gamma, nt, field, opts = case
+    dev = _dev()
+    _say(f"hgsoc pint {case}")
+    sgl = _lib()
+    prob, kw = make_case(n, M, P, sigma, beta, gamma, nt, y0=True, field=field)
+    sg = kkt.setup(prob)
+    h = _setup([kw], precond=sgl.SG_PRECOND_HGSOC, rtol=1e-12, max_iter=800, **opts)
+    x = np.random.default_rng(23).uniform(-1, 1, size=kkt.rhs(sg).size)
+    xd = torch.from_numpy(kkt_to_canonical(sg, x)).to(dev)
+    zd = torch.full_like(xd, np.nan)
+    h.precond_apply(xd, zd)
+    z32 = torch.full_like(xd, np.nan, dtype=torch.float32)
+    h.precond_apply(xd.float(), z32)
+    torch.cuda.synchronize()
+    pt = precond.PtildeSolve(sg, "cheb", adjoint="schur")
+    pt.inner = precond.make_inner(sg, "exact" if opts.get("mean_solver", 0) == 1 else "gmg")
+    ref = precond.hgsoc_pint(sg, x, pt, opts.get("truncation_r", 0) or len(sg.G))
+    assert rel_max(canonical_to_kkt(sg, zd.cpu().numpy()), ref) < 1e-12
+    assert rel_max(canonical_to_kkt(sg, z32.double().cpu().numpy()), ref) < 1e-5
+    assert ring_is_zero(zd.cpu().numpy(), n)
+    sol = torch.zeros(h.kkt_elems, dtype=torch.float64, device=dev)
+    rc, info = h.solve(sol)
+    assert rc == 0 and info[0].rel_res_true <= 1e-12
+    xs = canonical_to_kkt(sg, sol.cpu().numpy())
+    for a, b in zip(kkt.split(sg, xs), kkt.split(sg, kkt.solve_direct(sg))):
+        assert rel_max(a, b) < 1e-8
+
 
 @pytest.mark.parametrize("case", HGSOC_CASES)
 def test_hgsoc_preconditioner(case):
