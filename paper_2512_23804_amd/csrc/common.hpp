@@ -197,12 +197,13 @@ void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, 
 // All Chebyshev mass steps in one LDS-tiled kernel; false when steps > 9.
 template <typename T>
 bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, int steps, hipStream_t st);
-// The same on the columns l0 .. l0+ncols-1 of [y | u] (n_t n_xi state columns,
-// then the control columns; the block scalings of those columns), input and
-// output with their own vector strides.
+// The same on ngrp groups of ncols consecutive columns of [y | u] (n_t n_xi
+// state columns, then the control columns; the block scalings of those
+// columns), group g starting at column l0 + g * gstride, input and output
+// with their own vector strides.
 template <typename T>
 bool launch_mass_cheb_cols(const Shape& s, const OpDev& op, const T* r, int64_t rstride, T* z, int64_t zstride, int l0,
-                           int ncols, int nvec, int steps, hipStream_t st);
+                           int ncols, int ngrp, int gstride, int nvec, int steps, hipStream_t st);
 
 // Exact solve by the 2D sine transform (dst.hip) on ncols columns:
 // mode 1: x = (a1 K + b1 M)^{-1} b with the scalars of member c / cpm;

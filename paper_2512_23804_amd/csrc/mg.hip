@@ -308,7 +308,8 @@ struct ChebW {
 template <typename T, int TF, int H, int NT>
 __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, int time, int64_t nodes, OpDev op,
                                                          int64_t vstride, const T* __restrict__ r, T* __restrict__ z,
-                                                         ChebW cw, int tiles_x, int64_t zstride, int l0) {
+                                                         ChebW cw, int tiles_x, int64_t zstride, int l0, int cpg,
+                                                         int gstride) {
     // H = steps - 1 stencil steps; the region keeps a halo of at least one node
     // so that the first tile row and column also hold the ring at index 0
     constexpr int HR = H > 0 ? H : 1;
@@ -318,7 +319,9 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
     __shared__ T sA[W * W];           // x_k (read by the mass stencil), two copies: one barrier per step
     __shared__ T sB[W * W];
     const SG g;
-    const int l = l0 + blockIdx.y;                   // column of [y | u]: n_t n_xi state columns, then control
+    // column of [y | u] (n_t n_xi state columns, then control): groups of cpg
+    // consecutive columns, gstride columns apart
+    const int l = l0 + (int)(blockIdx.y / cpg) * gstride + (int)(blockIdx.y % cpg);
     const int vec = blockIdx.z;
     if (op.active && !op.active[vec]) return;        // uniform per block, before any barrier
     const int mem = op.mem_shared ? 0 : vec;
@@ -637,14 +640,14 @@ void tail_m(const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColM
 
 template <typename T, int H>
 void cheb_h(const Shape& s, const OpDev& op, const T* r, int64_t rstride, T* z, int64_t zstride, int l0, int ncols,
-            int nvec, const ChebW& cw, hipStream_t st) {
-    if (ncols > 65535 || nvec > 65535) throw Error(SG_ERR_INVALID, "Chebyshev: launch grid too large");
+            int ngrp, int gstride, int nvec, const ChebW& cw, hipStream_t st) {
+    if ((int64_t)ncols * ngrp > 65535 || nvec > 65535) throw Error(SG_ERR_INVALID, "Chebyshev: launch grid too large");
     // 32-node tiles at every grid size: 64-node tiles (512 threads) fetch fewer
     // halo nodes but measured slower at 128^2 and 512^2
     constexpr int TF = 32;
     const int tx = (s.n - 1 + TF - 1) / TF;
-    hipLaunchKernelGGL((k_mass_cheb_fused<T, TF, H, 256>), dim3(tx * tx, ncols, nvec), dim3(256), 0, st, s.n, s.nxi,
-                       s.nt, (int)s.time, s.nodes, op, rstride, r, z, cw, tx, zstride, l0);
+    hipLaunchKernelGGL((k_mass_cheb_fused<T, TF, H, 256>), dim3(tx * tx, ncols * ngrp, nvec), dim3(256), 0, st, s.n,
+                       s.nxi, s.nt, (int)s.time, s.nodes, op, rstride, r, z, cw, tx, zstride, l0, ncols, gstride);
 }
 
 constexpr int TCD = 16;   // coarse nodes per down tile side
@@ -731,12 +734,12 @@ void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, 
 // Returns false when the step count has no fused kernel (more than 9 steps).
 template <typename T>
 bool launch_mass_cheb_fused(const Shape& s, const OpDev& op, const T* r, T* z, int nvec, int steps, hipStream_t st) {
-    return launch_mass_cheb_cols<T>(s, op, r, 3 * s.blk, z, 3 * s.blk, 0, 2 * s.nt * s.nxi, nvec, steps, st);
+    return launch_mass_cheb_cols<T>(s, op, r, 3 * s.blk, z, 3 * s.blk, 0, 2 * s.nt * s.nxi, 1, 0, nvec, steps, st);
 }
 
 template <typename T>
 bool launch_mass_cheb_cols(const Shape& s, const OpDev& op, const T* r, int64_t rstride, T* z, int64_t zstride, int l0,
-                           int ncols, int nvec, int steps, hipStream_t st) {
+                           int ncols, int ngrp, int gstride, int nvec, int steps, hipStream_t st) {
     if (steps < 1 || steps > 9) return false;
     ChebW cw{};
     const double rho = 0.8;
@@ -746,15 +749,15 @@ bool launch_mass_cheb_cols(const Shape& s, const OpDev& op, const T* r, int64_t 
         cw.omega[k - 1] = omega;
     }
     switch (steps - 1) {
-        case 0: cheb_h<T, 0>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        case 1: cheb_h<T, 1>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        case 2: cheb_h<T, 2>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        case 3: cheb_h<T, 3>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        case 4: cheb_h<T, 4>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        case 5: cheb_h<T, 5>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        case 6: cheb_h<T, 6>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        case 7: cheb_h<T, 7>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
-        default: cheb_h<T, 8>(s, op, r, rstride, z, zstride, l0, ncols, nvec, cw, st); break;
+        case 0: cheb_h<T, 0>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        case 1: cheb_h<T, 1>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        case 2: cheb_h<T, 2>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        case 3: cheb_h<T, 3>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        case 4: cheb_h<T, 4>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        case 5: cheb_h<T, 5>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        case 6: cheb_h<T, 6>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        case 7: cheb_h<T, 7>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
+        default: cheb_h<T, 8>(s, op, r, rstride, z, zstride, l0, ncols, ngrp, gstride, nvec, cw, st); break;
     }
     SG_HIP(hipGetLastError());
     return true;
@@ -763,9 +766,9 @@ bool launch_mass_cheb_cols(const Shape& s, const OpDev& op, const T* r, int64_t 
 template bool launch_mass_cheb_fused<double>(const Shape&, const OpDev&, const double*, double*, int, int, hipStream_t);
 template bool launch_mass_cheb_fused<float>(const Shape&, const OpDev&, const float*, float*, int, int, hipStream_t);
 template bool launch_mass_cheb_cols<double>(const Shape&, const OpDev&, const double*, int64_t, double*, int64_t, int,
-                                            int, int, int, hipStream_t);
+                                            int, int, int, int, int, hipStream_t);
 template bool launch_mass_cheb_cols<float>(const Shape&, const OpDev&, const float*, int64_t, float*, int64_t, int, int,
-                                           int, int, hipStream_t);
+                                           int, int, int, int, hipStream_t);
 
 template void launch_mg_tail<double>(int, const LevelDev*, int, int, int, const double*, ColMap, double*, ColMap,
                                      const double*, int, int, const int*, int, hipStream_t);

@@ -340,16 +340,14 @@ void hgsoc_apply(Handle& h, const T* r, T* z, int nvec, bool shared, hipStream_t
             bL = BL;
             bYm = bLm = bm;
         }
-        // state and control columns of the level, per time step (a level's
-        // columns are contiguous within a step): Chebyshev with the block scalings
+        // state and control columns of the level (L consecutive columns in each
+        // time step, n_xi apart): Chebyshev with the block scalings
         const bool yb = bY == BY;
-        for (int t = 0; t < s.nt; ++t) {
-            const int c0 = t * s.nxi + s.off[d];
-            if (!launch_mass_cheb_cols<T>(s, op, yb ? BY : r, yb ? s.blk : kkt, z, kkt, c0, L, nvec,
-                                          h.opt.cheb_steps, st) ||
-                !launch_mass_cheb_cols<T>(s, op, r, kkt, z, kkt, s.nt * s.nxi + c0, L, nvec, h.opt.cheb_steps, st))
-                throw Error(SG_ERR_INVALID, "hGSoc needs cheb_steps in [1, 9]");
-        }
+        if (!launch_mass_cheb_cols<T>(s, op, yb ? BY : r, yb ? s.blk : kkt, z, kkt, s.off[d], L, s.nt, s.nxi, nvec,
+                                      h.opt.cheb_steps, st) ||
+            !launch_mass_cheb_cols<T>(s, op, r, kkt, z, kkt, s.nt * s.nxi + s.off[d], L, s.nt, s.nxi, nvec,
+                                      h.opt.cheb_steps, st))
+            throw Error(SG_ERR_INVALID, "hGSoc needs cheb_steps in [1, 9]");
         // adjoint columns: A-tilde_1^{-1} h^gamma_j M A-tilde_1^{-1}
         mean_solve<T>(h, bL, bLm, T1, bm, ncols, cpm, cpv, nvec, st);
         launch_mass_scaled<T>(s, op, T1, bm, T2, bm, ncols, nvec, st);
