@@ -488,6 +488,28 @@ HGSOC_PINT_CASES = [
 ]
 
 
+def test_hgsoc_batch_equals_alone():
+    """hGSoc batches (steady, and time-dependent under Algorithm 4): members
+    with different sigma and beta give the iterations and bit-identical
+    solutions of their alone solves."""
+    dev = _dev()
+    sgl = _lib()
+    _say("hgsoc batch invariance")
+    for nt in (1, 3):
+        kws = [make_case(16, 3, 2, sg, b, 0.0, nt, seed=sd, y0=nt > 1)[1]
+               for sg, b, sd in ((0.2, 1e-2, 0), (0.3, 1e-3, 1))]
+        hb = _setup(kws, precond=sgl.SG_PRECOND_HGSOC, rtol=1e-10, max_iter=600)
+        xb = torch.zeros(2 * hb.kkt_elems, dtype=torch.float64, device=dev)
+        rc, infos = hb.solve(xb)
+        assert rc == 0
+        for i, kw in enumerate(kws):
+            ha = _setup([kw], precond=sgl.SG_PRECOND_HGSOC, rtol=1e-10, max_iter=600)
+            xa = torch.zeros(ha.kkt_elems, dtype=torch.float64, device=dev)
+            rca, ia = ha.solve(xa)
+            assert rca == 0 and ia[0].iters == infos[i].iters
+            assert torch.equal(xa, xb[i * ha.kkt_elems:(i + 1) * ha.kkt_elems])
+
+
 @pytest.mark.parametrize("case", HGSOC_PINT_CASES)
 def test_hgsoc_pint_preconditioner(case):
     """SG_PRECOND_HGSOC on the all-at-once time-dependent system (Algorithm 4:
