@@ -404,10 +404,7 @@ __global__ __launch_bounds__(NT) void k_mass_cheb_fused(int n, int nxi, int nt, 
 // template instance (compile-time width); a thread's nodes are a vertical
 // segment (Seg) whose b, iterate and step direction stay in registers.
 // --------------------------------------------------------------------------
-#ifndef SG_TAIL_THREADS
-#define SG_TAIL_THREADS 1024
-#endif
-constexpr int kTailThreads = SG_TAIL_THREADS;
+constexpr int kTailThreads = 1024;   // 512 or 256 measured slower (bit-identical)
 
 __host__ __device__ constexpr int tail_levels(int m0) { return m0 <= kCoarseN ? 1 : 1 + tail_levels(m0 / 2); }
 __host__ __device__ constexpr int tail_offset(int m0, int k) {
