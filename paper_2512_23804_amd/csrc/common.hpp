@@ -179,16 +179,16 @@ void launch_mass_scaled(const Shape& s, const OpDev& op, const T* V, ColMap vmap
                         int ncols, int nvec_members, hipStream_t st);
 
 // Fused multigrid levels (mg.hip): down = npre pre-smoothing steps from zero +
-// residual + restriction; up = the same pre-smoothing recomputed from b +
+// residual + restriction, the pre-smoothed iterate stored to xp; up = xp +
 // prolongation of the coarse correction + npost post-smoothing steps.  Coarse
-// arrays are contiguous [column][(m/2+1)^2].
+// arrays and xp are contiguous [column][(m/2+1)^2] and [column][(m+1)^2].
 // Columns c with act != null and act[c / cpv] == 0 are skipped (cpv: columns
 // per vector).
 template <typename T>
-void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, int ncols, int cpm,
-                    const int* act, int cpv, hipStream_t st);
+void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, T* xp, int ncols,
+                    int cpm, const int* act, int cpv, hipStream_t st);
 template <typename T>
-void launch_mg_up(int m, const LevelDev* lev, int lvl, int npre, int npost, const T* ec, const T* b, ColMap bmap,
+void launch_mg_up(int m, const LevelDev* lev, int lvl, int npost, const T* ec, const T* b, ColMap bmap, const T* xp,
                   T* xo, ColMap xomap, int ncols, int cpm, const int* act, int cpv, hipStream_t st);
 template <typename T>
 void launch_mg_tail(int m0, const LevelDev* lev, int lvl0, int npre, int npost, const T* b, ColMap bmap, T* x,

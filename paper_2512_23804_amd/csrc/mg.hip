@@ -4,10 +4,11 @@
 //   down: x = pre-smoothing of b from a zero guess (NU Chebyshev steps),
 //         r = b - A x, b_coarse = P^T r           (b read once, x and b_coarse written)
 //   up:   x' = x + P e_coarse, then NU post-smoothing steps from x'
+//         (b and x read, x' written)
 // Each workgroup stages a tile of the level plus a halo of NU+1 nodes in LDS
 // and runs all steps there (the halo shrinks by one node per stencil step),
-// so the finest level is read about twice and written about twice per
-// V-cycle.  The smoother is the Chebyshev iteration
+// so the finest level is read about three times and written about twice
+// per V-cycle.  The smoother is the Chebyshev iteration
 //   r = b - A x;  d = c_d d + c_r D^{-1} r;  x = x + d
 // with per-member, per-level coefficients (c_d = 0 in the first step).
 // Tiles start at node 1 (the Dirichlet ring is zero), so 2^k - 1 interior
@@ -84,9 +85,7 @@ __device__ __forceinline__ void st9_seg(const T* s, int X, int Y0, T wc, T we, T
 // Pre-smoothing from a zero guess on a W x W region: x_1 = c_r D^{-1} b, then
 // NPRE-1 Chebyshev steps, step s updating [s, W-s).  The iterate is in LDS
 // (sx, read by the stencil); b, the step direction and the iterate of the
-// thread's nodes are in registers.  Shared by the down kernel and by the up
-// kernel, which recomputes the pre-smoothed iterate from b (same arithmetic)
-// instead of reading it back from memory.
+// thread's nodes are in registers.
 template <typename T, int W, int PPT, int NPRE>
 __device__ __forceinline__ void pre_smooth(const T (&breg)[PPT], T (&d)[PPT], T (&xr)[PPT], T* sx, int FX0, int FY0,
                                            int m, const LevelDev& L, T wc, T we, T wd, T dinv) {
@@ -139,11 +138,13 @@ __device__ __forceinline__ void load_region(T (&breg)[PPT], const T* __restrict_
 // down: coarse tile of TC x TC coarse nodes starting at (I0, J0) = 1 + TC (tx, ty).
 // Fine region: origin (2 I0 - 1 - NU, 2 J0 - 1 - NU), width W = 2 TC + 1 + 2 NU:
 // pre-smoothing from zero (NU steps), residual, restriction b_c = P^T r.  The
-// pre-smoothed iterate is not stored (the up kernel recomputes it).
+// pre-smoothed iterate of the fine tile [2 I0 - 1, 2 I0 - 1 + 2 TC)^2 (interior
+// nodes; the tiles cover the interior) is stored to xp ([column][(m+1)^2]) for
+// the up kernel.
 template <typename T, int TC, int NU>
 __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restrict__ lev, int lvl,
-                                                 const T* __restrict__ b, ColMap bmap, T* __restrict__ bc, int cpm,
-                                                 int tiles_x, Skip sk) {
+                                                 const T* __restrict__ b, ColMap bmap, T* __restrict__ bc,
+                                                 T* __restrict__ xp, int cpm, int tiles_x, Skip sk) {
     constexpr int W = 2 * TC + 1 + 2 * NU;
     constexpr int PPT = (W * W + 255) / 256;
     __shared__ T sx[W * W];
@@ -159,6 +160,17 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
     T breg[PPT], d[PPT], xr[PPT];
     load_region<T, W, PPT>(breg, b + bmap.off(c), FX0, FY0, m);
     pre_smooth<T, W, PPT, NU>(breg, d, xr, sx, FX0, FY0, m, L, wc, we, wd, dinv);
+    {
+        T* xpc = xp + (int64_t)c * (m + 1) * (m + 1);
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+            const int q = threadIdx.x + 256 * p;
+            const int i = q % W, j = q / W;
+            const int X = FX0 + i, Y = FY0 + j;
+            if (q < W * W && i >= NU && i < NU + 2 * TC && j >= NU && j < NU + 2 * TC && interior(X, Y, m))
+                xpc[Y * (m + 1) + X] = xr[p];
+        }
+    }
     // residual on [NU, W-NU) (into registers, then over the iterate in LDS)
     T rr[PPT];
 #pragma unroll
@@ -195,15 +207,16 @@ __global__ __launch_bounds__(256) void k_mg_down(int m, const LevelDev* __restri
 }
 
 // up: fine tile of TF x TF nodes starting at (X0, Y0) = 1 + TF (tx, ty), region
-// with halo H = NPOST + NPRE - 1: the pre-smoothed iterate is recomputed from b
-// (valid on [NPRE-1, W-NPRE+1)), the interpolated coarse correction added, and
+// with halo H = NPOST: the pre-smoothed iterate stored by the down kernel is
+// read (zero off the interior), the interpolated coarse correction added, and
 // NPOST post-smoothing steps run; the owned tile is written.
-template <typename T, int TF, int NPRE, int NPOST>
+template <typename T, int TF, int NPOST>
 __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict__ lev, int lvl,
                                                const T* __restrict__ ec, const T* __restrict__ b, ColMap bmap,
-                                               T* __restrict__ xo, ColMap xomap, int cpm, int tiles_x, Skip sk) {
-    constexpr int H0 = NPRE - 1;
-    constexpr int H = NPOST + H0;
+                                               const T* __restrict__ xp, T* __restrict__ xo, ColMap xomap, int cpm,
+                                               int tiles_x, Skip sk) {
+    constexpr int H0 = 0;
+    constexpr int H = NPOST;
     constexpr int W = TF + 2 * H;
     constexpr int PPT = (W * W + 255) / 256;
     __shared__ T sx[W * W];
@@ -239,8 +252,9 @@ __global__ __launch_bounds__(256) void k_mg_up(int m, const LevelDev* __restrict
     }
     T breg[PPT], d[PPT], xr[PPT];
     load_region<T, W, PPT>(breg, b + bmap.off(c), FX0, FY0, m);
-    pre_smooth<T, W, PPT, NPRE>(breg, d, xr, sx, FX0, FY0, m, L, wc, we, wd, dinv);   // (its barriers cover se)
-    // x += P e_c on the nodes where the pre-smoothed iterate is valid
+    load_region<T, W, PPT>(xr, xp + (int64_t)c * N1 * N1, FX0, FY0, m);
+    __syncthreads();                    // se complete
+    // x += P e_c on the region's interior nodes
 #pragma unroll
     for (int p = 0; p < PPT; ++p) {
         const int q = threadIdx.x + 256 * p;
@@ -651,62 +665,50 @@ constexpr int TCD = 16;   // coarse nodes per down tile side
 constexpr int TFU = 32;   // fine nodes per up tile side
 
 template <typename T, int NU>
-void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* bc, int ncols, int cpm, Skip sk,
+void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* bc, T* xp, int ncols, int cpm, Skip sk,
              hipStream_t st) {
     const int mc = m / 2;
     const int tx = (mc - 1 + TCD - 1) / TCD;
     dim3 grid(tx * tx, ncols);
-    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, bc, cpm, tx, sk);
+    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, bc, xp, cpm, tx, sk);
 }
 
-template <typename T, int NPRE, int NPOST>
-void up_nu(int m, const LevelDev* lev, int lvl, const T* ec, const T* b, ColMap bmap, T* xo, ColMap xomap, int ncols,
-           int cpm, Skip sk, hipStream_t st) {
+template <typename T, int NPOST>
+void up_nu(int m, const LevelDev* lev, int lvl, const T* ec, const T* b, ColMap bmap, const T* xp, T* xo,
+           ColMap xomap, int ncols, int cpm, Skip sk, hipStream_t st) {
     const int tx = (m - 1 + TFU - 1) / TFU;
     dim3 grid(tx * tx, ncols);
-    hipLaunchKernelGGL((k_mg_up<T, TFU, NPRE, NPOST>), grid, dim3(256), 0, st, m, lev, lvl, ec, b, bmap, xo, xomap,
+    hipLaunchKernelGGL((k_mg_up<T, TFU, NPOST>), grid, dim3(256), 0, st, m, lev, lvl, ec, b, bmap, xp, xo, xomap,
                        cpm, tx, sk);
-}
-
-template <typename T, int NPRE>
-void up_pre(int m, const LevelDev* lev, int lvl, int npost, const T* ec, const T* b, ColMap bmap, T* xo, ColMap xomap,
-            int ncols, int cpm, Skip sk, hipStream_t st) {
-    switch (npost) {
-        case 1: up_nu<T, NPRE, 1>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
-        case 2: up_nu<T, NPRE, 2>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
-        case 3: up_nu<T, NPRE, 3>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
-        case 4: up_nu<T, NPRE, 4>(m, lev, lvl, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
-        default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
-    }
 }
 
 }  // namespace
 
 template <typename T>
-void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, int ncols, int cpm,
-                    const int* act, int cpv, hipStream_t st) {
+void launch_mg_down(int m, const LevelDev* lev, int lvl, int npre, const T* b, ColMap bmap, T* bc, T* xp, int ncols,
+                    int cpm, const int* act, int cpv, hipStream_t st) {
     if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
     const Skip sk{act, cpv};
     switch (npre) {
-        case 1: down_nu<T, 1>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
-        case 2: down_nu<T, 2>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
-        case 3: down_nu<T, 3>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
-        case 4: down_nu<T, 4>(m, lev, lvl, b, bmap, bc, ncols, cpm, sk, st); break;
+        case 1: down_nu<T, 1>(m, lev, lvl, b, bmap, bc, xp, ncols, cpm, sk, st); break;
+        case 2: down_nu<T, 2>(m, lev, lvl, b, bmap, bc, xp, ncols, cpm, sk, st); break;
+        case 3: down_nu<T, 3>(m, lev, lvl, b, bmap, bc, xp, ncols, cpm, sk, st); break;
+        case 4: down_nu<T, 4>(m, lev, lvl, b, bmap, bc, xp, ncols, cpm, sk, st); break;
         default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     }
     SG_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_mg_up(int m, const LevelDev* lev, int lvl, int npre, int npost, const T* ec, const T* b, ColMap bmap,
+void launch_mg_up(int m, const LevelDev* lev, int lvl, int npost, const T* ec, const T* b, ColMap bmap, const T* xp,
                   T* xo, ColMap xomap, int ncols, int cpm, const int* act, int cpv, hipStream_t st) {
     if (ncols > 65535) throw Error(SG_ERR_INVALID, "multigrid: too many columns in one launch");
     const Skip sk{act, cpv};
-    switch (npre) {
-        case 1: up_pre<T, 1>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
-        case 2: up_pre<T, 2>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
-        case 3: up_pre<T, 3>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
-        case 4: up_pre<T, 4>(m, lev, lvl, npost, ec, b, bmap, xo, xomap, ncols, cpm, sk, st); break;
+    switch (npost) {
+        case 1: up_nu<T, 1>(m, lev, lvl, ec, b, bmap, xp, xo, xomap, ncols, cpm, sk, st); break;
+        case 2: up_nu<T, 2>(m, lev, lvl, ec, b, bmap, xp, xo, xomap, ncols, cpm, sk, st); break;
+        case 3: up_nu<T, 3>(m, lev, lvl, ec, b, bmap, xp, xo, xomap, ncols, cpm, sk, st); break;
+        case 4: up_nu<T, 4>(m, lev, lvl, ec, b, bmap, xp, xo, xomap, ncols, cpm, sk, st); break;
         default: throw Error(SG_ERR_INVALID, "smoothing degree must be 1..4");
     }
     SG_HIP(hipGetLastError());
@@ -771,13 +773,13 @@ template void launch_mg_tail<double>(int, const LevelDev*, int, int, int, const 
                                      const double*, int, int, const int*, int, hipStream_t);
 template void launch_mg_tail<float>(int, const LevelDev*, int, int, int, const float*, ColMap, float*, ColMap,
                                     const float*, int, int, const int*, int, hipStream_t);
-template void launch_mg_down<double>(int, const LevelDev*, int, int, const double*, ColMap, double*, int, int,
-                                     const int*, int, hipStream_t);
-template void launch_mg_down<float>(int, const LevelDev*, int, int, const float*, ColMap, float*, int, int,
+template void launch_mg_down<double>(int, const LevelDev*, int, int, const double*, ColMap, double*, double*, int,
+                                     int, const int*, int, hipStream_t);
+template void launch_mg_down<float>(int, const LevelDev*, int, int, const float*, ColMap, float*, float*, int, int,
                                     const int*, int, hipStream_t);
-template void launch_mg_up<double>(int, const LevelDev*, int, int, int, const double*, const double*, ColMap, double*,
-                                   ColMap, int, int, const int*, int, hipStream_t);
-template void launch_mg_up<float>(int, const LevelDev*, int, int, int, const float*, const float*, ColMap, float*,
-                                  ColMap, int, int, const int*, int, hipStream_t);
+template void launch_mg_up<double>(int, const LevelDev*, int, int, const double*, const double*, ColMap,
+                                   const double*, double*, ColMap, int, int, const int*, int, hipStream_t);
+template void launch_mg_up<float>(int, const LevelDev*, int, int, const float*, const float*, ColMap, const float*,
+                                  float*, ColMap, int, int, const int*, int, hipStream_t);
 
 }  // namespace sg

@@ -91,10 +91,11 @@ int mg_first_fused(const Handle& h, bool& tail) {
 
 // Per-level multigrid scratch of a V-cycle over ncols columns: bs (restricted
 // right-hand side, l >= 1), xf (after post-smoothing, l >= 1; level 0 writes
-// to x); xs only for the coarsest level solved directly.
+// to x), xp (pre-smoothed iterate, levels run by the down/up kernels); xs only
+// for the coarsest level solved directly.
 template <typename T>
 void mg_buffers(Handle& h, int ncols, std::vector<T*>& xs, std::vector<T*>& bs, std::vector<T*>& xf,
-                std::vector<ColMap>& cm) {
+                std::vector<T*>& xp, std::vector<ColMap>& cm) {
     const Shape& s = h.s;
     const int nl = s.nlev_mg;
     bool tail = false;
@@ -102,6 +103,7 @@ void mg_buffers(Handle& h, int ncols, std::vector<T*>& xs, std::vector<T*>& bs, 
     xs.assign(nl, nullptr);
     bs.assign(nl, nullptr);
     xf.assign(nl, nullptr);
+    xp.assign(nl, nullptr);
     cm.assign(nl, ColMap{});
     for (int l = 0; l <= lc; ++l) {
         const int m = s.mg_n[l];
@@ -110,6 +112,7 @@ void mg_buffers(Handle& h, int ncols, std::vector<T*>& xs, std::vector<T*>& bs, 
         const std::string tag = std::string("mg") + tname<T>() + "_" + std::to_string(l);
         cm[l] = contiguous_cols(ncols, nodes);
         if (l == lc && !tail) xs[l] = h.ws.get_t<T>(tag + "_xs", cnt);
+        if (l < lc) xp[l] = h.ws.get_t<T>(tag + "_xp", cnt);
         if (l > 0) {
             bs[l] = h.ws.get_t<T>(tag + "_bs", cnt);
             xf[l] = h.ws.get_t<T>(tag + "_xf", cnt);
@@ -133,16 +136,16 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
     }
     bool tail = false;
     const int lc = mg_first_fused(h, tail);
-    std::vector<T*> xs, bs, xf;
+    std::vector<T*> xs, bs, xf, xp;
     std::vector<ColMap> cm;
-    mg_buffers<T>(h, ncols, xs, bs, xf, cm);
+    mg_buffers<T>(h, ncols, xs, bs, xf, xp, cm);
     for (int l = 0; l < lc; ++l) {
         const int m = s.mg_n[l];
         const double nodes = (double)(m + 1) * (m + 1);
         const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_SMOOTH, st);
-        launch_mg_down<T>(m, lev, l, npre, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], bs[l + 1], ncols, cpm, h.active,
-                          cpv, st);
-        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 1.25);   // read b, write b_coarse
+        launch_mg_down<T>(m, lev, l, npre, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], bs[l + 1], xp[l], ncols, cpm,
+                          h.active, cpv, st);
+        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);   // read b, write the iterate and b_coarse
     }
     const T* e;
     if (tail) {
@@ -162,9 +165,9 @@ void vcycle(Handle& h, const T* b, ColMap bmap, T* x, ColMap xmap, int ncols, in
         const double nodes = (double)(m + 1) * (m + 1);
         T* out = l == 0 ? x : xf[l];
         const bool tp = l == 0 && prof_begin(h, SG_PROF_MG_UP, st);
-        launch_mg_up<T>(m, lev, l, npre, npost, e, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], out,
+        launch_mg_up<T>(m, lev, l, npost, e, l == 0 ? b : bs[l], l == 0 ? bmap : cm[l], xp[l], out,
                         l == 0 ? xmap : cm[l], ncols, cpm, h.active, cpv, st);
-        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 2.25);  // read b, e_coarse; write x
+        if (tp) prof_end(h, st, sizeof(T) * ncols * nodes * 3.25);  // read b, the iterate, e_coarse; write x
         e = out;
     }
 }
@@ -427,9 +430,9 @@ void precond_reserve(Handle& h, int nvec) {
     if (s.nlev_mg > 1) {
         int lmax = 0;
         for (int d = 0; d <= s.P; ++d) lmax = std::max(lmax, s.off[d + 1] - s.off[d]);
-        std::vector<T*> xs, bs, xf;
+        std::vector<T*> xs, bs, xf, xp;
         std::vector<ColMap> cm;
-        mg_buffers<T>(h, lmax * s.nt * nvec, xs, bs, xf, cm);
+        mg_buffers<T>(h, lmax * s.nt * nvec, xs, bs, xf, xp, cm);
     }
 }
 
@@ -450,14 +453,14 @@ template void precond_apply<float>(Handle&, const float*, float*, int, bool, hip
 namespace {
 
 // one mean-block solve of one column: a multigrid V-cycle reads b and writes
-// the coarse right-hand side going down (1.25 node passes), reads b and the
-// coarse correction and writes x going up (2.25), over levels shrinking by
-// four (x 4/3); the sine-transform solve makes four FP64 passes, each reading
-// and writing the column
+// the pre-smoothed iterate and the coarse right-hand side going down (2.25
+// node passes), reads b, that iterate and the coarse correction and writes x
+// going up (3.25), over levels shrinking by four (x 4/3); the sine-transform
+// solve makes four FP64 passes, each reading and writing the column
 double mean_solve_bytes(const Handle& h, double sz) {
     const double nodes = (double)h.s.nodes;
     if (h.opt.mean_solver == SG_MEAN_EXACT) return 8.0 * 8.0 * nodes;
-    return sz * nodes * 3.5 * 4.0 / 3.0;
+    return sz * nodes * 5.5 * 4.0 / 3.0;
 }
 
 // one hGS sweep pair (Alg. 1) on one member's field block: the level
