@@ -50,7 +50,9 @@ size_t footprint_bytes(const sg_problem& p, const sg_options& o) {
     const double sz = o.precision == SG_PREC_FP64 ? 8.0 : 4.0;       // Z and preconditioner scratch
     double bytes = (v32 ? 4.0 : 8.0) * N * (m + 1) + sz * N * m;      // basis V, preconditioned vectors Z
     bytes += 8.0 * N * (v32 ? 5 : 6);                                 // FP64 b, x, r (+ w), refinement r, d
-    // preconditioner scratch: Schur 2 blocks, hGS 1, multigrid ~0.6 of the widest degree level at 1.4 nodes
+    // preconditioner scratch: Schur 2 blocks, hGS 1; multigrid for the widest degree level (~0.6 n_xi
+    // columns): restricted right-hand sides, post-smoothed and stored pre-smoothed iterates, about 2 node
+    // passes per column over the levels, counted as 4 x 1.4
     bytes += sz * blk * 3 + sz * 4 * nodes * 1.4 * nxi * 0.6;
     if (refine) bytes += 4.0 * N * (v32 ? 2 : 3);                      // FP32 operator output and staging
     if (o.precision == SG_PREC_FP32_PRECOND) bytes += 4.0 * N + 8.0 * N;   // FP32 staging, FP64 copy of Z_j
