@@ -414,6 +414,12 @@ OPTION_CASES = [
     ("truncation r=3", (32, 4, 2, 0.25, 1e-3, 0.0, 1), dict(truncation_r=3)),
     ("coarse-only hierarchy", (8, 2, 2, 0.2, 1e-2, 0.0, 1), {}),
     ("three level kernels above the tail", (256, 2, 1, 0.2, 1e-2, 0.0, 1), {}),
+    # the down kernel stores its pre-smoothed iterate and the up kernel reads it:
+    # other smoothing degrees on a level above the tail (one pre step, the
+    # most pre and post steps, time-dependent columns)
+    ("smoothing 1/3 above the tail", (128, 2, 1, 0.25, 1e-3, 0.0, 1), dict(gmg_pre=1, gmg_post=3)),
+    ("smoothing 4/1 above the tail", (128, 2, 1, 0.25, 1e-3, 0.3, 1), dict(gmg_pre=4, gmg_post=1)),
+    ("smoothing 3/4 above the tail, time", (128, 1, 1, 0.2, 1e-3, 0.0, 2), dict(gmg_pre=3, gmg_post=4)),
     ("exact mean-block solves", (32, 3, 2, 0.25, 1e-3, 0.0, 1), dict(mean_solver=1)),
     ("exact mean-block solves, time", (16, 3, 2, 0.25, 1e-3, 0.0, 3), dict(mean_solver=1)),
     ("exact mass solves", (32, 3, 2, 0.25, 1e-3, 0.3, 1), dict(cheb_steps=0)),
@@ -430,9 +436,9 @@ OPTION_CASES = [
 def test_option_paths(label, shape, opts):
     """Code paths the default workloads do not take: the gather kernels for
     M > 8, the per-step Chebyshev kernel (more than 9 steps), other smoothing
-    degrees (separate kernel instances), intermediate truncation, the
-    hierarchy that is only the coarse grid, and several level kernels above
-    the fused tail.  KKT and preconditioner applies against the oracle, then
+    degrees (separate kernel instances, in the fused tail and in the level
+    kernels above it), intermediate truncation, the hierarchy that is only the
+    coarse grid, and several level kernels above the fused tail.  KKT and preconditioner applies against the oracle, then
     the solve (against the direct solution, or the oracle's true residual at
     the large grid)."""
     n, M, P, sigma, beta, gamma, nt = shape
