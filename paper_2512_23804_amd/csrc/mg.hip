@@ -663,23 +663,41 @@ void cheb_h(const Shape& s, const OpDev& op, const T* r, int64_t rstride, T* z, 
 
 constexpr int TCD = 16;   // coarse nodes per down tile side
 constexpr int TFU = 32;   // fine nodes per up tile side
+// Launches with fewer workgroups than this at the tile sizes above (a few
+// columns on a level) take half-size tiles instead: the launch then lasts
+// about one workgroup's chain of barriered steps, which halves with the tile.
+// Every node's arithmetic is the same in either tiling.
+constexpr int64_t kSmallTileBlocks = 512;
 
 template <typename T, int NU>
 void down_nu(int m, const LevelDev* lev, int lvl, const T* b, ColMap bmap, T* bc, T* xp, int ncols, int cpm, Skip sk,
              hipStream_t st) {
     const int mc = m / 2;
     const int tx = (mc - 1 + TCD - 1) / TCD;
-    dim3 grid(tx * tx, ncols);
-    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), grid, dim3(256), 0, st, m, lev, lvl, b, bmap, bc, xp, cpm, tx, sk);
+    if ((int64_t)tx * tx * ncols < kSmallTileBlocks) {
+        constexpr int TC = TCD / 2;
+        const int ts = (mc - 1 + TC - 1) / TC;
+        hipLaunchKernelGGL((k_mg_down<T, TC, NU>), dim3(ts * ts, ncols), dim3(256), 0, st, m, lev, lvl, b, bmap, bc,
+                           xp, cpm, ts, sk);
+        return;
+    }
+    hipLaunchKernelGGL((k_mg_down<T, TCD, NU>), dim3(tx * tx, ncols), dim3(256), 0, st, m, lev, lvl, b, bmap, bc, xp,
+                       cpm, tx, sk);
 }
 
 template <typename T, int NPOST>
 void up_nu(int m, const LevelDev* lev, int lvl, const T* ec, const T* b, ColMap bmap, const T* xp, T* xo,
            ColMap xomap, int ncols, int cpm, Skip sk, hipStream_t st) {
     const int tx = (m - 1 + TFU - 1) / TFU;
-    dim3 grid(tx * tx, ncols);
-    hipLaunchKernelGGL((k_mg_up<T, TFU, NPOST>), grid, dim3(256), 0, st, m, lev, lvl, ec, b, bmap, xp, xo, xomap,
-                       cpm, tx, sk);
+    if ((int64_t)tx * tx * ncols < kSmallTileBlocks) {
+        constexpr int TF = TFU / 2;
+        const int ts = (m - 1 + TF - 1) / TF;
+        hipLaunchKernelGGL((k_mg_up<T, TF, NPOST>), dim3(ts * ts, ncols), dim3(256), 0, st, m, lev, lvl, ec, b, bmap,
+                           xp, xo, xomap, cpm, ts, sk);
+        return;
+    }
+    hipLaunchKernelGGL((k_mg_up<T, TFU, NPOST>), dim3(tx * tx, ncols), dim3(256), 0, st, m, lev, lvl, ec, b, bmap, xp,
+                       xo, xomap, cpm, tx, sk);
 }
 
 }  // namespace
