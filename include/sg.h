@@ -213,13 +213,13 @@ typedef struct sg_options {
 /* Kernels that sg_options.profile can time (HIP events around every launch). */
 #define SG_PROF_NONE        0
 #define SG_PROF_KKT_APPLY   1   /* fused KKT apply (two SG operator applies + mass terms) */
-#define SG_PROF_MG_SMOOTH   2   /* multigrid down kernel (pre-smoothing, residual, restriction), finest level */
+#define SG_PROF_MG_SMOOTH   2   /* multigrid down kernel (pre-smoothing, stored; residual, restriction), finest level */
 #define SG_PROF_MULTIDOT    3   /* Arnoldi dot-product pass (read-only pass over the basis) */
 #define SG_PROF_HGS_RHS     4   /* hierarchical Gauss-Seidel off-level right-hand side */
 #define SG_PROF_ARNOLDI_UPD 5   /* Arnoldi update pass (DCGS2: finalise V_j, next candidate) */
 #define SG_PROF_MG_TAIL     6   /* fused coarse end of the V-cycle (levels <= 64, direct solve) */
 #define SG_PROF_MASS_CHEB   7   /* Chebyshev semi-iteration on the mass blocks */
-#define SG_PROF_MG_UP       8   /* multigrid up kernel (pre-smoothing recomputed, correction, post-smoothing), finest level */
+#define SG_PROF_MG_UP       8   /* multigrid up kernel (stored pre-smoothed iterate, correction, post-smoothing), finest level */
 
 /* Per-solve report. */
 typedef struct sg_solve_info {
