@@ -104,3 +104,16 @@ def test_noalloc_rejects_sizes_beyond_the_scratch():
     h2 = _handle(SMALL)
     _compare(h2, torch.float64, 6)
     h2.close()
+
+
+def test_noalloc_level_kernels_above_the_tail():
+    """A 128 x 128 grid: the multigrid level kernels above the fused tail run,
+    with the pre-smoothed iterate the down kernel stores for the up kernel
+    carved from the fixed scratch like every other buffer (FP64, then FP32,
+    then FP64 again on the same handle)."""
+    _say("noalloc: 128x128, M=2, P=1 (multigrid level kernels)")
+    h = _handle([(128, 2, 1, 0.25, 1e-3, 0.0, 1)])
+    _compare(h, torch.float64, 7)
+    _compare(h, torch.float32, 8)
+    _compare(h, torch.float64, 9)
+    h.close()
